@@ -1,0 +1,161 @@
+"""ctypes binding of the CPU oracle (oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg. The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+TRACE_DTYPE = np.dtype([
+    ("iter", np.int64), ("var", np.int32), ("kind", np.int32), ("x_old", np.float64),
+    ("x_new", np.float64), ("score", np.float64), ("viol", np.int64), ("obj", np.float64),
+])
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp with g++ (IEEE FP64, no contraction, no fast-math)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        build()
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    i32, i64, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, f64, i32]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_num_norm_rows.restype = i32
+    lib.orc_num_norm_rows.argtypes = [P]
+    lib.orc_norm_rows.argtypes = [P, P, P]
+    lib.orc_bounds.argtypes = [P, P, P, P]
+    lib.orc_residual.restype = i64
+    lib.orc_residual.argtypes = [P, P, f64, P]
+    lib.orc_best_shift.argtypes = [P, P, P, f64, P, i64, P, P]
+    lib.orc_start_point.argtypes = [P, u64, P]
+    lib.orc_splitmix64.restype = u64
+    lib.orc_splitmix64.argtypes = [u64, u64]
+    lib.orc_tabu_run.restype = i64
+    lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def splitmix64(seed: int, index: int) -> int:
+    return int(_load().orc_splitmix64(seed, index))
+
+
+class OracleProblem:
+    """The normalised problem held by the oracle."""
+
+    def __init__(self, mip, eps: float = 1e-6, binary_as_general: bool = False):
+        lib = _load()
+        self._keep = [
+            np.ascontiguousarray(mip.csr_row_ptr, dtype=np.int64),
+            np.ascontiguousarray(mip.csr_col, dtype=np.int32),
+            np.ascontiguousarray(mip.csr_val, dtype=np.float64),
+            np.ascontiguousarray(mip.sense, dtype=np.uint8),
+            np.ascontiguousarray(mip.rhs, dtype=np.float64),
+            np.ascontiguousarray(mip.lb, dtype=np.float64),
+            np.ascontiguousarray(mip.ub, dtype=np.float64),
+            np.ascontiguousarray(mip.is_int, dtype=np.uint8),
+            np.ascontiguousarray(mip.obj, dtype=np.float64),
+        ]
+        self.n = int(mip.n)
+        self.eps = eps
+        self.h = lib.orc_create(int(mip.n), int(mip.m), *[_p(a) for a in self._keep], float(eps),
+                                int(bool(binary_as_general)))
+        self.mp = int(lib.orc_num_norm_rows(self.h))
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self._lib.orc_destroy(h)
+            self.h = None
+
+    def norm_rows(self):
+        orig = np.empty(self.mp, dtype=np.int32)
+        sign = np.empty(self.mp, dtype=np.int8)
+        self._lib.orc_norm_rows(self.h, _p(orig), _p(sign))
+        return orig, sign
+
+    def bounds(self):
+        lb = np.empty(self.n)
+        ub = np.empty(self.n)
+        isb = np.empty(self.n, dtype=np.uint8)
+        self._lib.orc_bounds(self.h, _p(lb), _p(ub), _p(isb))
+        return lb, ub, isb
+
+    def residual(self, x, cutoff_rhs: float = float("inf")):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        r = np.empty(self.mp + 1)
+        v = self._lib.orc_residual(self.h, _p(x), float(cutoff_rhs), _p(r))
+        return r, int(v)
+
+    def best_shift(self, x, w, cutoff_rhs: float = float("inf"), cols=None):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape[0] == self.mp + 1
+        if cols is None:
+            xh = np.empty(self.n)
+            s = np.empty(self.n)
+            self._lib.orc_best_shift(self.h, _p(x), _p(w), float(cutoff_rhs), None, 0, _p(xh), _p(s))
+        else:
+            cols = np.ascontiguousarray(cols, dtype=np.int32)
+            xh = np.empty(cols.shape[0])
+            s = np.empty(cols.shape[0])
+            self._lib.orc_best_shift(self.h, _p(x), _p(w), float(cutoff_rhs), _p(cols), cols.shape[0],
+                                     _p(xh), _p(s))
+        return xh, s
+
+    def start_point(self, seed: int):
+        x = np.empty(self.n)
+        self._lib.orc_start_point(self.h, int(seed), _p(x))
+        return x
+
+    def tabu_run(self, iters: int, tenure: int, seed: int, x0=None):
+        trace = np.zeros(max(iters, 1), dtype=TRACE_DTYPE)
+        x = np.empty(self.n)
+        r = np.empty(self.mp + 1)
+        w = np.empty(self.mp + 1, dtype=np.float32)
+        best_obj = ctypes.c_double()
+        best_x = np.empty(self.n)
+        has_best = ctypes.c_int32()
+        bc = ctypes.c_double()
+        x0p = None
+        if x0 is not None:
+            x0 = np.ascontiguousarray(x0, dtype=np.float64)
+            x0p = _p(x0)
+        self._lib.orc_tabu_run(self.h, int(iters), int(tenure), int(seed), x0p, _p(trace), _p(x), _p(r),
+                               _p(w), ctypes.byref(best_obj), _p(best_x), ctypes.byref(has_best),
+                               ctypes.byref(bc))
+        return {
+            "trace": trace[:iters], "x": x, "r": r, "w": w, "best_obj": best_obj.value,
+            "best_x": best_x if has_best.value else None, "cutoff_rhs": bc.value,
+        }
