@@ -1,0 +1,207 @@
+/*
+ * chap.h - C ABI of the MI355X (gfx950) tabu-search best-shift library.
+ *
+ * The library implements the GPU tabu-search hot path of the CHAP MIP primal
+ * heuristic (section 3.1 "GPU Tabu Search" of the paper): for every variable
+ * an exact best shift (Eq. 1; flip for binaries, Algorithm 1 "Best Shift via
+ * Sort-Scan-Argmax" for all others), the global best admissible move under a
+ * tabu list with aspiration, and the sparse residual update.
+ *
+ * Conventions shared by every call
+ *   - Every function except the destroy calls, chap_last_error and the
+ *     accessors returns int: CHAP_OK (0) on success, a negative CHAP_E* code
+ *     on failure. chap_last_error() returns the message of the last failure on
+ *     the calling thread. A failed call leaves every handle unchanged.
+ *   - Handles are not thread-safe: one thread (and one HIP stream) at a time
+ *     per handle.
+ *   - Problem form (section 3.1, problem statement):
+ *         min c^T x  s.t.  A x (<=, >=, =) b,  l <= x <= u,  x_j integer
+ *     for is_int[j] = 1. Rows are normalised to '<=' (section 3.1 "Memory
+ *     Considerations", second remark): a 'L' row stays, a 'G' row is negated,
+ *     an 'E' row becomes the consecutive pair (row, negated row). The
+ *     normalised rows are numbered 0..m'-1 in that order; index m' is the
+ *     objective cutoff row c^T x <= cutoff (section 3.2), inactive until a
+ *     feasible point is known.
+ *   - A normalised row i is violated iff its residual r_i = a_i^T x - b_i
+ *     exceeds the feasibility tolerance eps (residual storage: section 3.1
+ *     "Memory Considerations", first remark). The breakpoint of row i on
+ *     variable j is t = xbar_j + (eps - r_i) / a_ij, rounded down when
+ *     a_ij > 0 and up when a_ij < 0 for an integer variable (Algorithm 1,
+ *     phase 1).
+ *   - Arithmetic is IEEE FP64 (no contraction, correctly rounded division).
+ *     Scores are sums of +-w_i and +-w_i/2; with integer-valued weights they
+ *     are exact, so results do not depend on summation order.
+ */
+#ifndef CHAP_H
+#define CHAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHAP_OK = 0,
+  CHAP_EINVAL = -1,   /* invalid argument or inconsistent problem data */
+  CHAP_ENOMEM = -2,   /* host or device allocation failed */
+  CHAP_EHIP = -3,     /* a HIP runtime call failed */
+  CHAP_ESTATE = -4,   /* call not valid in the handle's current state */
+  CHAP_ENOTBUILT = -5 /* no usable gfx950 device */
+};
+
+typedef struct chap_problem chap_problem;
+typedef struct chap_run chap_run;
+
+typedef struct {
+  double feas_tol;      /* eps; default 1e-6 */
+  int32_t graph_iters;  /* tabu iterations recorded per HIP graph; 0 = 64 */
+  int32_t short_max;    /* normalised entries up to which a column is scored
+                           by one lane (1..8); 0 = 8 */
+  int32_t chunk_min;    /* entries above which an integer column with at most
+                           64 values is split over workgroups; 0 = 4096 */
+  int32_t chunk_len;    /* nonzeros per workgroup chunk for those columns;
+                           0 = 4096 */
+} chap_options;
+
+/* One trace record per tabu iteration (48 bytes, host order). */
+typedef struct {
+  int64_t iter;  /* iteration index k */
+  int32_t var;   /* moved variable, -1 when the step reweighted */
+  int32_t kind;  /* 0 move, 1 move allowed by aspiration, 2 reweight */
+  double x_old;  /* value before the move (0 for a reweight) */
+  double x_new;  /* value after the move (0 for a reweight) */
+  double score;  /* best-shift score s_j of the move (0 for a reweight) */
+  int64_t viol;  /* violated normalised rows after the step (cutoff row
+                    counted when active) */
+  double obj;    /* c^T x after the step */
+} chap_trace_record;
+
+/* Fills *opt with the defaults. */
+void chap_options_default(chap_options *opt);
+
+/*
+ * chap_problem_create - validate, normalise and upload one MIP.
+ *
+ * Defined by the problem statement of section 3.1 and the normalisation of
+ * section 3.1 "Memory Considerations".
+ *   n, m           variables and original rows (>= 0).
+ *   csr_*          host CSR of A: csr_row_ptr (m+1, int64, [0]=0, non-
+ *                  decreasing), csr_col (nnz, int32 in [0,n)), csr_val (nnz).
+ *   csc_*          host CSC of the same A: csc_col_ptr (n+1), csc_row (nnz,
+ *                  int32 in [0,m)), csc_val (nnz). CSR and CSC must hold the
+ *                  same entries (any order within a row or column); no
+ *                  (row, col) pair may repeat; stored zeros are dropped.
+ *   sense          m chars 'L', 'G' or 'E'.     rhs   m finite values.
+ *   lb, ub         n bounds; -inf/+inf allowed (HUGE_VAL). Integer bounds
+ *                  are rounded inward; lb must not exceed ub afterwards.
+ *   is_int         n flags (0/1). A [0,1] integer variable is binary.
+ *   obj            n finite objective coefficients.
+ *   opt            NULL for the defaults.
+ * All host arrays are copied; the caller may free them on return. The
+ * residual of every row is accumulated in the order of csr_col within the row.
+ * Limits: nnz < 2^31 and every column shorter than 2^31 entries.
+ * Errors: CHAP_EINVAL (with a message naming the first offending entry),
+ * CHAP_ENOMEM, CHAP_EHIP, CHAP_ENOTBUILT. On error *out is left unchanged.
+ */
+int chap_problem_create(chap_problem **out, int32_t n, int32_t m, const int64_t *csr_row_ptr,
+                        const int32_t *csr_col, const double *csr_val, const int64_t *csc_col_ptr,
+                        const int32_t *csc_row, const double *csc_val, const char *sense,
+                        const double *rhs, const double *lb, const double *ub, const uint8_t *is_int,
+                        const double *obj, const chap_options *opt);
+
+void chap_problem_destroy(chap_problem *p);
+
+/* m' (normalised rows, excluding the cutoff row whose index is m'). */
+int32_t chap_problem_num_norm_rows(const chap_problem *p);
+
+/* For each normalised row: its original row and sign (+1 or -1). Host
+ * arrays of m' entries. */
+int chap_problem_norm_row_map(const chap_problem *p, int32_t *orig_row, int8_t *sign);
+
+/*
+ * chap_best_shift - one exact best-shift pass over all variables.
+ *
+ * Computes the residuals of every normalised row from scratch at d_x, then
+ * for every variable j the best shift of Eq. (1): the flip for a binary
+ * variable; otherwise the smallest candidate position (bounds and row
+ * breakpoints inside [l_j, u_j], the incumbent excluded) that maximises the
+ * score s_j of section 3.1 "Scoring Functions", as Algorithm 1 returns it.
+ * When no candidate scores above zero the result is (xbar_j, 0) (Algorithm 1
+ * explanation, phase 4).
+ *   d_x        device, n doubles: the incumbent (inside the bounds, integral
+ *              on integer variables; otherwise the result is unspecified).
+ *   d_w        device, m'+1 floats: row weights in normalised order, the last
+ *              one for the cutoff row. Must be finite and >= 0.
+ *   cutoff_rhs the cutoff row c^T x <= cutoff_rhs is active iff finite.
+ *   d_shift    device, n doubles, out: xhat_j.
+ *   d_score    device, n doubles, out: s_j (> 0, or 0 when no improvement).
+ *   hip_stream hipStream_t to run on (NULL = the null stream).
+ * Asynchronous: returns once the work is queued. The problem's internal
+ * buffers are reused by every call, so calls on one problem must not overlap
+ * (queue them on one stream). Errors: CHAP_EINVAL, CHAP_EHIP.
+ */
+int chap_best_shift(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
+                    double *d_shift, double *d_score, void *hip_stream);
+
+/*
+ * chap_best_shift_pass_ms - duration of the best-shift kernels (the pass
+ * after the residual and weight set-up) of the most recent chap_best_shift
+ * call on this problem, measured with HIP events recorded on that call's
+ * stream. Waits for that call to finish. *ms = 0 before the first call.
+ * Errors: CHAP_EINVAL, CHAP_EHIP.
+ */
+int chap_best_shift_pass_ms(chap_problem *p, double *ms);
+
+/*
+ * chap_tabu_run - one tabu walk of `iters` iterations (section 3.1).
+ *
+ * Start point: seed = 0 -> x_j = clamp(0, l_j, u_j); otherwise an integer
+ * variable with finite bounds starts at l_j + (h mod (u_j - l_j + 1)) with h
+ * the (j+1)-th output of SplitMix64 seeded with `seed`; continuous and
+ * unbounded variables start at clamp(0, l_j, u_j). Weights start at 1.
+ * Every iteration: if no normalised row is violated the point is an
+ * incumbent (objective cutoff c^T x <= f_best - delta, section 3.2; delta = 1
+ * when the objective is integral on integer variables, else
+ * 1e-4 max(1, |f_best|)); then every variable's best shift is computed; the
+ * move is the highest positive score (lowest index on ties) among variables
+ * not tabu, except that the overall best may be taken while tabu when its
+ * move leaves no violated row (aspiration); a moved variable stays tabu for
+ * `tenure` iterations; when no move is admissible, the weight of every
+ * violated normalised row (cutoff included) grows by 1.
+ *   iters >= 0, tenure >= 0, iters + tenure < 2^31.
+ *   x0         optional host start point (n doubles) replacing the seed rule;
+ *              NULL to use the seed rule.
+ *   hip_stream work is ordered after what is queued on this stream.
+ * Synchronous: on return *out holds the trace and the final state.
+ * Errors: CHAP_EINVAL, CHAP_ENOMEM, CHAP_EHIP.
+ */
+int chap_tabu_run(chap_problem *p, int64_t iters, int32_t tenure, uint64_t seed, const double *x0,
+                  chap_run **out, void *hip_stream);
+
+/* Trace of a run: *records points into the run (valid until
+ * chap_run_destroy), *count = iters. */
+int chap_run_trace(const chap_run *r, const chap_trace_record **records, int64_t *count);
+
+/*
+ * Final state of a run, copied into caller host arrays (any pointer may be
+ * NULL to skip it): x (n), resid (m'+1, normalised order, cutoff last; 0 for
+ * an inactive cutoff), w (m'+1), best_x (n, only written when a feasible
+ * point was found). *best_obj = +inf and *cutoff_rhs = +inf when none was.
+ */
+int chap_run_state(const chap_run *r, double *x, double *resid, float *w, double *best_obj,
+                   double *best_x, double *cutoff_rhs);
+
+/* GPU time of the run's iteration graphs in milliseconds (HIP events). */
+double chap_run_elapsed_ms(const chap_run *r);
+
+void chap_run_destroy(chap_run *r);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *chap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHAP_H */

@@ -1,0 +1,223 @@
+"""Python binding of libchap.so, the gfx950 tabu-search best-shift library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/chap.h. PyTorch provides device
+memory and streams. There is no CPU fallback: importing the binding raises if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchap.so")
+
+CHAP_OK = 0
+ERRORS = {-1: "CHAP_EINVAL", -2: "CHAP_ENOMEM", -3: "CHAP_EHIP", -4: "CHAP_ESTATE", -5: "CHAP_ENOTBUILT"}
+
+TRACE_DTYPE = np.dtype([
+    ("iter", np.int64), ("var", np.int32), ("kind", np.int32), ("x_old", np.float64),
+    ("x_new", np.float64), ("score", np.float64), ("viol", np.int64), ("obj", np.float64),
+])
+
+
+class ChapOptions(ctypes.Structure):
+    _fields_ = [("feas_tol", ctypes.c_double), ("graph_iters", ctypes.c_int32), ("short_max", ctypes.c_int32),
+                ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32)]
+
+
+class ChapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libchap.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2605_05086_amd/build.py (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.chap_options_default.argtypes = [ctypes.POINTER(ChapOptions)]
+    lib.chap_options_default.restype = None
+    lib.chap_last_error.restype = ctypes.c_char_p
+    lib.chap_problem_create.argtypes = [ctypes.POINTER(P), i32, i32, P, P, P, P, P, P, P, P, P, P, P, P,
+                                        ctypes.POINTER(ChapOptions)]
+    lib.chap_problem_create.restype = ctypes.c_int
+    lib.chap_problem_destroy.argtypes = [P]
+    lib.chap_problem_destroy.restype = None
+    lib.chap_problem_num_norm_rows.argtypes = [P]
+    lib.chap_problem_num_norm_rows.restype = i32
+    lib.chap_problem_norm_row_map.argtypes = [P, P, P]
+    lib.chap_problem_norm_row_map.restype = ctypes.c_int
+    lib.chap_best_shift.argtypes = [P, P, P, f64, P, P, P]
+    lib.chap_best_shift.restype = ctypes.c_int
+    lib.chap_best_shift_pass_ms.argtypes = [P, ctypes.POINTER(f64)]
+    lib.chap_best_shift_pass_ms.restype = ctypes.c_int
+    lib.chap_tabu_run.argtypes = [P, i64, i32, u64, P, ctypes.POINTER(P), P]
+    lib.chap_tabu_run.restype = ctypes.c_int
+    lib.chap_run_trace.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(i64)]
+    lib.chap_run_trace.restype = ctypes.c_int
+    lib.chap_run_state.argtypes = [P, P, P, P, ctypes.POINTER(f64), P, ctypes.POINTER(f64)]
+    lib.chap_run_state.restype = ctypes.c_int
+    lib.chap_run_elapsed_ms.argtypes = [P]
+    lib.chap_run_elapsed_ms.restype = f64
+    lib.chap_run_destroy.argtypes = [P]
+    lib.chap_run_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != CHAP_OK:
+        raise ChapError(rc, load_library().chap_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def default_options() -> ChapOptions:
+    o = ChapOptions()
+    load_library().chap_options_default(ctypes.byref(o))
+    return o
+
+
+class Run:
+    """Result of chap_tabu_run: trace and final state (host arrays)."""
+
+    def __init__(self, handle, n: int, mp: int):
+        lib = load_library()
+        self._h = handle
+        rec = ctypes.c_void_p()
+        cnt = ctypes.c_int64()
+        _check(lib.chap_run_trace(handle, ctypes.byref(rec), ctypes.byref(cnt)))
+        if cnt.value > 0:
+            buf = (ctypes.c_char * (cnt.value * TRACE_DTYPE.itemsize)).from_address(rec.value)
+            self.trace = np.frombuffer(bytes(buf), dtype=TRACE_DTYPE).copy()
+        else:
+            self.trace = np.zeros(0, dtype=TRACE_DTYPE)
+        self.x = np.empty(n)
+        self.resid = np.empty(mp + 1)
+        self.w = np.empty(mp + 1, dtype=np.float32)
+        self.best_x = np.full(n, np.nan)
+        best_obj = ctypes.c_double()
+        cut = ctypes.c_double()
+        _check(lib.chap_run_state(handle, _ptr(self.x), _ptr(self.resid), _ptr(self.w), ctypes.byref(best_obj),
+                                  _ptr(self.best_x), ctypes.byref(cut)))
+        self.best_obj = best_obj.value
+        self.cutoff_rhs = cut.value
+        if math.isinf(self.best_obj):
+            self.best_x = None
+        self.elapsed_ms = lib.chap_run_elapsed_ms(handle)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load_library().chap_run_destroy(h)
+            self._h = None
+
+
+class Problem:
+    """chap_problem_create on a MIP in original form (host numpy arrays)."""
+
+    def __init__(self, mip, feas_tol: float = 1e-6, graph_iters: int = 0, short_max: int = 0, chunk_min: int = 0,
+                 chunk_len: int = 0):
+        lib = load_library()
+        self._keep = dict(
+            csr_row_ptr=np.ascontiguousarray(mip.csr_row_ptr, dtype=np.int64),
+            csr_col=np.ascontiguousarray(mip.csr_col, dtype=np.int32),
+            csr_val=np.ascontiguousarray(mip.csr_val, dtype=np.float64),
+            csc_col_ptr=np.ascontiguousarray(mip.csc_col_ptr, dtype=np.int64),
+            csc_row=np.ascontiguousarray(mip.csc_row, dtype=np.int32),
+            csc_val=np.ascontiguousarray(mip.csc_val, dtype=np.float64),
+            sense=np.ascontiguousarray(mip.sense, dtype=np.uint8),
+            rhs=np.ascontiguousarray(mip.rhs, dtype=np.float64),
+            lb=np.ascontiguousarray(mip.lb, dtype=np.float64),
+            ub=np.ascontiguousarray(mip.ub, dtype=np.float64),
+            is_int=np.ascontiguousarray(mip.is_int, dtype=np.uint8),
+            obj=np.ascontiguousarray(mip.obj, dtype=np.float64),
+        )
+        o = default_options()
+        o.feas_tol = feas_tol
+        o.graph_iters = graph_iters
+        o.short_max = short_max
+        o.chunk_min = chunk_min
+        o.chunk_len = chunk_len
+        h = ctypes.c_void_p()
+        k = self._keep
+        _check(lib.chap_problem_create(ctypes.byref(h), int(mip.n), int(mip.m), _ptr(k["csr_row_ptr"]),
+                                       _ptr(k["csr_col"]), _ptr(k["csr_val"]), _ptr(k["csc_col_ptr"]),
+                                       _ptr(k["csc_row"]), _ptr(k["csc_val"]), _ptr(k["sense"]), _ptr(k["rhs"]),
+                                       _ptr(k["lb"]), _ptr(k["ub"]), _ptr(k["is_int"]), _ptr(k["obj"]),
+                                       ctypes.byref(o)))
+        self._h = h
+        self._keep = None
+        self.n = int(mip.n)
+        self.m = int(mip.m)
+        self.mp = int(lib.chap_problem_num_norm_rows(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load_library().chap_problem_destroy(h)
+            self._h = None
+
+    def norm_row_map(self):
+        orig = np.empty(self.mp, dtype=np.int32)
+        sign = np.empty(self.mp, dtype=np.int8)
+        _check(load_library().chap_problem_norm_row_map(self._h, _ptr(orig), _ptr(sign)))
+        return orig, sign
+
+    def best_shift(self, x, w, cutoff_rhs: float = math.inf, out_shift=None, out_score=None, stream=None):
+        """chap_best_shift on device tensors x (n, float64) and w (m'+1,
+        float32); returns (xhat, score) device tensors."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n
+        assert w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.numel() == self.mp + 1
+        if out_shift is None:
+            out_shift = torch.empty_like(x)
+        if out_score is None:
+            out_score = torch.empty_like(x)
+        _check(load_library().chap_best_shift(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                              float(cutoff_rhs), ctypes.c_void_p(out_shift.data_ptr()),
+                                              ctypes.c_void_p(out_score.data_ptr()), _stream_handle(stream)))
+        return out_shift, out_score
+
+    def last_pass_ms(self) -> float:
+        """chap_best_shift_pass_ms: HIP-event duration of the last pass."""
+        ms = ctypes.c_double()
+        _check(load_library().chap_best_shift_pass_ms(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def tabu_run(self, iters: int, tenure: int, seed: int, x0=None, stream=None) -> Run:
+        """chap_tabu_run: synchronous; returns the trace and final state."""
+        h = ctypes.c_void_p()
+        x0p = None
+        if x0 is not None:
+            x0 = np.ascontiguousarray(x0, dtype=np.float64)
+            assert x0.shape[0] == self.n
+            x0p = _ptr(x0)
+        _check(load_library().chap_tabu_run(self._h, int(iters), int(tenure), int(seed), x0p, ctypes.byref(h),
+                                            _stream_handle(stream)))
+        return Run(h, self.n, self.mp)

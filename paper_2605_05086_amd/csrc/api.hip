@@ -1,0 +1,682 @@
+// C ABI of the gfx950 tabu-search library: problem creation (validation,
+// normalisation to '<=' rows, column routing, upload), the single best-shift
+// pass and the graph-captured tabu walk.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "chap_internal.h"
+
+using namespace chap;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+#define CHAP_HIP(call)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return fail(CHAP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device allocations owned by one object, freed together.
+struct DeviceArena {
+  std::vector<void*> ptrs;
+  ~DeviceArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return hipSuccess;
+  }
+  template <typename T>
+  hipError_t upload(T** out, const std::vector<T>& v) {
+    hipError_t e = alloc(out, v.size());
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+};
+
+}  // namespace
+
+struct chap_problem {
+  int32_t n = 0, m = 0, mp = 0;
+  double eps = 1e-6;
+  chap_options opt{};
+  int32_t obj_integral = 1;
+  int32_t max_col_deg = 0;
+  // host copies used by runs
+  std::vector<double> lb, ub, obj;
+  std::vector<uint8_t> is_int;
+  std::vector<int32_t> nidx;  // normalised index of each stored row
+  std::vector<uint8_t> pair;  // stored row is an equality (two normalised rows)
+  std::vector<int32_t> norm_orig;
+  std::vector<int8_t> norm_sign;
+  // device
+  DeviceArena arena;
+  DevProblem dev{};
+  PassPlan plan{};
+  const int32_t* d_nidx = nullptr;
+  const uint8_t* d_pair = nullptr;
+  int32_t device = 0;
+  // scratch of chap_best_shift
+  RowState* bs_rs = nullptr;
+  WalkState* bs_state = nullptr;
+  double* bs_partial = nullptr;
+  uint32_t* bs_ticket = nullptr;
+  hipEvent_t pass_ev[2] = {nullptr, nullptr};
+  bool pass_timed = false;
+  ~chap_problem() {
+    for (hipEvent_t e : pass_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+struct chap_run {
+  std::vector<chap_trace_record> trace;
+  std::vector<double> x, resid, best_x;
+  std::vector<float> w;
+  double best_obj = HUGE_VAL;
+  double cutoff_rhs = HUGE_VAL;
+  bool has_best = false;
+  double elapsed_ms = 0.0;
+};
+
+namespace {
+
+uint64_t splitmix64_output(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+struct WalkBuffers {
+  DeviceArena arena;
+  double *x = nullptr, *xhat = nullptr, *s = nullptr, *best_x = nullptr, *partial = nullptr, *argmax_partial = nullptr;
+  int32_t* tabu = nullptr;
+  RowState* rs = nullptr;
+  WalkState* st = nullptr;
+  chap_trace_record* trace = nullptr;
+  uint32_t* ticket = nullptr;
+};
+
+}  // namespace
+
+extern "C" {
+
+void chap_options_default(chap_options* opt) {
+  if (!opt) return;
+  opt->feas_tol = 1e-6;
+  opt->graph_iters = 64;
+  opt->short_max = kShortMax;
+  opt->chunk_min = 4096;
+  opt->chunk_len = 4096;
+}
+
+const char* chap_last_error(void) { return g_error.c_str(); }
+
+int32_t chap_problem_num_norm_rows(const chap_problem* p) { return p ? p->mp : -1; }
+
+int chap_problem_norm_row_map(const chap_problem* p, int32_t* orig_row, int8_t* sign) {
+  if (!p || (p->mp > 0 && (!orig_row || !sign))) return fail(CHAP_EINVAL, "chap_problem_norm_row_map: null argument");
+  std::copy(p->norm_orig.begin(), p->norm_orig.end(), orig_row);
+  std::copy(p->norm_sign.begin(), p->norm_sign.end(), sign);
+  return CHAP_OK;
+}
+
+void chap_problem_destroy(chap_problem* p) { delete p; }
+
+int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t* csr_row_ptr, const int32_t* csr_col,
+                        const double* csr_val, const int64_t* csc_col_ptr, const int32_t* csc_row,
+                        const double* csc_val, const char* sense, const double* rhs, const double* lb,
+                        const double* ub, const uint8_t* is_int, const double* obj, const chap_options* opt) {
+  if (!out) return fail(CHAP_EINVAL, "chap_problem_create: out is null");
+  if (n < 0 || m < 0) return fail(CHAP_EINVAL, "chap_problem_create: negative size");
+  if (!csr_row_ptr || !csc_col_ptr) return fail(CHAP_EINVAL, "chap_problem_create: null row/column pointers");
+  if (n > 0 && (!lb || !ub || !is_int || !obj)) return fail(CHAP_EINVAL, "chap_problem_create: null variable array");
+  if (m > 0 && (!sense || !rhs)) return fail(CHAP_EINVAL, "chap_problem_create: null row array");
+  chap_options o;
+  chap_options_default(&o);
+  if (opt) {
+    if (!(opt->feas_tol >= 0.0) || !std::isfinite(opt->feas_tol))
+      return fail(CHAP_EINVAL, "chap_problem_create: feas_tol must be finite and >= 0");
+    o.feas_tol = opt->feas_tol;
+    if (opt->graph_iters < 0 || opt->short_max < 0 || opt->short_max > kShortMax || opt->chunk_min < 0 ||
+        opt->chunk_len < 0)
+      return fail(CHAP_EINVAL, "chap_problem_create: option out of range");
+    if (opt->graph_iters) o.graph_iters = opt->graph_iters;
+    if (opt->short_max) o.short_max = opt->short_max;
+    if (opt->chunk_min) o.chunk_min = opt->chunk_min;
+    if (opt->chunk_len) o.chunk_len = opt->chunk_len;
+  }
+  // ---- structural checks -------------------------------------------------
+  if (csr_row_ptr[0] != 0) return fail(CHAP_EINVAL, "csr_row_ptr[0] must be 0");
+  for (int32_t i = 0; i < m; ++i)
+    if (csr_row_ptr[i + 1] < csr_row_ptr[i]) return fail(CHAP_EINVAL, "csr_row_ptr decreases at row " + std::to_string(i));
+  const int64_t nnz_in = csr_row_ptr[m];
+  if (csc_col_ptr[0] != 0) return fail(CHAP_EINVAL, "csc_col_ptr[0] must be 0");
+  for (int32_t j = 0; j < n; ++j)
+    if (csc_col_ptr[j + 1] < csc_col_ptr[j]) return fail(CHAP_EINVAL, "csc_col_ptr decreases at column " + std::to_string(j));
+  if (csc_col_ptr[n] != nnz_in) return fail(CHAP_EINVAL, "CSR and CSC hold different numbers of entries");
+  if (nnz_in > 0 && (!csr_col || !csr_val || !csc_row || !csc_val))
+    return fail(CHAP_EINVAL, "chap_problem_create: null nonzero arrays");
+  for (int64_t k = 0; k < nnz_in; ++k) {
+    if (csr_col[k] < 0 || csr_col[k] >= n) return fail(CHAP_EINVAL, "csr_col out of range at entry " + std::to_string(k));
+    if (!std::isfinite(csr_val[k])) return fail(CHAP_EINVAL, "non-finite csr_val at entry " + std::to_string(k));
+    if (csc_row[k] < 0 || csc_row[k] >= m) return fail(CHAP_EINVAL, "csc_row out of range at entry " + std::to_string(k));
+    if (!std::isfinite(csc_val[k])) return fail(CHAP_EINVAL, "non-finite csc_val at entry " + std::to_string(k));
+  }
+  for (int32_t i = 0; i < m; ++i) {
+    if (sense[i] != 'L' && sense[i] != 'G' && sense[i] != 'E')
+      return fail(CHAP_EINVAL, "row " + std::to_string(i) + ": sense must be 'L', 'G' or 'E'");
+    if (!std::isfinite(rhs[i])) return fail(CHAP_EINVAL, "row " + std::to_string(i) + ": rhs must be finite");
+  }
+  std::unique_ptr<chap_problem> P(new chap_problem());
+  P->n = n;
+  P->m = m;
+  P->opt = o;
+  P->eps = o.feas_tol;
+  P->lb.resize(n);
+  P->ub.resize(n);
+  P->obj.assign(obj, obj + n);
+  P->is_int.resize(n);
+  for (int32_t j = 0; j < n; ++j) {
+    if (is_int[j] > 1) return fail(CHAP_EINVAL, "variable " + std::to_string(j) + ": is_int must be 0 or 1");
+    double l = lb[j], u = ub[j];
+    if (std::isnan(l) || std::isnan(u)) return fail(CHAP_EINVAL, "variable " + std::to_string(j) + ": NaN bound");
+    if (is_int[j]) {
+      l = std::ceil(l);
+      u = std::floor(u);
+    }
+    if (l > u || l == HUGE_VAL || u == -HUGE_VAL)
+      return fail(CHAP_EINVAL, "variable " + std::to_string(j) + ": empty domain");
+    if (!std::isfinite(obj[j])) return fail(CHAP_EINVAL, "variable " + std::to_string(j) + ": objective must be finite");
+    P->lb[j] = l;
+    P->ub[j] = u;
+    P->is_int[j] = is_int[j];
+    if (obj[j] != 0.0 && (!is_int[j] || std::floor(obj[j]) != obj[j])) P->obj_integral = 0;
+  }
+  // ---- CSR and CSC must be the same matrix (stored zeros dropped) --------
+  // transpose of the CSR, rows ascending within each column
+  std::vector<int64_t> tptr((size_t)n + 1, 0);
+  for (int64_t k = 0; k < nnz_in; ++k)
+    if (csr_val[k] != 0.0) tptr[csr_col[k] + 1] += 1;
+  for (int32_t j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
+  const int64_t nnz = tptr[n];
+  if (nnz >= (int64_t)INT32_MAX) return fail(CHAP_EINVAL, "more than 2^31-1 nonzeros");
+  std::vector<int32_t> trow(nnz);
+  std::vector<double> tval(nnz);
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int32_t i = 0; i < m; ++i)
+      for (int64_t k = csr_row_ptr[i]; k < csr_row_ptr[i + 1]; ++k) {
+        if (csr_val[k] == 0.0) continue;
+        const int32_t c = csr_col[k];
+        trow[fill[c]] = i;
+        tval[fill[c]] = csr_val[k];
+        fill[c] += 1;
+      }
+  }
+  {
+    std::vector<std::pair<int32_t, double>> colbuf;
+    for (int32_t j = 0; j < n; ++j) {
+      colbuf.clear();
+      for (int64_t k = csc_col_ptr[j]; k < csc_col_ptr[j + 1]; ++k)
+        if (csc_val[k] != 0.0) colbuf.emplace_back(csc_row[k], csc_val[k]);
+      if ((int64_t)colbuf.size() != tptr[j + 1] - tptr[j])
+        return fail(CHAP_EINVAL, "column " + std::to_string(j) + ": CSR and CSC differ");
+      std::sort(colbuf.begin(), colbuf.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) { return a.first < b.first; });
+      for (size_t q = 0; q < colbuf.size(); ++q) {
+        const int64_t t = tptr[j] + (int64_t)q;
+        if (q > 0 && (colbuf[q].first == colbuf[q - 1].first || trow[t] == trow[t - 1]))
+          return fail(CHAP_EINVAL, "column " + std::to_string(j) + ": repeated row " + std::to_string(colbuf[q].first));
+        if (colbuf[q].first != trow[t] || colbuf[q].second != tval[t])
+          return fail(CHAP_EINVAL, "column " + std::to_string(j) + ": CSR and CSC differ at row " +
+                                       std::to_string(colbuf[q].first));
+      }
+    }
+  }
+  // ---- normalisation: one stored row per original row --------------------
+  std::vector<double> sgn(m);
+  std::vector<int32_t> rptr((size_t)m + 1, 0);
+  std::vector<int32_t> rcol;
+  std::vector<double> rval, rrhs(m);
+  rcol.reserve(nnz);
+  rval.reserve(nnz);
+  P->nidx.resize(m);
+  P->pair.resize(m);
+  int32_t mp = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    const double s = (sense[i] == 'G') ? -1.0 : 1.0;
+    sgn[i] = s;
+    for (int64_t k = csr_row_ptr[i]; k < csr_row_ptr[i + 1]; ++k) {
+      if (csr_val[k] == 0.0) continue;
+      rcol.push_back(csr_col[k]);
+      rval.push_back(s * csr_val[k]);
+    }
+    rptr[i + 1] = (int32_t)rcol.size();
+    rrhs[i] = s * rhs[i];
+    P->nidx[i] = mp;
+    P->pair[i] = sense[i] == 'E';
+    P->norm_orig.push_back(i);
+    P->norm_sign.push_back((int8_t)s);
+    mp += 1;
+    if (sense[i] == 'E') {
+      P->norm_orig.push_back(i);
+      P->norm_sign.push_back(-1);
+      mp += 1;
+    }
+  }
+  P->mp = mp;
+  // column view in the caller's CSC order, stored orientation
+  std::vector<int32_t> cptr((size_t)n + 1, 0), crow;
+  std::vector<double> cval;
+  crow.reserve(nnz);
+  cval.reserve(nnz);
+  std::vector<int32_t> deg(n), ne(n);
+  for (int32_t j = 0; j < n; ++j) {
+    int32_t d = 0, e = 0;
+    for (int64_t k = csc_col_ptr[j]; k < csc_col_ptr[j + 1]; ++k) {
+      if (csc_val[k] == 0.0) continue;
+      const int32_t i = csc_row[k];
+      crow.push_back(i);
+      cval.push_back(sgn[i] * csc_val[k]);
+      d += 1;
+      e += P->pair[i] ? 2 : 1;
+    }
+    cptr[j + 1] = (int32_t)crow.size();
+    deg[j] = d;
+    ne[j] = e + (obj[j] != 0.0 ? 1 : 0);
+    P->max_col_deg = std::max(P->max_col_deg, d);
+  }
+  // ---- column classes and work lists --------------------------------------
+  std::vector<uint8_t> cls(n);
+  for (int32_t j = 0; j < n; ++j) {
+    const double l = P->lb[j], u = P->ub[j];
+    if (P->is_int[j] && l == 0.0 && u == 1.0)
+      cls[j] = COL_BINARY;
+    else if (P->is_int[j] && std::isfinite(l) && std::isfinite(u) && u - l + 1.0 <= (double)kNarrowBins)
+      cls[j] = COL_NARROW;
+    else
+      cls[j] = COL_GENERAL;
+  }
+  std::vector<std::vector<int32_t>> seg(kShortMax + 2);
+  std::vector<int32_t> flip, narrow, sortl[kSortCaps];
+  std::vector<ChunkTask> chunks;
+  std::vector<LongTask> longs;
+  int32_t nlongnarrow = 0;
+  int64_t long_total = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    if (ne[j] <= o.short_max) {
+      seg[cls[j] == COL_BINARY ? 0 : 1 + deg[j]].push_back(j);
+    } else if (cls[j] == COL_BINARY) {
+      flip.push_back(j);
+    } else if (cls[j] == COL_NARROW) {
+      if (ne[j] <= o.chunk_min) {
+        narrow.push_back(j);
+      } else {
+        const int32_t nch = (deg[j] + o.chunk_len - 1) / o.chunk_len;
+        const int32_t first = (int32_t)chunks.size();
+        for (int32_t q = 0; q < nch; ++q) {
+          ChunkTask t;
+          t.col = j;
+          t.e_beg = cptr[j] + q * o.chunk_len;
+          t.e_end = std::min(cptr[j + 1], t.e_beg + o.chunk_len);
+          t.slot = nlongnarrow;
+          t.first = first;
+          t.nchunks = nch;
+          chunks.push_back(t);
+        }
+        nlongnarrow += 1;
+      }
+    } else {
+      const int32_t entries = ne[j] + 2;
+      int c = 0;
+      while (c < kSortCaps && kSortCap[c] < entries) ++c;
+      if (c < kSortCaps) {
+        sortl[c].push_back(j);
+      } else {
+        int32_t cap = kSortCap[kSortCaps - 1];
+        while (cap < entries) cap <<= 1;
+        LongTask t;
+        t.col = j;
+        t.cap = cap;
+        t.offset = long_total;
+        long_total += cap;
+        longs.push_back(t);
+      }
+    }
+  }
+  // binaries by degree so that a wavefront's lanes loop equally long
+  std::stable_sort(seg[0].begin(), seg[0].end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  std::vector<int32_t> short_list;
+  P->plan.short_segs[0] = 0;
+  for (int g = 0; g < kShortMax + 2; ++g) {
+    for (int32_t j : seg[g]) short_list.push_back(j);
+    while (short_list.size() % 256) short_list.push_back(-1);
+    P->plan.short_segs[g + 1] = (int32_t)(short_list.size() / 256);
+  }
+  // ---- upload --------------------------------------------------------------
+  {
+    int dev = 0;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(CHAP_ENOTBUILT, "no HIP device visible");
+    CHAP_HIP(hipGetDevice(&dev));
+    P->device = dev;
+  }
+  DeviceArena& A = P->arena;
+  DevProblem& D = P->dev;
+  D.n = n;
+  D.ms = m;
+  D.eps = P->eps;
+  int32_t *d_cptr, *d_crow, *d_rptr, *d_rcol;
+  double *d_cval, *d_rval, *d_rrhs, *d_lb, *d_ub, *d_obj;
+  uint8_t *d_cls, *d_isint, *d_pair;
+  int32_t* d_nidx;
+  CHAP_HIP(A.upload(&d_cptr, cptr));
+  CHAP_HIP(A.upload(&d_crow, crow));
+  CHAP_HIP(A.upload(&d_cval, cval));
+  CHAP_HIP(A.upload(&d_rptr, rptr));
+  CHAP_HIP(A.upload(&d_rcol, rcol));
+  CHAP_HIP(A.upload(&d_rval, rval));
+  CHAP_HIP(A.upload(&d_rrhs, rrhs));
+  CHAP_HIP(A.upload(&d_lb, P->lb));
+  CHAP_HIP(A.upload(&d_ub, P->ub));
+  CHAP_HIP(A.upload(&d_obj, P->obj));
+  CHAP_HIP(A.upload(&d_cls, cls));
+  CHAP_HIP(A.upload(&d_isint, P->is_int));
+  CHAP_HIP(A.upload(&d_pair, P->pair));
+  CHAP_HIP(A.upload(&d_nidx, P->nidx));
+  D.col_ptr = d_cptr;
+  D.col_row = d_crow;
+  D.col_val = d_cval;
+  D.row_ptr = d_rptr;
+  D.row_col = d_rcol;
+  D.row_val = d_rval;
+  D.row_rhs = d_rrhs;
+  D.lb = d_lb;
+  D.ub = d_ub;
+  D.obj = d_obj;
+  D.cls = d_cls;
+  D.is_int = d_isint;
+  P->d_pair = d_pair;
+  P->d_nidx = d_nidx;
+  PassPlan& L = P->plan;
+  L.short_max = o.short_max;
+  if (!short_list.empty()) {
+    int32_t* d;
+    CHAP_HIP(A.upload(&d, short_list));
+    L.short_cols = d;
+    L.n_short = (int32_t)short_list.size();
+  }
+  if (!flip.empty()) {
+    int32_t* d;
+    CHAP_HIP(A.upload(&d, flip));
+    L.flip_cols = d;
+    L.n_flip = (int32_t)flip.size();
+  }
+  if (!narrow.empty()) {
+    int32_t* d;
+    CHAP_HIP(A.upload(&d, narrow));
+    L.narrow_cols = d;
+    L.n_narrow = (int32_t)narrow.size();
+  }
+  if (!chunks.empty()) {
+    ChunkTask* d;
+    CHAP_HIP(A.upload(&d, chunks));
+    L.chunks = d;
+    L.n_chunks = (int32_t)chunks.size();
+    CHAP_HIP(A.alloc(&L.partials, chunks.size()));
+    CHAP_HIP(A.alloc(&L.chunk_counters, (size_t)nlongnarrow));
+    CHAP_HIP(hipMemset(L.chunk_counters, 0, sizeof(uint32_t) * (size_t)nlongnarrow));
+  }
+  for (int c = 0; c < kSortCaps; ++c) {
+    if (sortl[c].empty()) continue;
+    int32_t* d;
+    CHAP_HIP(A.upload(&d, sortl[c]));
+    L.sort_cols[c] = d;
+    L.n_sort[c] = (int32_t)sortl[c].size();
+  }
+  if (!longs.empty()) {
+    LongTask* d;
+    CHAP_HIP(A.upload(&d, longs));
+    L.long_tasks = d;
+    L.n_long = (int32_t)longs.size();
+    CHAP_HIP(A.alloc(&L.long_pos, (size_t)long_total));
+    CHAP_HIP(A.alloc(&L.long_delta, (size_t)long_total));
+    CHAP_HIP(A.alloc(&L.long_marker, (size_t)long_total));
+  }
+  CHAP_HIP(A.alloc(&P->bs_rs, (size_t)m));
+  CHAP_HIP(A.alloc(&P->bs_state, 1));
+  CHAP_HIP(A.alloc(&P->bs_partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&P->bs_ticket, 1));
+  CHAP_HIP(hipMemset(P->bs_ticket, 0, sizeof(uint32_t)));
+  CHAP_HIP(hipEventCreate(&P->pass_ev[0]));
+  CHAP_HIP(hipEventCreate(&P->pass_ev[1]));
+  CHAP_HIP(hipDeviceSynchronize());
+  *out = P.release();
+  return CHAP_OK;
+}
+
+int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double cutoff_rhs, double* d_shift,
+                    double* d_score, void* hip_stream) {
+  if (!p) return fail(CHAP_EINVAL, "chap_best_shift: null problem");
+  if (p->n > 0 && (!d_x || !d_shift || !d_score)) return fail(CHAP_EINVAL, "chap_best_shift: null device array");
+  if (!d_w) return fail(CHAP_EINVAL, "chap_best_shift: null weights");
+  if (std::isnan(cutoff_rhs)) return fail(CHAP_EINVAL, "chap_best_shift: cutoff_rhs is NaN");
+  hipStream_t s = (hipStream_t)hip_stream;
+  CHAP_HIP(launch_residual(p->dev, d_x, p->bs_rs, s));
+  CHAP_HIP(launch_scatter_weights(p->d_nidx, p->d_pair, d_w, p->bs_rs, p->m, s));
+  const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
+  CHAP_HIP(launch_state_init(p->dev, d_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0, p->obj_integral,
+                             cut, d_w + p->mp, 0, s));
+  CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
+  if (p->n > 0) CHAP_HIP(launch_best_shift_pass(p->dev, p->plan, d_x, p->bs_rs, p->bs_state, d_shift, d_score, s));
+  CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
+  p->pass_timed = true;
+  return CHAP_OK;
+}
+
+int chap_best_shift_pass_ms(chap_problem* p, double* ms) {
+  if (!p || !ms) return fail(CHAP_EINVAL, "chap_best_shift_pass_ms: null argument");
+  *ms = 0.0;
+  if (!p->pass_timed) return CHAP_OK;
+  CHAP_HIP(hipEventSynchronize(p->pass_ev[1]));
+  float t = 0.0f;
+  CHAP_HIP(hipEventElapsedTime(&t, p->pass_ev[0], p->pass_ev[1]));
+  *ms = t;
+  return CHAP_OK;
+}
+
+int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed, const double* x0, chap_run** out,
+                  void* hip_stream) {
+  if (!p || !out) return fail(CHAP_EINVAL, "chap_tabu_run: null argument");
+  if (iters < 0 || tenure < 0 || iters + (int64_t)tenure >= (int64_t)INT32_MAX)
+    return fail(CHAP_EINVAL, "chap_tabu_run: iters and tenure must be >= 0 with iters + tenure < 2^31");
+  const int32_t n = p->n, m = p->m;
+  std::vector<double> xs(n);
+  if (x0) {
+    for (int32_t j = 0; j < n; ++j) {
+      if (!std::isfinite(x0[j])) return fail(CHAP_EINVAL, "chap_tabu_run: non-finite start value at " + std::to_string(j));
+      xs[j] = x0[j];
+    }
+  } else {
+    for (int32_t j = 0; j < n; ++j) {
+      const double l = p->lb[j], u = p->ub[j];
+      if (seed != 0 && p->is_int[j] && std::isfinite(l) && std::isfinite(u)) {
+        const uint64_t h = splitmix64_output(seed, (uint64_t)j);
+        const uint64_t width = (uint64_t)(u - l) + 1;
+        xs[j] = l + (double)(h % width);
+      } else {
+        double v = 0.0;
+        if (v < l) v = l;
+        if (v > u) v = u;
+        xs[j] = v;
+      }
+    }
+  }
+  WalkBuffers B;
+  DeviceArena& A = B.arena;
+  CHAP_HIP(A.alloc(&B.x, n));
+  CHAP_HIP(A.alloc(&B.xhat, n));
+  CHAP_HIP(A.alloc(&B.s, n));
+  CHAP_HIP(A.alloc(&B.best_x, n));
+  CHAP_HIP(A.alloc(&B.tabu, n));
+  CHAP_HIP(A.alloc(&B.rs, m));
+  CHAP_HIP(A.alloc(&B.st, 1));
+  CHAP_HIP(A.alloc(&B.trace, (size_t)std::max<int64_t>(iters, 1)));
+  CHAP_HIP(A.alloc(&B.partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&B.argmax_partial, 4 * kArgmaxBlocks));
+  CHAP_HIP(A.alloc(&B.ticket, 1));
+  hipStream_t user = (hipStream_t)hip_stream;
+  hipStream_t s;
+  CHAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } sg{s};
+  hipEvent_t e_user, e0, e1;
+  CHAP_HIP(hipEventCreate(&e_user));
+  CHAP_HIP(hipEventCreate(&e0));
+  CHAP_HIP(hipEventCreate(&e1));
+  struct EventGuard {
+    hipEvent_t a, b, c;
+    ~EventGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      (void)hipEventDestroy(c);
+    }
+  } eg{e_user, e0, e1};
+  CHAP_HIP(hipEventRecord(e_user, user));
+  CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
+  CHAP_HIP(hipMemsetAsync(B.ticket, 0, sizeof(uint32_t), s));
+  CHAP_HIP(hipMemsetAsync(B.st, 0, sizeof(WalkState), s));
+  if (n > 0) {
+    CHAP_HIP(hipMemcpyAsync(B.x, xs.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, B.tabu, -1, (int64_t)n);
+    CHAP_HIP(hipGetLastError());
+  }
+  CHAP_HIP(launch_residual(p->dev, B.x, B.rs, s));
+  CHAP_HIP(launch_set_weights_unit(p->d_pair, B.rs, m, s));
+  CHAP_HIP(launch_state_init(p->dev, B.x, B.rs, B.st, B.partial, B.ticket, iters, tenure, p->obj_integral, HUGE_VAL,
+                             nullptr, 1, s));
+  CHAP_HIP(launch_copy_best(B.x, B.best_x, B.st, n, s));
+  const int apply_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (std::max(m, p->max_col_deg) + 255) / 256));
+  double ms_total = 0.0;
+  if (iters > 0) {
+    const int64_t K = std::min<int64_t>(iters, p->opt.graph_iters);
+    hipGraph_t graph;
+    CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t cap_err = hipSuccess;
+    for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
+      if (n > 0) cap_err = launch_best_shift_pass(p->dev, p->plan, B.x, B.rs, B.st, B.xhat, B.s, s);
+      if (cap_err == hipSuccess)
+        cap_err = launch_walk_step(p->dev, B.x, B.xhat, B.s, B.rs, B.tabu, B.st, B.trace, B.best_x, B.argmax_partial,
+                                   apply_blocks, s);
+    }
+    hipError_t end_err = hipStreamEndCapture(s, &graph);
+    if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));
+    if (end_err != hipSuccess) return fail(CHAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(end_err));
+    hipGraphExec_t exec;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(CHAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    const int64_t launches = (iters + K - 1) / K;
+    hipError_t le = hipEventRecord(e0, s);
+    for (int64_t q = 0; q < launches && le == hipSuccess; ++q) le = hipGraphLaunch(exec, s);
+    if (le == hipSuccess) le = hipEventRecord(e1, s);
+    if (le == hipSuccess) le = hipStreamSynchronize(s);
+    float ms = 0.0f;
+    if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (le != hipSuccess) return fail(CHAP_EHIP, std::string("graph launch: ") + hipGetErrorString(le));
+    ms_total = ms;
+  }
+  CHAP_HIP(hipStreamSynchronize(s));
+  std::unique_ptr<chap_run> R(new chap_run());
+  R->elapsed_ms = ms_total;
+  R->trace.resize((size_t)iters);
+  if (iters > 0)
+    CHAP_HIP(hipMemcpy(R->trace.data(), B.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
+  R->x.resize(n);
+  std::vector<double> bx(n);
+  if (n > 0) {
+    CHAP_HIP(hipMemcpy(R->x.data(), B.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    CHAP_HIP(hipMemcpy(bx.data(), B.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+  }
+  std::vector<RowState> rs(m);
+  if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), B.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
+  WalkState st;
+  CHAP_HIP(hipMemcpy(&st, B.st, sizeof(WalkState), hipMemcpyDeviceToHost));
+  R->resid.assign((size_t)p->mp + 1, 0.0);
+  R->w.assign((size_t)p->mp + 1, 0.0f);
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t k = p->nidx[i];
+    R->resid[k] = rs[i].r;
+    R->w[k] = rs[i].w0;
+    if (p->pair[i]) {
+      R->resid[k + 1] = -rs[i].r;
+      R->w[k + 1] = rs[i].w1;
+    }
+  }
+  R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
+  R->w[p->mp] = st.wc;
+  R->has_best = st.has_best != 0;
+  R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
+  R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
+  if (R->has_best) R->best_x = bx;
+  *out = R.release();
+  return CHAP_OK;
+}
+
+int chap_run_trace(const chap_run* r, const chap_trace_record** records, int64_t* count) {
+  if (!r || !records || !count) return fail(CHAP_EINVAL, "chap_run_trace: null argument");
+  *records = r->trace.data();
+  *count = (int64_t)r->trace.size();
+  return CHAP_OK;
+}
+
+int chap_run_state(const chap_run* r, double* x, double* resid, float* w, double* best_obj, double* best_x,
+                   double* cutoff_rhs) {
+  if (!r) return fail(CHAP_EINVAL, "chap_run_state: null run");
+  if (x) std::copy(r->x.begin(), r->x.end(), x);
+  if (resid) std::copy(r->resid.begin(), r->resid.end(), resid);
+  if (w) std::copy(r->w.begin(), r->w.end(), w);
+  if (best_obj) *best_obj = r->best_obj;
+  if (best_x && r->has_best) std::copy(r->best_x.begin(), r->best_x.end(), best_x);
+  if (cutoff_rhs) *cutoff_rhs = r->cutoff_rhs;
+  return CHAP_OK;
+}
+
+double chap_run_elapsed_ms(const chap_run* r) { return r ? r->elapsed_ms : 0.0; }
+
+void chap_run_destroy(chap_run* r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,790 @@
+// Best-shift pass kernels for gfx950 (wave64).
+//
+// One pass computes, for every variable j, the best shift (Eq. 1 of section
+// 3.1 "Best Shift Moves") at the current point: the flip for a binary
+// variable, and for every other variable the result of Algorithm 1 ("Best
+// Shift via Sort-Scan-Argmax"). Columns are routed by class and length:
+//
+//   k_short        one lane per column with at most 8 normalised entries;
+//                  scores every candidate position directly (bounds and
+//                  breakpoints, incumbent excluded) from the penalty
+//                  definition written in breakpoint form.
+//   k_flip_wave    one wavefront per longer binary column (flip score).
+//   k_narrow_wave  one wavefront per integer column with <= 64 values: the
+//                  sort of Algorithm 1 becomes a counting sort into 64 LDS
+//                  bins, the scan a wavefront prefix sum, the argmax a
+//                  wavefront reduction over candidate bins.
+//   k_narrow_chunk the same for long columns split over many workgroups;
+//                  partial bins are combined by the last workgroup to finish.
+//   k_sort_block   one workgroup per general column: LDS bitonic sort of the
+//                  breakpoints, block scan, block argmax.
+//   k_sort_long    general columns beyond the LDS capacity: the same steps in
+//                  global scratch memory.
+//
+// Phase 1 of Algorithm 1 emits, per row, the accumulators beta/alpha and up to
+// two triplets. Here the two triplets of an a_ij > 0 row, (t,-1,0) and
+// (t,+1,d), are merged into one entry "d applies strictly after t, and t is a
+// candidate"; an a_ij < 0 row gives "d applies from t on". The score at a
+// candidate position p is beta + (sum of entries applying at p) +
+// alpha [p > xbar], the value Algorithm 1's scan produces at that position.
+// Only finite positions inside [l, u] other than xbar are candidates, ties go
+// to the smallest position, and (xbar, 0) is returned when no candidate scores
+// above zero.
+
+#include <cfloat>
+#include <cmath>
+
+#include "chap_internal.h"
+
+namespace chap {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double breakpoint(double xb, double r, double a, double eps, bool is_int) {
+  double t = xb + (eps - r) / a;
+  if (is_int) t = (a > 0.0) ? floor(t) : ceil(t);
+  return t;
+}
+
+// Penalty p_ij of section 3.1 "Scoring Functions" for a residual r -> r2.
+__device__ __forceinline__ double penalty(double r, double r2, double w, double eps) {
+  const bool v = r > eps, v2 = r2 > eps;
+  if (!v && v2) return -w;
+  if (v && !v2) return w;
+  if (v && v2) {
+    if (r2 < r) return 0.5 * w;
+    if (r2 > r) return -0.5 * w;
+  }
+  return 0.0;
+}
+
+// Phase 1 of Algorithm 1 for one normalised row entry (a, r, w) of a
+// non-binary column at xbar. Updates beta/alpha, returns the merged entry.
+struct BkEntry {
+  double t;
+  double delta;
+  int marker;  // -1: applies from t on, +1: applies after t
+  bool has;
+};
+
+__device__ __forceinline__ BkEntry phase1(double xb, double r, double a, double w, double eps, bool is_int,
+                                          double& beta, double& alpha) {
+  BkEntry e;
+  e.t = breakpoint(xb, r, a, eps, is_int);
+  e.has = true;
+  if (a < 0.0) {
+    e.marker = -1;
+    if (xb < e.t) {
+      beta -= 0.5 * w;
+      alpha += w;
+      e.delta = 0.5 * w;
+    } else if (xb > e.t) {
+      beta -= w;
+      e.delta = w;
+    } else {
+      beta -= w;
+      alpha += w;
+      e.delta = 0.0;
+      e.has = false;
+    }
+  } else {
+    e.marker = 1;
+    if (xb > e.t) {
+      beta += w;
+      alpha -= w;
+      e.delta = -0.5 * w;
+    } else if (xb < e.t) {
+      e.delta = -w;
+    } else {
+      alpha -= w;
+      e.delta = 0.0;
+      e.has = false;
+    }
+  }
+  return e;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// (value desc, key asc) argmax across the wavefront; invalid lanes carry
+// value = -inf and key = INT_MAX.
+__device__ __forceinline__ void wave_argmax(double& v, int& key) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, kWave);
+    const int ok = __shfl_xor(key, o, kWave);
+    if (ov > v || (ov == v && ok < key)) {
+      v = ov;
+      key = ok;
+    }
+  }
+}
+
+__device__ __forceinline__ void write_result(double* xhat, double* sc, int j, bool found, double best, double bestp,
+                                             double xb) {
+  if (found && best > 0.0) {
+    xhat[j] = bestp + 0.0;  // canonical +0.0
+    sc[j] = best;
+  } else {
+    xhat[j] = xb;
+    sc[j] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_short: one lane per column.
+// ---------------------------------------------------------------------------
+
+struct ShortSegs {
+  int32_t wg_begin[kShortMax + 3];  // segment g: workgroups [wg_begin[g], wg_begin[g+1])
+};
+
+__device__ __forceinline__ void flip_column(const DevProblem& P, const double* x, const RowState* rs,
+                                            const WalkState* st, double* xhat, double* sc, int j) {
+  const double eps = P.eps;
+  const double xb = x[j];
+  const double xn = 1.0 - xb;
+  const double d = xn - xb;
+  double s = 0.0;
+  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  for (int e = beg; e < end; ++e) {
+    const RowState q = rs[P.col_row[e]];
+    const double r2 = q.r + P.col_val[e] * d;
+    s += penalty(q.r, r2, (double)q.w0, eps);
+    if (q.w1 >= 0.0f) s += penalty(-q.r, -r2, (double)q.w1, eps);
+  }
+  if (st->cut_active) {
+    const double c = P.obj[j];
+    if (c != 0.0) {
+      const double r2 = st->rc + c * d;
+      s += penalty(st->rc, r2, (double)st->wc, eps);
+    }
+  }
+  write_result(xhat, sc, j, true, s, xn, xb);
+}
+
+template <int D>
+__device__ __forceinline__ void short_general(const DevProblem& P, const double* x, const RowState* rs,
+                                              const WalkState* st, double* xhat, double* sc, int j) {
+  constexpr int NSLOT = 2 * D + 1;
+  const double eps = P.eps;
+  const double xb = x[j];
+  const bool isint = P.is_int[j] != 0;
+  const double l = P.lb[j], u = P.ub[j];
+  const int beg = P.col_ptr[j];
+  double tau[NSLOT];
+  double wv[NSLOT];
+  uint32_t valid = 0, apos = 0, sat0 = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int e = beg + q;
+    const RowState rr = rs[P.col_row[e]];
+    const double a = P.col_val[e];
+    const double t0 = breakpoint(xb, rr.r, a, eps, isint);
+    tau[2 * q] = t0;
+    wv[2 * q] = (double)rr.w0;
+    valid |= 1u << (2 * q);
+    if (a > 0.0) {
+      apos |= 1u << (2 * q);
+      if (xb <= t0) sat0 |= 1u << (2 * q);
+    } else if (xb >= t0) {
+      sat0 |= 1u << (2 * q);
+    }
+    if (rr.w1 >= 0.0f) {
+      const double t1 = breakpoint(xb, -rr.r, -a, eps, isint);
+      tau[2 * q + 1] = t1;
+      wv[2 * q + 1] = (double)rr.w1;
+      valid |= 1u << (2 * q + 1);
+      if (-a > 0.0) {
+        apos |= 1u << (2 * q + 1);
+        if (xb <= t1) sat0 |= 1u << (2 * q + 1);
+      } else if (xb >= t1) {
+        sat0 |= 1u << (2 * q + 1);
+      }
+    } else {
+      tau[2 * q + 1] = 0.0;
+      wv[2 * q + 1] = 0.0;
+    }
+  }
+  tau[2 * D] = 0.0;
+  wv[2 * D] = 0.0;
+  if (st->cut_active) {
+    const double c = P.obj[j];
+    if (c != 0.0) {
+      const double t2 = breakpoint(xb, st->rc, c, eps, isint);
+      tau[2 * D] = t2;
+      wv[2 * D] = (double)st->wc;
+      valid |= 1u << (2 * D);
+      if (c > 0.0) {
+        apos |= 1u << (2 * D);
+        if (xb <= t2) sat0 |= 1u << (2 * D);
+      } else if (xb >= t2) {
+        sat0 |= 1u << (2 * D);
+      }
+    }
+  }
+  bool found = false;
+  double best = 0.0, bestp = xb;
+  auto consider = [&](double p) {
+    if (!(p >= l && p <= u) || p == xb || !isfinite(p)) return;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+      if ((valid >> k) & 1u) {
+        const bool ap = (apos >> k) & 1u;
+        const bool s0 = (sat0 >> k) & 1u;
+        const bool s1 = ap ? (p <= tau[k]) : (p >= tau[k]);
+        double c;
+        if (s0)
+          c = s1 ? 0.0 : -wv[k];
+        else if (s1)
+          c = wv[k];
+        else
+          c = (ap ? (p < xb) : (p > xb)) ? 0.5 * wv[k] : -0.5 * wv[k];
+        v += c;
+      }
+    }
+    if (!found || v > best || (v == best && p < bestp)) {
+      found = true;
+      best = v;
+      bestp = p;
+    }
+  };
+  consider(l);
+  consider(u);
+#pragma unroll
+  for (int k = 0; k < NSLOT; ++k)
+    if ((valid >> k) & 1u) consider(tau[k]);
+  write_result(xhat, sc, j, found, best, bestp, xb);
+}
+
+__global__ __launch_bounds__(256) void k_short(DevProblem P, const double* __restrict__ x,
+                                               const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                               double* __restrict__ xhat, double* __restrict__ sc,
+                                               const int32_t* __restrict__ list, ShortSegs segs) {
+  if (st->k >= st->iters) return;
+  const int b = blockIdx.x;
+  const int j = list[b * 256 + threadIdx.x];
+  if (j < 0) return;
+  int g = 0;
+#pragma unroll
+  for (int q = 1; q < kShortMax + 2; ++q)
+    if (b >= segs.wg_begin[q]) g = q;
+  switch (g) {
+    case 0: flip_column(P, x, rs, st, xhat, sc, j); break;
+    case 1: short_general<0>(P, x, rs, st, xhat, sc, j); break;
+    case 2: short_general<1>(P, x, rs, st, xhat, sc, j); break;
+    case 3: short_general<2>(P, x, rs, st, xhat, sc, j); break;
+    case 4: short_general<3>(P, x, rs, st, xhat, sc, j); break;
+    case 5: short_general<4>(P, x, rs, st, xhat, sc, j); break;
+    case 6: short_general<5>(P, x, rs, st, xhat, sc, j); break;
+    case 7: short_general<6>(P, x, rs, st, xhat, sc, j); break;
+    case 8: short_general<7>(P, x, rs, st, xhat, sc, j); break;
+    default: short_general<8>(P, x, rs, st, xhat, sc, j); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_flip_wave: one wavefront per binary column.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_flip_wave(DevProblem P, const double* __restrict__ x,
+                                                   const RowState* __restrict__ rs,
+                                                   const WalkState* __restrict__ st, double* __restrict__ xhat,
+                                                   double* __restrict__ sc, const int32_t* __restrict__ list,
+                                                   int32_t count) {
+  if (st->k >= st->iters) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= count) return;
+  const int j = list[idx];
+  const double eps = P.eps;
+  const double xb = x[j];
+  const double xn = 1.0 - xb;
+  const double d = xn - xb;
+  double s = 0.0;
+  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  for (int e = beg + lane; e < end; e += kWave) {
+    const RowState q = rs[P.col_row[e]];
+    const double r2 = q.r + P.col_val[e] * d;
+    s += penalty(q.r, r2, (double)q.w0, eps);
+    if (q.w1 >= 0.0f) s += penalty(-q.r, -r2, (double)q.w1, eps);
+  }
+  if (lane == 0 && st->cut_active) {
+    const double c = P.obj[j];
+    if (c != 0.0) {
+      const double r2 = st->rc + c * d;
+      s += penalty(st->rc, r2, (double)st->wc, eps);
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) write_result(xhat, sc, j, true, s, xn, xb);
+}
+
+// ---------------------------------------------------------------------------
+// Narrow integer columns: counting sort into LDS bins.
+// ---------------------------------------------------------------------------
+
+// Adds one normalised entry of column (l, u, W) at xbar into the bins.
+__device__ __forceinline__ void narrow_entry(double xb, double r, double a, double w, double eps, double l,
+                                             double u, int W, double* bins, double& beta, double& alpha,
+                                             unsigned long long& cand) {
+  const BkEntry e = phase1(xb, r, a, w, eps, true, beta, alpha);
+  if (!e.has) return;
+  if (e.t < l) {
+    beta += e.delta;
+    return;
+  }
+  if (e.t > u) return;
+  const int k = (int)(e.t - l);
+  cand |= 1ull << k;
+  if (e.marker < 0)
+    atomicAdd(&bins[k], e.delta);
+  else if (k + 1 < W)
+    atomicAdd(&bins[k + 1], e.delta);
+}
+
+// Scan + argmax over the bins of one column, done by one wavefront. Lane k
+// holds bins[k]; returns (found, best, bestp) on lane 0.
+__device__ __forceinline__ void narrow_finish(double binv, double beta, double alpha, unsigned long long cand,
+                                              double xb, double l, int W, int lane, bool& found, double& best,
+                                              double& bestp) {
+  double v = (lane < W) ? binv : 0.0;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  const double pos = l + (double)lane;
+  double val = beta + v + ((pos > xb) ? alpha : 0.0);
+  const bool ok = lane < W && ((((cand >> lane) & 1ull) != 0) || lane == 0 || lane == W - 1) && pos != xb;
+  int key = ok ? lane : INT_MAX;
+  if (!ok) val = -DBL_MAX;
+  wave_argmax(val, key);
+  found = key != INT_MAX;
+  best = val;
+  bestp = found ? l + (double)key : xb;
+}
+
+__global__ __launch_bounds__(256) void k_narrow_wave(DevProblem P, const double* __restrict__ x,
+                                                     const RowState* __restrict__ rs,
+                                                     const WalkState* __restrict__ st, double* __restrict__ xhat,
+                                                     double* __restrict__ sc, const int32_t* __restrict__ list,
+                                                     int32_t count) {
+  if (st->k >= st->iters) return;
+  __shared__ double bins[4][kNarrowBins];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 4 + wv;
+  const bool active = idx < count;
+  bins[wv][lane] = 0.0;
+  __syncthreads();
+  const double eps = P.eps;
+  double beta = 0.0, alpha = 0.0;
+  unsigned long long cand = 0;
+  int j = 0, W = 0;
+  double xb = 0.0, l = 0.0, u = 0.0;
+  if (active) {
+    j = list[idx];
+    xb = x[j];
+    l = P.lb[j];
+    u = P.ub[j];
+    W = (int)(u - l) + 1;
+    const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+    for (int e = beg + lane; e < end; e += kWave) {
+      const RowState q = rs[P.col_row[e]];
+      const double a = P.col_val[e];
+      narrow_entry(xb, q.r, a, (double)q.w0, eps, l, u, W, bins[wv], beta, alpha, cand);
+      if (q.w1 >= 0.0f) narrow_entry(xb, -q.r, -a, (double)q.w1, eps, l, u, W, bins[wv], beta, alpha, cand);
+    }
+    if (lane == 0 && st->cut_active) {
+      const double c = P.obj[j];
+      if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins[wv], beta, alpha, cand);
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  beta = wave_sum(beta);
+  alpha = wave_sum(alpha);
+  cand = wave_or(cand);
+  bool found;
+  double best, bestp;
+  narrow_finish(bins[wv][lane], beta, alpha, cand, xb, l, W, lane, found, best, bestp);
+  if (lane == 0) write_result(xhat, sc, j, found, best, bestp, xb);
+}
+
+__global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double* __restrict__ x,
+                                                      const RowState* __restrict__ rs,
+                                                      const WalkState* __restrict__ st,
+                                                      double* __restrict__ xhat, double* __restrict__ sc,
+                                                      const ChunkTask* __restrict__ tasks, ChunkPartial* partials,
+                                                      uint32_t* counters) {
+  if (st->k >= st->iters) return;
+  __shared__ double bins[kNarrowBins];
+  __shared__ double red_b[4], red_a[4];
+  __shared__ unsigned long long red_c[4];
+  __shared__ uint32_t ticket;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid >> 6;
+  const ChunkTask T = tasks[blockIdx.x];
+  const int j = T.col;
+  const double eps = P.eps;
+  const double xb = x[j];
+  const double l = P.lb[j], u = P.ub[j];
+  const int W = (int)(u - l) + 1;
+  if (tid < kNarrowBins) bins[tid] = 0.0;
+  __syncthreads();
+  double beta = 0.0, alpha = 0.0;
+  unsigned long long cand = 0;
+  for (int e = T.e_beg + tid; e < T.e_end; e += blockDim.x) {
+    const RowState q = rs[P.col_row[e]];
+    const double a = P.col_val[e];
+    narrow_entry(xb, q.r, a, (double)q.w0, eps, l, u, W, bins, beta, alpha, cand);
+    if (q.w1 >= 0.0f) narrow_entry(xb, -q.r, -a, (double)q.w1, eps, l, u, W, bins, beta, alpha, cand);
+  }
+  if (tid == 0 && blockIdx.x == T.first && st->cut_active) {
+    const double c = P.obj[j];
+    if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
+  }
+  beta = wave_sum(beta);
+  alpha = wave_sum(alpha);
+  cand = wave_or(cand);
+  if (lane == 0) {
+    red_b[wv] = beta;
+    red_a[wv] = alpha;
+    red_c[wv] = cand;
+  }
+  __syncthreads();
+  ChunkPartial* mine = partials + blockIdx.x;
+  if (tid < kNarrowBins) mine->bins[tid] = bins[tid];
+  if (tid == 0) {
+    mine->beta = red_b[0] + red_b[1] + red_b[2] + red_b[3];
+    mine->alpha = red_a[0] + red_a[1] + red_a[2] + red_a[3];
+    mine->cand = red_c[0] | red_c[1] | red_c[2] | red_c[3];
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) ticket = atomicAdd(&counters[T.slot], 1u);
+  __syncthreads();
+  if (ticket != (uint32_t)(T.nchunks - 1)) return;
+  // last workgroup of this column: combine the partials in chunk order
+  __threadfence();
+  if (wv != 0) return;
+  double bv = 0.0, b = 0.0, a = 0.0;
+  unsigned long long c = 0;
+  for (int q = 0; q < T.nchunks; ++q) {
+    const ChunkPartial* pp = partials + T.first + q;
+    bv += pp->bins[lane];
+    if (lane == 0) {
+      b += pp->beta;
+      a += pp->alpha;
+      c |= pp->cand;
+    }
+  }
+  b = __shfl(b, 0, kWave);
+  a = __shfl(a, 0, kWave);
+  c = __shfl(c, 0, kWave);
+  bool found;
+  double best, bestp;
+  narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
+  if (lane == 0) {
+    write_result(xhat, sc, j, found, best, bestp, xb);
+    counters[T.slot] = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// General columns: Algorithm 1 with a bitonic sort.
+// ---------------------------------------------------------------------------
+
+// Sort key: position (canonical +0.0), then marker (-1 < +1 < pad).
+__device__ __forceinline__ bool key_greater(double pa, int ma, double pb, int mb) {
+  return pa > pb || (pa == pb && ma > mb);
+}
+
+constexpr int kPadMarker = 3;
+
+// Emits the entries of column j into (pos, marker, delta) arrays through an
+// atomic slot counter; beta/alpha are accumulated per thread.
+template <typename Emit>
+__device__ __forceinline__ void general_phase1(const DevProblem& P, const RowState* rs, const WalkState* st,
+                                               int j, double xb, int tid, int nthreads, double& beta,
+                                               double& alpha, Emit emit) {
+  const double eps = P.eps;
+  const bool isint = P.is_int[j] != 0;
+  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  for (int e = beg + tid; e < end; e += nthreads) {
+    const RowState q = rs[P.col_row[e]];
+    const double a = P.col_val[e];
+    BkEntry b0 = phase1(xb, q.r, a, (double)q.w0, eps, isint, beta, alpha);
+    if (b0.has) emit(b0.t + 0.0, b0.marker, b0.delta);
+    if (q.w1 >= 0.0f) {
+      BkEntry b1 = phase1(xb, -q.r, -a, (double)q.w1, eps, isint, beta, alpha);
+      if (b1.has) emit(b1.t + 0.0, b1.marker, b1.delta);
+    }
+  }
+  if (tid == 0) {
+    const double l = P.lb[j], u = P.ub[j];
+    if (isfinite(l)) emit(l + 0.0, -1, 0.0);
+    if (isfinite(u)) emit(u + 0.0, -1, 0.0);
+    if (st->cut_active) {
+      const double c = P.obj[j];
+      if (c != 0.0) {
+        BkEntry b2 = phase1(xb, st->rc, c, (double)st->wc, eps, isint, beta, alpha);
+        if (b2.has) emit(b2.t + 0.0, b2.marker, b2.delta);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+  return t;
+}
+
+// In-place ascending bitonic sort of cap (power of two) keyed entries.
+template <typename PosT, typename MarkT, typename DelT>
+__device__ __forceinline__ void bitonic_sort(PosT pos, MarkT mk, DelT dl, int cap) {
+  for (int size = 2; size <= cap; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int p = threadIdx.x; p < (cap >> 1); p += blockDim.x) {
+        const int i = 2 * p - (p & (stride - 1));
+        const int k = i + stride;
+        const bool up = (i & size) == 0;
+        const double pi = pos[i], pk = pos[k];
+        const int mi = mk[i], mk2 = mk[k];
+        if (key_greater(pi, mi, pk, mk2) == up) {
+          const double di = dl[i];
+          pos[i] = pk;
+          pos[k] = pi;
+          mk[i] = mk2;
+          mk[k] = mi;
+          dl[i] = dl[k];
+          dl[k] = di;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Scan (phase 3) and argmax (phase 4) over sorted entries; one workgroup.
+// Elements [0, cap) are split into contiguous per-thread runs.
+template <typename PosT, typename MarkT, typename DelT>
+__device__ __forceinline__ void scan_argmax(PosT pos, MarkT mk, DelT dl, int cap, double beta, double alpha,
+                                            double xb, double l, double u, double* red, int* redk, bool& found,
+                                            double& best, double& bestp) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (cap + nt - 1) / nt;
+  const int lo = min(cap, tid * per), hi = min(cap, lo + per);
+  double run = 0.0;
+  for (int i = lo; i < hi; ++i) run += dl[i];
+  // exclusive scan of run totals across the workgroup
+  const int lane = tid & 63, wv = tid >> 6;
+  double inc = run;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[wv] = inc;
+  __syncthreads();
+  double off = inc - run;
+  for (int q = 0; q < wv; ++q) off += red[q];
+  // per-entry score, best per thread (value desc, index asc)
+  double bv = -DBL_MAX;
+  int bk = INT_MAX;
+  double prefix = off;
+  for (int i = lo; i < hi; ++i) {
+    const double d = dl[i];
+    const double incl = prefix + d;
+    const double p = pos[i];
+    const int m = mk[i];
+    if (m != kPadMarker && isfinite(p) && p >= l && p <= u && p != xb) {
+      const double sigma = beta + ((m < 0) ? incl : prefix) + ((p > xb) ? alpha : 0.0);
+      if (sigma > bv) {
+        bv = sigma;
+        bk = i;
+      }
+    }
+    prefix = incl;
+  }
+  wave_argmax(bv, bk);
+  __syncthreads();
+  if (lane == 0) {
+    red[wv] = bv;
+    redk[wv] = bk;
+  }
+  __syncthreads();
+  bv = red[0];
+  bk = redk[0];
+  for (int q = 1; q < (nt >> 6); ++q) {
+    if (red[q] > bv || (red[q] == bv && redk[q] < bk)) {
+      bv = red[q];
+      bk = redk[q];
+    }
+  }
+  found = bk != INT_MAX;
+  best = bv;
+  bestp = found ? pos[bk] : xb;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* __restrict__ x,
+                                                    const RowState* __restrict__ rs,
+                                                    const WalkState* __restrict__ st, double* __restrict__ xhat,
+                                                    double* __restrict__ sc, const int32_t* __restrict__ list,
+                                                    int32_t count) {
+  if (st->k >= st->iters) return;
+  __shared__ double spos[CAP];
+  __shared__ double sdel[CAP];
+  __shared__ int smk[CAP];
+  __shared__ int scount;
+  __shared__ double red[8];
+  __shared__ int redk[8];
+  const int j = list[blockIdx.x];
+  const double xb = x[j];
+  if (threadIdx.x == 0) scount = 0;
+  __syncthreads();
+  double beta = 0.0, alpha = 0.0;
+  general_phase1(P, rs, st, j, xb, threadIdx.x, blockDim.x, beta, alpha, [&](double p, int m, double d) {
+    const int s = atomicAdd(&scount, 1);
+    spos[s] = p;
+    smk[s] = m;
+    sdel[s] = d;
+  });
+  beta = block_sum256(beta, red);
+  alpha = block_sum256(alpha, red);
+  __syncthreads();
+  const int cnt = scount;
+  for (int i = cnt + threadIdx.x; i < CAP; i += blockDim.x) {
+    spos[i] = HUGE_VAL;
+    smk[i] = kPadMarker;
+    sdel[i] = 0.0;
+  }
+  __syncthreads();
+  int cap = 64;
+  while (cap < cnt) cap <<= 1;
+  bitonic_sort(spos, smk, sdel, cap);
+  bool found;
+  double best, bestp;
+  scan_argmax(spos, smk, sdel, cap, beta, alpha, xb, P.lb[j], P.ub[j], red, redk, found, best, bestp);
+  if (threadIdx.x == 0) write_result(xhat, sc, j, found, best, bestp, xb);
+}
+
+__global__ __launch_bounds__(1024) void k_sort_long(DevProblem P, const double* __restrict__ x,
+                                                    const RowState* __restrict__ rs,
+                                                    const WalkState* __restrict__ st, double* __restrict__ xhat,
+                                                    double* __restrict__ sc, const LongTask* __restrict__ tasks,
+                                                    double* gpos, int32_t* gmk, double* gdel) {
+  if (st->k >= st->iters) return;
+  __shared__ int scount;
+  __shared__ double red[16];
+  __shared__ int redk[16];
+  const LongTask T = tasks[blockIdx.x];
+  const int j = T.col;
+  double* pos = gpos + T.offset;
+  int32_t* mk = gmk + T.offset;
+  double* dl = gdel + T.offset;
+  const double xb = x[j];
+  if (threadIdx.x == 0) scount = 0;
+  __syncthreads();
+  double beta = 0.0, alpha = 0.0;
+  general_phase1(P, rs, st, j, xb, threadIdx.x, blockDim.x, beta, alpha, [&](double p, int m, double d) {
+    const int s = atomicAdd(&scount, 1);
+    pos[s] = p;
+    mk[s] = m;
+    dl[s] = d;
+  });
+  {
+    double b = wave_sum(beta), a = wave_sum(alpha);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+      red[wv] = b;
+      redk[wv] = 0;
+    }
+    __syncthreads();
+    b = 0.0;
+    for (int q = 0; q < 16; ++q) b += red[q];
+    __syncthreads();
+    if (lane == 0) red[wv] = a;
+    __syncthreads();
+    a = 0.0;
+    for (int q = 0; q < 16; ++q) a += red[q];
+    beta = b;
+    alpha = a;
+  }
+  __syncthreads();
+  const int cnt = scount;
+  for (int i = cnt + threadIdx.x; i < T.cap; i += blockDim.x) {
+    pos[i] = HUGE_VAL;
+    mk[i] = kPadMarker;
+    dl[i] = 0.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  bitonic_sort(pos, mk, dl, T.cap);
+  bool found;
+  double best, bestp;
+  scan_argmax(pos, mk, dl, T.cap, beta, alpha, xb, P.lb[j], P.ub[j], red, redk, found, best, bestp);
+  if (threadIdx.x == 0) write_result(xhat, sc, j, found, best, bestp, xb);
+}
+
+}  // namespace
+
+hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, const double* x, const RowState* rs,
+                                  const WalkState* st, double* xhat, double* s, hipStream_t stream) {
+  if (plan.n_short > 0) {
+    ShortSegs segs;
+    for (int q = 0; q < kShortMax + 3; ++q) segs.wg_begin[q] = plan.short_segs[q];
+    const int blocks = plan.short_segs[kShortMax + 2];
+    hipLaunchKernelGGL(k_short, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, xhat, s, plan.short_cols, segs);
+  }
+  if (plan.n_flip > 0)
+    hipLaunchKernelGGL(k_flip_wave, dim3((plan.n_flip + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.flip_cols, plan.n_flip);
+  if (plan.n_narrow > 0)
+    hipLaunchKernelGGL(k_narrow_wave, dim3((plan.n_narrow + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.narrow_cols, plan.n_narrow);
+  if (plan.n_chunks > 0)
+    hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.chunks, plan.partials, plan.chunk_counters);
+  if (plan.n_sort[0] > 0)
+    hipLaunchKernelGGL(k_sort_block<64>, dim3(plan.n_sort[0]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.sort_cols[0], plan.n_sort[0]);
+  if (plan.n_sort[1] > 0)
+    hipLaunchKernelGGL(k_sort_block<256>, dim3(plan.n_sort[1]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.sort_cols[1], plan.n_sort[1]);
+  if (plan.n_sort[2] > 0)
+    hipLaunchKernelGGL(k_sort_block<1024>, dim3(plan.n_sort[2]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.sort_cols[2], plan.n_sort[2]);
+  if (plan.n_sort[3] > 0)
+    hipLaunchKernelGGL(k_sort_block<4096>, dim3(plan.n_sort[3]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.sort_cols[3], plan.n_sort[3]);
+  if (plan.n_long > 0)
+    hipLaunchKernelGGL(k_sort_long, dim3(plan.n_long), dim3(1024), 0, stream, P, x, rs, st, xhat, s,
+                       plan.long_tasks, plan.long_pos, plan.long_marker, plan.long_delta);
+  return hipGetLastError();
+}
+
+}  // namespace chap

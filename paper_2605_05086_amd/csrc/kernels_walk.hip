@@ -1,0 +1,468 @@
+// Tabu-walk kernels for gfx950: residual from scratch, state initialisation,
+// global move selection under tabu/aspiration, sparse move application and
+// weight update.
+//
+// Residuals r_i = sum_k a_ik x_k - b_i are stored per row (section 3.1
+// "Memory Considerations", first remark) in the row's '<=' orientation; the
+// negated twin of an equality row has residual -r_i. A move of variable j by
+// d updates only the rows of column j: r_i += a_ij d. The objective cutoff
+// row c^T x <= bc (section 3.2) is kept in the walk state.
+
+#include <climits>
+#include <cmath>
+
+#include "chap_internal.h"
+
+namespace chap {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum across a workgroup of 256 threads; every thread gets the total.
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* red) {
+  v = wave_sum_ll(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  long long t = 0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+  return t;
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+  return t;
+}
+
+__device__ __forceinline__ int viol_change(double r, double r2, double eps) {
+  return (r2 > eps ? 1 : 0) - (r > eps ? 1 : 0);
+}
+
+// Incumbent rule, run by one thread when no normalised row is violated: the
+// point is feasible; record it if it improves the best objective and (re)set
+// the cutoff row c^T x <= f_best - delta (section 3.2).
+__device__ void incumbent_check(WalkState* st, double eps) {
+  if (st->V != 0) return;
+  const double f = st->f;
+  if (!st->has_best || f < st->fbest) {
+    st->fbest = f;
+    st->has_best = 1;
+    st->copy_best = 1;
+  }
+  const double delta = st->obj_integral ? 1.0 : 1e-4 * fmax(1.0, fabs(st->fbest));
+  st->bc = st->fbest - delta;
+  st->cut_active = 1;
+  st->rc = f - st->bc;
+  st->V = (st->rc > eps) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __restrict__ x,
+                                                  RowState* __restrict__ rs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.ms) return;
+  double acc = 0.0;
+  const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
+  for (int e = beg; e < end; ++e) {
+    const double prod = P.row_val[e] * x[P.row_col[e]];
+    acc = acc + prod;
+  }
+  rs[i].r = acc - P.row_rhs[i];
+}
+
+__global__ __launch_bounds__(256) void k_weights_unit(const uint8_t* __restrict__ pair, RowState* __restrict__ rs,
+                                                      int32_t ms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ms) return;
+  rs[i].w0 = 1.0f;
+  rs[i].w1 = pair[i] ? 1.0f : -1.0f;
+}
+
+__global__ __launch_bounds__(256) void k_weights_scatter(const int32_t* __restrict__ nidx,
+                                                         const uint8_t* __restrict__ pair,
+                                                         const float* __restrict__ w, RowState* __restrict__ rs,
+                                                         int32_t ms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ms) return;
+  const int k = nidx[i];
+  rs[i].w0 = w[k];
+  rs[i].w1 = pair[i] ? w[k + 1] : -1.0f;
+}
+
+// f = c^T x and V = violated rows, as fixed-order (deterministic) grid
+// reductions; the last workgroup writes the walk state.
+__global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* __restrict__ x,
+                                                    const RowState* __restrict__ rs, WalkState* st,
+                                                    double* partial, uint32_t* ticket, int64_t iters,
+                                                    int32_t tenure, int32_t obj_integral, double cutoff_rhs,
+                                                    const float* cutoff_w, int32_t check_incumbent) {
+  __shared__ double redd[4];
+  __shared__ long long redl[4];
+  __shared__ uint32_t last;
+  const double eps = P.eps;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gs = gridDim.x * blockDim.x;
+  double f = 0.0;
+  for (int j = gt; j < P.n; j += gs) {
+    const double c = P.obj[j];
+    if (c != 0.0) f += c * x[j];
+  }
+  long long v = 0;
+  for (int i = gt; i < P.ms; i += gs) {
+    const RowState q = rs[i];
+    v += (q.r > eps) ? 1 : 0;
+    if (q.w1 >= 0.0f && -q.r > eps) v += 1;
+  }
+  f = block_sum_d(f, redd);
+  v = block_sum_ll(v, redl);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = f;
+    partial[2 * blockIdx.x + 1] = (double)v;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u);
+  __syncthreads();
+  if (last != gridDim.x - 1) return;
+  __threadfence();
+  if (threadIdx.x != 0) return;
+  double ft = 0.0, vt = 0.0;
+  for (unsigned b = 0; b < gridDim.x; ++b) {
+    ft += partial[2 * b];
+    vt += partial[2 * b + 1];
+  }
+  *ticket = 0u;
+  st->k = 0;
+  st->iters = iters;
+  st->tenure = tenure;
+  st->obj_integral = obj_integral;
+  st->f = ft;
+  st->fbest = HUGE_VAL;
+  st->has_best = 0;
+  st->copy_best = 0;
+  st->V = (int64_t)vt;
+  st->wc = cutoff_w ? *cutoff_w : 1.0f;
+  st->bc = 0.0;
+  st->rc = 0.0;
+  st->cut_active = 0;
+  if (isfinite(cutoff_rhs)) {
+    st->cut_active = 1;
+    st->bc = cutoff_rhs;
+    st->rc = ft - cutoff_rhs;
+    if (st->rc > eps) st->V += 1;
+  }
+  st->j_all = -1;
+  st->j_nt = -1;
+  st->mv_j = -1;
+  st->mv_kind = 2;
+  st->dV = 0ull;
+  st->argmax_ticket = 0u;
+  st->apply_ticket = 0u;
+  if (check_incumbent) incumbent_check(st, eps);
+}
+
+__device__ __forceinline__ bool better(double sa, int ja, double sb, int jb) {
+  return sa > sb || (sa == sb && ja < jb);
+}
+
+// Best positive score overall (j_all) and among non-tabu variables (j_nt),
+// ties to the lowest index.
+__global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, const int32_t* __restrict__ tabu,
+                                                WalkState* st, double* partial, int32_t n) {
+  if (st->k >= st->iters) return;
+  __shared__ double rs_a[4], rs_n[4];
+  __shared__ int rj_a[4], rj_n[4];
+  __shared__ uint32_t last;
+  const int64_t k = st->k;
+  double sa = 0.0, sn = 0.0;
+  int ja = INT_MAX, jn = INT_MAX;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gs = gridDim.x * blockDim.x;
+  for (int j = gt; j < n; j += gs) {
+    const double v = s[j];
+    if (!(v > 0.0)) continue;
+    if (better(v, j, sa, ja)) {
+      sa = v;
+      ja = j;
+    }
+    if (k > (int64_t)tabu[j] && better(v, j, sn, jn)) {
+      sn = v;
+      jn = j;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double osa = __shfl_xor(sa, o, kWave);
+    const int oja = __shfl_xor(ja, o, kWave);
+    const double osn = __shfl_xor(sn, o, kWave);
+    const int ojn = __shfl_xor(jn, o, kWave);
+    if (better(osa, oja, sa, ja)) {
+      sa = osa;
+      ja = oja;
+    }
+    if (better(osn, ojn, sn, jn)) {
+      sn = osn;
+      jn = ojn;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    rs_a[wv] = sa;
+    rj_a[wv] = ja;
+    rs_n[wv] = sn;
+    rj_n[wv] = jn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) {
+      if (better(rs_a[q], rj_a[q], sa, ja)) {
+        sa = rs_a[q];
+        ja = rj_a[q];
+      }
+      if (better(rs_n[q], rj_n[q], sn, jn)) {
+        sn = rs_n[q];
+        jn = rj_n[q];
+      }
+    }
+    partial[4 * blockIdx.x] = sa;
+    partial[4 * blockIdx.x + 1] = (double)ja;
+    partial[4 * blockIdx.x + 2] = sn;
+    partial[4 * blockIdx.x + 3] = (double)jn;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&st->argmax_ticket, 1u);
+  __syncthreads();
+  if (last != gridDim.x - 1) return;
+  __threadfence();
+  if (threadIdx.x != 0) return;
+  sa = 0.0;
+  sn = 0.0;
+  ja = INT_MAX;
+  jn = INT_MAX;
+  for (unsigned b = 0; b < gridDim.x; ++b) {
+    const double a = partial[4 * b], na = partial[4 * b + 2];
+    const int aj = (int)partial[4 * b + 1], nj = (int)partial[4 * b + 3];
+    if (better(a, aj, sa, ja)) {
+      sa = a;
+      ja = aj;
+    }
+    if (better(na, nj, sn, jn)) {
+      sn = na;
+      jn = nj;
+    }
+  }
+  st->j_all = (ja == INT_MAX) ? -1 : ja;
+  st->s_all = sa;
+  st->j_nt = (jn == INT_MAX) ? -1 : jn;
+  st->s_nt = sn;
+  st->argmax_ticket = 0u;
+}
+
+// Tabu/aspiration decision by one workgroup; the aspiration test walks the
+// column of the overall best variable.
+__global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __restrict__ x,
+                                                const double* __restrict__ xhat, const double* __restrict__ s,
+                                                const RowState* __restrict__ rs, const int32_t* __restrict__ tabu,
+                                                WalkState* st, chap_trace_record* trace) {
+  if (st->k >= st->iters) return;
+  __shared__ long long red[4];
+  const double eps = P.eps;
+  const int64_t k = st->k;
+  const int ja = st->j_all, jn = st->j_nt;
+  int jstar = -1, kind = 2;
+  if (ja >= 0 && k > (int64_t)tabu[ja]) {
+    jstar = ja;
+    kind = 0;
+  } else if (ja >= 0) {
+    const double d = xhat[ja] - x[ja];
+    long long dv = 0;
+    const int beg = P.col_ptr[ja], end = P.col_ptr[ja + 1];
+    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
+      const RowState q = rs[P.col_row[e]];
+      const double r2 = q.r + P.col_val[e] * d;
+      dv += viol_change(q.r, r2, eps);
+      if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+    }
+    dv = block_sum_ll(dv, red);
+    if (st->cut_active) {
+      const double c = P.obj[ja];
+      if (c != 0.0) dv += viol_change(st->rc, st->rc + c * d, eps);
+    }
+    if (st->V + dv == 0) {
+      jstar = ja;
+      kind = 1;
+    } else if (jn >= 0) {
+      jstar = jn;
+      kind = 0;
+    }
+  }
+  if (threadIdx.x != 0) return;
+  st->copy_best = 0;
+  st->mv_j = jstar;
+  st->mv_kind = kind;
+  chap_trace_record* t = trace + k;
+  t->iter = k;
+  t->var = jstar;
+  t->kind = kind;
+  if (jstar >= 0) {
+    const double xo = x[jstar], xn = xhat[jstar];
+    st->mv_old = xo;
+    st->mv_new = xn;
+    st->mv_delta = xn - xo;
+    st->mv_score = s[jstar];
+    t->x_old = xo;
+    t->x_new = xn;
+    t->score = s[jstar];
+  } else {
+    st->mv_delta = 0.0;
+    t->x_old = 0.0;
+    t->x_new = 0.0;
+    t->score = 0.0;
+  }
+}
+
+// Applies the chosen move (rows of one column) or the weight update (every
+// violated row); the last workgroup finishes the iteration.
+__global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict__ x, RowState* __restrict__ rs,
+                                               int32_t* __restrict__ tabu, WalkState* st,
+                                               chap_trace_record* trace) {
+  if (st->k >= st->iters) return;
+  __shared__ long long red[4];
+  __shared__ uint32_t last;
+  const double eps = P.eps;
+  const int jstar = st->mv_j;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gs = gridDim.x * blockDim.x;
+  long long dv = 0;
+  if (jstar >= 0) {
+    const double d = st->mv_delta;
+    const int beg = P.col_ptr[jstar], end = P.col_ptr[jstar + 1];
+    for (int e = beg + gt; e < end; e += gs) {
+      const int i = P.col_row[e];
+      const RowState q = rs[i];
+      const double r2 = q.r + P.col_val[e] * d;
+      rs[i].r = r2;
+      dv += viol_change(q.r, r2, eps);
+      if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+    }
+  } else {
+    for (int i = gt; i < P.ms; i += gs) {
+      const RowState q = rs[i];
+      if (q.r > eps) rs[i].w0 = q.w0 + 1.0f;
+      if (q.w1 >= 0.0f && -q.r > eps) rs[i].w1 = q.w1 + 1.0f;
+    }
+  }
+  dv = block_sum_ll(dv, red);
+  if (threadIdx.x == 0 && dv != 0) atomicAdd(&st->dV, (unsigned long long)dv);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&st->apply_ticket, 1u);
+  __syncthreads();
+  if (last != gridDim.x - 1 || threadIdx.x != 0) return;
+  __threadfence();
+  const int64_t k = st->k;
+  long long V = st->V + (long long)st->dV;
+  if (jstar >= 0) {
+    const double c = P.obj[jstar];
+    const double d = st->mv_delta;
+    if (st->cut_active && c != 0.0) {
+      const double r2 = st->rc + c * d;
+      V += viol_change(st->rc, r2, eps);
+      st->rc = r2;
+    }
+    if (c != 0.0) st->f = st->f + c * d;
+    x[jstar] = st->mv_new;
+    tabu[jstar] = (int32_t)(k + st->tenure);
+  } else if (st->cut_active && st->rc > eps) {
+    st->wc = st->wc + 1.0f;
+  }
+  st->dV = 0ull;
+  st->V = V;
+  trace[k].viol = V;
+  trace[k].obj = st->f;
+  incumbent_check(st, eps);
+  st->k = k + 1;
+  st->apply_ticket = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_copy_best(const double* __restrict__ x, double* __restrict__ best_x,
+                                                   const WalkState* st, int32_t n) {
+  if (!st->copy_best) return;
+  const int gs = gridDim.x * blockDim.x;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gs) best_x[j] = x[j];
+}
+
+inline int blocks_for(int64_t work, int cap) {
+  int64_t b = (work + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream) {
+  if (P.ms > 0) hipLaunchKernelGGL(k_residual, dim3((P.ms + 255) / 256), dim3(256), 0, stream, P, x, rs);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_weights_unit(const uint8_t* pair, RowState* rs, int32_t ms, hipStream_t stream) {
+  if (ms > 0) hipLaunchKernelGGL(k_weights_unit, dim3((ms + 255) / 256), dim3(256), 0, stream, pair, rs, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_weights(const int32_t* nidx, const uint8_t* pair, const float* w_norm, RowState* rs,
+                                  int32_t ms, hipStream_t stream) {
+  if (ms > 0)
+    hipLaunchKernelGGL(k_weights_scatter, dim3((ms + 255) / 256), dim3(256), 0, stream, nidx, pair, w_norm, rs,
+                       ms);
+  return hipGetLastError();
+}
+
+constexpr int kInitBlocks = 256;
+
+hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
+                             double* partial, uint32_t* ticket, int64_t iters, int32_t tenure, int32_t obj_integral,
+                             double cutoff_rhs, const float* cutoff_w, int check_incumbent, hipStream_t stream) {
+  const int blocks = blocks_for((int64_t)(P.n > P.ms ? P.n : P.ms), kInitBlocks);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, partial, ticket, iters, tenure,
+                     obj_integral, cutoff_rhs, cutoff_w, check_incumbent);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, const double* s, RowState* rs,
+                            int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
+                            double* argmax_partial, int32_t apply_blocks, hipStream_t stream) {
+  const int ab = blocks_for(P.n, kArgmaxBlocks);
+  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, st, argmax_partial, P.n);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace);
+  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, tabu_until, st, trace);
+  hipLaunchKernelGGL(k_copy_best, dim3(blocks_for(P.n, 1024)), dim3(256), 0, stream, x, best_x, st, P.n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(k_copy_best, dim3(blocks_for(n, 1024)), dim3(256), 0, stream, x, best_x, st, n);
+  return hipGetLastError();
+}
+
+}  // namespace chap
