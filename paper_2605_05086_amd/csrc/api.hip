@@ -62,6 +62,10 @@ struct chap_problem {
   chap_options opt{};
   int32_t obj_integral = 1;
   int32_t max_col_deg = 0;
+  // 1 when every variable is integer with finite bounds and every
+  // coefficient and right-hand side is an integer small enough that all row
+  // activities are exact in FP64: incremental residual updates are then exact
+  int32_t exact_incremental = 0;
   // host copies used by runs
   std::vector<double> lb, ub, obj;
   std::vector<uint8_t> is_int;
@@ -292,6 +296,23 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     }
   }
   P->mp = mp;
+  {
+    bool exact = true;
+    for (int32_t j = 0; j < n && exact; ++j)
+      exact = P->is_int[j] && std::isfinite(P->lb[j]) && std::isfinite(P->ub[j]);
+    for (int32_t i = 0; i < m && exact; ++i) {
+      double mag = std::fabs(rrhs[i]);
+      exact = std::floor(rrhs[i]) == rrhs[i];
+      for (int32_t e = rptr[i]; e < rptr[i + 1] && exact; ++e) {
+        const double a = rval[e];
+        const int32_t c = rcol[e];
+        exact = std::floor(a) == a;
+        mag += std::fabs(a) * std::max(std::fabs(P->lb[c]), std::fabs(P->ub[c]));
+      }
+      exact = exact && mag < 4503599627370496.0;  // 2^52
+    }
+    P->exact_incremental = exact ? 1 : 0;
+  }
   // column view in the caller's CSC order, stored orientation
   std::vector<int32_t> cptr((size_t)n + 1, 0), crow;
   std::vector<double> cval;
@@ -596,7 +617,7 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
       if (n > 0) cap_err = launch_best_shift_pass(p->dev, p->plan, B.x, B.rs, B.st, B.xhat, B.s, s);
       if (cap_err == hipSuccess)
         cap_err = launch_walk_step(p->dev, B.x, B.xhat, B.s, B.rs, B.tabu, B.st, B.trace, B.best_x, B.argmax_partial,
-                                   apply_blocks, s);
+                                   apply_blocks, p->exact_incremental ? 0 : 1, s);
     }
     hipError_t end_err = hipStreamEndCapture(s, &graph);
     if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));

@@ -156,7 +156,8 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
                              int check_incumbent, hipStream_t stream);
 hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, const double* s, RowState* rs,
                             int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
-                            double* argmax_partial, int32_t apply_blocks, hipStream_t stream);
+                            double* argmax_partial, int32_t apply_blocks, int32_t recompute,
+                            hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
 
 }  // namespace chap

@@ -340,11 +340,28 @@ __global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __re
   }
 }
 
+// Residual of stored row i from scratch at x with x_j replaced by xj, in
+// the row's stored order (the order of the caller's CSR).
+__device__ __forceinline__ double row_residual(const DevProblem& P, const double* x, int i, int j, double xj) {
+  double acc = 0.0;
+  const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
+  for (int e = beg; e < end; ++e) {
+    const int c = P.row_col[e];
+    const double prod = P.row_val[e] * ((c == j) ? xj : x[c]);
+    acc = acc + prod;
+  }
+  return acc - P.row_rhs[i];
+}
+
 // Applies the chosen move (rows of one column) or the weight update (every
-// violated row); the last workgroup finishes the iteration.
+// violated row); the last workgroup finishes the iteration. With
+// recompute = 0 the rows of the moved column are updated as r += a_ij d,
+// which is exact on all-integer data; otherwise each touched row is summed
+// again from scratch so that the kept residual equals its definition bit for
+// bit.
 __global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict__ x, RowState* __restrict__ rs,
                                                int32_t* __restrict__ tabu, WalkState* st,
-                                               chap_trace_record* trace) {
+                                               chap_trace_record* trace, int32_t recompute) {
   if (st->k >= st->iters) return;
   __shared__ long long red[4];
   __shared__ uint32_t last;
@@ -359,7 +376,7 @@ __global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict_
     for (int e = beg + gt; e < end; e += gs) {
       const int i = P.col_row[e];
       const RowState q = rs[i];
-      const double r2 = q.r + P.col_val[e] * d;
+      const double r2 = recompute ? row_residual(P, x, i, jstar, st->mv_new) : q.r + P.col_val[e] * d;
       rs[i].r = r2;
       dv += viol_change(q.r, r2, eps);
       if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
@@ -451,11 +468,11 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
 
 hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, const double* s, RowState* rs,
                             int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
-                            double* argmax_partial, int32_t apply_blocks, hipStream_t stream) {
+                            double* argmax_partial, int32_t apply_blocks, int32_t recompute, hipStream_t stream) {
   const int ab = blocks_for(P.n, kArgmaxBlocks);
   hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, st, argmax_partial, P.n);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace);
-  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, tabu_until, st, trace);
+  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, tabu_until, st, trace, recompute);
   hipLaunchKernelGGL(k_copy_best, dim3(blocks_for(P.n, 1024)), dim3(256), 0, stream, x, best_x, st, P.n);
   return hipGetLastError();
 }
