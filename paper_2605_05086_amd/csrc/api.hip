@@ -347,9 +347,8 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   }
   std::vector<std::vector<int32_t>> seg(kShortMax + 2);
   std::vector<int32_t> flip, narrow, sortl[kSortCaps];
-  std::vector<ChunkTask> chunks;
+  std::vector<ChunkTask> chunks, chunk_heads;
   std::vector<LongTask> longs;
-  int32_t nlongnarrow = 0;
   int64_t long_total = 0;
   for (int32_t j = 0; j < n; ++j) {
     if (ne[j] <= o.short_max) {
@@ -367,12 +366,11 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
           t.col = j;
           t.e_beg = cptr[j] + q * o.chunk_len;
           t.e_end = std::min(cptr[j + 1], t.e_beg + o.chunk_len);
-          t.slot = nlongnarrow;
           t.first = first;
           t.nchunks = nch;
           chunks.push_back(t);
         }
-        nlongnarrow += 1;
+        chunk_heads.push_back(chunks[first]);
       }
     } else {
       const int32_t entries = ne[j] + 2;
@@ -472,8 +470,10 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     L.chunks = d;
     L.n_chunks = (int32_t)chunks.size();
     CHAP_HIP(A.alloc(&L.partials, chunks.size()));
-    CHAP_HIP(A.alloc(&L.chunk_counters, (size_t)nlongnarrow));
-    CHAP_HIP(hipMemset(L.chunk_counters, 0, sizeof(uint32_t) * (size_t)nlongnarrow));
+    ChunkTask* dh;
+    CHAP_HIP(A.upload(&dh, chunk_heads));
+    L.chunk_heads = dh;
+    L.n_chunk_cols = (int32_t)chunk_heads.size();
   }
   for (int c = 0; c < kSortCaps; ++c) {
     if (sortl[c].empty()) continue;
@@ -606,7 +606,7 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
   CHAP_HIP(launch_state_init(p->dev, B.x, B.rs, B.st, B.partial, B.ticket, iters, tenure, p->obj_integral, HUGE_VAL,
                              nullptr, 1, s));
   CHAP_HIP(launch_copy_best(B.x, B.best_x, B.st, n, s));
-  const int apply_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (std::max(m, p->max_col_deg) + 255) / 256));
+  const int apply_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (std::max(m, p->max_col_deg) + 255) / 256));
   double ms_total = 0.0;
   if (iters > 0) {
     const int64_t K = std::min<int64_t>(iters, p->opt.graph_iters);
@@ -632,6 +632,8 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
     hipError_t le = hipEventRecord(e0, s);
     for (int64_t q = 0; q < launches && le == hipSuccess; ++q) le = hipGraphLaunch(exec, s);
     if (le == hipSuccess) le = hipEventRecord(e1, s);
+    // an incumbent found by the last iteration is copied here
+    if (le == hipSuccess) le = launch_copy_best(B.x, B.best_x, B.st, n, s);
     if (le == hipSuccess) le = hipStreamSynchronize(s);
     float ms = 0.0f;
     if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);

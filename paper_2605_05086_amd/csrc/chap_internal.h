@@ -82,8 +82,6 @@ struct __align__(16) WalkState {
   double mv_delta;
   double mv_score;
   unsigned long long dV;  // two's complement accumulator of violation changes
-  uint32_t argmax_ticket;
-  uint32_t apply_ticket;
 };
 
 // A slice of a long narrow-integer column handled by one workgroup.
@@ -91,7 +89,6 @@ struct ChunkTask {
   int32_t col;
   int32_t e_beg;
   int32_t e_end;
-  int32_t slot;      // index of the column among long narrow columns
   int32_t first;     // task index of the column's first chunk
   int32_t nchunks;
 };
@@ -126,7 +123,8 @@ struct PassPlan {
   const ChunkTask* chunks = nullptr;
   int32_t n_chunks = 0;
   ChunkPartial* partials = nullptr;
-  uint32_t* chunk_counters = nullptr;
+  const ChunkTask* chunk_heads = nullptr;  // first chunk of each long narrow column
+  int32_t n_chunk_cols = 0;
   const int32_t* sort_cols[kSortCaps] = {nullptr, nullptr, nullptr, nullptr};
   int32_t n_sort[kSortCaps] = {0, 0, 0, 0};
   const LongTask* long_tasks = nullptr;

@@ -424,17 +424,17 @@ __global__ __launch_bounds__(256) void k_narrow_wave(DevProblem P, const double*
   if (lane == 0) write_result(xhat, sc, j, found, best, bestp, xb);
 }
 
+// One workgroup per chunk of a long narrow column: bins, beta, alpha and the
+// candidate mask of the chunk go to its partial record (plain stores).
 __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double* __restrict__ x,
                                                       const RowState* __restrict__ rs,
                                                       const WalkState* __restrict__ st,
-                                                      double* __restrict__ xhat, double* __restrict__ sc,
-                                                      const ChunkTask* __restrict__ tasks, ChunkPartial* partials,
-                                                      uint32_t* counters) {
+                                                      const ChunkTask* __restrict__ tasks,
+                                                      ChunkPartial* __restrict__ partials) {
   if (st->k >= st->iters) return;
   __shared__ double bins[kNarrowBins];
   __shared__ double red_b[4], red_a[4];
   __shared__ unsigned long long red_c[4];
-  __shared__ uint32_t ticket;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid >> 6;
@@ -474,35 +474,36 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
     mine->alpha = red_a[0] + red_a[1] + red_a[2] + red_a[3];
     mine->cand = red_c[0] | red_c[1] | red_c[2] | red_c[3];
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) ticket = atomicAdd(&counters[T.slot], 1u);
-  __syncthreads();
-  if (ticket != (uint32_t)(T.nchunks - 1)) return;
-  // last workgroup of this column: combine the partials in chunk order
-  __threadfence();
-  if (wv != 0) return;
+}
+
+// One wavefront per long narrow column: combines its chunks' partials in
+// chunk order (deterministic), then scan and argmax over the bins.
+__global__ __launch_bounds__(256) void k_narrow_combine(DevProblem P, const double* __restrict__ x,
+                                                        const WalkState* __restrict__ st, double* __restrict__ xhat,
+                                                        double* __restrict__ sc, const ChunkTask* __restrict__ heads,
+                                                        int32_t count, const ChunkPartial* __restrict__ partials) {
+  if (st->k >= st->iters) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= count) return;
+  const ChunkTask T = heads[idx];
+  const int j = T.col;
+  const double xb = x[j];
+  const double l = P.lb[j], u = P.ub[j];
+  const int W = (int)(u - l) + 1;
   double bv = 0.0, b = 0.0, a = 0.0;
   unsigned long long c = 0;
   for (int q = 0; q < T.nchunks; ++q) {
     const ChunkPartial* pp = partials + T.first + q;
     bv += pp->bins[lane];
-    if (lane == 0) {
-      b += pp->beta;
-      a += pp->alpha;
-      c |= pp->cand;
-    }
+    b += pp->beta;
+    a += pp->alpha;
+    c |= pp->cand;
   }
-  b = __shfl(b, 0, kWave);
-  a = __shfl(a, 0, kWave);
-  c = __shfl(c, 0, kWave);
   bool found;
   double best, bestp;
   narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) {
-    write_result(xhat, sc, j, found, best, bestp, xb);
-    counters[T.slot] = 0u;
-  }
+  if (lane == 0) write_result(xhat, sc, j, found, best, bestp, xb);
 }
 
 // ---------------------------------------------------------------------------
@@ -766,9 +767,12 @@ hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, con
   if (plan.n_narrow > 0)
     hipLaunchKernelGGL(k_narrow_wave, dim3((plan.n_narrow + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
                        plan.narrow_cols, plan.n_narrow);
-  if (plan.n_chunks > 0)
-    hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.chunks, plan.partials, plan.chunk_counters);
+  if (plan.n_chunks > 0) {
+    hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, plan.chunks,
+                       plan.partials);
+    hipLaunchKernelGGL(k_narrow_combine, dim3((plan.n_chunk_cols + 3) / 4), dim3(256), 0, stream, P, x, st, xhat, s,
+                       plan.chunk_heads, plan.n_chunk_cols, plan.partials);
+  }
   if (plan.n_sort[0] > 0)
     hipLaunchKernelGGL(k_sort_block<64>, dim3(plan.n_sort[0]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
                        plan.sort_cols[0], plan.n_sort[0]);

@@ -174,8 +174,6 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
   st->mv_j = -1;
   st->mv_kind = 2;
   st->dV = 0ull;
-  st->argmax_ticket = 0u;
-  st->apply_ticket = 0u;
   if (check_incumbent) incumbent_check(st, eps);
 }
 
@@ -184,19 +182,24 @@ __device__ __forceinline__ bool better(double sa, int ja, double sb, int jb) {
 }
 
 // Best positive score overall (j_all) and among non-tabu variables (j_nt),
-// ties to the lowest index.
+// ties to the lowest index; one partial record per workgroup. The pending
+// copy of a new incumbent (flagged by the previous iteration, before this
+// iteration's move changes x) is done here too.
 __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, const int32_t* __restrict__ tabu,
-                                                WalkState* st, double* partial, int32_t n) {
+                                                const WalkState* __restrict__ st, double* __restrict__ partial,
+                                                const double* __restrict__ x, double* __restrict__ best_x,
+                                                int32_t n) {
   if (st->k >= st->iters) return;
   __shared__ double rs_a[4], rs_n[4];
   __shared__ int rj_a[4], rj_n[4];
-  __shared__ uint32_t last;
   const int64_t k = st->k;
+  const bool copy = st->copy_best != 0;
   double sa = 0.0, sn = 0.0;
   int ja = INT_MAX, jn = INT_MAX;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int gs = gridDim.x * blockDim.x;
   for (int j = gt; j < n; j += gs) {
+    if (copy) best_x[j] = x[j];
     const double v = s[j];
     if (!(v > 0.0)) continue;
     if (better(v, j, sa, ja)) {
@@ -247,18 +250,27 @@ __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, co
     partial[4 * blockIdx.x + 2] = sn;
     partial[4 * blockIdx.x + 3] = (double)jn;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&st->argmax_ticket, 1u);
-  __syncthreads();
-  if (last != gridDim.x - 1) return;
-  __threadfence();
-  if (threadIdx.x != 0) return;
-  sa = 0.0;
-  sn = 0.0;
-  ja = INT_MAX;
-  jn = INT_MAX;
-  for (unsigned b = 0; b < gridDim.x; ++b) {
+}
+
+// One workgroup: finishes the argmax over the partial records, then the
+// tabu/aspiration decision. A tabu overall best is taken only if its move
+// leaves no violated row; since a move changes at most one violation per
+// normalised entry of its column, that is impossible while V exceeds the
+// column's entry count, and the column is only scanned otherwise.
+__global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __restrict__ x,
+                                                const double* __restrict__ xhat, const double* __restrict__ s,
+                                                const RowState* __restrict__ rs, const int32_t* __restrict__ tabu,
+                                                WalkState* st, chap_trace_record* trace,
+                                                const double* __restrict__ partial, int32_t nparts) {
+  if (st->k >= st->iters) return;
+  __shared__ double rs_a[4], rs_n[4];
+  __shared__ int rj_a[4], rj_n[4];
+  __shared__ long long red[4];
+  const double eps = P.eps;
+  const int64_t k = st->k;
+  double sa = 0.0, sn = 0.0;
+  int ja = INT_MAX, jn = INT_MAX;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
     const double a = partial[4 * b], na = partial[4 * b + 2];
     const int aj = (int)partial[4 * b + 1], nj = (int)partial[4 * b + 3];
     if (better(a, aj, sa, ja)) {
@@ -270,44 +282,64 @@ __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, co
       jn = nj;
     }
   }
-  st->j_all = (ja == INT_MAX) ? -1 : ja;
-  st->s_all = sa;
-  st->j_nt = (jn == INT_MAX) ? -1 : jn;
-  st->s_nt = sn;
-  st->argmax_ticket = 0u;
-}
-
-// Tabu/aspiration decision by one workgroup; the aspiration test walks the
-// column of the overall best variable.
-__global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __restrict__ x,
-                                                const double* __restrict__ xhat, const double* __restrict__ s,
-                                                const RowState* __restrict__ rs, const int32_t* __restrict__ tabu,
-                                                WalkState* st, chap_trace_record* trace) {
-  if (st->k >= st->iters) return;
-  __shared__ long long red[4];
-  const double eps = P.eps;
-  const int64_t k = st->k;
-  const int ja = st->j_all, jn = st->j_nt;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double osa = __shfl_xor(sa, o, kWave);
+    const int oja = __shfl_xor(ja, o, kWave);
+    const double osn = __shfl_xor(sn, o, kWave);
+    const int ojn = __shfl_xor(jn, o, kWave);
+    if (better(osa, oja, sa, ja)) {
+      sa = osa;
+      ja = oja;
+    }
+    if (better(osn, ojn, sn, jn)) {
+      sn = osn;
+      jn = ojn;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    rs_a[wv] = sa;
+    rj_a[wv] = ja;
+    rs_n[wv] = sn;
+    rj_n[wv] = jn;
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    if (better(rs_a[q], rj_a[q], sa, ja)) {
+      sa = rs_a[q];
+      ja = rj_a[q];
+    }
+    if (better(rs_n[q], rj_n[q], sn, jn)) {
+      sn = rs_n[q];
+      jn = rj_n[q];
+    }
+  }
+  if (ja == INT_MAX) ja = -1;
+  if (jn == INT_MAX) jn = -1;
   int jstar = -1, kind = 2;
   if (ja >= 0 && k > (int64_t)tabu[ja]) {
     jstar = ja;
     kind = 0;
   } else if (ja >= 0) {
-    const double d = xhat[ja] - x[ja];
-    long long dv = 0;
     const int beg = P.col_ptr[ja], end = P.col_ptr[ja + 1];
-    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
-      const RowState q = rs[P.col_row[e]];
-      const double r2 = q.r + P.col_val[e] * d;
-      dv += viol_change(q.r, r2, eps);
-      if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+    const int64_t bound = 2 * (int64_t)(end - beg) + 1;
+    long long dv = 0;
+    if (st->V <= bound) {
+      const double d = xhat[ja] - x[ja];
+      for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const RowState q = rs[P.col_row[e]];
+        const double r2 = q.r + P.col_val[e] * d;
+        dv += viol_change(q.r, r2, eps);
+        if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+      }
+      dv = block_sum_ll(dv, red);
+      if (st->cut_active) {
+        const double c = P.obj[ja];
+        if (c != 0.0) dv += viol_change(st->rc, st->rc + c * d, eps);
+      }
     }
-    dv = block_sum_ll(dv, red);
-    if (st->cut_active) {
-      const double c = P.obj[ja];
-      if (c != 0.0) dv += viol_change(st->rc, st->rc + c * d, eps);
-    }
-    if (st->V + dv == 0) {
+    if (st->V <= bound && st->V + dv == 0) {
       jstar = ja;
       kind = 1;
     } else if (jn >= 0) {
@@ -316,6 +348,10 @@ __global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __re
     }
   }
   if (threadIdx.x != 0) return;
+  st->j_all = ja;
+  st->s_all = sa;
+  st->j_nt = jn;
+  st->s_nt = sn;
   st->copy_best = 0;
   st->mv_j = jstar;
   st->mv_kind = kind;
@@ -353,18 +389,16 @@ __device__ __forceinline__ double row_residual(const DevProblem& P, const double
   return acc - P.row_rhs[i];
 }
 
-// Applies the chosen move (rows of one column) or the weight update (every
-// violated row); the last workgroup finishes the iteration. With
-// recompute = 0 the rows of the moved column are updated as r += a_ij d,
-// which is exact on all-integer data; otherwise each touched row is summed
-// again from scratch so that the kept residual equals its definition bit for
-// bit.
-__global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict__ x, RowState* __restrict__ rs,
-                                               int32_t* __restrict__ tabu, WalkState* st,
-                                               chap_trace_record* trace, int32_t recompute) {
+// Applies the chosen move to the rows of one column, or the weight update to
+// every violated row; violation changes are summed into st->dV (read by
+// k_finish after this kernel). With recompute = 0 the rows are updated as
+// r += a_ij d, exact on all-integer data; otherwise each touched row is
+// summed again from scratch so the kept residual equals its definition bit
+// for bit.
+__global__ __launch_bounds__(256) void k_apply(DevProblem P, const double* __restrict__ x,
+                                               RowState* __restrict__ rs, WalkState* st, int32_t recompute) {
   if (st->k >= st->iters) return;
   __shared__ long long red[4];
-  __shared__ uint32_t last;
   const double eps = P.eps;
   const int jstar = st->mv_j;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,15 +406,18 @@ __global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict_
   long long dv = 0;
   if (jstar >= 0) {
     const double d = st->mv_delta;
+    const double xn = st->mv_new;
     const int beg = P.col_ptr[jstar], end = P.col_ptr[jstar + 1];
     for (int e = beg + gt; e < end; e += gs) {
       const int i = P.col_row[e];
       const RowState q = rs[i];
-      const double r2 = recompute ? row_residual(P, x, i, jstar, st->mv_new) : q.r + P.col_val[e] * d;
+      const double r2 = recompute ? row_residual(P, x, i, jstar, xn) : q.r + P.col_val[e] * d;
       rs[i].r = r2;
       dv += viol_change(q.r, r2, eps);
       if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
     }
+    dv = block_sum_ll(dv, red);
+    if (threadIdx.x == 0 && dv != 0) atomicAdd(&st->dV, (unsigned long long)dv);
   } else {
     for (int i = gt; i < P.ms; i += gs) {
       const RowState q = rs[i];
@@ -388,15 +425,15 @@ __global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict_
       if (q.w1 >= 0.0f && -q.r > eps) rs[i].w1 = q.w1 + 1.0f;
     }
   }
-  dv = block_sum_ll(dv, red);
-  if (threadIdx.x == 0 && dv != 0) atomicAdd(&st->dV, (unsigned long long)dv);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&st->apply_ticket, 1u);
-  __syncthreads();
-  if (last != gridDim.x - 1 || threadIdx.x != 0) return;
-  __threadfence();
+}
+
+// Ends the iteration: objective, cutoff row, incumbent rule, trace, k + 1.
+__global__ void k_finish(DevProblem P, double* __restrict__ x, int32_t* __restrict__ tabu, WalkState* st,
+                         chap_trace_record* trace) {
+  if (threadIdx.x != 0 || st->k >= st->iters) return;
+  const double eps = P.eps;
   const int64_t k = st->k;
+  const int jstar = st->mv_j;
   long long V = st->V + (long long)st->dV;
   if (jstar >= 0) {
     const double c = P.obj[jstar];
@@ -418,7 +455,6 @@ __global__ __launch_bounds__(256) void k_apply(DevProblem P, double* __restrict_
   trace[k].obj = st->f;
   incumbent_check(st, eps);
   st->k = k + 1;
-  st->apply_ticket = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_copy_best(const double* __restrict__ x, double* __restrict__ best_x,
@@ -470,10 +506,11 @@ hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, 
                             int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
                             double* argmax_partial, int32_t apply_blocks, int32_t recompute, hipStream_t stream) {
   const int ab = blocks_for(P.n, kArgmaxBlocks);
-  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, st, argmax_partial, P.n);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace);
-  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, tabu_until, st, trace, recompute);
-  hipLaunchKernelGGL(k_copy_best, dim3(blocks_for(P.n, 1024)), dim3(256), 0, stream, x, best_x, st, P.n);
+  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, st, argmax_partial, x, best_x, P.n);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace,
+                     argmax_partial, ab);
+  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, st, recompute);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, stream, P, x, tabu_until, st, trace);
   return hipGetLastError();
 }
 
