@@ -85,6 +85,10 @@ struct chap_problem {
   WalkState* bs_state = nullptr;
   double* bs_partial = nullptr;
   uint32_t* bs_ticket = nullptr;
+  double* bs_x = nullptr;
+  double* bs_xhat = nullptr;
+  double* bs_s = nullptr;
+  std::vector<int32_t> perm;  // original index of each internal column
   hipEvent_t pass_ev[2] = {nullptr, nullptr};
   bool pass_timed = false;
   ~chap_problem() {
@@ -313,92 +317,175 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     }
     P->exact_incremental = exact ? 1 : 0;
   }
-  // column view in the caller's CSC order, stored orientation
-  std::vector<int32_t> cptr((size_t)n + 1, 0), crow;
-  std::vector<double> cval;
-  crow.reserve(nnz);
-  cval.reserve(nnz);
+  // per original column: stored entries (rows ascending), degree, entries
   std::vector<int32_t> deg(n), ne(n);
   for (int32_t j = 0; j < n; ++j) {
     int32_t d = 0, e = 0;
     for (int64_t k = csc_col_ptr[j]; k < csc_col_ptr[j + 1]; ++k) {
       if (csc_val[k] == 0.0) continue;
-      const int32_t i = csc_row[k];
-      crow.push_back(i);
-      cval.push_back(sgn[i] * csc_val[k]);
       d += 1;
-      e += P->pair[i] ? 2 : 1;
+      e += P->pair[csc_row[k]] ? 2 : 1;
     }
-    cptr[j + 1] = (int32_t)crow.size();
     deg[j] = d;
     ne[j] = e + (obj[j] != 0.0 ? 1 : 0);
     P->max_col_deg = std::max(P->max_col_deg, d);
   }
-  // ---- column classes and work lists --------------------------------------
+  // ---- column classes and the internal column order ----------------------
+  // Every kernel of the pass scores one contiguous range of internal
+  // columns: short binaries (by degree), short non-binary columns by stored
+  // degree D = 0..8, long binaries, narrow columns, chunked narrow columns,
+  // general columns by LDS sort capacity, very long general columns.
+  enum Cls { BIN, NARROW, GENERAL };
   std::vector<uint8_t> cls(n);
   for (int32_t j = 0; j < n; ++j) {
     const double l = P->lb[j], u = P->ub[j];
     if (P->is_int[j] && l == 0.0 && u == 1.0)
-      cls[j] = COL_BINARY;
+      cls[j] = BIN;
     else if (P->is_int[j] && std::isfinite(l) && std::isfinite(u) && u - l + 1.0 <= (double)kNarrowBins)
-      cls[j] = COL_NARROW;
+      cls[j] = NARROW;
     else
-      cls[j] = COL_GENERAL;
+      cls[j] = GENERAL;
   }
-  std::vector<std::vector<int32_t>> seg(kShortMax + 2);
-  std::vector<int32_t> flip, narrow, sortl[kSortCaps];
-  std::vector<ChunkTask> chunks, chunk_heads;
-  std::vector<LongTask> longs;
-  int64_t long_total = 0;
+  std::vector<std::vector<int32_t>> short_seg(kShortMax + 2), sortl(kSortCaps);
+  std::vector<int32_t> flip, narrow, chunked, longg;
   for (int32_t j = 0; j < n; ++j) {
     if (ne[j] <= o.short_max) {
-      seg[cls[j] == COL_BINARY ? 0 : 1 + deg[j]].push_back(j);
-    } else if (cls[j] == COL_BINARY) {
+      short_seg[cls[j] == BIN ? 0 : 1 + deg[j]].push_back(j);
+    } else if (cls[j] == BIN) {
       flip.push_back(j);
-    } else if (cls[j] == COL_NARROW) {
+    } else if (cls[j] == NARROW) {
       if (ne[j] <= o.chunk_min) {
         narrow.push_back(j);
       } else {
-        const int32_t nch = (deg[j] + o.chunk_len - 1) / o.chunk_len;
-        const int32_t first = (int32_t)chunks.size();
-        for (int32_t q = 0; q < nch; ++q) {
-          ChunkTask t;
-          t.col = j;
-          t.e_beg = cptr[j] + q * o.chunk_len;
-          t.e_end = std::min(cptr[j + 1], t.e_beg + o.chunk_len);
-          t.first = first;
-          t.nchunks = nch;
-          chunks.push_back(t);
-        }
-        chunk_heads.push_back(chunks[first]);
+        chunked.push_back(j);
       }
     } else {
       const int32_t entries = ne[j] + 2;
       int c = 0;
       while (c < kSortCaps && kSortCap[c] < entries) ++c;
-      if (c < kSortCaps) {
+      if (c < kSortCaps)
         sortl[c].push_back(j);
-      } else {
-        int32_t cap = kSortCap[kSortCaps - 1];
-        while (cap < entries) cap <<= 1;
-        LongTask t;
-        t.col = j;
-        t.cap = cap;
-        t.offset = long_total;
-        long_total += cap;
-        longs.push_back(t);
-      }
+      else
+        longg.push_back(j);
     }
   }
-  // binaries by degree so that a wavefront's lanes loop equally long
-  std::stable_sort(seg[0].begin(), seg[0].end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
-  std::vector<int32_t> short_list;
-  P->plan.short_segs[0] = 0;
+  std::stable_sort(short_seg[0].begin(), short_seg[0].end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  std::stable_sort(flip.begin(), flip.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  PassPlan& L = P->plan;
+  std::vector<int32_t> perm;
+  perm.reserve(n);
+  auto append = [&](const std::vector<int32_t>& v) { perm.insert(perm.end(), v.begin(), v.end()); };
+  L.short_seg[0] = 0;
   for (int g = 0; g < kShortMax + 2; ++g) {
-    for (int32_t j : seg[g]) short_list.push_back(j);
-    while (short_list.size() % 256) short_list.push_back(-1);
-    P->plan.short_segs[g + 1] = (int32_t)(short_list.size() / 256);
+    append(short_seg[g]);
+    L.short_seg[g + 1] = (int32_t)perm.size();
   }
+  L.flip_begin = (int32_t)perm.size();
+  append(flip);
+  L.flip_end = (int32_t)perm.size();
+  L.narrow_begin = (int32_t)perm.size();
+  append(narrow);
+  L.narrow_end = (int32_t)perm.size();
+  const int32_t chunk_begin = (int32_t)perm.size();
+  append(chunked);
+  for (int c = 0; c < kSortCaps; ++c) {
+    L.sort_begin[c] = (int32_t)perm.size();
+    append(sortl[c]);
+  }
+  L.sort_begin[kSortCaps] = (int32_t)perm.size();
+  const int32_t long_begin = (int32_t)perm.size();
+  append(longg);
+  std::vector<int32_t> inv(n);
+  for (int32_t q = 0; q < n; ++q) inv[perm[q]] = q;
+  // internal CSC (stored orientation, rows ascending) and per-column data
+  std::vector<int32_t> cptr((size_t)n + 1, 0), crow;
+  std::vector<double> cval, lbq(n), ubq(n), objq(n);
+  std::vector<uint8_t> isintq(n);
+  crow.reserve(nnz);
+  cval.reserve(nnz);
+  {
+    std::vector<std::pair<int32_t, double>> buf;
+    for (int32_t q = 0; q < n; ++q) {
+      const int32_t j = perm[q];
+      buf.clear();
+      for (int64_t k = csc_col_ptr[j]; k < csc_col_ptr[j + 1]; ++k) {
+        if (csc_val[k] == 0.0) continue;
+        const int32_t i = csc_row[k];
+        buf.emplace_back(i, sgn[i] * csc_val[k]);
+      }
+      std::sort(buf.begin(), buf.end(),
+                [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) { return a.first < b.first; });
+      for (const auto& e : buf) {
+        crow.push_back(e.first);
+        cval.push_back(e.second);
+      }
+      cptr[q + 1] = (int32_t)crow.size();
+      lbq[q] = P->lb[j];
+      ubq[q] = P->ub[j];
+      objq[q] = P->obj[j];
+      isintq[q] = P->is_int[j];
+    }
+  }
+  for (int32_t& c : rcol) c = inv[c];
+  // chunk tasks of long narrow columns: each column's entries are cut at the
+  // kXcds row-range boundaries and into pieces of chunk_len; the task list
+  // interleaves the ranges so that task t gathers from range t mod kXcds
+  std::vector<ChunkTask> tasks;
+  std::vector<ChunkCol> ccols;
+  {
+    std::vector<std::vector<ChunkTask>> per_range(kXcds);
+    int32_t slot = 0;
+    for (int32_t q = chunk_begin; q < chunk_begin + (int32_t)chunked.size(); ++q) {
+      ChunkCol C;
+      C.col = q;
+      C.first = slot;
+      bool first = true;
+      int32_t e = cptr[q];
+      for (int r = 0; r < kXcds; ++r) {
+        const int64_t row_end = ((int64_t)m * (r + 1)) / kXcds;
+        int32_t e_end = e;
+        while (e_end < cptr[q + 1] && crow[e_end] < row_end) ++e_end;
+        for (int32_t b = e; b < e_end; b += o.chunk_len) {
+          ChunkTask t;
+          t.col = q;
+          t.e_beg = b;
+          t.e_end = std::min(e_end, b + o.chunk_len);
+          t.slot = slot++;
+          t.first = first ? 1 : 0;
+          first = false;
+          per_range[r].push_back(t);
+        }
+        e = e_end;
+      }
+      C.nparts = slot - C.first;
+      ccols.push_back(C);
+    }
+    size_t rounds = 0;
+    for (const auto& v : per_range) rounds = std::max(rounds, v.size());
+    for (size_t k = 0; k < rounds; ++k)
+      for (int r = 0; r < kXcds; ++r) {
+        if (k < per_range[r].size()) {
+          tasks.push_back(per_range[r][k]);
+        } else {
+          ChunkTask t{-1, 0, 0, 0, 0};
+          tasks.push_back(t);
+        }
+      }
+  }
+  std::vector<LongTask> longs;
+  int64_t long_total = 0;
+  for (int32_t q = long_begin; q < n; ++q) {
+    const int32_t entries = ne[perm[q]] + 2;
+    int32_t cap = kSortCap[kSortCaps - 1];
+    while (cap < entries) cap <<= 1;
+    LongTask t;
+    t.col = q;
+    t.cap = cap;
+    t.offset = long_total;
+    long_total += cap;
+    longs.push_back(t);
+  }
+  P->perm = perm;
   // ---- upload --------------------------------------------------------------
   {
     int dev = 0;
@@ -412,9 +499,9 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   D.n = n;
   D.ms = m;
   D.eps = P->eps;
-  int32_t *d_cptr, *d_crow, *d_rptr, *d_rcol;
+  int32_t *d_cptr, *d_crow, *d_rptr, *d_rcol, *d_perm;
   double *d_cval, *d_rval, *d_rrhs, *d_lb, *d_ub, *d_obj;
-  uint8_t *d_cls, *d_isint, *d_pair;
+  uint8_t *d_isint, *d_pair;
   int32_t* d_nidx;
   CHAP_HIP(A.upload(&d_cptr, cptr));
   CHAP_HIP(A.upload(&d_crow, crow));
@@ -423,11 +510,11 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(A.upload(&d_rcol, rcol));
   CHAP_HIP(A.upload(&d_rval, rval));
   CHAP_HIP(A.upload(&d_rrhs, rrhs));
-  CHAP_HIP(A.upload(&d_lb, P->lb));
-  CHAP_HIP(A.upload(&d_ub, P->ub));
-  CHAP_HIP(A.upload(&d_obj, P->obj));
-  CHAP_HIP(A.upload(&d_cls, cls));
-  CHAP_HIP(A.upload(&d_isint, P->is_int));
+  CHAP_HIP(A.upload(&d_lb, lbq));
+  CHAP_HIP(A.upload(&d_ub, ubq));
+  CHAP_HIP(A.upload(&d_obj, objq));
+  CHAP_HIP(A.upload(&d_isint, isintq));
+  CHAP_HIP(A.upload(&d_perm, perm));
   CHAP_HIP(A.upload(&d_pair, P->pair));
   CHAP_HIP(A.upload(&d_nidx, P->nidx));
   D.col_ptr = d_cptr;
@@ -440,47 +527,20 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   D.lb = d_lb;
   D.ub = d_ub;
   D.obj = d_obj;
-  D.cls = d_cls;
   D.is_int = d_isint;
+  D.perm = d_perm;
   P->d_pair = d_pair;
   P->d_nidx = d_nidx;
-  PassPlan& L = P->plan;
-  L.short_max = o.short_max;
-  if (!short_list.empty()) {
-    int32_t* d;
-    CHAP_HIP(A.upload(&d, short_list));
-    L.short_cols = d;
-    L.n_short = (int32_t)short_list.size();
-  }
-  if (!flip.empty()) {
-    int32_t* d;
-    CHAP_HIP(A.upload(&d, flip));
-    L.flip_cols = d;
-    L.n_flip = (int32_t)flip.size();
-  }
-  if (!narrow.empty()) {
-    int32_t* d;
-    CHAP_HIP(A.upload(&d, narrow));
-    L.narrow_cols = d;
-    L.n_narrow = (int32_t)narrow.size();
-  }
-  if (!chunks.empty()) {
-    ChunkTask* d;
-    CHAP_HIP(A.upload(&d, chunks));
-    L.chunks = d;
-    L.n_chunks = (int32_t)chunks.size();
-    CHAP_HIP(A.alloc(&L.partials, chunks.size()));
-    ChunkTask* dh;
-    CHAP_HIP(A.upload(&dh, chunk_heads));
-    L.chunk_heads = dh;
-    L.n_chunk_cols = (int32_t)chunk_heads.size();
-  }
-  for (int c = 0; c < kSortCaps; ++c) {
-    if (sortl[c].empty()) continue;
-    int32_t* d;
-    CHAP_HIP(A.upload(&d, sortl[c]));
-    L.sort_cols[c] = d;
-    L.n_sort[c] = (int32_t)sortl[c].size();
+  if (!tasks.empty()) {
+    ChunkTask* dt;
+    CHAP_HIP(A.upload(&dt, tasks));
+    L.chunks = dt;
+    L.n_chunks = (int32_t)tasks.size();
+    CHAP_HIP(A.alloc(&L.partials, (size_t)ccols.back().first + ccols.back().nparts));
+    ChunkCol* dc;
+    CHAP_HIP(A.upload(&dc, ccols));
+    L.chunk_cols = dc;
+    L.n_chunk_cols = (int32_t)ccols.size();
   }
   if (!longs.empty()) {
     LongTask* d;
@@ -491,6 +551,9 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.alloc(&L.long_delta, (size_t)long_total));
     CHAP_HIP(A.alloc(&L.long_marker, (size_t)long_total));
   }
+  CHAP_HIP(A.alloc(&P->bs_x, (size_t)n));
+  CHAP_HIP(A.alloc(&P->bs_xhat, (size_t)n));
+  CHAP_HIP(A.alloc(&P->bs_s, (size_t)n));
   CHAP_HIP(A.alloc(&P->bs_rs, (size_t)m));
   CHAP_HIP(A.alloc(&P->bs_state, 1));
   CHAP_HIP(A.alloc(&P->bs_partial, 2 * 1024));
@@ -510,14 +573,17 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   if (!d_w) return fail(CHAP_EINVAL, "chap_best_shift: null weights");
   if (std::isnan(cutoff_rhs)) return fail(CHAP_EINVAL, "chap_best_shift: cutoff_rhs is NaN");
   hipStream_t s = (hipStream_t)hip_stream;
-  CHAP_HIP(launch_residual(p->dev, d_x, p->bs_rs, s));
+  CHAP_HIP(launch_gather(p->dev.perm, d_x, p->bs_x, p->n, s));
+  CHAP_HIP(launch_residual(p->dev, p->bs_x, p->bs_rs, s));
   CHAP_HIP(launch_scatter_weights(p->d_nidx, p->d_pair, d_w, p->bs_rs, p->m, s));
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
-  CHAP_HIP(launch_state_init(p->dev, d_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0, p->obj_integral,
-                             cut, d_w + p->mp, 0, s));
+  CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
+                             p->obj_integral, cut, d_w + p->mp, 0, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
-  if (p->n > 0) CHAP_HIP(launch_best_shift_pass(p->dev, p->plan, d_x, p->bs_rs, p->bs_state, d_shift, d_score, s));
+  if (p->n > 0)
+    CHAP_HIP(launch_best_shift_pass(p->dev, p->plan, p->bs_x, p->bs_rs, p->bs_state, p->bs_xhat, p->bs_s, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
+  CHAP_HIP(launch_scatter2(p->dev.perm, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
   p->pass_timed = true;
   return CHAP_OK;
 }
@@ -571,7 +637,7 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
   CHAP_HIP(A.alloc(&B.st, 1));
   CHAP_HIP(A.alloc(&B.trace, (size_t)std::max<int64_t>(iters, 1)));
   CHAP_HIP(A.alloc(&B.partial, 2 * 1024));
-  CHAP_HIP(A.alloc(&B.argmax_partial, 4 * kArgmaxBlocks));
+  CHAP_HIP(A.alloc(&B.argmax_partial, (size_t)kArgmaxRecord * kArgmaxBlocks));
   CHAP_HIP(A.alloc(&B.ticket, 1));
   hipStream_t user = (hipStream_t)hip_stream;
   hipStream_t s;
@@ -596,8 +662,10 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
   CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
   CHAP_HIP(hipMemsetAsync(B.ticket, 0, sizeof(uint32_t), s));
   CHAP_HIP(hipMemsetAsync(B.st, 0, sizeof(WalkState), s));
+  std::vector<double> xq(n);
+  for (int32_t q = 0; q < n; ++q) xq[q] = xs[p->perm[q]];
   if (n > 0) {
-    CHAP_HIP(hipMemcpyAsync(B.x, xs.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
+    CHAP_HIP(hipMemcpyAsync(B.x, xq.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, B.tabu, -1, (int64_t)n);
     CHAP_HIP(hipGetLastError());
   }
@@ -649,10 +717,14 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
   if (iters > 0)
     CHAP_HIP(hipMemcpy(R->trace.data(), B.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
   R->x.resize(n);
-  std::vector<double> bx(n);
+  std::vector<double> bx(n), xin(n), bxin(n);
   if (n > 0) {
-    CHAP_HIP(hipMemcpy(R->x.data(), B.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
-    CHAP_HIP(hipMemcpy(bx.data(), B.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    CHAP_HIP(hipMemcpy(xin.data(), B.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    CHAP_HIP(hipMemcpy(bxin.data(), B.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+  }
+  for (int32_t q = 0; q < n; ++q) {
+    R->x[p->perm[q]] = xin[q];
+    bx[p->perm[q]] = bxin[q];
   }
   std::vector<RowState> rs(m);
   if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), B.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));

@@ -19,10 +19,12 @@ enum : uint8_t {
 };
 
 constexpr int kShortMax = 8;       // normalised entries a single lane can score
+constexpr int kXcds = 8;           // L2 domains (XCDs) of an MI355X; chunks are cut into as many row ranges
 constexpr int kNarrowBins = 64;    // values of a narrow integer column
 constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
 constexpr int kArgmaxBlocks = 1024;  // workgroups of the move-selection reduction
+constexpr int kArgmaxRecord = 8;     // doubles per workgroup record of that reduction
 
 // Residual and weights of one stored row. A stored row is a normalised row;
 // an equality row is stored once in its '<=' orientation and carries a second
@@ -39,18 +41,18 @@ struct DevProblem {
   int32_t n;
   int32_t ms;  // stored rows
   double eps;
-  const int32_t* col_ptr;  // n+1
-  const int32_t* col_row;  // stored row of each CSC entry
+  const int32_t* col_ptr;  // n+1, internal column order
+  const int32_t* col_row;  // stored row of each CSC entry (ascending within a column)
   const double* col_val;   // coefficient in the stored orientation
   const int32_t* row_ptr;  // ms+1
-  const int32_t* row_col;
+  const int32_t* row_col;  // internal column index, caller's order within the row
   const double* row_val;
   const double* row_rhs;
-  const double* lb;
+  const double* lb;  // per internal column
   const double* ub;
   const double* obj;
-  const uint8_t* cls;
   const uint8_t* is_int;
+  const int32_t* perm;  // original index of each internal column
 };
 
 // Mutable state of one walk (also used, with k = 0 and iters = 1, by a single
@@ -69,12 +71,12 @@ struct __align__(16) WalkState {
   int64_t V;     // violated normalised rows (cutoff included when active)
   int32_t has_best;
   int32_t copy_best;
-  // selection
+  // selection (original indices)
   int32_t j_all;
   int32_t j_nt;
   double s_all;
   double s_nt;
-  // chosen step
+  // chosen step (internal column index)
   int32_t mv_j;
   int32_t mv_kind;
   double mv_old;
@@ -84,13 +86,21 @@ struct __align__(16) WalkState {
   unsigned long long dV;  // two's complement accumulator of violation changes
 };
 
-// A slice of a long narrow-integer column handled by one workgroup.
+// A slice of a long narrow-integer column handled by one workgroup; col < 0
+// marks an empty task that only keeps the row-range interleave.
 struct ChunkTask {
-  int32_t col;
-  int32_t e_beg;
+  int32_t col;    // internal column index
+  int32_t e_beg;  // CSC entry range
   int32_t e_end;
-  int32_t first;     // task index of the column's first chunk
-  int32_t nchunks;
+  int32_t slot;   // partial record written by this task
+  int32_t first;  // 1 for exactly one task per column (adds the cutoff entry)
+};
+
+// A long narrow column and its partial records [first, first + nparts).
+struct ChunkCol {
+  int32_t col;
+  int32_t first;
+  int32_t nparts;
 };
 
 // Per-chunk partial result: bins, beta, alpha, candidate mask.
@@ -109,30 +119,26 @@ struct LongTask {
   int64_t offset;    // into the long-sort scratch arrays
 };
 
-// Device work lists of one best-shift pass.
+// Work of one best-shift pass. Columns live in an internal order in which
+// each kernel's columns form one contiguous range of internal indices.
 struct PassPlan {
-  const int32_t* short_cols = nullptr;  // padded to whole workgroups with -1
-  int32_t n_short = 0;
-  // workgroup ranges of the short-column segments: 0 binary, 1 + D non-binary
-  // with D stored entries (D = 0..8); the last entry is the total
-  int32_t short_segs[kShortMax + 3] = {0};
-  const int32_t* flip_cols = nullptr;
-  int32_t n_flip = 0;
-  const int32_t* narrow_cols = nullptr;
-  int32_t n_narrow = 0;
+  // short columns: binaries [short_seg[0], short_seg[1]), then non-binary
+  // columns with D stored entries [short_seg[1+D], short_seg[2+D])
+  int32_t short_seg[kShortMax + 3] = {0};
+  int32_t flip_begin = 0, flip_end = 0;
+  // narrow columns scored by one wavefront each
+  int32_t narrow_begin = 0, narrow_end = 0;
   const ChunkTask* chunks = nullptr;
   int32_t n_chunks = 0;
   ChunkPartial* partials = nullptr;
-  const ChunkTask* chunk_heads = nullptr;  // first chunk of each long narrow column
+  const ChunkCol* chunk_cols = nullptr;
   int32_t n_chunk_cols = 0;
-  const int32_t* sort_cols[kSortCaps] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t n_sort[kSortCaps] = {0, 0, 0, 0};
+  int32_t sort_begin[kSortCaps + 1] = {0};
   const LongTask* long_tasks = nullptr;
   int32_t n_long = 0;
   double* long_pos = nullptr;
   double* long_delta = nullptr;
   int32_t* long_marker = nullptr;
-  int32_t short_max = kShortMax;
 };
 
 // ---- launchers (kernels_pass.hip) -----------------------------------------
@@ -157,5 +163,10 @@ hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, 
                             double* argmax_partial, int32_t apply_blocks, int32_t recompute,
                             hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
+// dst[q] = src[perm[q]] (original order -> internal order)
+hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream);
+// da[perm[q]] = a[q], db[perm[q]] = b[q] (internal order -> original order)
+hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
+                           hipStream_t stream);
 
 }  // namespace chap

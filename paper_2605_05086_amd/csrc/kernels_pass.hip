@@ -14,8 +14,8 @@
 //                  sort of Algorithm 1 becomes a counting sort into 64 LDS
 //                  bins, the scan a wavefront prefix sum, the argmax a
 //                  wavefront reduction over candidate bins.
-//   k_narrow_chunk the same for long columns split over many workgroups;
-//                  partial bins are combined by the last workgroup to finish.
+//   k_narrow_chunk the same for long columns split over many workgroups by
+//                  row range; k_narrow_combine adds the partial bins.
 //   k_sort_block   one workgroup per general column: LDS bitonic sort of the
 //                  breakpoints, block scan, block argmax.
 //   k_sort_long    general columns beyond the LDS capacity: the same steps in
@@ -143,96 +143,84 @@ __device__ __forceinline__ void write_result(double* xhat, double* sc, int j, bo
 }
 
 // ---------------------------------------------------------------------------
-// k_short: one lane per column.
+// k_short: one lane per column (at most 8 normalised entries).
 // ---------------------------------------------------------------------------
 
-struct ShortSegs {
-  int32_t wg_begin[kShortMax + 3];  // segment g: workgroups [wg_begin[g], wg_begin[g+1])
-};
-
 __device__ __forceinline__ void flip_column(const DevProblem& P, const double* x, const RowState* rs,
-                                            const WalkState* st, double* xhat, double* sc, int j) {
+                                            const WalkState* st, double* xhat, double* sc, int q) {
   const double eps = P.eps;
-  const double xb = x[j];
+  const double xb = x[q];
   const double xn = 1.0 - xb;
   const double d = xn - xb;
   double s = 0.0;
-  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
   for (int e = beg; e < end; ++e) {
-    const RowState q = rs[P.col_row[e]];
-    const double r2 = q.r + P.col_val[e] * d;
-    s += penalty(q.r, r2, (double)q.w0, eps);
-    if (q.w1 >= 0.0f) s += penalty(-q.r, -r2, (double)q.w1, eps);
+    const RowState r = rs[P.col_row[e]];
+    const double r2 = r.r + P.col_val[e] * d;
+    s += penalty(r.r, r2, (double)r.w0, eps);
+    if (r.w1 >= 0.0f) s += penalty(-r.r, -r2, (double)r.w1, eps);
   }
   if (st->cut_active) {
-    const double c = P.obj[j];
+    const double c = P.obj[q];
     if (c != 0.0) {
       const double r2 = st->rc + c * d;
       s += penalty(st->rc, r2, (double)st->wc, eps);
     }
   }
-  write_result(xhat, sc, j, true, s, xn, xb);
+  write_result(xhat, sc, q, true, s, xn, xb);
 }
+
+// Normalised entries of a short column held in compile-time indexed slots.
+struct ShortSlots {
+  double tau[kShortMax];
+  double w[kShortMax];
+  uint32_t apos = 0, sat0 = 0;
+  int ns = 0;
+  __device__ __forceinline__ void push(double t, double wt, bool ap, double xb) {
+#pragma unroll
+    for (int k = 0; k < kShortMax; ++k)
+      if (k == ns) {
+        tau[k] = t;
+        w[k] = wt;
+      }
+    const bool s0 = ap ? (xb <= t) : (xb >= t);
+    apos |= (ap ? 1u : 0u) << ns;
+    sat0 |= (s0 ? 1u : 0u) << ns;
+    ns += 1;
+  }
+};
 
 template <int D>
 __device__ __forceinline__ void short_general(const DevProblem& P, const double* x, const RowState* rs,
-                                              const WalkState* st, double* xhat, double* sc, int j) {
-  constexpr int NSLOT = 2 * D + 1;
+                                              const WalkState* st, double* xhat, double* sc, int q) {
   const double eps = P.eps;
-  const double xb = x[j];
-  const bool isint = P.is_int[j] != 0;
-  const double l = P.lb[j], u = P.ub[j];
-  const int beg = P.col_ptr[j];
-  double tau[NSLOT];
-  double wv[NSLOT];
-  uint32_t valid = 0, apos = 0, sat0 = 0;
+  const double xb = x[q];
+  const bool isint = P.is_int[q] != 0;
+  const double l = P.lb[q], u = P.ub[q];
+  const int beg = P.col_ptr[q];
+  ShortSlots S;
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    const int e = beg + q;
-    const RowState rr = rs[P.col_row[e]];
-    const double a = P.col_val[e];
-    const double t0 = breakpoint(xb, rr.r, a, eps, isint);
-    tau[2 * q] = t0;
-    wv[2 * q] = (double)rr.w0;
-    valid |= 1u << (2 * q);
-    if (a > 0.0) {
-      apos |= 1u << (2 * q);
-      if (xb <= t0) sat0 |= 1u << (2 * q);
-    } else if (xb >= t0) {
-      sat0 |= 1u << (2 * q);
-    }
-    if (rr.w1 >= 0.0f) {
-      const double t1 = breakpoint(xb, -rr.r, -a, eps, isint);
-      tau[2 * q + 1] = t1;
-      wv[2 * q + 1] = (double)rr.w1;
-      valid |= 1u << (2 * q + 1);
-      if (-a > 0.0) {
-        apos |= 1u << (2 * q + 1);
-        if (xb <= t1) sat0 |= 1u << (2 * q + 1);
-      } else if (xb >= t1) {
-        sat0 |= 1u << (2 * q + 1);
-      }
-    } else {
-      tau[2 * q + 1] = 0.0;
-      wv[2 * q + 1] = 0.0;
-    }
+  for (int k = 0; k < kShortMax; ++k) {
+    S.tau[k] = 0.0;
+    S.w[k] = 0.0;
   }
-  tau[2 * D] = 0.0;
-  wv[2 * D] = 0.0;
+  // loads of all D entries first (independent), then the breakpoints
+  RowState rr[D > 0 ? D : 1];
+  double av[D > 0 ? D : 1];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    av[k] = P.col_val[beg + k];
+    rr[k] = rs[P.col_row[beg + k]];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = av[k];
+    S.push(breakpoint(xb, rr[k].r, a, eps, isint), (double)rr[k].w0, a > 0.0, xb);
+    if (rr[k].w1 >= 0.0f) S.push(breakpoint(xb, -rr[k].r, -a, eps, isint), (double)rr[k].w1, -a > 0.0, xb);
+  }
   if (st->cut_active) {
-    const double c = P.obj[j];
-    if (c != 0.0) {
-      const double t2 = breakpoint(xb, st->rc, c, eps, isint);
-      tau[2 * D] = t2;
-      wv[2 * D] = (double)st->wc;
-      valid |= 1u << (2 * D);
-      if (c > 0.0) {
-        apos |= 1u << (2 * D);
-        if (xb <= t2) sat0 |= 1u << (2 * D);
-      } else if (xb >= t2) {
-        sat0 |= 1u << (2 * D);
-      }
-    }
+    const double c = P.obj[q];
+    if (c != 0.0) S.push(breakpoint(xb, st->rc, c, eps, isint), (double)st->wc, c > 0.0, xb);
   }
   bool found = false;
   double best = 0.0, bestp = xb;
@@ -240,18 +228,18 @@ __device__ __forceinline__ void short_general(const DevProblem& P, const double*
     if (!(p >= l && p <= u) || p == xb || !isfinite(p)) return;
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < NSLOT; ++k) {
-      if ((valid >> k) & 1u) {
-        const bool ap = (apos >> k) & 1u;
-        const bool s0 = (sat0 >> k) & 1u;
-        const bool s1 = ap ? (p <= tau[k]) : (p >= tau[k]);
+    for (int k = 0; k < kShortMax; ++k) {
+      if (k < S.ns) {
+        const bool ap = (S.apos >> k) & 1u;
+        const bool s0 = (S.sat0 >> k) & 1u;
+        const bool s1 = ap ? (p <= S.tau[k]) : (p >= S.tau[k]);
         double c;
         if (s0)
-          c = s1 ? 0.0 : -wv[k];
+          c = s1 ? 0.0 : -S.w[k];
         else if (s1)
-          c = wv[k];
+          c = S.w[k];
         else
-          c = (ap ? (p < xb) : (p > xb)) ? 0.5 * wv[k] : -0.5 * wv[k];
+          c = (ap ? (p < xb) : (p > xb)) ? 0.5 * S.w[k] : -0.5 * S.w[k];
         v += c;
       }
     }
@@ -264,72 +252,78 @@ __device__ __forceinline__ void short_general(const DevProblem& P, const double*
   consider(l);
   consider(u);
 #pragma unroll
-  for (int k = 0; k < NSLOT; ++k)
-    if ((valid >> k) & 1u) consider(tau[k]);
-  write_result(xhat, sc, j, found, best, bestp, xb);
+  for (int k = 0; k < kShortMax; ++k)
+    if (k < S.ns) consider(S.tau[k]);
+  write_result(xhat, sc, q, found, best, bestp, xb);
 }
+
+// Short columns occupy the internal range [seg[0], seg[10]): binaries in
+// [seg[0], seg[1]), then non-binary columns with D stored entries in
+// [seg[1 + D], seg[2 + D]) for D = 0..8.
+struct ShortSegs {
+  int32_t seg[kShortMax + 3];
+};
 
 __global__ __launch_bounds__(256) void k_short(DevProblem P, const double* __restrict__ x,
                                                const RowState* __restrict__ rs, const WalkState* __restrict__ st,
-                                               double* __restrict__ xhat, double* __restrict__ sc,
-                                               const int32_t* __restrict__ list, ShortSegs segs) {
+                                               double* __restrict__ xhat, double* __restrict__ sc, ShortSegs S) {
   if (st->k >= st->iters) return;
-  const int b = blockIdx.x;
-  const int j = list[b * 256 + threadIdx.x];
-  if (j < 0) return;
-  int g = 0;
+  const int q = S.seg[0] + blockIdx.x * 256 + threadIdx.x;
+  if (q >= S.seg[kShortMax + 2]) return;
+  if (q < S.seg[1]) {
+    flip_column(P, x, rs, st, xhat, sc, q);
+    return;
+  }
+  int D = 0;
 #pragma unroll
-  for (int q = 1; q < kShortMax + 2; ++q)
-    if (b >= segs.wg_begin[q]) g = q;
-  switch (g) {
-    case 0: flip_column(P, x, rs, st, xhat, sc, j); break;
-    case 1: short_general<0>(P, x, rs, st, xhat, sc, j); break;
-    case 2: short_general<1>(P, x, rs, st, xhat, sc, j); break;
-    case 3: short_general<2>(P, x, rs, st, xhat, sc, j); break;
-    case 4: short_general<3>(P, x, rs, st, xhat, sc, j); break;
-    case 5: short_general<4>(P, x, rs, st, xhat, sc, j); break;
-    case 6: short_general<5>(P, x, rs, st, xhat, sc, j); break;
-    case 7: short_general<6>(P, x, rs, st, xhat, sc, j); break;
-    case 8: short_general<7>(P, x, rs, st, xhat, sc, j); break;
-    default: short_general<8>(P, x, rs, st, xhat, sc, j); break;
+  for (int k = 1; k <= kShortMax; ++k)
+    if (q >= S.seg[1 + k]) D = k;
+  switch (D) {
+    case 0: short_general<0>(P, x, rs, st, xhat, sc, q); break;
+    case 1: short_general<1>(P, x, rs, st, xhat, sc, q); break;
+    case 2: short_general<2>(P, x, rs, st, xhat, sc, q); break;
+    case 3: short_general<3>(P, x, rs, st, xhat, sc, q); break;
+    case 4: short_general<4>(P, x, rs, st, xhat, sc, q); break;
+    case 5: short_general<5>(P, x, rs, st, xhat, sc, q); break;
+    case 6: short_general<6>(P, x, rs, st, xhat, sc, q); break;
+    case 7: short_general<7>(P, x, rs, st, xhat, sc, q); break;
+    default: short_general<8>(P, x, rs, st, xhat, sc, q); break;
   }
 }
 
 // ---------------------------------------------------------------------------
-// k_flip_wave: one wavefront per binary column.
+// k_flip_wave: one wavefront per longer binary column.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_flip_wave(DevProblem P, const double* __restrict__ x,
                                                    const RowState* __restrict__ rs,
                                                    const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                   double* __restrict__ sc, const int32_t* __restrict__ list,
-                                                   int32_t count) {
+                                                   double* __restrict__ sc, int32_t q0, int32_t q1) {
   if (st->k >= st->iters) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= count) return;
-  const int j = list[idx];
+  const int q = q0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= q1) return;
   const double eps = P.eps;
-  const double xb = x[j];
+  const double xb = x[q];
   const double xn = 1.0 - xb;
   const double d = xn - xb;
   double s = 0.0;
-  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
   for (int e = beg + lane; e < end; e += kWave) {
-    const RowState q = rs[P.col_row[e]];
-    const double r2 = q.r + P.col_val[e] * d;
-    s += penalty(q.r, r2, (double)q.w0, eps);
-    if (q.w1 >= 0.0f) s += penalty(-q.r, -r2, (double)q.w1, eps);
+    const RowState r = rs[P.col_row[e]];
+    const double r2 = r.r + P.col_val[e] * d;
+    s += penalty(r.r, r2, (double)r.w0, eps);
+    if (r.w1 >= 0.0f) s += penalty(-r.r, -r2, (double)r.w1, eps);
   }
   if (lane == 0 && st->cut_active) {
-    const double c = P.obj[j];
+    const double c = P.obj[q];
     if (c != 0.0) {
       const double r2 = st->rc + c * d;
       s += penalty(st->rc, r2, (double)st->wc, eps);
     }
   }
   s = wave_sum(s);
-  if (lane == 0) write_result(xhat, sc, j, true, s, xn, xb);
+  if (lane == 0) write_result(xhat, sc, q, true, s, xn, xb);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,8 +349,8 @@ __device__ __forceinline__ void narrow_entry(double xb, double r, double a, doub
     atomicAdd(&bins[k + 1], e.delta);
 }
 
-// Scan + argmax over the bins of one column, done by one wavefront. Lane k
-// holds bins[k]; returns (found, best, bestp) on lane 0.
+// Scan + argmax over the 64 bins of one column by one wavefront; lane b holds
+// bin b. The result is valid on every lane.
 __device__ __forceinline__ void narrow_finish(double binv, double beta, double alpha, unsigned long long cand,
                                               double xb, double l, int W, int lane, bool& found, double& best,
                                               double& bestp) {
@@ -377,39 +371,38 @@ __device__ __forceinline__ void narrow_finish(double binv, double beta, double a
   bestp = found ? l + (double)key : xb;
 }
 
+// One wavefront per narrow column (4 columns per workgroup), 64 LDS bins each.
 __global__ __launch_bounds__(256) void k_narrow_wave(DevProblem P, const double* __restrict__ x,
                                                      const RowState* __restrict__ rs,
                                                      const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                     double* __restrict__ sc, const int32_t* __restrict__ list,
-                                                     int32_t count) {
+                                                     double* __restrict__ sc, int32_t q0, int32_t q1) {
   if (st->k >= st->iters) return;
   __shared__ double bins[4][kNarrowBins];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
-  const int idx = blockIdx.x * 4 + wv;
-  const bool active = idx < count;
+  const int q = q0 + blockIdx.x * 4 + wv;
+  const bool active = q < q1;
   bins[wv][lane] = 0.0;
   __syncthreads();
   const double eps = P.eps;
   double beta = 0.0, alpha = 0.0;
   unsigned long long cand = 0;
-  int j = 0, W = 0;
   double xb = 0.0, l = 0.0, u = 0.0;
+  int W = 0;
   if (active) {
-    j = list[idx];
-    xb = x[j];
-    l = P.lb[j];
-    u = P.ub[j];
+    xb = x[q];
+    l = P.lb[q];
+    u = P.ub[q];
     W = (int)(u - l) + 1;
-    const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+    const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
     for (int e = beg + lane; e < end; e += kWave) {
-      const RowState q = rs[P.col_row[e]];
+      const RowState r = rs[P.col_row[e]];
       const double a = P.col_val[e];
-      narrow_entry(xb, q.r, a, (double)q.w0, eps, l, u, W, bins[wv], beta, alpha, cand);
-      if (q.w1 >= 0.0f) narrow_entry(xb, -q.r, -a, (double)q.w1, eps, l, u, W, bins[wv], beta, alpha, cand);
+      narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins[wv], beta, alpha, cand);
+      if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins[wv], beta, alpha, cand);
     }
     if (lane == 0 && st->cut_active) {
-      const double c = P.obj[j];
+      const double c = P.obj[q];
       if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins[wv], beta, alpha, cand);
     }
   }
@@ -421,11 +414,13 @@ __global__ __launch_bounds__(256) void k_narrow_wave(DevProblem P, const double*
   bool found;
   double best, bestp;
   narrow_finish(bins[wv][lane], beta, alpha, cand, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(xhat, sc, j, found, best, bestp, xb);
+  if (lane == 0) write_result(xhat, sc, q, found, best, bestp, xb);
 }
 
 // One workgroup per chunk of a long narrow column: bins, beta, alpha and the
-// candidate mask of the chunk go to its partial record (plain stores).
+// candidate mask of the chunk go to the chunk's partial record. Chunks are
+// cut along row ranges and ordered so that consecutive workgroups (placed on
+// consecutive XCDs) gather rows from one range each.
 __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double* __restrict__ x,
                                                       const RowState* __restrict__ rs,
                                                       const WalkState* __restrict__ st,
@@ -439,24 +434,41 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
   const int lane = tid & (kWave - 1);
   const int wv = tid >> 6;
   const ChunkTask T = tasks[blockIdx.x];
-  const int j = T.col;
-  const double eps = P.eps;
-  const double xb = x[j];
-  const double l = P.lb[j], u = P.ub[j];
-  const int W = (int)(u - l) + 1;
   if (tid < kNarrowBins) bins[tid] = 0.0;
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
   unsigned long long cand = 0;
-  for (int e = T.e_beg + tid; e < T.e_end; e += blockDim.x) {
-    const RowState q = rs[P.col_row[e]];
-    const double a = P.col_val[e];
-    narrow_entry(xb, q.r, a, (double)q.w0, eps, l, u, W, bins, beta, alpha, cand);
-    if (q.w1 >= 0.0f) narrow_entry(xb, -q.r, -a, (double)q.w1, eps, l, u, W, bins, beta, alpha, cand);
-  }
-  if (tid == 0 && blockIdx.x == T.first && st->cut_active) {
-    const double c = P.obj[j];
-    if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
+  if (T.col >= 0) {
+    const int q = T.col;
+    const double eps = P.eps;
+    const double xb = x[q];
+    const double l = P.lb[q], u = P.ub[q];
+    const int W = (int)(u - l) + 1;
+    int e = T.e_beg + tid;
+    // two entries per step: both gathers are issued before either is used
+    for (; e + 256 < T.e_end; e += 512) {
+      const int i0 = __builtin_nontemporal_load(&P.col_row[e]);
+      const int i1 = __builtin_nontemporal_load(&P.col_row[e + 256]);
+      const double a0 = __builtin_nontemporal_load(&P.col_val[e]);
+      const double a1 = __builtin_nontemporal_load(&P.col_val[e + 256]);
+      const RowState r0 = rs[i0];
+      const RowState r1 = rs[i1];
+      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u, W, bins, beta, alpha, cand);
+      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u, W, bins, beta, alpha, cand);
+      narrow_entry(xb, r1.r, a1, (double)r1.w0, eps, l, u, W, bins, beta, alpha, cand);
+      if (r1.w1 >= 0.0f) narrow_entry(xb, -r1.r, -a1, (double)r1.w1, eps, l, u, W, bins, beta, alpha, cand);
+    }
+    if (e < T.e_end) {
+      const int i0 = __builtin_nontemporal_load(&P.col_row[e]);
+      const double a0 = __builtin_nontemporal_load(&P.col_val[e]);
+      const RowState r0 = rs[i0];
+      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u, W, bins, beta, alpha, cand);
+      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u, W, bins, beta, alpha, cand);
+    }
+    if (tid == 0 && T.first && st->cut_active) {
+      const double c = P.obj[q];
+      if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
+    }
   }
   beta = wave_sum(beta);
   alpha = wave_sum(alpha);
@@ -467,7 +479,8 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
     red_c[wv] = cand;
   }
   __syncthreads();
-  ChunkPartial* mine = partials + blockIdx.x;
+  if (T.col < 0) return;
+  ChunkPartial* mine = partials + T.slot;
   if (tid < kNarrowBins) mine->bins[tid] = bins[tid];
   if (tid == 0) {
     mine->beta = red_b[0] + red_b[1] + red_b[2] + red_b[3];
@@ -477,24 +490,24 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
 }
 
 // One wavefront per long narrow column: combines its chunks' partials in
-// chunk order (deterministic), then scan and argmax over the bins.
+// slot order (deterministic), then scan and argmax over the bins.
 __global__ __launch_bounds__(256) void k_narrow_combine(DevProblem P, const double* __restrict__ x,
                                                         const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                        double* __restrict__ sc, const ChunkTask* __restrict__ heads,
+                                                        double* __restrict__ sc, const ChunkCol* __restrict__ cols,
                                                         int32_t count, const ChunkPartial* __restrict__ partials) {
   if (st->k >= st->iters) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (idx >= count) return;
-  const ChunkTask T = heads[idx];
-  const int j = T.col;
-  const double xb = x[j];
-  const double l = P.lb[j], u = P.ub[j];
+  const ChunkCol C = cols[idx];
+  const int q = C.col;
+  const double xb = x[q];
+  const double l = P.lb[q], u = P.ub[q];
   const int W = (int)(u - l) + 1;
   double bv = 0.0, b = 0.0, a = 0.0;
   unsigned long long c = 0;
-  for (int q = 0; q < T.nchunks; ++q) {
-    const ChunkPartial* pp = partials + T.first + q;
+  for (int k = 0; k < C.nparts; ++k) {
+    const ChunkPartial* pp = partials + C.first + k;
     bv += pp->bins[lane];
     b += pp->beta;
     a += pp->alpha;
@@ -503,7 +516,7 @@ __global__ __launch_bounds__(256) void k_narrow_combine(DevProblem P, const doub
   bool found;
   double best, bestp;
   narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(xhat, sc, j, found, best, bestp, xb);
+  if (lane == 0) write_result(xhat, sc, q, found, best, bestp, xb);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,8 +666,7 @@ template <int CAP>
 __global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* __restrict__ x,
                                                     const RowState* __restrict__ rs,
                                                     const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                    double* __restrict__ sc, const int32_t* __restrict__ list,
-                                                    int32_t count) {
+                                                    double* __restrict__ sc, int32_t q0) {
   if (st->k >= st->iters) return;
   __shared__ double spos[CAP];
   __shared__ double sdel[CAP];
@@ -662,7 +674,7 @@ __global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* 
   __shared__ int scount;
   __shared__ double red[8];
   __shared__ int redk[8];
-  const int j = list[blockIdx.x];
+  const int j = q0 + blockIdx.x;
   const double xb = x[j];
   if (threadIdx.x == 0) scount = 0;
   __syncthreads();
@@ -755,36 +767,36 @@ __global__ __launch_bounds__(1024) void k_sort_long(DevProblem P, const double* 
 
 hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, const double* x, const RowState* rs,
                                   const WalkState* st, double* xhat, double* s, hipStream_t stream) {
-  if (plan.n_short > 0) {
+  const int nshort = plan.short_seg[kShortMax + 2] - plan.short_seg[0];
+  if (nshort > 0) {
     ShortSegs segs;
-    for (int q = 0; q < kShortMax + 3; ++q) segs.wg_begin[q] = plan.short_segs[q];
-    const int blocks = plan.short_segs[kShortMax + 2];
-    hipLaunchKernelGGL(k_short, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, xhat, s, plan.short_cols, segs);
+    for (int k = 0; k < kShortMax + 3; ++k) segs.seg[k] = plan.short_seg[k];
+    hipLaunchKernelGGL(k_short, dim3((nshort + 255) / 256), dim3(256), 0, stream, P, x, rs, st, xhat, s, segs);
   }
-  if (plan.n_flip > 0)
-    hipLaunchKernelGGL(k_flip_wave, dim3((plan.n_flip + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.flip_cols, plan.n_flip);
-  if (plan.n_narrow > 0)
-    hipLaunchKernelGGL(k_narrow_wave, dim3((plan.n_narrow + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.narrow_cols, plan.n_narrow);
+  const int nflip = plan.flip_end - plan.flip_begin;
+  if (nflip > 0)
+    hipLaunchKernelGGL(k_flip_wave, dim3((nflip + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.flip_begin, plan.flip_end);
+  const int nnarrow = plan.narrow_end - plan.narrow_begin;
+  if (nnarrow > 0)
+    hipLaunchKernelGGL(k_narrow_wave, dim3((nnarrow + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
+                       plan.narrow_begin, plan.narrow_end);
   if (plan.n_chunks > 0) {
     hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, plan.chunks,
                        plan.partials);
     hipLaunchKernelGGL(k_narrow_combine, dim3((plan.n_chunk_cols + 3) / 4), dim3(256), 0, stream, P, x, st, xhat, s,
-                       plan.chunk_heads, plan.n_chunk_cols, plan.partials);
+                       plan.chunk_cols, plan.n_chunk_cols, plan.partials);
   }
-  if (plan.n_sort[0] > 0)
-    hipLaunchKernelGGL(k_sort_block<64>, dim3(plan.n_sort[0]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.sort_cols[0], plan.n_sort[0]);
-  if (plan.n_sort[1] > 0)
-    hipLaunchKernelGGL(k_sort_block<256>, dim3(plan.n_sort[1]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.sort_cols[1], plan.n_sort[1]);
-  if (plan.n_sort[2] > 0)
-    hipLaunchKernelGGL(k_sort_block<1024>, dim3(plan.n_sort[2]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.sort_cols[2], plan.n_sort[2]);
-  if (plan.n_sort[3] > 0)
-    hipLaunchKernelGGL(k_sort_block<4096>, dim3(plan.n_sort[3]), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.sort_cols[3], plan.n_sort[3]);
+  for (int c = 0; c < kSortCaps; ++c) {
+    const int q0 = plan.sort_begin[c], n = plan.sort_begin[c + 1] - q0;
+    if (n <= 0) continue;
+    switch (c) {
+      case 0: hipLaunchKernelGGL(k_sort_block<64>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
+      case 1: hipLaunchKernelGGL(k_sort_block<256>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
+      case 2: hipLaunchKernelGGL(k_sort_block<1024>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
+      default: hipLaunchKernelGGL(k_sort_block<4096>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
+    }
+  }
   if (plan.n_long > 0)
     hipLaunchKernelGGL(k_sort_long, dim3(plan.n_long), dim3(1024), 0, stream, P, x, rs, st, xhat, s,
                        plan.long_tasks, plan.long_pos, plan.long_marker, plan.long_delta);

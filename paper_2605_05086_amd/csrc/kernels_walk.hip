@@ -181,74 +181,74 @@ __device__ __forceinline__ bool better(double sa, int ja, double sb, int jb) {
   return sa > sb || (sa == sb && ja < jb);
 }
 
-// Best positive score overall (j_all) and among non-tabu variables (j_nt),
-// ties to the lowest index; one partial record per workgroup. The pending
-// copy of a new incumbent (flagged by the previous iteration, before this
+// Running best (score desc, original index asc) with the internal index.
+struct Best {
+  double s = 0.0;
+  int j = INT_MAX;  // original index
+  int q = -1;       // internal index
+  __device__ __forceinline__ void offer(double s2, int j2, int q2) {
+    if (better(s2, j2, s, j)) {
+      s = s2;
+      j = j2;
+      q = q2;
+    }
+  }
+  __device__ __forceinline__ void wave_reduce() {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) offer(__shfl_xor(s, o, kWave), __shfl_xor(j, o, kWave), __shfl_xor(q, o, kWave));
+  }
+};
+
+constexpr int kPartialStride = kArgmaxRecord;
+
+// Best positive score overall and among non-tabu variables, ties to the
+// lowest original index; one partial record per workgroup. The pending copy
+// of a new incumbent (flagged by the previous iteration, before this
 // iteration's move changes x) is done here too.
 __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, const int32_t* __restrict__ tabu,
-                                                const WalkState* __restrict__ st, double* __restrict__ partial,
-                                                const double* __restrict__ x, double* __restrict__ best_x,
-                                                int32_t n) {
+                                                const int32_t* __restrict__ perm, const WalkState* __restrict__ st,
+                                                double* __restrict__ partial, const double* __restrict__ x,
+                                                double* __restrict__ best_x, int32_t n) {
   if (st->k >= st->iters) return;
-  __shared__ double rs_a[4], rs_n[4];
-  __shared__ int rj_a[4], rj_n[4];
+  __shared__ double sa_s[4], sn_s[4];
+  __shared__ int ja_s[4], jn_s[4], qa_s[4], qn_s[4];
   const int64_t k = st->k;
   const bool copy = st->copy_best != 0;
-  double sa = 0.0, sn = 0.0;
-  int ja = INT_MAX, jn = INT_MAX;
+  Best ba, bn;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int gs = gridDim.x * blockDim.x;
-  for (int j = gt; j < n; j += gs) {
-    if (copy) best_x[j] = x[j];
-    const double v = s[j];
+  for (int q = gt; q < n; q += gs) {
+    if (copy) best_x[q] = x[q];
+    const double v = s[q];
     if (!(v > 0.0)) continue;
-    if (better(v, j, sa, ja)) {
-      sa = v;
-      ja = j;
-    }
-    if (k > (int64_t)tabu[j] && better(v, j, sn, jn)) {
-      sn = v;
-      jn = j;
-    }
+    const int j = perm[q];
+    ba.offer(v, j, q);
+    if (k > (int64_t)tabu[q]) bn.offer(v, j, q);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double osa = __shfl_xor(sa, o, kWave);
-    const int oja = __shfl_xor(ja, o, kWave);
-    const double osn = __shfl_xor(sn, o, kWave);
-    const int ojn = __shfl_xor(jn, o, kWave);
-    if (better(osa, oja, sa, ja)) {
-      sa = osa;
-      ja = oja;
-    }
-    if (better(osn, ojn, sn, jn)) {
-      sn = osn;
-      jn = ojn;
-    }
-  }
+  ba.wave_reduce();
+  bn.wave_reduce();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
-    rs_a[wv] = sa;
-    rj_a[wv] = ja;
-    rs_n[wv] = sn;
-    rj_n[wv] = jn;
+    sa_s[wv] = ba.s;
+    ja_s[wv] = ba.j;
+    qa_s[wv] = ba.q;
+    sn_s[wv] = bn.s;
+    jn_s[wv] = bn.j;
+    qn_s[wv] = bn.q;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 1; q < 4; ++q) {
-      if (better(rs_a[q], rj_a[q], sa, ja)) {
-        sa = rs_a[q];
-        ja = rj_a[q];
-      }
-      if (better(rs_n[q], rj_n[q], sn, jn)) {
-        sn = rs_n[q];
-        jn = rj_n[q];
-      }
+    for (int w = 1; w < 4; ++w) {
+      ba.offer(sa_s[w], ja_s[w], qa_s[w]);
+      bn.offer(sn_s[w], jn_s[w], qn_s[w]);
     }
-    partial[4 * blockIdx.x] = sa;
-    partial[4 * blockIdx.x + 1] = (double)ja;
-    partial[4 * blockIdx.x + 2] = sn;
-    partial[4 * blockIdx.x + 3] = (double)jn;
+    double* rec = partial + kPartialStride * blockIdx.x;
+    rec[0] = ba.s;
+    rec[1] = (double)ba.j;
+    rec[2] = (double)ba.q;
+    rec[3] = bn.s;
+    rec[4] = (double)bn.j;
+    rec[5] = (double)bn.q;
   }
 }
 
@@ -263,111 +263,89 @@ __global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __re
                                                 WalkState* st, chap_trace_record* trace,
                                                 const double* __restrict__ partial, int32_t nparts) {
   if (st->k >= st->iters) return;
-  __shared__ double rs_a[4], rs_n[4];
-  __shared__ int rj_a[4], rj_n[4];
+  __shared__ double sa_s[4], sn_s[4];
+  __shared__ int ja_s[4], jn_s[4], qa_s[4], qn_s[4];
   __shared__ long long red[4];
   const double eps = P.eps;
   const int64_t k = st->k;
-  double sa = 0.0, sn = 0.0;
-  int ja = INT_MAX, jn = INT_MAX;
+  Best ba, bn;
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    const double a = partial[4 * b], na = partial[4 * b + 2];
-    const int aj = (int)partial[4 * b + 1], nj = (int)partial[4 * b + 3];
-    if (better(a, aj, sa, ja)) {
-      sa = a;
-      ja = aj;
-    }
-    if (better(na, nj, sn, jn)) {
-      sn = na;
-      jn = nj;
-    }
+    const double* rec = partial + kPartialStride * b;
+    ba.offer(rec[0], (int)rec[1], (int)rec[2]);
+    bn.offer(rec[3], (int)rec[4], (int)rec[5]);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double osa = __shfl_xor(sa, o, kWave);
-    const int oja = __shfl_xor(ja, o, kWave);
-    const double osn = __shfl_xor(sn, o, kWave);
-    const int ojn = __shfl_xor(jn, o, kWave);
-    if (better(osa, oja, sa, ja)) {
-      sa = osa;
-      ja = oja;
-    }
-    if (better(osn, ojn, sn, jn)) {
-      sn = osn;
-      jn = ojn;
-    }
-  }
+  ba.wave_reduce();
+  bn.wave_reduce();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
-    rs_a[wv] = sa;
-    rj_a[wv] = ja;
-    rs_n[wv] = sn;
-    rj_n[wv] = jn;
+    sa_s[wv] = ba.s;
+    ja_s[wv] = ba.j;
+    qa_s[wv] = ba.q;
+    sn_s[wv] = bn.s;
+    jn_s[wv] = bn.j;
+    qn_s[wv] = bn.q;
   }
   __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    if (better(rs_a[q], rj_a[q], sa, ja)) {
-      sa = rs_a[q];
-      ja = rj_a[q];
-    }
-    if (better(rs_n[q], rj_n[q], sn, jn)) {
-      sn = rs_n[q];
-      jn = rj_n[q];
-    }
+  for (int w = 0; w < 4; ++w) {
+    ba.offer(sa_s[w], ja_s[w], qa_s[w]);
+    bn.offer(sn_s[w], jn_s[w], qn_s[w]);
   }
-  if (ja == INT_MAX) ja = -1;
-  if (jn == INT_MAX) jn = -1;
-  int jstar = -1, kind = 2;
-  if (ja >= 0 && k > (int64_t)tabu[ja]) {
-    jstar = ja;
+  const int qa = (ba.j == INT_MAX) ? -1 : ba.q;
+  const int qn = (bn.j == INT_MAX) ? -1 : bn.q;
+  int qstar = -1, jstar = -1, kind = 2;
+  if (qa >= 0 && k > (int64_t)tabu[qa]) {
+    qstar = qa;
+    jstar = ba.j;
     kind = 0;
-  } else if (ja >= 0) {
-    const int beg = P.col_ptr[ja], end = P.col_ptr[ja + 1];
+  } else if (qa >= 0) {
+    const int beg = P.col_ptr[qa], end = P.col_ptr[qa + 1];
     const int64_t bound = 2 * (int64_t)(end - beg) + 1;
     long long dv = 0;
     if (st->V <= bound) {
-      const double d = xhat[ja] - x[ja];
+      const double d = xhat[qa] - x[qa];
       for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const RowState q = rs[P.col_row[e]];
-        const double r2 = q.r + P.col_val[e] * d;
-        dv += viol_change(q.r, r2, eps);
-        if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+        const RowState r = rs[P.col_row[e]];
+        const double r2 = r.r + P.col_val[e] * d;
+        dv += viol_change(r.r, r2, eps);
+        if (r.w1 >= 0.0f) dv += viol_change(-r.r, -r2, eps);
       }
       dv = block_sum_ll(dv, red);
       if (st->cut_active) {
-        const double c = P.obj[ja];
+        const double c = P.obj[qa];
         if (c != 0.0) dv += viol_change(st->rc, st->rc + c * d, eps);
       }
     }
     if (st->V <= bound && st->V + dv == 0) {
-      jstar = ja;
+      qstar = qa;
+      jstar = ba.j;
       kind = 1;
-    } else if (jn >= 0) {
-      jstar = jn;
+    } else if (qn >= 0) {
+      qstar = qn;
+      jstar = bn.j;
       kind = 0;
     }
   }
   if (threadIdx.x != 0) return;
-  st->j_all = ja;
-  st->s_all = sa;
-  st->j_nt = jn;
-  st->s_nt = sn;
+  st->j_all = (qa >= 0) ? ba.j : -1;
+  st->s_all = ba.s;
+  st->j_nt = (qn >= 0) ? bn.j : -1;
+  st->s_nt = bn.s;
   st->copy_best = 0;
-  st->mv_j = jstar;
+  st->mv_j = qstar;
   st->mv_kind = kind;
   chap_trace_record* t = trace + k;
   t->iter = k;
   t->var = jstar;
   t->kind = kind;
-  if (jstar >= 0) {
-    const double xo = x[jstar], xn = xhat[jstar];
+  if (qstar >= 0) {
+    const double xo = x[qstar], xn = xhat[qstar];
     st->mv_old = xo;
     st->mv_new = xn;
     st->mv_delta = xn - xo;
-    st->mv_score = s[jstar];
+    st->mv_score = s[qstar];
     t->x_old = xo;
     t->x_new = xn;
-    t->score = s[jstar];
+    t->score = s[qstar];
   } else {
     st->mv_delta = 0.0;
     t->x_old = 0.0;
@@ -464,6 +442,22 @@ __global__ __launch_bounds__(256) void k_copy_best(const double* __restrict__ x,
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gs) best_x[j] = x[j];
 }
 
+__global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                                                double* __restrict__ dst, int32_t n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[perm[q]];
+}
+
+__global__ __launch_bounds__(256) void k_scatter2(const int32_t* __restrict__ perm, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double* __restrict__ da,
+                                                  double* __restrict__ db, int32_t n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int j = perm[q];
+  da[j] = a[q];
+  db[j] = b[q];
+}
+
 inline int blocks_for(int64_t work, int cap) {
   int64_t b = (work + 255) / 256;
   if (b < 1) b = 1;
@@ -506,11 +500,23 @@ hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, 
                             int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
                             double* argmax_partial, int32_t apply_blocks, int32_t recompute, hipStream_t stream) {
   const int ab = blocks_for(P.n, kArgmaxBlocks);
-  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, st, argmax_partial, x, best_x, P.n);
+  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, P.perm, st, argmax_partial, x, best_x,
+                     P.n);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace,
                      argmax_partial, ab);
   hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, st, recompute);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, stream, P, x, tabu_until, st, trace);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream) {
+  if (n > 0) hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, stream, perm, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
+                           hipStream_t stream) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter2, dim3((n + 255) / 256), dim3(256), 0, stream, perm, a, b, da, db, n);
   return hipGetLastError();
 }
 

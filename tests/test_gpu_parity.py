@@ -314,3 +314,25 @@ def test_full_size_powerlaw(chap):
     G = chap.Problem(mip)
     say("tabu powerlaw full 3 iters")
     compare_runs(G.tabu_run(3, 10, 0), P.tabu_run(3, 10, 0), "powerlaw full")
+
+
+def test_best_shift_repeatable(chap):
+    """Identical passes on one problem give identical results equal to the
+    oracle (catches timing-dependent corruption in the pass kernels)."""
+    import torch
+
+    mip = mipgen.powerlaw(0, n=200_000, m=100_000, nnz=2_000_000, cap=20_000)
+    P = oracle.OracleProblem(mip)
+    w = mipgen.random_weights(P.mp + 1, 1, wmax=5)
+    G = chap.Problem(mip)
+    wd = torch.from_numpy(w).cuda()
+    for seed in (0, 3):
+        x = P.start_point(seed)
+        oxh, os_ = P.best_shift(x, w)
+        xd = torch.from_numpy(x).cuda()
+        for rep in range(4):
+            say(f"best_shift repeat seed={seed} rep={rep}")
+            xh, s = G.best_shift(xd, wd)
+            torch.cuda.synchronize()
+            assert_same(s.cpu().numpy(), os_, f"score rep={rep}")
+            assert_same(xh.cpu().numpy(), oxh, f"shift rep={rep}")
