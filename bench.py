@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--small", action="store_true", help="reduced instance for quick checks")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path does not "
@@ -119,6 +121,15 @@ def main():
     achieved = B / (pass_ms * 1e-3) / 1e9
     log(f"best-shift pass {pass_ms * 1e3:.1f} us, {B / 1e6:.1f} MB algorithmic, {achieved:.0f} GB/s")
 
+    if args.calibrate_copy_mb > 0:
+        src = torch.ones(args.calibrate_copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy_mb} MiB done")
+        del src, dst
+
     value = args.steps / wall
     result = {
         "metric": METRIC,
@@ -141,7 +152,7 @@ def main():
         "best_shift_nnz_per_s": nnz_pass / (pass_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "best-shift pass (k_short + k_narrow_wave + k_narrow_chunk)",
+                     "kernel": "best-shift pass (k_short + k_narrow_pack + k_narrow_chunk + k_narrow_combine)",
                      "bytes_per_launch": B},
     }
     if not args.no_cpu:

@@ -383,9 +383,23 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   L.flip_begin = (int32_t)perm.size();
   append(flip);
   L.flip_end = (int32_t)perm.size();
-  L.narrow_begin = (int32_t)perm.size();
+  std::vector<PackTask> packs;
+  {
+    int32_t q = (int32_t)perm.size();
+    PackTask t{q, q};
+    int64_t entries = 0;
+    for (int32_t j : narrow) {
+      if (t.q_end > t.q_begin && (t.q_end - t.q_begin == kPackCols || entries + deg[j] > kPackEntries)) {
+        packs.push_back(t);
+        t.q_begin = t.q_end;
+        entries = 0;
+      }
+      t.q_end += 1;
+      entries += deg[j];
+    }
+    if (t.q_end > t.q_begin) packs.push_back(t);
+  }
   append(narrow);
-  L.narrow_end = (int32_t)perm.size();
   const int32_t chunk_begin = (int32_t)perm.size();
   append(chunked);
   for (int c = 0; c < kSortCaps; ++c) {
@@ -531,6 +545,12 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   D.perm = d_perm;
   P->d_pair = d_pair;
   P->d_nidx = d_nidx;
+  if (!packs.empty()) {
+    PackTask* dp;
+    CHAP_HIP(A.upload(&dp, packs));
+    L.packs = dp;
+    L.n_packs = (int32_t)packs.size();
+  }
   if (!tasks.empty()) {
     ChunkTask* dt;
     CHAP_HIP(A.upload(&dt, tasks));

@@ -96,6 +96,14 @@ struct ChunkTask {
   int32_t first;  // 1 for exactly one task per column (adds the cutoff entry)
 };
 
+// Whole narrow columns [q_begin, q_end) scored by one workgroup.
+constexpr int kPackCols = 32;       // columns per pack (LDS: 32 x 64 bins)
+constexpr int kPackEntries = 1024;  // target stored entries per pack
+struct PackTask {
+  int32_t q_begin;
+  int32_t q_end;
+};
+
 // A long narrow column and its partial records [first, first + nparts).
 struct ChunkCol {
   int32_t col;
@@ -126,8 +134,9 @@ struct PassPlan {
   // columns with D stored entries [short_seg[1+D], short_seg[2+D])
   int32_t short_seg[kShortMax + 3] = {0};
   int32_t flip_begin = 0, flip_end = 0;
-  // narrow columns scored by one wavefront each
-  int32_t narrow_begin = 0, narrow_end = 0;
+  // packs of whole narrow columns
+  const PackTask* packs = nullptr;
+  int32_t n_packs = 0;
   const ChunkTask* chunks = nullptr;
   int32_t n_chunks = 0;
   ChunkPartial* partials = nullptr;

@@ -10,10 +10,10 @@
 //                  breakpoints, incumbent excluded) from the penalty
 //                  definition written in breakpoint form.
 //   k_flip_wave    one wavefront per longer binary column (flip score).
-//   k_narrow_wave  one wavefront per integer column with <= 64 values: the
-//                  sort of Algorithm 1 becomes a counting sort into 64 LDS
-//                  bins, the scan a wavefront prefix sum, the argmax a
-//                  wavefront reduction over candidate bins.
+//   k_narrow_pack  integer columns with <= 64 values, packed whole into
+//                  workgroups: the sort of Algorithm 1 becomes a counting sort
+//                  into 64 LDS bins per column, the scan a wavefront prefix
+//                  sum, the argmax a wavefront reduction over candidate bins.
 //   k_narrow_chunk the same for long columns split over many workgroups by
 //                  row range; k_narrow_combine adds the partial bins.
 //   k_sort_block   one workgroup per general column: LDS bitonic sort of the
@@ -371,50 +371,83 @@ __device__ __forceinline__ void narrow_finish(double binv, double beta, double a
   bestp = found ? l + (double)key : xb;
 }
 
-// One wavefront per narrow column (4 columns per workgroup), 64 LDS bins each.
-__global__ __launch_bounds__(256) void k_narrow_wave(DevProblem P, const double* __restrict__ x,
+// One workgroup per pack of whole narrow columns (consecutive internal
+// columns, at most kPackCols of them, about kPackEntries entries). The 256
+// threads stream the pack's concatenated CSC entries as one flat range; each
+// entry finds its column by binary search over the column starts and adds
+// into that column's 64 LDS bins, beta, alpha and candidate mask. Each
+// wavefront then scans and reduces a quarter of the pack's columns.
+__global__ __launch_bounds__(256) void k_narrow_pack(DevProblem P, const double* __restrict__ x,
                                                      const RowState* __restrict__ rs,
                                                      const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                     double* __restrict__ sc, int32_t q0, int32_t q1) {
+                                                     double* __restrict__ sc, const PackTask* __restrict__ packs) {
   if (st->k >= st->iters) return;
-  __shared__ double bins[4][kNarrowBins];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x >> 6;
-  const int q = q0 + blockIdx.x * 4 + wv;
-  const bool active = q < q1;
-  bins[wv][lane] = 0.0;
+  __shared__ double bins[kPackCols][kNarrowBins];
+  __shared__ double sbeta[kPackCols], salpha[kPackCols], sxb[kPackCols], sl[kPackCols], su[kPackCols];
+  __shared__ unsigned long long scand[kPackCols];
+  __shared__ int sstart[kPackCols + 1];
+  const int tid = threadIdx.x;
+  const PackTask T = packs[blockIdx.x];
+  const int nc = T.q_end - T.q_begin;
+  if (tid < nc) {
+    const int q = T.q_begin + tid;
+    sxb[tid] = x[q];
+    sl[tid] = P.lb[q];
+    su[tid] = P.ub[q];
+    sstart[tid] = P.col_ptr[q];
+    sbeta[tid] = 0.0;
+    salpha[tid] = 0.0;
+    scand[tid] = 0ull;
+  }
+  if (tid == 0) sstart[nc] = P.col_ptr[T.q_end];
+  for (int i = tid; i < nc * kNarrowBins; i += blockDim.x) bins[i / kNarrowBins][i % kNarrowBins] = 0.0;
   __syncthreads();
   const double eps = P.eps;
-  double beta = 0.0, alpha = 0.0;
-  unsigned long long cand = 0;
-  double xb = 0.0, l = 0.0, u = 0.0;
-  int W = 0;
-  if (active) {
-    xb = x[q];
-    l = P.lb[q];
-    u = P.ub[q];
-    W = (int)(u - l) + 1;
-    const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
-    for (int e = beg + lane; e < end; e += kWave) {
-      const RowState r = rs[P.col_row[e]];
-      const double a = P.col_val[e];
-      narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins[wv], beta, alpha, cand);
-      if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins[wv], beta, alpha, cand);
+  const int e0 = sstart[0], e1 = sstart[nc];
+  for (int e = e0 + tid; e < e1; e += blockDim.x) {
+    int lo = 0, hi = nc - 1;  // largest slot with sstart[slot] <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sstart[mid] <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
-    if (lane == 0 && st->cut_active) {
-      const double c = P.obj[q];
-      if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins[wv], beta, alpha, cand);
+    const int slot = lo;
+    const double xb = sxb[slot], l = sl[slot], u = su[slot];
+    const int W = (int)(u - l) + 1;
+    const RowState r = rs[P.col_row[e]];
+    const double a = P.col_val[e];
+    double db = 0.0, da = 0.0;
+    unsigned long long dc = 0ull;
+    narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins[slot], db, da, dc);
+    if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins[slot], db, da, dc);
+    if (db != 0.0) atomicAdd(&sbeta[slot], db);
+    if (da != 0.0) atomicAdd(&salpha[slot], da);
+    if (dc) atomicOr(&scand[slot], dc);
+  }
+  if (tid < nc && st->cut_active) {
+    const double c = P.obj[T.q_begin + tid];
+    if (c != 0.0) {
+      const double xb = sxb[tid], l = sl[tid], u = su[tid];
+      double db = 0.0, da = 0.0;
+      unsigned long long dc = 0ull;
+      narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, (int)(u - l) + 1, bins[tid], db, da, dc);
+      if (db != 0.0) atomicAdd(&sbeta[tid], db);
+      if (da != 0.0) atomicAdd(&salpha[tid], da);
+      if (dc) atomicOr(&scand[tid], dc);
     }
   }
   __syncthreads();
-  if (!active) return;
-  beta = wave_sum(beta);
-  alpha = wave_sum(alpha);
-  cand = wave_or(cand);
-  bool found;
-  double best, bestp;
-  narrow_finish(bins[wv][lane], beta, alpha, cand, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(xhat, sc, q, found, best, bestp, xb);
+  const int lane = tid & (kWave - 1);
+  for (int slot = tid >> 6; slot < nc; slot += (int)(blockDim.x >> 6)) {
+    const double l = sl[slot], xb = sxb[slot];
+    const int W = (int)(su[slot] - l) + 1;
+    bool found;
+    double best, bestp;
+    narrow_finish(bins[slot][lane], sbeta[slot], salpha[slot], scand[slot], xb, l, W, lane, found, best, bestp);
+    if (lane == 0) write_result(xhat, sc, T.q_begin + slot, found, best, bestp, xb);
+  }
 }
 
 // One workgroup per chunk of a long narrow column: bins, beta, alpha and the
@@ -777,10 +810,8 @@ hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, con
   if (nflip > 0)
     hipLaunchKernelGGL(k_flip_wave, dim3((nflip + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
                        plan.flip_begin, plan.flip_end);
-  const int nnarrow = plan.narrow_end - plan.narrow_begin;
-  if (nnarrow > 0)
-    hipLaunchKernelGGL(k_narrow_wave, dim3((nnarrow + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.narrow_begin, plan.narrow_end);
+  if (plan.n_packs > 0)
+    hipLaunchKernelGGL(k_narrow_pack, dim3(plan.n_packs), dim3(256), 0, stream, P, x, rs, st, xhat, s, plan.packs);
   if (plan.n_chunks > 0) {
     hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, plan.chunks,
                        plan.partials);
