@@ -179,6 +179,29 @@ int chap_best_shift_pass_ms(chap_problem *p, double *ms);
 int chap_tabu_run(chap_problem *p, int64_t iters, int32_t tenure, uint64_t seed, const double *x0,
                   chap_run **out, void *hip_stream);
 
+/*
+ * chap_batch_run - many independent tabu walks advanced together (section
+ * 3.1 "Parallel Tabu Search Instances": each walk has its own point, tabu
+ * list and weights).
+ *
+ * Walk w runs on problem probs[walk_prob[w]] from the start point of seed
+ * walk_seed[w] (the rule of chap_tabu_run). All walks run `iters`
+ * iterations with the same tenure. Every iteration is one launch per kernel
+ * over all walks (the blocks of each launch are divided among the walks by
+ * their work), several iterations are recorded in one HIP graph. Walk w's
+ * result is identical to chap_tabu_run(probs[walk_prob[w]], iters, tenure,
+ * walk_seed[w], NULL, ...).
+ *   probs      nprob problem handles (same device); a problem may serve any
+ *              number of walks.
+ *   walk_prob  nwalks indices into probs.    walk_seed  nwalks seeds.
+ *   out        host array of nwalks run handles, filled on success (each
+ *              released with chap_run_destroy).
+ * Synchronous. Errors: CHAP_EINVAL, CHAP_ENOMEM, CHAP_EHIP.
+ */
+int chap_batch_run(chap_problem *const *probs, int32_t nprob, const int32_t *walk_prob,
+                   const uint64_t *walk_seed, int32_t nwalks, int64_t iters, int32_t tenure,
+                   chap_run **out, void *hip_stream);
+
 /* Trace of a run: *records points into the run (valid until
  * chap_run_destroy), *count = iters. */
 int chap_run_trace(const chap_run *r, const chap_trace_record **records, int64_t *count);
@@ -192,13 +215,70 @@ int chap_run_trace(const chap_run *r, const chap_trace_record **records, int64_t
 int chap_run_state(const chap_run *r, double *x, double *resid, float *w, double *best_obj,
                    double *best_x, double *cutoff_rhs);
 
-/* GPU time of the run's iteration graphs in milliseconds (HIP events). */
+/* GPU time of the run's iteration graphs in milliseconds (HIP events); for
+ * a batch, the time of the whole batch. */
 double chap_run_elapsed_ms(const chap_run *r);
 
 void chap_run_destroy(chap_run *r);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *chap_last_error(void);
+
+/*
+ * Candidate-proposal network.
+ *
+ * The paper scores every variable exactly in every iteration (section 3.1,
+ * "Scoring Functions"). The learned proposal is an addition beside that
+ * method: a small network ranks the variables, only its top-ranked ones get
+ * the exact FP64 best shift of Eq. 1 / Algorithm 1, and a periodic full pass
+ * is both the fallback and the judge, so every move taken is still an exact
+ * best shift. The network maps 16 inputs to one output through two hidden
+ * layers of 64 ReLU units:
+ *     y = W3 relu(W2 relu(W1 x + b1) + b2) + b3.
+ * Products take bfloat16 operands (inputs, weights and hidden activations
+ * rounded to nearest even) and accumulate in FP32 on the matrix cores;
+ * parameters and biases are FP32. Training minimises the mean squared error
+ * with Adam (beta1 0.9, beta2 0.999, epsilon 1e-8) on FP32 master parameters,
+ * whose bfloat16 copy the forward pass uses.
+ *
+ * Parameters, flat FP32 order (CHAP_MODEL_NPARAM values): W1[64][16] (row =
+ * hidden unit), b1[64], W2[64][64], b2[64], W3[64], b3.
+ * Feature rows: 16 bfloat16 values per sample (uint16_t bit patterns), row
+ * major, in the input order listed under chap_learned_run.
+ */
+#define CHAP_MODEL_NPARAM 5313
+
+typedef struct chap_model chap_model;
+
+/* New network on the current device with He-uniform weights: weight p of a
+ * layer with fan-in k is (2u - 1) sqrt(6/k), u = (splitmix64(seed, p) >> 11)
+ * 2^-53 (SplitMix64 as for start points), rounded to FP32; biases 0. */
+int chap_model_create(chap_model **out, uint64_t seed);
+void chap_model_destroy(chap_model *m);
+
+/* Copies the FP32 parameters to / from a host array of CHAP_MODEL_NPARAM
+ * floats. set rejects non-finite values (CHAP_EINVAL) and resets Adam. Both
+ * synchronise the device. */
+int chap_model_get_params(const chap_model *m, float *params);
+int chap_model_set_params(chap_model *m, const float *params);
+
+/* Network outputs for n feature rows: d_feat (device, n x 16 bfloat16),
+ * d_out (device, n floats). Asynchronous on hip_stream. */
+int chap_model_forward(chap_model *m, const uint16_t *d_feat, int64_t n, float *d_out,
+                       void *hip_stream);
+
+/* Gradient of L = (1/n) sum_i (y_i - target_i)^2 with respect to the flat
+ * parameters: d_feat (device, n x 16), d_target (device, n floats), d_grad
+ * (device, CHAP_MODEL_NPARAM floats). Sums are taken in a fixed order, so
+ * the result is reproducible bit for bit. Asynchronous on hip_stream. */
+int chap_model_grad(chap_model *m, const uint16_t *d_feat, const float *d_target, int64_t n,
+                    float *d_grad, void *hip_stream);
+
+/* `steps` Adam steps with learning rate lr on minibatches of `batch` pairs
+ * drawn from the npairs rows of (d_feat, d_target): sample i of step k is row
+ * splitmix64(seed, k * batch + i) mod npairs. Asynchronous on hip_stream. */
+int chap_model_train(chap_model *m, const uint16_t *d_feat, const float *d_target, int64_t npairs,
+                     int32_t steps, int32_t batch, float lr, uint64_t seed, void *hip_stream);
 
 #ifdef __cplusplus
 }

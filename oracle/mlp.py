@@ -175,7 +175,7 @@ def backward_bound(flat, X, t):
     B = y.shape[0]
     Bt = B + 2
     g3 = 2.0 * (y - t) / B
-    eg3 = 2.0 * ey / B + 2 * U32 * np.abs(g3)
+    eg3 = 2.0 * ey / B + 4 * U32 * np.abs(g3)
     aW2, aW3 = np.abs(c["W2"]), np.abs(c["W3"])
     ah1, ah2, aX = np.abs(c["h1"]), np.abs(c["h2"]), np.abs(c["Xb"])
     dW3 = eg3 @ (ah2 + b["r2"]) + np.abs(g3) @ b["r2"] + Bt * U32 * (np.abs(g3) @ ah2)

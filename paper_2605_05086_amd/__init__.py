@@ -67,6 +67,8 @@ def load_library():
     lib.chap_best_shift_pass_ms.restype = ctypes.c_int
     lib.chap_tabu_run.argtypes = [P, i64, i32, u64, P, ctypes.POINTER(P), P]
     lib.chap_tabu_run.restype = ctypes.c_int
+    lib.chap_batch_run.argtypes = [P, i32, P, P, i32, i64, i32, P, P]
+    lib.chap_batch_run.restype = ctypes.c_int
     lib.chap_run_trace.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(i64)]
     lib.chap_run_trace.restype = ctypes.c_int
     lib.chap_run_state.argtypes = [P, P, P, P, ctypes.POINTER(f64), P, ctypes.POINTER(f64)]
@@ -75,6 +77,20 @@ def load_library():
     lib.chap_run_elapsed_ms.restype = f64
     lib.chap_run_destroy.argtypes = [P]
     lib.chap_run_destroy.restype = None
+    lib.chap_model_create.argtypes = [ctypes.POINTER(P), u64]
+    lib.chap_model_create.restype = ctypes.c_int
+    lib.chap_model_destroy.argtypes = [P]
+    lib.chap_model_destroy.restype = None
+    lib.chap_model_get_params.argtypes = [P, P]
+    lib.chap_model_get_params.restype = ctypes.c_int
+    lib.chap_model_set_params.argtypes = [P, P]
+    lib.chap_model_set_params.restype = ctypes.c_int
+    lib.chap_model_forward.argtypes = [P, P, i64, P, P]
+    lib.chap_model_forward.restype = ctypes.c_int
+    lib.chap_model_grad.argtypes = [P, P, P, i64, P, P]
+    lib.chap_model_grad.restype = ctypes.c_int
+    lib.chap_model_train.argtypes = [P, P, P, i64, i32, i32, ctypes.c_float, u64, P]
+    lib.chap_model_train.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -221,3 +237,88 @@ class Problem:
         _check(load_library().chap_tabu_run(self._h, int(iters), int(tenure), int(seed), x0p, ctypes.byref(h),
                                             _stream_handle(stream)))
         return Run(h, self.n, self.mp)
+
+
+def batch_run(problems, walk_prob, walk_seed, iters: int, tenure: int, stream=None):
+    """chap_batch_run: walk w runs on problems[walk_prob[w]] with seed
+    walk_seed[w]; returns one Run per walk."""
+    lib = load_library()
+    nprob = len(problems)
+    handles = (ctypes.c_void_p * nprob)(*[p._h.value for p in problems])
+    wp = np.ascontiguousarray(walk_prob, dtype=np.int32)
+    ws = np.ascontiguousarray(walk_seed, dtype=np.uint64)
+    nw = wp.shape[0]
+    out = (ctypes.c_void_p * nw)()
+    _check(lib.chap_batch_run(ctypes.cast(handles, ctypes.c_void_p), nprob, _ptr(wp), _ptr(ws), nw, int(iters),
+                              int(tenure), ctypes.cast(out, ctypes.c_void_p), _stream_handle(stream)))
+    return [Run(ctypes.c_void_p(out[w]), problems[wp[w]].n, problems[wp[w]].mp) for w in range(nw)]
+
+
+MODEL_NPARAM = 5313
+
+
+def _dev_ptr(t, dtype, numel=None):
+    import torch
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+    if numel is not None:
+        assert t.numel() == numel, (t.numel(), numel)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Model:
+    """The candidate-proposal network (chap_model_*). Feature tensors are
+    (n, 16) int16 tensors holding bfloat16 bit patterns (or torch.bfloat16)."""
+
+    def __init__(self, seed: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.chap_model_create(ctypes.byref(h), int(seed)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load_library().chap_model_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def _feat(feat):
+        import torch
+        if feat.dtype == torch.bfloat16:
+            feat = feat.view(torch.int16)
+        assert feat.dim() == 2 and feat.shape[1] == 16
+        return _dev_ptr(feat, torch.int16)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MODEL_NPARAM, dtype=np.float32)
+        _check(load_library().chap_model_get_params(self._h, _ptr(out)))
+        return out
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (MODEL_NPARAM,)
+        _check(load_library().chap_model_set_params(self._h, _ptr(p)))
+
+    def forward(self, feat, out=None, stream=None):
+        import torch
+        n = feat.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=feat.device)
+        _check(load_library().chap_model_forward(self._h, self._feat(feat), n, _dev_ptr(out, torch.float32, n),
+                                                 _stream_handle(stream)))
+        return out
+
+    def grad(self, feat, target, out=None, stream=None):
+        import torch
+        n = feat.shape[0]
+        if out is None:
+            out = torch.empty(MODEL_NPARAM, dtype=torch.float32, device=feat.device)
+        _check(load_library().chap_model_grad(self._h, self._feat(feat), _dev_ptr(target, torch.float32, n), n,
+                                              _dev_ptr(out, torch.float32, MODEL_NPARAM), _stream_handle(stream)))
+        return out
+
+    def train(self, feat, target, steps: int, batch: int, lr: float, seed: int = 0, stream=None) -> None:
+        import torch
+        n = feat.shape[0]
+        _check(load_library().chap_model_train(self._h, self._feat(feat), _dev_ptr(target, torch.float32, n), n,
+                                               int(steps), int(batch), float(lr), int(seed), _stream_handle(stream)))

@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchap.so")
-SOURCES = ["api.hip", "kernels_pass.hip", "kernels_walk.hip"]
-HEADERS = [os.path.join(CSRC, "chap_internal.h"), os.path.join(INCLUDE, "chap.h")]
+SOURCES = ["api.hip", "api_model.hip", "kernels_pass.hip", "kernels_walk.hip", "kernels_mlp.hip"]
+HEADERS = [os.path.join(CSRC, "chap_internal.h"), os.path.join(CSRC, "mlp_core.h"), os.path.join(INCLUDE, "chap.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # IEEE FP64 everywhere (no contraction, no fast-math); packed FP32 ops off.

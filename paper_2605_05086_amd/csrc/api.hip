@@ -15,7 +15,7 @@
 
 using namespace chap;
 
-namespace {
+namespace chap {
 
 thread_local std::string g_error;
 
@@ -24,37 +24,7 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define CHAP_HIP(call)                                                                               \
-  do {                                                                                              \
-    hipError_t e_ = (call);                                                                         \
-    if (e_ != hipSuccess) return fail(CHAP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-// Device allocations owned by one object, freed together.
-struct DeviceArena {
-  std::vector<void*> ptrs;
-  ~DeviceArena() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-  template <typename T>
-  hipError_t alloc(T** out, size_t count) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
-    if (e != hipSuccess) return e;
-    ptrs.push_back(p);
-    *out = (T*)p;
-    return hipSuccess;
-  }
-  template <typename T>
-  hipError_t upload(T** out, const std::vector<T>& v) {
-    hipError_t e = alloc(out, v.size());
-    if (e != hipSuccess) return e;
-    if (!v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    return e;
-  }
-};
-
-}  // namespace
+}  // namespace chap
 
 struct chap_problem {
   int32_t n = 0, m = 0, mp = 0;
@@ -89,6 +59,7 @@ struct chap_problem {
   double* bs_xhat = nullptr;
   double* bs_s = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
+  BatchLaunch bs_launch;
   hipEvent_t pass_ev[2] = {nullptr, nullptr};
   bool pass_timed = false;
   ~chap_problem() {
@@ -109,27 +80,34 @@ struct chap_run {
 
 namespace {
 
-uint64_t splitmix64_output(uint64_t seed, uint64_t index) {
-  uint64_t z = seed + (index + 1) * 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
-
 __global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
 }
 
-struct WalkBuffers {
-  DeviceArena arena;
-  double *x = nullptr, *xhat = nullptr, *s = nullptr, *best_x = nullptr, *partial = nullptr, *argmax_partial = nullptr;
-  int32_t* tabu = nullptr;
-  RowState* rs = nullptr;
-  WalkState* st = nullptr;
-  chap_trace_record* trace = nullptr;
-  uint32_t* ticket = nullptr;
-};
+// Uploads per-walk contexts and the per-kernel block prefix tables.
+hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLaunch* L) {
+  L->nw = (int32_t)ctx.size();
+  WalkCtx* d;
+  hipError_t e = A.upload(&d, ctx);
+  if (e != hipSuccess) return e;
+  L->walks = d;
+  for (int k = 0; k < KS_COUNT; ++k) {
+    std::vector<int32_t> off(ctx.size() + 1, 0);
+    for (size_t w = 0; w < ctx.size(); ++w) off[w + 1] = off[w] + kernel_blocks(ctx[w], k);
+    int32_t* doff;
+    e = A.upload(&doff, off);
+    if (e != hipSuccess) return e;
+    L->off[k] = doff;
+    L->total[k] = off.back();
+  }
+  return hipSuccess;
+}
+
+int blocks_for_host(int64_t work, int cap) {
+  int64_t b = (work + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
 
 }  // namespace
 
@@ -556,7 +534,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.upload(&dt, tasks));
     L.chunks = dt;
     L.n_chunks = (int32_t)tasks.size();
-    CHAP_HIP(A.alloc(&L.partials, (size_t)ccols.back().first + ccols.back().nparts));
+    L.n_partials = ccols.back().first + ccols.back().nparts;
     ChunkCol* dc;
     CHAP_HIP(A.upload(&dc, ccols));
     L.chunk_cols = dc;
@@ -567,9 +545,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.upload(&d, longs));
     L.long_tasks = d;
     L.n_long = (int32_t)longs.size();
-    CHAP_HIP(A.alloc(&L.long_pos, (size_t)long_total));
-    CHAP_HIP(A.alloc(&L.long_delta, (size_t)long_total));
-    CHAP_HIP(A.alloc(&L.long_marker, (size_t)long_total));
+    L.long_scratch = long_total;
   }
   CHAP_HIP(A.alloc(&P->bs_x, (size_t)n));
   CHAP_HIP(A.alloc(&P->bs_xhat, (size_t)n));
@@ -579,6 +555,22 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(A.alloc(&P->bs_partial, 2 * 1024));
   CHAP_HIP(A.alloc(&P->bs_ticket, 1));
   CHAP_HIP(hipMemset(P->bs_ticket, 0, sizeof(uint32_t)));
+  {
+    // one-walk launch table of chap_best_shift over the problem's scratch
+    WalkCtx c{};
+    c.P = P->dev;
+    c.plan = P->plan;
+    c.x = P->bs_x;
+    c.xhat = P->bs_xhat;
+    c.s = P->bs_s;
+    c.rs = P->bs_rs;
+    c.st = P->bs_state;
+    CHAP_HIP(A.alloc(&c.partials, (size_t)P->plan.n_partials));
+    CHAP_HIP(A.alloc(&c.long_pos, (size_t)P->plan.long_scratch));
+    CHAP_HIP(A.alloc(&c.long_delta, (size_t)P->plan.long_scratch));
+    CHAP_HIP(A.alloc(&c.long_marker, (size_t)P->plan.long_scratch));
+    CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &P->bs_launch));
+  }
   CHAP_HIP(hipEventCreate(&P->pass_ev[0]));
   CHAP_HIP(hipEventCreate(&P->pass_ev[1]));
   CHAP_HIP(hipDeviceSynchronize());
@@ -600,8 +592,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
                              p->obj_integral, cut, d_w + p->mp, 0, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
-  if (p->n > 0)
-    CHAP_HIP(launch_best_shift_pass(p->dev, p->plan, p->bs_x, p->bs_rs, p->bs_state, p->bs_xhat, p->bs_s, s));
+  if (p->n > 0) CHAP_HIP(launch_pass(p->bs_launch, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
   CHAP_HIP(launch_scatter2(p->dev.perm, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
   p->pass_timed = true;
@@ -619,47 +610,83 @@ int chap_best_shift_pass_ms(chap_problem* p, double* ms) {
   return CHAP_OK;
 }
 
-int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed, const double* x0, chap_run** out,
-                  void* hip_stream) {
-  if (!p || !out) return fail(CHAP_EINVAL, "chap_tabu_run: null argument");
-  if (iters < 0 || tenure < 0 || iters + (int64_t)tenure >= (int64_t)INT32_MAX)
-    return fail(CHAP_EINVAL, "chap_tabu_run: iters and tenure must be >= 0 with iters + tenure < 2^31");
-  const int32_t n = p->n, m = p->m;
-  std::vector<double> xs(n);
-  if (x0) {
-    for (int32_t j = 0; j < n; ++j) {
-      if (!std::isfinite(x0[j])) return fail(CHAP_EINVAL, "chap_tabu_run: non-finite start value at " + std::to_string(j));
-      xs[j] = x0[j];
-    }
-  } else {
-    for (int32_t j = 0; j < n; ++j) {
-      const double l = p->lb[j], u = p->ub[j];
-      if (seed != 0 && p->is_int[j] && std::isfinite(l) && std::isfinite(u)) {
-        const uint64_t h = splitmix64_output(seed, (uint64_t)j);
-        const uint64_t width = (uint64_t)(u - l) + 1;
-        xs[j] = l + (double)(h % width);
-      } else {
-        double v = 0.0;
-        if (v < l) v = l;
-        if (v > u) v = u;
-        xs[j] = v;
-      }
+}  // extern "C"
+
+namespace {
+
+// One walk of a run: its problem, start point (original order) and seed.
+struct WalkSpec {
+  chap_problem* p;
+  uint64_t seed;
+  const double* x0;
+};
+
+void start_point(const chap_problem* p, uint64_t seed, double* x) {
+  for (int32_t j = 0; j < p->n; ++j) {
+    const double l = p->lb[j], u = p->ub[j];
+    if (seed != 0 && p->is_int[j] && std::isfinite(l) && std::isfinite(u)) {
+      const uint64_t h = splitmix64(seed, (uint64_t)j);
+      const uint64_t width = (uint64_t)(u - l) + 1;
+      x[j] = l + (double)(h % width);
+    } else {
+      double v = 0.0;
+      if (v < l) v = l;
+      if (v > u) v = u;
+      x[j] = v;
     }
   }
-  WalkBuffers B;
-  DeviceArena& A = B.arena;
-  CHAP_HIP(A.alloc(&B.x, n));
-  CHAP_HIP(A.alloc(&B.xhat, n));
-  CHAP_HIP(A.alloc(&B.s, n));
-  CHAP_HIP(A.alloc(&B.best_x, n));
-  CHAP_HIP(A.alloc(&B.tabu, n));
-  CHAP_HIP(A.alloc(&B.rs, m));
-  CHAP_HIP(A.alloc(&B.st, 1));
-  CHAP_HIP(A.alloc(&B.trace, (size_t)std::max<int64_t>(iters, 1)));
-  CHAP_HIP(A.alloc(&B.partial, 2 * 1024));
-  CHAP_HIP(A.alloc(&B.argmax_partial, (size_t)kArgmaxRecord * kArgmaxBlocks));
-  CHAP_HIP(A.alloc(&B.ticket, 1));
-  hipStream_t user = (hipStream_t)hip_stream;
+}
+
+// Runs every walk for `iters` iterations: per-walk buffers, set-up kernels,
+// then a HIP graph of `graph_iters` iterations in which each kernel is one
+// launch over all walks. Results are copied back into chap_run objects.
+int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure, hipStream_t user,
+              std::vector<std::unique_ptr<chap_run>>& out) {
+  if (iters < 0 || tenure < 0 || iters + (int64_t)tenure >= (int64_t)INT32_MAX)
+    return fail(CHAP_EINVAL, "iters and tenure must be >= 0 with iters + tenure < 2^31");
+  const size_t nw = specs.size();
+  DeviceArena A;
+  std::vector<WalkCtx> ctx(nw);
+  std::vector<std::vector<double>> xq(nw);
+  for (size_t w = 0; w < nw; ++w) {
+    const chap_problem* p = specs[w].p;
+    const int32_t n = p->n;
+    std::vector<double> xs(n);
+    if (specs[w].x0) {
+      for (int32_t j = 0; j < n; ++j) {
+        if (!std::isfinite(specs[w].x0[j]))
+          return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
+        xs[j] = specs[w].x0[j];
+      }
+    } else {
+      start_point(p, specs[w].seed, xs.data());
+    }
+    xq[w].resize(n);
+    for (int32_t q = 0; q < n; ++q) xq[w][q] = xs[p->perm[q]];
+    WalkCtx& c = ctx[w];
+    c.P = p->dev;
+    c.plan = p->plan;
+    c.argmax_blocks = blocks_for_host(n, kArgmaxBlocks);
+    c.apply_blocks = blocks_for_host(std::max(p->m, p->max_col_deg), 256);
+    c.recompute = p->exact_incremental ? 0 : 1;
+    CHAP_HIP(A.alloc(&c.x, (size_t)n));
+    CHAP_HIP(A.alloc(&c.xhat, (size_t)n));
+    CHAP_HIP(A.alloc(&c.s, (size_t)n));
+    CHAP_HIP(A.alloc(&c.best_x, (size_t)n));
+    CHAP_HIP(A.alloc(&c.tabu, (size_t)n));
+    CHAP_HIP(A.alloc(&c.rs, (size_t)p->m));
+    CHAP_HIP(A.alloc(&c.st, 1));
+    CHAP_HIP(A.alloc(&c.trace, (size_t)std::max<int64_t>(iters, 1)));
+    CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * c.argmax_blocks));
+    CHAP_HIP(A.alloc(&c.partials, (size_t)p->plan.n_partials));
+    CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
+    CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));
+    CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
+  }
+  double* partial;
+  uint32_t* ticket;
+  CHAP_HIP(A.alloc(&partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&ticket, 1));
   hipStream_t s;
   CHAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct StreamGuard {
@@ -680,32 +707,34 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
   } eg{e_user, e0, e1};
   CHAP_HIP(hipEventRecord(e_user, user));
   CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
-  CHAP_HIP(hipMemsetAsync(B.ticket, 0, sizeof(uint32_t), s));
-  CHAP_HIP(hipMemsetAsync(B.st, 0, sizeof(WalkState), s));
-  std::vector<double> xq(n);
-  for (int32_t q = 0; q < n; ++q) xq[q] = xs[p->perm[q]];
-  if (n > 0) {
-    CHAP_HIP(hipMemcpyAsync(B.x, xq.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, B.tabu, -1, (int64_t)n);
-    CHAP_HIP(hipGetLastError());
+  CHAP_HIP(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
+  for (size_t w = 0; w < nw; ++w) {
+    const chap_problem* p = specs[w].p;
+    const WalkCtx& c = ctx[w];
+    const int32_t n = p->n;
+    CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
+    if (n > 0) {
+      CHAP_HIP(hipMemcpyAsync(c.x, xq[w].data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)n);
+      CHAP_HIP(hipGetLastError());
+    }
+    CHAP_HIP(launch_residual(p->dev, c.x, c.rs, s));
+    CHAP_HIP(launch_set_weights_unit(p->d_pair, c.rs, p->m, s));
+    CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
+                               nullptr, 1, s));
+    CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
   }
-  CHAP_HIP(launch_residual(p->dev, B.x, B.rs, s));
-  CHAP_HIP(launch_set_weights_unit(p->d_pair, B.rs, m, s));
-  CHAP_HIP(launch_state_init(p->dev, B.x, B.rs, B.st, B.partial, B.ticket, iters, tenure, p->obj_integral, HUGE_VAL,
-                             nullptr, 1, s));
-  CHAP_HIP(launch_copy_best(B.x, B.best_x, B.st, n, s));
-  const int apply_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (std::max(m, p->max_col_deg) + 255) / 256));
+  BatchLaunch L;
+  CHAP_HIP(build_launch(A, ctx, &L));
   double ms_total = 0.0;
   if (iters > 0) {
-    const int64_t K = std::min<int64_t>(iters, p->opt.graph_iters);
+    const int64_t K = std::min<int64_t>(iters, specs[0].p->opt.graph_iters);
     hipGraph_t graph;
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
     for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
-      if (n > 0) cap_err = launch_best_shift_pass(p->dev, p->plan, B.x, B.rs, B.st, B.xhat, B.s, s);
-      if (cap_err == hipSuccess)
-        cap_err = launch_walk_step(p->dev, B.x, B.xhat, B.s, B.rs, B.tabu, B.st, B.trace, B.best_x, B.argmax_partial,
-                                   apply_blocks, p->exact_incremental ? 0 : 1, s);
+      cap_err = launch_pass(L, s);
+      if (cap_err == hipSuccess) cap_err = launch_walk_step(L, s);
     }
     hipError_t end_err = hipStreamEndCapture(s, &graph);
     if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));
@@ -720,8 +749,8 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
     hipError_t le = hipEventRecord(e0, s);
     for (int64_t q = 0; q < launches && le == hipSuccess; ++q) le = hipGraphLaunch(exec, s);
     if (le == hipSuccess) le = hipEventRecord(e1, s);
-    // an incumbent found by the last iteration is copied here
-    if (le == hipSuccess) le = launch_copy_best(B.x, B.best_x, B.st, n, s);
+    // an incumbent found by a walk's last iteration is copied here
+    if (le == hipSuccess) le = launch_copy_best_batch(L, s);
     if (le == hipSuccess) le = hipStreamSynchronize(s);
     float ms = 0.0f;
     if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
@@ -731,43 +760,84 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
     ms_total = ms;
   }
   CHAP_HIP(hipStreamSynchronize(s));
-  std::unique_ptr<chap_run> R(new chap_run());
-  R->elapsed_ms = ms_total;
-  R->trace.resize((size_t)iters);
-  if (iters > 0)
-    CHAP_HIP(hipMemcpy(R->trace.data(), B.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
-  R->x.resize(n);
-  std::vector<double> bx(n), xin(n), bxin(n);
-  if (n > 0) {
-    CHAP_HIP(hipMemcpy(xin.data(), B.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
-    CHAP_HIP(hipMemcpy(bxin.data(), B.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
-  }
-  for (int32_t q = 0; q < n; ++q) {
-    R->x[p->perm[q]] = xin[q];
-    bx[p->perm[q]] = bxin[q];
-  }
-  std::vector<RowState> rs(m);
-  if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), B.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
-  WalkState st;
-  CHAP_HIP(hipMemcpy(&st, B.st, sizeof(WalkState), hipMemcpyDeviceToHost));
-  R->resid.assign((size_t)p->mp + 1, 0.0);
-  R->w.assign((size_t)p->mp + 1, 0.0f);
-  for (int32_t i = 0; i < m; ++i) {
-    const int32_t k = p->nidx[i];
-    R->resid[k] = rs[i].r;
-    R->w[k] = rs[i].w0;
-    if (p->pair[i]) {
-      R->resid[k + 1] = -rs[i].r;
-      R->w[k + 1] = rs[i].w1;
+  out.clear();
+  for (size_t w = 0; w < nw; ++w) {
+    const chap_problem* p = specs[w].p;
+    const WalkCtx& c = ctx[w];
+    const int32_t n = p->n, m = p->m;
+    std::unique_ptr<chap_run> R(new chap_run());
+    R->elapsed_ms = ms_total;
+    R->trace.resize((size_t)iters);
+    if (iters > 0)
+      CHAP_HIP(hipMemcpy(R->trace.data(), c.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
+    std::vector<double> xin(n), bxin(n);
+    if (n > 0) {
+      CHAP_HIP(hipMemcpy(xin.data(), c.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+      CHAP_HIP(hipMemcpy(bxin.data(), c.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
     }
+    R->x.resize(n);
+    std::vector<double> bx(n);
+    for (int32_t q = 0; q < n; ++q) {
+      R->x[p->perm[q]] = xin[q];
+      bx[p->perm[q]] = bxin[q];
+    }
+    std::vector<RowState> rs(m);
+    if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), c.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
+    WalkState st;
+    CHAP_HIP(hipMemcpy(&st, c.st, sizeof(WalkState), hipMemcpyDeviceToHost));
+    R->resid.assign((size_t)p->mp + 1, 0.0);
+    R->w.assign((size_t)p->mp + 1, 0.0f);
+    for (int32_t i = 0; i < m; ++i) {
+      const int32_t k = p->nidx[i];
+      R->resid[k] = rs[i].r;
+      R->w[k] = rs[i].w0;
+      if (p->pair[i]) {
+        R->resid[k + 1] = -rs[i].r;
+        R->w[k + 1] = rs[i].w1;
+      }
+    }
+    R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
+    R->w[p->mp] = st.wc;
+    R->has_best = st.has_best != 0;
+    R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
+    R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
+    if (R->has_best) R->best_x = bx;
+    out.push_back(std::move(R));
   }
-  R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
-  R->w[p->mp] = st.wc;
-  R->has_best = st.has_best != 0;
-  R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
-  R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
-  if (R->has_best) R->best_x = bx;
-  *out = R.release();
+  return CHAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed, const double* x0, chap_run** out,
+                  void* hip_stream) {
+  if (!p || !out) return fail(CHAP_EINVAL, "chap_tabu_run: null argument");
+  std::vector<std::unique_ptr<chap_run>> runs;
+  const int rc = run_walks({WalkSpec{p, seed, x0}}, iters, tenure, (hipStream_t)hip_stream, runs);
+  if (rc != CHAP_OK) return rc;
+  *out = runs[0].release();
+  return CHAP_OK;
+}
+
+int chap_batch_run(chap_problem* const* probs, int32_t nprob, const int32_t* walk_prob, const uint64_t* walk_seed,
+                   int32_t nwalks, int64_t iters, int32_t tenure, chap_run** out, void* hip_stream) {
+  if (!probs || !walk_prob || !walk_seed || !out || nprob <= 0 || nwalks <= 0)
+    return fail(CHAP_EINVAL, "chap_batch_run: null argument or empty batch");
+  std::vector<WalkSpec> specs;
+  for (int32_t w = 0; w < nwalks; ++w) {
+    if (walk_prob[w] < 0 || walk_prob[w] >= nprob || !probs[walk_prob[w]])
+      return fail(CHAP_EINVAL, "chap_batch_run: walk " + std::to_string(w) + " names no problem");
+    specs.push_back(WalkSpec{probs[walk_prob[w]], walk_seed[w], nullptr});
+  }
+  const int dev = specs[0].p->device;
+  for (const WalkSpec& ws : specs)
+    if (ws.p->device != dev) return fail(CHAP_EINVAL, "chap_batch_run: problems on different devices");
+  std::vector<std::unique_ptr<chap_run>> runs;
+  const int rc = run_walks(specs, iters, tenure, (hipStream_t)hip_stream, runs);
+  if (rc != CHAP_OK) return rc;
+  for (int32_t w = 0; w < nwalks; ++w) out[w] = runs[w].release();
   return CHAP_OK;
 }
 

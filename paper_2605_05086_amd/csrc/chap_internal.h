@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -10,6 +11,51 @@
 #include "chap.h"
 
 namespace chap {
+
+// (index+1)-th output of SplitMix64 started at state `seed` (Steele, Lea and
+// Flood, "Fast splittable pseudorandom number generators", 2014).
+__host__ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string& msg);
+
+#define CHAP_HIP(call)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return fail(CHAP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device allocations owned by one object, freed together.
+struct DeviceArena {
+  std::vector<void*> ptrs;
+  DeviceArena() = default;
+  DeviceArena(const DeviceArena&) = delete;
+  DeviceArena& operator=(const DeviceArena&) = delete;
+  ~DeviceArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return hipSuccess;
+  }
+  template <typename T>
+  hipError_t upload(T** out, const std::vector<T>& v) {
+    hipError_t e = alloc(out, v.size());
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+};
 
 // Column classes, decided once at problem creation.
 enum : uint8_t {
@@ -127,8 +173,9 @@ struct LongTask {
   int64_t offset;    // into the long-sort scratch arrays
 };
 
-// Work of one best-shift pass. Columns live in an internal order in which
-// each kernel's columns form one contiguous range of internal indices.
+// Work of one best-shift pass over one instance. Columns live in an internal
+// order in which each kernel's columns form one contiguous range of internal
+// indices.
 struct PassPlan {
   // short columns: binaries [short_seg[0], short_seg[1]), then non-binary
   // columns with D stored entries [short_seg[1+D], short_seg[2+D])
@@ -137,26 +184,77 @@ struct PassPlan {
   // packs of whole narrow columns
   const PackTask* packs = nullptr;
   int32_t n_packs = 0;
+  // long narrow columns cut into chunks, and their partial records
   const ChunkTask* chunks = nullptr;
   int32_t n_chunks = 0;
-  ChunkPartial* partials = nullptr;
   const ChunkCol* chunk_cols = nullptr;
   int32_t n_chunk_cols = 0;
+  int32_t n_partials = 0;
   int32_t sort_begin[kSortCaps + 1] = {0};
   const LongTask* long_tasks = nullptr;
   int32_t n_long = 0;
-  double* long_pos = nullptr;
-  double* long_delta = nullptr;
-  int32_t* long_marker = nullptr;
+  int64_t long_scratch = 0;  // entries of the long-sort scratch arrays
 };
 
+// Everything the kernels of one walk need: its instance, the instance's pass
+// plan, and the walk's own buffers. One record per walk in device memory;
+// a single best-shift pass or a single walk is a batch of one.
+struct WalkCtx {
+  DevProblem P;
+  PassPlan plan;
+  double* x;
+  double* xhat;
+  double* s;
+  double* best_x;
+  int32_t* tabu;
+  RowState* rs;
+  WalkState* st;
+  chap_trace_record* trace;
+  double* argmax_partial;
+  ChunkPartial* partials;
+  double* long_pos;
+  double* long_delta;
+  int32_t* long_marker;
+  int32_t argmax_blocks;
+  int32_t apply_blocks;
+  int32_t recompute;
+};
+
+// Kernels of one iteration; each has its own per-walk block counts.
+enum KernelSlot {
+  KS_SHORT = 0,
+  KS_FLIP,
+  KS_PACK,
+  KS_CHUNK,
+  KS_COMBINE,
+  KS_SORT0,
+  KS_LONG = KS_SORT0 + kSortCaps,
+  KS_ARGMAX,
+  KS_SELECT,
+  KS_APPLY,
+  KS_FINISH,
+  KS_COUNT
+};
+
+// Launch table of a batch of walks: for every kernel the prefix sums of the
+// per-walk block counts (device arrays of nw + 1 entries) and their total.
+// Block b of a launch belongs to the walk w with off[w] <= b < off[w + 1].
+struct BatchLaunch {
+  int32_t nw = 0;
+  const WalkCtx* walks = nullptr;
+  const int32_t* off[KS_COUNT] = {};
+  int32_t total[KS_COUNT] = {};
+};
+
+// Blocks kernel `slot` needs for one walk.
+int32_t kernel_blocks(const WalkCtx& c, int slot);
+
 // ---- launchers (kernels_pass.hip) -----------------------------------------
-// One exact best-shift pass over all columns: xhat, s per variable.
-hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, const double* x,
-                                  const RowState* rs, const WalkState* st, double* xhat, double* s,
-                                  hipStream_t stream);
+// One exact best-shift pass over all columns of every walk of the batch.
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream);
 
 // ---- launchers (kernels_walk.hip) -----------------------------------------
+// Single-walk set-up kernels.
 hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream);
 hipError_t launch_set_weights_unit(const uint8_t* pair, RowState* rs, int32_t ms, hipStream_t stream);
 hipError_t launch_scatter_weights(const int32_t* nidx, const uint8_t* pair, const float* w_norm, RowState* rs,
@@ -167,15 +265,45 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
                              double* partial, uint32_t* ticket, int64_t iters, int32_t tenure,
                              int32_t obj_integral, double cutoff_rhs, const float* cutoff_w,
                              int check_incumbent, hipStream_t stream);
-hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, const double* s, RowState* rs,
-                            int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
-                            double* argmax_partial, int32_t apply_blocks, int32_t recompute,
-                            hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
 // dst[q] = src[perm[q]] (original order -> internal order)
 hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream);
 // da[perm[q]] = a[q], db[perm[q]] = b[q] (internal order -> original order)
 hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
                            hipStream_t stream);
+// Move selection, application and iteration end for every walk of the batch.
+hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream);
+// Final copy of an incumbent found by a walk's last iteration.
+hipError_t launch_copy_best_batch(const BatchLaunch& L, hipStream_t stream);
+
+// ---- proposal network (kernels_mlp.hip) -----------------------------------
+constexpr int kNParamPad = 5376;   // row stride of gradient partials (>= 5313 parameters)
+constexpr int kGradBlocks = 64;    // most workgroups of one gradient launch
+constexpr double kAdamBeta1 = 0.9;
+constexpr double kAdamBeta2 = 0.999;
+constexpr float kAdamEps = 1e-8f;
+
+// Device state of one network: FP32 parameters (flat order W1, b1, W2, b2,
+// W3, b3), their bfloat16 copy, Adam moments and step, gradient buffers.
+struct ModelDev {
+  float* w = nullptr;
+  uint16_t* wb = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  double* adam = nullptr;  // beta1^t, beta2^t, t
+  float* grad = nullptr;
+  float* partials = nullptr;  // kGradBlocks x kNParamPad
+};
+
+hipError_t launch_mlp_forward(const ModelDev& M, const uint16_t* feat, int64_t n, float* out, hipStream_t s);
+// Gradient partials of the mean squared error over nb samples of (feat,
+// target) with `rows` rows: sample i is row i, or with `sample` row
+// splitmix64(seed, base + i) mod rows.
+hipError_t launch_mlp_grad(const ModelDev& M, const uint16_t* feat, const float* target, int64_t rows, int64_t nb,
+                           int sample, uint64_t seed, uint64_t base, hipStream_t s);
+// Reduces the partials of the last gradient launch over nb samples into
+// M.grad; with `update`, one Adam step with learning rate lr.
+hipError_t launch_mlp_reduce(const ModelDev& M, int64_t nb, int update, float lr, hipStream_t s);
+hipError_t launch_mlp_bf16_copy(const ModelDev& M, hipStream_t s);
 
 }  // namespace chap

@@ -142,6 +142,22 @@ __device__ __forceinline__ void write_result(double* xhat, double* sc, int j, bo
   }
 }
 
+// Walk of this block and the block's index inside that walk: the largest w
+// with off[w] <= blockIdx.x (off is the prefix of per-walk block counts).
+__device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int nw, int& local) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nw - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  local = b - off[lo];
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
 // k_short: one lane per column (at most 8 normalised entries).
 // ---------------------------------------------------------------------------
@@ -260,34 +276,32 @@ __device__ __forceinline__ void short_general(const DevProblem& P, const double*
 // Short columns occupy the internal range [seg[0], seg[10]): binaries in
 // [seg[0], seg[1]), then non-binary columns with D stored entries in
 // [seg[1 + D], seg[2 + D]) for D = 0..8.
-struct ShortSegs {
-  int32_t seg[kShortMax + 3];
-};
-
-__global__ __launch_bounds__(256) void k_short(DevProblem P, const double* __restrict__ x,
-                                               const RowState* __restrict__ rs, const WalkState* __restrict__ st,
-                                               double* __restrict__ xhat, double* __restrict__ sc, ShortSegs S) {
-  if (st->k >= st->iters) return;
-  const int q = S.seg[0] + blockIdx.x * 256 + threadIdx.x;
-  if (q >= S.seg[kShortMax + 2]) return;
-  if (q < S.seg[1]) {
-    flip_column(P, x, rs, st, xhat, sc, q);
+__global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                               int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  const int32_t* seg = C.plan.short_seg;
+  const int q = seg[0] + lb * 256 + threadIdx.x;
+  if (q >= seg[kShortMax + 2]) return;
+  if (q < seg[1]) {
+    flip_column(C.P, C.x, C.rs, C.st, C.xhat, C.s, q);
     return;
   }
   int D = 0;
 #pragma unroll
   for (int k = 1; k <= kShortMax; ++k)
-    if (q >= S.seg[1 + k]) D = k;
+    if (q >= seg[1 + k]) D = k;
   switch (D) {
-    case 0: short_general<0>(P, x, rs, st, xhat, sc, q); break;
-    case 1: short_general<1>(P, x, rs, st, xhat, sc, q); break;
-    case 2: short_general<2>(P, x, rs, st, xhat, sc, q); break;
-    case 3: short_general<3>(P, x, rs, st, xhat, sc, q); break;
-    case 4: short_general<4>(P, x, rs, st, xhat, sc, q); break;
-    case 5: short_general<5>(P, x, rs, st, xhat, sc, q); break;
-    case 6: short_general<6>(P, x, rs, st, xhat, sc, q); break;
-    case 7: short_general<7>(P, x, rs, st, xhat, sc, q); break;
-    default: short_general<8>(P, x, rs, st, xhat, sc, q); break;
+    case 0: short_general<0>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 1: short_general<1>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 2: short_general<2>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 3: short_general<3>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 4: short_general<4>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 5: short_general<5>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 6: short_general<6>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 7: short_general<7>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    default: short_general<8>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
   }
 }
 
@@ -295,14 +309,20 @@ __global__ __launch_bounds__(256) void k_short(DevProblem P, const double* __res
 // k_flip_wave: one wavefront per longer binary column.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_flip_wave(DevProblem P, const double* __restrict__ x,
-                                                   const RowState* __restrict__ rs,
-                                                   const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                   double* __restrict__ sc, int32_t q0, int32_t q1) {
+__global__ __launch_bounds__(256) void k_flip_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                                   int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const RowState* rs = C.rs;
+  const WalkState* st = C.st;
+  double* xhat = C.xhat;
+  double* sc = C.s;
   if (st->k >= st->iters) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int q = q0 + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= q1) return;
+  const int q = C.plan.flip_begin + lb * 4 + (threadIdx.x >> 6);
+  if (q >= C.plan.flip_end) return;
   const double eps = P.eps;
   const double xb = x[q];
   const double xn = 1.0 - xb;
@@ -377,17 +397,23 @@ __device__ __forceinline__ void narrow_finish(double binv, double beta, double a
 // entry finds its column by binary search over the column starts and adds
 // into that column's 64 LDS bins, beta, alpha and candidate mask. Each
 // wavefront then scans and reduces a quarter of the pack's columns.
-__global__ __launch_bounds__(256) void k_narrow_pack(DevProblem P, const double* __restrict__ x,
-                                                     const RowState* __restrict__ rs,
-                                                     const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                     double* __restrict__ sc, const PackTask* __restrict__ packs) {
+__global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__ walks,
+                                                     const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const RowState* rs = C.rs;
+  const WalkState* st = C.st;
+  double* xhat = C.xhat;
+  double* sc = C.s;
   if (st->k >= st->iters) return;
   __shared__ double bins[kPackCols][kNarrowBins];
   __shared__ double sbeta[kPackCols], salpha[kPackCols], sxb[kPackCols], sl[kPackCols], su[kPackCols];
   __shared__ unsigned long long scand[kPackCols];
   __shared__ int sstart[kPackCols + 1];
   const int tid = threadIdx.x;
-  const PackTask T = packs[blockIdx.x];
+  const PackTask T = C.plan.packs[lb];
   const int nc = T.q_end - T.q_begin;
   if (tid < nc) {
     const int q = T.q_begin + tid;
@@ -454,11 +480,15 @@ __global__ __launch_bounds__(256) void k_narrow_pack(DevProblem P, const double*
 // candidate mask of the chunk go to the chunk's partial record. Chunks are
 // cut along row ranges and ordered so that consecutive workgroups (placed on
 // consecutive XCDs) gather rows from one range each.
-__global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double* __restrict__ x,
-                                                      const RowState* __restrict__ rs,
-                                                      const WalkState* __restrict__ st,
-                                                      const ChunkTask* __restrict__ tasks,
-                                                      ChunkPartial* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict__ walks,
+                                                      const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const RowState* rs = C.rs;
+  const WalkState* st = C.st;
+  ChunkPartial* partials = C.partials;
   if (st->k >= st->iters) return;
   __shared__ double bins[kNarrowBins];
   __shared__ double red_b[4], red_a[4];
@@ -466,7 +496,7 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid >> 6;
-  const ChunkTask T = tasks[blockIdx.x];
+  const ChunkTask T = C.plan.chunks[lb];
   if (tid < kNarrowBins) bins[tid] = 0.0;
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
@@ -524,13 +554,21 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(DevProblem P, const double
 
 // One wavefront per long narrow column: combines its chunks' partials in
 // slot order (deterministic), then scan and argmax over the bins.
-__global__ __launch_bounds__(256) void k_narrow_combine(DevProblem P, const double* __restrict__ x,
-                                                        const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                        double* __restrict__ sc, const ChunkCol* __restrict__ cols,
-                                                        int32_t count, const ChunkPartial* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restrict__ walks,
+                                                        const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& W0 = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = W0.P;
+  const double* x = W0.x;
+  const WalkState* st = W0.st;
+  double* xhat = W0.xhat;
+  double* sc = W0.s;
+  const ChunkCol* cols = W0.plan.chunk_cols;
+  const int32_t count = W0.plan.n_chunk_cols;
+  const ChunkPartial* partials = W0.partials;
   if (st->k >= st->iters) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int idx = lb * 4 + (threadIdx.x >> 6);
   if (idx >= count) return;
   const ChunkCol C = cols[idx];
   const int q = C.col;
@@ -696,10 +734,19 @@ __device__ __forceinline__ void scan_argmax(PosT pos, MarkT mk, DelT dl, int cap
 }
 
 template <int CAP>
-__global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* __restrict__ x,
-                                                    const RowState* __restrict__ rs,
-                                                    const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                    double* __restrict__ sc, int32_t q0) {
+__global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                                    int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const RowState* rs = C.rs;
+  const WalkState* st = C.st;
+  double* xhat = C.xhat;
+  double* sc = C.s;
+  int c = 0;
+  while (c < kSortCaps - 1 && kSortCap[c] != CAP) ++c;
+  const int32_t q0 = C.plan.sort_begin[c];
   if (st->k >= st->iters) return;
   __shared__ double spos[CAP];
   __shared__ double sdel[CAP];
@@ -707,7 +754,7 @@ __global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* 
   __shared__ int scount;
   __shared__ double red[8];
   __shared__ int redk[8];
-  const int j = q0 + blockIdx.x;
+  const int j = q0 + lb;
   const double xb = x[j];
   if (threadIdx.x == 0) scount = 0;
   __syncthreads();
@@ -737,16 +784,24 @@ __global__ __launch_bounds__(256) void k_sort_block(DevProblem P, const double* 
   if (threadIdx.x == 0) write_result(xhat, sc, j, found, best, bestp, xb);
 }
 
-__global__ __launch_bounds__(1024) void k_sort_long(DevProblem P, const double* __restrict__ x,
-                                                    const RowState* __restrict__ rs,
-                                                    const WalkState* __restrict__ st, double* __restrict__ xhat,
-                                                    double* __restrict__ sc, const LongTask* __restrict__ tasks,
-                                                    double* gpos, int32_t* gmk, double* gdel) {
+__global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ walks,
+                                                    const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const RowState* rs = C.rs;
+  const WalkState* st = C.st;
+  double* xhat = C.xhat;
+  double* sc = C.s;
+  double* gpos = C.long_pos;
+  int32_t* gmk = C.long_marker;
+  double* gdel = C.long_delta;
   if (st->k >= st->iters) return;
   __shared__ int scount;
   __shared__ double red[16];
   __shared__ int redk[16];
-  const LongTask T = tasks[blockIdx.x];
+  const LongTask T = C.plan.long_tasks[lb];
   const int j = T.col;
   double* pos = gpos + T.offset;
   int32_t* mk = gmk + T.offset;
@@ -798,39 +853,51 @@ __global__ __launch_bounds__(1024) void k_sort_long(DevProblem P, const double* 
 
 }  // namespace
 
-hipError_t launch_best_shift_pass(const DevProblem& P, const PassPlan& plan, const double* x, const RowState* rs,
-                                  const WalkState* st, double* xhat, double* s, hipStream_t stream) {
-  const int nshort = plan.short_seg[kShortMax + 2] - plan.short_seg[0];
-  if (nshort > 0) {
-    ShortSegs segs;
-    for (int k = 0; k < kShortMax + 3; ++k) segs.seg[k] = plan.short_seg[k];
-    hipLaunchKernelGGL(k_short, dim3((nshort + 255) / 256), dim3(256), 0, stream, P, x, rs, st, xhat, s, segs);
+int32_t kernel_blocks(const WalkCtx& c, int slot) {
+  const PassPlan& p = c.plan;
+  switch (slot) {
+    case KS_SHORT: return (p.short_seg[kShortMax + 2] - p.short_seg[0] + 255) / 256;
+    case KS_FLIP: return (p.flip_end - p.flip_begin + 3) / 4;
+    case KS_PACK: return p.n_packs;
+    case KS_CHUNK: return p.n_chunks;
+    case KS_COMBINE: return (p.n_chunk_cols + 3) / 4;
+    case KS_LONG: return p.n_long;
+    case KS_ARGMAX: return c.argmax_blocks;
+    case KS_SELECT: return 1;
+    case KS_APPLY: return c.apply_blocks;
+    case KS_FINISH: return 1;
+    default:
+      if (slot >= KS_SORT0 && slot < KS_SORT0 + kSortCaps)
+        return p.sort_begin[slot - KS_SORT0 + 1] - p.sort_begin[slot - KS_SORT0];
+      return 0;
   }
-  const int nflip = plan.flip_end - plan.flip_begin;
-  if (nflip > 0)
-    hipLaunchKernelGGL(k_flip_wave, dim3((nflip + 3) / 4), dim3(256), 0, stream, P, x, rs, st, xhat, s,
-                       plan.flip_begin, plan.flip_end);
-  if (plan.n_packs > 0)
-    hipLaunchKernelGGL(k_narrow_pack, dim3(plan.n_packs), dim3(256), 0, stream, P, x, rs, st, xhat, s, plan.packs);
-  if (plan.n_chunks > 0) {
-    hipLaunchKernelGGL(k_narrow_chunk, dim3(plan.n_chunks), dim3(256), 0, stream, P, x, rs, st, plan.chunks,
-                       plan.partials);
-    hipLaunchKernelGGL(k_narrow_combine, dim3((plan.n_chunk_cols + 3) / 4), dim3(256), 0, stream, P, x, st, xhat, s,
-                       plan.chunk_cols, plan.n_chunk_cols, plan.partials);
+}
+
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream) {
+  const int nw = L.nw;
+  auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
+  if (L.total[KS_SHORT] > 0)
+    hipLaunchKernelGGL(k_short, grid(KS_SHORT), dim3(256), 0, stream, L.walks, L.off[KS_SHORT], nw);
+  if (L.total[KS_FLIP] > 0)
+    hipLaunchKernelGGL(k_flip_wave, grid(KS_FLIP), dim3(256), 0, stream, L.walks, L.off[KS_FLIP], nw);
+  if (L.total[KS_PACK] > 0)
+    hipLaunchKernelGGL(k_narrow_pack, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
+  if (L.total[KS_CHUNK] > 0) {
+    hipLaunchKernelGGL(k_narrow_chunk, grid(KS_CHUNK), dim3(256), 0, stream, L.walks, L.off[KS_CHUNK], nw);
+    hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
   }
-  for (int c = 0; c < kSortCaps; ++c) {
-    const int q0 = plan.sort_begin[c], n = plan.sort_begin[c + 1] - q0;
-    if (n <= 0) continue;
-    switch (c) {
-      case 0: hipLaunchKernelGGL(k_sort_block<64>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
-      case 1: hipLaunchKernelGGL(k_sort_block<256>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
-      case 2: hipLaunchKernelGGL(k_sort_block<1024>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
-      default: hipLaunchKernelGGL(k_sort_block<4096>, dim3(n), dim3(256), 0, stream, P, x, rs, st, xhat, s, q0); break;
-    }
-  }
-  if (plan.n_long > 0)
-    hipLaunchKernelGGL(k_sort_long, dim3(plan.n_long), dim3(1024), 0, stream, P, x, rs, st, xhat, s,
-                       plan.long_tasks, plan.long_pos, plan.long_marker, plan.long_delta);
+  if (L.total[KS_SORT0] > 0)
+    hipLaunchKernelGGL(k_sort_block<64>, grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
+  if (L.total[KS_SORT0 + 1] > 0)
+    hipLaunchKernelGGL(k_sort_block<256>, grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 1], nw);
+  if (L.total[KS_SORT0 + 2] > 0)
+    hipLaunchKernelGGL(k_sort_block<1024>, grid(KS_SORT0 + 2), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 2],
+                       nw);
+  if (L.total[KS_SORT0 + 3] > 0)
+    hipLaunchKernelGGL(k_sort_block<4096>, grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 3],
+                       nw);
+  if (L.total[KS_LONG] > 0)
+    hipLaunchKernelGGL(k_sort_long, grid(KS_LONG), dim3(1024), 0, stream, L.walks, L.off[KS_LONG], nw);
   return hipGetLastError();
 }
 

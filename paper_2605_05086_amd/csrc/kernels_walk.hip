@@ -57,6 +57,22 @@ __device__ __forceinline__ int viol_change(double r, double r2, double eps) {
   return (r2 > eps ? 1 : 0) - (r > eps ? 1 : 0);
 }
 
+// Walk of this block and the block's index inside that walk (off is the
+// prefix of per-walk block counts).
+__device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int nw, int& local) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nw - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  local = b - off[lo];
+  return lo;
+}
+
 // Incumbent rule, run by one thread when no normalised row is violated: the
 // point is feasible; record it if it improves the best objective and (re)set
 // the cutoff row c^T x <= f_best - delta (section 3.2).
@@ -205,18 +221,25 @@ constexpr int kPartialStride = kArgmaxRecord;
 // lowest original index; one partial record per workgroup. The pending copy
 // of a new incumbent (flagged by the previous iteration, before this
 // iteration's move changes x) is done here too.
-__global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, const int32_t* __restrict__ tabu,
-                                                const int32_t* __restrict__ perm, const WalkState* __restrict__ st,
-                                                double* __restrict__ partial, const double* __restrict__ x,
-                                                double* __restrict__ best_x, int32_t n) {
+__global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                                int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const double* s = C.s;
+  const int32_t* tabu = C.tabu;
+  const int32_t* perm = C.P.perm;
+  const WalkState* st = C.st;
+  const double* x = C.x;
+  double* best_x = C.best_x;
+  const int32_t n = C.P.n;
   if (st->k >= st->iters) return;
   __shared__ double sa_s[4], sn_s[4];
   __shared__ int ja_s[4], jn_s[4], qa_s[4], qn_s[4];
   const int64_t k = st->k;
   const bool copy = st->copy_best != 0;
   Best ba, bn;
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gs = gridDim.x * blockDim.x;
+  const int gt = lb * blockDim.x + threadIdx.x;
+  const int gs = C.argmax_blocks * blockDim.x;
   for (int q = gt; q < n; q += gs) {
     if (copy) best_x[q] = x[q];
     const double v = s[q];
@@ -242,7 +265,7 @@ __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, co
       ba.offer(sa_s[w], ja_s[w], qa_s[w]);
       bn.offer(sn_s[w], jn_s[w], qn_s[w]);
     }
-    double* rec = partial + kPartialStride * blockIdx.x;
+    double* rec = C.argmax_partial + kPartialStride * lb;
     rec[0] = ba.s;
     rec[1] = (double)ba.j;
     rec[2] = (double)ba.q;
@@ -257,11 +280,18 @@ __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ s, co
 // leaves no violated row; since a move changes at most one violation per
 // normalised entry of its column, that is impossible while V exceeds the
 // column's entry count, and the column is only scanned otherwise.
-__global__ __launch_bounds__(256) void k_select(DevProblem P, const double* __restrict__ x,
-                                                const double* __restrict__ xhat, const double* __restrict__ s,
-                                                const RowState* __restrict__ rs, const int32_t* __restrict__ tabu,
-                                                WalkState* st, chap_trace_record* trace,
-                                                const double* __restrict__ partial, int32_t nparts) {
+__global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walks) {
+  const WalkCtx& C = walks[blockIdx.x];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const double* xhat = C.xhat;
+  const double* s = C.s;
+  const RowState* rs = C.rs;
+  const int32_t* tabu = C.tabu;
+  WalkState* st = C.st;
+  chap_trace_record* trace = C.trace;
+  const double* partial = C.argmax_partial;
+  const int32_t nparts = C.argmax_blocks;
   if (st->k >= st->iters) return;
   __shared__ double sa_s[4], sn_s[4];
   __shared__ int ja_s[4], jn_s[4], qa_s[4], qn_s[4];
@@ -373,14 +403,21 @@ __device__ __forceinline__ double row_residual(const DevProblem& P, const double
 // r += a_ij d, exact on all-integer data; otherwise each touched row is
 // summed again from scratch so the kept residual equals its definition bit
 // for bit.
-__global__ __launch_bounds__(256) void k_apply(DevProblem P, const double* __restrict__ x,
-                                               RowState* __restrict__ rs, WalkState* st, int32_t recompute) {
+__global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                               int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  RowState* rs = C.rs;
+  WalkState* st = C.st;
+  const int32_t recompute = C.recompute;
   if (st->k >= st->iters) return;
   __shared__ long long red[4];
   const double eps = P.eps;
   const int jstar = st->mv_j;
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gs = gridDim.x * blockDim.x;
+  const int gt = lb * blockDim.x + threadIdx.x;
+  const int gs = C.apply_blocks * blockDim.x;
   long long dv = 0;
   if (jstar >= 0) {
     const double d = st->mv_delta;
@@ -406,8 +443,13 @@ __global__ __launch_bounds__(256) void k_apply(DevProblem P, const double* __res
 }
 
 // Ends the iteration: objective, cutoff row, incumbent rule, trace, k + 1.
-__global__ void k_finish(DevProblem P, double* __restrict__ x, int32_t* __restrict__ tabu, WalkState* st,
-                         chap_trace_record* trace) {
+__global__ void k_finish(const WalkCtx* __restrict__ walks) {
+  const WalkCtx& C = walks[blockIdx.x];
+  const DevProblem& P = C.P;
+  double* x = C.x;
+  int32_t* tabu = C.tabu;
+  WalkState* st = C.st;
+  chap_trace_record* trace = C.trace;
   if (threadIdx.x != 0 || st->k >= st->iters) return;
   const double eps = P.eps;
   const int64_t k = st->k;
@@ -440,6 +482,15 @@ __global__ __launch_bounds__(256) void k_copy_best(const double* __restrict__ x,
   if (!st->copy_best) return;
   const int gs = gridDim.x * blockDim.x;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gs) best_x[j] = x[j];
+}
+
+__global__ __launch_bounds__(256) void k_copy_best_batch(const WalkCtx* __restrict__ walks,
+                                                         const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (!C.st->copy_best) return;
+  const int gs = C.argmax_blocks * blockDim.x;
+  for (int q = lb * blockDim.x + threadIdx.x; q < C.P.n; q += gs) C.best_x[q] = C.x[q];
 }
 
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ perm, const double* __restrict__ src,
@@ -496,16 +547,18 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
   return hipGetLastError();
 }
 
-hipError_t launch_walk_step(const DevProblem& P, double* x, const double* xhat, const double* s, RowState* rs,
-                            int32_t* tabu_until, WalkState* st, chap_trace_record* trace, double* best_x,
-                            double* argmax_partial, int32_t apply_blocks, int32_t recompute, hipStream_t stream) {
-  const int ab = blocks_for(P.n, kArgmaxBlocks);
-  hipLaunchKernelGGL(k_argmax, dim3(ab), dim3(256), 0, stream, s, tabu_until, P.perm, st, argmax_partial, x, best_x,
-                     P.n);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(256), 0, stream, P, x, xhat, s, rs, tabu_until, st, trace,
-                     argmax_partial, ab);
-  hipLaunchKernelGGL(k_apply, dim3(apply_blocks), dim3(256), 0, stream, P, x, rs, st, recompute);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, stream, P, x, tabu_until, st, trace);
+hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream) {
+  const int nw = L.nw;
+  hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw);
+  hipLaunchKernelGGL(k_select, dim3((unsigned)nw), dim3(256), 0, stream, L.walks);
+  hipLaunchKernelGGL(k_apply, dim3((unsigned)L.total[KS_APPLY]), dim3(256), 0, stream, L.walks, L.off[KS_APPLY], nw);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)nw), dim3(64), 0, stream, L.walks);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_best_batch(const BatchLaunch& L, hipStream_t stream) {
+  hipLaunchKernelGGL(k_copy_best_batch, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks,
+                     L.off[KS_ARGMAX], L.nw);
   return hipGetLastError();
 }
 

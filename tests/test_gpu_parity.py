@@ -336,3 +336,26 @@ def test_best_shift_repeatable(chap):
             torch.cuda.synchronize()
             assert_same(s.cpu().numpy(), os_, f"score rep={rep}")
             assert_same(xh.cpu().numpy(), oxh, f"shift rep={rep}")
+
+
+def test_batch_equals_plain(chap):
+    """Batched walks over instances of uneven size: every walk's trace and
+    final state equal the plain walk's, bit for bit; two walks are also
+    checked against the oracle."""
+    mips = [mipgen.general(900 + k, n=n, m=n // 2) for k, n in enumerate((3000, 800, 6000))]
+    mips.append(mipgen.powerlaw(5, n=8000, m=4000, nnz=80_000, cap=3000))
+    probs = [chap.Problem(m) for m in mips]
+    walk_prob = [w % len(probs) for w in range(10)]
+    walk_seed = [w + 1 for w in range(10)]
+    say("batch of 10 walks on 4 instances, 120 iterations")
+    runs = chap.batch_run(probs, walk_prob, walk_seed, 120, 10)
+    for w, r in enumerate(runs):
+        say(f"plain walk {w}")
+        g = probs[walk_prob[w]].tabu_run(120, 10, walk_seed[w])
+        assert r.trace.tobytes() == g.trace.tobytes(), f"walk {w} trace"
+        assert r.x.tobytes() == g.x.tobytes() and r.resid.tobytes() == g.resid.tobytes()
+        assert r.w.tobytes() == g.w.tobytes() and r.best_obj == g.best_obj
+    for w in (3, 7):
+        say(f"oracle walk {w}")
+        o = oracle.OracleProblem(mips[walk_prob[w]]).tabu_run(120, 10, walk_seed[w])
+        compare_runs(runs[w], o, f"batch walk {w}", exact=True, exact_obj=walk_prob[w] == 3)
