@@ -58,6 +58,8 @@ def _load():
     lib.orc_splitmix64.argtypes = [u64, u64]
     lib.orc_tabu_run.restype = i64
     lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P]
+    lib.orc_learned_replay.restype = i64
+    lib.orc_learned_replay.argtypes = [P, i64, i32, u64, P, i32, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -139,7 +141,21 @@ class OracleProblem:
         self._lib.orc_start_point(self.h, int(seed), _p(x))
         return x
 
+    def learned_replay(self, iters: int, tenure: int, seed: int, full_every: int, sets, set_offsets, x0=None):
+        """The learned proposal form of the walk (orc_learned_replay): full
+        evaluations by the block rule, the listed sets (original indices)
+        everywhere else."""
+        sets = np.ascontiguousarray(sets if sets is not None and len(sets) else np.zeros(1), dtype=np.int32)
+        offs = np.ascontiguousarray(set_offsets, dtype=np.int64)
+        assert offs.shape[0] == iters + 1
+        return self._walk(iters, tenure, seed, x0, lambda *a: self._lib.orc_learned_replay(
+            self.h, int(iters), int(tenure), int(seed), a[0], int(full_every), _p(sets), _p(offs), *a[1:]))
+
     def tabu_run(self, iters: int, tenure: int, seed: int, x0=None):
+        return self._walk(iters, tenure, seed, x0, lambda *a: self._lib.orc_tabu_run(
+            self.h, int(iters), int(tenure), int(seed), *a))
+
+    def _walk(self, iters, tenure, seed, x0, call):
         trace = np.zeros(max(iters, 1), dtype=TRACE_DTYPE)
         x = np.empty(self.n)
         r = np.empty(self.mp + 1)
@@ -152,9 +168,8 @@ class OracleProblem:
         if x0 is not None:
             x0 = np.ascontiguousarray(x0, dtype=np.float64)
             x0p = _p(x0)
-        self._lib.orc_tabu_run(self.h, int(iters), int(tenure), int(seed), x0p, _p(trace), _p(x), _p(r),
-                               _p(w), ctypes.byref(best_obj), _p(best_x), ctypes.byref(has_best),
-                               ctypes.byref(bc))
+        call(x0p, _p(trace), _p(x), _p(r), _p(w), ctypes.byref(best_obj), _p(best_x), ctypes.byref(has_best),
+             ctypes.byref(bc))
         return {
             "trace": trace[:iters], "x": x, "r": r, "w": w, "best_obj": best_obj.value,
             "best_x": best_x if has_best.value else None, "cutoff_rhs": bc.value,

@@ -397,12 +397,18 @@ void orc_start_point(void* h, uint64_t seed, double* x) { start_point(*(OraclePr
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t index) { return splitmix64_output(seed, index); }
 
-// One tabu walk. trace must hold `iters` records. Returns the number of
-// records written (== iters).
-int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
-                     void* trace_out, double* x_out, double* r_out, float* w_out, double* best_obj,
-                     double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
-  OracleProblem& P = *(OracleProblem*)h;
+// One tabu walk. With full_every = 1 every iteration evaluates every column
+// (the method of section 3.1). With full_every > 1 the walk is the learned
+// proposal form: an iteration is a full evaluation when it is the first,
+// follows a stall, or comes full_every iterations after the last full
+// evaluation; any other iteration evaluates only the columns listed for it in
+// sets[set_off[k] .. set_off[k+1]) (original indices) and chooses among them
+// with the same rules; without an admissible move there it is a stall (kind
+// 3: no move, no reweight). Moves chosen from a list get kind + 8.
+int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
+                     int32_t full_every, const int32_t* sets, const int64_t* set_off, void* trace_out,
+                     double* x_out, double* r_out, float* w_out, double* best_obj, double* best_x, int32_t* has_best,
+                     double* cutoff_rhs_out) {
   const int32_t n = P.n;
   std::vector<double> x(n);
   if (x0)
@@ -418,6 +424,7 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
   double bc = 0.0;
   std::vector<double> r;
   std::vector<double> xhat(n), s(n);
+  std::vector<int32_t> cands;
   TraceRec* trace = (TraceRec*)trace_out;
 
   residual_from_scratch(P, x.data(), cutoff, bc, r);
@@ -439,18 +446,28 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
   };
   incumbent_check();
 
+  int64_t k_last_full = 0;
+  bool stalled = false;
   for (int64_t k = 0; k < iters; ++k) {
+    const bool full = full_every <= 1 || k == 0 || stalled || k - k_last_full >= full_every;
+    if (full) k_last_full = k;
     residual_from_scratch(P, x.data(), cutoff, bc, r);
     V = count_violated(P, r, cutoff);
-    for (int32_t j = 0; j < n; ++j) best_shift_one(P, j, x.data(), r, w.data(), cutoff, &xhat[j], &s[j]);
+    cands.clear();
+    if (full) {
+      for (int32_t j = 0; j < n; ++j) cands.push_back(j);
+    } else {
+      for (int64_t t = set_off[k]; t < set_off[k + 1]; ++t) cands.push_back(sets[t]);
+    }
+    for (int32_t j : cands) best_shift_one(P, j, x.data(), r, w.data(), cutoff, &xhat[j], &s[j]);
     int32_t j_all = -1, j_nt = -1;
-    for (int32_t j = 0; j < n; ++j) {
+    for (int32_t j : cands) {
       if (!(s[j] > 0.0)) continue;
-      if (j_all < 0 || s[j] > s[j_all]) j_all = j;
-      if (k > tabu_until[j] && (j_nt < 0 || s[j] > s[j_nt])) j_nt = j;
+      if (j_all < 0 || s[j] > s[j_all] || (s[j] == s[j_all] && j < j_all)) j_all = j;
+      if (k > tabu_until[j] && (j_nt < 0 || s[j] > s[j_nt] || (s[j] == s[j_nt] && j < j_nt))) j_nt = j;
     }
     int32_t jstar = -1;
-    int32_t kind = 2;
+    int32_t kind = full ? 2 : 3;
     if (j_all >= 0 && k > tabu_until[j_all]) {
       jstar = j_all;
       kind = 0;
@@ -471,13 +488,17 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
         kind = 0;
       }
     }
+    if (jstar >= 0 && !full) kind += 8;
+    stalled = (jstar < 0 && !full);
     TraceRec& t = trace[k];
     t.iter = k;
     t.kind = kind;
     if (jstar < 0) {
-      for (int32_t i = 0; i < P.mp; ++i)
-        if (r[i] > P.eps) w[i] += 1.0f;
-      if (cutoff && r[P.mp] > P.eps) w[P.mp] += 1.0f;
+      if (full) {
+        for (int32_t i = 0; i < P.mp; ++i)
+          if (r[i] > P.eps) w[i] += 1.0f;
+        if (cutoff && r[P.mp] > P.eps) w[P.mp] += 1.0f;
+      }
       t.var = -1;
       t.x_old = 0.0;
       t.x_new = 0.0;
@@ -507,6 +528,24 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
   *has_best = found ? 1 : 0;
   *cutoff_rhs_out = cutoff ? bc : kInf;
   return iters;
+}
+
+// One tabu walk. trace must hold `iters` records. Returns the number of
+// records written (== iters).
+int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
+                     void* trace_out, double* x_out, double* r_out, float* w_out, double* best_obj,
+                     double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
+  return learned_walk(*(OracleProblem*)h, iters, tenure, seed, x0, 1, nullptr, nullptr, trace_out, x_out, r_out,
+                      w_out, best_obj, best_x, has_best, cutoff_rhs_out);
+}
+
+// The learned proposal form of the walk, replaying the listed sets.
+int64_t orc_learned_replay(void* h, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
+                           int32_t full_every, const int32_t* sets, const int64_t* set_off, void* trace_out,
+                           double* x_out, double* r_out, float* w_out, double* best_obj, double* best_x,
+                           int32_t* has_best, double* cutoff_rhs_out) {
+  return learned_walk(*(OracleProblem*)h, iters, tenure, seed, x0, full_every, sets, set_off, trace_out, x_out,
+                      r_out, w_out, best_obj, best_x, has_best, cutoff_rhs_out);
 }
 
 }  // extern "C"
