@@ -280,6 +280,108 @@ int chap_model_grad(chap_model *m, const uint16_t *d_feat, const float *d_target
 int chap_model_train(chap_model *m, const uint16_t *d_feat, const float *d_target, int64_t npairs,
                      int32_t steps, int32_t batch, float lr, uint64_t seed, void *hip_stream);
 
+/*
+ * Learned tabu walk.
+ *
+ * Iterations run in blocks of full_every. The first iteration of a block is
+ * a full evaluation, identical to an iteration of chap_tabu_run (exact best
+ * shift of every column, selection under tabu/aspiration, move or reweight);
+ * it also judges the network (was its move in the network's current
+ * proposal set?), optionally trains the network on that evaluation, and
+ * refreshes the stored inputs. Each further iteration is a proposal
+ * iteration: the network scores every proposable column, the topk best
+ * (ties: lowest internal index) get the exact best shift of Eq. 1 /
+ * Algorithm 1, and the move is chosen among them with the same tabu and
+ * aspiration rules (aspiration needs the move to leave no violated row). A
+ * proposal iteration without an admissible move makes no move and no
+ * reweight (a stall); the rest of its block does nothing and the next
+ * iteration is a full evaluation. Every move taken is an exact best shift.
+ *
+ * Trace kinds: 0/1/2 as chap_tabu_run for full evaluations; 8 (move) and
+ * 9 (move by aspiration) for proposal iterations; 3 for a stall.
+ *
+ * Proposable columns: those whose breakpoints fit one workgroup (normalised
+ * entries + 2 bounds + cutoff entry <= 4096). Longer columns are scored only
+ * by the full evaluations.
+ *
+ * Network inputs of column j (index: meaning), each computed in FP64 and
+ * rounded once to bfloat16:
+ *   0 weighted violated share: sum of w_i over violated normalised rows of j
+ *     / sum of w_i over all normalised rows of j (cutoff row excluded; 0 if
+ *     none)            1 log2(1 + stored entries of j)
+ *   2 c_j / max|c| (0 if c = 0)
+ *   3 s_last_j / sum_i w_i, clamped to [-4, 4] (0 if no rows), s_last = the
+ *     exact score at the last full evaluation
+ *   4 1 if binary   5 1 if integer and not binary   6 1 if continuous
+ *   7 (x_j - l_j)/(u_j - l_j); 0.5 with an infinite bound; 0 if l_j = u_j
+ *   8 log2(1 + min(u_j - l_j, 2^20)); 20 with an infinite bound
+ *   9 violated normalised rows of j / normalised rows of j (0 if none)
+ *  10 sum over violated rows of |a_ij| min(r_i, 1000) / (1000 sum_i |a_ij|)
+ *  11 sign(xhat_last_j - x_j), xhat_last = best shift at the last full
+ *     evaluation
+ *  12 min(k - last_move_j, 1024) / 1024 (never moved: last_move = -1024)
+ *  13 min(k - k_last_full, 64) / 64
+ *  14 V / m' (violated normalised rows, cutoff included when active)
+ *  15 log2(1 + moves of j)
+ * Inputs 0, 3, 9, 10 are refreshed at full evaluations only; 7, 11, 12, 15
+ * follow the column's own moves at once.
+ *
+ * Training (train_steps > 0): at each full evaluation, the T = train_pairs
+ * columns with the largest exact scores and T proposable columns drawn with
+ * SplitMix64 (train_seed, index evals * 2T + i) form 2T pairs whose target
+ * is max(s_j, 0) / max_i s_i (0 when no score is positive); train_steps Adam
+ * steps are taken on them with learning rate lr. With log_pairs > 0 the
+ * pairs of every full evaluation are also kept (until log_pairs pairs).
+ */
+typedef struct {
+  int32_t topk;        /* columns given the exact best shift per proposal
+                          iteration; default 1024 */
+  int32_t full_every;  /* iterations per block; 1 = every iteration full
+                          (the chap_tabu_run trajectory); default 64 */
+  int32_t train_steps; /* Adam steps per full evaluation; default 0 */
+  int32_t train_pairs; /* T; default 1024 */
+  float lr;            /* Adam learning rate; default 1e-3 */
+  int32_t log_sets;    /* 1: keep every proposal set in the run */
+  int64_t log_pairs;   /* capacity of the pair log (pairs); default 0 */
+  uint64_t train_seed; /* seed of the random training pairs; default 0 */
+} chap_learned_options;
+
+void chap_learned_options_default(chap_learned_options *opt);
+
+/* One learned walk with model m (same device as p; trained in place when
+ * train_steps > 0). Start point, seed, tenure and iters as chap_tabu_run;
+ * opt may be NULL for the defaults. Synchronous; *out as chap_tabu_run.
+ * CHAP_EINVAL on invalid options (topk, full_every, train_pairs <= 0,
+ * lr <= 0, train_steps < 0). */
+int chap_learned_run(chap_problem *p, chap_model *m, const chap_learned_options *opt,
+                     int64_t iters, int32_t tenure, uint64_t seed, const double *x0,
+                     chap_run **out, void *hip_stream);
+
+/* Counters of a learned run: full evaluations, evaluations whose move was
+ * in the network's proposal set, stalls. Zero for other runs. */
+int chap_run_learned_stats(const chap_run *r, int64_t *evals, int64_t *hits, int64_t *stalls);
+
+/* Proposal sets of a learned run with log_sets: iteration k's set is
+ * sets[offsets[k] .. offsets[k+1]) (original column indices, ascending
+ * internal order); full evaluations have empty ranges. *iters = 0 without
+ * the log. Pointers valid until chap_run_destroy. */
+int chap_run_proposals(const chap_run *r, const int32_t **sets, const int64_t **offsets,
+                       int64_t *iters);
+
+/* Logged training pairs (count x 16 bfloat16 inputs, count targets). */
+int chap_run_pairs(const chap_run *r, const uint16_t **feat, const float **target, int64_t *count);
+
+/* Network inputs of every column at a given state, as defined above:
+ * d_x (n), d_w (m'+1, cutoff weight last), cutoff_rhs (+inf: inactive),
+ * d_s_last and d_xhat_last (n, FP64), d_last_move and d_moves (n, int32),
+ * iteration k and k_last_full <= k; all device arrays in original order.
+ * Writes d_out (device, n x 16 bfloat16 bits, original order); rows of
+ * columns that are never proposed are zero. Synchronous. */
+int chap_features(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
+                  const double *d_s_last, const double *d_xhat_last, const int32_t *d_last_move,
+                  const int32_t *d_moves, int64_t k, int64_t k_last_full, uint16_t *d_out,
+                  void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,12 @@ class ChapOptions(ctypes.Structure):
                 ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32)]
 
 
+class LearnedOptions(ctypes.Structure):
+    _fields_ = [("topk", ctypes.c_int32), ("full_every", ctypes.c_int32), ("train_steps", ctypes.c_int32),
+                ("train_pairs", ctypes.c_int32), ("lr", ctypes.c_float), ("log_sets", ctypes.c_int32),
+                ("log_pairs", ctypes.c_int64), ("train_seed", ctypes.c_uint64)]
+
+
 class ChapError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -91,6 +97,18 @@ def load_library():
     lib.chap_model_grad.restype = ctypes.c_int
     lib.chap_model_train.argtypes = [P, P, P, i64, i32, i32, ctypes.c_float, u64, P]
     lib.chap_model_train.restype = ctypes.c_int
+    lib.chap_learned_options_default.argtypes = [ctypes.POINTER(LearnedOptions)]
+    lib.chap_learned_options_default.restype = None
+    lib.chap_learned_run.argtypes = [P, P, ctypes.POINTER(LearnedOptions), i64, i32, u64, P, ctypes.POINTER(P), P]
+    lib.chap_learned_run.restype = ctypes.c_int
+    lib.chap_run_learned_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.chap_run_learned_stats.restype = ctypes.c_int
+    lib.chap_run_proposals.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
+    lib.chap_run_proposals.restype = ctypes.c_int
+    lib.chap_run_pairs.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
+    lib.chap_run_pairs.restype = ctypes.c_int
+    lib.chap_features.argtypes = [P, P, P, f64, P, P, P, P, i64, i64, P, P]
+    lib.chap_features.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -146,6 +164,31 @@ class Run:
         if math.isinf(self.best_obj):
             self.best_x = None
         self.elapsed_ms = lib.chap_run_elapsed_ms(handle)
+        ev, hi, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.chap_run_learned_stats(handle, ctypes.byref(ev), ctypes.byref(hi), ctypes.byref(st)))
+        self.evals, self.hits, self.stalls = ev.value, hi.value, st.value
+        sets, offs, iters = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib.chap_run_proposals(handle, ctypes.byref(sets), ctypes.byref(offs), ctypes.byref(iters)))
+        self.set_offsets = None
+        self.sets = None
+        if iters.value > 0:
+            o = np.ctypeslib.as_array((ctypes.c_int64 * (iters.value + 1)).from_address(offs.value)).copy()
+            self.set_offsets = o
+            self.sets = (np.ctypeslib.as_array((ctypes.c_int32 * int(o[-1])).from_address(sets.value)).copy()
+                         if o[-1] > 0 else np.zeros(0, dtype=np.int32))
+        pf, pt, cnt = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib.chap_run_pairs(handle, ctypes.byref(pf), ctypes.byref(pt), ctypes.byref(cnt)))
+        self.pair_feat = None
+        self.pair_target = None
+        if cnt.value > 0:
+            self.pair_feat = np.ctypeslib.as_array(
+                (ctypes.c_uint16 * (cnt.value * 16)).from_address(pf.value)).copy().reshape(cnt.value, 16)
+            self.pair_target = np.ctypeslib.as_array((ctypes.c_float * cnt.value).from_address(pt.value)).copy()
+
+    def proposal_set(self, k: int):
+        """Original column indices proposed at iteration k (empty for a full
+        evaluation); needs a run with log_sets."""
+        return self.sets[self.set_offsets[k]:self.set_offsets[k + 1]]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -237,6 +280,47 @@ class Problem:
         _check(load_library().chap_tabu_run(self._h, int(iters), int(tenure), int(seed), x0p, ctypes.byref(h),
                                             _stream_handle(stream)))
         return Run(h, self.n, self.mp)
+
+
+def learned_options(**kw) -> LearnedOptions:
+    o = LearnedOptions()
+    load_library().chap_learned_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown learned option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def learned_run(problem, model, iters: int, tenure: int, seed: int, x0=None, stream=None, **options) -> Run:
+    """chap_learned_run: synchronous; options as chap_learned_options
+    (topk, full_every, train_steps, train_pairs, lr, log_sets, log_pairs,
+    train_seed)."""
+    o = learned_options(**options)
+    h = ctypes.c_void_p()
+    x0p = None
+    if x0 is not None:
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        assert x0.shape[0] == problem.n
+        x0p = _ptr(x0)
+    _check(load_library().chap_learned_run(problem._h, model._h, ctypes.byref(o), int(iters), int(tenure), int(seed),
+                                           x0p, ctypes.byref(h), _stream_handle(stream)))
+    return Run(h, problem.n, problem.mp)
+
+
+def features(problem, x, w, cutoff_rhs, s_last, xhat_last, last_move, moves, k: int, k_last_full: int,
+             stream=None):
+    """chap_features on device tensors (original order); returns an (n, 16)
+    int16 tensor of bfloat16 bit patterns."""
+    import torch
+    n = problem.n
+    out = torch.empty((n, 16), dtype=torch.int16, device=x.device)
+    _check(load_library().chap_features(
+        problem._h, _dev_ptr(x, torch.float64, n), _dev_ptr(w, torch.float32, problem.mp + 1), float(cutoff_rhs),
+        _dev_ptr(s_last, torch.float64, n), _dev_ptr(xhat_last, torch.float64, n), _dev_ptr(last_move, torch.int32, n),
+        _dev_ptr(moves, torch.int32, n), int(k), int(k_last_full), _dev_ptr(out, torch.int16, n * 16),
+        _stream_handle(stream)))
+    return out
 
 
 def batch_run(problems, walk_prob, walk_seed, iters: int, tenure: int, stream=None):

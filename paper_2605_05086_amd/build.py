@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchap.so")
-SOURCES = ["api.hip", "api_model.hip", "kernels_pass.hip", "kernels_walk.hip", "kernels_mlp.hip"]
+SOURCES = ["api.hip", "api_model.hip", "api_learned.hip", "kernels_pass.hip", "kernels_walk.hip", "kernels_mlp.hip",
+           "kernels_learned.hip"]
 HEADERS = [os.path.join(CSRC, "chap_internal.h"), os.path.join(CSRC, "mlp_core.h"), os.path.join(INCLUDE, "chap.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

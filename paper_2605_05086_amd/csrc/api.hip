@@ -26,64 +26,16 @@ int fail(int code, const std::string& msg) {
 
 }  // namespace chap
 
-struct chap_problem {
-  int32_t n = 0, m = 0, mp = 0;
-  double eps = 1e-6;
-  chap_options opt{};
-  int32_t obj_integral = 1;
-  int32_t max_col_deg = 0;
-  // 1 when every variable is integer with finite bounds and every
-  // coefficient and right-hand side is an integer small enough that all row
-  // activities are exact in FP64: incremental residual updates are then exact
-  int32_t exact_incremental = 0;
-  // host copies used by runs
-  std::vector<double> lb, ub, obj;
-  std::vector<uint8_t> is_int;
-  std::vector<int32_t> nidx;  // normalised index of each stored row
-  std::vector<uint8_t> pair;  // stored row is an equality (two normalised rows)
-  std::vector<int32_t> norm_orig;
-  std::vector<int8_t> norm_sign;
-  // device
-  DeviceArena arena;
-  DevProblem dev{};
-  PassPlan plan{};
-  const int32_t* d_nidx = nullptr;
-  const uint8_t* d_pair = nullptr;
-  int32_t device = 0;
-  // scratch of chap_best_shift
-  RowState* bs_rs = nullptr;
-  WalkState* bs_state = nullptr;
-  double* bs_partial = nullptr;
-  uint32_t* bs_ticket = nullptr;
-  double* bs_x = nullptr;
-  double* bs_xhat = nullptr;
-  double* bs_s = nullptr;
-  std::vector<int32_t> perm;  // original index of each internal column
-  BatchLaunch bs_launch;
-  hipEvent_t pass_ev[2] = {nullptr, nullptr};
-  bool pass_timed = false;
-  ~chap_problem() {
-    for (hipEvent_t e : pass_ev)
-      if (e) (void)hipEventDestroy(e);
-  }
-};
-
-struct chap_run {
-  std::vector<chap_trace_record> trace;
-  std::vector<double> x, resid, best_x;
-  std::vector<float> w;
-  double best_obj = HUGE_VAL;
-  double cutoff_rhs = HUGE_VAL;
-  bool has_best = false;
-  double elapsed_ms = 0.0;
-};
-
 namespace {
 
 __global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
 }
+
+}  // namespace
+
+namespace chap {
 
 // Uploads per-walk contexts and the per-kernel block prefix tables.
 hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLaunch* L) {
@@ -109,7 +61,7 @@ int blocks_for_host(int64_t work, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
-}  // namespace
+}  // namespace chap
 
 extern "C" {
 
@@ -478,6 +430,15 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     longs.push_back(t);
   }
   P->perm = perm;
+  // learned proposal: columns whose breakpoints fit one workgroup's LDS sort
+  P->sub_cls.assign(n, SUB_NONE);
+  for (int32_t q = 0; q < n; ++q) {
+    const int32_t j = perm[q];
+    if (ne[j] + 2 > kSubsetCap) continue;
+    P->sub_cls[q] = cls[j] == BIN ? SUB_FLIP : (cls[j] == NARROW ? SUB_NARROW : SUB_GENERAL);
+  }
+  P->c_max = 0.0;
+  for (int32_t j = 0; j < n; ++j) P->c_max = std::max(P->c_max, std::fabs(P->obj[j]));
   // ---- upload --------------------------------------------------------------
   {
     int dev = 0;
@@ -614,13 +575,6 @@ int chap_best_shift_pass_ms(chap_problem* p, double* ms) {
 
 namespace {
 
-// One walk of a run: its problem, start point (original order) and seed.
-struct WalkSpec {
-  chap_problem* p;
-  uint64_t seed;
-  const double* x0;
-};
-
 void start_point(const chap_problem* p, uint64_t seed, double* x) {
   for (int32_t j = 0; j < p->n; ++j) {
     const double l = p->lb[j], u = p->ub[j];
@@ -637,6 +591,104 @@ void start_point(const chap_problem* p, uint64_t seed, double* x) {
   }
 }
 
+}  // namespace
+
+namespace chap {
+
+int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
+                 uint32_t* ticket, hipStream_t s) {
+  const chap_problem* p = spec.p;
+  const int32_t n = p->n;
+  std::vector<double> xs(n), xq(n);
+  if (spec.x0) {
+    for (int32_t j = 0; j < n; ++j) {
+      if (!std::isfinite(spec.x0[j])) return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
+      xs[j] = spec.x0[j];
+    }
+  } else {
+    start_point(p, spec.seed, xs.data());
+  }
+  for (int32_t q = 0; q < n; ++q) xq[q] = xs[p->perm[q]];
+  c = WalkCtx{};
+  c.P = p->dev;
+  c.plan = p->plan;
+  c.argmax_blocks = blocks_for_host(n, kArgmaxBlocks);
+  c.apply_blocks = blocks_for_host(std::max(p->m, p->max_col_deg), 256);
+  c.recompute = p->exact_incremental ? 0 : 1;
+  CHAP_HIP(A.alloc(&c.x, (size_t)n));
+  CHAP_HIP(A.alloc(&c.xhat, (size_t)n));
+  CHAP_HIP(A.alloc(&c.s, (size_t)n));
+  CHAP_HIP(A.alloc(&c.best_x, (size_t)n));
+  CHAP_HIP(A.alloc(&c.tabu, (size_t)n));
+  CHAP_HIP(A.alloc(&c.rs, (size_t)p->m));
+  CHAP_HIP(A.alloc(&c.st, 1));
+  CHAP_HIP(A.alloc(&c.trace, (size_t)std::max<int64_t>(iters, 1)));
+  CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * c.argmax_blocks));
+  CHAP_HIP(A.alloc(&c.partials, (size_t)p->plan.n_partials));
+  CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
+  CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));
+  CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
+  CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
+  if (n > 0) {
+    CHAP_HIP(hipMemcpyAsync(c.x, xq.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)n);
+    CHAP_HIP(hipGetLastError());
+  }
+  CHAP_HIP(launch_residual(p->dev, c.x, c.rs, s));
+  CHAP_HIP(launch_set_weights_unit(p->d_pair, c.rs, p->m, s));
+  CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
+                             nullptr, 1, s));
+  CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
+  // the host copy of xq must outlive the asynchronous upload
+  CHAP_HIP(hipStreamSynchronize(s));
+  return CHAP_OK;
+}
+
+int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double ms, chap_run* R) {
+  const int32_t n = p->n, m = p->m;
+  R->elapsed_ms = ms;
+  R->trace.resize((size_t)iters);
+  if (iters > 0)
+    CHAP_HIP(hipMemcpy(R->trace.data(), c.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
+  std::vector<double> xin(n), bxin(n);
+  if (n > 0) {
+    CHAP_HIP(hipMemcpy(xin.data(), c.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    CHAP_HIP(hipMemcpy(bxin.data(), c.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+  }
+  R->x.resize(n);
+  std::vector<double> bx(n);
+  for (int32_t q = 0; q < n; ++q) {
+    R->x[p->perm[q]] = xin[q];
+    bx[p->perm[q]] = bxin[q];
+  }
+  std::vector<RowState> rs(m);
+  if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), c.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
+  WalkState st;
+  CHAP_HIP(hipMemcpy(&st, c.st, sizeof(WalkState), hipMemcpyDeviceToHost));
+  R->resid.assign((size_t)p->mp + 1, 0.0);
+  R->w.assign((size_t)p->mp + 1, 0.0f);
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t k = p->nidx[i];
+    R->resid[k] = rs[i].r;
+    R->w[k] = rs[i].w0;
+    if (p->pair[i]) {
+      R->resid[k + 1] = -rs[i].r;
+      R->w[k + 1] = rs[i].w1;
+    }
+  }
+  R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
+  R->w[p->mp] = st.wc;
+  R->has_best = st.has_best != 0;
+  R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
+  R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
+  if (R->has_best) R->best_x = bx;
+  return CHAP_OK;
+}
+
+}  // namespace chap
+
+namespace {
+
 // Runs every walk for `iters` iterations: per-walk buffers, set-up kernels,
 // then a HIP graph of `graph_iters` iterations in which each kernel is one
 // launch over all walks. Results are copied back into chap_run objects.
@@ -647,42 +699,6 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   const size_t nw = specs.size();
   DeviceArena A;
   std::vector<WalkCtx> ctx(nw);
-  std::vector<std::vector<double>> xq(nw);
-  for (size_t w = 0; w < nw; ++w) {
-    const chap_problem* p = specs[w].p;
-    const int32_t n = p->n;
-    std::vector<double> xs(n);
-    if (specs[w].x0) {
-      for (int32_t j = 0; j < n; ++j) {
-        if (!std::isfinite(specs[w].x0[j]))
-          return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
-        xs[j] = specs[w].x0[j];
-      }
-    } else {
-      start_point(p, specs[w].seed, xs.data());
-    }
-    xq[w].resize(n);
-    for (int32_t q = 0; q < n; ++q) xq[w][q] = xs[p->perm[q]];
-    WalkCtx& c = ctx[w];
-    c.P = p->dev;
-    c.plan = p->plan;
-    c.argmax_blocks = blocks_for_host(n, kArgmaxBlocks);
-    c.apply_blocks = blocks_for_host(std::max(p->m, p->max_col_deg), 256);
-    c.recompute = p->exact_incremental ? 0 : 1;
-    CHAP_HIP(A.alloc(&c.x, (size_t)n));
-    CHAP_HIP(A.alloc(&c.xhat, (size_t)n));
-    CHAP_HIP(A.alloc(&c.s, (size_t)n));
-    CHAP_HIP(A.alloc(&c.best_x, (size_t)n));
-    CHAP_HIP(A.alloc(&c.tabu, (size_t)n));
-    CHAP_HIP(A.alloc(&c.rs, (size_t)p->m));
-    CHAP_HIP(A.alloc(&c.st, 1));
-    CHAP_HIP(A.alloc(&c.trace, (size_t)std::max<int64_t>(iters, 1)));
-    CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * c.argmax_blocks));
-    CHAP_HIP(A.alloc(&c.partials, (size_t)p->plan.n_partials));
-    CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
-    CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));
-    CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
-  }
   double* partial;
   uint32_t* ticket;
   CHAP_HIP(A.alloc(&partial, 2 * 1024));
@@ -709,20 +725,8 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
   CHAP_HIP(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
   for (size_t w = 0; w < nw; ++w) {
-    const chap_problem* p = specs[w].p;
-    const WalkCtx& c = ctx[w];
-    const int32_t n = p->n;
-    CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
-    if (n > 0) {
-      CHAP_HIP(hipMemcpyAsync(c.x, xq[w].data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)n);
-      CHAP_HIP(hipGetLastError());
-    }
-    CHAP_HIP(launch_residual(p->dev, c.x, c.rs, s));
-    CHAP_HIP(launch_set_weights_unit(p->d_pair, c.rs, p->m, s));
-    CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
-                               nullptr, 1, s));
-    CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
+    const int rc = prepare_walk(specs[w], iters, tenure, A, ctx[w], partial, ticket, s);
+    if (rc != CHAP_OK) return rc;
   }
   BatchLaunch L;
   CHAP_HIP(build_launch(A, ctx, &L));
@@ -762,46 +766,9 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   CHAP_HIP(hipStreamSynchronize(s));
   out.clear();
   for (size_t w = 0; w < nw; ++w) {
-    const chap_problem* p = specs[w].p;
-    const WalkCtx& c = ctx[w];
-    const int32_t n = p->n, m = p->m;
     std::unique_ptr<chap_run> R(new chap_run());
-    R->elapsed_ms = ms_total;
-    R->trace.resize((size_t)iters);
-    if (iters > 0)
-      CHAP_HIP(hipMemcpy(R->trace.data(), c.trace, sizeof(chap_trace_record) * (size_t)iters, hipMemcpyDeviceToHost));
-    std::vector<double> xin(n), bxin(n);
-    if (n > 0) {
-      CHAP_HIP(hipMemcpy(xin.data(), c.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
-      CHAP_HIP(hipMemcpy(bxin.data(), c.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
-    }
-    R->x.resize(n);
-    std::vector<double> bx(n);
-    for (int32_t q = 0; q < n; ++q) {
-      R->x[p->perm[q]] = xin[q];
-      bx[p->perm[q]] = bxin[q];
-    }
-    std::vector<RowState> rs(m);
-    if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), c.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
-    WalkState st;
-    CHAP_HIP(hipMemcpy(&st, c.st, sizeof(WalkState), hipMemcpyDeviceToHost));
-    R->resid.assign((size_t)p->mp + 1, 0.0);
-    R->w.assign((size_t)p->mp + 1, 0.0f);
-    for (int32_t i = 0; i < m; ++i) {
-      const int32_t k = p->nidx[i];
-      R->resid[k] = rs[i].r;
-      R->w[k] = rs[i].w0;
-      if (p->pair[i]) {
-        R->resid[k + 1] = -rs[i].r;
-        R->w[k + 1] = rs[i].w1;
-      }
-    }
-    R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
-    R->w[p->mp] = st.wc;
-    R->has_best = st.has_best != 0;
-    R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
-    R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
-    if (R->has_best) R->best_x = bx;
+    const int rc = collect_walk(specs[w].p, ctx[w], iters, ms_total, R.get());
+    if (rc != CHAP_OK) return rc;
     out.push_back(std::move(R));
   }
   return CHAP_OK;

@@ -12,12 +12,6 @@
 
 using namespace chap;
 
-struct chap_model {
-  int32_t device = 0;
-  DeviceArena arena;
-  ModelDev dev;
-};
-
 namespace {
 
 // He-uniform initial parameters: weight p of a layer with fan-in k is

@@ -130,6 +130,8 @@ struct __align__(16) WalkState {
   double mv_delta;
   double mv_score;
   unsigned long long dV;  // two's complement accumulator of violation changes
+  int32_t skip;           // learned walks: this iteration does nothing (block idle)
+  int32_t pad;
 };
 
 // A slice of a long narrow-integer column handled by one workgroup; col < 0
@@ -305,5 +307,198 @@ hipError_t launch_mlp_grad(const ModelDev& M, const uint16_t* feat, const float*
 // M.grad; with `update`, one Adam step with learning rate lr.
 hipError_t launch_mlp_reduce(const ModelDev& M, int64_t nb, int update, float lr, hipStream_t s);
 hipError_t launch_mlp_bf16_copy(const ModelDev& M, hipStream_t s);
+// Guarded variants used inside a learned walk's graph: they do nothing while
+// *active == 0.
+hipError_t launch_mlp_grad_guarded(const ModelDev& M, const int32_t* active, const uint16_t* feat,
+                                   const float* target, int64_t nb, hipStream_t s);
+hipError_t launch_mlp_reduce_guarded(const ModelDev& M, const int32_t* active, int64_t nb, float lr, hipStream_t s);
+
+// ---- learned candidate proposal (kernels_learned.hip) ---------------------
+constexpr int kRadixBins = 2048;   // radix-select digit bins (11, 11, 10 bits)
+constexpr int kTopkChunk = 4096;   // columns per workgroup of the top-k compaction
+constexpr int kSubsetCap = 4096;   // breakpoint capacity of the subset best-shift workgroup
+constexpr int kStallKind = 3;      // trace kind of a proposal iteration without a move
+constexpr int kProposalKind = 8;   // added to the kind of a move chosen from a proposal set
+
+// Per-column proposal class (internal order).
+enum : uint8_t { SUB_NONE = 0, SUB_FLIP = 1, SUB_NARROW = 2, SUB_GENERAL = 3 };
+
+// Input slots of a stored feature row (16 bfloat16 values per column):
+// slots 0..11 hold network inputs 0..11, slots 12..13 the int32 iteration of
+// the column's last move, slot 14 is unused and slot 15 holds input 15.
+// Inputs 12..14 are computed when a row is read.
+struct TopkState {
+  uint32_t prefix;     // digits chosen so far
+  int32_t remaining;   // entries still to take under that prefix
+  uint32_t thresh;     // final key T (0: take every nonzero key)
+  int32_t need_eq;     // entries with key == T to take, lowest column first
+  int32_t count;       // entries selected
+  int32_t done;        // 1 once the threshold is final
+};
+
+struct LearnState {
+  int32_t idle;          // the rest of this block's proposal iterations do nothing
+  int32_t train_active;  // the block's full evaluation trains the network
+  int64_t k_last_full;   // iteration of the last full evaluation
+  int64_t evals;         // full evaluations
+  int64_t hits;          // full evaluations whose move was in the network's proposal set
+  int64_t stalls;        // proposal iterations without an admissible move
+  int64_t logged;        // pairs written to the pair log
+  int64_t set_pos;       // entries written to the proposal-set log
+  TopkState tk[2];       // 0: proposal set, 1: training labels
+};
+
+struct LearnCtx {
+  const uint8_t* cls;        // SUB_* per internal column
+  const int32_t* elig_list;  // internal indices of proposable columns
+  int32_t n_elig;
+  int32_t mp;                // normalised rows (for the violated fraction)
+  double c_max;              // max |c_j| (0 when c = 0)
+  uint16_t* feat;            // n x 16 stored rows
+  int32_t* moves;            // moves per column
+  double* xhat_last;         // best shift at the last full evaluation
+  uint32_t* keys[2];         // 0: network scores, 1: labels
+  uint32_t* hist;            // 2 x 3 x kRadixBins
+  int32_t* wg_cnt;           // 2 x nwg x 2 (greater, equal)
+  int32_t* wg_base;          // 2 x nwg x 2
+  int32_t* sel[2];           // selected columns, ascending internal index
+  int32_t K[2];
+  int32_t nwg;               // workgroups of the compaction
+  uint16_t* pair_feat;       // 2T x 16 training inputs
+  float* pair_tgt;           // 2T targets
+  uint16_t* log_feat;        // pair log (nullable)
+  float* log_tgt;
+  int64_t log_cap;
+  int32_t* set_log;          // proposal-set log (nullable), original indices
+  int64_t* set_off;          // iters + 1 offsets into set_log (nullable)
+  int64_t set_log_cap;
+  int32_t T;
+  int32_t full_every;
+  uint64_t seed;
+  LearnState* ls;
+};
+
+// One learned walk (C: one walk context on the device, L: its learned
+// context on the device, Lh: host copy of L).
+// Stored rows of every column; last_move and moves (original order) may be
+// null for a walk's start (never moved).
+hipError_t launch_learn_init(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int32_t n,
+                             const int32_t* last_move, const int32_t* moves, hipStream_t s);
+hipError_t launch_learn_refresh(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, hipStream_t s);
+hipError_t launch_learn_begin(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
+// Network scores of every column and the proposal set (top K[0]).
+hipError_t launch_learn_propose(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
+                                int32_t n, int full_iteration, hipStream_t s);
+// Training pairs of a full evaluation (top T by score + T random) and the
+// network update.
+hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
+                              int32_t n, int32_t steps, float lr, hipStream_t s);
+hipError_t launch_learn_judge(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
+hipError_t launch_learn_copy_best(const WalkCtx* C, const LearnCtx* L, int32_t n, hipStream_t s);
+hipError_t launch_learn_move(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
+// Materialised inputs of every column at the walk's state (original order).
+hipError_t launch_learn_features_out(const WalkCtx* C, const LearnCtx* L, int32_t n, int64_t k, int64_t k_last_full,
+                                     uint16_t* out, hipStream_t s);
+// Exact best shift of the proposal set (kernels_pass.hip).
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, int32_t K, hipStream_t s);
+// Move choice over the proposal set (kernels_walk.hip).
+hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
+
+}  // namespace chap
+
+// Handles of the C ABI (defined here so every source file of the library
+// sees them).
+struct chap_problem {
+  int32_t n = 0, m = 0, mp = 0;
+  double eps = 1e-6;
+  chap_options opt{};
+  int32_t obj_integral = 1;
+  int32_t max_col_deg = 0;
+  // 1 when every variable is integer with finite bounds and every
+  // coefficient and right-hand side is an integer small enough that all row
+  // activities are exact in FP64: incremental residual updates are then exact
+  int32_t exact_incremental = 0;
+  // host copies used by runs
+  std::vector<double> lb, ub, obj;
+  std::vector<uint8_t> is_int;
+  std::vector<int32_t> nidx;  // normalised index of each stored row
+  std::vector<uint8_t> pair;  // stored row is an equality (two normalised rows)
+  std::vector<int32_t> norm_orig;
+  std::vector<int8_t> norm_sign;
+  // device
+  chap::DeviceArena arena;
+  chap::DevProblem dev{};
+  chap::PassPlan plan{};
+  const int32_t* d_nidx = nullptr;
+  const uint8_t* d_pair = nullptr;
+  int32_t device = 0;
+  // scratch of chap_best_shift
+  chap::RowState* bs_rs = nullptr;
+  chap::WalkState* bs_state = nullptr;
+  double* bs_partial = nullptr;
+  uint32_t* bs_ticket = nullptr;
+  double* bs_x = nullptr;
+  double* bs_xhat = nullptr;
+  double* bs_s = nullptr;
+  std::vector<int32_t> perm;  // original index of each internal column
+  // learned proposal: SUB_* class per internal column, max |c_j|
+  std::vector<uint8_t> sub_cls;
+  double c_max = 0.0;
+  chap::BatchLaunch bs_launch;
+  hipEvent_t pass_ev[2] = {nullptr, nullptr};
+  bool pass_timed = false;
+  ~chap_problem() {
+    for (hipEvent_t e : pass_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+struct chap_run {
+  std::vector<chap_trace_record> trace;
+  std::vector<double> x, resid, best_x;
+  std::vector<float> w;
+  double best_obj = HUGE_VAL;
+  double cutoff_rhs = HUGE_VAL;
+  bool has_best = false;
+  double elapsed_ms = 0.0;
+  // learned walks
+  int64_t evals = 0, hits = 0, stalls = 0;
+  std::vector<int32_t> sets;     // proposal sets (original indices)
+  std::vector<int64_t> set_off;  // iters + 1 offsets into sets
+  std::vector<uint16_t> pair_feat;
+  std::vector<float> pair_tgt;
+};
+
+
+struct chap_model {
+  int32_t device = 0;
+  chap::DeviceArena arena;
+  chap::ModelDev dev;
+};
+
+namespace chap {
+
+// One walk of a run: its problem, start point (original order, or null for
+// the seeded start point) and seed.
+struct WalkSpec {
+  chap_problem* p;
+  uint64_t seed;
+  const double* x0;
+};
+
+// Allocates one walk's buffers in A, uploads its start point and runs the
+// set-up kernels on stream s (residual, unit weights, state, incumbent).
+int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
+                 uint32_t* ticket, hipStream_t s);
+// Copies a finished walk back into R (host order).
+int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double ms, chap_run* R);
+// Device copy of the walk contexts and the per-kernel launch tables.
+hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLaunch* L);
+int blocks_for_host(int64_t work, int cap);
+// The parts of launch_walk_step: argmax + selection, application, end of
+// iteration.
+hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream);
+hipError_t launch_walk_apply(const BatchLaunch& L, hipStream_t stream);
+hipError_t launch_walk_finish(const BatchLaunch& L, hipStream_t stream);
 
 }  // namespace chap

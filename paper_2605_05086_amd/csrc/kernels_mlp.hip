@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
                                                   const uint16_t* __restrict__ feat,
                                                   const float* __restrict__ target, int64_t rows, int64_t nb,
                                                   int32_t sample, uint64_t seed, uint64_t base, float inv_nb,
-                                                  float* __restrict__ partials) {
+                                                  float* __restrict__ partials, const int32_t* active) {
+  if (active && !*active) return;
   __shared__ uint16_t sG2[kWaves][kHid * 16];
   __shared__ uint16_t sH1[kWaves][kHid * 16];
   __shared__ uint16_t sG1[kWaves][kHid * 16];
@@ -218,8 +219,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
 }
 
 // Advances Adam's step counter and the powers beta1^t, beta2^t (FP64).
-__global__ void k_adam_begin(double* adam, double beta1, double beta2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_adam_begin(double* adam, double beta1, double beta2, const int32_t* active) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || (active && !*active)) return;
   adam[0] *= beta1;
   adam[1] *= beta2;
   adam[2] += 1.0;
@@ -233,7 +234,8 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(float* __restrict__ w, uint1
                                                     const double* __restrict__ adam, float* __restrict__ grad,
                                                     const float* __restrict__ partials, int32_t nparts,
                                                     int32_t update, float lr, float beta1, float omb1, float beta2,
-                                                    float omb2, float eps) {
+                                                    float omb2, float eps, const int32_t* active) {
+  if (active && !*active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kNParam) return;
   float gsum = 0.0f;
@@ -273,20 +275,38 @@ int32_t mlp_grad_blocks(int64_t nb) {
   return (int32_t)std::max<int64_t>(1, std::min<int64_t>((tiles + kWaves - 1) / kWaves, kGradBlocks));
 }
 
-hipError_t launch_mlp_grad(const ModelDev& M, const uint16_t* feat, const float* target, int64_t rows, int64_t nb,
-                           int sample, uint64_t seed, uint64_t base, hipStream_t s) {
+hipError_t grad_impl(const ModelDev& M, const int32_t* active, const uint16_t* feat, const float* target,
+                     int64_t rows, int64_t nb, int sample, uint64_t seed, uint64_t base, hipStream_t s) {
   const int32_t blocks = mlp_grad_blocks(nb);
   hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)blocks), dim3(256), 0, s, M.w, M.wb, feat, target, rows, nb,
-                     (int32_t)sample, seed, base, (float)(1.0 / (double)nb), M.partials);
+                     (int32_t)sample, seed, base, (float)(1.0 / (double)nb), M.partials, active);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_reduce(const ModelDev& M, int64_t nb, int update, float lr, hipStream_t s) {
-  if (update) hipLaunchKernelGGL(k_adam_begin, dim3(1), dim3(64), 0, s, M.adam, kAdamBeta1, kAdamBeta2);
+hipError_t reduce_impl(const ModelDev& M, const int32_t* active, int64_t nb, int update, float lr, hipStream_t s) {
+  if (update) hipLaunchKernelGGL(k_adam_begin, dim3(1), dim3(64), 0, s, M.adam, kAdamBeta1, kAdamBeta2, active);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 255) / 256), dim3(256), 0, s, M.w, M.wb, M.m, M.v, M.adam, M.grad,
                      M.partials, mlp_grad_blocks(nb), (int32_t)update, lr, (float)kAdamBeta1,
-                     (float)(1.0 - kAdamBeta1), (float)kAdamBeta2, (float)(1.0 - kAdamBeta2), kAdamEps);
+                     (float)(1.0 - kAdamBeta1), (float)kAdamBeta2, (float)(1.0 - kAdamBeta2), kAdamEps, active);
   return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const ModelDev& M, const uint16_t* feat, const float* target, int64_t rows, int64_t nb,
+                           int sample, uint64_t seed, uint64_t base, hipStream_t s) {
+  return grad_impl(M, nullptr, feat, target, rows, nb, sample, seed, base, s);
+}
+
+hipError_t launch_mlp_reduce(const ModelDev& M, int64_t nb, int update, float lr, hipStream_t s) {
+  return reduce_impl(M, nullptr, nb, update, lr, s);
+}
+
+hipError_t launch_mlp_grad_guarded(const ModelDev& M, const int32_t* active, const uint16_t* feat,
+                                   const float* target, int64_t nb, hipStream_t s) {
+  return grad_impl(M, active, feat, target, nb, nb, 0, 0, 0, s);
+}
+
+hipError_t launch_mlp_reduce_guarded(const ModelDev& M, const int32_t* active, int64_t nb, float lr, hipStream_t s) {
+  return reduce_impl(M, active, nb, 1, lr, s);
 }
 
 hipError_t launch_mlp_bf16_copy(const ModelDev& M, hipStream_t s) {

@@ -851,7 +851,114 @@ __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ 
   if (threadIdx.x == 0) write_result(xhat, sc, j, found, best, bestp, xb);
 }
 
+// ---------------------------------------------------------------------------
+// k_subset: exact best shift of the columns of a proposal set, one workgroup
+// per column, with the same per-entry arithmetic as the full pass (flip sum,
+// counting sort into bins, or LDS bitonic sort, scan and argmax).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_subset(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  if (st->k >= st->iters || L.ls->idle) return;
+  if ((int)blockIdx.x >= L.ls->tk[0].count) return;
+  __shared__ double spos[kSubsetCap];
+  __shared__ double sdel[kSubsetCap];
+  __shared__ int smk[kSubsetCap];
+  __shared__ int scount;
+  __shared__ double red[8];
+  __shared__ int redk[8];
+  __shared__ unsigned long long scand;
+  const int q = L.sel[0][blockIdx.x];
+  const uint8_t cls = L.cls[q];
+  const double eps = P.eps;
+  const double xb = C.x[q];
+  const int tid = threadIdx.x;
+  if (cls == SUB_FLIP) {
+    const double xn = 1.0 - xb;
+    const double d = xn - xb;
+    double v = 0.0;
+    for (int e = P.col_ptr[q] + tid; e < P.col_ptr[q + 1]; e += blockDim.x) {
+      const RowState r = C.rs[P.col_row[e]];
+      const double r2 = r.r + P.col_val[e] * d;
+      v += penalty(r.r, r2, (double)r.w0, eps);
+      if (r.w1 >= 0.0f) v += penalty(-r.r, -r2, (double)r.w1, eps);
+    }
+    v = block_sum256(v, red);
+    if (tid == 0) {
+      if (st->cut_active && P.obj[q] != 0.0) v += penalty(st->rc, st->rc + P.obj[q] * d, (double)st->wc, eps);
+      write_result(C.xhat, C.s, q, true, v, xn, xb);
+    }
+    return;
+  }
+  if (cls == SUB_NARROW) {
+    double* bins = spos;
+    const double l = P.lb[q], u = P.ub[q];
+    const int W = (int)(u - l) + 1;
+    if (tid < kNarrowBins) bins[tid] = 0.0;
+    if (tid == 0) scand = 0ull;
+    __syncthreads();
+    double beta = 0.0, alpha = 0.0;
+    unsigned long long cand = 0ull;
+    for (int e = P.col_ptr[q] + tid; e < P.col_ptr[q + 1]; e += blockDim.x) {
+      const RowState r = C.rs[P.col_row[e]];
+      const double a = P.col_val[e];
+      narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins, beta, alpha, cand);
+      if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins, beta, alpha, cand);
+    }
+    if (tid == 0 && st->cut_active && P.obj[q] != 0.0)
+      narrow_entry(xb, st->rc, P.obj[q], (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
+    cand = wave_or(cand);
+    if ((tid & 63) == 0 && cand) atomicOr(&scand, cand);
+    beta = block_sum256(beta, red);
+    __syncthreads();
+    alpha = block_sum256(alpha, red);
+    __syncthreads();
+    if (tid < kWave) {
+      bool found;
+      double best, bestp;
+      narrow_finish(bins[tid], beta, alpha, scand, xb, l, W, tid, found, best, bestp);
+      if (tid == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
+    }
+    return;
+  }
+  // general column
+  if (tid == 0) scount = 0;
+  __syncthreads();
+  double beta = 0.0, alpha = 0.0;
+  general_phase1(P, C.rs, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
+    const int k = atomicAdd(&scount, 1);
+    spos[k] = p;
+    smk[k] = m;
+    sdel[k] = d;
+  });
+  beta = block_sum256(beta, red);
+  alpha = block_sum256(alpha, red);
+  __syncthreads();
+  const int cnt = scount;
+  int cap = 64;
+  while (cap < cnt) cap <<= 1;
+  for (int i = cnt + tid; i < cap; i += blockDim.x) {
+    spos[i] = HUGE_VAL;
+    smk[i] = kPadMarker;
+    sdel[i] = 0.0;
+  }
+  __syncthreads();
+  bitonic_sort(spos, smk, sdel, cap);
+  bool found;
+  double best, bestp;
+  scan_argmax(spos, smk, sdel, cap, beta, alpha, xb, P.lb[q], P.ub[q], red, redk, found, best, bestp);
+  if (tid == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
+}
+
 }  // namespace
+
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, int32_t K, hipStream_t s) {
+  if (K > 0) hipLaunchKernelGGL(k_subset, dim3((unsigned)K), dim3(256), 0, s, C, L);
+  return hipGetLastError();
+}
 
 int32_t kernel_blocks(const WalkCtx& c, int slot) {
   const PassPlan& p = c.plan;

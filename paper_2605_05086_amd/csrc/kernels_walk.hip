@@ -275,38 +275,14 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
   }
 }
 
-// One workgroup: finishes the argmax over the partial records, then the
-// tabu/aspiration decision. A tabu overall best is taken only if its move
-// leaves no violated row; since a move changes at most one violation per
-// normalised entry of its column, that is impossible while V exceeds the
-// column's entry count, and the column is only scanned otherwise.
-__global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walks) {
-  const WalkCtx& C = walks[blockIdx.x];
-  const DevProblem& P = C.P;
-  const double* x = C.x;
-  const double* xhat = C.xhat;
-  const double* s = C.s;
-  const RowState* rs = C.rs;
-  const int32_t* tabu = C.tabu;
-  WalkState* st = C.st;
-  chap_trace_record* trace = C.trace;
-  const double* partial = C.argmax_partial;
-  const int32_t nparts = C.argmax_blocks;
-  if (st->k >= st->iters) return;
+// Reduces the per-thread bests of a workgroup (every thread gets the result).
+__device__ __forceinline__ void block_best(Best& ba, Best& bn) {
   __shared__ double sa_s[4], sn_s[4];
   __shared__ int ja_s[4], jn_s[4], qa_s[4], qn_s[4];
-  __shared__ long long red[4];
-  const double eps = P.eps;
-  const int64_t k = st->k;
-  Best ba, bn;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    const double* rec = partial + kPartialStride * b;
-    ba.offer(rec[0], (int)rec[1], (int)rec[2]);
-    bn.offer(rec[3], (int)rec[4], (int)rec[5]);
-  }
   ba.wave_reduce();
   bn.wave_reduce();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0) {
     sa_s[wv] = ba.s;
     ja_s[wv] = ba.j;
@@ -320,10 +296,30 @@ __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walk
     ba.offer(sa_s[w], ja_s[w], qa_s[w]);
     bn.offer(sn_s[w], jn_s[w], qn_s[w]);
   }
+}
+
+// Tabu/aspiration decision of one workgroup from the best positive score
+// overall (ba) and among non-tabu columns (bn). A tabu overall best is taken
+// only if its move leaves no violated row; since a move changes at most one
+// violation per normalised entry of its column, that is impossible while V
+// exceeds the column's entry count, and the column is only scanned
+// otherwise. Without a move the kind is `none_kind` (a reweight for the full
+// pass); moves get `kind_offset` added. Writes the chosen step and trace
+// record; returns the kind.
+__device__ int decide(const WalkCtx& C, const Best& ba, const Best& bn, int none_kind, int kind_offset) {
+  __shared__ long long red[4];
+  const DevProblem& P = C.P;
+  const double* x = C.x;
+  const double* xhat = C.xhat;
+  const double* s = C.s;
+  const RowState* rs = C.rs;
+  WalkState* st = C.st;
+  const double eps = P.eps;
+  const int64_t k = st->k;
   const int qa = (ba.j == INT_MAX) ? -1 : ba.q;
   const int qn = (bn.j == INT_MAX) ? -1 : bn.q;
-  int qstar = -1, jstar = -1, kind = 2;
-  if (qa >= 0 && k > (int64_t)tabu[qa]) {
+  int qstar = -1, jstar = -1, kind = none_kind;
+  if (qa >= 0 && k > (int64_t)C.tabu[qa]) {
     qstar = qa;
     jstar = ba.j;
     kind = 0;
@@ -355,7 +351,8 @@ __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walk
       kind = 0;
     }
   }
-  if (threadIdx.x != 0) return;
+  if (qstar >= 0) kind += kind_offset;
+  if (threadIdx.x != 0) return kind;
   st->j_all = (qa >= 0) ? ba.j : -1;
   st->s_all = ba.s;
   st->j_nt = (qn >= 0) ? bn.j : -1;
@@ -363,7 +360,7 @@ __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walk
   st->copy_best = 0;
   st->mv_j = qstar;
   st->mv_kind = kind;
-  chap_trace_record* t = trace + k;
+  chap_trace_record* t = C.trace + k;
   t->iter = k;
   t->var = jstar;
   t->kind = kind;
@@ -381,6 +378,59 @@ __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walk
     t->x_old = 0.0;
     t->x_new = 0.0;
     t->score = 0.0;
+  }
+  return kind;
+}
+
+// One workgroup per walk: finishes the argmax over the partial records, then
+// the tabu/aspiration decision.
+__global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walks) {
+  const WalkCtx& C = walks[blockIdx.x];
+  const double* partial = C.argmax_partial;
+  const int32_t nparts = C.argmax_blocks;
+  if (C.st->k >= C.st->iters) return;
+  Best ba, bn;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    const double* rec = partial + kPartialStride * b;
+    ba.offer(rec[0], (int)rec[1], (int)rec[2]);
+    bn.offer(rec[3], (int)rec[4], (int)rec[5]);
+  }
+  block_best(ba, bn);
+  decide(C, ba, bn, 2, 0);
+}
+
+// Move choice of a proposal iteration over the proposal set, same rules as
+// k_select. Without an admissible move the iteration is a stall (no
+// reweight) and the block's remaining proposal iterations do nothing.
+__global__ __launch_bounds__(256) void k_subset_select(const WalkCtx* __restrict__ walks,
+                                                       const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  WalkState* st = C.st;
+  if (st->k >= st->iters) return;
+  if (L.ls->idle) {
+    if (threadIdx.x == 0) st->skip = 1;
+    return;
+  }
+  const int64_t k = st->k;
+  const int cnt = L.ls->tk[0].count;
+  Best ba, bn;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int q = L.sel[0][i];
+    const double v = C.s[q];
+    if (!(v > 0.0)) continue;
+    const int j = C.P.perm[q];
+    ba.offer(v, j, q);
+    if (k > (int64_t)C.tabu[q]) bn.offer(v, j, q);
+  }
+  block_best(ba, bn);
+  const int kind = decide(C, ba, bn, kStallKind, kProposalKind);
+  if (threadIdx.x == 0) {
+    st->skip = 0;
+    if (kind == kStallKind) {
+      L.ls->stalls += 1;
+      L.ls->idle = 1;
+    }
   }
 }
 
@@ -412,7 +462,7 @@ __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks
   RowState* rs = C.rs;
   WalkState* st = C.st;
   const int32_t recompute = C.recompute;
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->skip || st->mv_kind == kStallKind) return;
   __shared__ long long red[4];
   const double eps = P.eps;
   const int jstar = st->mv_j;
@@ -450,7 +500,7 @@ __global__ void k_finish(const WalkCtx* __restrict__ walks) {
   int32_t* tabu = C.tabu;
   WalkState* st = C.st;
   chap_trace_record* trace = C.trace;
-  if (threadIdx.x != 0 || st->k >= st->iters) return;
+  if (threadIdx.x != 0 || st->k >= st->iters || st->skip) return;
   const double eps = P.eps;
   const int64_t k = st->k;
   const int jstar = st->mv_j;
@@ -466,7 +516,7 @@ __global__ void k_finish(const WalkCtx* __restrict__ walks) {
     if (c != 0.0) st->f = st->f + c * d;
     x[jstar] = st->mv_new;
     tabu[jstar] = (int32_t)(k + st->tenure);
-  } else if (st->cut_active && st->rc > eps) {
+  } else if (st->mv_kind != kStallKind && st->cut_active && st->rc > eps) {
     st->wc = st->wc + 1.0f;
   }
   st->dV = 0ull;
@@ -547,12 +597,32 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
   return hipGetLastError();
 }
 
-hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream) {
+hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream) {
   const int nw = L.nw;
   hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw);
   hipLaunchKernelGGL(k_select, dim3((unsigned)nw), dim3(256), 0, stream, L.walks);
-  hipLaunchKernelGGL(k_apply, dim3((unsigned)L.total[KS_APPLY]), dim3(256), 0, stream, L.walks, L.off[KS_APPLY], nw);
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)nw), dim3(64), 0, stream, L.walks);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_apply(const BatchLaunch& L, hipStream_t stream) {
+  hipLaunchKernelGGL(k_apply, dim3((unsigned)L.total[KS_APPLY]), dim3(256), 0, stream, L.walks, L.off[KS_APPLY], L.nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_finish(const BatchLaunch& L, hipStream_t stream) {
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)L.nw), dim3(64), 0, stream, L.walks);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream) {
+  hipError_t e = launch_walk_choose(L, stream);
+  if (e == hipSuccess) e = launch_walk_apply(L, stream);
+  if (e == hipSuccess) e = launch_walk_finish(L, stream);
+  return e;
+}
+
+hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s) {
+  hipLaunchKernelGGL(k_subset_select, dim3(1), dim3(256), 0, s, C, L);
   return hipGetLastError();
 }
 

@@ -1,0 +1,223 @@
+"""GPU parity of the learned proposal form against the CPU oracle.
+
+* network inputs at a given state against oracle/features.py (integer data:
+  bit-exact);
+* with full_every = 1 the learned walk is the plain walk, record for record;
+* every learned walk replays exactly in the oracle given its logged proposal
+  sets (the sets are the network's choice; everything else is unique);
+* each logged set is a valid top-K of the reference network scores at its
+  iteration, within the FP32 accumulation bound of oracle/mlp.py.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import mipgen
+import oracle
+from oracle import features as F
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def chap():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2605_05086_amd as c
+
+    c.load_library()
+    return c
+
+
+def dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def bf16_values(bits):
+    b = np.asarray(bits).astype(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
+
+
+def compare_traces(g, o, what):
+    """Every field bit-exact except the traced objective, which the walk
+    updates incrementally (f += c_j d) and the oracle sums from scratch: with
+    continuous variables the two differ by rounding (1e-12 relative)."""
+    for f in ("iter", "var", "kind", "x_old", "x_new", "score", "viol"):
+        a, b = g[f], o[f]
+        bad = np.flatnonzero(a != b)
+        assert bad.size == 0, f"{what}: field {f} differs first at iteration {bad[0]}: gpu {a[bad[0]]} oracle {b[bad[0]]}"
+    np.testing.assert_allclose(g["obj"], o["obj"], rtol=1e-12, atol=1e-9, err_msg=what)
+
+
+def random_state(mip, P, seed, k):
+    rng = np.random.default_rng(seed)
+    lb, ub, _ = P.bounds()
+    x = mipgen.random_point(mip, seed)
+    xh = mipgen.random_point(mip, seed + 1)
+    w = rng.integers(1, 6, P.mp + 1).astype(np.float32)
+    s_last = rng.integers(-8, 9, mip.n).astype(np.float64)
+    last_move = rng.integers(-1024, k, mip.n).astype(np.int32)
+    moves = rng.integers(0, 40, mip.n).astype(np.int32)
+    return x, w, s_last, xh, last_move, moves
+
+
+@pytest.mark.parametrize("seed,cut", [(0, False), (1, True), (2, False)])
+def test_features_parity(chap, seed, cut):
+    import torch
+    mip = mipgen.random_mixed(300 + seed, n=300, m=200, max_row_nnz=8, int_width=40, long_cols=2, long_deg=60,
+                              inf_bounds=0.1)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    k, klf = 100, 90
+    x, w, s_last, xh, lm, mv = random_state(mip, P, seed, k)
+    cutoff = float(np.floor(mip.obj @ x)) - 2.0 if cut else math.inf
+    say(f"features seed={seed} cut={cut}")
+    out = chap.features(G, dev(x, torch.float64), dev(w, torch.float32), cutoff, dev(s_last, torch.float64),
+                        dev(xh, torch.float64), dev(lm, torch.int32), dev(mv, torch.int32), k, klf)
+    got = bf16_values(out.cpu().numpy())
+    want, ok = F.inputs(mip, P, x, w, cutoff, s_last, xh, lm, mv, k, klf)
+    assert np.array_equal(got[~ok], np.zeros_like(got[~ok]))
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (bad[:5], got[tuple(bad[0])], want[tuple(bad[0])])
+
+
+def test_full_every_one_is_plain(chap):
+    mip = mipgen.random_mixed(410, n=200, m=150, max_row_nnz=8, int_width=30, long_cols=2, long_deg=40)
+    G = chap.Problem(mip)
+    M = chap.Model(1)
+    say("learned full_every=1 vs plain")
+    plain = G.tabu_run(300, 10, 3)
+    lr = chap.learned_run(G, M, 300, 10, 3, full_every=1, topk=16, train_steps=2, train_pairs=32)
+    compare_traces(lr.trace, plain.trace, "learned(F=1) vs plain")
+    np.testing.assert_array_equal(lr.x, plain.x)
+    np.testing.assert_array_equal(lr.w, plain.w)
+    assert lr.evals == 300 and lr.stalls == 0
+
+
+CASES = [
+    # (generator seed, n, m, iters, full_every, topk, train_steps)
+    (420, 200, 150, 400, 8, 16, 0),
+    (421, 300, 200, 500, 16, 32, 2),
+    (422, 120, 100, 300, 4, 8, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"seed{c[0]}-F{c[4]}-K{c[5]}-T{c[6]}")
+def test_learned_walk_replays_exactly(chap, case):
+    gseed, n, m, iters, F_, K, steps = case
+    mip = mipgen.random_mixed(gseed, n=n, m=m, max_row_nnz=8, int_width=30, long_cols=2, long_deg=50)
+    G = chap.Problem(mip)
+    M = chap.Model(gseed)
+    say(f"learned walk {case}")
+    run = chap.learned_run(G, M, iters, 10, 2, full_every=F_, topk=K, train_steps=steps, train_pairs=24, lr=3e-3,
+                           log_sets=1)
+    P = oracle.OracleProblem(mip)
+    ref = P.learned_replay(iters, 10, 2, F_, run.sets, run.set_offsets)
+    compare_traces(run.trace, ref["trace"], f"learned {case}")
+    np.testing.assert_array_equal(run.x, ref["x"])
+    np.testing.assert_array_equal(run.w, ref["w"])
+    assert run.best_obj == ref["best_obj"] and run.cutoff_rhs == ref["cutoff_rhs"]
+    kinds = run.trace["kind"]
+    assert (kinds >= 8).sum() > 0, "no move came from a proposal set"
+    full = np.isin(kinds, [0, 1, 2])
+    assert run.evals == int(full.sum())
+    assert run.stalls == int((kinds == 3).sum())
+    for k in np.flatnonzero(~full):
+        s = run.proposal_set(k)
+        assert 0 < s.size <= K and np.unique(s).size == s.size
+
+
+def test_tiny_binary_learned_replay(chap):
+    mip = mipgen.tiny_binary(0)
+    G = chap.Problem(mip)
+    M = chap.Model(0)
+    say("tiny binary learned walk")
+    run = chap.learned_run(G, M, 1000, 10, 0, full_every=16, topk=32, train_steps=1, train_pairs=16, log_sets=1)
+    ref = oracle.OracleProblem(mip).learned_replay(1000, 10, 0, 16, run.sets, run.set_offsets)
+    compare_traces(run.trace, ref["trace"], "tiny binary learned")
+    assert run.best_obj == ref["best_obj"]
+
+
+def _state_at(P, iters_prefix, F_, sets, offs, seed):
+    """Oracle replay of the first `iters_prefix` iterations."""
+    o = offs[:iters_prefix + 1]
+    return P.learned_replay(iters_prefix, 10, seed, F_, sets, o)
+
+
+def test_proposal_sets_are_top_k(chap):
+    mip = mipgen.random_mixed(430, n=400, m=300, max_row_nnz=8, int_width=30, long_cols=2, long_deg=50)
+    G = chap.Problem(mip)
+    M = chap.Model(5)
+    params = M.get_params().astype(np.float64)
+    F_, K, iters, seed = 8, 24, 60, 4
+    say("proposal sets vs reference scores")
+    run = chap.learned_run(G, M, iters, 10, seed, full_every=F_, topk=K, log_sets=1)
+    P = oracle.OracleProblem(mip)
+    kinds = run.trace["kind"]
+    full_iters = np.flatnonzero(np.isin(kinds, [0, 1, 2]))
+    checked = 0
+    for kstar in (5, 13, 30, 45):
+        if kstar >= iters or np.isin(kinds[kstar], [0, 1, 2]) or kinds[kstar - 1] == 3:
+            continue
+        klf = int(full_iters[full_iters < kstar].max())
+        now = _state_at(P, kstar, F_, run.sets, run.set_offsets, seed)
+        at_full = _state_at(P, klf, F_, run.sets, run.set_offsets, seed)
+        after_full = _state_at(P, klf + 1, F_, run.sets, run.set_offsets, seed)
+        xh, s_last = P.best_shift(at_full["x"], at_full["w"], at_full["cutoff_rhs"])
+        tr = run.trace[:kstar]
+        moved = tr["var"] >= 0
+        last_move = np.full(mip.n, -1024)
+        moves = np.zeros(mip.n, dtype=np.int64)
+        for k in np.flatnonzero(moved):
+            last_move[tr["var"][k]] = k
+            moves[tr["var"][k]] += 1
+        X, ok = F.inputs(mip, P, now["x"], now["w"], now["cutoff_rhs"], s_last, xh, last_move, moves, kstar, klf,
+                         refresh=(after_full["x"], after_full["w"], after_full["cutoff_rhs"]))
+        y, _ = mlp.forward(params, X, True)
+        ey, _ = mlp.forward_bound(params, X)
+        chosen = np.zeros(mip.n, dtype=bool)
+        chosen[run.proposal_set(kstar)] = True
+        assert not (chosen & ~ok).any()
+        assert chosen.sum() == min(K, ok.sum())
+        lo = np.min((y + ey)[chosen])
+        hi = np.max((y - ey)[ok & ~chosen])
+        assert lo >= hi, (kstar, lo, hi)
+        checked += 1
+    assert checked >= 2
+
+
+def test_learned_options_rejected(chap):
+    mip = mipgen.random_mixed(440, n=50, m=40)
+    G = chap.Problem(mip)
+    M = chap.Model(0)
+    for bad in (dict(topk=0), dict(full_every=0), dict(train_pairs=0), dict(lr=0.0), dict(train_steps=-1)):
+        with pytest.raises(chap.ChapError) as e:
+            chap.learned_run(G, M, 10, 10, 0, **bad)
+        assert e.value.code == -1
+
+
+def test_learned_edge_cases(chap):
+    mip = mipgen.random_mixed(450, n=60, m=40, max_row_nnz=6, long_cols=1, long_deg=30)
+    G = chap.Problem(mip)
+    M = chap.Model(2)
+    P = oracle.OracleProblem(mip)
+    for iters, F_, K in ((0, 8, 4), (1, 8, 4), (7, 64, 4), (40, 5, 1000), (40, 3, 1)):
+        say(f"learned edge iters={iters} F={F_} K={K}")
+        run = chap.learned_run(G, M, iters, 5, 1, full_every=F_, topk=K, log_sets=1)
+        assert run.trace.shape[0] == iters
+        if iters == 0:
+            continue
+        ref = P.learned_replay(iters, 5, 1, F_, run.sets, run.set_offsets)
+        compare_traces(run.trace, ref["trace"], f"edge iters={iters} F={F_} K={K}")
