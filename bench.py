@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="reduced instance for quick checks")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference for HBM counters)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the learned-proposal and batched-walk comparisons against the plain walk")
+    ap.add_argument("--batch-iters", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path does not "
@@ -155,10 +158,104 @@ def main():
                      "kernel": "best-shift pass (k_short + k_narrow_pack + k_narrow_chunk + k_narrow_combine)",
                      "bytes_per_launch": B},
     }
+    if not args.no_compare:
+        result["learned"] = compare_learned(chap, G, tr, wall, args.steps, tenure, seed)
+        del G
+        result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations")
         result["cpu_baseline"] = cpu_baseline(mip, args.cpu_iters)
     print(json.dumps(result), flush=True)
+
+
+def compare_learned(chap, G, plain_trace, plain_wall, steps, tenure, seed):
+    """Learned proposal against the plain walk on the same instance and start
+    point: violation reduction per second at equal final score. The network
+    is trained beforehand (not timed) on pairs logged by a plain walk from
+    another start point (seed + 7)."""
+    import torch
+
+    v0 = int(plain_trace["viol"][0])
+    vp = int(plain_trace["viol"][-1])
+    t0 = time.perf_counter()
+    M = chap.Model(0)
+    logrun = chap.learned_run(G, M, 100, tenure, seed + 7, full_every=1, topk=1024, train_pairs=1024,
+                              log_pairs=100 * 2048)
+    feat = torch.from_numpy(logrun.pair_feat.view(np.int16)).cuda()
+    tgt = torch.from_numpy(logrun.pair_target).cuda()
+    M.train(feat, tgt, steps=1000, batch=1024, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    opts = dict(full_every=64, topk=1024)
+    chap.learned_run(G, M, 64, tenure, seed, **opts)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = chap.learned_run(G, M, steps, tenure, seed, **opts)
+    torch.cuda.synchronize()
+    lwall = time.perf_counter() - t0
+    viol = run.trace["viol"]
+    reach = np.flatnonzero(viol <= vp)
+    out = {"instance": "the same 20M-nonzero instance and start point", "iters": steps,
+           "options": dict(opts, train_steps=0), "ms_per_iter": lwall * 1e3 / steps,
+           "plain_ms_per_iter": plain_wall * 1e3 / steps, "final_viol": int(viol[-1]), "plain_final_viol": vp,
+           "judge_hits": run.hits, "judge_evals": run.evals, "stalls": run.stalls,
+           "training": f"1000 Adam steps (batch 1024, lr 1e-3) on {logrun.pair_target.shape[0]} pairs from 100 "
+                       f"full evaluations of a plain walk from seed {seed + 7}; {train_s:.1f} s, not timed"}
+    if reach.size:
+        it = int(reach[0]) + 1
+        t0 = time.perf_counter()
+        again = chap.learned_run(G, M, it, tenure, seed, **opts)
+        torch.cuda.synchronize()
+        treach = time.perf_counter() - t0
+        assert int(again.trace["viol"][-1]) <= vp
+        out.update({"iters_to_plain_final": it, "seconds_to_plain_final": treach, "plain_seconds": plain_wall,
+                    "violation_reduction_per_s": {"plain": (v0 - vp) / plain_wall, "learned": (v0 - vp) / treach},
+                    "speedup_at_equal_final_score": plain_wall / treach})
+    else:
+        out.update({"iters_to_plain_final": None, "speedup_at_equal_final_score": None})
+    log(f"learned: {out['ms_per_iter']:.3f} ms/iter, reaches plain final at {out['iters_to_plain_final']}, "
+        f"speedup {out['speedup_at_equal_final_score']}")
+    return out
+
+
+def compare_batched(chap, iters, tenure, small):
+    """256 walks over the pool of general instances (walk w on instance
+    w mod P, start seed w + 1) as one batch, against the same walks run one by
+    one. Both give identical trajectories (same final score); the ratio of
+    GPU times is the speedup at equal final score."""
+    import torch
+
+    import mipgen
+
+    t0 = time.perf_counter()
+    pool = mipgen.batch_pool(total_nnz=2_000_000 if small else 20_000_000)
+    probs = [chap.Problem(m) for m in pool]
+    nw = 256
+    wp = np.arange(nw) % len(pool)
+    ws = np.arange(nw) + 1
+    log(f"batch pool: {len(pool)} instances, {sum(m.nnz for m in pool)} nonzeros, set up in "
+        f"{time.perf_counter() - t0:.1f} s")
+    chap.batch_run(probs, wp, ws, 4, tenure)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = chap.batch_run(probs, wp, ws, iters, tenure)
+    bwall = time.perf_counter() - t0
+    bms = runs[0].elapsed_ms
+    pms = 0.0
+    pwall = 0.0
+    same = True
+    for w in range(nw):
+        t0 = time.perf_counter()
+        r = probs[wp[w]].tabu_run(iters, tenure, int(ws[w]))
+        pwall += time.perf_counter() - t0
+        pms += r.elapsed_ms
+        same = same and np.array_equal(r.trace, runs[w].trace)
+    out = {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
+           "batched_gpu_ms": bms, "plain_gpu_ms_sum": pms, "batched_wall_s": bwall, "plain_wall_s": pwall,
+           "identical_trajectories": bool(same), "speedup_at_equal_final_score": pms / bms,
+           "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3), "plain": nw * iters / (pms * 1e-3)}}
+    log(f"batched: {bms:.1f} ms vs plain {pms:.1f} ms (GPU graphs), identical={same}")
+    return out
 
 
 if __name__ == "__main__":

@@ -300,9 +300,11 @@ int chap_model_train(chap_model *m, const uint16_t *d_feat, const float *d_targe
  * Trace kinds: 0/1/2 as chap_tabu_run for full evaluations; 8 (move) and
  * 9 (move by aspiration) for proposal iterations; 3 for a stall.
  *
- * Proposable columns: those whose breakpoints fit one workgroup (normalised
- * entries + 2 bounds + cutoff entry <= 4096). Longer columns are scored only
- * by the full evaluations.
+ * Proposable columns: binaries and integer columns with finite bounds and at
+ * most 64 values, at any length; other columns when their breakpoints fit
+ * one workgroup (normalised entries + 2 bounds + cutoff entry <= 4096).
+ * Longer general columns are scored only by the full evaluations.
+ * topk and train_pairs are at most 8192.
  *
  * Network inputs of column j (index: meaning), each computed in FP64 and
  * rounded once to bfloat16:

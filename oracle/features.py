@@ -25,8 +25,10 @@ the objective cutoff row is excluded), each value rounded once to bfloat16:
   15 log2(1 + moves)
 
 A row is violated when its residual exceeds eps. A column is proposable when
-its normalised entries, plus one for a nonzero objective coefficient, plus
-two bounds, number at most 4096; other columns get all-zero rows.
+it is binary, or integer with finite bounds and at most 64 values (any
+length), or when its normalised entries, plus one for a nonzero objective
+coefficient, plus two bounds, number at most 4096; other columns get
+all-zero rows.
 """
 from __future__ import annotations
 
@@ -57,11 +59,13 @@ def column_rows(mip, orig_row, sign):
     return cols
 
 
-def proposable(mip, cols):
+def proposable(mip, cols, lb, ub):
     out = np.zeros(mip.n, dtype=bool)
     for j in range(mip.n):
+        l, u = float(lb[j]), float(ub[j])
+        narrow = bool(mip.is_int[j]) and math.isfinite(l) and math.isfinite(u) and u - l + 1 <= 64
         entries = len(cols[j]) + (1 if mip.obj[j] != 0.0 else 0) + 2
-        out[j] = entries <= SUBSET_CAP
+        out[j] = narrow or entries <= SUBSET_CAP
     return out
 
 
@@ -76,7 +80,7 @@ def inputs(mip, oracle_problem, x, w, cutoff_rhs, s_last, xhat_last, last_move, 
     orig_row, sign = P.norm_rows()
     lb, ub, is_bin = P.bounds()
     cols = column_rows(mip, orig_row, sign)
-    ok = proposable(mip, cols)
+    ok = proposable(mip, cols, lb, ub)
     r_now, V = P.residual(x, cutoff_rhs)
     if refresh is None:
         r_ref, w_ref = r_now, w

@@ -113,6 +113,14 @@ def load_library():
     return lib
 
 
+def _release(fn: str, handle) -> None:
+    """Destroys a handle; a no-op while the interpreter shuts down (module
+    globals may already be gone then)."""
+    lib = _lib
+    if lib is not None and getattr(lib, fn, None) is not None:
+        getattr(lib, fn)(handle)
+
+
 def _check(rc: int):
     if rc != CHAP_OK:
         raise ChapError(rc, load_library().chap_last_error().decode())
@@ -193,7 +201,7 @@ class Run:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            load_library().chap_run_destroy(h)
+            _release("chap_run_destroy", h)
             self._h = None
 
 
@@ -239,7 +247,7 @@ class Problem:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            load_library().chap_problem_destroy(h)
+            _release("chap_problem_destroy", h)
             self._h = None
 
     def norm_row_map(self):
@@ -362,7 +370,7 @@ class Model:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            load_library().chap_model_destroy(h)
+            _release("chap_model_destroy", h)
             self._h = None
 
     @staticmethod

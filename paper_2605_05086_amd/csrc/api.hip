@@ -430,12 +430,20 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     longs.push_back(t);
   }
   P->perm = perm;
-  // learned proposal: columns whose breakpoints fit one workgroup's LDS sort
+  // learned proposal: binaries and narrow columns of any length; general
+  // columns whose breakpoints fit one workgroup's LDS sort
   P->sub_cls.assign(n, SUB_NONE);
+  P->col_entries.assign(n, 0);
+  P->nnz = (int64_t)crow.size();
   for (int32_t q = 0; q < n; ++q) {
     const int32_t j = perm[q];
-    if (ne[j] + 2 > kSubsetCap) continue;
-    P->sub_cls[q] = cls[j] == BIN ? SUB_FLIP : (cls[j] == NARROW ? SUB_NARROW : SUB_GENERAL);
+    P->col_entries[q] = cptr[q + 1] - cptr[q];
+    if (cls[j] == BIN)
+      P->sub_cls[q] = SUB_FLIP;
+    else if (cls[j] == NARROW)
+      P->sub_cls[q] = SUB_NARROW;
+    else if (ne[j] + 2 <= kSubsetCap)
+      P->sub_cls[q] = SUB_GENERAL;
   }
   P->c_max = 0.0;
   for (int32_t j = 0; j < n; ++j) P->c_max = std::max(P->c_max, std::fabs(P->obj[j]));

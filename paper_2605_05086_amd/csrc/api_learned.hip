@@ -17,7 +17,8 @@ int check_options(const chap_learned_options& o) {
   if (o.topk <= 0 || o.full_every <= 0 || o.train_steps < 0 || o.train_pairs <= 0 || !(o.lr > 0.0f) ||
       !std::isfinite(o.lr) || o.log_pairs < 0)
     return fail(CHAP_EINVAL, "chap_learned_run: invalid options");
-  if (o.topk > (1 << 20) || o.train_pairs > (1 << 16)) return fail(CHAP_EINVAL, "chap_learned_run: topk or pairs too large");
+  if (o.topk > kTopkMax || o.train_pairs > kTopkMax)
+    return fail(CHAP_EINVAL, "chap_learned_run: topk and train_pairs must be at most " + std::to_string(kTopkMax));
   return CHAP_OK;
 }
 
@@ -38,6 +39,42 @@ int build_learn_ctx(const chap_problem* p, const chap_learned_options& o, int64_
   L.n_elig = (int32_t)elig.size();
   L.mp = p->mp;
   L.c_max = p->c_max;
+  // refresh work: short columns by lane groups, long ones in chunks
+  {
+    std::vector<int32_t> shorts;
+    std::vector<ChunkTask> chunks;
+    std::vector<ChunkCol> cols;
+    std::vector<int32_t> cptr((size_t)n + 1, 0);  // internal CSC offsets
+    for (int32_t q = 0; q < n; ++q) cptr[q + 1] = cptr[q] + p->col_entries[q];
+    for (int32_t q = 0; q < n; ++q) {
+      if (p->sub_cls[q] == SUB_NONE) continue;
+      const int32_t e = p->col_entries[q];
+      if (e <= kRefreshShort) {
+        shorts.push_back(q);
+        continue;
+      }
+      ChunkCol cc{q, (int32_t)chunks.size(), 0};
+      for (int32_t b = cptr[q]; b < cptr[q + 1]; b += kRefreshChunk) {
+        ChunkTask t{q, b, std::min(cptr[q + 1], b + kRefreshChunk), (int32_t)chunks.size(), 0};
+        chunks.push_back(t);
+      }
+      cc.nparts = (int32_t)chunks.size() - cc.first;
+      cols.push_back(cc);
+    }
+    int32_t* d_short;
+    ChunkTask* d_chunks;
+    ChunkCol* d_cols;
+    CHAP_HIP(A.upload(&d_short, shorts));
+    CHAP_HIP(A.upload(&d_chunks, chunks));
+    CHAP_HIP(A.upload(&d_cols, cols));
+    L.ref_short = d_short;
+    L.n_ref_short = (int32_t)shorts.size();
+    L.ref_chunks = d_chunks;
+    L.n_ref_chunks = (int32_t)chunks.size();
+    L.ref_cols = d_cols;
+    L.n_ref_cols = (int32_t)cols.size();
+    CHAP_HIP(A.alloc(&L.ref_parts, std::max<size_t>(chunks.size(), 1)));
+  }
   CHAP_HIP(A.alloc(&L.feat, (size_t)n * 16));
   CHAP_HIP(A.alloc(&L.moves, (size_t)n));
   CHAP_HIP(A.alloc(&L.xhat_last, (size_t)n));
@@ -47,11 +84,15 @@ int build_learn_ctx(const chap_problem* p, const chap_learned_options& o, int64_
   CHAP_HIP(hipMemset(L.hist, 0, sizeof(uint32_t) * 2 * 3 * kRadixBins));
   L.nwg = std::max<int32_t>(1, (n + kTopkChunk - 1) / kTopkChunk);
   CHAP_HIP(A.alloc(&L.wg_cnt, (size_t)2 * L.nwg * 2));
-  CHAP_HIP(A.alloc(&L.wg_base, (size_t)2 * L.nwg * 2));
   L.K[0] = o.topk;
   L.K[1] = o.train_pairs;
   CHAP_HIP(A.alloc(&L.sel[0], (size_t)L.K[0]));
   CHAP_HIP(A.alloc(&L.sel[1], (size_t)L.K[1]));
+  // subset-pass chunks: at most sum over the selected columns of
+  // ceil(entries / kSubsetChunk) <= nnz / kSubsetChunk + K
+  L.sub_cap = (int32_t)std::min<int64_t>(INT32_MAX, p->nnz / kSubsetChunk + L.K[0] + 1);
+  CHAP_HIP(A.alloc(&L.sub_off, (size_t)L.K[0] + 1));
+  CHAP_HIP(A.alloc(&L.sub_parts, (size_t)L.sub_cap));
   L.T = o.train_pairs;
   CHAP_HIP(A.alloc(&L.pair_feat, (size_t)2 * L.T * 16));
   CHAP_HIP(A.alloc(&L.pair_tgt, (size_t)2 * L.T));
@@ -76,7 +117,8 @@ int build_learn_ctx(const chap_problem* p, const chap_learned_options& o, int64_
 }
 
 hipError_t capture_block(const BatchLaunch& BL, const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh,
-                         const ModelDev& M, const chap_learned_options& o, int32_t n, hipStream_t s) {
+                         const ModelDev& M, const chap_learned_options& o, int32_t n, int has_general,
+                         hipStream_t s) {
   hipError_t e = launch_learn_begin(C, L, s);
   // full evaluation: exact pass, judge set, training, move, row refresh
   if (e == hipSuccess) e = launch_pass(BL, s);
@@ -85,17 +127,14 @@ hipError_t capture_block(const BatchLaunch& BL, const WalkCtx* C, const LearnCtx
   if (e == hipSuccess) e = launch_walk_choose(BL, s);
   if (e == hipSuccess) e = launch_learn_judge(C, L, s);
   if (e == hipSuccess) e = launch_walk_apply(BL, s);
-  if (e == hipSuccess) e = launch_learn_move(C, L, s);
   if (e == hipSuccess) e = launch_walk_finish(BL, s);
   if (e == hipSuccess) e = launch_learn_refresh(C, L, Lh, s);
   // proposal iterations
   for (int32_t t = 1; t < o.full_every && e == hipSuccess; ++t) {
     if (Lh.n_elig > 0) e = launch_learn_propose(C, L, Lh, M, n, 0, s);
-    if (e == hipSuccess) e = launch_learn_copy_best(C, L, n, s);
-    if (e == hipSuccess) e = launch_subset_pass(C, L, std::min<int32_t>(o.topk, std::max(Lh.n_elig, 1)), s);
+    if (e == hipSuccess && Lh.n_elig > 0) e = launch_subset_pass(C, L, Lh, has_general, s);
     if (e == hipSuccess) e = launch_subset_select(C, L, s);
     if (e == hipSuccess) e = launch_walk_apply(BL, s);
-    if (e == hipSuccess) e = launch_learn_move(C, L, s);
     if (e == hipSuccess) e = launch_walk_finish(BL, s);
   }
   return e;
@@ -177,7 +216,9 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
   if (iters > 0) {
     hipGraph_t graph;
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const hipError_t cap_err = capture_block(BL, dC, dL, Lh, m->dev, o, n, s);
+    int has_general = 0;
+    for (uint8_t c : p->sub_cls) has_general |= (c == SUB_GENERAL) ? 1 : 0;
+    const hipError_t cap_err = capture_block(BL, dC, dL, Lh, m->dev, o, n, has_general, s);
     const hipError_t end_err = hipStreamEndCapture(s, &graph);
     if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));
     if (end_err != hipSuccess) return fail(CHAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(end_err));

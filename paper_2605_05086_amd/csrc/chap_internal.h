@@ -314,31 +314,30 @@ hipError_t launch_mlp_grad_guarded(const ModelDev& M, const int32_t* active, con
 hipError_t launch_mlp_reduce_guarded(const ModelDev& M, const int32_t* active, int64_t nb, float lr, hipStream_t s);
 
 // ---- learned candidate proposal (kernels_learned.hip) ---------------------
-constexpr int kRadixBins = 2048;   // radix-select digit bins (11, 11, 10 bits)
-constexpr int kTopkChunk = 4096;   // columns per workgroup of the top-k compaction
-constexpr int kSubsetCap = 4096;   // breakpoint capacity of the subset best-shift workgroup
-constexpr int kStallKind = 3;      // trace kind of a proposal iteration without a move
-constexpr int kProposalKind = 8;   // added to the kind of a move chosen from a proposal set
+constexpr int kRadixBins = 2048;    // radix-select digit bins (11, 11, 10 bits)
+constexpr int kTopkChunk = 4096;    // columns per workgroup of the top-K compaction
+constexpr int kTopkMax = 8192;      // largest proposal set
+constexpr int kSubsetCap = 4096;    // breakpoint capacity of the subset sort workgroup
+constexpr int kSubsetChunk = 1024;  // stored entries per workgroup chunk of the subset pass
+constexpr int kSubsetGrid = 2048;   // workgroups of the subset chunk kernel (grid-stride)
+constexpr int kRefreshShort = 64;   // stored entries up to which 8 lanes refresh a column
+constexpr int kRefreshChunk = 4096; // stored entries per workgroup chunk of the long-column refresh
+constexpr int kStallKind = 3;       // trace kind of a proposal iteration without a move
+constexpr int kProposalKind = 8;    // added to the kind of a move chosen from a proposal set
 
-// Per-column proposal class (internal order).
+// Per-column proposal class (internal order): binaries and narrow integer
+// columns of any length (chunked subset pass), general columns whose
+// breakpoints fit one workgroup's LDS sort.
 enum : uint8_t { SUB_NONE = 0, SUB_FLIP = 1, SUB_NARROW = 2, SUB_GENERAL = 3 };
 
-// Input slots of a stored feature row (16 bfloat16 values per column):
-// slots 0..11 hold network inputs 0..11, slots 12..13 the int32 iteration of
-// the column's last move, slot 14 is unused and slot 15 holds input 15.
-// Inputs 12..14 are computed when a row is read.
 struct TopkState {
-  uint32_t prefix;     // digits chosen so far
-  int32_t remaining;   // entries still to take under that prefix
-  uint32_t thresh;     // final key T (0: take every nonzero key)
-  int32_t need_eq;     // entries with key == T to take, lowest column first
-  int32_t count;       // entries selected
-  int32_t done;        // 1 once the threshold is final
+  int32_t count;   // entries selected
+  int32_t chunks;  // subset-pass chunks of the selected columns (proposal set only)
 };
 
 struct LearnState {
   int32_t idle;          // the rest of this block's proposal iterations do nothing
-  int32_t train_active;  // the block's full evaluation trains the network
+  int32_t train_active;  // the block's full evaluation ran: train, refresh the rows
   int64_t k_last_full;   // iteration of the last full evaluation
   int64_t evals;         // full evaluations
   int64_t hits;          // full evaluations whose move was in the network's proposal set
@@ -348,22 +347,43 @@ struct LearnState {
   TopkState tk[2];       // 0: proposal set, 1: training labels
 };
 
+// Partial sums of one refresh chunk: sum w, sum w (violated), violated rows,
+// rows, sum |a|, sum |a| min(r, 1000) (violated).
+struct __align__(16) RefreshPart {
+  double v[6];
+};
+
+// Stored feature rows (16 bfloat16 per column): slots 0..11 hold network
+// inputs 0..11, slots 12..13 the int32 iteration of the column's last move,
+// slot 14 is unused and slot 15 holds input 15. Inputs 12..14 are computed
+// when a row is read.
 struct LearnCtx {
   const uint8_t* cls;        // SUB_* per internal column
   const int32_t* elig_list;  // internal indices of proposable columns
   int32_t n_elig;
   int32_t mp;                // normalised rows (for the violated fraction)
   double c_max;              // max |c_j| (0 when c = 0)
+  // row refresh work: short proposable columns, chunks of long ones
+  const int32_t* ref_short;
+  int32_t n_ref_short;
+  int32_t n_ref_chunks;
+  const ChunkTask* ref_chunks;
+  const ChunkCol* ref_cols;
+  int32_t n_ref_cols;
+  int32_t pad0;
+  RefreshPart* ref_parts;
   uint16_t* feat;            // n x 16 stored rows
   int32_t* moves;            // moves per column
   double* xhat_last;         // best shift at the last full evaluation
   uint32_t* keys[2];         // 0: network scores, 1: labels
   uint32_t* hist;            // 2 x 3 x kRadixBins
   int32_t* wg_cnt;           // 2 x nwg x 2 (greater, equal)
-  int32_t* wg_base;          // 2 x nwg x 2
   int32_t* sel[2];           // selected columns, ascending internal index
   int32_t K[2];
   int32_t nwg;               // workgroups of the compaction
+  int32_t sub_cap;           // capacity of sub_parts
+  int32_t* sub_off;          // K[0] + 1 chunk offsets of the selected columns
+  ChunkPartial* sub_parts;   // per-chunk partial bins of the subset pass
   uint16_t* pair_feat;       // 2T x 16 training inputs
   float* pair_tgt;           // 2T targets
   uint16_t* log_feat;        // pair log (nullable)
@@ -386,22 +406,24 @@ hipError_t launch_learn_init(const WalkCtx* C, const LearnCtx* L, const LearnCtx
                              const int32_t* last_move, const int32_t* moves, hipStream_t s);
 hipError_t launch_learn_refresh(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, hipStream_t s);
 hipError_t launch_learn_begin(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
-// Network scores of every column and the proposal set (top K[0]).
+// Network scores of every column and the proposal set (top K[0]); also the
+// pending incumbent copy of the iteration.
 hipError_t launch_learn_propose(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                                 int32_t n, int full_iteration, hipStream_t s);
 // Training pairs of a full evaluation (top T by score + T random) and the
 // network update.
 hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                               int32_t n, int32_t steps, float lr, hipStream_t s);
+// Judge of a full evaluation and the stored-row update of its move.
 hipError_t launch_learn_judge(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
-hipError_t launch_learn_copy_best(const WalkCtx* C, const LearnCtx* L, int32_t n, hipStream_t s);
-hipError_t launch_learn_move(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
 // Materialised inputs of every column at the walk's state (original order).
 hipError_t launch_learn_features_out(const WalkCtx* C, const LearnCtx* L, int32_t n, int64_t k, int64_t k_last_full,
                                      uint16_t* out, hipStream_t s);
 // Exact best shift of the proposal set (kernels_pass.hip).
-hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, int32_t K, hipStream_t s);
-// Move choice over the proposal set (kernels_walk.hip).
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general,
+                              hipStream_t s);
+// Move choice over the proposal set and the stored-row update of its move
+// (kernels_walk.hip).
 hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
 
 }  // namespace chap
@@ -441,8 +463,11 @@ struct chap_problem {
   double* bs_xhat = nullptr;
   double* bs_s = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
-  // learned proposal: SUB_* class per internal column, max |c_j|
+  // learned proposal: SUB_* class and stored entries per internal column,
+  // max |c_j|
   std::vector<uint8_t> sub_cls;
+  std::vector<int32_t> col_entries;
+  int64_t nnz = 0;
   double c_max = 0.0;
   chap::BatchLaunch bs_launch;
   hipEvent_t pass_ev[2] = {nullptr, nullptr};

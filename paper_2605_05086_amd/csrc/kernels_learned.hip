@@ -29,31 +29,26 @@
 // Top-K: scores become order-preserving 32-bit keys (0 = never proposed); a
 // three-digit radix select (11, 11, 10 bits) finds the K-th key, and an
 // order-preserving compaction lists the selected columns in ascending
-// internal index (equal keys: lowest index first).
+// internal index (equal keys: lowest index first). Each kernel of the select
+// re-derives the digits chosen so far from the histograms of the earlier
+// kernels (a few kilobytes from L2), so no single-workgroup kernel sits
+// between them.
 
 #include <climits>
 #include <cmath>
 
 #include "chap_internal.h"
+#include "learned_rows.h"
 #include "mlp_core.h"
 
 namespace chap {
 namespace {
 
 using namespace mlp;
+using namespace learned;
 
 constexpr int kWave = 64;
-constexpr int64_t kAgeCap = 1024;
-constexpr int64_t kNeverMoved = -1024;
-
-// FP64 -> bfloat16 bits, round to nearest even, for magnitudes in FP32's
-// normal range (or zero).
-__device__ __forceinline__ uint16_t d2bf(double d) {
-  unsigned long long b = (unsigned long long)__double_as_longlong(d);
-  b += 0xFFFFFFFFFFFull + ((b >> 45) & 1ull);
-  b &= ~((1ull << 45) - 1ull);
-  return f2bf((float)__longlong_as_double((long long)b));
-}
+constexpr int kBlock = 256;
 
 // Order-preserving key of a finite score; never 0.
 __device__ __forceinline__ uint32_t order_key(float y) {
@@ -61,45 +56,43 @@ __device__ __forceinline__ uint32_t order_key(float y) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
 __device__ __forceinline__ bool active(const WalkState* st, const LearnState* ls) {
   return st->k < st->iters && !ls->idle;
 }
 
-__device__ __forceinline__ double position(double x, double l, double u) {
-  if (!isfinite(l) || !isfinite(u)) return 0.5;
-  if (u > l) return (x - l) / (u - l);
-  return 0.0;
+// Inputs 13 and 14, the same for every column at one iteration.
+struct Globals {
+  short since;  // bfloat16 bits of min(k - k_last_full, 64) / 64
+  short vfrac;  // bfloat16 bits of V / m'
+};
+
+__device__ __forceinline__ Globals globals(int64_t k, int64_t k_last_full, int64_t V, int32_t mp) {
+  Globals G;
+  G.since = (short)d2bf((double)min(k - k_last_full, (int64_t)64) / 64.0);
+  G.vfrac = (short)d2bf((double)V / (double)max(mp, 1));
+  return G;
 }
 
-__device__ __forceinline__ double sign_of(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
-
 // The network inputs of column q in B layout (inputs 4g..4g+3 of this lane's
-// group) at iteration k.
+// group) at iteration k. The tabu age min(k - last, 1024) / 1024 is a
+// multiple of 2^-10 in [0, 1], exact in FP64 before its single rounding.
 __device__ __forceinline__ bf16x4 assemble(const uint16_t* __restrict__ feat, int q, int g, int64_t k,
-                                           int64_t k_last_full, int64_t V, int32_t mp) {
+                                           const Globals& G) {
   const bf16x4 raw = *(const bf16x4*)(feat + (int64_t)q * 16 + 4 * g);
   if (g != 3) return raw;
   const int32_t last = (int32_t)(((uint32_t)(uint16_t)raw[1] << 16) | (uint32_t)(uint16_t)raw[0]);
   const int64_t age = min(k - (int64_t)last, kAgeCap);
-  const int64_t since = min(k - k_last_full, (int64_t)64);
   bf16x4 x;
-  x[0] = (short)d2bf((double)age / (double)kAgeCap);
-  x[1] = (short)d2bf((double)since / 64.0);
-  x[2] = (short)d2bf((double)V / (double)max(mp, 1));
+  x[0] = (short)d2bf((double)age * (1.0 / (double)kAgeCap));
+  x[1] = G.since;
+  x[2] = G.vfrac;
   x[3] = raw[3];
   return x;
 }
 
-__device__ __forceinline__ void set_last_move(uint16_t* row, int32_t k) {
-  row[12] = (uint16_t)((uint32_t)k & 0xFFFFu);
-  row[13] = (uint16_t)((uint32_t)k >> 16);
-}
+// ---------------------------------------------------------------------------
+// Stored rows
+// ---------------------------------------------------------------------------
 
 // Static inputs and initial dynamic state of every column: never moved, or
 // the given last-move iterations and move counts (original order).
@@ -127,73 +120,116 @@ __global__ __launch_bounds__(256) void k_learn_init(const WalkCtx* __restrict__ 
   row[8] = d2bf((isfinite(l) && isfinite(u)) ? log2(1.0 + fmin(u - l, 1048576.0)) : 20.0);
   const int j = P.perm[q];
   const int32_t mv = moves ? moves[j] : 0;
-  set_last_move(row, last_move ? last_move[j] : (int32_t)kNeverMoved);
+  set_last_move(row, last_move ? last_move[j] : kNeverMoved);
   row[15] = d2bf(log2(1.0 + (double)mv));
   L.moves[q] = mv;
   L.xhat_last[q] = C.x[q];
 }
 
-// Row-aggregate inputs of every proposable column at the current point, one
-// wavefront per column (fixed-order sums); also inputs 3, 7, 11 from the
-// last full pass (s, xhat).
-__global__ __launch_bounds__(256) void k_learn_refresh(const WalkCtx* __restrict__ walks,
+// Contributions of stored entry e to the six refresh sums.
+__device__ __forceinline__ void refresh_entry(const DevProblem& P, const RowState* rs, int e, double* v) {
+  const RowState r = rs[P.col_row[e]];
+  const double a = fabs(P.col_val[e]);
+  const double eps = P.eps;
+  v[0] += (double)r.w0;
+  v[3] += 1.0;
+  v[4] += a;
+  if (r.r > eps) {
+    v[1] += (double)r.w0;
+    v[2] += 1.0;
+    v[5] += a * fmin(r.r, 1000.0);
+  }
+  if (r.w1 >= 0.0f) {
+    const double r1 = -r.r;
+    v[0] += (double)r.w1;
+    v[3] += 1.0;
+    v[4] += a;
+    if (r1 > eps) {
+      v[1] += (double)r.w1;
+      v[2] += 1.0;
+      v[5] += a * fmin(r1, 1000.0);
+    }
+  }
+}
+
+// Inputs 0, 3, 7, 9, 10, 11 of column q from its six sums; xhat_last := xhat.
+__device__ __forceinline__ void refresh_write(const WalkCtx& C, const LearnCtx& L, int q, const double* v) {
+  uint16_t* row = L.feat + (int64_t)q * 16;
+  const double sw = v[0], swv = v[1], nv = v[2], ne = v[3], sa = v[4], sav = v[5];
+  const double x = C.x[q], xh = C.xhat[q];
+  row[0] = d2bf(sw > 0.0 ? swv / sw : 0.0);
+  row[3] = d2bf(sw > 0.0 ? fmin(fmax(C.s[q] / sw, -4.0), 4.0) : 0.0);
+  row[7] = d2bf(position(x, C.P.lb[q], C.P.ub[q]));
+  row[9] = d2bf(ne > 0.0 ? nv / ne : 0.0);
+  row[10] = d2bf(sa > 0.0 ? sav / (1000.0 * sa) : 0.0);
+  row[11] = d2bf(sign_of(xh - x));
+  L.xhat_last[q] = xh;
+}
+
+// Short proposable columns: eight lanes per column, fixed-order sums.
+__global__ __launch_bounds__(256) void k_refresh_short(const WalkCtx* __restrict__ walks,
                                                        const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
-  const DevProblem& P = C.P;
   if (!L.ls->train_active) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const double eps = P.eps;
-  for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < L.n_elig; idx += wstride) {
-    const int q = L.elig_list[idx];
-    double sw = 0.0, swv = 0.0, nv = 0.0, ne = 0.0, sa = 0.0, sav = 0.0;
-    const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
-    for (int e = beg + lane; e < end; e += kWave) {
-      const RowState rs = C.rs[P.col_row[e]];
-      const double a = fabs(P.col_val[e]);
-      {
-        const bool v = rs.r > eps;
-        sw += (double)rs.w0;
-        ne += 1.0;
-        sa += a;
-        if (v) {
-          swv += (double)rs.w0;
-          nv += 1.0;
-          sav += a * fmin(rs.r, 1000.0);
-        }
-      }
-      if (rs.w1 >= 0.0f) {
-        const double r1 = -rs.r;
-        const bool v = r1 > eps;
-        sw += (double)rs.w1;
-        ne += 1.0;
-        sa += a;
-        if (v) {
-          swv += (double)rs.w1;
-          nv += 1.0;
-          sav += a * fmin(r1, 1000.0);
-        }
-      }
-    }
-    sw = wsum(sw);
-    swv = wsum(swv);
-    nv = wsum(nv);
-    ne = wsum(ne);
-    sa = wsum(sa);
-    sav = wsum(sav);
-    if (lane == 0) {
-      uint16_t* row = L.feat + (int64_t)q * 16;
-      const double x = C.x[q], xh = C.xhat[q];
-      row[0] = d2bf(sw > 0.0 ? swv / sw : 0.0);
-      row[3] = d2bf(sw > 0.0 ? fmin(fmax(C.s[q] / sw, -4.0), 4.0) : 0.0);
-      row[7] = d2bf(position(x, P.lb[q], P.ub[q]));
-      row[9] = d2bf(ne > 0.0 ? nv / ne : 0.0);
-      row[10] = d2bf(sa > 0.0 ? sav / (1000.0 * sa) : 0.0);
-      row[11] = d2bf(sign_of(xh - x));
-      L.xhat_last[q] = xh;
-    }
+  const int sub = threadIdx.x & 7;
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x >> 3);
+  for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x >> 3) + (threadIdx.x >> 3); idx < L.n_ref_short;
+       idx += groups) {
+    const int q = L.ref_short[idx];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int e = C.P.col_ptr[q] + sub; e < C.P.col_ptr[q + 1]; e += 8) refresh_entry(C.P, C.rs, e, v);
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) v[t] += __shfl_xor(v[t], o, kWave);
+    if (sub == 0) refresh_write(C, L, q, v);
   }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+// Chunks of long proposable columns: one workgroup per chunk (grid-stride),
+// partial sums per chunk.
+__global__ __launch_bounds__(256) void k_refresh_chunks(const WalkCtx* __restrict__ walks,
+                                                        const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  if (!L.ls->train_active) return;
+  __shared__ double red[4];
+  for (int t = blockIdx.x; t < L.n_ref_chunks; t += gridDim.x) {
+    const ChunkTask T = L.ref_chunks[t];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int e = T.e_beg + threadIdx.x; e < T.e_end; e += blockDim.x) refresh_entry(C.P, C.rs, e, v);
+    double out[6];
+    for (int k = 0; k < 6; ++k) out[k] = block_sum(v[k], red);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 6; ++k) L.ref_parts[T.slot].v[k] = out[k];
+  }
+}
+
+// Long proposable columns: sums of their chunks in order.
+__global__ __launch_bounds__(256) void k_refresh_combine(const WalkCtx* __restrict__ walks,
+                                                         const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  if (!L.ls->train_active) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_ref_cols) return;
+  const ChunkCol cc = L.ref_cols[i];
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < cc.nparts; ++k)
+    for (int t = 0; t < 6; ++t) v[t] += L.ref_parts[cc.first + k].v[t];
+  refresh_write(C, L, cc.col, v);
 }
 
 // Start of a block of iterations (full evaluation first).
@@ -213,6 +249,100 @@ __global__ void k_learn_begin(const WalkCtx* __restrict__ walks, const LearnCtx*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Radix top-K
+// ---------------------------------------------------------------------------
+
+struct Select {
+  bool all;          // at most K nonzero keys: take every nonzero key
+  uint32_t prefix;   // digits chosen so far (levels below `upto`)
+  int rem;           // keys still to take under the prefix
+  uint32_t thresh;   // final key T (upto == 3)
+  int need_eq;       // keys == T to take (upto == 3)
+  int count;         // keys selected (upto == 3 or all)
+};
+
+// Whole workgroup (256 threads): the bin of histogram h (bins from the top)
+// that holds the rem-th largest key; *left = rank of that key inside the bin.
+__device__ void find_digit(const uint32_t* __restrict__ h, int rem, int* digit, int* left, uint32_t* total) {
+  __shared__ uint32_t part[kBlock / kWave];
+  __shared__ int res[2];
+  constexpr int per = kRadixBins / kBlock;  // 8 bins per thread, thread 0 the highest
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t c[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int t = 0; t < per; ++t) {
+    c[t] = h[kRadixBins - 1 - (tid * per + t)];
+    sum += c[t];
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) part[wv] = inc;
+  if (tid == 0) {
+    res[0] = 0;
+    res[1] = 0;
+  }
+  __syncthreads();
+  uint32_t before_w = 0, all = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    if (w < wv) before_w += part[w];
+    all += part[w];
+  }
+  const uint32_t hi = before_w + inc, lo = hi - sum;
+  if (lo < (uint32_t)rem && hi >= (uint32_t)rem) {
+    uint32_t cum = lo;
+#pragma unroll
+    for (int t = 0; t < per; ++t) {
+      if (cum < (uint32_t)rem && cum + c[t] >= (uint32_t)rem) {
+        res[0] = kRadixBins - 1 - (tid * per + t);
+        res[1] = rem - (int)cum;
+      }
+      cum += c[t];
+    }
+  }
+  __syncthreads();
+  *digit = res[0];
+  *left = res[1];
+  *total = all;
+  __syncthreads();
+}
+
+// Digits of levels < upto (upto = 3: the final threshold) from the
+// histograms of the earlier kernels. Whole workgroup.
+__device__ Select derive(const LearnCtx& L, int which, int upto) {
+  const uint32_t* H = L.hist + which * 3 * kRadixBins;
+  const int K = L.K[which];
+  Select S{false, 0u, K, 0u, 0, 0};
+  int d, left;
+  uint32_t total;
+  find_digit(H, K, &d, &left, &total);
+  if (total <= (uint32_t)K) {
+    S.all = true;
+    S.count = (int)total;
+    return S;
+  }
+  S.prefix = (uint32_t)d;
+  S.rem = left;
+  if (upto >= 2) {
+    find_digit(H + kRadixBins, S.rem, &d, &left, &total);
+    S.prefix = (S.prefix << 11) | (uint32_t)d;
+    S.rem = left;
+  }
+  if (upto >= 3) {
+    find_digit(H + 2 * kRadixBins, S.rem, &d, &left, &total);
+    S.thresh = (S.prefix << 10) | (uint32_t)d;
+    S.need_eq = left;
+    S.count = K;
+  }
+  return S;
+}
+
 __device__ __forceinline__ void flush_hist(uint32_t* lds, uint32_t* global) {
   __syncthreads();
   for (int b = threadIdx.x; b < kRadixBins; b += blockDim.x) {
@@ -221,7 +351,8 @@ __device__ __forceinline__ void flush_hist(uint32_t* lds, uint32_t* global) {
   }
 }
 
-// Network score key of every column plus the first-digit histogram.
+// Network score key of every column plus the first-digit histogram; also the
+// pending incumbent copy (before this iteration's move changes x).
 __global__ __launch_bounds__(256) void k_learn_score(const WalkCtx* __restrict__ walks,
                                                      const LearnCtx* __restrict__ lc, const float* __restrict__ w,
                                                      const uint16_t* __restrict__ wb, int32_t n) {
@@ -231,24 +362,32 @@ __global__ __launch_bounds__(256) void k_learn_score(const WalkCtx* __restrict__
   if (!active(st, L.ls)) return;
   __shared__ uint32_t hist[kRadixBins];
   for (int b = threadIdx.x; b < kRadixBins; b += blockDim.x) hist[b] = 0;
+  if (st->copy_best)
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) C.best_x[q] = C.x[q];
   __syncthreads();
   Weights W;
   load_weights(wb, w, W);
   const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
-  const int64_t k = st->k, klf = L.ls->k_last_full, V = st->V;
+  const int64_t k = st->k;
+  const Globals Gl = globals(k, L.ls->k_last_full, st->V, L.mp);
   const int ntiles = (n + 15) / 16;
-  for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += gridDim.x * 4) {
+  const int stride = gridDim.x * 4;
+  const bf16x4 zero = {0, 0, 0, 0};
+  int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // the next tile's inputs are loaded before the current tile is computed
+  bf16x4 x = (tile < ntiles && tile * 16 + r < n) ? assemble(L.feat, tile * 16 + r, g, k, Gl) : zero;
+  for (; tile < ntiles; tile += stride) {
     const int q = tile * 16 + r;
-    const bool valid = q < n;
-    const bf16x4 zero = {0, 0, 0, 0};
-    const bf16x4 x = valid ? assemble(L.feat, q, g, k, klf, V, L.mp) : zero;
+    const int qn = q + stride * 16;
+    const bf16x4 xn = (qn < n) ? assemble(L.feat, qn, g, k, Gl) : zero;
     Acts A;
     forward(W, x, A);
-    if (l < 16 && valid) {
+    if (l < 16 && q < n) {
       const uint32_t key = L.cls[q] != SUB_NONE ? order_key(A.y) : 0u;
       L.keys[0][q] = key;
       if (key) atomicAdd(&hist[key >> 21], 1u);
     }
+    x = xn;
   }
   flush_hist(hist, L.hist);
 }
@@ -271,109 +410,39 @@ __global__ __launch_bounds__(256) void k_label_keys(const WalkCtx* __restrict__ 
 }
 
 __device__ __forceinline__ uint32_t digit_of(uint32_t key, int level) {
-  return level == 0 ? (key >> 21) : (level == 1 ? ((key >> 10) & 0x7FFu) : (key & 0x3FFu));
+  return level == 1 ? ((key >> 10) & 0x7FFu) : (key & 0x3FFu);
 }
 
 __device__ __forceinline__ uint32_t prefix_of(uint32_t key, int level) {
   return level == 1 ? (key >> 21) : (key >> 10);
 }
 
-// One digit of the radix select, one wavefront: the digit whose bin holds
-// the remaining K-th largest key. Clears the histogram it read.
-__global__ void k_topk_digit(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc, int32_t which,
-                             int32_t level) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
-  if (!active(C.st, L.ls)) return;
-  TopkState& T = L.ls->tk[which];
-  uint32_t* hist = L.hist + (which * 3 + level) * kRadixBins;
-  const int lane = threadIdx.x;
-  const int per = kRadixBins / kWave;  // 32 bins per lane, lane 0 the highest
-  if (level == 0) {
-    // first digit: the state starts here
-    if (lane == 0) {
-      T.prefix = 0;
-      T.remaining = L.K[which];
-      T.done = 0;
-      T.thresh = 0;
-      T.need_eq = 0;
-    }
-  }
-  __syncthreads();
-  const int rem = T.remaining;
-  const bool done = T.done != 0;
-  uint32_t c[32];
-  uint32_t part = 0;
-  for (int t = 0; t < per; ++t) {
-    c[t] = hist[kRadixBins - 1 - (lane * per + t)];
-    part += c[t];
-  }
-  // inclusive prefix over lanes (highest bins first)
-  uint32_t inc = part;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o, kWave);
-    if (lane >= o) inc += y;
-  }
-  const uint32_t total = __shfl(inc, kWave - 1, kWave);
-  __syncthreads();
-  for (int t = 0; t < per; ++t) hist[kRadixBins - 1 - (lane * per + t)] = 0;
-  if (done) return;
-  if (level == 0 && total < (uint32_t)rem) {
-    // fewer proposable columns than K: take every nonzero key
-    if (lane == 0) {
-      T.thresh = 0;
-      T.need_eq = 0;
-      T.done = 1;
-    }
-    return;
-  }
-  const uint32_t before = inc - part;
-  const bool mine = before < (uint32_t)rem && inc >= (uint32_t)rem;
-  if (mine) {
-    uint32_t cum = before;
-    int d = 0;
-    for (int t = 0; t < per; ++t) {
-      if (cum + c[t] >= (uint32_t)rem) {
-        d = kRadixBins - 1 - (lane * per + t);
-        break;
-      }
-      cum += c[t];
-    }
-    const int left = rem - (int)cum;
-    const int bits = (level == 2) ? 10 : 11;
-    const uint32_t pre = (level == 0) ? (uint32_t)d : ((T.prefix << bits) | (uint32_t)d);
-    T.prefix = pre;
-    T.remaining = left;
-    if (level == 2) {
-      T.thresh = pre;
-      T.need_eq = left;
-      T.done = 1;
-    }
-  }
-}
-
-// Histogram of the next digit over keys that match the chosen prefix.
+// Histogram of digit `level` (1 or 2) over keys that match the digits above.
 __global__ __launch_bounds__(256) void k_topk_hist(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc,
                                                    int32_t which, int32_t level, int32_t n) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
   if (!active(C.st, L.ls)) return;
-  const TopkState& T = L.ls->tk[which];
-  if (T.done) return;
+  const Select S = derive(L, which, level);
+  if (S.all) return;
   __shared__ uint32_t hist[kRadixBins];
   for (int b = threadIdx.x; b < kRadixBins; b += blockDim.x) hist[b] = 0;
   __syncthreads();
-  const uint32_t pre = T.prefix;
   const uint32_t* keys = L.keys[which];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const uint32_t key = keys[q];
-    if (key && prefix_of(key, level) == pre) atomicAdd(&hist[digit_of(key, level)], 1u);
+    if (key && prefix_of(key, level) == S.prefix) atomicAdd(&hist[digit_of(key, level)], 1u);
   }
   flush_hist(hist, L.hist + (which * 3 + level) * kRadixBins);
 }
 
-__device__ __forceinline__ bool above(uint32_t key, uint32_t thresh) { return key != 0u && key > thresh; }
+__device__ __forceinline__ bool take_above(uint32_t key, const Select& S) {
+  return key != 0u && (S.all || key > S.thresh);
+}
+
+__device__ __forceinline__ bool take_equal(uint32_t key, const Select& S) {
+  return !S.all && key == S.thresh;
+}
 
 // Per-workgroup counts of keys above and equal to the threshold.
 __global__ __launch_bounds__(256) void k_topk_count(const WalkCtx* __restrict__ walks,
@@ -381,17 +450,16 @@ __global__ __launch_bounds__(256) void k_topk_count(const WalkCtx* __restrict__ 
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
   if (!active(C.st, L.ls)) return;
+  const Select S = derive(L, which, 3);
   __shared__ int red[8];
-  const TopkState& T = L.ls->tk[which];
-  const uint32_t th = T.thresh;
   const uint32_t* keys = L.keys[which];
   int gt = 0, eq = 0;
   const int beg = blockIdx.x * kTopkChunk;
   const int end = min(n, beg + kTopkChunk);
   for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
     const uint32_t key = keys[q];
-    gt += above(key, th) ? 1 : 0;
-    eq += (th != 0u && key == th) ? 1 : 0;
+    gt += take_above(key, S) ? 1 : 0;
+    eq += take_equal(key, S) ? 1 : 0;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -416,51 +484,46 @@ __global__ __launch_bounds__(256) void k_topk_count(const WalkCtx* __restrict__ 
   }
 }
 
-// Exclusive prefix of the per-workgroup counts (one workgroup).
-__global__ __launch_bounds__(256) void k_topk_scan(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc,
-                                                   int32_t which) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
-  if (!active(C.st, L.ls)) return;
-  if (threadIdx.x != 0) return;
-  TopkState& T = L.ls->tk[which];
-  const int32_t* cnt = L.wg_cnt + (int64_t)which * L.nwg * 2;
-  int32_t* base = L.wg_base + (int64_t)which * L.nwg * 2;
-  int gt = 0, eq = 0;
-  for (int b = 0; b < L.nwg; ++b) {
-    base[2 * b] = gt;
-    base[2 * b + 1] = eq;
-    gt += cnt[2 * b];
-    eq += cnt[2 * b + 1];
-  }
-  T.count = gt + min(eq, T.need_eq);
-}
-
-// Order-preserving compaction of the selected columns.
+// Order-preserving compaction of the selected columns; each workgroup sums
+// the counts of the workgroups before it.
 __global__ __launch_bounds__(256) void k_topk_write(const WalkCtx* __restrict__ walks,
                                                     const LearnCtx* __restrict__ lc, int32_t which, int32_t n) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
   if (!active(C.st, L.ls)) return;
+  const Select S = derive(L, which, 3);
   __shared__ int sg[4], se[4];
-  const TopkState& T = L.ls->tk[which];
-  const uint32_t th = T.thresh;
-  const int need = T.need_eq;
   const uint32_t* keys = L.keys[which];
-  const int32_t* base = L.wg_base + (int64_t)which * L.nwg * 2;
-  const int gt_base = base[2 * blockIdx.x], eq_base = base[2 * blockIdx.x + 1];
-  constexpr int per = kTopkChunk / 256;
+  const int32_t* cnt = L.wg_cnt + (int64_t)which * L.nwg * 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int bg = 0, be = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += blockDim.x) {
+    bg += cnt[2 * b];
+    be += cnt[2 * b + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bg += __shfl_xor(bg, o, kWave);
+    be += __shfl_xor(be, o, kWave);
+  }
+  if (lane == 0) {
+    sg[wv] = bg;
+    se[wv] = be;
+  }
+  __syncthreads();
+  const int gt_base = sg[0] + sg[1] + sg[2] + sg[3];
+  const int eq_base = se[0] + se[1] + se[2] + se[3];
+  __syncthreads();
+  constexpr int per = kTopkChunk / kBlock;
   const int beg = blockIdx.x * kTopkChunk + threadIdx.x * per;
   int gt = 0, eq = 0;
   for (int t = 0; t < per; ++t) {
     const int q = beg + t;
     if (q >= n) break;
     const uint32_t key = keys[q];
-    gt += above(key, th) ? 1 : 0;
-    eq += (th != 0u && key == th) ? 1 : 0;
+    gt += take_above(key, S) ? 1 : 0;
+    eq += take_equal(key, S) ? 1 : 0;
   }
-  // exclusive scans over the workgroup's threads
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int ig = gt, ie = eq;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
@@ -481,20 +544,94 @@ __global__ __launch_bounds__(256) void k_topk_write(const WalkCtx* __restrict__ 
     oe += se[k];
   }
   int eq_rank = eq_base + oe;  // equal keys before this thread's run
-  int pos = gt_base + og + min(eq_rank, need);
+  int pos = gt_base + og + min(eq_rank, S.need_eq);
   int32_t* out = L.sel[which];
   for (int t = 0; t < per; ++t) {
     const int q = beg + t;
     if (q >= n) break;
     const uint32_t key = keys[q];
-    bool take = above(key, th);
-    if (th != 0u && key == th) {
-      take = eq_rank < need;
+    bool take = take_above(key, S);
+    if (take_equal(key, S)) {
+      take = eq_rank < S.need_eq;
       ++eq_rank;
     }
     if (take) out[pos++] = q;
   }
 }
+
+// End of a selection (one workgroup): the selected count; for the proposal
+// set also the subset-pass chunk offsets and the set log; then clears the
+// histograms for the next selection.
+__global__ __launch_bounds__(256) void k_topk_finish(const WalkCtx* __restrict__ walks,
+                                                     const LearnCtx* __restrict__ lc, int32_t which, int32_t full) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  const WalkState* st = C.st;
+  if (!active(st, L.ls)) return;
+  const Select S = derive(L, which, 3);
+  const int cnt = S.count;
+  __shared__ int wsum[4];
+  __shared__ int carry;
+  if (which == 0) {
+    // exclusive prefix of per-column chunk counts, in tiles of 256 columns
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int base = 0; base < cnt; base += kBlock) {
+      const int i = base + threadIdx.x;
+      int c = 0;
+      if (i < cnt) {
+        const int q = L.sel[0][i];
+        const uint8_t cl = L.cls[q];
+        const int e = C.P.col_ptr[q + 1] - C.P.col_ptr[q];
+        c = (cl == SUB_GENERAL) ? 0 : max(1, (e + kSubsetChunk - 1) / kSubsetChunk);
+      }
+      int inc = c;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) wsum[wv] = inc;
+      __syncthreads();
+      int off = carry + inc - c;
+      for (int k = 0; k < wv; ++k) off += wsum[k];
+      if (i < cnt) L.sub_off[i] = off;
+      __syncthreads();
+      if (threadIdx.x == kBlock - 1) carry = off + c;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      L.sub_off[cnt] = carry;
+      L.ls->tk[0].chunks = carry;
+    }
+    // proposal-set log (original indices); a full evaluation records an empty range
+    if (L.set_off != nullptr) {
+      const int64_t k = st->k;
+      const int64_t pos = L.ls->set_pos;
+      const int c2 = full ? 0 : cnt;
+      const bool fits = pos + c2 <= L.set_log_cap;
+      if (fits)
+        for (int i = threadIdx.x; i < c2; i += blockDim.x) L.set_log[pos + i] = C.P.perm[L.sel[0][i]];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int64_t end = fits ? pos + c2 : pos;
+        L.set_off[k] = pos;
+        L.set_off[k + 1] = end;
+        L.ls->set_pos = end;
+      }
+    }
+  }
+  if (threadIdx.x == 0) L.ls->tk[which].count = cnt;
+  // every reader of the histograms has finished (earlier kernels, derive above)
+  __syncthreads();
+  uint32_t* H = L.hist + which * 3 * kRadixBins;
+  for (int b = threadIdx.x; b < 3 * kRadixBins; b += blockDim.x) H[b] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Training pairs, judge, features
+// ---------------------------------------------------------------------------
 
 // Materialised training inputs and targets of a full evaluation: the top T
 // columns by exact score and T random proposable columns; target =
@@ -518,7 +655,8 @@ __global__ __launch_bounds__(256) void k_learn_pairs(const WalkCtx* __restrict__
   if (lane == 0) red[wv] = smax;
   __syncthreads();
   smax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  const int64_t k = st->k, klf = L.ls->k_last_full, V = st->V;
+  const int64_t k = st->k;
+  const Globals Gl = globals(k, L.ls->k_last_full, st->V, L.mp);
   const int64_t logged = L.ls->logged;
   const bool log = L.log_feat != nullptr && logged + T2 <= L.log_cap;
   for (int i = threadIdx.x; i < T2; i += blockDim.x) {
@@ -531,7 +669,7 @@ __global__ __launch_bounds__(256) void k_learn_pairs(const WalkCtx* __restrict__
     L.pair_tgt[i] = (float)tgt;
     if (log) L.log_tgt[logged + i] = (float)tgt;
     for (int gg = 0; gg < 4; ++gg) {
-      const bf16x4 x = assemble(L.feat, q, gg, k, klf, V, L.mp);
+      const bf16x4 x = assemble(L.feat, q, gg, k, Gl);
       for (int t = 0; t < 4; ++t) {
         L.pair_feat[(int64_t)i * 16 + 4 * gg + t] = (uint16_t)x[t];
         if (log) L.log_feat[(logged + i) * 16 + 4 * gg + t] = (uint16_t)x[t];
@@ -542,7 +680,8 @@ __global__ __launch_bounds__(256) void k_learn_pairs(const WalkCtx* __restrict__
   if (threadIdx.x == 0 && log) L.ls->logged = logged + T2;
 }
 
-// Judge of a full evaluation: was its move in the network's proposal set?
+// Judge of a full evaluation (was its move in the network's proposal set?)
+// and the stored-row update of the move.
 __global__ void k_learn_judge(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
@@ -552,6 +691,7 @@ __global__ void k_learn_judge(const WalkCtx* __restrict__ walks, const LearnCtx*
   ls->evals += 1;
   const int q = st->mv_j;
   if (q < 0) return;
+  after_move(C, L);
   const int32_t* set = L.sel[0];
   int lo = 0, hi = ls->tk[0].count - 1;
   while (lo <= hi) {
@@ -567,56 +707,6 @@ __global__ void k_learn_judge(const WalkCtx* __restrict__ walks, const LearnCtx*
   }
 }
 
-// Pending incumbent copy of a proposal iteration (the full pass does it in
-// its argmax kernel).
-__global__ __launch_bounds__(256) void k_learn_copy_best(const WalkCtx* __restrict__ walks,
-                                                         const LearnCtx* __restrict__ lc, int32_t n) {
-  const WalkCtx& C = walks[0];
-  if (!active(C.st, lc->ls) || !C.st->copy_best) return;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) C.best_x[q] = C.x[q];
-}
-
-// Appends the proposal set (original indices) to the set log; a full
-// evaluation records an empty range.
-__global__ __launch_bounds__(256) void k_learn_log_set(const WalkCtx* __restrict__ walks,
-                                                       const LearnCtx* __restrict__ lc, int32_t full) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
-  const WalkState* st = C.st;
-  if (!active(st, L.ls) || L.set_off == nullptr) return;
-  const int64_t k = st->k;
-  const int64_t pos = L.ls->set_pos;
-  const int cnt = full ? 0 : L.ls->tk[0].count;
-  const bool fits = pos + cnt <= L.set_log_cap;
-  if (fits)
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) L.set_log[pos + i] = C.P.perm[L.sel[0][i]];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t end = fits ? pos + cnt : pos;
-    L.set_off[k] = pos;
-    L.set_off[k + 1] = end;
-    L.ls->set_pos = end;
-  }
-}
-
-// Stored-row updates for the moved column (before k_finish advances k).
-__global__ void k_learn_move(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
-  const WalkState* st = C.st;
-  if (threadIdx.x != 0 || st->k >= st->iters || st->skip) return;
-  const int q = st->mv_j;
-  if (q < 0) return;
-  uint16_t* row = L.feat + (int64_t)q * 16;
-  const int32_t mv = L.moves[q] + 1;
-  L.moves[q] = mv;
-  const double xn = st->mv_new;
-  row[7] = d2bf(position(xn, C.P.lb[q], C.P.ub[q]));
-  row[11] = d2bf(sign_of(L.xhat_last[q] - xn));
-  row[15] = d2bf(log2(1.0 + (double)mv));
-  set_last_move(row, (int32_t)st->k);
-}
-
 // All 16 inputs of every column in original order (zeros for columns that
 // are never proposed).
 __global__ __launch_bounds__(256) void k_learn_features_out(const WalkCtx* __restrict__ walks,
@@ -628,8 +718,9 @@ __global__ __launch_bounds__(256) void k_learn_features_out(const WalkCtx* __res
   if (q >= n) return;
   uint16_t* o = out + (int64_t)C.P.perm[q] * 16;
   const bool ok = L.cls[q] != SUB_NONE;
+  const Globals Gl = globals(k, k_last_full, C.st->V, L.mp);
   for (int gg = 0; gg < 4; ++gg) {
-    const bf16x4 x = assemble(L.feat, q, gg, k, k_last_full, C.st->V, L.mp);
+    const bf16x4 x = assemble(L.feat, q, gg, k, Gl);
     for (int t = 0; t < 4; ++t) o[4 * gg + t] = ok ? (uint16_t)x[t] : 0;
   }
 }
@@ -639,16 +730,14 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
-hipError_t topk(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int which, int32_t n, hipStream_t s) {
+hipError_t topk(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int which, int full, int32_t n,
+                hipStream_t s) {
   const int hb = grid_for(n, 256 * 16, 1024);
-  hipLaunchKernelGGL(k_topk_digit, dim3(1), dim3(64), 0, s, C, L, which, 0);
-  hipLaunchKernelGGL(k_topk_hist, dim3(hb), dim3(256), 0, s, C, L, which, 1, n);
-  hipLaunchKernelGGL(k_topk_digit, dim3(1), dim3(64), 0, s, C, L, which, 1);
-  hipLaunchKernelGGL(k_topk_hist, dim3(hb), dim3(256), 0, s, C, L, which, 2, n);
-  hipLaunchKernelGGL(k_topk_digit, dim3(1), dim3(64), 0, s, C, L, which, 2);
-  hipLaunchKernelGGL(k_topk_count, dim3(Lh.nwg), dim3(256), 0, s, C, L, which, n);
-  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(64), 0, s, C, L, which);
-  hipLaunchKernelGGL(k_topk_write, dim3(Lh.nwg), dim3(256), 0, s, C, L, which, n);
+  hipLaunchKernelGGL(k_topk_hist, dim3(hb), dim3(kBlock), 0, s, C, L, which, 1, n);
+  hipLaunchKernelGGL(k_topk_hist, dim3(hb), dim3(kBlock), 0, s, C, L, which, 2, n);
+  hipLaunchKernelGGL(k_topk_count, dim3(Lh.nwg), dim3(kBlock), 0, s, C, L, which, n);
+  hipLaunchKernelGGL(k_topk_write, dim3(Lh.nwg), dim3(kBlock), 0, s, C, L, which, n);
+  hipLaunchKernelGGL(k_topk_finish, dim3(1), dim3(kBlock), 0, s, C, L, which, (int32_t)full);
   return hipGetLastError();
 }
 
@@ -661,8 +750,12 @@ hipError_t launch_learn_init(const WalkCtx* C, const LearnCtx* L, const LearnCtx
 }
 
 hipError_t launch_learn_refresh(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, hipStream_t s) {
-  if (Lh.n_elig > 0)
-    hipLaunchKernelGGL(k_learn_refresh, dim3(grid_for(Lh.n_elig, 4, 8192)), dim3(256), 0, s, C, L);
+  if (Lh.n_ref_short > 0)
+    hipLaunchKernelGGL(k_refresh_short, dim3(grid_for(Lh.n_ref_short, 32, 8192)), dim3(256), 0, s, C, L);
+  if (Lh.n_ref_chunks > 0) {
+    hipLaunchKernelGGL(k_refresh_chunks, dim3(std::min(Lh.n_ref_chunks, 4096)), dim3(256), 0, s, C, L);
+    hipLaunchKernelGGL(k_refresh_combine, dim3((Lh.n_ref_cols + 255) / 256), dim3(256), 0, s, C, L);
+  }
   return hipGetLastError();
 }
 
@@ -674,18 +767,15 @@ hipError_t launch_learn_begin(const WalkCtx* C, const LearnCtx* L, hipStream_t s
 hipError_t launch_learn_propose(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                                 int32_t n, int full_iteration, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_learn_score, dim3(grid_for(n, 64, 2048)), dim3(256), 0, s, C, L, M.w, M.wb, n);
-  hipError_t e = topk(C, L, Lh, 0, n, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_learn_log_set, dim3(1), dim3(256), 0, s, C, L, (int32_t)full_iteration);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_learn_score, dim3(grid_for(n, 128, 4096)), dim3(256), 0, s, C, L, M.w, M.wb, n);
+  return topk(C, L, Lh, 0, full_iteration, n, s);
 }
 
 hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                               int32_t n, int32_t steps, float lr, hipStream_t s) {
   if (n <= 0 || (steps <= 0 && Lh.log_feat == nullptr)) return hipSuccess;
   hipLaunchKernelGGL(k_label_keys, dim3(grid_for(n, 256 * 16, 1024)), dim3(256), 0, s, C, L, n);
-  hipError_t e = topk(C, L, Lh, 1, n, s);
+  hipError_t e = topk(C, L, Lh, 1, 1, n, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_learn_pairs, dim3(1), dim3(256), 0, s, C, L);
   for (int32_t t = 0; t < steps; ++t) {
@@ -699,16 +789,6 @@ hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCt
 
 hipError_t launch_learn_judge(const WalkCtx* C, const LearnCtx* L, hipStream_t s) {
   hipLaunchKernelGGL(k_learn_judge, dim3(1), dim3(64), 0, s, C, L);
-  return hipGetLastError();
-}
-
-hipError_t launch_learn_copy_best(const WalkCtx* C, const LearnCtx* L, int32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_learn_copy_best, dim3(grid_for(n, 256, 256)), dim3(256), 0, s, C, L, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_learn_move(const WalkCtx* C, const LearnCtx* L, hipStream_t s) {
-  hipLaunchKernelGGL(k_learn_move, dim3(1), dim3(64), 0, s, C, L);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@
 // to the smallest position, and (xbar, 0) is returned when no candidate scores
 // above zero.
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -852,49 +853,60 @@ __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// k_subset: exact best shift of the columns of a proposal set, one workgroup
-// per column, with the same per-entry arithmetic as the full pass (flip sum,
-// counting sort into bins, or LDS bitonic sort, scan and argmax).
+// Subset pass: exact best shift of the columns of a proposal set, with the
+// same per-entry arithmetic as the full pass. Binary and narrow columns of
+// any length are cut into chunks of kSubsetChunk stored entries
+// (k_subset_chunks, partial flip sum or bins per chunk) and combined in chunk
+// order (k_subset_combine); general columns use one workgroup's LDS sort
+// (k_subset_general).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_subset(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
+__global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict__ walks,
+                                                       const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
-  if ((int)blockIdx.x >= L.ls->tk[0].count) return;
-  __shared__ double spos[kSubsetCap];
-  __shared__ double sdel[kSubsetCap];
-  __shared__ int smk[kSubsetCap];
-  __shared__ int scount;
-  __shared__ double red[8];
-  __shared__ int redk[8];
+  __shared__ double bins[kNarrowBins];
+  __shared__ double red[4];
   __shared__ unsigned long long scand;
-  const int q = L.sel[0][blockIdx.x];
-  const uint8_t cls = L.cls[q];
-  const double eps = P.eps;
-  const double xb = C.x[q];
+  const int cnt = L.ls->tk[0].count;
+  const int chunks = L.ls->tk[0].chunks;
   const int tid = threadIdx.x;
-  if (cls == SUB_FLIP) {
-    const double xn = 1.0 - xb;
-    const double d = xn - xb;
-    double v = 0.0;
-    for (int e = P.col_ptr[q] + tid; e < P.col_ptr[q + 1]; e += blockDim.x) {
-      const RowState r = C.rs[P.col_row[e]];
-      const double r2 = r.r + P.col_val[e] * d;
-      v += penalty(r.r, r2, (double)r.w0, eps);
-      if (r.w1 >= 0.0f) v += penalty(-r.r, -r2, (double)r.w1, eps);
+  const double eps = P.eps;
+  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+    // selected column of chunk c: the largest i with sub_off[i] <= c
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.sub_off[mid] <= c)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
-    v = block_sum256(v, red);
-    if (tid == 0) {
-      if (st->cut_active && P.obj[q] != 0.0) v += penalty(st->rc, st->rc + P.obj[q] * d, (double)st->wc, eps);
-      write_result(C.xhat, C.s, q, true, v, xn, xb);
+    const int q = L.sel[0][lo];
+    const int first = (c == L.sub_off[lo]);
+    const int e_beg = P.col_ptr[q] + (c - L.sub_off[lo]) * kSubsetChunk;
+    const int e_end = min(P.col_ptr[q + 1], e_beg + kSubsetChunk);
+    const double xb = C.x[q];
+    ChunkPartial* out = L.sub_parts + c;
+    if (L.cls[q] == SUB_FLIP) {
+      const double d = (1.0 - xb) - xb;
+      double v = 0.0;
+      for (int e = e_beg + tid; e < e_end; e += blockDim.x) {
+        const RowState r = C.rs[P.col_row[e]];
+        const double r2 = r.r + P.col_val[e] * d;
+        v += penalty(r.r, r2, (double)r.w0, eps);
+        if (r.w1 >= 0.0f) v += penalty(-r.r, -r2, (double)r.w1, eps);
+      }
+      if (tid == 0 && first && st->cut_active && P.obj[q] != 0.0)
+        v += penalty(st->rc, st->rc + P.obj[q] * d, (double)st->wc, eps);
+      v = block_sum256(v, red);
+      if (tid == 0) out->beta = v;
+      __syncthreads();
+      continue;
     }
-    return;
-  }
-  if (cls == SUB_NARROW) {
-    double* bins = spos;
     const double l = P.lb[q], u = P.ub[q];
     const int W = (int)(u - l) + 1;
     if (tid < kNarrowBins) bins[tid] = 0.0;
@@ -902,29 +914,88 @@ __global__ __launch_bounds__(256) void k_subset(const WalkCtx* __restrict__ walk
     __syncthreads();
     double beta = 0.0, alpha = 0.0;
     unsigned long long cand = 0ull;
-    for (int e = P.col_ptr[q] + tid; e < P.col_ptr[q + 1]; e += blockDim.x) {
+    for (int e = e_beg + tid; e < e_end; e += blockDim.x) {
       const RowState r = C.rs[P.col_row[e]];
       const double a = P.col_val[e];
       narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins, beta, alpha, cand);
       if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins, beta, alpha, cand);
     }
-    if (tid == 0 && st->cut_active && P.obj[q] != 0.0)
+    if (tid == 0 && first && st->cut_active && P.obj[q] != 0.0)
       narrow_entry(xb, st->rc, P.obj[q], (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
     cand = wave_or(cand);
     if ((tid & 63) == 0 && cand) atomicOr(&scand, cand);
     beta = block_sum256(beta, red);
-    __syncthreads();
     alpha = block_sum256(alpha, red);
     __syncthreads();
-    if (tid < kWave) {
-      bool found;
-      double best, bestp;
-      narrow_finish(bins[tid], beta, alpha, scand, xb, l, W, tid, found, best, bestp);
-      if (tid == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
+    if (tid < kNarrowBins) out->bins[tid] = bins[tid];
+    if (tid == 0) {
+      out->beta = beta;
+      out->alpha = alpha;
+      out->cand = scand;
     }
+    __syncthreads();
+  }
+}
+
+// One wavefront per selected binary or narrow column: its chunks in order,
+// then the flip score or the bins' scan and argmax.
+__global__ __launch_bounds__(256) void k_subset_combine(const WalkCtx* __restrict__ walks,
+                                                        const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  if (st->k >= st->iters || L.ls->idle) return;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= L.ls->tk[0].count) return;
+  const int q = L.sel[0][i];
+  const uint8_t cl = L.cls[q];
+  if (cl == SUB_GENERAL) return;
+  const int lane = threadIdx.x & 63;
+  const int c0 = L.sub_off[i], c1 = L.sub_off[i + 1];
+  const double xb = C.x[q];
+  if (cl == SUB_FLIP) {
+    double v = 0.0;
+    for (int c = c0; c < c1; ++c) v += L.sub_parts[c].beta;
+    if (lane == 0) write_result(C.xhat, C.s, q, true, v, 1.0 - xb, xb);
     return;
   }
-  // general column
+  double bv = 0.0, b = 0.0, a = 0.0;
+  unsigned long long cand = 0ull;
+  for (int c = c0; c < c1; ++c) {
+    const ChunkPartial* pp = L.sub_parts + c;
+    bv += pp->bins[lane];
+    b += pp->beta;
+    a += pp->alpha;
+    cand |= pp->cand;
+  }
+  const double l = P.lb[q];
+  const int W = (int)(P.ub[q] - l) + 1;
+  bool found;
+  double best, bestp;
+  narrow_finish(bv, b, a, cand, xb, l, W, lane, found, best, bestp);
+  if (lane == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
+}
+
+// One workgroup per selected general column (Algorithm 1 with the LDS sort).
+__global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restrict__ walks,
+                                                        const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  if (st->k >= st->iters || L.ls->idle) return;
+  if ((int)blockIdx.x >= L.ls->tk[0].count) return;
+  const int q = L.sel[0][blockIdx.x];
+  if (L.cls[q] != SUB_GENERAL) return;
+  __shared__ double spos[kSubsetCap];
+  __shared__ double sdel[kSubsetCap];
+  __shared__ int smk[kSubsetCap];
+  __shared__ int scount;
+  __shared__ double red[8];
+  __shared__ int redk[8];
+  const int tid = threadIdx.x;
+  const double xb = C.x[q];
   if (tid == 0) scount = 0;
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
@@ -955,8 +1026,13 @@ __global__ __launch_bounds__(256) void k_subset(const WalkCtx* __restrict__ walk
 
 }  // namespace
 
-hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, int32_t K, hipStream_t s) {
-  if (K > 0) hipLaunchKernelGGL(k_subset, dim3((unsigned)K), dim3(256), 0, s, C, L);
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general,
+                              hipStream_t s) {
+  const int K = Lh.K[0];
+  hipLaunchKernelGGL(k_subset_chunks, dim3((unsigned)std::min(kSubsetGrid, std::max(Lh.sub_cap, 1))), dim3(256), 0, s,
+                     C, L);
+  hipLaunchKernelGGL(k_subset_combine, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, C, L);
+  if (has_general) hipLaunchKernelGGL(k_subset_general, dim3((unsigned)K), dim3(256), 0, s, C, L);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "chap_internal.h"
+#include "learned_rows.h"
 
 namespace chap {
 namespace {
@@ -430,6 +431,8 @@ __global__ __launch_bounds__(256) void k_subset_select(const WalkCtx* __restrict
     if (kind == kStallKind) {
       L.ls->stalls += 1;
       L.ls->idle = 1;
+    } else {
+      learned::after_move(C, L);
     }
   }
 }

@@ -64,11 +64,14 @@ def test_features_refresh_point_and_eligibility():
     np.testing.assert_array_equal(np.delete(now, [0, 3, 9, 10], axis=1), np.delete(ref, [0, 3, 9, 10], axis=1))
     r0, _ = F.inputs(mip, P, x0, w, math.inf, z, x0, lm, mv, 3, 0)
     np.testing.assert_array_equal(ref[:, [0, 3, 9, 10]], r0[:, [0, 3, 9, 10]])
-    # a column with 4094 normalised entries is proposable, one more is not
-    for cnt, expect in ((4094, True), (4095, False)):
+    # a general column with 4094 normalised entries is proposable, one more
+    # is not; binary and narrow integer columns are proposable at any length
+    for cnt, ub, expect in ((4094, 100, True), (4095, 100, False), (5000, 63, True), (5000, 1, True)):
         rows = [({0: 1}, "L", 1)] * cnt
-        m2 = make_mip(1, rows, [0], [5], [1])
-        assert F.proposable(m2, F.column_rows(m2, *oracle.OracleProblem(m2).norm_rows()))[0] == expect
+        m2 = make_mip(1, rows, [0], [ub], [1])
+        O2 = oracle.OracleProblem(m2)
+        lb2, ub2, _ = O2.bounds()
+        assert F.proposable(m2, F.column_rows(m2, *O2.norm_rows()), lb2, ub2)[0] == expect
 
 
 def _walk_pair(mip, iters, full_every, sets_fn):
