@@ -202,6 +202,26 @@ int chap_batch_run(chap_problem *const *probs, int32_t nprob, const int32_t *wal
                    const uint64_t *walk_seed, int32_t nwalks, int64_t iters, int32_t tenure,
                    chap_run **out, void *hip_stream);
 
+/*
+ * chap_autotune - picks the kernel routing thresholds and graph size for an
+ * instance by measurement (the paper fixes its length classes for H100,
+ * section 3.1 "Kernel Specialization"; here they are tuned per instance).
+ *
+ * For each candidate option set the problem is re-planned from a host copy
+ * of p's input arrays and walk_iters tabu iterations are timed (start seed 0,
+ * tenure 10, after a short warm-up). Results never depend on the options
+ * (same trajectories), only speed does.
+ *   cands, ncand  candidate sets (feas_tol is ignored: p's is kept); ncand = 0
+ *                 uses a built-in grid of 8 over short_max {4, 8},
+ *                 chunk_min = chunk_len {2048, 4096}, graph_iters {32, 64}
+ *   walk_iters    1 .. 2^20 timed iterations per candidate
+ *   best          the fastest candidate (pass it to chap_problem_create)
+ *   ms_per_iter   optional, one entry per candidate (8 for the grid)
+ * Synchronous; uses the current device. CHAP_EINVAL on bad arguments.
+ */
+int chap_autotune(const chap_problem *p, const chap_options *cands, int32_t ncand, int64_t walk_iters,
+                  chap_options *best, double *ms_per_iter);
+
 /* Trace of a run: *records points into the run (valid until
  * chap_run_destroy), *count = iters. */
 int chap_run_trace(const chap_run *r, const chap_trace_record **records, int64_t *count);

@@ -97,6 +97,8 @@ def load_library():
     lib.chap_model_grad.restype = ctypes.c_int
     lib.chap_model_train.argtypes = [P, P, P, i64, i32, i32, ctypes.c_float, u64, P]
     lib.chap_model_train.restype = ctypes.c_int
+    lib.chap_autotune.argtypes = [P, P, i32, i64, ctypes.POINTER(ChapOptions), P]
+    lib.chap_autotune.restype = ctypes.c_int
     lib.chap_learned_options_default.argtypes = [ctypes.POINTER(LearnedOptions)]
     lib.chap_learned_options_default.restype = None
     lib.chap_learned_run.argtypes = [P, P, ctypes.POINTER(LearnedOptions), i64, i32, u64, P, ctypes.POINTER(P), P]
@@ -288,6 +290,27 @@ class Problem:
         _check(load_library().chap_tabu_run(self._h, int(iters), int(tenure), int(seed), x0p, ctypes.byref(h),
                                             _stream_handle(stream)))
         return Run(h, self.n, self.mp)
+
+
+def autotune(problem, candidates=None, walk_iters: int = 64):
+    """chap_autotune: returns (best ChapOptions, ms per iteration of every
+    candidate). candidates: list of dicts of option overrides, or None for the
+    built-in grid."""
+    lib = load_library()
+    if candidates:
+        arr = (ChapOptions * len(candidates))()
+        for i, c in enumerate(candidates):
+            o = default_options()
+            for k, v in c.items():
+                setattr(o, k, v)
+            arr[i] = o
+        ptr, nc = ctypes.cast(arr, ctypes.c_void_p), len(candidates)
+    else:
+        ptr, nc = None, 0
+    ms = np.zeros(max(nc, 8))
+    best = ChapOptions()
+    _check(lib.chap_autotune(problem._h, ptr, nc, int(walk_iters), ctypes.byref(best), _ptr(ms)))
+    return best, ms[:nc if nc else 8]
 
 
 def learned_options(**kw) -> LearnedOptions:

@@ -133,6 +133,21 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     if (!std::isfinite(rhs[i])) return fail(CHAP_EINVAL, "row " + std::to_string(i) + ": rhs must be finite");
   }
   std::unique_ptr<chap_problem> P(new chap_problem());
+  {
+    chap_problem::Raw& R = P->raw;
+    R.csr_row_ptr.assign(csr_row_ptr, csr_row_ptr + (size_t)m + 1);
+    R.csc_col_ptr.assign(csc_col_ptr, csc_col_ptr + (size_t)n + 1);
+    R.csr_col.assign(csr_col, csr_col + nnz_in);
+    R.csr_val.assign(csr_val, csr_val + nnz_in);
+    R.csc_row.assign(csc_row, csc_row + nnz_in);
+    R.csc_val.assign(csc_val, csc_val + nnz_in);
+    R.sense.assign(sense, sense + m);
+    R.rhs.assign(rhs, rhs + m);
+    R.lb.assign(lb, lb + n);
+    R.ub.assign(ub, ub + n);
+    R.is_int.assign(is_int, is_int + n);
+    R.obj.assign(obj, obj + n);
+  }
   P->n = n;
   P->m = m;
   P->opt = o;
@@ -813,6 +828,53 @@ int chap_batch_run(chap_problem* const* probs, int32_t nprob, const int32_t* wal
   const int rc = run_walks(specs, iters, tenure, (hipStream_t)hip_stream, runs);
   if (rc != CHAP_OK) return rc;
   for (int32_t w = 0; w < nwalks; ++w) out[w] = runs[w].release();
+  return CHAP_OK;
+}
+
+int chap_autotune(const chap_problem* p, const chap_options* cands, int32_t ncand, int64_t walk_iters,
+                  chap_options* best, double* ms_per_iter) {
+  if (!p || !best || ncand < 0 || (ncand > 0 && !cands) || walk_iters <= 0 || walk_iters > (1 << 20))
+    return fail(CHAP_EINVAL, "chap_autotune: bad argument");
+  std::vector<chap_options> grid;
+  if (ncand > 0) {
+    grid.assign(cands, cands + ncand);
+  } else {
+    for (int32_t sm : {4, 8})
+      for (int32_t cl : {2048, 4096})
+        for (int32_t gi : {32, 64}) {
+          chap_options o = p->opt;
+          o.short_max = sm;
+          o.chunk_min = cl;
+          o.chunk_len = cl;
+          o.graph_iters = gi;
+          grid.push_back(o);
+        }
+  }
+  const chap_problem::Raw& R = p->raw;
+  double best_ms = HUGE_VAL;
+  int32_t best_i = -1;
+  for (size_t c = 0; c < grid.size(); ++c) {
+    chap_options o = grid[c];
+    o.feas_tol = p->opt.feas_tol;  // the tolerance is part of the problem, not a tuning knob
+    chap_problem* t = nullptr;
+    int rc = chap_problem_create(&t, p->n, p->m, R.csr_row_ptr.data(), R.csr_col.data(), R.csr_val.data(),
+                                 R.csc_col_ptr.data(), R.csc_row.data(), R.csc_val.data(), R.sense.data(),
+                                 R.rhs.data(), R.lb.data(), R.ub.data(), R.is_int.data(), R.obj.data(), &o);
+    if (rc != CHAP_OK) return rc;
+    std::unique_ptr<chap_problem> guard(t);
+    std::vector<std::unique_ptr<chap_run>> runs;
+    rc = run_walks({WalkSpec{t, 0, nullptr}}, std::min<int64_t>(walk_iters, 8), 10, nullptr, runs);  // warm-up
+    if (rc == CHAP_OK) rc = run_walks({WalkSpec{t, 0, nullptr}}, walk_iters, 10, nullptr, runs);
+    if (rc != CHAP_OK) return rc;
+    const double ms = runs[0]->elapsed_ms / (double)walk_iters;
+    if (ms_per_iter) ms_per_iter[c] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_i = (int32_t)c;
+    }
+  }
+  *best = grid[best_i];
+  best->feas_tol = p->opt.feas_tol;
   return CHAP_OK;
 }
 

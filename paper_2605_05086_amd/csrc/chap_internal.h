@@ -463,6 +463,14 @@ struct chap_problem {
   double* bs_xhat = nullptr;
   double* bs_s = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
+  // host copy of the caller's arrays (the autotuner re-plans from them)
+  struct Raw {
+    std::vector<int64_t> csr_row_ptr, csc_col_ptr;
+    std::vector<int32_t> csr_col, csc_row;
+    std::vector<double> csr_val, csc_val, rhs, lb, ub, obj;
+    std::vector<char> sense;
+    std::vector<uint8_t> is_int;
+  } raw;
   // learned proposal: SUB_* class and stored entries per internal column,
   // max |c_j|
   std::vector<uint8_t> sub_cls;

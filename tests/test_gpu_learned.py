@@ -221,3 +221,33 @@ def test_learned_edge_cases(chap):
             continue
         ref = P.learned_replay(iters, 5, 1, F_, run.sets, run.set_offsets)
         compare_traces(run.trace, ref["trace"], f"edge iters={iters} F={F_} K={K}")
+
+
+def test_trained_network_gains_over_untrained(chap):
+    """What the trained network gains: on a 2M-nonzero power-law instance, a
+    network trained on pairs logged by a plain walk from another start point
+    puts the full evaluation's own choice into its proposal set far more
+    often than the same network untrained, and the moves its walk takes from
+    proposal sets have larger exact scores. (Violation counts of single
+    walks are too noisy at this size to rank the two.)"""
+    import torch
+    mip = mipgen.powerlaw(0, n=200_000, m=100_000, nnz=2_000_000, cap=20_000)
+    G = chap.Problem(mip)
+    iters, tenure = 768, 10
+    say("gain: plain walk")
+    plain = G.tabu_run(iters, tenure, 0)
+    vp = int(plain.trace["viol"][-1])
+    trained = chap.Model(0)
+    say("gain: logging walk and training")
+    log = chap.learned_run(G, trained, 64, tenure, 7, full_every=1, topk=256, train_pairs=512, log_pairs=64 * 1024)
+    trained.train(torch.from_numpy(log.pair_feat.view(np.int16)).cuda(), torch.from_numpy(log.pair_target).cuda(),
+                  steps=600, batch=1024, lr=1e-3, seed=1)
+    out = {}
+    for name, M in (("trained", trained), ("untrained", chap.Model(0))):
+        say(f"gain: learned walk, {name}")
+        run = chap.learned_run(G, M, iters, tenure, 0, full_every=16, topk=256)
+        prop = run.trace["kind"] >= 8
+        out[name] = (run.hits / run.evals, float(np.mean(run.trace["score"][prop])), int(run.trace["viol"][-1]))
+    say(f"gain: (hit rate, mean proposal-move score, final violations) {out}; plain final {vp}")
+    assert out["trained"][0] >= 0.5 and out["trained"][0] >= out["untrained"][0] + 0.3, out
+    assert out["trained"][1] > 1.2 * out["untrained"][1], out

@@ -359,3 +359,19 @@ def test_batch_equals_plain(chap):
         say(f"oracle walk {w}")
         o = oracle.OracleProblem(mips[walk_prob[w]]).tabu_run(120, 10, walk_seed[w])
         compare_runs(runs[w], o, f"batch walk {w}", exact=True, exact_obj=walk_prob[w] == 3)
+
+
+def test_autotune_picks_a_candidate(chap):
+    mip = mipgen.random_mixed(77, n=400, m=300, max_row_nnz=8, long_cols=4, long_deg=120)
+    G = chap.Problem(mip)
+    say("autotune grid")
+    best, ms = chap.autotune(G, walk_iters=16)
+    assert ms.shape == (8,) and np.all(ms > 0)
+    assert best.short_max in (4, 8) and best.chunk_len in (2048, 4096) and best.graph_iters in (32, 64)
+    cands = [dict(short_max=2, chunk_min=16, chunk_len=16, graph_iters=8), dict(short_max=8, graph_iters=64)]
+    best2, ms2 = chap.autotune(G, cands, walk_iters=16)
+    assert ms2.shape == (2,) and (best2.short_max, best2.graph_iters) in ((2, 8), (8, 64))
+    # the tuned problem walks exactly as the default one
+    T = chap.Problem(mip, short_max=best2.short_max, chunk_min=best2.chunk_min, chunk_len=best2.chunk_len,
+                     graph_iters=best2.graph_iters)
+    np.testing.assert_array_equal(T.tabu_run(100, 10, 3).trace, G.tabu_run(100, 10, 3).trace)
