@@ -115,12 +115,14 @@ def load_library():
     return lib
 
 
-def _release(fn: str, handle) -> None:
+def _release(fn: str, handle, _mod=__import__("sys").modules[__name__]) -> None:
     """Destroys a handle; a no-op while the interpreter shuts down (module
     globals may already be gone then)."""
-    lib = _lib
-    if lib is not None and getattr(lib, fn, None) is not None:
-        getattr(lib, fn)(handle)
+    lib = getattr(_mod, "_lib", None)
+    if lib is not None:
+        f = getattr(lib, fn, None)
+        if f is not None:
+            f(handle)
 
 
 def _check(rc: int):
@@ -200,7 +202,7 @@ class Run:
         evaluation); needs a run with log_sets."""
         return self.sets[self.set_offsets[k]:self.set_offsets[k + 1]]
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         h = getattr(self, "_h", None)
         if h:
             _release("chap_run_destroy", h)
@@ -246,7 +248,7 @@ class Problem:
         self.m = int(mip.m)
         self.mp = int(lib.chap_problem_num_norm_rows(h))
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         h = getattr(self, "_h", None)
         if h:
             _release("chap_problem_destroy", h)
@@ -390,7 +392,7 @@ class Model:
         _check(lib.chap_model_create(ctypes.byref(h), int(seed)))
         self._h = h
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             _release("chap_model_destroy", h)

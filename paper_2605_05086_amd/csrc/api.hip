@@ -555,6 +555,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.alloc(&c.long_marker, (size_t)P->plan.long_scratch));
     CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &P->bs_launch));
   }
+  CHAP_HIP(P->bs_streams.create());
   CHAP_HIP(hipEventCreate(&P->pass_ev[0]));
   CHAP_HIP(hipEventCreate(&P->pass_ev[1]));
   CHAP_HIP(hipDeviceSynchronize());
@@ -576,7 +577,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
                              p->obj_integral, cut, d_w + p->mp, 0, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
-  if (p->n > 0) CHAP_HIP(launch_pass(p->bs_launch, s));
+  if (p->n > 0) CHAP_HIP(launch_pass(p->bs_launch, s, &p->bs_streams));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
   CHAP_HIP(launch_scatter2(p->dev.perm, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
   p->pass_timed = true;
@@ -730,8 +731,13 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   CHAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct StreamGuard {
     hipStream_t s;
-    ~StreamGuard() { (void)hipStreamDestroy(s); }
-  } sg{s};
+    PassStreams ps;
+    ~StreamGuard() {
+      ps.destroy();
+      (void)hipStreamDestroy(s);
+    }
+  } sg{s, {}};
+  CHAP_HIP(sg.ps.create());
   hipEvent_t e_user, e0, e1;
   CHAP_HIP(hipEventCreate(&e_user));
   CHAP_HIP(hipEventCreate(&e0));
@@ -760,7 +766,7 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
     for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
-      cap_err = launch_pass(L, s);
+      cap_err = launch_pass(L, s, &sg.ps);
       if (cap_err == hipSuccess) cap_err = launch_walk_step(L, s);
     }
     hipError_t end_err = hipStreamEndCapture(s, &graph);

@@ -118,10 +118,10 @@ int build_learn_ctx(const chap_problem* p, const chap_learned_options& o, int64_
 
 hipError_t capture_block(const BatchLaunch& BL, const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh,
                          const ModelDev& M, const chap_learned_options& o, int32_t n, int has_general,
-                         hipStream_t s) {
+                         hipStream_t s, const PassStreams* ps) {
   hipError_t e = launch_learn_begin(C, L, s);
   // full evaluation: exact pass, judge set, training, move, row refresh
-  if (e == hipSuccess) e = launch_pass(BL, s);
+  if (e == hipSuccess) e = launch_pass(BL, s, ps);
   if (e == hipSuccess && Lh.n_elig > 0) e = launch_learn_propose(C, L, Lh, M, n, 1, s);
   if (e == hipSuccess && Lh.n_elig > 0) e = launch_learn_train(C, L, Lh, M, n, o.train_steps, o.lr, s);
   if (e == hipSuccess) e = launch_walk_choose(BL, s);
@@ -178,8 +178,13 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
   CHAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   struct StreamGuard {
     hipStream_t s;
-    ~StreamGuard() { (void)hipStreamDestroy(s); }
-  } sg{s};
+    PassStreams ps;
+    ~StreamGuard() {
+      ps.destroy();
+      (void)hipStreamDestroy(s);
+    }
+  } sg{s, {}};
+  CHAP_HIP(sg.ps.create());
   hipEvent_t e_user, e0, e1;
   CHAP_HIP(hipEventCreate(&e_user));
   CHAP_HIP(hipEventCreate(&e0));
@@ -218,7 +223,7 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int has_general = 0;
     for (uint8_t c : p->sub_cls) has_general |= (c == SUB_GENERAL) ? 1 : 0;
-    const hipError_t cap_err = capture_block(BL, dC, dL, Lh, m->dev, o, n, has_general, s);
+    const hipError_t cap_err = capture_block(BL, dC, dL, Lh, m->dev, o, n, has_general, s, &sg.ps);
     const hipError_t end_err = hipStreamEndCapture(s, &graph);
     if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));
     if (end_err != hipSuccess) return fail(CHAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(end_err));

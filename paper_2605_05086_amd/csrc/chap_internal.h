@@ -251,9 +251,22 @@ struct BatchLaunch {
 // Blocks kernel `slot` needs for one walk.
 int32_t kernel_blocks(const WalkCtx& c, int slot);
 
+// Side streams on which the pass kernels run beside the main stream (they
+// write disjoint columns): fork and join events order them with the main
+// stream, also under graph capture.
+struct PassStreams {
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[2] = {nullptr, nullptr};
+  hipError_t create();
+  void destroy();
+};
+
 // ---- launchers (kernels_pass.hip) -----------------------------------------
-// One exact best-shift pass over all columns of every walk of the batch.
-hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream);
+// One exact best-shift pass over all columns of every walk of the batch;
+// with `ps`, the short-column and long-column kernels run on side streams
+// beside the pack kernel.
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps = nullptr);
 
 // ---- launchers (kernels_walk.hip) -----------------------------------------
 // Single-walk set-up kernels.
@@ -479,10 +492,12 @@ struct chap_problem {
   double c_max = 0.0;
   chap::BatchLaunch bs_launch;
   hipEvent_t pass_ev[2] = {nullptr, nullptr};
+  chap::PassStreams bs_streams;
   bool pass_timed = false;
   ~chap_problem() {
     for (hipEvent_t e : pass_ev)
       if (e) (void)hipEventDestroy(e);
+    bs_streams.destroy();
   }
 };
 

@@ -431,24 +431,54 @@ __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__
   __syncthreads();
   const double eps = P.eps;
   const int e0 = sstart[0], e1 = sstart[nc];
-  for (int e = e0 + tid; e < e1; e += blockDim.x) {
-    int lo = 0, hi = nc - 1;  // largest slot with sstart[slot] <= e
+  // Each thread takes kPackRun consecutive entries per step (the loads of a
+  // run are issued together); runs mostly stay inside one column, so beta,
+  // alpha and the candidate mask are summed in registers and added to LDS
+  // once per column change instead of once per entry.
+  constexpr int kPackRun = 4;
+  const int step = blockDim.x * kPackRun;
+  for (int base = e0 + tid * kPackRun; base < e1; base += step) {
+    const int cnt = min(kPackRun, e1 - base);
+    int row[kPackRun];
+    double a[kPackRun];
+    RowState r[kPackRun];
+#pragma unroll
+    for (int u = 0; u < kPackRun; ++u)
+      if (u < cnt) {
+        row[u] = P.col_row[base + u];
+        a[u] = P.col_val[base + u];
+      }
+#pragma unroll
+    for (int u = 0; u < kPackRun; ++u)
+      if (u < cnt) r[u] = rs[row[u]];
+    int lo = 0, hi = nc - 1;  // largest slot with sstart[slot] <= base
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (sstart[mid] <= e)
+      if (sstart[mid] <= base)
         lo = mid;
       else
         hi = mid - 1;
     }
-    const int slot = lo;
-    const double xb = sxb[slot], l = sl[slot], u = su[slot];
-    const int W = (int)(u - l) + 1;
-    const RowState r = rs[P.col_row[e]];
-    const double a = P.col_val[e];
+    int slot = lo;
     double db = 0.0, da = 0.0;
     unsigned long long dc = 0ull;
-    narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins[slot], db, da, dc);
-    if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins[slot], db, da, dc);
+#pragma unroll
+    for (int u = 0; u < kPackRun; ++u) {
+      if (u >= cnt) break;
+      while (base + u >= sstart[slot + 1]) {
+        if (db != 0.0) atomicAdd(&sbeta[slot], db);
+        if (da != 0.0) atomicAdd(&salpha[slot], da);
+        if (dc) atomicOr(&scand[slot], dc);
+        db = 0.0;
+        da = 0.0;
+        dc = 0ull;
+        ++slot;
+      }
+      const double xb = sxb[slot], l = sl[slot], u2 = su[slot];
+      const int W = (int)(u2 - l) + 1;
+      narrow_entry(xb, r[u].r, a[u], (double)r[u].w0, eps, l, u2, W, bins[slot], db, da, dc);
+      if (r[u].w1 >= 0.0f) narrow_entry(xb, -r[u].r, -a[u], (double)r[u].w1, eps, l, u2, W, bins[slot], db, da, dc);
+    }
     if (db != 0.0) atomicAdd(&sbeta[slot], db);
     if (da != 0.0) atomicAdd(&salpha[slot], da);
     if (dc) atomicOr(&scand[slot], dc);
@@ -1056,19 +1086,50 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
   }
 }
 
-hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream) {
+hipError_t PassStreams::create() {
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+}
+
+void PassStreams::destroy() {
+  for (int k = 0; k < 2; ++k) {
+    if (side[k]) (void)hipStreamDestroy(side[k]);
+    if (join[k]) (void)hipEventDestroy(join[k]);
+    side[k] = nullptr;
+    join[k] = nullptr;
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  fork = nullptr;
+}
+
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
   const int nw = L.nw;
   auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
+  hipStream_t s_short = stream, s_long = stream;
+  if (ps) {
+    hipError_t e = hipEventRecord(ps->fork, stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->fork, 0);
+    if (e != hipSuccess) return e;
+    s_short = ps->side[0];
+    s_long = ps->side[1];
+  }
   if (L.total[KS_SHORT] > 0)
-    hipLaunchKernelGGL(k_short, grid(KS_SHORT), dim3(256), 0, stream, L.walks, L.off[KS_SHORT], nw);
+    hipLaunchKernelGGL(k_short, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
   if (L.total[KS_FLIP] > 0)
-    hipLaunchKernelGGL(k_flip_wave, grid(KS_FLIP), dim3(256), 0, stream, L.walks, L.off[KS_FLIP], nw);
+    hipLaunchKernelGGL(k_flip_wave, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
+  if (L.total[KS_CHUNK] > 0) {
+    hipLaunchKernelGGL(k_narrow_chunk, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
+    hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+  }
+  if (L.total[KS_LONG] > 0)
+    hipLaunchKernelGGL(k_sort_long, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
   if (L.total[KS_PACK] > 0)
     hipLaunchKernelGGL(k_narrow_pack, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
-  if (L.total[KS_CHUNK] > 0) {
-    hipLaunchKernelGGL(k_narrow_chunk, grid(KS_CHUNK), dim3(256), 0, stream, L.walks, L.off[KS_CHUNK], nw);
-    hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
-  }
   if (L.total[KS_SORT0] > 0)
     hipLaunchKernelGGL(k_sort_block<64>, grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
   if (L.total[KS_SORT0 + 1] > 0)
@@ -1079,9 +1140,14 @@ hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream) {
   if (L.total[KS_SORT0 + 3] > 0)
     hipLaunchKernelGGL(k_sort_block<4096>, grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 3],
                        nw);
-  if (L.total[KS_LONG] > 0)
-    hipLaunchKernelGGL(k_sort_long, grid(KS_LONG), dim3(1024), 0, stream, L.walks, L.off[KS_LONG], nw);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (ps) {
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      e = hipEventRecord(ps->join[k], ps->side[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, ps->join[k], 0);
+    }
+  }
+  return e;
 }
 
 }  // namespace chap
