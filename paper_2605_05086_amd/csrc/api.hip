@@ -247,6 +247,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   P->mp = mp;
   {
     bool exact = true;
+    double max_mag = 0.0;
     for (int32_t j = 0; j < n && exact; ++j)
       exact = P->is_int[j] && std::isfinite(P->lb[j]) && std::isfinite(P->ub[j]);
     for (int32_t i = 0; i < m && exact; ++i) {
@@ -259,8 +260,11 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
         mag += std::fabs(a) * std::max(std::fabs(P->lb[c]), std::fabs(P->ub[c]));
       }
       exact = exact && mag < 4503599627370496.0;  // 2^52
+      max_mag = std::max(max_mag, mag);
     }
     P->exact_incremental = exact ? 1 : 0;
+    // every residual a^T x - b with l <= x <= u is bounded by mag
+    P->compact_ok = (exact && max_mag < 2147483647.0) ? 1 : 0;
   }
   // per original column: stored entries (rows ascending), degree, entries
   std::vector<int32_t> deg(n), ne(n);
@@ -549,11 +553,16 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     c.s = P->bs_s;
     c.rs = P->bs_rs;
     c.st = P->bs_state;
+    if (P->compact_ok) {
+      CHAP_HIP(A.alloc(&P->bs_grow, (size_t)m));
+      c.grow = P->bs_grow;
+    }
     CHAP_HIP(A.alloc(&c.partials, (size_t)P->plan.n_partials));
     CHAP_HIP(A.alloc(&c.long_pos, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.long_delta, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.long_marker, (size_t)P->plan.long_scratch));
     CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &P->bs_launch));
+    P->bs_launch.compact = P->compact_ok ? 2 : 0;
   }
   CHAP_HIP(P->bs_streams.create());
   CHAP_HIP(hipEventCreate(&P->pass_ev[0]));
@@ -576,6 +585,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
                              p->obj_integral, cut, d_w + p->mp, 0, s));
+  if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
   if (p->n > 0) CHAP_HIP(launch_pass(p->bs_launch, s, &p->bs_streams));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
@@ -620,7 +630,7 @@ void start_point(const chap_problem* p, uint64_t seed, double* x) {
 namespace chap {
 
 int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
-                 uint32_t* ticket, hipStream_t s) {
+                 uint32_t* ticket, hipStream_t s, int compact) {
   const chap_problem* p = spec.p;
   const int32_t n = p->n;
   std::vector<double> xs(n), xq(n);
@@ -663,6 +673,10 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
   CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
                              nullptr, 1, s));
   CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
+  if (compact) {
+    CHAP_HIP(A.alloc(&c.grow, (size_t)p->m));
+    CHAP_HIP(launch_fill_compact(c.rs, c.grow, p->m, s));
+  }
   // the host copy of xq must outlive the asynchronous upload
   CHAP_HIP(hipStreamSynchronize(s));
   return CHAP_OK;
@@ -711,6 +725,18 @@ int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double 
 
 }  // namespace chap
 
+namespace chap {
+
+int compact_walks(const std::vector<WalkSpec>& specs, int64_t iters) {
+  // weights start at 1 and grow by at most 1 per iteration
+  if (iters + 1 >= (int64_t)kNoTwin) return 0;
+  for (const WalkSpec& w : specs)
+    if (!w.p->compact_ok) return 0;
+  return 1;
+}
+
+}  // namespace chap
+
 namespace {
 
 // Runs every walk for `iters` iterations: per-walk buffers, set-up kernels,
@@ -753,12 +779,14 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   CHAP_HIP(hipEventRecord(e_user, user));
   CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
   CHAP_HIP(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
+  const int compact = compact_walks(specs, iters);
   for (size_t w = 0; w < nw; ++w) {
-    const int rc = prepare_walk(specs[w], iters, tenure, A, ctx[w], partial, ticket, s);
+    const int rc = prepare_walk(specs[w], iters, tenure, A, ctx[w], partial, ticket, s, compact);
     if (rc != CHAP_OK) return rc;
   }
   BatchLaunch L;
   CHAP_HIP(build_launch(A, ctx, &L));
+  L.compact = compact;
   double ms_total = 0.0;
   if (iters > 0) {
     const int64_t K = std::min<int64_t>(iters, specs[0].p->opt.graph_iters);

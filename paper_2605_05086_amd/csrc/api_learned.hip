@@ -200,10 +200,12 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
   CHAP_HIP(hipEventRecord(e_user, (hipStream_t)hip_stream));
   CHAP_HIP(hipStreamWaitEvent(s, e_user, 0));
   WalkCtx c;
-  rc = prepare_walk(WalkSpec{p, seed, x0}, iters, tenure, A, c, partial, ticket, s);
+  const int compact = compact_walks({WalkSpec{p, seed, x0}}, iters);
+  rc = prepare_walk(WalkSpec{p, seed, x0}, iters, tenure, A, c, partial, ticket, s, compact);
   if (rc != CHAP_OK) return rc;
   BatchLaunch BL;
   CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &BL));
+  BL.compact = compact;
   LearnCtx Lh;
   rc = build_learn_ctx(p, o, iters, A, Lh);
   if (rc != CHAP_OK) return rc;

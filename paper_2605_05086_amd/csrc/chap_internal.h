@@ -82,6 +82,17 @@ struct __align__(16) RowState {
   float w1;
 };
 
+// Exact 8-byte copy of a RowState for all-integer walks whose residuals fit
+// int32 and whose weights stay below 65535 (w1 = 0xFFFF: no twin row). The
+// pass gathers it instead of the 16-byte RowState: half the footprint, the
+// same FP64 values after conversion.
+struct __align__(8) GatherRow {
+  int32_t r;
+  uint16_t w0;
+  uint16_t w1;
+};
+constexpr uint16_t kNoTwin = 0xFFFF;
+
 // Read-only problem data on the device, passed to kernels by value.
 struct DevProblem {
   int32_t n;
@@ -131,7 +142,7 @@ struct __align__(16) WalkState {
   double mv_score;
   unsigned long long dV;  // two's complement accumulator of violation changes
   int32_t skip;           // learned walks: this iteration does nothing (block idle)
-  int32_t pad;
+  int32_t compact_rows;   // single passes: the compact row copy is exact for these weights
 };
 
 // A slice of a long narrow-integer column handled by one workgroup; col < 0
@@ -210,6 +221,7 @@ struct WalkCtx {
   double* best_x;
   int32_t* tabu;
   RowState* rs;
+  GatherRow* grow;  // compact copy of rs kept by the walk kernels, or null
   WalkState* st;
   chap_trace_record* trace;
   double* argmax_partial;
@@ -243,6 +255,9 @@ enum KernelSlot {
 // Block b of a launch belongs to the walk w with off[w] <= b < off[w + 1].
 struct BatchLaunch {
   int32_t nw = 0;
+  // 0: the pass gathers RowState; 1: every walk keeps a GatherRow copy and the
+  // pass gathers it; 2: the copy is used where WalkState::compact_rows says so
+  int32_t compact = 0;
   const WalkCtx* walks = nullptr;
   const int32_t* off[KS_COUNT] = {};
   int32_t total[KS_COUNT] = {};
@@ -281,6 +296,12 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
                              int32_t obj_integral, double cutoff_rhs, const float* cutoff_w,
                              int check_incumbent, hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
+// grow[i] = compact copy of rs[i]
+hipError_t launch_fill_compact(const RowState* rs, GatherRow* grow, int32_t ms, hipStream_t stream);
+// The same for a single pass with caller weights: clears st->compact_rows
+// (set by the state initialisation) when a residual or weight does not fit.
+hipError_t launch_fill_compact_checked(const RowState* rs, GatherRow* grow, WalkState* st, int32_t ms,
+                                       hipStream_t stream);
 // dst[q] = src[perm[q]] (original order -> internal order)
 hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream);
 // da[perm[q]] = a[q], db[perm[q]] = b[q] (internal order -> original order)
@@ -453,6 +474,9 @@ struct chap_problem {
   // coefficient and right-hand side is an integer small enough that all row
   // activities are exact in FP64: incremental residual updates are then exact
   int32_t exact_incremental = 0;
+  // 1 when additionally every row activity fits int32 (walks may then gather
+  // residuals from the compact GatherRow copy)
+  int32_t compact_ok = 0;
   // host copies used by runs
   std::vector<double> lb, ub, obj;
   std::vector<uint8_t> is_int;
@@ -475,6 +499,7 @@ struct chap_problem {
   double* bs_x = nullptr;
   double* bs_xhat = nullptr;
   double* bs_s = nullptr;
+  chap::GatherRow* bs_grow = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
   // host copy of the caller's arrays (the autotuner re-plans from them)
   struct Raw {
@@ -537,7 +562,9 @@ struct WalkSpec {
 // Allocates one walk's buffers in A, uploads its start point and runs the
 // set-up kernels on stream s (residual, unit weights, state, incumbent).
 int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
-                 uint32_t* ticket, hipStream_t s);
+                 uint32_t* ticket, hipStream_t s, int compact);
+// 1 when every walk of a run may keep the compact GatherRow copy.
+int compact_walks(const std::vector<WalkSpec>& specs, int64_t iters);
 // Copies a finished walk back into R (host order).
 int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double ms, chap_run* R);
 // Device copy of the walk contexts and the per-kernel launch tables.

@@ -42,6 +42,49 @@ namespace {
 
 constexpr int kWave = 64;
 
+// Row accessors: the walk's RowState array, or its compact GatherRow copy.
+struct FullRows {
+  const RowState* p;
+  __device__ __forceinline__ RowState operator[](int i) const { return p[i]; }
+};
+
+struct CompactRows {
+  const GatherRow* p;
+  __device__ __forceinline__ RowState operator[](int i) const {
+    const GatherRow g = p[i];
+    RowState o;
+    o.r = (double)g.r;
+    o.w0 = (float)g.w0;
+    o.w1 = (g.w1 == kNoTwin) ? -1.0f : (float)g.w1;
+    return o;
+  }
+};
+
+// Either of the two, as the walk state says (single passes with caller weights).
+struct DualRows {
+  const RowState* p;
+  const GatherRow* g;
+  int32_t use_g;
+  __device__ __forceinline__ RowState operator[](int i) const {
+    return use_g ? CompactRows{g}[i] : p[i];
+  }
+};
+
+template <typename Rows>
+__device__ __forceinline__ Rows rows_of(const WalkCtx& C);
+template <>
+__device__ __forceinline__ DualRows rows_of<DualRows>(const WalkCtx& C) {
+  return DualRows{C.rs, C.grow, C.st->compact_rows};
+}
+template <>
+__device__ __forceinline__ FullRows rows_of<FullRows>(const WalkCtx& C) {
+  return FullRows{C.rs};
+}
+template <>
+__device__ __forceinline__ CompactRows rows_of<CompactRows>(const WalkCtx& C) {
+  return CompactRows{C.grow};
+}
+
 __device__ __forceinline__ double breakpoint(double xb, double r, double a, double eps, bool is_int) {
   double t = xb + (eps - r) / a;
   if (is_int) t = (a > 0.0) ? floor(t) : ceil(t);
@@ -163,7 +206,8 @@ __device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int n
 // k_short: one lane per column (at most 8 normalised entries).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void flip_column(const DevProblem& P, const double* x, const RowState* rs,
+template <typename Rows>
+__device__ __forceinline__ void flip_column(const DevProblem& P, const double* x, const Rows& rs,
                                             const WalkState* st, double* xhat, double* sc, int q) {
   const double eps = P.eps;
   const double xb = x[q];
@@ -207,8 +251,8 @@ struct ShortSlots {
   }
 };
 
-template <int D>
-__device__ __forceinline__ void short_general(const DevProblem& P, const double* x, const RowState* rs,
+template <int D, typename Rows>
+__device__ __forceinline__ void short_general(const DevProblem& P, const double* x, const Rows& rs,
                                               const WalkState* st, double* xhat, double* sc, int q) {
   const double eps = P.eps;
   const double xb = x[q];
@@ -277,16 +321,18 @@ __device__ __forceinline__ void short_general(const DevProblem& P, const double*
 // Short columns occupy the internal range [seg[0], seg[10]): binaries in
 // [seg[0], seg[1]), then non-binary columns with D stored entries in
 // [seg[1 + D], seg[2 + D]) for D = 0..8.
+template <typename Rows>
 __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const Rows rs = rows_of<Rows>(C);
   if (C.st->k >= C.st->iters) return;
   const int32_t* seg = C.plan.short_seg;
   const int q = seg[0] + lb * 256 + threadIdx.x;
   if (q >= seg[kShortMax + 2]) return;
   if (q < seg[1]) {
-    flip_column(C.P, C.x, C.rs, C.st, C.xhat, C.s, q);
+    flip_column(C.P, C.x, rs, C.st, C.xhat, C.s, q);
     return;
   }
   int D = 0;
@@ -294,15 +340,15 @@ __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks
   for (int k = 1; k <= kShortMax; ++k)
     if (q >= seg[1 + k]) D = k;
   switch (D) {
-    case 0: short_general<0>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 1: short_general<1>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 2: short_general<2>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 3: short_general<3>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 4: short_general<4>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 5: short_general<5>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 6: short_general<6>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    case 7: short_general<7>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
-    default: short_general<8>(C.P, C.x, C.rs, C.st, C.xhat, C.s, q); break;
+    case 0: short_general<0>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 1: short_general<1>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 2: short_general<2>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 3: short_general<3>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 4: short_general<4>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 5: short_general<5>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 6: short_general<6>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    case 7: short_general<7>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    default: short_general<8>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
   }
 }
 
@@ -310,13 +356,14 @@ __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks
 // k_flip_wave: one wavefront per longer binary column.
 // ---------------------------------------------------------------------------
 
+template <typename Rows>
 __global__ __launch_bounds__(256) void k_flip_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                    int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const DevProblem& P = C.P;
   const double* x = C.x;
-  const RowState* rs = C.rs;
+  const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
@@ -398,13 +445,14 @@ __device__ __forceinline__ void narrow_finish(double binv, double beta, double a
 // entry finds its column by binary search over the column starts and adds
 // into that column's 64 LDS bins, beta, alpha and candidate mask. Each
 // wavefront then scans and reduces a quarter of the pack's columns.
+template <typename Rows>
 __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__ walks,
                                                      const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const DevProblem& P = C.P;
   const double* x = C.x;
-  const RowState* rs = C.rs;
+  const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
@@ -511,13 +559,14 @@ __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__
 // candidate mask of the chunk go to the chunk's partial record. Chunks are
 // cut along row ranges and ordered so that consecutive workgroups (placed on
 // consecutive XCDs) gather rows from one range each.
+template <typename Rows>
 __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict__ walks,
                                                       const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const DevProblem& P = C.P;
   const double* x = C.x;
-  const RowState* rs = C.rs;
+  const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   ChunkPartial* partials = C.partials;
   if (st->k >= st->iters) return;
@@ -634,8 +683,8 @@ constexpr int kPadMarker = 3;
 
 // Emits the entries of column j into (pos, marker, delta) arrays through an
 // atomic slot counter; beta/alpha are accumulated per thread.
-template <typename Emit>
-__device__ __forceinline__ void general_phase1(const DevProblem& P, const RowState* rs, const WalkState* st,
+template <typename Rows, typename Emit>
+__device__ __forceinline__ void general_phase1(const DevProblem& P, const Rows& rs, const WalkState* st,
                                                int j, double xb, int tid, int nthreads, double& beta,
                                                double& alpha, Emit emit) {
   const double eps = P.eps;
@@ -764,14 +813,14 @@ __device__ __forceinline__ void scan_argmax(PosT pos, MarkT mk, DelT dl, int cap
   bestp = found ? pos[bk] : xb;
 }
 
-template <int CAP>
+template <int CAP, typename Rows>
 __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                     int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const DevProblem& P = C.P;
   const double* x = C.x;
-  const RowState* rs = C.rs;
+  const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
@@ -815,13 +864,14 @@ __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ 
   if (threadIdx.x == 0) write_result(xhat, sc, j, found, best, bestp, xb);
 }
 
+template <typename Rows>
 __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ walks,
                                                     const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const DevProblem& P = C.P;
   const double* x = C.x;
-  const RowState* rs = C.rs;
+  const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
@@ -1029,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
   if (tid == 0) scount = 0;
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
-  general_phase1(P, C.rs, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
+  general_phase1(P, FullRows{C.rs}, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
     const int k = atomicAdd(&scount, 1);
     spos[k] = p;
     smk[k] = m;
@@ -1107,7 +1157,8 @@ void PassStreams::destroy() {
   fork = nullptr;
 }
 
-hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
+template <typename Rows>
+hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
   const int nw = L.nw;
   auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
   hipStream_t s_short = stream, s_long = stream;
@@ -1119,27 +1170,28 @@ hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStrea
     s_long = ps->side[1];
   }
   if (L.total[KS_SHORT] > 0)
-    hipLaunchKernelGGL(k_short, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
+    hipLaunchKernelGGL(k_short<Rows>, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
   if (L.total[KS_FLIP] > 0)
-    hipLaunchKernelGGL(k_flip_wave, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
+    hipLaunchKernelGGL(k_flip_wave<Rows>, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
   if (L.total[KS_CHUNK] > 0) {
-    hipLaunchKernelGGL(k_narrow_chunk, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
+    hipLaunchKernelGGL(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
     hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
   }
   if (L.total[KS_LONG] > 0)
-    hipLaunchKernelGGL(k_sort_long, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
+    hipLaunchKernelGGL(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
   if (L.total[KS_PACK] > 0)
-    hipLaunchKernelGGL(k_narrow_pack, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
+    hipLaunchKernelGGL(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
   if (L.total[KS_SORT0] > 0)
-    hipLaunchKernelGGL(k_sort_block<64>, grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
+    hipLaunchKernelGGL((k_sort_block<64, Rows>), grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
   if (L.total[KS_SORT0 + 1] > 0)
-    hipLaunchKernelGGL(k_sort_block<256>, grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 1], nw);
+    hipLaunchKernelGGL((k_sort_block<256, Rows>), grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks,
+                       L.off[KS_SORT0 + 1], nw);
   if (L.total[KS_SORT0 + 2] > 0)
-    hipLaunchKernelGGL(k_sort_block<1024>, grid(KS_SORT0 + 2), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 2],
-                       nw);
+    hipLaunchKernelGGL((k_sort_block<1024, Rows>), grid(KS_SORT0 + 2), dim3(256), 0, stream, L.walks,
+                       L.off[KS_SORT0 + 2], nw);
   if (L.total[KS_SORT0 + 3] > 0)
-    hipLaunchKernelGGL(k_sort_block<4096>, grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks, L.off[KS_SORT0 + 3],
-                       nw);
+    hipLaunchKernelGGL((k_sort_block<4096, Rows>), grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks,
+                       L.off[KS_SORT0 + 3], nw);
   hipError_t e = hipGetLastError();
   if (ps) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
@@ -1148,6 +1200,12 @@ hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStrea
     }
   }
   return e;
+}
+
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
+  if (L.compact == 1) return launch_pass_rows<CompactRows>(L, stream, ps);
+  if (L.compact == 2) return launch_pass_rows<DualRows>(L, stream, ps);
+  return launch_pass_rows<FullRows>(L, stream, ps);
 }
 
 }  // namespace chap

@@ -191,6 +191,7 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
   st->mv_j = -1;
   st->mv_kind = 2;
   st->dV = 0ull;
+  st->compact_rows = 1;
   if (check_incumbent) incumbent_check(st, eps);
 }
 
@@ -481,6 +482,7 @@ __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks
       const RowState q = rs[i];
       const double r2 = recompute ? row_residual(P, x, i, jstar, xn) : q.r + P.col_val[e] * d;
       rs[i].r = r2;
+      if (C.grow) C.grow[i].r = (int32_t)r2;
       dv += viol_change(q.r, r2, eps);
       if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
     }
@@ -489,8 +491,14 @@ __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks
   } else {
     for (int i = gt; i < P.ms; i += gs) {
       const RowState q = rs[i];
-      if (q.r > eps) rs[i].w0 = q.w0 + 1.0f;
-      if (q.w1 >= 0.0f && -q.r > eps) rs[i].w1 = q.w1 + 1.0f;
+      if (q.r > eps) {
+        rs[i].w0 = q.w0 + 1.0f;
+        if (C.grow) C.grow[i].w0 = (uint16_t)(q.w0 + 1.0f);
+      }
+      if (q.w1 >= 0.0f && -q.r > eps) {
+        rs[i].w1 = q.w1 + 1.0f;
+        if (C.grow) C.grow[i].w1 = (uint16_t)(q.w1 + 1.0f);
+      }
     }
   }
 }
@@ -560,6 +568,34 @@ __global__ __launch_bounds__(256) void k_scatter2(const int32_t* __restrict__ pe
   const int j = perm[q];
   da[j] = a[q];
   db[j] = b[q];
+}
+
+__global__ __launch_bounds__(256) void k_fill_compact(const RowState* __restrict__ rs, GatherRow* __restrict__ grow,
+                                                      int32_t ms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ms) return;
+  const RowState q = rs[i];
+  GatherRow g;
+  g.r = (int32_t)q.r;
+  g.w0 = (uint16_t)q.w0;
+  g.w1 = q.w1 >= 0.0f ? (uint16_t)q.w1 : kNoTwin;
+  grow[i] = g;
+}
+
+__global__ __launch_bounds__(256) void k_fill_compact_checked(const RowState* __restrict__ rs,
+                                                              GatherRow* __restrict__ grow, WalkState* st,
+                                                              int32_t ms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ms) return;
+  const RowState q = rs[i];
+  const bool ok = q.r == floor(q.r) && fabs(q.r) <= 2147483647.0 && q.w0 == floorf(q.w0) && q.w0 >= 0.0f &&
+                  q.w0 < 65535.0f && (q.w1 < 0.0f || (q.w1 == floorf(q.w1) && q.w1 < 65535.0f));
+  if (!ok) st->compact_rows = 0;  // every writer stores the same value
+  GatherRow g;
+  g.r = ok ? (int32_t)q.r : 0;
+  g.w0 = ok ? (uint16_t)q.w0 : 0;
+  g.w1 = (ok && q.w1 >= 0.0f) ? (uint16_t)q.w1 : kNoTwin;
+  grow[i] = g;
 }
 
 inline int blocks_for(int64_t work, int cap) {
@@ -643,6 +679,18 @@ hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, in
 hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
                            hipStream_t stream) {
   if (n > 0) hipLaunchKernelGGL(k_scatter2, dim3((n + 255) / 256), dim3(256), 0, stream, perm, a, b, da, db, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_compact_checked(const RowState* rs, GatherRow* grow, WalkState* st, int32_t ms,
+                                       hipStream_t stream) {
+  if (ms > 0)
+    hipLaunchKernelGGL(k_fill_compact_checked, dim3((ms + 255) / 256), dim3(256), 0, stream, rs, grow, st, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_compact(const RowState* rs, GatherRow* grow, int32_t ms, hipStream_t stream) {
+  if (ms > 0) hipLaunchKernelGGL(k_fill_compact, dim3((ms + 255) / 256), dim3(256), 0, stream, rs, grow, ms);
   return hipGetLastError();
 }
 

@@ -375,3 +375,23 @@ def test_autotune_picks_a_candidate(chap):
     T = chap.Problem(mip, short_max=best2.short_max, chunk_min=best2.chunk_min, chunk_len=best2.chunk_len,
                      graph_iters=best2.graph_iters)
     np.testing.assert_array_equal(T.tabu_run(100, 10, 3).trace, G.tabu_run(100, 10, 3).trace)
+
+
+@pytest.mark.parametrize("wkind", ["integral", "fractional", "large"])
+def test_best_shift_weight_kinds(chap, wkind):
+    """All-integer instances let a single pass gather a compact copy of the
+    rows when the caller's weights are integers below 65535; fractional or
+    large weights must take the full-row path. Both agree with the oracle."""
+    mip = mipgen.random_mixed(91, n=300, m=200, max_row_nnz=8, int_width=30, long_cols=3, long_deg=60)
+    P = oracle.OracleProblem(mip)
+    x = mipgen.random_point(mip, 4)
+    w = mipgen.random_weights(P.mp + 1, 5)
+    if wkind == "fractional":
+        w = w + np.float32(0.5)
+    elif wkind == "large":
+        w[::7] = 70000.0
+    say(f"best_shift weights {wkind}")
+    xh, s = gpu_best_shift(chap, mip, x, w)
+    oxh, os_ = P.best_shift(x, w)
+    assert_same(xh, oxh, f"shift ({wkind} weights)")
+    assert_same(s, os_, f"score ({wkind} weights)")
