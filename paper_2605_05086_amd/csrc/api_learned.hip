@@ -132,7 +132,7 @@ hipError_t capture_block(const BatchLaunch& BL, const WalkCtx* C, const LearnCtx
   // proposal iterations
   for (int32_t t = 1; t < o.full_every && e == hipSuccess; ++t) {
     if (Lh.n_elig > 0) e = launch_learn_propose(C, L, Lh, M, n, 0, s);
-    if (e == hipSuccess && Lh.n_elig > 0) e = launch_subset_pass(C, L, Lh, has_general, s);
+    if (e == hipSuccess && Lh.n_elig > 0) e = launch_subset_pass(C, L, Lh, has_general, BL.compact, s);
     if (e == hipSuccess) e = launch_subset_select(C, L, s);
     if (e == hipSuccess) e = launch_walk_apply(BL, s);
     if (e == hipSuccess) e = launch_walk_finish(BL, s);

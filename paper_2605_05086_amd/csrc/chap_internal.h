@@ -352,7 +352,7 @@ constexpr int kRadixBins = 2048;    // radix-select digit bins (11, 11, 10 bits)
 constexpr int kTopkChunk = 4096;    // columns per workgroup of the top-K compaction
 constexpr int kTopkMax = 8192;      // largest proposal set
 constexpr int kSubsetCap = 4096;    // breakpoint capacity of the subset sort workgroup
-constexpr int kSubsetChunk = 1024;  // stored entries per workgroup chunk of the subset pass
+constexpr int kSubsetChunk = 2048;  // stored entries per workgroup chunk of the subset pass
 constexpr int kSubsetGrid = 2048;   // workgroups of the subset chunk kernel (grid-stride)
 constexpr int kRefreshShort = 64;   // stored entries up to which 8 lanes refresh a column
 constexpr int kRefreshChunk = 4096; // stored entries per workgroup chunk of the long-column refresh
@@ -454,7 +454,7 @@ hipError_t launch_learn_judge(const WalkCtx* C, const LearnCtx* L, hipStream_t s
 hipError_t launch_learn_features_out(const WalkCtx* C, const LearnCtx* L, int32_t n, int64_t k, int64_t k_last_full,
                                      uint16_t* out, hipStream_t s);
 // Exact best shift of the proposal set (kernels_pass.hip).
-hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general,
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
                               hipStream_t s);
 // Move choice over the proposal set and the stored-row update of its move
 // (kernels_walk.hip).

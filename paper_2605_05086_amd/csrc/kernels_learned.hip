@@ -373,21 +373,33 @@ __global__ __launch_bounds__(256) void k_learn_score(const WalkCtx* __restrict__
   const int ntiles = (n + 15) / 16;
   const int stride = gridDim.x * 4;
   const bf16x4 zero = {0, 0, 0, 0};
-  int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  // the next tile's inputs are loaded before the current tile is computed
-  bf16x4 x = (tile < ntiles && tile * 16 + r < n) ? assemble(L.feat, tile * 16 + r, g, k, Gl) : zero;
-  for (; tile < ntiles; tile += stride) {
-    const int q = tile * 16 + r;
-    const int qn = q + stride * 16;
-    const bf16x4 xn = (qn < n) ? assemble(L.feat, qn, g, k, Gl) : zero;
-    Acts A;
-    forward(W, x, A);
-    if (l < 16 && q < n) {
-      const uint32_t key = L.cls[q] != SUB_NONE ? order_key(A.y) : 0u;
-      L.keys[0][q] = key;
-      if (key) atomicAdd(&hist[key >> 21], 1u);
+  // a ring of kScoreDepth tiles per wavefront: the inputs of the tile
+  // kScoreDepth steps ahead are loaded while the current one is computed
+  constexpr int kScoreDepth = 8;
+  const int tile0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  bf16x4 ring[kScoreDepth];
+#pragma unroll
+  for (int d = 0; d < kScoreDepth; ++d) {
+    const int t = tile0 + d * stride;
+    ring[d] = (t < ntiles && t * 16 + r < n) ? assemble(L.feat, t * 16 + r, g, k, Gl) : zero;
+  }
+  for (int base = tile0; base < ntiles; base += kScoreDepth * stride) {
+#pragma unroll
+    for (int d = 0; d < kScoreDepth; ++d) {
+      const int t = base + d * stride;
+      if (t >= ntiles) break;
+      const bf16x4 x = ring[d];
+      const int tn = t + kScoreDepth * stride;
+      ring[d] = (tn < ntiles && tn * 16 + r < n) ? assemble(L.feat, tn * 16 + r, g, k, Gl) : zero;
+      Acts A;
+      forward(W, x, A);
+      const int q = t * 16 + r;
+      if (l < 16 && q < n) {
+        const uint32_t key = L.cls[q] != SUB_NONE ? order_key(A.y) : 0u;
+        L.keys[0][q] = key;
+        if (key) atomicAdd(&hist[key >> 21], 1u);
+      }
     }
-    x = xn;
   }
   flush_hist(hist, L.hist);
 }
@@ -767,7 +779,7 @@ hipError_t launch_learn_begin(const WalkCtx* C, const LearnCtx* L, hipStream_t s
 hipError_t launch_learn_propose(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                                 int32_t n, int full_iteration, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_learn_score, dim3(grid_for(n, 128, 4096)), dim3(256), 0, s, C, L, M.w, M.wb, n);
+  hipLaunchKernelGGL(k_learn_score, dim3(grid_for(n, 64, 768)), dim3(256), 0, s, C, L, M.w, M.wb, n);
   return topk(C, L, Lh, 0, full_iteration, n, s);
 }
 

@@ -123,13 +123,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
     bf16x4 g2b[4];
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
+      float v[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         accW3[o][t] += g3 * bf2f((uint16_t)A.h2[o][t]);
-        const float v = (A.z2[o][t] > 0.0f) ? g3 * w3r[o][t] : 0.0f;
-        accB2[o][t] += v;
-        g2b[o][t] = (short)f2bf(v);
+        v[t] = (A.z2[o][t] > 0.0f) ? g3 * w3r[o][t] : 0.0f;
+        accB2[o][t] += v[t];
       }
+      g2b[o] = to_bf16x4(v[0], v[1], v[2], v[3]);
     }
     // dL/dh1 = W2^T g2, gated by z1 > 0
     bf16x4 g1b[4];
@@ -138,12 +139,13 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
       f32x4 acc = zero4;
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob) acc = mma(a2t[ib][ob], g2b[ob], acc);
+      float v[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float v = (A.z1[ib][t] > 0.0f) ? acc[t] : 0.0f;
-        accB1[ib][t] += v;
-        g1b[ib][t] = (short)f2bf(v);
+        v[t] = (A.z1[ib][t] > 0.0f) ? acc[t] : 0.0f;
+        accB1[ib][t] += v[t];
       }
+      g1b[ib] = to_bf16x4(v[0], v[1], v[2], v[3]);
     }
     // transpose the tile through LDS: unit-major rows of 16 samples
 #pragma unroll

@@ -941,10 +941,12 @@ __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ 
 // (k_subset_general).
 // ---------------------------------------------------------------------------
 
+template <typename Rows>
 __global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict__ walks,
                                                        const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
   const LearnCtx& L = *lc;
+  const Rows rs = rows_of<Rows>(C);
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
@@ -975,7 +977,7 @@ __global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict
       const double d = (1.0 - xb) - xb;
       double v = 0.0;
       for (int e = e_beg + tid; e < e_end; e += blockDim.x) {
-        const RowState r = C.rs[P.col_row[e]];
+        const RowState r = rs[P.col_row[e]];
         const double r2 = r.r + P.col_val[e] * d;
         v += penalty(r.r, r2, (double)r.w0, eps);
         if (r.w1 >= 0.0f) v += penalty(-r.r, -r2, (double)r.w1, eps);
@@ -995,7 +997,7 @@ __global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict
     double beta = 0.0, alpha = 0.0;
     unsigned long long cand = 0ull;
     for (int e = e_beg + tid; e < e_end; e += blockDim.x) {
-      const RowState r = C.rs[P.col_row[e]];
+      const RowState r = rs[P.col_row[e]];
       const double a = P.col_val[e];
       narrow_entry(xb, r.r, a, (double)r.w0, eps, l, u, W, bins, beta, alpha, cand);
       if (r.w1 >= 0.0f) narrow_entry(xb, -r.r, -a, (double)r.w1, eps, l, u, W, bins, beta, alpha, cand);
@@ -1106,11 +1108,14 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
 
 }  // namespace
 
-hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general,
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
                               hipStream_t s) {
   const int K = Lh.K[0];
-  hipLaunchKernelGGL(k_subset_chunks, dim3((unsigned)std::min(kSubsetGrid, std::max(Lh.sub_cap, 1))), dim3(256), 0, s,
-                     C, L);
+  const dim3 grid((unsigned)std::min(kSubsetGrid, std::max(Lh.sub_cap, 1)));
+  if (compact)
+    hipLaunchKernelGGL(k_subset_chunks<CompactRows>, grid, dim3(256), 0, s, C, L);
+  else
+    hipLaunchKernelGGL(k_subset_chunks<FullRows>, grid, dim3(256), 0, s, C, L);
   hipLaunchKernelGGL(k_subset_combine, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, C, L);
   if (has_general) hipLaunchKernelGGL(k_subset_general, dim3((unsigned)K), dim3(256), 0, s, C, L);
   return hipGetLastError();

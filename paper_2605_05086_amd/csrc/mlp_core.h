@@ -11,7 +11,8 @@
 //   D[i][j]: j = r, i = 4g + t
 // The D layout of one layer equals the B layout of the next, so hidden
 // activations pass between layers in registers: bias, ReLU and the rounding
-// to bfloat16 are applied in place.
+// to bfloat16 (the native packed conversion, round to nearest even) are
+// applied in place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,11 +85,27 @@ struct Acts {
   float y;  // network output of sample r, valid on lanes with g == 0
 };
 
-__device__ __forceinline__ bf16x4 relu_bf16(f32x4 z) {
+typedef __bf16 bf16x2n __attribute__((ext_vector_type(2)));
+
+// Four FP32 values to bfloat16 (round to nearest even) with the native
+// packed conversion.
+__device__ __forceinline__ bf16x4 to_bf16x4(float a, float b, float c, float d) {
+  bf16x2n lo, hi;
+  lo[0] = (__bf16)a;
+  lo[1] = (__bf16)b;
+  hi[0] = (__bf16)c;
+  hi[1] = (__bf16)d;
+  const uint32_t ul = __builtin_bit_cast(uint32_t, lo), uh = __builtin_bit_cast(uint32_t, hi);
   bf16x4 h;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) h[t] = (short)f2bf(z[t] > 0.0f ? z[t] : 0.0f);
+  h[0] = (short)(ul & 0xFFFFu);
+  h[1] = (short)(ul >> 16);
+  h[2] = (short)(uh & 0xFFFFu);
+  h[3] = (short)(uh >> 16);
   return h;
+}
+
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 z) {
+  return to_bf16x4(fmaxf(z[0], 0.0f), fmaxf(z[1], 0.0f), fmaxf(z[2], 0.0f), fmaxf(z[3], 0.0f));
 }
 
 // x: the tile's inputs in B layout (sample r, inputs 4g..4g+3) as bfloat16.
