@@ -24,6 +24,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per best-shift pass on the 20M-nonzero instance, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) over k_short, k_narrow_pack,
+# k_narrow_chunk and k_narrow_combine, scaled by the counters of a 1 GiB
+# device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see
+# profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the pass
+# kernels as they are; set to None when they change until measured again.
+PASS_TRAFFIC_BYTES = 1_161_000_000
 METRIC = "tabu moves/s, best-shift nnz/s, % HBM peak; plain vs batched/learned"
 
 
@@ -69,6 +76,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned-proposal and batched-walk comparisons against the plain walk")
     ap.add_argument("--batch-iters", type=int, default=200)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-walk comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path does not "
@@ -154,14 +162,16 @@ def main():
         "best_shift_pass_us": pass_ms * 1e3,
         "best_shift_nnz_per_s": nnz_pass / (pass_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": PASS_TRAFFIC_BYTES if not args.small else None,
                      "kernel": "best-shift pass (k_short + k_narrow_pack + k_narrow_chunk + k_narrow_combine)",
                      "bytes_per_launch": B},
     }
     if not args.no_compare:
         result["learned"] = compare_learned(chap, G, tr, wall, args.steps, tenure, seed)
         del G
-        result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small)
+        if not args.no_batched:
+            result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations")
         result["cpu_baseline"] = cpu_baseline(mip, args.cpu_iters)
