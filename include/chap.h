@@ -62,6 +62,12 @@ typedef struct {
                            64 values is split over workgroups; 0 = 4096 */
   int32_t chunk_len;    /* nonzeros per workgroup chunk for those columns;
                            0 = 4096 */
+  int32_t row_stage;    /* 1 (default, also 0): on all-integer instances whose
+                           row activities fit int32, score short and packed
+                           columns with at most 64 values from per-entry
+                           records made by workgroups that each gather rows
+                           from one eighth of the rows (the same results,
+                           fewer HBM bytes); -1: never */
 } chap_options;
 
 /* One trace record per tabu iteration (48 bytes, host order). */

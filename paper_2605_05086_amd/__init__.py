@@ -27,7 +27,7 @@ TRACE_DTYPE = np.dtype([
 
 class ChapOptions(ctypes.Structure):
     _fields_ = [("feas_tol", ctypes.c_double), ("graph_iters", ctypes.c_int32), ("short_max", ctypes.c_int32),
-                ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32)]
+                ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("row_stage", ctypes.c_int32)]
 
 
 class LearnedOptions(ctypes.Structure):
@@ -213,7 +213,7 @@ class Problem:
     """chap_problem_create on a MIP in original form (host numpy arrays)."""
 
     def __init__(self, mip, feas_tol: float = 1e-6, graph_iters: int = 0, short_max: int = 0, chunk_min: int = 0,
-                 chunk_len: int = 0):
+                 chunk_len: int = 0, row_stage: int = 0):
         lib = load_library()
         self._keep = dict(
             csr_row_ptr=np.ascontiguousarray(mip.csr_row_ptr, dtype=np.int64),
@@ -235,6 +235,7 @@ class Problem:
         o.short_max = short_max
         o.chunk_min = chunk_min
         o.chunk_len = chunk_len
+        o.row_stage = row_stage
         h = ctypes.c_void_p()
         k = self._keep
         _check(lib.chap_problem_create(ctypes.byref(h), int(mip.n), int(mip.m), _ptr(k["csr_row_ptr"]),

@@ -72,6 +72,7 @@ void chap_options_default(chap_options* opt) {
   opt->short_max = kShortMax;
   opt->chunk_min = 4096;
   opt->chunk_len = 4096;
+  opt->row_stage = 1;
 }
 
 const char* chap_last_error(void) { return g_error.c_str(); }
@@ -103,8 +104,9 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
       return fail(CHAP_EINVAL, "chap_problem_create: feas_tol must be finite and >= 0");
     o.feas_tol = opt->feas_tol;
     if (opt->graph_iters < 0 || opt->short_max < 0 || opt->short_max > kShortMax || opt->chunk_min < 0 ||
-        opt->chunk_len < 0)
+        opt->chunk_len < 0 || opt->row_stage < -1 || opt->row_stage > 1)
       return fail(CHAP_EINVAL, "chap_problem_create: option out of range");
+    if (opt->row_stage) o.row_stage = opt->row_stage;
     if (opt->graph_iters) o.graph_iters = opt->graph_iters;
     if (opt->short_max) o.short_max = opt->short_max;
     if (opt->chunk_min) o.chunk_min = opt->chunk_min;
@@ -295,11 +297,29 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     else
       cls[j] = GENERAL;
   }
+  // Row-range staging needs integer residuals and coefficients (compact_ok)
+  // and 0 < eps <= 1/2, under which the integer breakpoint is xbar plus the
+  // floor or ceiling of -r/a. The bound below keeps FP64 rounding of
+  // xbar + (eps - r)/a near [l, u] (error below 6 * 2^-53 * max(|l|,|u|) + 1
+  // relative units) under eps / max|a|, the least distance of that quotient
+  // from an integer, so the FP64 breakpoint equals the integer one.
+  bool stage = P->compact_ok && o.row_stage == 1 && P->eps > 0.0 && P->eps <= 0.5;
+  if (stage) {
+    double amax = 0.0, lmax = 0.0;
+    for (double a : rval) amax = std::max(amax, std::fabs(a));
+    for (int32_t j = 0; j < n; ++j)
+      if (cls[j] == NARROW) lmax = std::max(lmax, std::max(std::fabs(P->lb[j]), std::fabs(P->ub[j])) + 1.0);
+    stage = amax < 4194304.0 && lmax * amax <= P->eps * 17592186044416.0 &&  // 2^22, 2^44
+            (int64_t)m <= (int64_t)kStageMaxRb * kStageRowBlock;
+  }
   std::vector<std::vector<int32_t>> short_seg(kShortMax + 2), sortl(kSortCaps);
-  std::vector<int32_t> flip, narrow, chunked, longg;
+  std::vector<int32_t> flip, narrow, chunked, longg, sshort;
   for (int32_t j = 0; j < n; ++j) {
     if (ne[j] <= o.short_max) {
-      short_seg[cls[j] == BIN ? 0 : 1 + deg[j]].push_back(j);
+      if (stage && cls[j] == NARROW)
+        sshort.push_back(j);
+      else
+        short_seg[cls[j] == BIN ? 0 : 1 + deg[j]].push_back(j);
     } else if (cls[j] == BIN) {
       flip.push_back(j);
     } else if (cls[j] == NARROW) {
@@ -349,6 +369,10 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     if (t.q_end > t.q_begin) packs.push_back(t);
   }
   append(narrow);
+  L.stage_short_begin = (int32_t)perm.size();
+  std::stable_sort(sshort.begin(), sshort.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  append(sshort);
+  L.stage_short_end = (int32_t)perm.size();
   const int32_t chunk_begin = (int32_t)perm.size();
   append(chunked);
   for (int c = 0; c < kSortCaps; ++c) {
@@ -435,6 +459,77 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
         }
       }
   }
+  // staged tasks (narrow packs, then groups of short narrow columns of one
+  // degree); the staged entries in (row block, task, column, row) order; the
+  // segment table of every task and row block; workgroup slices of each row
+  // block, XCD-interleaved so that the slices of one block share an L2
+  std::vector<StageTask> stasks;
+  std::vector<int32_t> sseg;
+  std::vector<uint64_t> sent;
+  std::vector<StageRowTask> srtasks;
+  if (stage) {
+    for (const PackTask& t : packs) stasks.push_back(StageTask{t.q_begin, t.q_end, -1, 0});
+    packs.clear();
+    const int32_t npk = (int32_t)stasks.size();
+    for (int32_t q = L.stage_short_begin; q < L.stage_short_end;) {
+      const int32_t d = deg[perm[q]];
+      int32_t e = q + 1;
+      while (e < L.stage_short_end && e - q < kStageShort && deg[perm[e]] == d) ++e;
+      stasks.push_back(StageTask{q, e, d, 0});
+      q = e;
+    }
+    const size_t T = stasks.size();
+    const int32_t nrb = (int32_t)(((int64_t)m + kStageRowBlock - 1) / kStageRowBlock);
+    std::vector<std::vector<uint64_t>> ent_rb(nrb);
+    sseg.assign((T + 1) * (size_t)nrb, 0);
+    for (size_t t = 0; t < T; ++t) {
+      for (int32_t rb = 0; rb < nrb; ++rb) sseg[t * nrb + rb] = (int32_t)ent_rb[rb].size();
+      for (int32_t q = stasks[t].q_begin; q < stasks[t].q_end; ++q) {
+        const uint64_t lc = (uint64_t)(q - stasks[t].q_begin);
+        for (int32_t e = cptr[q]; e < cptr[q + 1]; ++e) {
+          const int32_t i = crow[e], rb = i / kStageRowBlock;
+          const uint64_t a24 = (uint64_t)((uint32_t)(int32_t)cval[e] & 0xFFFFFFu);
+          ent_rb[rb].push_back((uint64_t)(i - rb * kStageRowBlock) | (lc << 16) | (a24 << 24));
+        }
+      }
+    }
+    for (int32_t rb = 0; rb < nrb; ++rb) sseg[T * nrb + rb] = (int32_t)ent_rb[rb].size();
+    std::vector<std::vector<StageRowTask>> per_xcd(kXcds);
+    for (int32_t rb = 0; rb < nrb; ++rb) {
+      const int32_t e0 = (int32_t)sent.size();
+      for (size_t t = 0; t <= T; ++t) sseg[t * nrb + rb] += e0;
+      sent.insert(sent.end(), ent_rb[rb].begin(), ent_rb[rb].end());
+      const int32_t e1 = (int32_t)sent.size();
+      for (int32_t b = e0; b < e1; b += kStageSlice)
+        per_xcd[rb % kXcds].push_back(StageRowTask{rb, b, std::min(e1, b + kStageSlice), 0});
+    }
+    // per task: segment starts, then prefix counts of its records
+    {
+      const size_t per = 2 * (size_t)nrb + 1;
+      std::vector<int32_t> tab(T * per);
+      for (size_t t = 0; t < T; ++t) {
+        int32_t run = 0;
+        for (int32_t rb = 0; rb < nrb; ++rb) {
+          tab[t * per + rb] = sseg[t * nrb + rb];
+          tab[t * per + nrb + rb] = run;
+          run += sseg[(t + 1) * nrb + rb] - sseg[t * nrb + rb];
+        }
+        tab[t * per + 2 * nrb] = run;
+      }
+      sseg.swap(tab);
+    }
+    size_t rounds = 0;
+    for (const auto& v : per_xcd) rounds = std::max(rounds, v.size());
+    for (size_t k = 0; k < rounds; ++k)
+      for (int x = 0; x < kXcds; ++x)
+        srtasks.push_back(k < per_xcd[x].size() ? per_xcd[x][k] : StageRowTask{-1, 0, 0, 0});
+    L.n_stage_ent = (int32_t)sent.size();
+    L.n_stage_tasks = (int32_t)T;
+    L.n_stage_packs = npk;
+    L.n_stage_rtasks = (int32_t)srtasks.size();
+    L.n_stage_rb = nrb;
+    L.stage = T > 0 ? 1 : 0;
+  }
   std::vector<LongTask> longs;
   int64_t long_total = 0;
   for (int32_t q = long_begin; q < n; ++q) {
@@ -517,6 +612,20 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     L.packs = dp;
     L.n_packs = (int32_t)packs.size();
   }
+  if (L.stage) {
+    StageTask* dt;
+    int32_t* dseg;
+    uint64_t* dent;
+    StageRowTask* drt;
+    CHAP_HIP(A.upload(&dt, stasks));
+    CHAP_HIP(A.upload(&dseg, sseg));
+    CHAP_HIP(A.upload(&dent, sent));
+    CHAP_HIP(A.upload(&drt, srtasks));
+    L.stage_tasks = dt;
+    L.stage_seg = dseg;
+    L.stage_ent = dent;
+    L.stage_rtasks = drt;
+  }
   if (!tasks.empty()) {
     ChunkTask* dt;
     CHAP_HIP(A.upload(&dt, tasks));
@@ -561,6 +670,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.alloc(&c.long_pos, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.long_delta, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.long_marker, (size_t)P->plan.long_scratch));
+    CHAP_HIP(A.alloc(&c.stage_rec, (size_t)P->plan.n_stage_ent));
     CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &P->bs_launch));
     P->bs_launch.compact = P->compact_ok ? 2 : 0;
   }
@@ -662,6 +772,7 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
   CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
+  CHAP_HIP(A.alloc(&c.stage_rec, (size_t)p->plan.n_stage_ent));
   CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
   if (n > 0) {
     CHAP_HIP(hipMemcpyAsync(c.x, xq.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));

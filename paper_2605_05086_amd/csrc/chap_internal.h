@@ -179,6 +179,47 @@ struct __align__(16) ChunkPartial {
   double pad;
 };
 
+// Row-block staging (all-integer instances). The stored entries of narrow
+// packs and of short narrow columns are kept a second time, grouped by the
+// block of kStageRowBlock stored rows they touch. A workgroup of k_stage_rows
+// copies one row block into LDS and turns a slice of that block's entries
+// into per-entry records (in entry order), so no gather leaves the
+// workgroup's LDS. A scoring task finds its records in one segment per row
+// block. For integer r and a and 0 < eps < 1 the integer
+// breakpoint of Algorithm 1 phase 1 is xbar + floor(-r/a) for a > 0 and
+// xbar + ceil(-r/a) for a < 0, so a record holds the offset from xbar and
+// needs no column data.
+//
+// Staged entry (uint64): bits 0..15 row inside its block, 16..23 column
+// slot inside its task, 24..47 coefficient (24-bit two's complement).
+// Record (uint64): bits 0..7 column slot, bit 8 coefficient > 0, bit 9 twin
+// row present, bits 10..17 and 18..25 the offsets of the row and of its twin
+// plus 64 (clamped to [-64, 64]); bits 32..63 the weights w0 | w1 << 16 when
+// the walk keeps compact rows, else the stored row.
+constexpr int kStageRowBlock = 8192;  // stored rows per block (64 KB of LDS)
+constexpr int kStageSlice = 16384;    // staged entries per workgroup of k_stage_rows
+constexpr int kStageShort = 256;      // short narrow columns per scoring task
+constexpr int kStageClamp = 64;       // offsets beyond +-64 leave every narrow column
+constexpr int kStageMaxRb = 256;      // row blocks a scoring workgroup can index in LDS
+
+// A slice [e_beg, e_end) of the staged entries of row block rb (rb < 0: an
+// empty task that only keeps the XCD interleave).
+struct StageRowTask {
+  int32_t rb;
+  int32_t e_beg;
+  int32_t e_end;
+  int32_t pad;
+};
+
+// Columns [q_begin, q_end) scored by one workgroup of the staged kernels;
+// deg >= 0 marks a group of short columns that all hold deg stored entries.
+struct StageTask {
+  int32_t q_begin;
+  int32_t q_end;
+  int32_t deg;
+  int32_t pad;
+};
+
 // A general column whose entries exceed the largest LDS sort.
 struct LongTask {
   int32_t col;
@@ -207,6 +248,22 @@ struct PassPlan {
   const LongTask* long_tasks = nullptr;
   int32_t n_long = 0;
   int64_t long_scratch = 0;  // entries of the long-sort scratch arrays
+  // row-block staging: scoring tasks [0, n_stage_packs) are packs of narrow
+  // columns, the rest groups of at most kStageShort short narrow columns of
+  // one degree; stage_seg holds 2 n_stage_rb + 1 values per task: the first
+  // record of the task in each row block, then the task's records in the
+  // blocks before each block (the last value: all of them)
+  int32_t stage = 0;
+  int32_t n_stage_tasks = 0;
+  int32_t n_stage_packs = 0;
+  int32_t n_stage_rtasks = 0;
+  int32_t n_stage_rb = 0;
+  const StageTask* stage_tasks = nullptr;
+  const int32_t* stage_seg = nullptr;
+  const StageRowTask* stage_rtasks = nullptr;
+  const uint64_t* stage_ent = nullptr;
+  int32_t n_stage_ent = 0;
+  int32_t stage_short_begin = 0, stage_short_end = 0;
 };
 
 // Everything the kernels of one walk need: its instance, the instance's pass
@@ -229,6 +286,7 @@ struct WalkCtx {
   double* long_pos;
   double* long_delta;
   int32_t* long_marker;
+  uint64_t* stage_rec;  // records of the staged entries (row-range staging)
   int32_t argmax_blocks;
   int32_t apply_blocks;
   int32_t recompute;
@@ -243,6 +301,9 @@ enum KernelSlot {
   KS_COMBINE,
   KS_SORT0,
   KS_LONG = KS_SORT0 + kSortCaps,
+  KS_STAGE,
+  KS_STAGE_PACK,
+  KS_STAGE_SHORT,
   KS_ARGMAX,
   KS_SELECT,
   KS_APPLY,
@@ -272,6 +333,7 @@ int32_t kernel_blocks(const WalkCtx& c, int slot);
 struct PassStreams {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork = nullptr;
+  hipEvent_t mid = nullptr;  // staged records are ready (short groups may start)
   hipEvent_t join[2] = {nullptr, nullptr};
   hipError_t create();
   void destroy();

@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "chap_internal.h"
 
@@ -83,6 +84,24 @@ __device__ __forceinline__ FullRows rows_of<FullRows>(const WalkCtx& C) {
 template <>
 __device__ __forceinline__ CompactRows rows_of<CompactRows>(const WalkCtx& C) {
   return CompactRows{C.grow};
+}
+
+// Whether staged records carry the weights (exact in 16 bits): always with
+// the compact row copy, as the walk state says for single passes, never with
+// full rows (the scoring kernel then reads them from the row states).
+template <typename Rows>
+__device__ __forceinline__ bool stage_weights(const WalkCtx& C);
+template <>
+__device__ __forceinline__ bool stage_weights<CompactRows>(const WalkCtx&) {
+  return true;
+}
+template <>
+__device__ __forceinline__ bool stage_weights<DualRows>(const WalkCtx& C) {
+  return C.st->compact_rows != 0;
+}
+template <>
+__device__ __forceinline__ bool stage_weights<FullRows>(const WalkCtx&) {
+  return false;
 }
 
 __device__ __forceinline__ double breakpoint(double xb, double r, double a, double eps, bool is_int) {
@@ -251,6 +270,46 @@ struct ShortSlots {
   }
 };
 
+// Scores every candidate position of a short column (both bounds and the
+// breakpoints inside [l, u], xbar excluded) from the penalty definition: the
+// largest score, the smallest position on ties.
+__device__ __forceinline__ void short_best(const ShortSlots& S, double l, double u, double xb, bool& found,
+                                           double& best, double& bestp) {
+  found = false;
+  best = 0.0;
+  bestp = xb;
+  auto consider = [&](double p) {
+    if (!(p >= l && p <= u) || p == xb || !isfinite(p)) return;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kShortMax; ++k) {
+      if (k < S.ns) {
+        const bool ap = (S.apos >> k) & 1u;
+        const bool s0 = (S.sat0 >> k) & 1u;
+        const bool s1 = ap ? (p <= S.tau[k]) : (p >= S.tau[k]);
+        double c;
+        if (s0)
+          c = s1 ? 0.0 : -S.w[k];
+        else if (s1)
+          c = S.w[k];
+        else
+          c = (ap ? (p < xb) : (p > xb)) ? 0.5 * S.w[k] : -0.5 * S.w[k];
+        v += c;
+      }
+    }
+    if (!found || v > best || (v == best && p < bestp)) {
+      found = true;
+      best = v;
+      bestp = p;
+    }
+  };
+  consider(l);
+  consider(u);
+#pragma unroll
+  for (int k = 0; k < kShortMax; ++k)
+    if (k < S.ns) consider(S.tau[k]);
+}
+
 template <int D, typename Rows>
 __device__ __forceinline__ void short_general(const DevProblem& P, const double* x, const Rows& rs,
                                               const WalkState* st, double* xhat, double* sc, int q) {
@@ -283,38 +342,9 @@ __device__ __forceinline__ void short_general(const DevProblem& P, const double*
     const double c = P.obj[q];
     if (c != 0.0) S.push(breakpoint(xb, st->rc, c, eps, isint), (double)st->wc, c > 0.0, xb);
   }
-  bool found = false;
-  double best = 0.0, bestp = xb;
-  auto consider = [&](double p) {
-    if (!(p >= l && p <= u) || p == xb || !isfinite(p)) return;
-    double v = 0.0;
-#pragma unroll
-    for (int k = 0; k < kShortMax; ++k) {
-      if (k < S.ns) {
-        const bool ap = (S.apos >> k) & 1u;
-        const bool s0 = (S.sat0 >> k) & 1u;
-        const bool s1 = ap ? (p <= S.tau[k]) : (p >= S.tau[k]);
-        double c;
-        if (s0)
-          c = s1 ? 0.0 : -S.w[k];
-        else if (s1)
-          c = S.w[k];
-        else
-          c = (ap ? (p < xb) : (p > xb)) ? 0.5 * S.w[k] : -0.5 * S.w[k];
-        v += c;
-      }
-    }
-    if (!found || v > best || (v == best && p < bestp)) {
-      found = true;
-      best = v;
-      bestp = p;
-    }
-  };
-  consider(l);
-  consider(u);
-#pragma unroll
-  for (int k = 0; k < kShortMax; ++k)
-    if (k < S.ns) consider(S.tau[k]);
+  bool found;
+  double best, bestp;
+  short_best(S, l, u, xb, found, best, bestp);
   write_result(xhat, sc, q, found, best, bestp, xb);
 }
 
@@ -668,6 +698,515 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   double best, bestp;
   narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
   if (lane == 0) write_result(xhat, sc, q, found, best, bestp, xb);
+}
+
+// ---------------------------------------------------------------------------
+// Row-range staging (all-integer instances).
+// ---------------------------------------------------------------------------
+
+// One workgroup per slice of a row block's staged entries: the block's rows
+// go to LDS (as GatherRow; weights only when the records carry them), then
+// every entry of the slice becomes the record of the same index.
+template <typename Rows>
+__global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
+                                                    const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  const StageRowTask T = C.plan.stage_rtasks[lb];
+  if (T.rb < 0) return;
+  __shared__ GatherRow rows[kStageRowBlock];
+  const Rows rs = rows_of<Rows>(C);
+  const bool wts = stage_weights<Rows>(C);
+  const int r0 = T.rb * kStageRowBlock;
+  const int nr = min(kStageRowBlock, C.P.ms - r0);
+  const uint64_t* __restrict__ ent = C.plan.stage_ent;
+  uint64_t* __restrict__ rec = C.stage_rec;
+  constexpr int kThreads = 512;
+  constexpr int kU = 8;  // entries per thread and step, loaded before any is used
+  const int tid = threadIdx.x;
+  uint64_t wd[kU];
+  auto load_step = [&](int base) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads;
+      if (i < T.e_end) wd[u] = __builtin_nontemporal_load(&ent[i]);
+    }
+  };
+  // the first step's entries are in flight while the row block is loaded
+  load_step(T.e_beg + tid);
+  {
+    constexpr int kPer = kStageRowBlock / kThreads;
+    RowState g[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kThreads < nr) g[k] = rs[r0 + tid + k * kThreads];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kThreads < nr) {
+        GatherRow o;
+        o.r = (int32_t)g[k].r;
+        o.w0 = wts ? (uint16_t)g[k].w0 : (uint16_t)0;
+        o.w1 = g[k].w1 >= 0.0f ? (wts ? (uint16_t)g[k].w1 : (uint16_t)0) : kNoTwin;
+        rows[tid + k * kThreads] = o;
+      }
+  }
+  __syncthreads();
+  for (int base = T.e_beg + tid; base < T.e_end; base += kU * kThreads) {
+    if (base != T.e_beg + tid) load_step(base);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads;
+      if (i < T.e_end) {
+        const int local = (int)(wd[u] & 0xFFFFu);
+        const GatherRow g = rows[local];
+        const int a = ((int32_t)((uint32_t)(wd[u] >> 24) << 8)) >> 8;
+        const double qv = -(double)g.r / (double)a;
+        const double fl = fmin(fmax(floor(qv), -(double)kStageClamp), (double)kStageClamp);
+        const double ce = fmin(fmax(ceil(qv), -(double)kStageClamp), (double)kStageClamp);
+        const int d0 = (int)(a > 0 ? fl : ce);
+        const int d1 = (int)(a > 0 ? ce : fl);
+        const bool twin = g.w1 != kNoTwin;
+        const uint32_t lo = (uint32_t)((wd[u] >> 16) & 0xFFu) | ((a > 0 ? 1u : 0u) << 8) | ((twin ? 1u : 0u) << 9) |
+                            ((uint32_t)(d0 + kStageClamp) << 10) | ((uint32_t)(d1 + kStageClamp) << 18);
+        const uint32_t top = wts ? ((uint32_t)g.w0 | ((uint32_t)g.w1 << 16)) : (uint32_t)(r0 + local);
+        rec[i] = (uint64_t)lo | ((uint64_t)top << 32);
+      }
+    }
+  }
+}
+
+// Staged scoring keeps values as int32 counts of half weights when the
+// weights are integers (every term is a multiple of w/2: exact), else FP64.
+__device__ __forceinline__ int32_t stage_one(double w, int32_t) { return 2 * (int32_t)w; }
+__device__ __forceinline__ int32_t stage_half(double w, int32_t) { return (int32_t)w; }
+__device__ __forceinline__ double stage_one(double w, double) { return w; }
+__device__ __forceinline__ double stage_half(double w, double) { return 0.5 * w; }
+__device__ __forceinline__ double stage_score_of(int32_t v) { return 0.5 * (double)v; }
+__device__ __forceinline__ double stage_score_of(double v) { return v; }
+
+// One normalised row of a narrow column in offset form (coefficient sign ap,
+// breakpoint t = xbar + d, one = w and half = w/2 in value units): the cases
+// of Algorithm 1 phase 1, as phase1() takes them, decided by the sign of d.
+// The row adds beta at every position, alpha above xbar and delta from
+// offset thr on (thr = d, or d + 1 when the row holds after t).
+template <typename V>
+__device__ __forceinline__ void row_terms(bool ap, int d, V one, V half, V& beta, V& alpha, V& delta, int& thr) {
+  if (ap) {
+    thr = d + 1;
+    if (d < 0) {
+      beta += one;
+      alpha -= one;
+      delta = -half;
+    } else if (d > 0) {
+      delta = -one;
+    } else {
+      alpha -= one;
+      delta = 0;
+    }
+  } else {
+    thr = d;
+    if (d > 0) {
+      beta -= half;
+      alpha += one;
+      delta = half;
+    } else if (d < 0) {
+      beta -= one;
+      delta = one;
+    } else {
+      beta -= one;
+      alpha += one;
+      delta = 0;
+    }
+  }
+}
+
+// The same row added to a column's bins (k0 = xbar - l, W values) without
+// branches: beta goes to bin 0, alpha to bin k0 + 1 (the first position
+// above xbar), delta to the bin where it starts to apply (bin 0 when that is
+// below l); terms that apply nowhere go to the sink bin kNarrowBins. The
+// breakpoint is a candidate when inside [l, u].
+template <typename V>
+__device__ __forceinline__ void add_row(bool ap, int d, V one, V half, int k0, int W, V* bins,
+                                        unsigned long long* cand) {
+  const bool neg = d < 0, pos = d > 0;
+  const V zero = 0;
+  const V b = ap ? (neg ? one : zero) : (pos ? -half : -one);
+  const V al = ap ? (pos ? zero : -one) : (neg ? zero : one);
+  const V dl = ap ? (neg ? -half : (pos ? -one : zero)) : (pos ? half : (neg ? one : zero));
+  const int k = k0 + d;
+  const int kb = k + (ap ? 1 : 0);
+  const int idx = k < 0 ? 0 : ((k >= W || kb >= W) ? kNarrowBins : kb);
+  const int ia = k0 + 1 < W ? k0 + 1 : kNarrowBins;
+  if (b != zero) atomicAdd(&bins[0], b);
+  if (al != zero) atomicAdd(&bins[ia], al);
+  if (dl != zero) atomicAdd(&bins[idx], dl);
+  if (d != 0 && k >= 0 && k < W) atomicOr(cand, 1ull << k);
+}
+
+struct StageRec {
+  bool ap, twin;
+  int d0, d1, lc;
+  double w0, w1;
+};
+
+template <typename Rows>
+__device__ __forceinline__ StageRec decode_rec(uint64_t r, bool wts, const Rows& rs) {
+  StageRec o;
+  o.lc = (int)(r & 0xFFu);
+  o.ap = (r >> 8) & 1u;
+  o.twin = (r >> 9) & 1u;
+  o.d0 = (int)((r >> 10) & 0xFFu) - kStageClamp;
+  o.d1 = (int)((r >> 18) & 0xFFu) - kStageClamp;
+  if (wts) {
+    o.w0 = (double)((r >> 32) & 0xFFFFu);
+    o.w1 = (double)(r >> 48);
+  } else {
+    const RowState g = rs[(int)(r >> 32)];
+    o.w0 = (double)g.w0;
+    o.w1 = (double)g.w1;
+  }
+  return o;
+}
+
+// Offset of the cutoff row's breakpoint from xbar, clamped like the records.
+__device__ __forceinline__ int cutoff_offset(double xb, const WalkState* st, double c, double eps) {
+  const double t = breakpoint(xb, st->rc, c, eps, true);
+  return (int)fmin(fmax(t - xb, -(double)kStageClamp), (double)kStageClamp);
+}
+
+template <typename V>
+struct StagePackSmem {
+  V bins[kPackCols][kNarrowBins + 1];  // padded: lane c reads row c without bank conflicts
+  unsigned long long cand[kPackCols];
+  double xb[kPackCols];
+  int32_t W[kPackCols], k0[kPackCols];
+};
+
+struct StageShortSmem {
+  uint64_t rec[kShortMax][kStageShort];  // slot-major: thread c reads rec[*][c]
+  int32_t cnt[kStageShort];
+};
+
+// Segment table of scoring task t in LDS: beg[rb] = first record of the
+// task in row block rb, pre[rb] = the task's records in blocks before rb
+// (pre[nrb] = all of them). Ends with a barrier.
+struct StageSegs {
+  int32_t beg[kStageMaxRb];
+  int32_t pre[kStageMaxRb + 1];
+};
+
+__device__ __forceinline__ int stage_segments(const WalkCtx& C, int t, StageSegs& G) {
+  const int nrb = C.plan.n_stage_rb;
+  const int per = 2 * nrb + 1;
+  const int32_t* __restrict__ tab = C.plan.stage_seg + (size_t)t * per;
+  for (int k = threadIdx.x; k < per; k += blockDim.x) {
+    const int32_t v = tab[k];
+    if (k < nrb)
+      G.beg[k] = v;
+    else
+      G.pre[k - nrb] = v;
+  }
+  __syncthreads();
+  return G.pre[nrb];
+}
+
+// Record index of the task's flattened record i, with rb the segment
+// holding it (found by bisection for the first i of a thread, then advanced).
+__device__ __forceinline__ int stage_find_rb(const StageSegs& G, int nrb, int i) {
+  int lo = 0, hi = nrb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (G.pre[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// A pack of narrow columns from its records: counting sort into LDS bins
+// that also hold beta (bin 0) and alpha (bin xbar - l + 1), so the score of
+// position l + k is the prefix sum of bins 0..k; one lane per column then
+// scans its bins and keeps the best candidate (smallest position on ties).
+template <typename Rows, typename V>
+__device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, bool wts, int tix, StagePackSmem<V>& S,
+                                           StageSegs& G) {
+  const StageTask T = C.plan.stage_tasks[tix];
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  const int tid = threadIdx.x;
+  const int nc = T.q_end - T.q_begin;
+  if (tid < nc) {
+    const int q = T.q_begin + tid;
+    const double xb = C.x[q], l = P.lb[q];
+    S.xb[tid] = xb;
+    S.W[tid] = (int)(P.ub[q] - l) + 1;
+    S.k0[tid] = (int)(xb - l);
+    S.cand[tid] = 0ull;
+  }
+  for (int i = tid; i < nc * (kNarrowBins + 1); i += blockDim.x)
+    S.bins[i / (kNarrowBins + 1)][i % (kNarrowBins + 1)] = 0;
+  const V zero = 0;  // stage_segments below ends with a barrier
+  const int nrb = C.plan.n_stage_rb;
+  const int E = stage_segments(C, tix, G);
+  const uint64_t* __restrict__ recs = C.stage_rec;
+  // kRun consecutive records of the flattened task per thread and step
+  constexpr int kRun = 4;
+  for (int i0 = tid * kRun; i0 < E; i0 += (int)blockDim.x * kRun) {
+    uint64_t r[kRun];
+    int rb = stage_find_rb(G, nrb, i0);
+#pragma unroll
+    for (int u = 0; u < kRun; ++u)
+      if (i0 + u < E) {
+        while (i0 + u >= G.pre[rb + 1]) ++rb;
+        r[u] = recs[G.beg[rb] + i0 + u - G.pre[rb]];
+      }
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+      if (i0 + u < E) {
+        const StageRec e = decode_rec(r[u], wts, rs);
+        const int k0 = S.k0[e.lc], W = S.W[e.lc];
+        add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
+        if (e.twin)
+          add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
+      }
+    }
+  }
+  if (tid < nc && st->cut_active) {
+    const double c = P.obj[T.q_begin + tid];
+    if (c != 0.0) {
+      const double wc = (double)st->wc;
+      add_row(c > 0.0, cutoff_offset(S.xb[tid], st, c, P.eps), stage_one(wc, zero), stage_half(wc, zero), S.k0[tid],
+              S.W[tid], S.bins[tid], &S.cand[tid]);
+    }
+  }
+  __syncthreads();
+  if (tid >= nc) return;
+  const int W = S.W[tid], k0 = S.k0[tid];
+  const unsigned long long cand = S.cand[tid];
+  const uint32_t clo = (uint32_t)cand, chi = (uint32_t)(cand >> 32);
+  V acc = 0, best = 0;
+  int bk = -1;
+#pragma unroll
+  for (int k = 0; k < kNarrowBins; ++k) {
+    if (k < W) {
+      acc += S.bins[tid][k];
+      const bool bit = k < 32 ? ((clo >> k) & 1u) != 0 : ((chi >> (k - 32)) & 1u) != 0;
+      const bool ok = (bit || k == 0 || k == W - 1) && k != k0;
+      if (ok && (bk < 0 || acc > best)) {
+        best = acc;
+        bk = k;
+      }
+    }
+  }
+  const double xb = S.xb[tid];
+  write_result(C.xhat, C.s, T.q_begin + tid, bk >= 0, stage_score_of(best), xb + (double)(bk - k0), xb);
+}
+
+__device__ __forceinline__ void cswap_u64(uint64_t& a, uint64_t& b) {
+  const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// One short narrow column with D stored entries (records v[0..D-1]) scored
+// directly: value(c) = beta + alpha [c >= 1] + sum of delta [c >= thr] at the
+// candidate offsets c (both bounds, breakpoints inside [l, u]; c = 0 is
+// xbar and excluded), the largest value, the smallest position on ties.
+template <int D, typename V, typename Rows>
+__device__ __forceinline__ void stage_short_col(const uint64_t* v, bool wts, const Rows& rs, double xb, int k0,
+                                                int W, bool cut, bool cpos, int dcut, double wc, bool& found,
+                                                double& best, double& bestp) {
+  constexpr int NR = 2 * D + 1;
+  const V zero = 0;
+  V beta = 0, alpha = 0;
+  V dl[NR];
+  int th[NR], cd[NR];
+  bool cv[NR];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const StageRec e = decode_rec(v[k], wts, rs);
+    row_terms(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), beta, alpha, dl[2 * k], th[2 * k]);
+    cd[2 * k] = e.d0;
+    cv[2 * k] = true;
+    if (e.twin) {
+      row_terms(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), beta, alpha, dl[2 * k + 1],
+                th[2 * k + 1]);
+      cd[2 * k + 1] = e.d1;
+      cv[2 * k + 1] = true;
+    } else {
+      dl[2 * k + 1] = 0;
+      th[2 * k + 1] = 0;
+      cd[2 * k + 1] = 0;
+      cv[2 * k + 1] = false;
+    }
+  }
+  if (cut) {
+    row_terms(cpos, dcut, stage_one(wc, zero), stage_half(wc, zero), beta, alpha, dl[NR - 1], th[NR - 1]);
+    cd[NR - 1] = dcut;
+    cv[NR - 1] = true;
+  } else {
+    dl[NR - 1] = 0;
+    th[NR - 1] = 0;
+    cd[NR - 1] = 0;
+    cv[NR - 1] = false;
+  }
+  const int lo = -k0, hi = W - 1 - k0;
+  V bv = 0;
+  int bc = 0;
+  found = false;
+  auto consider = [&](int c) {
+    if (c < lo || c > hi || c == 0) return;
+    V val = beta + (c >= 1 ? alpha : zero);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) val += (c >= th[j]) ? dl[j] : zero;
+    if (!found || val > bv || (val == bv && c < bc)) {
+      found = true;
+      bv = val;
+      bc = c;
+    }
+  };
+  consider(lo);
+  consider(hi);
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+    if (cv[j]) consider(cd[j]);
+  best = stage_score_of(bv);
+  bestp = xb + (double)bc;
+}
+
+template <typename Rows>
+__device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bool wts, int tix, StageShortSmem& S,
+                                            StageSegs& G) {
+  const StageTask T = C.plan.stage_tasks[tix];
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  const int tid = threadIdx.x;
+  const int nc = T.q_end - T.q_begin;
+  const int D = T.deg;
+  // the column's own data is loaded while the records arrive
+  const int q = T.q_begin + min(tid, max(nc - 1, 0));
+  const double xb = C.x[q], l = P.lb[q], ub = P.ub[q], c = P.obj[q];
+  S.cnt[tid] = 0;  // stage_segments ends with a barrier
+  const int nrb = C.plan.n_stage_rb;
+  const int E = stage_segments(C, tix, G);
+  const uint64_t* __restrict__ recs = C.stage_rec;
+  constexpr int kRun = 2;
+  for (int i0 = tid * kRun; i0 < E; i0 += (int)blockDim.x * kRun) {
+    uint64_t r[kRun];
+    int rb = stage_find_rb(G, nrb, i0);
+#pragma unroll
+    for (int u = 0; u < kRun; ++u)
+      if (i0 + u < E) {
+        while (i0 + u >= G.pre[rb + 1]) ++rb;
+        r[u] = recs[G.beg[rb] + i0 + u - G.pre[rb]];
+      }
+#pragma unroll
+    for (int u = 0; u < kRun; ++u)
+      if (i0 + u < E) {
+        const int lc = (int)(r[u] & 0xFFu);
+        const int k = atomicAdd(&S.cnt[lc], 1);
+        S.rec[k][lc] = r[u];
+      }
+  }
+  __syncthreads();
+  if (tid >= nc) return;
+  const int W = (int)(ub - l) + 1, k0 = (int)(xb - l);
+  uint64_t v[kShortMax];
+#pragma unroll
+  for (int k = 0; k < kShortMax; ++k) v[k] = (k < D) ? S.rec[k][tid] : ~0ull;
+  if (!wts) {
+    // records arrive in varying order; sort them so that sums of
+    // non-integral weights are formed in one order
+#pragma unroll
+    for (int i = 0; i < kShortMax; ++i)
+#pragma unroll
+      for (int k = 0; k + 1 < kShortMax - i; ++k) cswap_u64(v[k], v[k + 1]);
+  }
+  const bool cut = st->cut_active && c != 0.0;
+  const int dcut = cut ? cutoff_offset(xb, st, c, P.eps) : 0;
+  const double wc = (double)st->wc;
+  bool found = false;
+  double best = 0.0, bestp = xb;
+#define CHAP_SHORT_CASE(DD)                                                                                       \
+  case DD:                                                                                                        \
+    if (wts)                                                                                                      \
+      stage_short_col<DD, int32_t>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);            \
+    else                                                                                                          \
+      stage_short_col<DD, double>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);             \
+    break;
+  switch (D) {
+    CHAP_SHORT_CASE(0)
+    CHAP_SHORT_CASE(1)
+    CHAP_SHORT_CASE(2)
+    CHAP_SHORT_CASE(3)
+    CHAP_SHORT_CASE(4)
+    CHAP_SHORT_CASE(5)
+    CHAP_SHORT_CASE(6)
+    CHAP_SHORT_CASE(7)
+    default:
+      CHAP_SHORT_CASE(8)
+  }
+#undef CHAP_SHORT_CASE
+  write_result(C.xhat, C.s, q, found, best, bestp, xb);
+}
+
+// Workgroups of a walk over ntask scoring tasks: kXcds * ceil(ntask / kXcds)
+// of them, workgroup lb taking task (lb mod kXcds) * ceil(ntask / kXcds) +
+// lb / kXcds, so that each XCD scores a contiguous run of tasks (whose
+// segments share cache lines); -1 for the padding.
+__device__ __forceinline__ int stage_task_of(int lb, int ntask) {
+  const int per = (ntask + kXcds - 1) / kXcds;
+  const int t = (lb % kXcds) * per + lb / kXcds;
+  return t < ntask ? t : -1;
+}
+
+inline int32_t stage_blocks(int32_t ntask) { return kXcds * ((ntask + kXcds - 1) / kXcds); }
+
+// One workgroup per pack of narrow columns, fed by the pack's records.
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_stage_pack(const WalkCtx* __restrict__ walks,
+                                                    const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  __shared__ StageSegs G;
+  const int t = stage_task_of(lb, C.plan.n_stage_packs);
+  if (t < 0) return;
+  const Rows rs = rows_of<Rows>(C);
+  // LDS for the value type(s) the row accessor can need
+  if constexpr (std::is_same<Rows, CompactRows>::value) {
+    __shared__ StagePackSmem<int32_t> si;
+    stage_pack<Rows, int32_t>(C, rs, true, t, si, G);
+  } else if constexpr (std::is_same<Rows, FullRows>::value) {
+    __shared__ StagePackSmem<double> sd;
+    stage_pack<Rows, double>(C, rs, false, t, sd, G);
+  } else {
+    __shared__ union {
+      StagePackSmem<int32_t> i;
+      StagePackSmem<double> d;
+    } sm;
+    if (stage_weights<Rows>(C))
+      stage_pack<Rows, int32_t>(C, rs, true, t, sm.i, G);
+    else
+      stage_pack<Rows, double>(C, rs, false, t, sm.d, G);
+  }
+}
+
+// One workgroup per group of short narrow columns of one degree: one lane
+// per column, fed by the group's records.
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_stage_short(const WalkCtx* __restrict__ walks,
+                                                     const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  __shared__ StageShortSmem sm;
+  __shared__ StageSegs G;
+  const int t = stage_task_of(lb, C.plan.n_stage_tasks - C.plan.n_stage_packs);
+  if (t < 0) return;
+  stage_short<Rows>(C, rows_of<Rows>(C), stage_weights<Rows>(C), C.plan.n_stage_packs + t, sm, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,6 +1669,9 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_CHUNK: return p.n_chunks;
     case KS_COMBINE: return (p.n_chunk_cols + 3) / 4;
     case KS_LONG: return p.n_long;
+    case KS_STAGE: return p.n_stage_rtasks;
+    case KS_STAGE_PACK: return stage_blocks(p.n_stage_packs);
+    case KS_STAGE_SHORT: return stage_blocks(p.n_stage_tasks - p.n_stage_packs);
     case KS_ARGMAX: return c.argmax_blocks;
     case KS_SELECT: return 1;
     case KS_APPLY: return c.apply_blocks;
@@ -1148,6 +1690,8 @@ hipError_t PassStreams::create() {
     e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
     if (e != hipSuccess) return e;
   }
+  hipError_t e = hipEventCreateWithFlags(&mid, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
   return hipEventCreateWithFlags(&fork, hipEventDisableTiming);
 }
 
@@ -1159,7 +1703,9 @@ void PassStreams::destroy() {
     join[k] = nullptr;
   }
   if (fork) (void)hipEventDestroy(fork);
+  if (mid) (void)hipEventDestroy(mid);
   fork = nullptr;
+  mid = nullptr;
 }
 
 template <typename Rows>
@@ -1167,8 +1713,9 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   const int nw = L.nw;
   auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
   hipStream_t s_short = stream, s_long = stream;
+  hipError_t e = hipSuccess;
   if (ps) {
-    hipError_t e = hipEventRecord(ps->fork, stream);
+    e = hipEventRecord(ps->fork, stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->fork, 0);
     if (e != hipSuccess) return e;
     s_short = ps->side[0];
@@ -1184,6 +1731,21 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   }
   if (L.total[KS_LONG] > 0)
     hipLaunchKernelGGL(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
+  // staged columns: records first, then the short groups beside the packs
+  if (L.total[KS_STAGE] > 0)
+    hipLaunchKernelGGL(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
+  if (L.total[KS_STAGE_SHORT] > 0) {
+    if (ps) {
+      e = hipEventRecord(ps->mid, stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s_short, ps->mid, 0);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks,
+                       L.off[KS_STAGE_SHORT], nw);
+  }
+  if (L.total[KS_STAGE_PACK] > 0)
+    hipLaunchKernelGGL(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks,
+                       L.off[KS_STAGE_PACK], nw);
   if (L.total[KS_PACK] > 0)
     hipLaunchKernelGGL(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
   if (L.total[KS_SORT0] > 0)
@@ -1197,7 +1759,7 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   if (L.total[KS_SORT0 + 3] > 0)
     hipLaunchKernelGGL((k_sort_block<4096, Rows>), grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks,
                        L.off[KS_SORT0 + 3], nw);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (ps) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       e = hipEventRecord(ps->join[k], ps->side[k]);

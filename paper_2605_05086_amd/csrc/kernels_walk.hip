@@ -586,6 +586,11 @@ __global__ __launch_bounds__(256) void k_fill_compact_checked(const RowState* __
                                                               GatherRow* __restrict__ grow, WalkState* st,
                                                               int32_t ms) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    // the cutoff weight enters the staged scores as a count of half weights
+    const float wc = st->wc;
+    if (!(wc == floorf(wc) && wc >= 0.0f && wc < 65535.0f)) st->compact_rows = 0;
+  }
   if (i >= ms) return;
   const RowState q = rs[i];
   const bool ok = q.r == floor(q.r) && fabs(q.r) <= 2147483647.0 && q.w0 == floorf(q.w0) && q.w0 >= 0.0f &&
@@ -684,8 +689,8 @@ hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b
 
 hipError_t launch_fill_compact_checked(const RowState* rs, GatherRow* grow, WalkState* st, int32_t ms,
                                        hipStream_t stream) {
-  if (ms > 0)
-    hipLaunchKernelGGL(k_fill_compact_checked, dim3((ms + 255) / 256), dim3(256), 0, stream, rs, grow, st, ms);
+  hipLaunchKernelGGL(k_fill_compact_checked, dim3(std::max(1, (ms + 255) / 256)), dim3(256), 0, stream, rs, grow, st,
+                     ms);
   return hipGetLastError();
 }
 

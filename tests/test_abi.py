@@ -41,7 +41,7 @@ def test_header_symbols_exported(lib):
 def test_options_defaults(lib):
     o = chap.default_options()
     assert o.feas_tol == 1e-6 and o.graph_iters == 64 and o.short_max == 8
-    assert o.chunk_min == 4096 and o.chunk_len == 4096
+    assert o.chunk_min == 4096 and o.chunk_len == 4096 and o.row_stage == 1
 
 
 def _create_rc(mip, **over):

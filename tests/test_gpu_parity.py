@@ -395,3 +395,48 @@ def test_best_shift_weight_kinds(chap, wkind):
     oxh, os_ = P.best_shift(x, w)
     assert_same(xh, oxh, f"shift ({wkind} weights)")
     assert_same(s, os_, f"score ({wkind} weights)")
+
+
+STAGE_CASES = [
+    ("mixed", lambda: mipgen.random_mixed(71, n=400, m=300, max_row_nnz=9, frac_bin=0.2, frac_int=0.8,
+                                          int_width=90, long_cols=4, long_deg=120)),
+    ("few rows", lambda: mipgen.random_mixed(72, n=50, m=5, max_row_nnz=12, frac_bin=0.3, frac_int=0.7)),
+    ("powerlaw", lambda: mipgen.powerlaw(73, n=30_000, m=15_000, nnz=300_000, cap=5000)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(STAGE_CASES)))
+@pytest.mark.parametrize("row_stage", [1, -1])
+@pytest.mark.parametrize("cut", [False, True])
+def test_best_shift_row_stage(chap, case, row_stage, cut):
+    """Short and packed narrow columns scored from row-range records (the
+    default on all-integer instances) and from direct gathers (row_stage=-1):
+    both equal the oracle bit for bit, with and without the cutoff row, with
+    empty row ranges (5 rows) and offsets beyond the +-64 clamp."""
+    name, make = STAGE_CASES[case]
+    mip = make()
+    P = oracle.OracleProblem(mip)
+    for seed in (0, 2):
+        x = mipgen.random_point(mip, seed)
+        w = mipgen.random_weights(P.mp + 1, seed + 1, wmax=9)
+        cutoff = float(np.dot(mip.obj, x)) + 3.0 if cut else math.inf
+        say(f"best_shift staged {name} row_stage={row_stage} cut={cut} seed={seed}")
+        xh, s = gpu_best_shift(chap, mip, x, w, cutoff, row_stage=row_stage)
+        oxh, os_ = P.best_shift(x, w, cutoff)
+        assert_same(s, os_, f"{name} score")
+        assert_same(xh, oxh, f"{name} shift")
+
+
+def test_tabu_row_stage_full_rows(chap):
+    """A walk of 65540 iterations keeps full rows (weights may pass 65534), so
+    the staged records carry row indices instead of weights; the walk equals
+    the oracle and the unstaged walk."""
+    mip = mipgen.random_mixed(74, n=40, m=30, max_row_nnz=6, frac_bin=0.3, frac_int=0.7)
+    P = oracle.OracleProblem(mip)
+    iters = 65540
+    say(f"tabu staged full rows {iters} iters")
+    g = chap.Problem(mip).tabu_run(iters, 3, 1)
+    compare_runs(g, P.tabu_run(iters, 3, 1), "staged full rows")
+    say(f"tabu unstaged full rows {iters} iters")
+    h = chap.Problem(mip, row_stage=-1).tabu_run(iters, 3, 1)
+    assert g.trace.tobytes() == h.trace.tobytes()
