@@ -25,12 +25,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per best-shift pass on the 20M-nonzero instance, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) over k_short, k_narrow_pack,
-# k_narrow_chunk and k_narrow_combine, scaled by the counters of a 1 GiB
-# device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see
-# profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the pass
-# kernels as they are; set to None when they change until measured again.
-PASS_TRAFFIC_BYTES = 1_161_000_000
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) over the pass kernels, scaled
+# by the counters of a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
+# see profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the
+# pass kernels as they are; None until they are measured again after a change.
+PASS_TRAFFIC_BYTES = None
 METRIC = "tabu moves/s, best-shift nnz/s, % HBM peak; plain vs batched/learned"
 
 
@@ -164,7 +163,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": PASS_TRAFFIC_BYTES if not args.small else None,
-                     "kernel": "best-shift pass (k_short + k_narrow_pack + k_narrow_chunk + k_narrow_combine)",
+                     "kernel": "best-shift pass (k_stage_rows + k_stage_pack + k_stage_short + k_narrow_chunk + "
+                               "k_narrow_combine on the 20M instance)",
                      "bytes_per_launch": B},
     }
     if not args.no_compare:
