@@ -313,10 +313,12 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
             (int64_t)m <= (int64_t)kStageMaxRb * kStageRowBlock;
   }
   std::vector<std::vector<int32_t>> short_seg(kShortMax + 2), sortl(kSortCaps);
-  std::vector<int32_t> flip, narrow, chunked, longg, sshort;
+  std::vector<int32_t> flip, narrow, chunked, longg, sshort, sone;
   for (int32_t j = 0; j < n; ++j) {
     if (ne[j] <= o.short_max) {
-      if (stage && cls[j] == NARROW)
+      if (stage && cls[j] == NARROW && deg[j] == 1)
+        sone.push_back(j);
+      else if (stage && cls[j] == NARROW)
         sshort.push_back(j);
       else
         short_seg[cls[j] == BIN ? 0 : 1 + deg[j]].push_back(j);
@@ -357,8 +359,10 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     int32_t q = (int32_t)perm.size();
     PackTask t{q, q};
     int64_t entries = 0;
+    const int32_t pcols = stage ? kStagePackCols : kPackCols;
+    const int64_t pent = stage ? kStagePackEntries : kPackEntries;
     for (int32_t j : narrow) {
-      if (t.q_end > t.q_begin && (t.q_end - t.q_begin == kPackCols || entries + deg[j] > kPackEntries)) {
+      if (t.q_end > t.q_begin && (t.q_end - t.q_begin == pcols || entries + deg[j] > pent)) {
         packs.push_back(t);
         t.q_begin = t.q_end;
         entries = 0;
@@ -369,6 +373,16 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     if (t.q_end > t.q_begin) packs.push_back(t);
   }
   append(narrow);
+  // single-entry columns ordered by the row of their entry: the columns of
+  // one row block form one range
+  std::vector<int32_t> one_row(n, 0);
+  for (int32_t j : sone)
+    for (int64_t k = csc_col_ptr[j]; k < csc_col_ptr[j + 1]; ++k)
+      if (csc_val[k] != 0.0) one_row[j] = csc_row[k];
+  std::stable_sort(sone.begin(), sone.end(), [&](int32_t a, int32_t b) { return one_row[a] < one_row[b]; });
+  L.stage_one_begin = (int32_t)perm.size();
+  append(sone);
+  L.stage_one_end = (int32_t)perm.size();
   L.stage_short_begin = (int32_t)perm.size();
   std::stable_sort(sshort.begin(), sshort.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
   append(sshort);
@@ -495,13 +509,28 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     }
     for (int32_t rb = 0; rb < nrb; ++rb) sseg[T * nrb + rb] = (int32_t)ent_rb[rb].size();
     std::vector<std::vector<StageRowTask>> per_xcd(kXcds);
+    int32_t qone = L.stage_one_begin;
     for (int32_t rb = 0; rb < nrb; ++rb) {
       const int32_t e0 = (int32_t)sent.size();
       for (size_t t = 0; t <= T; ++t) sseg[t * nrb + rb] += e0;
       sent.insert(sent.end(), ent_rb[rb].begin(), ent_rb[rb].end());
       const int32_t e1 = (int32_t)sent.size();
-      for (int32_t b = e0; b < e1; b += kStageSlice)
-        per_xcd[rb % kXcds].push_back(StageRowTask{rb, b, std::min(e1, b + kStageSlice), 0});
+      const int32_t c0 = qone;
+      while (qone < L.stage_one_end && crow[cptr[qone]] < (rb + 1) * kStageRowBlock) ++qone;
+      const int32_t c1 = qone;
+      const int32_t ns = std::max((e1 - e0 + kStageSlice - 1) / kStageSlice,
+                                  (c1 - c0 + kStageSliceCols - 1) / kStageSliceCols);
+      if (ns == 0) continue;
+      const int32_t se = (e1 - e0 + ns - 1) / ns, sc = (c1 - c0 + ns - 1) / ns;
+      for (int32_t k = 0; k < ns; ++k) {
+        StageRowTask rt{};
+        rt.rb = rb;
+        rt.e_beg = std::min(e1, e0 + k * se);
+        rt.e_end = std::min(e1, e0 + (k + 1) * se);
+        rt.c_beg = std::min(c1, c0 + k * sc);
+        rt.c_end = std::min(c1, c0 + (k + 1) * sc);
+        per_xcd[rb % kXcds].push_back(rt);
+      }
     }
     // per task: segment starts, then prefix counts of its records
     {
@@ -522,13 +551,13 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     for (const auto& v : per_xcd) rounds = std::max(rounds, v.size());
     for (size_t k = 0; k < rounds; ++k)
       for (int x = 0; x < kXcds; ++x)
-        srtasks.push_back(k < per_xcd[x].size() ? per_xcd[x][k] : StageRowTask{-1, 0, 0, 0});
+        srtasks.push_back(k < per_xcd[x].size() ? per_xcd[x][k] : StageRowTask{-1, 0, 0, 0, 0, {0, 0, 0}});
     L.n_stage_ent = (int32_t)sent.size();
     L.n_stage_tasks = (int32_t)T;
     L.n_stage_packs = npk;
     L.n_stage_rtasks = (int32_t)srtasks.size();
     L.n_stage_rb = nrb;
-    L.stage = T > 0 ? 1 : 0;
+    L.stage = (T > 0 || L.stage_one_end > L.stage_one_begin) ? 1 : 0;
   }
   std::vector<LongTask> longs;
   int64_t long_total = 0;

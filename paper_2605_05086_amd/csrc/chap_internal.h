@@ -21,6 +21,32 @@ __host__ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t index) {
   return z ^ (z >> 31);
 }
 
+// Pointers kept in structures are generic to the compiler, which then emits
+// flat memory instructions and orders them behind pending LDS operations.
+// Device allocations are global memory: casting such pointers to the global
+// address space lets loads and stores issue without those waits.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
+// Loads element i of an 8- or 16-byte record array through a global pointer
+// (a plain vector load: records have no copy from the global address space).
+template <typename T>
+__device__ __forceinline__ T gload(gptr<const T> p, int64_t i) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte records");
+  if constexpr (sizeof(T) == 16) {
+    typedef unsigned int v4 __attribute__((ext_vector_type(4)));
+    const v4 v = ((gptr<const v4>)p)[i];
+    return __builtin_bit_cast(T, v);
+  } else {
+    const unsigned long long v = ((gptr<const unsigned long long>)p)[i];
+    return __builtin_bit_cast(T, v);
+  }
+}
+
 // Records msg as the calling thread's last error and returns code.
 int fail(int code, const std::string& msg);
 
@@ -201,14 +227,21 @@ constexpr int kStageSlice = 16384;    // staged entries per workgroup of k_stage
 constexpr int kStageShort = 256;      // short narrow columns per scoring task
 constexpr int kStageClamp = 64;       // offsets beyond +-64 leave every narrow column
 constexpr int kStageMaxRb = 256;      // row blocks a scoring workgroup can index in LDS
+constexpr int kStageSliceCols = 4096; // single-entry columns per workgroup of k_stage_rows
+constexpr int kStagePackCols = 64;    // columns per staged pack (one lane each in the final scan)
+constexpr int kStagePackEntries = 2048;  // target stored entries per staged pack
 
-// A slice [e_beg, e_end) of the staged entries of row block rb (rb < 0: an
-// empty task that only keeps the XCD interleave).
+// A slice [e_beg, e_end) of the staged entries of row block rb, and a range
+// [c_beg, c_end) of the short narrow columns whose one stored entry lies in
+// that block (scored there directly); rb < 0: an empty task that only keeps
+// the XCD interleave.
 struct StageRowTask {
   int32_t rb;
   int32_t e_beg;
   int32_t e_end;
-  int32_t pad;
+  int32_t c_beg;
+  int32_t c_end;
+  int32_t pad[3];
 };
 
 // Columns [q_begin, q_end) scored by one workgroup of the staged kernels;
@@ -264,6 +297,7 @@ struct PassPlan {
   const uint64_t* stage_ent = nullptr;
   int32_t n_stage_ent = 0;
   int32_t stage_short_begin = 0, stage_short_end = 0;
+  int32_t stage_one_begin = 0, stage_one_end = 0;  // single-entry short narrow columns
 };
 
 // Everything the kernels of one walk need: its instance, the instance's pass
@@ -286,7 +320,7 @@ struct WalkCtx {
   double* long_pos;
   double* long_delta;
   int32_t* long_marker;
-  uint64_t* stage_rec;  // records of the staged entries (row-range staging)
+  uint64_t* stage_rec;  // records of the staged entries (row-block staging)
   int32_t argmax_blocks;
   int32_t apply_blocks;
   int32_t recompute;

@@ -45,14 +45,14 @@ constexpr int kWave = 64;
 
 // Row accessors: the walk's RowState array, or its compact GatherRow copy.
 struct FullRows {
-  const RowState* p;
-  __device__ __forceinline__ RowState operator[](int i) const { return p[i]; }
+  gptr<const RowState> p;
+  __device__ __forceinline__ RowState operator[](int i) const { return gload(p, i); }
 };
 
 struct CompactRows {
-  const GatherRow* p;
+  gptr<const GatherRow> p;
   __device__ __forceinline__ RowState operator[](int i) const {
-    const GatherRow g = p[i];
+    const GatherRow g = gload(p, i);
     RowState o;
     o.r = (double)g.r;
     o.w0 = (float)g.w0;
@@ -63,11 +63,12 @@ struct CompactRows {
 
 // Either of the two, as the walk state says (single passes with caller weights).
 struct DualRows {
-  const RowState* p;
-  const GatherRow* g;
+  gptr<const RowState> p;
+  gptr<const GatherRow> g;
   int32_t use_g;
   __device__ __forceinline__ RowState operator[](int i) const {
-    return use_g ? CompactRows{g}[i] : p[i];
+    if (use_g) return CompactRows{g}[i];
+    return gload(p, i);
   }
 };
 
@@ -75,15 +76,15 @@ template <typename Rows>
 __device__ __forceinline__ Rows rows_of(const WalkCtx& C);
 template <>
 __device__ __forceinline__ DualRows rows_of<DualRows>(const WalkCtx& C) {
-  return DualRows{C.rs, C.grow, C.st->compact_rows};
+  return DualRows{gmem((const RowState*)C.rs), gmem((const GatherRow*)C.grow), C.st->compact_rows};
 }
 template <>
 __device__ __forceinline__ FullRows rows_of<FullRows>(const WalkCtx& C) {
-  return FullRows{C.rs};
+  return FullRows{gmem((const RowState*)C.rs)};
 }
 template <>
 __device__ __forceinline__ CompactRows rows_of<CompactRows>(const WalkCtx& C) {
-  return CompactRows{C.grow};
+  return CompactRows{gmem((const GatherRow*)C.grow)};
 }
 
 // Whether staged records carry the weights (exact in 16 bits): always with
@@ -194,7 +195,8 @@ __device__ __forceinline__ void wave_argmax(double& v, int& key) {
   }
 }
 
-__device__ __forceinline__ void write_result(double* xhat, double* sc, int j, bool found, double best, double bestp,
+template <typename Ptr>
+__device__ __forceinline__ void write_result(Ptr xhat, Ptr sc, int j, bool found, double best, double bestp,
                                              double xb) {
   if (found && best > 0.0) {
     xhat[j] = bestp + 0.0;  // canonical +0.0
@@ -614,33 +616,35 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
   if (T.col >= 0) {
     const int q = T.col;
     const double eps = P.eps;
-    const double xb = x[q];
-    const double l = P.lb[q], u = P.ub[q];
-    const int W = (int)(u - l) + 1;
+    const double xb = gmem(x)[q];
+    const double l = gmem(P.lb)[q], u2 = gmem(P.ub)[q];
+    const gptr<const int32_t> crow = gmem(P.col_row);
+    const gptr<const double> cval = gmem(P.col_val);
+    const int W = (int)(u2 - l) + 1;
     int e = T.e_beg + tid;
     // two entries per step: both gathers are issued before either is used
     for (; e + 256 < T.e_end; e += 512) {
-      const int i0 = __builtin_nontemporal_load(&P.col_row[e]);
-      const int i1 = __builtin_nontemporal_load(&P.col_row[e + 256]);
-      const double a0 = __builtin_nontemporal_load(&P.col_val[e]);
-      const double a1 = __builtin_nontemporal_load(&P.col_val[e + 256]);
+      const int i0 = __builtin_nontemporal_load(&crow[e]);
+      const int i1 = __builtin_nontemporal_load(&crow[e + 256]);
+      const double a0 = __builtin_nontemporal_load(&cval[e]);
+      const double a1 = __builtin_nontemporal_load(&cval[e + 256]);
       const RowState r0 = rs[i0];
       const RowState r1 = rs[i1];
-      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u, W, bins, beta, alpha, cand);
-      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u, W, bins, beta, alpha, cand);
-      narrow_entry(xb, r1.r, a1, (double)r1.w0, eps, l, u, W, bins, beta, alpha, cand);
-      if (r1.w1 >= 0.0f) narrow_entry(xb, -r1.r, -a1, (double)r1.w1, eps, l, u, W, bins, beta, alpha, cand);
+      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u2, W, bins, beta, alpha, cand);
+      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u2, W, bins, beta, alpha, cand);
+      narrow_entry(xb, r1.r, a1, (double)r1.w0, eps, l, u2, W, bins, beta, alpha, cand);
+      if (r1.w1 >= 0.0f) narrow_entry(xb, -r1.r, -a1, (double)r1.w1, eps, l, u2, W, bins, beta, alpha, cand);
     }
     if (e < T.e_end) {
-      const int i0 = __builtin_nontemporal_load(&P.col_row[e]);
-      const double a0 = __builtin_nontemporal_load(&P.col_val[e]);
+      const int i0 = __builtin_nontemporal_load(&crow[e]);
+      const double a0 = __builtin_nontemporal_load(&cval[e]);
       const RowState r0 = rs[i0];
-      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u, W, bins, beta, alpha, cand);
-      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u, W, bins, beta, alpha, cand);
+      narrow_entry(xb, r0.r, a0, (double)r0.w0, eps, l, u2, W, bins, beta, alpha, cand);
+      if (r0.w1 >= 0.0f) narrow_entry(xb, -r0.r, -a0, (double)r0.w1, eps, l, u2, W, bins, beta, alpha, cand);
     }
     if (tid == 0 && T.first && st->cut_active) {
       const double c = P.obj[q];
-      if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u, W, bins, beta, alpha, cand);
+      if (c != 0.0) narrow_entry(xb, st->rc, c, (double)st->wc, eps, l, u2, W, bins, beta, alpha, cand);
     }
   }
   beta = wave_sum(beta);
@@ -653,7 +657,7 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
   }
   __syncthreads();
   if (T.col < 0) return;
-  ChunkPartial* mine = partials + T.slot;
+  const gptr<ChunkPartial> mine = gmem(partials) + T.slot;
   if (tid < kNarrowBins) mine->bins[tid] = bins[tid];
   if (tid == 0) {
     mine->beta = red_b[0] + red_b[1] + red_b[2] + red_b[3];
@@ -682,13 +686,13 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   if (idx >= count) return;
   const ChunkCol C = cols[idx];
   const int q = C.col;
-  const double xb = x[q];
-  const double l = P.lb[q], u = P.ub[q];
+  const double xb = gmem(x)[q];
+  const double l = gmem(P.lb)[q], u = gmem(P.ub)[q];
   const int W = (int)(u - l) + 1;
   double bv = 0.0, b = 0.0, a = 0.0;
   unsigned long long c = 0;
   for (int k = 0; k < C.nparts; ++k) {
-    const ChunkPartial* pp = partials + C.first + k;
+    const gptr<const ChunkPartial> pp = gmem(partials) + C.first + k;
     bv += pp->bins[lane];
     b += pp->beta;
     a += pp->alpha;
@@ -697,84 +701,12 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   bool found;
   double best, bestp;
   narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(xhat, sc, q, found, best, bestp, xb);
+  if (lane == 0) write_result(gmem(xhat), gmem(sc), q, found, best, bestp, xb);
 }
 
 // ---------------------------------------------------------------------------
 // Row-range staging (all-integer instances).
 // ---------------------------------------------------------------------------
-
-// One workgroup per slice of a row block's staged entries: the block's rows
-// go to LDS (as GatherRow; weights only when the records carry them), then
-// every entry of the slice becomes the record of the same index.
-template <typename Rows>
-__global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
-                                                    const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (C.st->k >= C.st->iters) return;
-  const StageRowTask T = C.plan.stage_rtasks[lb];
-  if (T.rb < 0) return;
-  __shared__ GatherRow rows[kStageRowBlock];
-  const Rows rs = rows_of<Rows>(C);
-  const bool wts = stage_weights<Rows>(C);
-  const int r0 = T.rb * kStageRowBlock;
-  const int nr = min(kStageRowBlock, C.P.ms - r0);
-  const uint64_t* __restrict__ ent = C.plan.stage_ent;
-  uint64_t* __restrict__ rec = C.stage_rec;
-  constexpr int kThreads = 512;
-  constexpr int kU = 8;  // entries per thread and step, loaded before any is used
-  const int tid = threadIdx.x;
-  uint64_t wd[kU];
-  auto load_step = [&](int base) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = base + u * kThreads;
-      if (i < T.e_end) wd[u] = __builtin_nontemporal_load(&ent[i]);
-    }
-  };
-  // the first step's entries are in flight while the row block is loaded
-  load_step(T.e_beg + tid);
-  {
-    constexpr int kPer = kStageRowBlock / kThreads;
-    RowState g[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (tid + k * kThreads < nr) g[k] = rs[r0 + tid + k * kThreads];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (tid + k * kThreads < nr) {
-        GatherRow o;
-        o.r = (int32_t)g[k].r;
-        o.w0 = wts ? (uint16_t)g[k].w0 : (uint16_t)0;
-        o.w1 = g[k].w1 >= 0.0f ? (wts ? (uint16_t)g[k].w1 : (uint16_t)0) : kNoTwin;
-        rows[tid + k * kThreads] = o;
-      }
-  }
-  __syncthreads();
-  for (int base = T.e_beg + tid; base < T.e_end; base += kU * kThreads) {
-    if (base != T.e_beg + tid) load_step(base);
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = base + u * kThreads;
-      if (i < T.e_end) {
-        const int local = (int)(wd[u] & 0xFFFFu);
-        const GatherRow g = rows[local];
-        const int a = ((int32_t)((uint32_t)(wd[u] >> 24) << 8)) >> 8;
-        const double qv = -(double)g.r / (double)a;
-        const double fl = fmin(fmax(floor(qv), -(double)kStageClamp), (double)kStageClamp);
-        const double ce = fmin(fmax(ceil(qv), -(double)kStageClamp), (double)kStageClamp);
-        const int d0 = (int)(a > 0 ? fl : ce);
-        const int d1 = (int)(a > 0 ? ce : fl);
-        const bool twin = g.w1 != kNoTwin;
-        const uint32_t lo = (uint32_t)((wd[u] >> 16) & 0xFFu) | ((a > 0 ? 1u : 0u) << 8) | ((twin ? 1u : 0u) << 9) |
-                            ((uint32_t)(d0 + kStageClamp) << 10) | ((uint32_t)(d1 + kStageClamp) << 18);
-        const uint32_t top = wts ? ((uint32_t)g.w0 | ((uint32_t)g.w1 << 16)) : (uint32_t)(r0 + local);
-        rec[i] = (uint64_t)lo | ((uint64_t)top << 32);
-      }
-    }
-  }
-}
 
 // Staged scoring keeps values as int32 counts of half weights when the
 // weights are integers (every term is a multiple of w/2: exact), else FP64.
@@ -877,10 +809,10 @@ __device__ __forceinline__ int cutoff_offset(double xb, const WalkState* st, dou
 
 template <typename V>
 struct StagePackSmem {
-  V bins[kPackCols][kNarrowBins + 1];  // padded: lane c reads row c without bank conflicts
-  unsigned long long cand[kPackCols];
-  double xb[kPackCols];
-  int32_t W[kPackCols], k0[kPackCols];
+  V bins[kStagePackCols][kNarrowBins + 1];  // padded: lane c reads row c without bank conflicts
+  unsigned long long cand[kStagePackCols];
+  double xb[kStagePackCols];
+  int32_t W[kStagePackCols], k0[kStagePackCols];
 };
 
 struct StageShortSmem {
@@ -899,7 +831,7 @@ struct StageSegs {
 __device__ __forceinline__ int stage_segments(const WalkCtx& C, int t, StageSegs& G) {
   const int nrb = C.plan.n_stage_rb;
   const int per = 2 * nrb + 1;
-  const int32_t* __restrict__ tab = C.plan.stage_seg + (size_t)t * per;
+  const gptr<const int32_t> tab = gmem(C.plan.stage_seg + (size_t)t * per);
   for (int k = threadIdx.x; k < per; k += blockDim.x) {
     const int32_t v = tab[k];
     if (k < nrb)
@@ -909,20 +841,6 @@ __device__ __forceinline__ int stage_segments(const WalkCtx& C, int t, StageSegs
   }
   __syncthreads();
   return G.pre[nrb];
-}
-
-// Record index of the task's flattened record i, with rb the segment
-// holding it (found by bisection for the first i of a thread, then advanced).
-__device__ __forceinline__ int stage_find_rb(const StageSegs& G, int nrb, int i) {
-  int lo = 0, hi = nrb - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (G.pre[mid] <= i)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
 }
 
 // A pack of narrow columns from its records: counting sort into LDS bins
@@ -939,9 +857,9 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
   const int nc = T.q_end - T.q_begin;
   if (tid < nc) {
     const int q = T.q_begin + tid;
-    const double xb = C.x[q], l = P.lb[q];
+    const double xb = gmem((const double*)C.x)[q], l = gmem(P.lb)[q];
     S.xb[tid] = xb;
-    S.W[tid] = (int)(P.ub[q] - l) + 1;
+    S.W[tid] = (int)(gmem(P.ub)[q] - l) + 1;
     S.k0[tid] = (int)(xb - l);
     S.cand[tid] = 0ull;
   }
@@ -949,27 +867,31 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
     S.bins[i / (kNarrowBins + 1)][i % (kNarrowBins + 1)] = 0;
   const V zero = 0;  // stage_segments below ends with a barrier
   const int nrb = C.plan.n_stage_rb;
-  const int E = stage_segments(C, tix, G);
-  const uint64_t* __restrict__ recs = C.stage_rec;
-  // kRun consecutive records of the flattened task per thread and step
+  stage_segments(C, tix, G);
+  const gptr<const uint64_t> recs = gmem((const uint64_t*)C.stage_rec);
+  // tps threads per row-block segment, each a contiguous part of it, kRun
+  // records per step
   constexpr int kRun = 4;
-  for (int i0 = tid * kRun; i0 < E; i0 += (int)blockDim.x * kRun) {
-    uint64_t r[kRun];
-    int rb = stage_find_rb(G, nrb, i0);
+  const int tps = max(1, (int)blockDim.x / nrb);
+  for (int sg = tid / tps; sg < nrb; sg += (int)blockDim.x / tps) {
+    const int len = G.pre[sg + 1] - G.pre[sg];
+    const int per = (len + tps - 1) / tps;
+    const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
+    for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
+      uint64_t r[kRun];
 #pragma unroll
-    for (int u = 0; u < kRun; ++u)
-      if (i0 + u < E) {
-        while (i0 + u >= G.pre[rb + 1]) ++rb;
-        r[u] = recs[G.beg[rb] + i0 + u - G.pre[rb]];
-      }
+      for (int u = 0; u < kRun; ++u)
+        if (i0 + u < i1) r[u] = recs[i0 + u];
 #pragma unroll
-    for (int u = 0; u < kRun; ++u) {
-      if (i0 + u < E) {
-        const StageRec e = decode_rec(r[u], wts, rs);
-        const int k0 = S.k0[e.lc], W = S.W[e.lc];
-        add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
-        if (e.twin)
-          add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
+      for (int u = 0; u < kRun; ++u) {
+        if (i0 + u < i1) {
+          const StageRec e = decode_rec(r[u], wts, rs);
+          const int k0 = S.k0[e.lc], W = S.W[e.lc];
+          add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
+          if (e.twin)
+            add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[e.lc],
+                    &S.cand[e.lc]);
+        }
       }
     }
   }
@@ -1001,7 +923,7 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
     }
   }
   const double xb = S.xb[tid];
-  write_result(C.xhat, C.s, T.q_begin + tid, bk >= 0, stage_score_of(best), xb + (double)(bk - k0), xb);
+  write_result(gmem(C.xhat), gmem(C.s), T.q_begin + tid, bk >= 0, stage_score_of(best), xb + (double)(bk - k0), xb);
 }
 
 __device__ __forceinline__ void cswap_u64(uint64_t& a, uint64_t& b) {
@@ -1010,14 +932,13 @@ __device__ __forceinline__ void cswap_u64(uint64_t& a, uint64_t& b) {
   b = hi;
 }
 
-// One short narrow column with D stored entries (records v[0..D-1]) scored
-// directly: value(c) = beta + alpha [c >= 1] + sum of delta [c >= thr] at the
-// candidate offsets c (both bounds, breakpoints inside [l, u]; c = 0 is
-// xbar and excluded), the largest value, the smallest position on ties.
-template <int D, typename V, typename Rows>
-__device__ __forceinline__ void stage_short_col(const uint64_t* v, bool wts, const Rows& rs, double xb, int k0,
-                                                int W, bool cut, bool cpos, int dcut, double wc, bool& found,
-                                                double& best, double& bestp) {
+// One short narrow column with D stored entries (decoded records e[0..D-1])
+// scored directly: value(c) = beta + alpha [c >= 1] + sum of delta [c >= thr]
+// at the candidate offsets c (both bounds, breakpoints inside [l, u]; c = 0
+// is xbar and excluded), the largest value, the smallest position on ties.
+template <int D, typename V>
+__device__ __forceinline__ void stage_short_col(const StageRec* e, double xb, int k0, int W, bool cut, bool cpos,
+                                                int dcut, double wc, bool& found, double& best, double& bestp) {
   constexpr int NR = 2 * D + 1;
   const V zero = 0;
   V beta = 0, alpha = 0;
@@ -1026,14 +947,14 @@ __device__ __forceinline__ void stage_short_col(const uint64_t* v, bool wts, con
   bool cv[NR];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const StageRec e = decode_rec(v[k], wts, rs);
-    row_terms(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), beta, alpha, dl[2 * k], th[2 * k]);
-    cd[2 * k] = e.d0;
+    row_terms(e[k].ap, e[k].d0, stage_one(e[k].w0, zero), stage_half(e[k].w0, zero), beta, alpha, dl[2 * k],
+              th[2 * k]);
+    cd[2 * k] = e[k].d0;
     cv[2 * k] = true;
-    if (e.twin) {
-      row_terms(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), beta, alpha, dl[2 * k + 1],
-                th[2 * k + 1]);
-      cd[2 * k + 1] = e.d1;
+    if (e[k].twin) {
+      row_terms(!e[k].ap, e[k].d1, stage_one(e[k].w1, zero), stage_half(e[k].w1, zero), beta, alpha,
+                dl[2 * k + 1], th[2 * k + 1]);
+      cd[2 * k + 1] = e[k].d1;
       cv[2 * k + 1] = true;
     } else {
       dl[2 * k + 1] = 0;
@@ -1076,6 +997,16 @@ __device__ __forceinline__ void stage_short_col(const uint64_t* v, bool wts, con
   bestp = xb + (double)bc;
 }
 
+template <int D, typename V, typename Rows>
+__device__ __forceinline__ void stage_short_recs(const uint64_t* v, bool wts, const Rows& rs, double xb, int k0,
+                                                 int W, bool cut, bool cpos, int dcut, double wc, bool& found,
+                                                 double& best, double& bestp) {
+  StageRec e[D > 0 ? D : 1];
+#pragma unroll
+  for (int k = 0; k < D; ++k) e[k] = decode_rec(v[k], wts, rs);
+  stage_short_col<D, V>(e, xb, k0, W, cut, cpos, dcut, wc, found, best, bestp);
+}
+
 template <typename Rows>
 __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bool wts, int tix, StageShortSmem& S,
                                             StageSegs& G) {
@@ -1087,28 +1018,30 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
   const int D = T.deg;
   // the column's own data is loaded while the records arrive
   const int q = T.q_begin + min(tid, max(nc - 1, 0));
-  const double xb = C.x[q], l = P.lb[q], ub = P.ub[q], c = P.obj[q];
+  const double xb = gmem((const double*)C.x)[q], l = gmem(P.lb)[q], ub = gmem(P.ub)[q], c = gmem(P.obj)[q];
   S.cnt[tid] = 0;  // stage_segments ends with a barrier
   const int nrb = C.plan.n_stage_rb;
-  const int E = stage_segments(C, tix, G);
-  const uint64_t* __restrict__ recs = C.stage_rec;
-  constexpr int kRun = 2;
-  for (int i0 = tid * kRun; i0 < E; i0 += (int)blockDim.x * kRun) {
-    uint64_t r[kRun];
-    int rb = stage_find_rb(G, nrb, i0);
+  stage_segments(C, tix, G);
+  const gptr<const uint64_t> recs = gmem((const uint64_t*)C.stage_rec);
+  constexpr int kRun = 4;
+  const int tps = max(1, (int)blockDim.x / nrb);
+  for (int sg = tid / tps; sg < nrb; sg += (int)blockDim.x / tps) {
+    const int len = G.pre[sg + 1] - G.pre[sg];
+    const int per = (len + tps - 1) / tps;
+    const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
+    for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
+      uint64_t r[kRun];
 #pragma unroll
-    for (int u = 0; u < kRun; ++u)
-      if (i0 + u < E) {
-        while (i0 + u >= G.pre[rb + 1]) ++rb;
-        r[u] = recs[G.beg[rb] + i0 + u - G.pre[rb]];
-      }
+      for (int u = 0; u < kRun; ++u)
+        if (i0 + u < i1) r[u] = recs[i0 + u];
 #pragma unroll
-    for (int u = 0; u < kRun; ++u)
-      if (i0 + u < E) {
-        const int lc = (int)(r[u] & 0xFFu);
-        const int k = atomicAdd(&S.cnt[lc], 1);
-        S.rec[k][lc] = r[u];
-      }
+      for (int u = 0; u < kRun; ++u)
+        if (i0 + u < i1) {
+          const int lc = (int)(r[u] & 0xFFu);
+          const int k = atomicAdd(&S.cnt[lc], 1);
+          S.rec[k][lc] = r[u];
+        }
+    }
   }
   __syncthreads();
   if (tid >= nc) return;
@@ -1132,9 +1065,9 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
 #define CHAP_SHORT_CASE(DD)                                                                                       \
   case DD:                                                                                                        \
     if (wts)                                                                                                      \
-      stage_short_col<DD, int32_t>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);            \
+      stage_short_recs<DD, int32_t>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);           \
     else                                                                                                          \
-      stage_short_col<DD, double>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);             \
+      stage_short_recs<DD, double>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);            \
     break;
   switch (D) {
     CHAP_SHORT_CASE(0)
@@ -1149,7 +1082,124 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
       CHAP_SHORT_CASE(8)
   }
 #undef CHAP_SHORT_CASE
-  write_result(C.xhat, C.s, q, found, best, bestp, xb);
+  write_result(gmem(C.xhat), gmem(C.s), q, found, best, bestp, xb);
+}
+
+// One workgroup per slice of a row block's staged entries: the block's rows
+// go to LDS (as GatherRow; weights only when the records carry them), then
+// every entry of the slice becomes the record of the same index, and the
+// slice's single-entry columns (their entry lies in this block) are scored.
+template <typename Rows>
+__global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
+                                                    const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  const StageRowTask T = C.plan.stage_rtasks[lb];
+  if (T.rb < 0) return;
+  __shared__ GatherRow rows[kStageRowBlock];
+  const Rows rs = rows_of<Rows>(C);
+  const bool wts = stage_weights<Rows>(C);
+  const int r0 = T.rb * kStageRowBlock;
+  const int nr = min(kStageRowBlock, C.P.ms - r0);
+  const gptr<const uint64_t> ent = gmem(C.plan.stage_ent);
+  const gptr<uint64_t> rec = gmem(C.stage_rec);
+  constexpr int kThreads = 512;
+  constexpr int kU = 8;  // entries per thread and step, loaded before any is used
+  const int tid = threadIdx.x;
+  uint64_t wd[kU];
+  auto load_step = [&](int base) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads;
+      if (i < T.e_end) wd[u] = __builtin_nontemporal_load(&ent[i]);
+    }
+  };
+  // the first step's entries are in flight while the row block is loaded
+  load_step(T.e_beg + tid);
+  {
+    constexpr int kPer = kStageRowBlock / kThreads;
+    RowState g[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kThreads < nr) g[k] = rs[r0 + tid + k * kThreads];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kThreads < nr) {
+        GatherRow o;
+        o.r = (int32_t)g[k].r;
+        o.w0 = wts ? (uint16_t)g[k].w0 : (uint16_t)0;
+        o.w1 = g[k].w1 >= 0.0f ? (wts ? (uint16_t)g[k].w1 : (uint16_t)0) : kNoTwin;
+        rows[tid + k * kThreads] = o;
+      }
+  }
+  __syncthreads();
+  for (int base = T.e_beg + tid; base < T.e_end; base += kU * kThreads) {
+    if (base != T.e_beg + tid) load_step(base);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = base + u * kThreads;
+      if (i < T.e_end) {
+        const int local = (int)(wd[u] & 0xFFFFu);
+        const GatherRow g = rows[local];
+        const int a = ((int32_t)((uint32_t)(wd[u] >> 24) << 8)) >> 8;
+        const double qv = -(double)g.r / (double)a;
+        const double fl = fmin(fmax(floor(qv), -(double)kStageClamp), (double)kStageClamp);
+        const double ce = fmin(fmax(ceil(qv), -(double)kStageClamp), (double)kStageClamp);
+        const int d0 = (int)(a > 0 ? fl : ce);
+        const int d1 = (int)(a > 0 ? ce : fl);
+        const bool twin = g.w1 != kNoTwin;
+        const uint32_t lo = (uint32_t)((wd[u] >> 16) & 0xFFu) | ((a > 0 ? 1u : 0u) << 8) | ((twin ? 1u : 0u) << 9) |
+                            ((uint32_t)(d0 + kStageClamp) << 10) | ((uint32_t)(d1 + kStageClamp) << 18);
+        const uint32_t top = wts ? ((uint32_t)g.w0 | ((uint32_t)g.w1 << 16)) : (uint32_t)(r0 + local);
+        rec[i] = (uint64_t)lo | ((uint64_t)top << 32);
+      }
+    }
+  }
+  // single-entry columns of this block: scored here from the LDS rows
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  const bool cut_on = st->cut_active != 0;
+  const double wc = (double)st->wc;
+  const gptr<const int32_t> cptr = gmem(P.col_ptr), crow = gmem(P.col_row);
+  const gptr<const double> cval = gmem(P.col_val), xg = gmem((const double*)C.x), lbg = gmem(P.lb),
+                           ubg = gmem(P.ub), objg = gmem(P.obj);
+  const gptr<double> xhat = gmem(C.xhat), sco = gmem(C.s);
+  for (int q = T.c_beg + tid; q < T.c_end; q += kThreads) {
+    const int e = cptr[q];
+    const int row = crow[e];
+    const double a = cval[e];
+    const double xb = xg[q], l = lbg[q], u = ubg[q];
+    const double c = cut_on ? objg[q] : 0.0;
+    const GatherRow g = rows[row - r0];
+    StageRec re;
+    re.lc = 0;
+    re.ap = a > 0.0;
+    const double qv = -(double)g.r / a;
+    const double fl = fmin(fmax(floor(qv), -(double)kStageClamp), (double)kStageClamp);
+    const double ce = fmin(fmax(ceil(qv), -(double)kStageClamp), (double)kStageClamp);
+    re.d0 = (int)(re.ap ? fl : ce);
+    re.d1 = (int)(re.ap ? ce : fl);
+    re.twin = g.w1 != kNoTwin;
+    if (wts) {
+      re.w0 = (double)g.w0;
+      re.w1 = (double)g.w1;
+    } else {
+      const RowState full = rs[row];
+      re.w0 = (double)full.w0;
+      re.w1 = (double)full.w1;
+    }
+    const int W = (int)(u - l) + 1, k0 = (int)(xb - l);
+    const bool cut = c != 0.0;
+    const int dcut = cut ? cutoff_offset(xb, st, c, P.eps) : 0;
+    bool found;
+    double best, bestp;
+    if (wts)
+      stage_short_col<1, int32_t>(&re, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);
+    else
+      stage_short_col<1, double>(&re, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);
+    write_result(xhat, sco, q, found, best, bestp, xb);
+  }
 }
 
 // Workgroups of a walk over ntask scoring tasks: kXcds * ceil(ntask / kXcds)
@@ -1620,7 +1670,7 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
   if (tid == 0) scount = 0;
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
-  general_phase1(P, FullRows{C.rs}, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
+  general_phase1(P, FullRows{gmem((const RowState*)C.rs)}, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
     const int k = atomicAdd(&scount, 1);
     spos[k] = p;
     smk[k] = m;
@@ -1709,9 +1759,22 @@ void PassStreams::destroy() {
 }
 
 template <typename Rows>
+#define CHAP_LAUNCH(...)      \
+  do {                        \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+    check();                  \
+  } while (0)
+
 hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
   const int nw = L.nw;
   auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
+  // a launch error (say, an LDS size the device refuses) is kept by the first
+  // check after it; later successful calls would otherwise clear it
+  hipError_t first = hipSuccess;
+  auto check = [&]() {
+    const hipError_t le = hipGetLastError();
+    if (first == hipSuccess) first = le;
+  };
   hipStream_t s_short = stream, s_long = stream;
   hipError_t e = hipSuccess;
   if (ps) {
@@ -1722,44 +1785,47 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     s_long = ps->side[1];
   }
   if (L.total[KS_SHORT] > 0)
-    hipLaunchKernelGGL(k_short<Rows>, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
+    CHAP_LAUNCH(k_short<Rows>, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
   if (L.total[KS_FLIP] > 0)
-    hipLaunchKernelGGL(k_flip_wave<Rows>, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
+    CHAP_LAUNCH(k_flip_wave<Rows>, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
+  // staged columns: the records first (alone: they are bound by HBM), then
+  // the short groups and the packs beside the long-column kernels, which are
+  // bound by L2 gathers
+  const bool staged = L.total[KS_STAGE] > 0;
+  if (staged)
+    CHAP_LAUNCH(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
+  if (ps && staged) {
+    e = hipEventRecord(ps->mid, stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->mid, 0);
+    if (e != hipSuccess) return e;
+  }
   if (L.total[KS_CHUNK] > 0) {
-    hipLaunchKernelGGL(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
-    hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+    CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
+    CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
   }
   if (L.total[KS_LONG] > 0)
-    hipLaunchKernelGGL(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
-  // staged columns: records first, then the short groups beside the packs
-  if (L.total[KS_STAGE] > 0)
-    hipLaunchKernelGGL(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
-  if (L.total[KS_STAGE_SHORT] > 0) {
-    if (ps) {
-      e = hipEventRecord(ps->mid, stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s_short, ps->mid, 0);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks,
+    CHAP_LAUNCH(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
+  if (L.total[KS_STAGE_SHORT] > 0)
+    CHAP_LAUNCH(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks,
                        L.off[KS_STAGE_SHORT], nw);
-  }
   if (L.total[KS_STAGE_PACK] > 0)
-    hipLaunchKernelGGL(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks,
+    CHAP_LAUNCH(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks,
                        L.off[KS_STAGE_PACK], nw);
   if (L.total[KS_PACK] > 0)
-    hipLaunchKernelGGL(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
+    CHAP_LAUNCH(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
   if (L.total[KS_SORT0] > 0)
-    hipLaunchKernelGGL((k_sort_block<64, Rows>), grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
+    CHAP_LAUNCH((k_sort_block<64, Rows>), grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
   if (L.total[KS_SORT0 + 1] > 0)
-    hipLaunchKernelGGL((k_sort_block<256, Rows>), grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks,
+    CHAP_LAUNCH((k_sort_block<256, Rows>), grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks,
                        L.off[KS_SORT0 + 1], nw);
   if (L.total[KS_SORT0 + 2] > 0)
-    hipLaunchKernelGGL((k_sort_block<1024, Rows>), grid(KS_SORT0 + 2), dim3(256), 0, stream, L.walks,
+    CHAP_LAUNCH((k_sort_block<1024, Rows>), grid(KS_SORT0 + 2), dim3(256), 0, stream, L.walks,
                        L.off[KS_SORT0 + 2], nw);
   if (L.total[KS_SORT0 + 3] > 0)
-    hipLaunchKernelGGL((k_sort_block<4096, Rows>), grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks,
+    CHAP_LAUNCH((k_sort_block<4096, Rows>), grid(KS_SORT0 + 3), dim3(256), 0, stream, L.walks,
                        L.off[KS_SORT0 + 3], nw);
-  e = hipGetLastError();
+  check();
+  e = first;
   if (ps) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       e = hipEventRecord(ps->join[k], ps->side[k]);
@@ -1768,6 +1834,8 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   }
   return e;
 }
+
+#undef CHAP_LAUNCH
 
 hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
   if (L.compact == 1) return launch_pass_rows<CompactRows>(L, stream, ps);

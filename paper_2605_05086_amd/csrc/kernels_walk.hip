@@ -227,12 +227,12 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
                                                 int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  const double* s = C.s;
-  const int32_t* tabu = C.tabu;
-  const int32_t* perm = C.P.perm;
+  const gptr<const double> s = gmem((const double*)C.s);
+  const gptr<const int32_t> tabu = gmem((const int32_t*)C.tabu);
+  const gptr<const int32_t> perm = gmem(C.P.perm);
   const WalkState* st = C.st;
-  const double* x = C.x;
-  double* best_x = C.best_x;
+  const gptr<const double> x = gmem((const double*)C.x);
+  const gptr<double> best_x = gmem(C.best_x);
   const int32_t n = C.P.n;
   if (st->k >= st->iters) return;
   __shared__ double sa_s[4], sn_s[4];

@@ -399,9 +399,11 @@ def test_best_shift_weight_kinds(chap, wkind):
 
 STAGE_CASES = [
     ("mixed", lambda: mipgen.random_mixed(71, n=400, m=300, max_row_nnz=9, frac_bin=0.2, frac_int=0.8,
-                                          int_width=90, long_cols=4, long_deg=120)),
-    ("few rows", lambda: mipgen.random_mixed(72, n=50, m=5, max_row_nnz=12, frac_bin=0.3, frac_int=0.7)),
-    ("powerlaw", lambda: mipgen.powerlaw(73, n=30_000, m=15_000, nnz=300_000, cap=5000)),
+                                          int_width=90, long_cols=4, long_deg=120), {}),
+    ("few rows", lambda: mipgen.random_mixed(72, n=50, m=5, max_row_nnz=12, frac_bin=0.3, frac_int=0.7), {}),
+    ("powerlaw", lambda: mipgen.powerlaw(73, n=30_000, m=15_000, nnz=300_000, cap=5000), {}),
+    # many long columns spanning several 8192-row blocks
+    ("long", lambda: mipgen.powerlaw(75, n=40_000, m=30_000, nnz=400_000, cap=20_000), dict(chunk_min=24)),
 ]
 
 
@@ -413,7 +415,7 @@ def test_best_shift_row_stage(chap, case, row_stage, cut):
     default on all-integer instances) and from direct gathers (row_stage=-1):
     both equal the oracle bit for bit, with and without the cutoff row, with
     empty row ranges (5 rows) and offsets beyond the +-64 clamp."""
-    name, make = STAGE_CASES[case]
+    name, make, opts = STAGE_CASES[case]
     mip = make()
     P = oracle.OracleProblem(mip)
     for seed in (0, 2):
@@ -421,10 +423,22 @@ def test_best_shift_row_stage(chap, case, row_stage, cut):
         w = mipgen.random_weights(P.mp + 1, seed + 1, wmax=9)
         cutoff = float(np.dot(mip.obj, x)) + 3.0 if cut else math.inf
         say(f"best_shift staged {name} row_stage={row_stage} cut={cut} seed={seed}")
-        xh, s = gpu_best_shift(chap, mip, x, w, cutoff, row_stage=row_stage)
+        xh, s = gpu_best_shift(chap, mip, x, w, cutoff, row_stage=row_stage, **opts)
         oxh, os_ = P.best_shift(x, w, cutoff)
         assert_same(s, os_, f"{name} score")
         assert_same(xh, oxh, f"{name} shift")
+
+
+def test_tabu_row_stage_long_columns(chap):
+    """A walk whose long columns (more than 24 entries) take the row-block
+    partials: equal to the oracle and to the unstaged walk."""
+    mip = mipgen.powerlaw(76, n=20_000, m=20_000, nnz=200_000, cap=10_000)
+    P = oracle.OracleProblem(mip)
+    say("tabu staged long columns 60 iters")
+    g = chap.Problem(mip, chunk_min=24).tabu_run(60, 5, 2)
+    compare_runs(g, P.tabu_run(60, 5, 2), "staged long")
+    h = chap.Problem(mip, chunk_min=24, row_stage=-1).tabu_run(60, 5, 2)
+    assert g.trace.tobytes() == h.trace.tobytes()
 
 
 def test_tabu_row_stage_full_rows(chap):
