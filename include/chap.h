@@ -143,9 +143,11 @@ int chap_problem_norm_row_map(const chap_problem *p, int32_t *orig_row, int8_t *
  *   d_shift    device, n doubles, out: xhat_j.
  *   d_score    device, n doubles, out: s_j (> 0, or 0 when no improvement).
  *   hip_stream hipStream_t to run on (NULL = the null stream).
- * Asynchronous: returns once the work is queued. The problem's internal
- * buffers are reused by every call, so calls on one problem must not overlap
- * (queue them on one stream). Errors: CHAP_EINVAL, CHAP_EHIP.
+ * Asynchronous: returns once the work is queued. The pass kernels are
+ * captured into a HIP graph on the first call and replayed by later calls.
+ * The problem's internal buffers are reused by every call, so calls on one
+ * problem must not overlap (queue them on one stream). Errors: CHAP_EINVAL,
+ * CHAP_EHIP.
  */
 int chap_best_shift(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
                     double *d_shift, double *d_score, void *hip_stream);

@@ -725,8 +725,29 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
                              p->obj_integral, cut, d_w + p->mp, 0, s));
   if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
+  if (p->n > 0 && !p->bs_exec) {
+    // capture the pass once (its arguments are the problem's own buffers)
+    if (!p->bs_cap) CHAP_HIP(hipStreamCreateWithFlags(&p->bs_cap, hipStreamNonBlocking));
+    CHAP_HIP(hipStreamBeginCapture(p->bs_cap, hipStreamCaptureModeThreadLocal));
+    const hipError_t cap_err = launch_pass(p->bs_launch, p->bs_cap, &p->bs_streams);
+    hipGraph_t graph = nullptr;
+    const hipError_t end_err = hipStreamEndCapture(p->bs_cap, &graph);
+    if (cap_err != hipSuccess || end_err != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(CHAP_EHIP, std::string("pass capture: ") +
+                                 hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(CHAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    p->bs_graph = graph;
+    p->bs_exec = exec;
+  }
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
-  if (p->n > 0) CHAP_HIP(launch_pass(p->bs_launch, s, &p->bs_streams));
+  if (p->n > 0) CHAP_HIP(hipGraphLaunch(p->bs_exec, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
   CHAP_HIP(launch_scatter2(p->dev.perm, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
   p->pass_timed = true;

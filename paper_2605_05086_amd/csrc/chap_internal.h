@@ -615,9 +615,17 @@ struct chap_problem {
   hipEvent_t pass_ev[2] = {nullptr, nullptr};
   chap::PassStreams bs_streams;
   bool pass_timed = false;
+  // the pass kernels of chap_best_shift as one HIP graph, captured on the
+  // first call and replayed on the caller's stream
+  hipStream_t bs_cap = nullptr;
+  hipGraph_t bs_graph = nullptr;
+  hipGraphExec_t bs_exec = nullptr;
   ~chap_problem() {
     for (hipEvent_t e : pass_ev)
       if (e) (void)hipEventDestroy(e);
+    if (bs_exec) (void)hipGraphExecDestroy(bs_exec);
+    if (bs_graph) (void)hipGraphDestroy(bs_graph);
+    if (bs_cap) (void)hipStreamDestroy(bs_cap);
     bs_streams.destroy();
   }
 };

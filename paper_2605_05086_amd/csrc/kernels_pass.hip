@@ -809,10 +809,13 @@ __device__ __forceinline__ int cutoff_offset(double xb, const WalkState* st, dou
 
 template <typename V>
 struct StagePackSmem {
-  V bins[kStagePackCols][kNarrowBins + 1];  // padded: lane c reads row c without bank conflicts
-  unsigned long long cand[kStagePackCols];
-  double xb[kStagePackCols];
-  int32_t W[kStagePackCols], k0[kStagePackCols];
+  // columns binned at once: a whole pack with int32 values, half of one with
+  // FP64 values (which then takes two passes over the records)
+  static constexpr int kCols = sizeof(V) == 4 ? kStagePackCols : kStagePackCols / 2;
+  V bins[kCols][kNarrowBins + 1];  // padded: lane c reads row c without bank conflicts
+  unsigned long long cand[kCols];
+  double xb[kCols];
+  int32_t W[kCols], k0[kCols];
 };
 
 struct StageShortSmem {
@@ -850,80 +853,89 @@ __device__ __forceinline__ int stage_segments(const WalkCtx& C, int t, StageSegs
 template <typename Rows, typename V>
 __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, bool wts, int tix, StagePackSmem<V>& S,
                                            StageSegs& G) {
+  constexpr int kCols = StagePackSmem<V>::kCols;
   const StageTask T = C.plan.stage_tasks[tix];
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   const int tid = threadIdx.x;
   const int nc = T.q_end - T.q_begin;
-  if (tid < nc) {
-    const int q = T.q_begin + tid;
-    const double xb = gmem((const double*)C.x)[q], l = gmem(P.lb)[q];
-    S.xb[tid] = xb;
-    S.W[tid] = (int)(gmem(P.ub)[q] - l) + 1;
-    S.k0[tid] = (int)(xb - l);
-    S.cand[tid] = 0ull;
-  }
-  for (int i = tid; i < nc * (kNarrowBins + 1); i += blockDim.x)
-    S.bins[i / (kNarrowBins + 1)][i % (kNarrowBins + 1)] = 0;
-  const V zero = 0;  // stage_segments below ends with a barrier
+  const V zero = 0;
   const int nrb = C.plan.n_stage_rb;
   stage_segments(C, tix, G);
   const gptr<const uint64_t> recs = gmem((const uint64_t*)C.stage_rec);
-  // tps threads per row-block segment, each a contiguous part of it, kRun
-  // records per step
-  constexpr int kRun = 4;
   const int tps = max(1, (int)blockDim.x / nrb);
-  for (int sg = tid / tps; sg < nrb; sg += (int)blockDim.x / tps) {
-    const int len = G.pre[sg + 1] - G.pre[sg];
-    const int per = (len + tps - 1) / tps;
-    const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
-    for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
-      uint64_t r[kRun];
+  for (int c0 = 0; c0 < nc; c0 += kCols) {
+    const int ncw = min(kCols, nc - c0);
+    if (tid < ncw) {
+      const int q = T.q_begin + c0 + tid;
+      const double xb = gmem((const double*)C.x)[q], l = gmem(P.lb)[q];
+      S.xb[tid] = xb;
+      S.W[tid] = (int)(gmem(P.ub)[q] - l) + 1;
+      S.k0[tid] = (int)(xb - l);
+      S.cand[tid] = 0ull;
+    }
+    for (int i = tid; i < ncw * (kNarrowBins + 1); i += blockDim.x)
+      S.bins[i / (kNarrowBins + 1)][i % (kNarrowBins + 1)] = 0;
+    __syncthreads();
+    // tps threads per row-block segment, each a contiguous part of it, kRun
+    // records per step; records of columns outside this window are skipped
+    constexpr int kRun = 4;
+    for (int sg = tid / tps; sg < nrb; sg += (int)blockDim.x / tps) {
+      const int len = G.pre[sg + 1] - G.pre[sg];
+      const int per = (len + tps - 1) / tps;
+      const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
+      for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
+        uint64_t r[kRun];
 #pragma unroll
-      for (int u = 0; u < kRun; ++u)
-        if (i0 + u < i1) r[u] = recs[i0 + u];
+        for (int u = 0; u < kRun; ++u)
+          if (i0 + u < i1) r[u] = recs[i0 + u];
 #pragma unroll
-      for (int u = 0; u < kRun; ++u) {
-        if (i0 + u < i1) {
-          const StageRec e = decode_rec(r[u], wts, rs);
-          const int k0 = S.k0[e.lc], W = S.W[e.lc];
-          add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[e.lc], &S.cand[e.lc]);
-          if (e.twin)
-            add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[e.lc],
-                    &S.cand[e.lc]);
+        for (int u = 0; u < kRun; ++u) {
+          if (i0 + u < i1) {
+            const int lc = (int)(r[u] & 0xFFu) - c0;
+            if (lc < 0 || lc >= ncw) continue;
+            const StageRec e = decode_rec(r[u], wts, rs);
+            const int k0 = S.k0[lc], W = S.W[lc];
+            add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[lc], &S.cand[lc]);
+            if (e.twin)
+              add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[lc], &S.cand[lc]);
+          }
         }
       }
     }
-  }
-  if (tid < nc && st->cut_active) {
-    const double c = P.obj[T.q_begin + tid];
-    if (c != 0.0) {
-      const double wc = (double)st->wc;
-      add_row(c > 0.0, cutoff_offset(S.xb[tid], st, c, P.eps), stage_one(wc, zero), stage_half(wc, zero), S.k0[tid],
-              S.W[tid], S.bins[tid], &S.cand[tid]);
-    }
-  }
-  __syncthreads();
-  if (tid >= nc) return;
-  const int W = S.W[tid], k0 = S.k0[tid];
-  const unsigned long long cand = S.cand[tid];
-  const uint32_t clo = (uint32_t)cand, chi = (uint32_t)(cand >> 32);
-  V acc = 0, best = 0;
-  int bk = -1;
-#pragma unroll
-  for (int k = 0; k < kNarrowBins; ++k) {
-    if (k < W) {
-      acc += S.bins[tid][k];
-      const bool bit = k < 32 ? ((clo >> k) & 1u) != 0 : ((chi >> (k - 32)) & 1u) != 0;
-      const bool ok = (bit || k == 0 || k == W - 1) && k != k0;
-      if (ok && (bk < 0 || acc > best)) {
-        best = acc;
-        bk = k;
+    if (tid < ncw && st->cut_active) {
+      const double c = gmem(P.obj)[T.q_begin + c0 + tid];
+      if (c != 0.0) {
+        const double wc = (double)st->wc;
+        add_row(c > 0.0, cutoff_offset(S.xb[tid], st, c, P.eps), stage_one(wc, zero), stage_half(wc, zero),
+                S.k0[tid], S.W[tid], S.bins[tid], &S.cand[tid]);
       }
     }
+    __syncthreads();
+    if (tid < ncw) {
+      const int W = S.W[tid], k0 = S.k0[tid];
+      const unsigned long long cand = S.cand[tid];
+      const uint32_t clo = (uint32_t)cand, chi = (uint32_t)(cand >> 32);
+      V acc = 0, best = 0;
+      int bk = -1;
+#pragma unroll
+      for (int k = 0; k < kNarrowBins; ++k) {
+        if (k < W) {
+          acc += S.bins[tid][k];
+          const bool bit = k < 32 ? ((clo >> k) & 1u) != 0 : ((chi >> (k - 32)) & 1u) != 0;
+          const bool ok = (bit || k == 0 || k == W - 1) && k != k0;
+          if (ok && (bk < 0 || acc > best)) {
+            best = acc;
+            bk = k;
+          }
+        }
+      }
+      const double xb = S.xb[tid];
+      write_result(gmem(C.xhat), gmem(C.s), T.q_begin + c0 + tid, bk >= 0, stage_score_of(best),
+                   xb + (double)(bk - k0), xb);
+    }
+    __syncthreads();  // the next window reuses the LDS
   }
-  const double xb = S.xb[tid];
-  write_result(gmem(C.xhat), gmem(C.s), T.q_begin + tid, bk >= 0, stage_score_of(best), xb + (double)(bk - k0), xb);
 }
 
 __device__ __forceinline__ void cswap_u64(uint64_t& a, uint64_t& b) {
