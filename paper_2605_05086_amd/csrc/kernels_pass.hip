@@ -753,23 +753,33 @@ __device__ __forceinline__ void row_terms(bool ap, int d, V one, V half, V& beta
   }
 }
 
-// The same row added to a column's bins (k0 = xbar - l, W values) without
-// branches: beta goes to bin 0, alpha to bin k0 + 1 (the first position
-// above xbar), delta to the bin where it starts to apply (bin 0 when that is
-// below l); terms that apply nowhere go to the sink bin kNarrowBins. The
-// breakpoint is a candidate when inside [l, u].
+// Coefficients, in half weights, of beta, alpha and delta of a row for the
+// six cases of phase1() (index 3 [a > 0] + sign(d) + 1): 4-bit fields.
+constexpr uint32_t pack6(int c0, int c1, int c2, int c3, int c4, int c5) {
+  return (uint32_t)(c0 & 15) | (uint32_t)(c1 & 15) << 4 | (uint32_t)(c2 & 15) << 8 | (uint32_t)(c3 & 15) << 12 |
+         (uint32_t)(c4 & 15) << 16 | (uint32_t)(c5 & 15) << 20;
+}
+constexpr uint32_t kCoefBeta = pack6(-2, -2, -1, 2, 0, 0);
+constexpr uint32_t kCoefAlpha = pack6(0, 2, 2, -2, -2, 0);
+constexpr uint32_t kCoefDelta = pack6(2, 0, 1, -1, 0, -2);
+__device__ __forceinline__ int row_coef(uint32_t packed, int cs) { return ((int)(packed << (28 - 4 * cs))) >> 28; }
+
+// The same row added to a column's bins (k0 = xbar - l, W values; half =
+// w/2 in value units): beta goes to bin 0, alpha to bin k0 + 1 (the first
+// position above xbar), delta to the bin where it starts to apply (bin 0 when
+// that is below l, the sink bin kNarrowBins when above u). The breakpoint is
+// a candidate when inside [l, u].
 template <typename V>
-__device__ __forceinline__ void add_row(bool ap, int d, V one, V half, int k0, int W, V* bins,
-                                        unsigned long long* cand) {
-  const bool neg = d < 0, pos = d > 0;
-  const V zero = 0;
-  const V b = ap ? (neg ? one : zero) : (pos ? -half : -one);
-  const V al = ap ? (pos ? zero : -one) : (neg ? zero : one);
-  const V dl = ap ? (neg ? -half : (pos ? -one : zero)) : (pos ? half : (neg ? one : zero));
+__device__ __forceinline__ void add_row(bool ap, int d, V half, int k0, int W, V* bins, unsigned long long* cand) {
+  const int cs = (ap ? 4 : 1) + (d > 0 ? 1 : 0) - (d < 0 ? 1 : 0);
+  const V b = (V)row_coef(kCoefBeta, cs) * half;
+  const V al = (V)row_coef(kCoefAlpha, cs) * half;
+  const V dl = (V)row_coef(kCoefDelta, cs) * half;
   const int k = k0 + d;
   const int kb = k + (ap ? 1 : 0);
   const int idx = k < 0 ? 0 : ((k >= W || kb >= W) ? kNarrowBins : kb);
   const int ia = k0 + 1 < W ? k0 + 1 : kNarrowBins;
+  const V zero = 0;
   if (b != zero) atomicAdd(&bins[0], b);
   if (al != zero) atomicAdd(&bins[ia], al);
   if (dl != zero) atomicAdd(&bins[idx], dl);
@@ -896,9 +906,8 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
             if (lc < 0 || lc >= ncw) continue;
             const StageRec e = decode_rec(r[u], wts, rs);
             const int k0 = S.k0[lc], W = S.W[lc];
-            add_row(e.ap, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), k0, W, S.bins[lc], &S.cand[lc]);
-            if (e.twin)
-              add_row(!e.ap, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), k0, W, S.bins[lc], &S.cand[lc]);
+            add_row(e.ap, e.d0, stage_half(e.w0, zero), k0, W, S.bins[lc], &S.cand[lc]);
+            if (e.twin) add_row(!e.ap, e.d1, stage_half(e.w1, zero), k0, W, S.bins[lc], &S.cand[lc]);
           }
         }
       }
@@ -907,8 +916,8 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
       const double c = gmem(P.obj)[T.q_begin + c0 + tid];
       if (c != 0.0) {
         const double wc = (double)st->wc;
-        add_row(c > 0.0, cutoff_offset(S.xb[tid], st, c, P.eps), stage_one(wc, zero), stage_half(wc, zero),
-                S.k0[tid], S.W[tid], S.bins[tid], &S.cand[tid]);
+        add_row(c > 0.0, cutoff_offset(S.xb[tid], st, c, P.eps), stage_half(wc, zero), S.k0[tid], S.W[tid],
+                S.bins[tid], &S.cand[tid]);
       }
     }
     __syncthreads();
