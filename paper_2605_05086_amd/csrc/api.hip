@@ -481,6 +481,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   std::vector<int32_t> sseg;
   std::vector<uint64_t> sent;
   std::vector<StageRowTask> srtasks;
+  L.stage_exact = stage ? 1 : 0;
   if (stage) {
     for (const PackTask& t : packs) stasks.push_back(StageTask{t.q_begin, t.q_end, -1, 0});
     packs.clear();

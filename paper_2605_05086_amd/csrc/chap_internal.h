@@ -287,6 +287,7 @@ struct PassPlan {
   // record of the task in each row block, then the task's records in the
   // blocks before each block (the last value: all of them)
   int32_t stage = 0;
+  int32_t stage_exact = 0;  // the integer breakpoint identity holds (staging eligible)
   int32_t n_stage_tasks = 0;
   int32_t n_stage_packs = 0;
   int32_t n_stage_rtasks = 0;

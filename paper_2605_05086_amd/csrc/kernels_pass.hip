@@ -587,6 +587,44 @@ __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__
   }
 }
 
+// Offset of the cutoff row's breakpoint from xbar, clamped like the records.
+__device__ __forceinline__ int cutoff_offset(double xb, const WalkState* st, double c, double eps) {
+  const double t = breakpoint(xb, st->rc, c, eps, true);
+  return (int)fmin(fmax(t - xb, -(double)kStageClamp), (double)kStageClamp);
+}
+
+// Coefficients, in half weights, of beta, alpha and delta of a row for the
+// six cases of phase1() (index 3 [a > 0] + sign(d) + 1): 4-bit fields.
+constexpr uint32_t pack6(int c0, int c1, int c2, int c3, int c4, int c5) {
+  return (uint32_t)(c0 & 15) | (uint32_t)(c1 & 15) << 4 | (uint32_t)(c2 & 15) << 8 | (uint32_t)(c3 & 15) << 12 |
+         (uint32_t)(c4 & 15) << 16 | (uint32_t)(c5 & 15) << 20;
+}
+constexpr uint32_t kCoefBeta = pack6(-2, -2, -1, 2, 0, 0);
+constexpr uint32_t kCoefAlpha = pack6(0, 2, 2, -2, -2, 0);
+constexpr uint32_t kCoefDelta = pack6(2, 0, 1, -1, 0, -2);
+__device__ __forceinline__ int row_coef(uint32_t packed, int cs) { return ((int)(packed << (28 - 4 * cs))) >> 28; }
+
+// One row of a long column (one column per workgroup) in half weights:
+// beta, alpha and the candidate mask summed by the caller, delta into the
+// bins (the cases of phase1() in offset form, as add_row).
+__device__ __forceinline__ void add_row_reg(bool ap, int d, int32_t half, int k0, int W, int32_t* bins,
+                                            int32_t& beta, int32_t& alpha, unsigned long long& cand) {
+  const int cs = (ap ? 4 : 1) + (d > 0 ? 1 : 0) - (d < 0 ? 1 : 0);
+  beta += row_coef(kCoefBeta, cs) * half;
+  alpha += row_coef(kCoefAlpha, cs) * half;
+  if (d == 0) return;
+  const int32_t dl = row_coef(kCoefDelta, cs) * half;
+  const int k = k0 + d;
+  if (k < 0) {
+    beta += dl;
+    return;
+  }
+  if (k >= W) return;
+  cand |= 1ull << k;
+  const int kb = k + (ap ? 1 : 0);
+  if (kb < W) atomicAdd(&bins[kb], dl);
+}
+
 // One workgroup per chunk of a long narrow column: bins, beta, alpha and the
 // candidate mask of the chunk go to the chunk's partial record. Chunks are
 // cut along row ranges and ordered so that consecutive workgroups (placed on
@@ -603,17 +641,65 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
   ChunkPartial* partials = C.partials;
   if (st->k >= st->iters) return;
   __shared__ double bins[kNarrowBins];
+  __shared__ int32_t ibins[kNarrowBins];
   __shared__ double red_b[4], red_a[4];
   __shared__ unsigned long long red_c[4];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid >> 6;
   const ChunkTask T = C.plan.chunks[lb];
-  if (tid < kNarrowBins) bins[tid] = 0.0;
+  // integer data with integral weights: breakpoint offsets from one quotient
+  // and half-weight integer bins (the identity of row-block staging)
+  const bool exact = C.plan.stage_exact != 0 && stage_weights<Rows>(C);
+  if (tid < kNarrowBins) {
+    bins[tid] = 0.0;
+    ibins[tid] = 0;
+  }
   __syncthreads();
   double beta = 0.0, alpha = 0.0;
   unsigned long long cand = 0;
-  if (T.col >= 0) {
+  if (T.col >= 0 && exact) {
+    const int q = T.col;
+    const double xb = gmem(x)[q];
+    const double l = gmem(P.lb)[q];
+    const int W = (int)(gmem(P.ub)[q] - l) + 1, k0 = (int)(xb - l);
+    const gptr<const int32_t> crow = gmem(P.col_row);
+    const gptr<const double> cval = gmem(P.col_val);
+    int32_t ib = 0, ia = 0;
+    int e = T.e_beg + tid;
+    for (; e < T.e_end; e += 512) {
+      const bool two = e + 256 < T.e_end;
+      const int i0 = __builtin_nontemporal_load(&crow[e]);
+      const double a0 = __builtin_nontemporal_load(&cval[e]);
+      int i1 = i0;
+      double a1 = a0;
+      if (two) {
+        i1 = __builtin_nontemporal_load(&crow[e + 256]);
+        a1 = __builtin_nontemporal_load(&cval[e + 256]);
+      }
+      const RowState r0 = rs[i0];
+      const RowState r1 = rs[i1];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u == 1 && !two) break;
+        const RowState& r = u ? r1 : r0;
+        const double a = u ? a1 : a0;
+        const bool ap = a > 0.0;
+        const double qv = -r.r / a;
+        const double fl = fmin(fmax(floor(qv), -(double)kStageClamp), (double)kStageClamp);
+        const double ce = fmin(fmax(ceil(qv), -(double)kStageClamp), (double)kStageClamp);
+        add_row_reg(ap, (int)(ap ? fl : ce), (int32_t)r.w0, k0, W, ibins, ib, ia, cand);
+        if (r.w1 >= 0.0f) add_row_reg(!ap, (int)(ap ? ce : fl), (int32_t)r.w1, k0, W, ibins, ib, ia, cand);
+      }
+    }
+    if (tid == 0 && T.first && st->cut_active) {
+      const double c = P.obj[q];
+      if (c != 0.0)
+        add_row_reg(c > 0.0, cutoff_offset(xb, st, c, P.eps), (int32_t)st->wc, k0, W, ibins, ib, ia, cand);
+    }
+    beta = 0.5 * (double)ib;
+    alpha = 0.5 * (double)ia;
+  } else if (T.col >= 0) {
     const int q = T.col;
     const double eps = P.eps;
     const double xb = gmem(x)[q];
@@ -658,7 +744,7 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
   __syncthreads();
   if (T.col < 0) return;
   const gptr<ChunkPartial> mine = gmem(partials) + T.slot;
-  if (tid < kNarrowBins) mine->bins[tid] = bins[tid];
+  if (tid < kNarrowBins) mine->bins[tid] = exact ? 0.5 * (double)ibins[tid] : bins[tid];
   if (tid == 0) {
     mine->beta = red_b[0] + red_b[1] + red_b[2] + red_b[3];
     mine->alpha = red_a[0] + red_a[1] + red_a[2] + red_a[3];
@@ -753,17 +839,6 @@ __device__ __forceinline__ void row_terms(bool ap, int d, V one, V half, V& beta
   }
 }
 
-// Coefficients, in half weights, of beta, alpha and delta of a row for the
-// six cases of phase1() (index 3 [a > 0] + sign(d) + 1): 4-bit fields.
-constexpr uint32_t pack6(int c0, int c1, int c2, int c3, int c4, int c5) {
-  return (uint32_t)(c0 & 15) | (uint32_t)(c1 & 15) << 4 | (uint32_t)(c2 & 15) << 8 | (uint32_t)(c3 & 15) << 12 |
-         (uint32_t)(c4 & 15) << 16 | (uint32_t)(c5 & 15) << 20;
-}
-constexpr uint32_t kCoefBeta = pack6(-2, -2, -1, 2, 0, 0);
-constexpr uint32_t kCoefAlpha = pack6(0, 2, 2, -2, -2, 0);
-constexpr uint32_t kCoefDelta = pack6(2, 0, 1, -1, 0, -2);
-__device__ __forceinline__ int row_coef(uint32_t packed, int cs) { return ((int)(packed << (28 - 4 * cs))) >> 28; }
-
 // The same row added to a column's bins (k0 = xbar - l, W values; half =
 // w/2 in value units): beta goes to bin 0, alpha to bin k0 + 1 (the first
 // position above xbar), delta to the bin where it starts to apply (bin 0 when
@@ -811,11 +886,6 @@ __device__ __forceinline__ StageRec decode_rec(uint64_t r, bool wts, const Rows&
   return o;
 }
 
-// Offset of the cutoff row's breakpoint from xbar, clamped like the records.
-__device__ __forceinline__ int cutoff_offset(double xb, const WalkState* st, double c, double eps) {
-  const double t = breakpoint(xb, st->rc, c, eps, true);
-  return (int)fmin(fmax(t - xb, -(double)kStageClamp), (double)kStageClamp);
-}
 
 template <typename V>
 struct StagePackSmem {
