@@ -242,13 +242,31 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
   Best ba, bn;
   const int gt = lb * blockDim.x + threadIdx.x;
   const int gs = C.argmax_blocks * blockDim.x;
-  for (int q = gt; q < n; q += gs) {
-    if (copy) best_x[q] = x[q];
-    const double v = s[q];
-    if (!(v > 0.0)) continue;
-    const int j = perm[q];
-    ba.offer(v, j, q);
-    if (k > (int64_t)tabu[q]) bn.offer(v, j, q);
+  if (copy)
+    for (int q = gt; q < n; q += gs) best_x[q] = x[q];
+  // kU columns per thread and step, every load issued before any is used
+  constexpr int kU = 4;
+  for (int q0 = gt; q0 < n; q0 += kU * gs) {
+    double v[kU];
+    int j[kU], tb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + u * gs;
+      v[u] = 0.0;
+      if (q < n) {
+        v[u] = s[q];
+        j[u] = perm[q];
+        tb[u] = tabu[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + u * gs;
+      if (q < n && v[u] > 0.0) {
+        ba.offer(v[u], j[u], q);
+        if (k > (int64_t)tb[u]) bn.offer(v[u], j[u], q);
+      }
+    }
   }
   ba.wave_reduce();
   bn.wave_reduce();
@@ -392,10 +410,24 @@ __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walk
   const int32_t nparts = C.argmax_blocks;
   if (C.st->k >= C.st->iters) return;
   Best ba, bn;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    const double* rec = partial + kPartialStride * b;
-    ba.offer(rec[0], (int)rec[1], (int)rec[2]);
-    bn.offer(rec[3], (int)rec[4], (int)rec[5]);
+  const gptr<const double> pg = gmem(partial);
+  // all of a thread's records are loaded before any is compared
+  constexpr int kU = 4;
+  for (int b0 = threadIdx.x; b0 < nparts; b0 += kU * blockDim.x) {
+    double r[kU][6];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = b0 + u * blockDim.x;
+      if (b < nparts)
+#pragma unroll
+        for (int f = 0; f < 6; ++f) r[u][f] = pg[kPartialStride * b + f];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b0 + u * (int)blockDim.x < nparts) {
+        ba.offer(r[u][0], (int)r[u][1], (int)r[u][2]);
+        bn.offer(r[u][3], (int)r[u][4], (int)r[u][5]);
+      }
   }
   block_best(ba, bn);
   decide(C, ba, bn, 2, 0);
