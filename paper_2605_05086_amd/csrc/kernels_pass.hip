@@ -777,12 +777,28 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   const int W = (int)(u - l) + 1;
   double bv = 0.0, b = 0.0, a = 0.0;
   unsigned long long c = 0;
-  for (int k = 0; k < C.nparts; ++k) {
-    const gptr<const ChunkPartial> pp = gmem(partials) + C.first + k;
-    bv += pp->bins[lane];
-    b += pp->beta;
-    a += pp->alpha;
-    c |= pp->cand;
+  // partials in slot order (a fixed summation order); kU loaded at a time
+  constexpr int kU = 4;
+  const gptr<const ChunkPartial> pp = gmem(partials) + C.first;
+  for (int k0 = 0; k0 < C.nparts; k0 += kU) {
+    double pv[kU], pb[kU], pa[kU];
+    unsigned long long pc[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < C.nparts) {
+        pv[u] = pp[k0 + u].bins[lane];
+        pb[u] = pp[k0 + u].beta;
+        pa[u] = pp[k0 + u].alpha;
+        pc[u] = pp[k0 + u].cand;
+      }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < C.nparts) {
+        bv += pv[u];
+        b += pb[u];
+        a += pa[u];
+        c |= pc[u];
+      }
   }
   bool found;
   double best, bestp;
