@@ -481,6 +481,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   std::vector<int32_t> sseg;
   std::vector<uint64_t> sent;
   std::vector<StageRowTask> srtasks;
+  std::vector<int32_t> sunits;
   L.stage_exact = stage ? 1 : 0;
   if (stage) {
     for (const PackTask& t : packs) stasks.push_back(StageTask{t.q_begin, t.q_end, -1, 0});
@@ -553,12 +554,29 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     for (size_t k = 0; k < rounds; ++k)
       for (int x = 0; x < kXcds; ++x)
         srtasks.push_back(k < per_xcd[x].size() ? per_xcd[x][k] : StageRowTask{-1, 0, 0, 0, 0, {0, 0, 0}});
+    // units of the single scoring launch: chunk, pack and short-group units
+    // interleaved in proportion to their counts, so that the latency-bound
+    // chunk gathers and the VALU-bound scoring share every CU
+    {
+      const int32_t cnt[3] = {(int32_t)tasks.size() / kXcds, (npk + kXcds - 1) / kXcds,
+                              ((int32_t)T - npk + kXcds - 1) / kXcds};
+      int32_t done[3] = {0, 0, 0};
+      for (int32_t u = 0; u < cnt[0] + cnt[1] + cnt[2]; ++u) {
+        int best = -1;
+        for (int r = 0; r < 3; ++r)
+          if (done[r] < cnt[r] &&
+              (best < 0 || (2.0 * done[r] + 1.0) * cnt[best] < (2.0 * done[best] + 1.0) * cnt[r]))
+            best = r;
+        sunits.push_back((best << 28) | done[best]++);
+      }
+    }
     L.n_stage_ent = (int32_t)sent.size();
     L.n_stage_tasks = (int32_t)T;
     L.n_stage_packs = npk;
     L.n_stage_rtasks = (int32_t)srtasks.size();
     L.n_stage_rb = nrb;
     L.stage = (T > 0 || L.stage_one_end > L.stage_one_begin) ? 1 : 0;
+    L.n_stage_units = L.stage ? (int32_t)sunits.size() : 0;
   }
   std::vector<LongTask> longs;
   int64_t long_total = 0;
@@ -655,6 +673,11 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     L.stage_seg = dseg;
     L.stage_ent = dent;
     L.stage_rtasks = drt;
+    if (!sunits.empty()) {
+      int32_t* du;
+      CHAP_HIP(A.upload(&du, sunits));
+      L.stage_units = du;
+    }
   }
   if (!tasks.empty()) {
     ChunkTask* dt;

@@ -92,7 +92,8 @@ enum : uint8_t {
 
 constexpr int kShortMax = 8;       // normalised entries a single lane can score
 constexpr int kXcds = 8;           // L2 domains (XCDs) of an MI355X; chunks are cut into as many row ranges
-constexpr int kNarrowBins = 64;    // values of a narrow integer column
+constexpr int kNarrowBins = 64;
+constexpr int32_t kStageUnitMask = 0x0FFFFFFF;    // values of a narrow integer column
 constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
 constexpr int kArgmaxBlocks = 1024;  // workgroups of the move-selection reduction
@@ -299,6 +300,12 @@ struct PassPlan {
   int32_t n_stage_ent = 0;
   int32_t stage_short_begin = 0, stage_short_end = 0;
   int32_t stage_one_begin = 0, stage_one_end = 0;  // single-entry short narrow columns
+  // the scoring launch of a staged pass over the compact row copy, in units
+  // of kXcds workgroups: unit u runs role (stage_units[u] >> 28) (0 chunks,
+  // 1 packs, 2 short groups) on that role's unit (stage_units[u] &
+  // kStageUnitMask)
+  const int32_t* stage_units = nullptr;
+  int32_t n_stage_units = 0;
 };
 
 // Everything the kernels of one walk need: its instance, the instance's pass
@@ -339,6 +346,7 @@ enum KernelSlot {
   KS_STAGE,
   KS_STAGE_PACK,
   KS_STAGE_SHORT,
+  KS_STAGE_SCORE,
   KS_ARGMAX,
   KS_SELECT,
   KS_APPLY,

@@ -629,21 +629,67 @@ __device__ __forceinline__ void add_row_reg(bool ap, int d, int32_t half, int k0
 // candidate mask of the chunk go to the chunk's partial record. Chunks are
 // cut along row ranges and ordered so that consecutive workgroups (placed on
 // consecutive XCDs) gather rows from one range each.
+// Combines the partials of long narrow column idx (a ChunkCol record) in
+// slot order (a fixed summation order), then scan and argmax over the bins;
+// one wavefront.
+__device__ __forceinline__ void combine_col(const WalkCtx& W0, int idx, int lane) {
+  const DevProblem& P = W0.P;
+  const ChunkCol C = W0.plan.chunk_cols[idx];
+  const int q = C.col;
+  const double xb = gmem((const double*)W0.x)[q];
+  const double l = gmem(P.lb)[q], u = gmem(P.ub)[q];
+  const int W = (int)(u - l) + 1;
+  double bv = 0.0, b = 0.0, a = 0.0;
+  unsigned long long c = 0;
+  // kU partials loaded at a time
+  constexpr int kU = 4;
+  const gptr<const ChunkPartial> pp = gmem((const ChunkPartial*)W0.partials) + C.first;
+  for (int k0 = 0; k0 < C.nparts; k0 += kU) {
+    double pv[kU], pb[kU], pa[kU];
+    unsigned long long pc[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < C.nparts) {
+        pv[u] = pp[k0 + u].bins[lane];
+        pb[u] = pp[k0 + u].beta;
+        pa[u] = pp[k0 + u].alpha;
+        pc[u] = pp[k0 + u].cand;
+      }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < C.nparts) {
+        bv += pv[u];
+        b += pb[u];
+        a += pa[u];
+        c |= pc[u];
+      }
+  }
+  bool found;
+  double best, bestp;
+  narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
+  if (lane == 0) write_result(gmem(W0.xhat), gmem(W0.s), q, found, best, bestp, xb);
+}
+
+struct ChunkSmem {
+  double bins[kNarrowBins];
+  int32_t ibins[kNarrowBins];
+  double red_b[4], red_a[4];
+  unsigned long long red_c[4];
+};
+
 template <typename Rows>
-__global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict__ walks,
-                                                      const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+__device__ __forceinline__ void chunk_task(const WalkCtx& C, int lb, ChunkSmem& S) {
   const DevProblem& P = C.P;
   const double* x = C.x;
   const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   ChunkPartial* partials = C.partials;
   if (st->k >= st->iters) return;
-  __shared__ double bins[kNarrowBins];
-  __shared__ int32_t ibins[kNarrowBins];
-  __shared__ double red_b[4], red_a[4];
-  __shared__ unsigned long long red_c[4];
+  double* bins = S.bins;
+  int32_t* ibins = S.ibins;
+  double* red_b = S.red_b;
+  double* red_a = S.red_a;
+  unsigned long long* red_c = S.red_c;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid >> 6;
@@ -752,58 +798,24 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
   }
 }
 
-// One wavefront per long narrow column: combines its chunks' partials in
-// slot order (deterministic), then scan and argmax over the bins.
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict__ walks,
+                                                      const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  __shared__ ChunkSmem S;
+  chunk_task<Rows>(C, lb, S);
+}
+
+// One wavefront per long narrow column.
 __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restrict__ walks,
                                                         const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& W0 = walks[block_walk(off, nw, lb)];
-  const DevProblem& P = W0.P;
-  const double* x = W0.x;
-  const WalkState* st = W0.st;
-  double* xhat = W0.xhat;
-  double* sc = W0.s;
-  const ChunkCol* cols = W0.plan.chunk_cols;
-  const int32_t count = W0.plan.n_chunk_cols;
-  const ChunkPartial* partials = W0.partials;
-  if (st->k >= st->iters) return;
-  const int lane = threadIdx.x & (kWave - 1);
+  if (W0.st->k >= W0.st->iters) return;
   const int idx = lb * 4 + (threadIdx.x >> 6);
-  if (idx >= count) return;
-  const ChunkCol C = cols[idx];
-  const int q = C.col;
-  const double xb = gmem(x)[q];
-  const double l = gmem(P.lb)[q], u = gmem(P.ub)[q];
-  const int W = (int)(u - l) + 1;
-  double bv = 0.0, b = 0.0, a = 0.0;
-  unsigned long long c = 0;
-  // partials in slot order (a fixed summation order); kU loaded at a time
-  constexpr int kU = 4;
-  const gptr<const ChunkPartial> pp = gmem(partials) + C.first;
-  for (int k0 = 0; k0 < C.nparts; k0 += kU) {
-    double pv[kU], pb[kU], pa[kU];
-    unsigned long long pc[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        pv[u] = pp[k0 + u].bins[lane];
-        pb[u] = pp[k0 + u].beta;
-        pa[u] = pp[k0 + u].alpha;
-        pc[u] = pp[k0 + u].cand;
-      }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        bv += pv[u];
-        b += pb[u];
-        a += pa[u];
-        c |= pc[u];
-      }
-  }
-  bool found;
-  double best, bestp;
-  narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(gmem(xhat), gmem(sc), q, found, best, bestp, xb);
+  if (idx >= W0.plan.n_chunk_cols) return;
+  combine_col(W0, idx, threadIdx.x & (kWave - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -1114,6 +1126,70 @@ __device__ __forceinline__ void stage_short_recs(const uint64_t* v, bool wts, co
   stage_short_col<D, V>(e, xb, k0, W, cut, cpos, dcut, wc, found, best, bestp);
 }
 
+// The integer case of stage_short_col for a column whose records sit in LDS
+// slots rec[k][lane]: the records are decoded one at a time into thresholds
+// and half-weight deltas, and the breakpoint of each term is its threshold,
+// or one less where bit j of `below` is set (a row that holds after its
+// breakpoint). Two registers per term, so a short group's workgroup keeps
+// the occupancy of the other scoring kernels.
+template <int D>
+__device__ __forceinline__ void stage_short_int(const StageShortSmem& S, int lane, double xb, int k0, int W, bool cut,
+                                                bool cpos, int dcut, int32_t wc, bool& found, double& best,
+                                                double& bestp) {
+  constexpr int NR = 2 * D + 1;
+  constexpr int kNone = 127;  // threshold of an absent term: above every offset
+  int32_t beta = 0, alpha = 0;
+  int32_t dl[NR];
+  int th[NR];
+  uint32_t below = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const uint64_t r = S.rec[k][lane];
+    const bool ap = (r >> 8) & 1u;
+    const int d0 = (int)((r >> 10) & 0xFFu) - kStageClamp;
+    const int32_t w0 = (int32_t)((r >> 32) & 0xFFFFu);
+    row_terms(ap, d0, 2 * w0, w0, beta, alpha, dl[2 * k], th[2 * k]);
+    below |= (uint32_t)ap << (2 * k);
+    if ((r >> 9) & 1u) {
+      const int d1 = (int)((r >> 18) & 0xFFu) - kStageClamp;
+      const int32_t w1 = (int32_t)(r >> 48);
+      row_terms(!ap, d1, 2 * w1, w1, beta, alpha, dl[2 * k + 1], th[2 * k + 1]);
+      below |= (uint32_t)(!ap) << (2 * k + 1);
+    } else {
+      dl[2 * k + 1] = 0;
+      th[2 * k + 1] = kNone;
+    }
+  }
+  if (cut) {
+    row_terms(cpos, dcut, 2 * wc, wc, beta, alpha, dl[NR - 1], th[NR - 1]);
+    below |= (uint32_t)cpos << (NR - 1);
+  } else {
+    dl[NR - 1] = 0;
+    th[NR - 1] = kNone;
+  }
+  const int lo = -k0, hi = W - 1 - k0;
+  int32_t bv = 0;
+  int bc = 0;
+  found = false;
+  auto consider = [&](int c) {
+    if (c < lo || c > hi || c == 0) return;
+    int32_t val = beta + (c >= 1 ? alpha : 0);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) val += (c >= th[j]) ? dl[j] : 0;
+    if (!found || val > bv || (val == bv && c < bc)) {
+      found = true;
+      bv = val;
+      bc = c;
+    }
+  };
+  consider(lo);
+  consider(hi);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) consider(th[j] - (int)((below >> j) & 1u));
+  best = stage_score_of(bv);
+  bestp = xb + (double)bc;
+}
+
 template <typename Rows>
 __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bool wts, int tix, StageShortSmem& S,
                                             StageSegs& G) {
@@ -1153,42 +1229,58 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
   __syncthreads();
   if (tid >= nc) return;
   const int W = (int)(ub - l) + 1, k0 = (int)(xb - l);
-  uint64_t v[kShortMax];
+  const bool cut = st->cut_active && c != 0.0;
+  const int dcut = cut ? cutoff_offset(xb, st, c, P.eps) : 0;
+  bool found = false;
+  double best = 0.0, bestp = xb;
+  if (wts) {
+    const int32_t wc = (int32_t)st->wc;
+#define CHAP_SHORT_CASE(DD)                                                                   \
+  case DD:                                                                                    \
+    stage_short_int<DD>(S, tid, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);      \
+    break;
+    switch (D) {
+      CHAP_SHORT_CASE(0)
+      CHAP_SHORT_CASE(1)
+      CHAP_SHORT_CASE(2)
+      CHAP_SHORT_CASE(3)
+      CHAP_SHORT_CASE(4)
+      CHAP_SHORT_CASE(5)
+      CHAP_SHORT_CASE(6)
+      CHAP_SHORT_CASE(7)
+      default:
+        CHAP_SHORT_CASE(8)
+    }
+#undef CHAP_SHORT_CASE
+  } else {
+    uint64_t v[kShortMax];
 #pragma unroll
-  for (int k = 0; k < kShortMax; ++k) v[k] = (k < D) ? S.rec[k][tid] : ~0ull;
-  if (!wts) {
+    for (int k = 0; k < kShortMax; ++k) v[k] = (k < D) ? S.rec[k][tid] : ~0ull;
     // records arrive in varying order; sort them so that sums of
     // non-integral weights are formed in one order
 #pragma unroll
     for (int i = 0; i < kShortMax; ++i)
 #pragma unroll
       for (int k = 0; k + 1 < kShortMax - i; ++k) cswap_u64(v[k], v[k + 1]);
-  }
-  const bool cut = st->cut_active && c != 0.0;
-  const int dcut = cut ? cutoff_offset(xb, st, c, P.eps) : 0;
-  const double wc = (double)st->wc;
-  bool found = false;
-  double best = 0.0, bestp = xb;
-#define CHAP_SHORT_CASE(DD)                                                                                       \
-  case DD:                                                                                                        \
-    if (wts)                                                                                                      \
-      stage_short_recs<DD, int32_t>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);           \
-    else                                                                                                          \
-      stage_short_recs<DD, double>(v, wts, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);            \
+    const double wc = (double)st->wc;
+#define CHAP_SHORT_CASE(DD)                                                                                \
+  case DD:                                                                                                 \
+    stage_short_recs<DD, double>(v, false, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);     \
     break;
-  switch (D) {
-    CHAP_SHORT_CASE(0)
-    CHAP_SHORT_CASE(1)
-    CHAP_SHORT_CASE(2)
-    CHAP_SHORT_CASE(3)
-    CHAP_SHORT_CASE(4)
-    CHAP_SHORT_CASE(5)
-    CHAP_SHORT_CASE(6)
-    CHAP_SHORT_CASE(7)
-    default:
-      CHAP_SHORT_CASE(8)
-  }
+    switch (D) {
+      CHAP_SHORT_CASE(0)
+      CHAP_SHORT_CASE(1)
+      CHAP_SHORT_CASE(2)
+      CHAP_SHORT_CASE(3)
+      CHAP_SHORT_CASE(4)
+      CHAP_SHORT_CASE(5)
+      CHAP_SHORT_CASE(6)
+      CHAP_SHORT_CASE(7)
+      default:
+        CHAP_SHORT_CASE(8)
+    }
 #undef CHAP_SHORT_CASE
+  }
   write_result(gmem(C.xhat), gmem(C.s), q, found, best, bestp, xb);
 }
 
@@ -1319,7 +1411,7 @@ __device__ __forceinline__ int stage_task_of(int lb, int ntask) {
   return t < ntask ? t : -1;
 }
 
-inline int32_t stage_blocks(int32_t ntask) { return kXcds * ((ntask + kXcds - 1) / kXcds); }
+__host__ __device__ inline int32_t stage_blocks(int32_t ntask) { return kXcds * ((ntask + kXcds - 1) / kXcds); }
 
 // One workgroup per pack of narrow columns, fed by the pack's records.
 template <typename Rows>
@@ -1364,6 +1456,43 @@ __global__ __launch_bounds__(256) void k_stage_short(const WalkCtx* __restrict__
   const int t = stage_task_of(lb, C.plan.n_stage_tasks - C.plan.n_stage_packs);
   if (t < 0) return;
   stage_short<Rows>(C, rows_of<Rows>(C), stage_weights<Rows>(C), C.plan.n_stage_packs + t, sm, G);
+}
+
+// The scoring of a staged pass over the compact row copy in one launch: the
+// long-column chunks, the packs and the short groups are units of kXcds
+// workgroups of one grid, interleaved so that every CU runs latency-bound
+// gathers beside VALU-bound scoring; a role's workgroups keep their
+// XCD-aware task order. One launch on one stream, instead of three on three,
+// keeps the iteration a chain of kernels without event hops between them.
+union StageScoreSmem {
+  ChunkSmem chunk;
+  StagePackSmem<int32_t> pack;
+  StageShortSmem sh;
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(const WalkCtx* __restrict__ walks,
+                                                     const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  __shared__ StageScoreSmem sm;
+  __shared__ StageSegs G;
+  const int32_t unit = gmem(C.plan.stage_units)[lb / kXcds];
+  const int role = unit >> 28;
+  const int rb = (unit & kStageUnitMask) * kXcds + lb % kXcds;
+  if (role == 0) {
+    chunk_task<CompactRows>(C, rb, sm.chunk);
+    return;
+  }
+  const int npk = C.plan.n_stage_packs;
+  const CompactRows rs = rows_of<CompactRows>(C);
+  if (role == 1) {
+    const int t = stage_task_of(rb, npk);
+    if (t >= 0) stage_pack<CompactRows, int32_t>(C, rs, true, t, sm.pack, G);
+    return;
+  }
+  const int t = stage_task_of(rb, C.plan.n_stage_tasks - npk);
+  if (t >= 0) stage_short<CompactRows>(C, rs, true, npk + t, sm.sh, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -1829,6 +1958,7 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_STAGE: return p.n_stage_rtasks;
     case KS_STAGE_PACK: return stage_blocks(p.n_stage_packs);
     case KS_STAGE_SHORT: return stage_blocks(p.n_stage_tasks - p.n_stage_packs);
+    case KS_STAGE_SCORE: return p.n_stage_units * kXcds;
     case KS_ARGMAX: return c.argmax_blocks;
     case KS_SELECT: return 1;
     case KS_APPLY: return c.apply_blocks;
@@ -1882,9 +2012,14 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     const hipError_t le = hipGetLastError();
     if (first == hipSuccess) first = le;
   };
+  // over the compact row copy the staged scoring is one launch; the side
+  // streams then carry only the short, flip and long-sort kernels
+  const bool merged = std::is_same<Rows, CompactRows>::value && L.total[KS_STAGE_SCORE] > 0;
+  const bool fork = ps && (L.total[KS_SHORT] > 0 || L.total[KS_FLIP] > 0 || L.total[KS_LONG] > 0 ||
+                           (!merged && (L.total[KS_CHUNK] > 0 || L.total[KS_STAGE_SHORT] > 0)));
   hipStream_t s_short = stream, s_long = stream;
   hipError_t e = hipSuccess;
-  if (ps) {
+  if (fork) {
     e = hipEventRecord(ps->fork, stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->fork, 0);
     if (e != hipSuccess) return e;
@@ -1895,29 +2030,32 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     CHAP_LAUNCH(k_short<Rows>, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
   if (L.total[KS_FLIP] > 0)
     CHAP_LAUNCH(k_flip_wave<Rows>, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
-  // staged columns: the records first (alone: they are bound by HBM), then
-  // the short groups and the packs beside the long-column kernels, which are
-  // bound by L2 gathers
   const bool staged = L.total[KS_STAGE] > 0;
   if (staged)
     CHAP_LAUNCH(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
-  if (ps && staged) {
-    e = hipEventRecord(ps->mid, stream);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->mid, 0);
-    if (e != hipSuccess) return e;
-  }
-  if (L.total[KS_CHUNK] > 0) {
-    CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
-    CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+  if (merged) {
+    CHAP_LAUNCH(k_stage_score, grid(KS_STAGE_SCORE), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_SCORE], nw);
+  } else {
+    // staged columns: the records first (alone: they are bound by HBM), then
+    // the short groups and the packs beside the long-column kernels, which
+    // are bound by L2 gathers
+    if (fork && staged) {
+      e = hipEventRecord(ps->mid, stream);
+      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->mid, 0);
+      if (e != hipSuccess) return e;
+    }
+    if (L.total[KS_CHUNK] > 0) {
+      CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
+      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+    }
+    if (L.total[KS_STAGE_SHORT] > 0)
+      CHAP_LAUNCH(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_STAGE_SHORT],
+                  nw);
+    if (L.total[KS_STAGE_PACK] > 0)
+      CHAP_LAUNCH(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_PACK], nw);
   }
   if (L.total[KS_LONG] > 0)
     CHAP_LAUNCH(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
-  if (L.total[KS_STAGE_SHORT] > 0)
-    CHAP_LAUNCH(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks,
-                       L.off[KS_STAGE_SHORT], nw);
-  if (L.total[KS_STAGE_PACK] > 0)
-    CHAP_LAUNCH(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks,
-                       L.off[KS_STAGE_PACK], nw);
   if (L.total[KS_PACK] > 0)
     CHAP_LAUNCH(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
   if (L.total[KS_SORT0] > 0)
@@ -1933,7 +2071,7 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
                        L.off[KS_SORT0 + 3], nw);
   check();
   e = first;
-  if (ps) {
+  if (fork) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       e = hipEventRecord(ps->join[k], ps->side[k]);
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, ps->join[k], 0);
