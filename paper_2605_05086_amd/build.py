@@ -14,7 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchap.so")
 SOURCES = ["api.hip", "api_model.hip", "api_learned.hip", "kernels_pass.hip", "kernels_walk.hip", "kernels_mlp.hip",
            "kernels_learned.hip"]
-HEADERS = [os.path.join(CSRC, "chap_internal.h"), os.path.join(CSRC, "mlp_core.h"), os.path.join(INCLUDE, "chap.h")]
+HEADERS = [os.path.join(CSRC, h) for h in ("chap_internal.h", "mlp_core.h", "narrow_finish.h", "learned_rows.h")]
+HEADERS.append(os.path.join(INCLUDE, "chap.h"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # IEEE FP64 everywhere (no contraction, no fast-math); packed FP32 ops off.

@@ -979,8 +979,8 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
     for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
-      cap_err = launch_pass(L, s, &sg.ps);
-      if (cap_err == hipSuccess) cap_err = launch_walk_step(L, s);
+      cap_err = launch_pass(L, s, &sg.ps, true);
+      if (cap_err == hipSuccess) cap_err = launch_walk_step(L, s, true);
     }
     hipError_t end_err = hipStreamEndCapture(s, &graph);
     if (cap_err != hipSuccess) return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err));

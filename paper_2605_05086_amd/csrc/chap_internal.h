@@ -92,6 +92,7 @@ enum : uint8_t {
 
 constexpr int kShortMax = 8;       // normalised entries a single lane can score
 constexpr int kXcds = 8;           // L2 domains (XCDs) of an MI355X; chunks are cut into as many row ranges
+constexpr int kWave = 64;          // lanes of a gfx950 wavefront
 constexpr int kNarrowBins = 64;
 constexpr int32_t kStageUnitMask = 0x0FFFFFFF;    // values of a narrow integer column
 constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
@@ -385,8 +386,15 @@ struct PassStreams {
 // ---- launchers (kernels_pass.hip) -----------------------------------------
 // One exact best-shift pass over all columns of every walk of the batch;
 // with `ps`, the short-column and long-column kernels run on side streams
-// beside the pack kernel.
-hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps = nullptr);
+// beside the pack kernel. With defer_combine, a pass for which
+// pass_defers_combine(L) holds leaves the long narrow columns' partial bins
+// uncombined: the move selection that follows (launch_walk_choose with
+// combine) scores them while it scans.
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps = nullptr,
+                       bool defer_combine = false);
+inline bool pass_defers_combine(const BatchLaunch& L) {
+  return L.compact == 1 && L.total[KS_STAGE_SCORE] > 0 && L.total[KS_COMBINE] > 0;
+}
 
 // ---- launchers (kernels_walk.hip) -----------------------------------------
 // Single-walk set-up kernels.
@@ -412,8 +420,9 @@ hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, in
 // da[perm[q]] = a[q], db[perm[q]] = b[q] (internal order -> original order)
 hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
                            hipStream_t stream);
-// Move selection, application and iteration end for every walk of the batch.
-hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream);
+// Move selection, application and iteration end for every walk of the batch
+// (combine: after a pass launched with defer_combine).
+hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream, bool combine = false);
 // Final copy of an incumbent found by a walk's last iteration.
 hipError_t launch_copy_best_batch(const BatchLaunch& L, hipStream_t stream);
 
@@ -685,7 +694,7 @@ hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLa
 int blocks_for_host(int64_t work, int cap);
 // The parts of launch_walk_step: argmax + selection, application, end of
 // iteration.
-hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream);
+hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream, bool combine = false);
 hipError_t launch_walk_apply(const BatchLaunch& L, hipStream_t stream);
 hipError_t launch_walk_finish(const BatchLaunch& L, hipStream_t stream);
 

@@ -47,7 +47,6 @@ namespace {
 using namespace mlp;
 using namespace learned;
 
-constexpr int kWave = 64;
 constexpr int kBlock = 256;
 
 // Order-preserving key of a finite score; never 0.

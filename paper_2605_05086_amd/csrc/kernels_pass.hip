@@ -37,11 +37,11 @@
 #include <type_traits>
 
 #include "chap_internal.h"
+#include "narrow_finish.h"
 
 namespace chap {
 namespace {
 
-constexpr int kWave = 64;
 
 // Row accessors: the walk's RowState array, or its compact GatherRow copy.
 struct FullRows {
@@ -179,32 +179,6 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
   return v;
-}
-
-// (value desc, key asc) argmax across the wavefront; invalid lanes carry
-// value = -inf and key = INT_MAX.
-__device__ __forceinline__ void wave_argmax(double& v, int& key) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, kWave);
-    const int ok = __shfl_xor(key, o, kWave);
-    if (ov > v || (ov == v && ok < key)) {
-      v = ov;
-      key = ok;
-    }
-  }
-}
-
-template <typename Ptr>
-__device__ __forceinline__ void write_result(Ptr xhat, Ptr sc, int j, bool found, double best, double bestp,
-                                             double xb) {
-  if (found && best > 0.0) {
-    xhat[j] = bestp + 0.0;  // canonical +0.0
-    sc[j] = best;
-  } else {
-    xhat[j] = xb;
-    sc[j] = 0.0;
-  }
 }
 
 // Walk of this block and the block's index inside that walk: the largest w
@@ -449,27 +423,6 @@ __device__ __forceinline__ void narrow_entry(double xb, double r, double a, doub
     atomicAdd(&bins[k + 1], e.delta);
 }
 
-// Scan + argmax over the 64 bins of one column by one wavefront; lane b holds
-// bin b. The result is valid on every lane.
-__device__ __forceinline__ void narrow_finish(double binv, double beta, double alpha, unsigned long long cand,
-                                              double xb, double l, int W, int lane, bool& found, double& best,
-                                              double& bestp) {
-  double v = (lane < W) ? binv : 0.0;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const double y = __shfl_up(v, o, kWave);
-    if (lane >= o) v += y;
-  }
-  const double pos = l + (double)lane;
-  double val = beta + v + ((pos > xb) ? alpha : 0.0);
-  const bool ok = lane < W && ((((cand >> lane) & 1ull) != 0) || lane == 0 || lane == W - 1) && pos != xb;
-  int key = ok ? lane : INT_MAX;
-  if (!ok) val = -DBL_MAX;
-  wave_argmax(val, key);
-  found = key != INT_MAX;
-  best = val;
-  bestp = found ? l + (double)key : xb;
-}
 
 // One workgroup per pack of whole narrow columns (consecutive internal
 // columns, at most kPackCols of them, about kPackEntries entries). The 256
@@ -629,47 +582,6 @@ __device__ __forceinline__ void add_row_reg(bool ap, int d, int32_t half, int k0
 // candidate mask of the chunk go to the chunk's partial record. Chunks are
 // cut along row ranges and ordered so that consecutive workgroups (placed on
 // consecutive XCDs) gather rows from one range each.
-// Combines the partials of long narrow column idx (a ChunkCol record) in
-// slot order (a fixed summation order), then scan and argmax over the bins;
-// one wavefront.
-__device__ __forceinline__ void combine_col(const WalkCtx& W0, int idx, int lane) {
-  const DevProblem& P = W0.P;
-  const ChunkCol C = W0.plan.chunk_cols[idx];
-  const int q = C.col;
-  const double xb = gmem((const double*)W0.x)[q];
-  const double l = gmem(P.lb)[q], u = gmem(P.ub)[q];
-  const int W = (int)(u - l) + 1;
-  double bv = 0.0, b = 0.0, a = 0.0;
-  unsigned long long c = 0;
-  // kU partials loaded at a time
-  constexpr int kU = 4;
-  const gptr<const ChunkPartial> pp = gmem((const ChunkPartial*)W0.partials) + C.first;
-  for (int k0 = 0; k0 < C.nparts; k0 += kU) {
-    double pv[kU], pb[kU], pa[kU];
-    unsigned long long pc[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        pv[u] = pp[k0 + u].bins[lane];
-        pb[u] = pp[k0 + u].beta;
-        pa[u] = pp[k0 + u].alpha;
-        pc[u] = pp[k0 + u].cand;
-      }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        bv += pv[u];
-        b += pb[u];
-        a += pa[u];
-        c |= pc[u];
-      }
-  }
-  bool found;
-  double best, bestp;
-  narrow_finish(bv, b, a, c, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(gmem(W0.xhat), gmem(W0.s), q, found, best, bestp, xb);
-}
-
 struct ChunkSmem {
   double bins[kNarrowBins];
   int32_t ibins[kNarrowBins];
@@ -815,7 +727,8 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   if (W0.st->k >= W0.st->iters) return;
   const int idx = lb * 4 + (threadIdx.x >> 6);
   if (idx >= W0.plan.n_chunk_cols) return;
-  combine_col(W0, idx, threadIdx.x & (kWave - 1));
+  int q;
+  (void)combine_col(W0, idx, threadIdx.x & (kWave - 1), &q);
 }
 
 // ---------------------------------------------------------------------------
@@ -2002,7 +1915,7 @@ template <typename Rows>
     check();                  \
   } while (0)
 
-hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
+hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps, bool defer_combine) {
   const int nw = L.nw;
   auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
   // a launch error (say, an LDS size the device refuses) is kept by the first
@@ -2035,6 +1948,8 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     CHAP_LAUNCH(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
   if (merged) {
     CHAP_LAUNCH(k_stage_score, grid(KS_STAGE_SCORE), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_SCORE], nw);
+    if (L.total[KS_COMBINE] > 0 && !(defer_combine && pass_defers_combine(L)))
+      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
   } else {
     // staged columns: the records first (alone: they are bound by HBM), then
     // the short groups and the packs beside the long-column kernels, which
@@ -2082,10 +1997,10 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
 
 #undef CHAP_LAUNCH
 
-hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps) {
-  if (L.compact == 1) return launch_pass_rows<CompactRows>(L, stream, ps);
-  if (L.compact == 2) return launch_pass_rows<DualRows>(L, stream, ps);
-  return launch_pass_rows<FullRows>(L, stream, ps);
+hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps, bool defer_combine) {
+  if (L.compact == 1) return launch_pass_rows<CompactRows>(L, stream, ps, defer_combine);
+  if (L.compact == 2) return launch_pass_rows<DualRows>(L, stream, ps, false);
+  return launch_pass_rows<FullRows>(L, stream, ps, false);
 }
 
 }  // namespace chap

@@ -13,11 +13,11 @@
 
 #include "chap_internal.h"
 #include "learned_rows.h"
+#include "narrow_finish.h"
 
 namespace chap {
 namespace {
 
-constexpr int kWave = 64;
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -223,8 +223,12 @@ constexpr int kPartialStride = kArgmaxRecord;
 // lowest original index; one partial record per workgroup. The pending copy
 // of a new incumbent (flagged by the previous iteration, before this
 // iteration's move changes x) is done here too.
+//
+// With `combine` the long narrow columns' scores are not in s yet: their
+// partial bins are combined here first, one wavefront per column (which
+// writes the column's score), and the scan skips their index range.
 __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
-                                                int32_t nw) {
+                                                int32_t nw, int32_t combine) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   const gptr<const double> s = gmem((const double*)C.s);
@@ -244,6 +248,17 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
   const int gs = C.argmax_blocks * blockDim.x;
   if (copy)
     for (int q = gt; q < n; q += gs) best_x[q] = x[q];
+  const int ncc = combine ? C.plan.n_chunk_cols : 0;
+  const int cq0 = ncc > 0 ? C.plan.chunk_cols[0].col : 0;
+  for (int idx = lb * 4 + (int)(threadIdx.x >> 6); idx < ncc; idx += C.argmax_blocks * 4) {
+    int q;
+    const double v = combine_col(C, idx, threadIdx.x & 63, &q);
+    if ((threadIdx.x & 63) == 0 && v > 0.0) {
+      const int j = perm[q];
+      ba.offer(v, j, q);
+      if (k > (int64_t)tabu[q]) bn.offer(v, j, q);
+    }
+  }
   // kU columns per thread and step, every load issued before any is used
   constexpr int kU = 4;
   for (int q0 = gt; q0 < n; q0 += kU * gs) {
@@ -262,7 +277,7 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int q = q0 + u * gs;
-      if (q < n && v[u] > 0.0) {
+      if (q < n && v[u] > 0.0 && (unsigned)(q - cq0) >= (unsigned)ncc) {
         ba.offer(v[u], j[u], q);
         if (k > (int64_t)tb[u]) bn.offer(v[u], j[u], q);
       }
@@ -673,9 +688,11 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
   return hipGetLastError();
 }
 
-hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream) {
+hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream, bool combine) {
   const int nw = L.nw;
-  hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw);
+  const int32_t comb = (combine && pass_defers_combine(L)) ? 1 : 0;
+  hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw,
+                     comb);
   hipLaunchKernelGGL(k_select, dim3((unsigned)nw), dim3(256), 0, stream, L.walks);
   return hipGetLastError();
 }
@@ -690,8 +707,8 @@ hipError_t launch_walk_finish(const BatchLaunch& L, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream) {
-  hipError_t e = launch_walk_choose(L, stream);
+hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream, bool combine) {
+  hipError_t e = launch_walk_choose(L, stream, combine);
   if (e == hipSuccess) e = launch_walk_apply(L, stream);
   if (e == hipSuccess) e = launch_walk_finish(L, stream);
   return e;
