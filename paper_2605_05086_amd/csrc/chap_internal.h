@@ -301,10 +301,9 @@ struct PassPlan {
   int32_t n_stage_ent = 0;
   int32_t stage_short_begin = 0, stage_short_end = 0;
   int32_t stage_one_begin = 0, stage_one_end = 0;  // single-entry short narrow columns
-  // the scoring launch of a staged pass over the compact row copy, in units
-  // of kXcds workgroups: unit u runs role (stage_units[u] >> 28) (0 chunks,
-  // 1 packs, 2 short groups) on that role's unit (stage_units[u] &
-  // kStageUnitMask)
+  // the scoring launch of a staged pass, in units of kXcds workgroups: unit
+  // u runs role (stage_units[u] >> 28) (0 chunks, 1 packs, 2 short groups)
+  // on that role's unit (stage_units[u] & kStageUnitMask)
   const int32_t* stage_units = nullptr;
   int32_t n_stage_units = 0;
 };
@@ -345,8 +344,6 @@ enum KernelSlot {
   KS_SORT0,
   KS_LONG = KS_SORT0 + kSortCaps,
   KS_STAGE,
-  KS_STAGE_PACK,
-  KS_STAGE_SHORT,
   KS_STAGE_SCORE,
   KS_ARGMAX,
   KS_SELECT,
@@ -377,7 +374,6 @@ int32_t kernel_blocks(const WalkCtx& c, int slot);
 struct PassStreams {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork = nullptr;
-  hipEvent_t mid = nullptr;  // staged records are ready (short groups may start)
   hipEvent_t join[2] = {nullptr, nullptr};
   hipError_t create();
   void destroy();

@@ -21,6 +21,16 @@
 //   k_sort_long    general columns beyond the LDS capacity: the same steps in
 //                  global scratch memory.
 //
+// On all-integer instances with 0 < eps <= 1/2 the narrow columns are
+// row-block staged instead:
+//   k_stage_rows   one workgroup per slice of an 8192-row block held in LDS:
+//                  each staged entry becomes an 8-byte breakpoint record, and
+//                  single-entry columns are scored on the spot.
+//   k_stage_score  one launch for the rest: packs of columns (counting sort
+//                  of their records into LDS bins), groups of short columns
+//                  of one degree (one lane per column) and the chunks of long
+//                  columns, as interleaved units of the grid.
+//
 // Phase 1 of Algorithm 1 emits, per row, the accumulators beta/alpha and up to
 // two triplets. Here the two triplets of an a_ij > 0 row, (t,-1,0) and
 // (t,+1,d), are merged into one entry "d applies strictly after t, and t is a
@@ -1029,16 +1039,6 @@ __device__ __forceinline__ void stage_short_col(const StageRec* e, double xb, in
   bestp = xb + (double)bc;
 }
 
-template <int D, typename V, typename Rows>
-__device__ __forceinline__ void stage_short_recs(const uint64_t* v, bool wts, const Rows& rs, double xb, int k0,
-                                                 int W, bool cut, bool cpos, int dcut, double wc, bool& found,
-                                                 double& best, double& bestp) {
-  StageRec e[D > 0 ? D : 1];
-#pragma unroll
-  for (int k = 0; k < D; ++k) e[k] = decode_rec(v[k], wts, rs);
-  stage_short_col<D, V>(e, xb, k0, W, cut, cpos, dcut, wc, found, best, bestp);
-}
-
 // The integer case of stage_short_col for a column whose records sit in LDS
 // slots rec[k][lane]: the records are decoded one at a time into thresholds
 // and half-weight deltas, and the breakpoint of each term is its threshold,
@@ -1100,6 +1100,64 @@ __device__ __forceinline__ void stage_short_int(const StageShortSmem& S, int lan
 #pragma unroll
   for (int j = 0; j < NR; ++j) consider(th[j] - (int)((below >> j) & 1u));
   best = stage_score_of(bv);
+  bestp = xb + (double)bc;
+}
+
+// The FP64 case (weights gathered from the row states) in the same form:
+// the records are decoded one at a time from the LDS slots, which the
+// caller has sorted, so a lane holds three registers per term.
+template <int D, typename Rows>
+__device__ __forceinline__ void stage_short_dbl(const StageShortSmem& S, int lane, const Rows& rs, double xb, int k0,
+                                                int W, bool cut, bool cpos, int dcut, double wc, bool& found,
+                                                double& best, double& bestp) {
+  constexpr int NR = 2 * D + 1;
+  constexpr int kNone = 127;
+  const double zero = 0.0;
+  double beta = 0.0, alpha = 0.0;
+  double dl[NR];
+  int th[NR];
+  uint32_t below = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const StageRec e = decode_rec<Rows>(S.rec[k][lane], false, rs);
+    row_terms(e.ap != 0, e.d0, stage_one(e.w0, zero), stage_half(e.w0, zero), beta, alpha, dl[2 * k], th[2 * k]);
+    below |= (uint32_t)(e.ap != 0) << (2 * k);
+    if (e.twin) {
+      row_terms(e.ap == 0, e.d1, stage_one(e.w1, zero), stage_half(e.w1, zero), beta, alpha, dl[2 * k + 1],
+                th[2 * k + 1]);
+      below |= (uint32_t)(e.ap == 0) << (2 * k + 1);
+    } else {
+      dl[2 * k + 1] = 0.0;
+      th[2 * k + 1] = kNone;
+    }
+  }
+  if (cut) {
+    row_terms(cpos, dcut, stage_one(wc, zero), stage_half(wc, zero), beta, alpha, dl[NR - 1], th[NR - 1]);
+    below |= (uint32_t)cpos << (NR - 1);
+  } else {
+    dl[NR - 1] = 0.0;
+    th[NR - 1] = kNone;
+  }
+  const int lo = -k0, hi = W - 1 - k0;
+  double bv = 0.0;
+  int bc = 0;
+  found = false;
+  auto consider = [&](int c) {
+    if (c < lo || c > hi || c == 0) return;
+    double val = beta + (c >= 1 ? alpha : zero);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) val += (c >= th[j]) ? dl[j] : zero;
+    if (!found || val > bv || (val == bv && c < bc)) {
+      found = true;
+      bv = val;
+      bc = c;
+    }
+  };
+  consider(lo);
+  consider(hi);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) consider(th[j] - (int)((below >> j) & 1u));
+  best = bv;
   bestp = xb + (double)bc;
 }
 
@@ -1166,19 +1224,20 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
     }
 #undef CHAP_SHORT_CASE
   } else {
-    uint64_t v[kShortMax];
-#pragma unroll
-    for (int k = 0; k < kShortMax; ++k) v[k] = (k < D) ? S.rec[k][tid] : ~0ull;
-    // records arrive in varying order; sort them so that sums of
-    // non-integral weights are formed in one order
-#pragma unroll
-    for (int i = 0; i < kShortMax; ++i)
-#pragma unroll
-      for (int k = 0; k + 1 < kShortMax - i; ++k) cswap_u64(v[k], v[k + 1]);
+    // records arrive in varying order; sort each lane's slots (in LDS) so
+    // that sums of non-integral weights are formed in one order
+    for (int i = 0; i + 1 < D; ++i)
+      for (int k = 0; k + 1 < D - i; ++k) {
+        const uint64_t a = S.rec[k][tid], b = S.rec[k + 1][tid];
+        if (b < a) {
+          S.rec[k][tid] = b;
+          S.rec[k + 1][tid] = a;
+        }
+      }
     const double wc = (double)st->wc;
 #define CHAP_SHORT_CASE(DD)                                                                                \
   case DD:                                                                                                 \
-    stage_short_recs<DD, double>(v, false, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);     \
+    stage_short_dbl<DD, Rows>(S, tid, rs, xb, k0, W, cut, c > 0.0, dcut, wc, found, best, bestp);          \
     break;
     switch (D) {
       CHAP_SHORT_CASE(0)
@@ -1326,65 +1385,21 @@ __device__ __forceinline__ int stage_task_of(int lb, int ntask) {
 
 __host__ __device__ inline int32_t stage_blocks(int32_t ntask) { return kXcds * ((ntask + kXcds - 1) / kXcds); }
 
-// One workgroup per pack of narrow columns, fed by the pack's records.
-template <typename Rows>
-__global__ __launch_bounds__(256) void k_stage_pack(const WalkCtx* __restrict__ walks,
-                                                    const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (C.st->k >= C.st->iters) return;
-  __shared__ StageSegs G;
-  const int t = stage_task_of(lb, C.plan.n_stage_packs);
-  if (t < 0) return;
-  const Rows rs = rows_of<Rows>(C);
-  // LDS for the value type(s) the row accessor can need
-  if constexpr (std::is_same<Rows, CompactRows>::value) {
-    __shared__ StagePackSmem<int32_t> si;
-    stage_pack<Rows, int32_t>(C, rs, true, t, si, G);
-  } else if constexpr (std::is_same<Rows, FullRows>::value) {
-    __shared__ StagePackSmem<double> sd;
-    stage_pack<Rows, double>(C, rs, false, t, sd, G);
-  } else {
-    __shared__ union {
-      StagePackSmem<int32_t> i;
-      StagePackSmem<double> d;
-    } sm;
-    if (stage_weights<Rows>(C))
-      stage_pack<Rows, int32_t>(C, rs, true, t, sm.i, G);
-    else
-      stage_pack<Rows, double>(C, rs, false, t, sm.d, G);
-  }
-}
-
-// One workgroup per group of short narrow columns of one degree: one lane
-// per column, fed by the group's records.
-template <typename Rows>
-__global__ __launch_bounds__(256) void k_stage_short(const WalkCtx* __restrict__ walks,
-                                                     const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (C.st->k >= C.st->iters) return;
-  __shared__ StageShortSmem sm;
-  __shared__ StageSegs G;
-  const int t = stage_task_of(lb, C.plan.n_stage_tasks - C.plan.n_stage_packs);
-  if (t < 0) return;
-  stage_short<Rows>(C, rows_of<Rows>(C), stage_weights<Rows>(C), C.plan.n_stage_packs + t, sm, G);
-}
-
-// The scoring of a staged pass over the compact row copy in one launch: the
-// long-column chunks, the packs and the short groups are units of kXcds
+// The scoring of a staged pass in one launch: the long-column chunks, the packs and the short groups are units of kXcds
 // workgroups of one grid, interleaved so that every CU runs latency-bound
 // gathers beside VALU-bound scoring; a role's workgroups keep their
 // XCD-aware task order. One launch on one stream, instead of three on three,
 // keeps the iteration a chain of kernels without event hops between them.
 union StageScoreSmem {
   ChunkSmem chunk;
-  StagePackSmem<int32_t> pack;
+  StagePackSmem<int32_t> pack_i;
+  StagePackSmem<double> pack_d;
   StageShortSmem sh;
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(const WalkCtx* __restrict__ walks,
-                                                     const int32_t* __restrict__ off, int32_t nw) {
+template <typename Rows>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(
+    const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
   if (C.st->k >= C.st->iters) return;
@@ -1394,18 +1409,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int role = unit >> 28;
   const int rb = (unit & kStageUnitMask) * kXcds + lb % kXcds;
   if (role == 0) {
-    chunk_task<CompactRows>(C, rb, sm.chunk);
+    chunk_task<Rows>(C, rb, sm.chunk);
     return;
   }
   const int npk = C.plan.n_stage_packs;
-  const CompactRows rs = rows_of<CompactRows>(C);
+  const Rows rs = rows_of<Rows>(C);
+  const bool wts = stage_weights<Rows>(C);
   if (role == 1) {
     const int t = stage_task_of(rb, npk);
-    if (t >= 0) stage_pack<CompactRows, int32_t>(C, rs, true, t, sm.pack, G);
+    if (t < 0) return;
+    if (wts)
+      stage_pack<Rows, int32_t>(C, rs, true, t, sm.pack_i, G);
+    else
+      stage_pack<Rows, double>(C, rs, false, t, sm.pack_d, G);
     return;
   }
   const int t = stage_task_of(rb, C.plan.n_stage_tasks - npk);
-  if (t >= 0) stage_short<CompactRows>(C, rs, true, npk + t, sm.sh, G);
+  if (t >= 0) stage_short<Rows>(C, rs, wts, npk + t, sm.sh, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -1869,8 +1889,6 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_COMBINE: return (p.n_chunk_cols + 3) / 4;
     case KS_LONG: return p.n_long;
     case KS_STAGE: return p.n_stage_rtasks;
-    case KS_STAGE_PACK: return stage_blocks(p.n_stage_packs);
-    case KS_STAGE_SHORT: return stage_blocks(p.n_stage_tasks - p.n_stage_packs);
     case KS_STAGE_SCORE: return p.n_stage_units * kXcds;
     case KS_ARGMAX: return c.argmax_blocks;
     case KS_SELECT: return 1;
@@ -1890,8 +1908,6 @@ hipError_t PassStreams::create() {
     e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = hipEventCreateWithFlags(&mid, hipEventDisableTiming);
-  if (e != hipSuccess) return e;
   return hipEventCreateWithFlags(&fork, hipEventDisableTiming);
 }
 
@@ -1903,9 +1919,7 @@ void PassStreams::destroy() {
     join[k] = nullptr;
   }
   if (fork) (void)hipEventDestroy(fork);
-  if (mid) (void)hipEventDestroy(mid);
   fork = nullptr;
-  mid = nullptr;
 }
 
 template <typename Rows>
@@ -1925,11 +1939,10 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     const hipError_t le = hipGetLastError();
     if (first == hipSuccess) first = le;
   };
-  // over the compact row copy the staged scoring is one launch; the side
-  // streams then carry only the short, flip and long-sort kernels
-  const bool merged = std::is_same<Rows, CompactRows>::value && L.total[KS_STAGE_SCORE] > 0;
+  // the staged scoring is one launch on the main stream; the side streams
+  // carry the short, flip, chunk and long-sort kernels of unstaged columns
   const bool fork = ps && (L.total[KS_SHORT] > 0 || L.total[KS_FLIP] > 0 || L.total[KS_LONG] > 0 ||
-                           (!merged && (L.total[KS_CHUNK] > 0 || L.total[KS_STAGE_SHORT] > 0)));
+                           (L.total[KS_STAGE_SCORE] == 0 && L.total[KS_CHUNK] > 0));
   hipStream_t s_short = stream, s_long = stream;
   hipError_t e = hipSuccess;
   if (fork) {
@@ -1943,31 +1956,18 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
     CHAP_LAUNCH(k_short<Rows>, grid(KS_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_SHORT], nw);
   if (L.total[KS_FLIP] > 0)
     CHAP_LAUNCH(k_flip_wave<Rows>, grid(KS_FLIP), dim3(256), 0, s_short, L.walks, L.off[KS_FLIP], nw);
-  const bool staged = L.total[KS_STAGE] > 0;
-  if (staged)
+  // staged columns: the records (alone: they are bound by HBM), then the
+  // scoring of every staged task and long-column chunk
+  if (L.total[KS_STAGE] > 0)
     CHAP_LAUNCH(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
-  if (merged) {
-    CHAP_LAUNCH(k_stage_score, grid(KS_STAGE_SCORE), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_SCORE], nw);
+  if (L.total[KS_STAGE_SCORE] > 0) {
+    CHAP_LAUNCH(k_stage_score<Rows>, grid(KS_STAGE_SCORE), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_SCORE],
+                nw);
     if (L.total[KS_COMBINE] > 0 && !(defer_combine && pass_defers_combine(L)))
       CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
-  } else {
-    // staged columns: the records first (alone: they are bound by HBM), then
-    // the short groups and the packs beside the long-column kernels, which
-    // are bound by L2 gathers
-    if (fork && staged) {
-      e = hipEventRecord(ps->mid, stream);
-      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(ps->side[k], ps->mid, 0);
-      if (e != hipSuccess) return e;
-    }
-    if (L.total[KS_CHUNK] > 0) {
-      CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
-      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
-    }
-    if (L.total[KS_STAGE_SHORT] > 0)
-      CHAP_LAUNCH(k_stage_short<Rows>, grid(KS_STAGE_SHORT), dim3(256), 0, s_short, L.walks, L.off[KS_STAGE_SHORT],
-                  nw);
-    if (L.total[KS_STAGE_PACK] > 0)
-      CHAP_LAUNCH(k_stage_pack<Rows>, grid(KS_STAGE_PACK), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_PACK], nw);
+  } else if (L.total[KS_CHUNK] > 0) {
+    CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
+    CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
   }
   if (L.total[KS_LONG] > 0)
     CHAP_LAUNCH(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
