@@ -831,6 +831,7 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
   c.P = p->dev;
   c.plan = p->plan;
   c.argmax_blocks = blocks_for_host(n, kArgmaxBlocks);
+  c.argmax_comb = p->plan.stage ? (p->plan.n_chunk_cols + 3) / 4 : 0;
   c.apply_blocks = blocks_for_host(std::max(p->m, p->max_col_deg), 256);
   c.recompute = p->exact_incremental ? 0 : 1;
   CHAP_HIP(A.alloc(&c.x, (size_t)n));
@@ -841,7 +842,7 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
   CHAP_HIP(A.alloc(&c.rs, (size_t)p->m));
   CHAP_HIP(A.alloc(&c.st, 1));
   CHAP_HIP(A.alloc(&c.trace, (size_t)std::max<int64_t>(iters, 1)));
-  CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * c.argmax_blocks));
+  CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * (c.argmax_blocks + c.argmax_comb)));
   CHAP_HIP(A.alloc(&c.partials, (size_t)p->plan.n_partials));
   CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));

@@ -330,6 +330,10 @@ struct WalkCtx {
   int32_t* long_marker;
   uint64_t* stage_rec;  // records of the staged entries (row-block staging)
   int32_t argmax_blocks;
+  // further move-selection workgroups, one wavefront per long narrow column:
+  // they combine those columns' partial bins when the pass leaves that to
+  // the move selection, else they only write empty records
+  int32_t argmax_comb;
   int32_t apply_blocks;
   int32_t recompute;
 };

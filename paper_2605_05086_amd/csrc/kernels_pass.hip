@@ -1890,7 +1890,7 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_LONG: return p.n_long;
     case KS_STAGE: return p.n_stage_rtasks;
     case KS_STAGE_SCORE: return p.n_stage_units * kXcds;
-    case KS_ARGMAX: return c.argmax_blocks;
+    case KS_ARGMAX: return c.argmax_blocks + c.argmax_comb;
     case KS_SELECT: return 1;
     case KS_APPLY: return c.apply_blocks;
     case KS_FINISH: return 1;

@@ -224,9 +224,10 @@ constexpr int kPartialStride = kArgmaxRecord;
 // of a new incumbent (flagged by the previous iteration, before this
 // iteration's move changes x) is done here too.
 //
-// With `combine` the long narrow columns' scores are not in s yet: their
-// partial bins are combined here first, one wavefront per column (which
-// writes the column's score), and the scan skips their index range.
+// With `combine` the long narrow columns' scores are not in s yet: the
+// workgroups past argmax_blocks combine their partial bins, one wavefront
+// per column (which writes the column's score), beside the scan, which
+// skips their index range.
 __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                 int32_t nw, int32_t combine) {
   int lb;
@@ -246,40 +247,44 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
   Best ba, bn;
   const int gt = lb * blockDim.x + threadIdx.x;
   const int gs = C.argmax_blocks * blockDim.x;
-  if (copy)
-    for (int q = gt; q < n; q += gs) best_x[q] = x[q];
   const int ncc = combine ? C.plan.n_chunk_cols : 0;
   const int cq0 = ncc > 0 ? C.plan.chunk_cols[0].col : 0;
-  for (int idx = lb * 4 + (int)(threadIdx.x >> 6); idx < ncc; idx += C.argmax_blocks * 4) {
-    int q;
-    const double v = combine_col(C, idx, threadIdx.x & 63, &q);
-    if ((threadIdx.x & 63) == 0 && v > 0.0) {
-      const int j = perm[q];
-      ba.offer(v, j, q);
-      if (k > (int64_t)tabu[q]) bn.offer(v, j, q);
-    }
-  }
-  // kU columns per thread and step, every load issued before any is used
-  constexpr int kU = 4;
-  for (int q0 = gt; q0 < n; q0 += kU * gs) {
-    double v[kU];
-    int j[kU], tb[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int q = q0 + u * gs;
-      v[u] = 0.0;
-      if (q < n) {
-        v[u] = s[q];
-        j[u] = perm[q];
-        tb[u] = tabu[q];
+  if (lb >= C.argmax_blocks) {
+    const int idx = (lb - C.argmax_blocks) * 4 + (int)(threadIdx.x >> 6);
+    if (idx < ncc) {
+      int q;
+      const double v = combine_col(C, idx, threadIdx.x & 63, &q);
+      if ((threadIdx.x & 63) == 0 && v > 0.0) {
+        const int j = perm[q];
+        ba.offer(v, j, q);
+        if (k > (int64_t)tabu[q]) bn.offer(v, j, q);
       }
     }
+  } else {
+    if (copy)
+      for (int q = gt; q < n; q += gs) best_x[q] = x[q];
+    // kU columns per thread and step, every load issued before any is used
+    constexpr int kU = 4;
+    for (int q0 = gt; q0 < n; q0 += kU * gs) {
+      double v[kU];
+      int j[kU], tb[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int q = q0 + u * gs;
-      if (q < n && v[u] > 0.0 && (unsigned)(q - cq0) >= (unsigned)ncc) {
-        ba.offer(v[u], j[u], q);
-        if (k > (int64_t)tb[u]) bn.offer(v[u], j[u], q);
+      for (int u = 0; u < kU; ++u) {
+        const int q = q0 + u * gs;
+        v[u] = 0.0;
+        if (q < n) {
+          v[u] = s[q];
+          j[u] = perm[q];
+          tb[u] = tabu[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int q = q0 + u * gs;
+        if (q < n && v[u] > 0.0 && (unsigned)(q - cq0) >= (unsigned)ncc) {
+          ba.offer(v[u], j[u], q);
+          if (k > (int64_t)tb[u]) bn.offer(v[u], j[u], q);
+        }
       }
     }
   }
@@ -422,7 +427,7 @@ __device__ int decide(const WalkCtx& C, const Best& ba, const Best& bn, int none
 __global__ __launch_bounds__(256) void k_select(const WalkCtx* __restrict__ walks) {
   const WalkCtx& C = walks[blockIdx.x];
   const double* partial = C.argmax_partial;
-  const int32_t nparts = C.argmax_blocks;
+  const int32_t nparts = C.argmax_blocks + C.argmax_comb;
   if (C.st->k >= C.st->iters) return;
   Best ba, bn;
   const gptr<const double> pg = gmem(partial);
@@ -596,7 +601,7 @@ __global__ __launch_bounds__(256) void k_copy_best_batch(const WalkCtx* __restri
                                                          const int32_t* __restrict__ off, int32_t nw) {
   int lb;
   const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (!C.st->copy_best) return;
+  if (!C.st->copy_best || lb >= C.argmax_blocks) return;
   const int gs = C.argmax_blocks * blockDim.x;
   for (int q = lb * blockDim.x + threadIdx.x; q < C.P.n; q += gs) C.best_x[q] = C.x[q];
 }
