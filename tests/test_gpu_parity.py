@@ -441,6 +441,29 @@ def test_tabu_row_stage_long_columns(chap):
     assert g.trace.tobytes() == h.trace.tobytes()
 
 
+def test_batch_row_stage_long_columns(chap):
+    """Batched staged walks where some instances have long columns (their
+    partial bins are combined by the move selection's extra workgroups) and
+    one has none: every walk equals its plain walk bit for bit, and one
+    equals the oracle."""
+    mips = [mipgen.powerlaw(77, n=12_000, m=10_000, nnz=120_000, cap=6_000),
+            mipgen.powerlaw(78, n=6_000, m=8_000, nnz=40_000, cap=10),
+            mipgen.powerlaw(79, n=9_000, m=5_000, nnz=90_000, cap=4_000)]
+    probs = [chap.Problem(m, chunk_min=24) for m in mips]
+    walk_prob = [0, 1, 2, 0, 2, 1]
+    walk_seed = [3, 4, 5, 6, 7, 8]
+    say("batch of 6 staged walks on 3 instances, 50 iterations")
+    runs = chap.batch_run(probs, walk_prob, walk_seed, 50, 5)
+    for w, r in enumerate(runs):
+        say(f"plain staged walk {w}")
+        g = probs[walk_prob[w]].tabu_run(50, 5, walk_seed[w])
+        assert r.trace.tobytes() == g.trace.tobytes(), f"walk {w} trace"
+        assert r.x.tobytes() == g.x.tobytes() and r.w.tobytes() == g.w.tobytes()
+    say("oracle walk 4")
+    o = oracle.OracleProblem(mips[2]).tabu_run(50, 5, walk_seed[4])
+    compare_runs(runs[4], o, "batch staged walk 4")
+
+
 def test_tabu_row_stage_full_rows(chap):
     """A walk of 65540 iterations keeps full rows (weights may pass 65534), so
     the staged records carry row indices instead of weights; the walk equals
