@@ -511,6 +511,19 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     }
     for (int32_t rb = 0; rb < nrb; ++rb) sseg[T * nrb + rb] = (int32_t)ent_rb[rb].size();
     std::vector<std::vector<StageRowTask>> per_xcd(kXcds);
+    // slices per row block: at most one per kStageSlice entries, and at most
+    // the block's share of the workgroups the device holds at once, so that
+    // the record kernel runs in one round instead of a full round and a thin
+    // second one
+    int64_t staged = 0, resident = 0;
+    {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+      for (const auto& v : ent_rb) staged += (int64_t)v.size();
+      resident = (int64_t)kStageRowsPerCu * cus;
+    }
     int32_t qone = L.stage_one_begin;
     for (int32_t rb = 0; rb < nrb; ++rb) {
       const int32_t e0 = (int32_t)sent.size();
@@ -520,8 +533,9 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
       const int32_t c0 = qone;
       while (qone < L.stage_one_end && crow[cptr[qone]] < (rb + 1) * kStageRowBlock) ++qone;
       const int32_t c1 = qone;
-      const int32_t ns = std::max((e1 - e0 + kStageSlice - 1) / kStageSlice,
-                                  (c1 - c0 + kStageSliceCols - 1) / kStageSliceCols);
+      const int32_t by_e = (e1 - e0 + kStageSlice - 1) / kStageSlice;
+      const int32_t share = (int32_t)std::max<int64_t>(1, resident * (e1 - e0) / std::max<int64_t>(staged, 1));
+      const int32_t ns = std::max(std::min(by_e, share), (c1 - c0 + kStageSliceCols - 1) / kStageSliceCols);
       if (ns == 0) continue;
       const int32_t se = (e1 - e0 + ns - 1) / ns, sc = (c1 - c0 + ns - 1) / ns;
       for (int32_t k = 0; k < ns; ++k) {

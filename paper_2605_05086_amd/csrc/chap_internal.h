@@ -225,7 +225,8 @@ struct __align__(16) ChunkPartial {
 // plus 64 (clamped to [-64, 64]); bits 32..63 the weights w0 | w1 << 16 when
 // the walk keeps compact rows, else the stored row.
 constexpr int kStageRowBlock = 8192;  // stored rows per block (64 KB of LDS)
-constexpr int kStageSlice = 16384;    // staged entries per workgroup of k_stage_rows
+constexpr int kStageSlice = 16384;    // staged entries per workgroup of k_stage_rows (fewest)
+constexpr int kStageRowsPerCu = 2;    // k_stage_rows workgroups resident per CU (64 KB of LDS each)
 constexpr int kStageShort = 256;      // short narrow columns per scoring task
 constexpr int kStageClamp = 64;       // offsets beyond +-64 leave every narrow column
 constexpr int kStageMaxRb = 256;      // row blocks a scoring workgroup can index in LDS
