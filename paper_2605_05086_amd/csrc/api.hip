@@ -568,21 +568,22 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     for (size_t k = 0; k < rounds; ++k)
       for (int x = 0; x < kXcds; ++x)
         srtasks.push_back(k < per_xcd[x].size() ? per_xcd[x][k] : StageRowTask{-1, 0, 0, 0, 0, {0, 0, 0}});
-    // units of the single scoring launch: chunk, pack and short-group units
-    // interleaved in proportion to their counts, so that the latency-bound
-    // chunk gathers and the VALU-bound scoring share every CU
+    // units of the single scoring launch: chunk and pack units interleaved
+    // in proportion to their counts, so that the latency-bound chunk gathers
+    // and the VALU-bound pack scoring share every CU, then the short-group
+    // units, the shortest workgroups, which fill the grid's last round
     {
       const int32_t cnt[3] = {(int32_t)tasks.size() / kXcds, (npk + kXcds - 1) / kXcds,
                               ((int32_t)T - npk + kXcds - 1) / kXcds};
-      int32_t done[3] = {0, 0, 0};
-      for (int32_t u = 0; u < cnt[0] + cnt[1] + cnt[2]; ++u) {
-        int best = -1;
-        for (int r = 0; r < 3; ++r)
-          if (done[r] < cnt[r] &&
-              (best < 0 || (2.0 * done[r] + 1.0) * cnt[best] < (2.0 * done[best] + 1.0) * cnt[r]))
-            best = r;
-        sunits.push_back((best << 28) | done[best]++);
+      int32_t done[2] = {0, 0};
+      for (int32_t u = 0; u < cnt[0] + cnt[1]; ++u) {
+        const int r = (done[0] < cnt[0] && (done[1] >= cnt[1] || (2.0 * done[0] + 1.0) * cnt[1] <=
+                                                                     (2.0 * done[1] + 1.0) * cnt[0]))
+                          ? 0
+                          : 1;
+        sunits.push_back((r << 28) | done[r]++);
       }
+      for (int32_t u = 0; u < cnt[2]; ++u) sunits.push_back((2 << 28) | u);
     }
     L.n_stage_ent = (int32_t)sent.size();
     L.n_stage_tasks = (int32_t)T;
