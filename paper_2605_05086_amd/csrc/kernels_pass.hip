@@ -115,6 +115,12 @@ __device__ __forceinline__ bool stage_weights<FullRows>(const WalkCtx&) {
   return false;
 }
 
+// Whether the rows are read from the walk's compact copy (whose words then
+// have the staged LDS row format, weights included).
+__device__ __forceinline__ bool compact_source(const CompactRows&) { return true; }
+__device__ __forceinline__ bool compact_source(const DualRows& r) { return r.use_g != 0; }
+__device__ __forceinline__ bool compact_source(const FullRows&) { return false; }
+
 __device__ __forceinline__ double breakpoint(double xb, double r, double a, double eps, bool is_int) {
   double t = xb + (eps - r) / a;
   if (is_int) t = (a > 0.0) ? floor(t) : ceil(t);
@@ -1290,19 +1296,31 @@ __global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ 
   load_step(T.e_beg + tid);
   {
     constexpr int kPer = kStageRowBlock / kThreads;
-    RowState g[kPer];
+    if (compact_source(rs)) {
+      // the compact copy already has the LDS format (weights included)
+      const gptr<const GatherRow> src = gmem((const GatherRow*)C.grow);
+      GatherRow g[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (tid + k * kThreads < nr) g[k] = rs[r0 + tid + k * kThreads];
+      for (int k = 0; k < kPer; ++k)
+        if (tid + k * kThreads < nr) g[k] = gload(src, r0 + tid + k * kThreads);
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (tid + k * kThreads < nr) {
-        GatherRow o;
-        o.r = (int32_t)g[k].r;
-        o.w0 = wts ? (uint16_t)g[k].w0 : (uint16_t)0;
-        o.w1 = g[k].w1 >= 0.0f ? (wts ? (uint16_t)g[k].w1 : (uint16_t)0) : kNoTwin;
-        rows[tid + k * kThreads] = o;
-      }
+      for (int k = 0; k < kPer; ++k)
+        if (tid + k * kThreads < nr) rows[tid + k * kThreads] = g[k];
+    } else {
+      RowState g[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        if (tid + k * kThreads < nr) g[k] = rs[r0 + tid + k * kThreads];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        if (tid + k * kThreads < nr) {
+          GatherRow o;
+          o.r = (int32_t)g[k].r;
+          o.w0 = wts ? (uint16_t)g[k].w0 : (uint16_t)0;
+          o.w1 = g[k].w1 >= 0.0f ? (wts ? (uint16_t)g[k].w1 : (uint16_t)0) : kNoTwin;
+          rows[tid + k * kThreads] = o;
+        }
+    }
   }
   __syncthreads();
   for (int base = T.e_beg + tid; base < T.e_end; base += kU * kThreads) {
