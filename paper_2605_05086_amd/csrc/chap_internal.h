@@ -232,7 +232,7 @@ constexpr int kStageClamp = 64;       // offsets beyond +-64 leave every narrow 
 constexpr int kStageMaxRb = 256;      // row blocks a scoring workgroup can index in LDS
 constexpr int kStageSliceCols = 4096; // single-entry columns per workgroup of k_stage_rows
 constexpr int kStagePackCols = 64;    // columns per staged pack (one lane each in the final scan)
-constexpr int kStagePackEntries = 2048;  // target stored entries per staged pack
+constexpr int kStagePackEntries = 3072;  // target stored entries per staged pack
 
 // A slice [e_beg, e_end) of the staged entries of row block rb, and a range
 // [c_beg, c_end) of the short narrow columns whose one stored entry lies in
