@@ -97,7 +97,7 @@ constexpr int kNarrowBins = 64;
 constexpr int32_t kStageUnitMask = 0x0FFFFFFF;    // values of a narrow integer column
 constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
-constexpr int kArgmaxBlocks = 1024;  // workgroups of the move-selection reduction
+constexpr int kArgmaxBlocks = 512;  // workgroups of the move-selection reduction
 constexpr int kArgmaxRecord = 8;     // doubles per workgroup record of that reduction
 
 // Residual and weights of one stored row. A stored row is a normalised row;
