@@ -150,11 +150,15 @@ def default_options() -> ChapOptions:
 
 
 class Run:
-    """Result of chap_tabu_run: trace and final state (host arrays)."""
+    """Result of a walk: the trace, the best objective and cutoff, and the
+    final state (x, resid, w, best_x: host arrays, read from the library on
+    first access)."""
 
     def __init__(self, handle, n: int, mp: int):
         lib = load_library()
         self._h = handle
+        self._n, self._mp = n, mp
+        self._state = None
         rec = ctypes.c_void_p()
         cnt = ctypes.c_int64()
         _check(lib.chap_run_trace(handle, ctypes.byref(rec), ctypes.byref(cnt)))
@@ -163,18 +167,11 @@ class Run:
             self.trace = np.frombuffer(bytes(buf), dtype=TRACE_DTYPE).copy()
         else:
             self.trace = np.zeros(0, dtype=TRACE_DTYPE)
-        self.x = np.empty(n)
-        self.resid = np.empty(mp + 1)
-        self.w = np.empty(mp + 1, dtype=np.float32)
-        self.best_x = np.full(n, np.nan)
         best_obj = ctypes.c_double()
         cut = ctypes.c_double()
-        _check(lib.chap_run_state(handle, _ptr(self.x), _ptr(self.resid), _ptr(self.w), ctypes.byref(best_obj),
-                                  _ptr(self.best_x), ctypes.byref(cut)))
+        _check(lib.chap_run_state(handle, None, None, None, ctypes.byref(best_obj), None, ctypes.byref(cut)))
         self.best_obj = best_obj.value
         self.cutoff_rhs = cut.value
-        if math.isinf(self.best_obj):
-            self.best_x = None
         self.elapsed_ms = lib.chap_run_elapsed_ms(handle)
         ev, hi, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.chap_run_learned_stats(handle, ctypes.byref(ev), ctypes.byref(hi), ctypes.byref(st)))
@@ -196,6 +193,32 @@ class Run:
             self.pair_feat = np.ctypeslib.as_array(
                 (ctypes.c_uint16 * (cnt.value * 16)).from_address(pf.value)).copy().reshape(cnt.value, 16)
             self.pair_target = np.ctypeslib.as_array((ctypes.c_float * cnt.value).from_address(pt.value)).copy()
+
+    def _load_state(self):
+        if self._state is None:
+            x = np.empty(self._n)
+            resid = np.empty(self._mp + 1)
+            w = np.empty(self._mp + 1, dtype=np.float32)
+            best_x = np.full(self._n, np.nan)
+            _check(load_library().chap_run_state(self._h, _ptr(x), _ptr(resid), _ptr(w), None, _ptr(best_x), None))
+            self._state = (x, resid, w, None if math.isinf(self.best_obj) else best_x)
+        return self._state
+
+    @property
+    def x(self):
+        return self._load_state()[0]
+
+    @property
+    def resid(self):
+        return self._load_state()[1]
+
+    @property
+    def w(self):
+        return self._load_state()[2]
+
+    @property
+    def best_x(self):
+        return self._load_state()[3]
 
     def proposal_set(self, k: int):
         """Original column indices proposed at iteration k (empty for a full

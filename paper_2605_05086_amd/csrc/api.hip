@@ -745,6 +745,13 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(P->bs_streams.create());
   CHAP_HIP(hipEventCreate(&P->pass_ev[0]));
   CHAP_HIP(hipEventCreate(&P->pass_ev[1]));
+  P->pool = std::make_shared<WalkPool>();
+  P->pool->n = n;
+  P->pool->m = m;
+  P->pool->mp = P->mp;
+  P->pool->perm = P->perm;
+  P->pool->nidx = P->nidx;
+  P->pool->pair = P->pair;
   CHAP_HIP(hipDeviceSynchronize());
   *out = P.release();
   return CHAP_OK;
@@ -758,8 +765,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   if (std::isnan(cutoff_rhs)) return fail(CHAP_EINVAL, "chap_best_shift: cutoff_rhs is NaN");
   hipStream_t s = (hipStream_t)hip_stream;
   CHAP_HIP(launch_gather(p->dev.perm, d_x, p->bs_x, p->n, s));
-  CHAP_HIP(launch_residual(p->dev, p->bs_x, p->bs_rs, s));
-  CHAP_HIP(launch_scatter_weights(p->d_nidx, p->d_pair, d_w, p->bs_rs, p->m, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_rs, s));
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
                              p->obj_integral, cut, d_w + p->mp, 0, s));
@@ -806,42 +812,10 @@ int chap_best_shift_pass_ms(chap_problem* p, double* ms) {
 
 }  // extern "C"
 
-namespace {
-
-void start_point(const chap_problem* p, uint64_t seed, double* x) {
-  for (int32_t j = 0; j < p->n; ++j) {
-    const double l = p->lb[j], u = p->ub[j];
-    if (seed != 0 && p->is_int[j] && std::isfinite(l) && std::isfinite(u)) {
-      const uint64_t h = splitmix64(seed, (uint64_t)j);
-      const uint64_t width = (uint64_t)(u - l) + 1;
-      x[j] = l + (double)(h % width);
-    } else {
-      double v = 0.0;
-      if (v < l) v = l;
-      if (v > u) v = u;
-      x[j] = v;
-    }
-  }
-}
-
-}  // namespace
-
 namespace chap {
 
-int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
-                 uint32_t* ticket, hipStream_t s, int compact) {
-  const chap_problem* p = spec.p;
+int alloc_walk(const chap_problem* p, int64_t trace_cap, DeviceArena& A, WalkCtx& c) {
   const int32_t n = p->n;
-  std::vector<double> xs(n), xq(n);
-  if (spec.x0) {
-    for (int32_t j = 0; j < n; ++j) {
-      if (!std::isfinite(spec.x0[j])) return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
-      xs[j] = spec.x0[j];
-    }
-  } else {
-    start_point(p, spec.seed, xs.data());
-  }
-  for (int32_t q = 0; q < n; ++q) xq[q] = xs[p->perm[q]];
   c = WalkCtx{};
   c.P = p->dev;
   c.plan = p->plan;
@@ -856,32 +830,93 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
   CHAP_HIP(A.alloc(&c.tabu, (size_t)n));
   CHAP_HIP(A.alloc(&c.rs, (size_t)p->m));
   CHAP_HIP(A.alloc(&c.st, 1));
-  CHAP_HIP(A.alloc(&c.trace, (size_t)std::max<int64_t>(iters, 1)));
+  if (trace_cap > 0) CHAP_HIP(A.alloc(&c.trace, (size_t)trace_cap));
   CHAP_HIP(A.alloc(&c.argmax_partial, (size_t)kArgmaxRecord * (c.argmax_blocks + c.argmax_comb)));
   CHAP_HIP(A.alloc(&c.partials, (size_t)p->plan.n_partials));
   CHAP_HIP(A.alloc(&c.long_pos, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.long_delta, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.stage_rec, (size_t)p->plan.n_stage_ent));
+  if (p->compact_ok) CHAP_HIP(A.alloc(&c.grow, (size_t)p->m));
+  return CHAP_OK;
+}
+
+int init_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, const WalkCtx& c, double* partial,
+              uint32_t* ticket, hipStream_t s) {
+  const chap_problem* p = spec.p;
+  const int32_t n = p->n;
+  if (spec.x0) {
+    for (int32_t j = 0; j < n; ++j)
+      if (!std::isfinite(spec.x0[j])) return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
+    // caller's order into xhat (free until the first pass), then internal order
+    if (n > 0) {
+      CHAP_HIP(hipStreamSynchronize(s));
+      CHAP_HIP(hipMemcpy(c.xhat, spec.x0, sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
+      CHAP_HIP(launch_gather(p->dev.perm, c.xhat, c.x, n, s));
+    }
+  } else {
+    CHAP_HIP(launch_start_point(p->dev, spec.seed, c.x, s));
+  }
   CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
   if (n > 0) {
-    CHAP_HIP(hipMemcpyAsync(c.x, xq.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)n);
     CHAP_HIP(hipGetLastError());
   }
-  CHAP_HIP(launch_residual(p->dev, c.x, c.rs, s));
-  CHAP_HIP(launch_set_weights_unit(p->d_pair, c.rs, p->m, s));
+  CHAP_HIP(launch_residual_unit(p->dev, p->d_pair, c.x, c.rs, c.grow, s));
   CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
                              nullptr, 1, s));
   CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
-  if (compact) {
-    CHAP_HIP(A.alloc(&c.grow, (size_t)p->m));
-    CHAP_HIP(launch_fill_compact(c.rs, c.grow, p->m, s));
-  }
-  // the host copy of xq must outlive the asynchronous upload
+  return CHAP_OK;
+}
+
+int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
+                 uint32_t* ticket, hipStream_t s, int compact) {
+  int rc = alloc_walk(spec.p, std::max<int64_t>(iters, 1), A, c);
+  if (rc != CHAP_OK) return rc;
+  if (!compact) c.grow = nullptr;
+  rc = init_walk(spec, iters, tenure, c, partial, ticket, s);
+  if (rc != CHAP_OK) return rc;
   CHAP_HIP(hipStreamSynchronize(s));
   return CHAP_OK;
 }
+
+namespace {
+
+// Final state in the caller's order: x and best_x from internal order,
+// residuals and weights of the normalised rows (an equality row's twin has
+// residual -r and the second weight), the cutoff row last.
+void fill_state(int32_t n, int32_t m, int32_t mp, const int32_t* perm, const int32_t* nidx, const uint8_t* pair,
+                const double* xin, const double* bxin, const RowState* rs, const WalkState& st, chap_run* R) {
+  R->x.resize(n);
+  std::vector<double> bx(n);
+  for (int32_t q = 0; q < n; ++q) {
+    R->x[perm[q]] = xin[q];
+    bx[perm[q]] = bxin[q];
+  }
+  R->resid.assign((size_t)mp + 1, 0.0);
+  R->w.assign((size_t)mp + 1, 0.0f);
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t k = nidx[i];
+    R->resid[k] = rs[i].r;
+    R->w[k] = rs[i].w0;
+    if (pair[i]) {
+      R->resid[k + 1] = -rs[i].r;
+      R->w[k + 1] = rs[i].w1;
+    }
+  }
+  R->resid[mp] = st.cut_active ? st.rc : 0.0;
+  R->w[mp] = st.wc;
+  if (R->has_best) R->best_x.swap(bx);
+}
+
+void fill_summary(const WalkState& st, chap_run* R) {
+  R->st_end = st;
+  R->has_best = st.has_best != 0;
+  R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
+  R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
+}
+
+}  // namespace
 
 int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double ms, chap_run* R) {
   const int32_t n = p->n, m = p->m;
@@ -894,33 +929,33 @@ int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double 
     CHAP_HIP(hipMemcpy(xin.data(), c.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
     CHAP_HIP(hipMemcpy(bxin.data(), c.best_x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
   }
-  R->x.resize(n);
-  std::vector<double> bx(n);
-  for (int32_t q = 0; q < n; ++q) {
-    R->x[p->perm[q]] = xin[q];
-    bx[p->perm[q]] = bxin[q];
-  }
   std::vector<RowState> rs(m);
   if (m > 0) CHAP_HIP(hipMemcpy(rs.data(), c.rs, sizeof(RowState) * (size_t)m, hipMemcpyDeviceToHost));
   WalkState st;
   CHAP_HIP(hipMemcpy(&st, c.st, sizeof(WalkState), hipMemcpyDeviceToHost));
-  R->resid.assign((size_t)p->mp + 1, 0.0);
-  R->w.assign((size_t)p->mp + 1, 0.0f);
-  for (int32_t i = 0; i < m; ++i) {
-    const int32_t k = p->nidx[i];
-    R->resid[k] = rs[i].r;
-    R->w[k] = rs[i].w0;
-    if (p->pair[i]) {
-      R->resid[k + 1] = -rs[i].r;
-      R->w[k + 1] = rs[i].w1;
-    }
+  fill_summary(st, R);
+  fill_state(n, m, p->mp, p->perm.data(), p->nidx.data(), p->pair.data(), xin.data(), bxin.data(), rs.data(), st, R);
+  return CHAP_OK;
+}
+
+// Reads a single walk's final state from its slot (first chap_run_state
+// that asks for it), then returns the slot to the problem.
+int materialize(const chap_run* R) {
+  if (R->state_ready) return CHAP_OK;
+  const WalkPool& M = *R->pool;
+  const WalkCtx& c = R->slot->ctx;
+  std::vector<double> xin(M.n), bxin(M.n);
+  std::vector<RowState> rs(M.m);
+  if (M.n > 0) {
+    CHAP_HIP(hipMemcpy(xin.data(), c.x, sizeof(double) * (size_t)M.n, hipMemcpyDeviceToHost));
+    CHAP_HIP(hipMemcpy(bxin.data(), c.best_x, sizeof(double) * (size_t)M.n, hipMemcpyDeviceToHost));
   }
-  R->resid[p->mp] = st.cut_active ? st.rc : 0.0;
-  R->w[p->mp] = st.wc;
-  R->has_best = st.has_best != 0;
-  R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
-  R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
-  if (R->has_best) R->best_x = bx;
+  if (M.m > 0) CHAP_HIP(hipMemcpy(rs.data(), c.rs, sizeof(RowState) * (size_t)M.m, hipMemcpyDeviceToHost));
+  chap_run* W = const_cast<chap_run*>(R);
+  fill_state(M.n, M.m, M.mp, M.perm.data(), M.nidx.data(), M.pair.data(), xin.data(), bxin.data(), rs.data(),
+             R->st_end, W);
+  R->state_ready = true;
+  R->pool->give_back(R->slot);
   return CHAP_OK;
 }
 
@@ -1032,6 +1067,135 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   return CHAP_OK;
 }
 
+// Buffers, launch table and streams of a new walk slot for problem p.
+int slot_setup(const chap_problem* p, WalkSlot& S) {
+  int rc = alloc_walk(p, 0, S.A, S.ctx);
+  if (rc != CHAP_OK) return rc;
+  S.grow_buf = S.ctx.grow;
+  S.ctx.grow = nullptr;
+  CHAP_HIP(S.A.alloc(&S.partial, 2 * 1024));
+  CHAP_HIP(S.A.alloc(&S.ticket, 1));
+  CHAP_HIP(hipMemset(S.ticket, 0, sizeof(uint32_t)));
+  CHAP_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+  CHAP_HIP(S.ps.create());
+  for (hipEvent_t& e : S.ev) CHAP_HIP(hipEventCreate(&e));
+  CHAP_HIP(build_launch(S.A, std::vector<WalkCtx>{S.ctx}, &S.L));
+  return CHAP_OK;
+}
+
+// The graph of K iterations for the slot's walk (captured on first use).
+int slot_graph(WalkSlot& S, int64_t K, int compact, hipGraphExec_t* out) {
+  for (const WalkSlot::Graph& g : S.graphs)
+    if (g.K == K && g.compact == compact) {
+      *out = g.x;
+      return CHAP_OK;
+    }
+  hipGraph_t graph = nullptr;
+  CHAP_HIP(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
+  hipError_t cap_err = hipSuccess;
+  for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
+    cap_err = launch_pass(S.L, S.s, &S.ps, true);
+    if (cap_err == hipSuccess) cap_err = launch_walk_step(S.L, S.s, true);
+  }
+  const hipError_t end_err = hipStreamEndCapture(S.s, &graph);
+  if (cap_err != hipSuccess || end_err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(CHAP_EHIP, std::string("graph capture: ") + hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(CHAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  }
+  S.graphs.push_back(WalkSlot::Graph{K, compact, graph, exec});
+  *out = exec;
+  return CHAP_OK;
+}
+
+// One walk on the problem's cached slot. The iterations run as graphs of
+// graph_iters iterations and, for the rest, of decreasing powers of two, so
+// a slot holds a handful of graphs whatever `iters` is and no iteration is
+// launched beyond `iters`. The final point, residuals and weights stay on the
+// device until the caller asks for them.
+int run_single(chap_problem* p, uint64_t seed, const double* x0, int64_t iters, int32_t tenure, hipStream_t user,
+               std::unique_ptr<chap_run>& out) {
+  if (iters < 0 || tenure < 0 || iters + (int64_t)tenure >= (int64_t)INT32_MAX)
+    return fail(CHAP_EINVAL, "iters and tenure must be >= 0 with iters + tenure < 2^31");
+  const WalkSpec spec{p, seed, x0};
+  const int compact = compact_walks({spec}, iters);
+  std::unique_ptr<WalkSlot> slot;
+  if (!p->pool->idle.empty()) {
+    slot = std::move(p->pool->idle.back());
+    p->pool->idle.pop_back();
+  } else {
+    slot.reset(new WalkSlot());
+    const int rc = slot_setup(p, *slot);
+    if (rc != CHAP_OK) return rc;
+  }
+  WalkSlot& S = *slot;
+  // trace capacity and compact rows of this run, in the device record
+  bool dirty = false;
+  if (iters > S.trace_cap) {
+    if (S.trace_buf) CHAP_HIP(hipFree(S.trace_buf));
+    S.trace_buf = nullptr;
+    S.trace_cap = 0;
+    CHAP_HIP(hipMalloc(&S.trace_buf, sizeof(chap_trace_record) * (size_t)iters));
+    S.trace_cap = iters;
+    S.ctx.trace = S.trace_buf;
+    dirty = true;
+  }
+  GatherRow* g = compact ? S.grow_buf : nullptr;
+  if (g != S.ctx.grow) {
+    S.ctx.grow = g;
+    dirty = true;
+  }
+  if (dirty) CHAP_HIP(hipMemcpy((void*)S.L.walks, &S.ctx, sizeof(WalkCtx), hipMemcpyHostToDevice));
+  S.L.compact = compact;
+  std::vector<hipGraphExec_t> launches;
+  {
+    const int64_t G = std::max<int32_t>(1, p->opt.graph_iters);
+    for (int64_t left = iters; left > 0;) {
+      int64_t K = G;
+      if (left < G) {
+        K = 1;
+        while (2 * K <= left) K *= 2;
+      }
+      hipGraphExec_t x;
+      const int rc = slot_graph(S, K, compact, &x);
+      if (rc != CHAP_OK) return rc;
+      launches.push_back(x);
+      left -= K;
+    }
+  }
+  CHAP_HIP(hipEventRecord(S.ev[0], user));
+  CHAP_HIP(hipStreamWaitEvent(S.s, S.ev[0], 0));
+  int rc = init_walk(spec, iters, tenure, S.ctx, S.partial, S.ticket, S.s);
+  if (rc != CHAP_OK) return rc;
+  std::unique_ptr<chap_run> R(new chap_run());
+  R->trace.resize((size_t)iters);
+  WalkState st;
+  CHAP_HIP(hipEventRecord(S.ev[1], S.s));
+  for (hipGraphExec_t x : launches) CHAP_HIP(hipGraphLaunch(x, S.s));
+  CHAP_HIP(hipEventRecord(S.ev[2], S.s));
+  // an incumbent found by the last iteration is copied here
+  CHAP_HIP(launch_copy_best_batch(S.L, S.s));
+  if (iters > 0)
+    CHAP_HIP(hipMemcpyAsync(R->trace.data(), S.trace_buf, sizeof(chap_trace_record) * (size_t)iters,
+                            hipMemcpyDeviceToHost, S.s));
+  CHAP_HIP(hipMemcpyAsync(&st, S.ctx.st, sizeof(WalkState), hipMemcpyDeviceToHost, S.s));
+  CHAP_HIP(hipStreamSynchronize(S.s));
+  float ms = 0.0f;
+  CHAP_HIP(hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
+  R->elapsed_ms = ms;
+  fill_summary(st, R.get());
+  R->state_ready = false;
+  R->pool = p->pool;
+  R->slot = std::move(slot);
+  out = std::move(R);
+  return CHAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1039,10 +1203,10 @@ extern "C" {
 int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed, const double* x0, chap_run** out,
                   void* hip_stream) {
   if (!p || !out) return fail(CHAP_EINVAL, "chap_tabu_run: null argument");
-  std::vector<std::unique_ptr<chap_run>> runs;
-  const int rc = run_walks({WalkSpec{p, seed, x0}}, iters, tenure, (hipStream_t)hip_stream, runs);
+  std::unique_ptr<chap_run> run;
+  const int rc = run_single(p, seed, x0, iters, tenure, (hipStream_t)hip_stream, run);
   if (rc != CHAP_OK) return rc;
-  *out = runs[0].release();
+  *out = run.release();
   return CHAP_OK;
 }
 
@@ -1123,6 +1287,10 @@ int chap_run_trace(const chap_run* r, const chap_trace_record** records, int64_t
 int chap_run_state(const chap_run* r, double* x, double* resid, float* w, double* best_obj, double* best_x,
                    double* cutoff_rhs) {
   if (!r) return fail(CHAP_EINVAL, "chap_run_state: null run");
+  if (x || resid || w || best_x) {
+    const int rc = materialize(r);
+    if (rc != CHAP_OK) return rc;
+  }
   if (x) std::copy(r->x.begin(), r->x.end(), x);
   if (resid) std::copy(r->resid.begin(), r->resid.end(), resid);
   if (w) std::copy(r->w.begin(), r->w.end(), w);

@@ -338,8 +338,7 @@ int chap_features(chap_problem* p, const double* d_x, const float* d_w, double c
   CHAP_HIP(launch_gather(p->dev.perm, d_x, c.x, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_s_last, c.s, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_xhat_last, c.xhat, n, s));
-  CHAP_HIP(launch_residual(p->dev, c.x, c.rs, s));
-  CHAP_HIP(launch_scatter_weights(p->d_nidx, p->d_pair, d_w, c.rs, p->m, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, c.x, c.rs, s));
   CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, 1, 0, p->obj_integral, cutoff_rhs,
                              d_w + p->mp, 0, s));
   chap_learned_options o;

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -393,16 +395,25 @@ struct PassStreams {
 // combine) scores them while it scans.
 hipError_t launch_pass(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps = nullptr,
                        bool defer_combine = false);
+// Only when every walk with long narrow columns is staged (no k_narrow_chunk
+// blocks): the move selection's extra workgroups exist for staged walks only.
 inline bool pass_defers_combine(const BatchLaunch& L) {
-  return L.compact == 1 && L.total[KS_STAGE_SCORE] > 0 && L.total[KS_COMBINE] > 0;
+  return L.compact == 1 && L.total[KS_STAGE_SCORE] > 0 && L.total[KS_COMBINE] > 0 && L.total[KS_CHUNK] == 0;
 }
 
 // ---- launchers (kernels_walk.hip) -----------------------------------------
 // Single-walk set-up kernels.
+// Residuals from scratch (weights left as they are).
 hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream);
-hipError_t launch_set_weights_unit(const uint8_t* pair, RowState* rs, int32_t ms, hipStream_t stream);
-hipError_t launch_scatter_weights(const int32_t* nidx, const uint8_t* pair, const float* w_norm, RowState* rs,
-                                  int32_t ms, hipStream_t stream);
+// Residuals from scratch with unit weights, and the compact copy when grow
+// is not null.
+hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, RowState* rs,
+                                GatherRow* grow, hipStream_t stream);
+// Residuals from scratch with the caller's normalised weights w_norm.
+hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair,
+                                   const float* w_norm, const double* x, RowState* rs, hipStream_t stream);
+// Seeded start point (internal order).
+hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hipStream_t stream);
 // Initialise a walk state; computes f = c^T x, V, and the cutoff from
 // cutoff_rhs (active iff finite) or the incumbent rule when check_incumbent.
 hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
@@ -577,6 +588,10 @@ hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t
 
 }  // namespace chap
 
+namespace chap {
+struct WalkPool;
+}  // namespace chap
+
 // Handles of the C ABI (defined here so every source file of the library
 // sees them).
 struct chap_problem {
@@ -639,6 +654,8 @@ struct chap_problem {
   hipStream_t bs_cap = nullptr;
   hipGraph_t bs_graph = nullptr;
   hipGraphExec_t bs_exec = nullptr;
+  // buffers of single walks kept between chap_tabu_run calls
+  std::shared_ptr<chap::WalkPool> pool;
   ~chap_problem() {
     for (hipEvent_t e : pass_ev)
       if (e) (void)hipEventDestroy(e);
@@ -649,6 +666,63 @@ struct chap_problem {
   }
 };
 
+namespace chap {
+
+// Device buffers, launch table, streams and captured iteration graphs of one
+// single walk. A problem keeps one idle slot between runs, so repeated
+// chap_tabu_run calls allocate, upload and capture nothing: a call is the
+// set-up kernels, the graph launches and the trace copy.
+struct WalkSlot {
+  DeviceArena A;
+  WalkCtx ctx{};  // host copy of the device record L.walks[0]
+  BatchLaunch L{};
+  GatherRow* grow_buf = nullptr;  // compact rows (all-integer instances), used when a run allows them
+  chap_trace_record* trace_buf = nullptr;
+  int64_t trace_cap = 0;
+  double* partial = nullptr;
+  uint32_t* ticket = nullptr;
+  hipStream_t s = nullptr;
+  PassStreams ps;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // caller's stream, graph start, graph end
+  struct Graph {
+    int64_t K;
+    int compact;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<Graph> graphs;  // K iterations each (K a power of two or graph_iters)
+  WalkSlot() = default;
+  WalkSlot(const WalkSlot&) = delete;
+  WalkSlot& operator=(const WalkSlot&) = delete;
+  ~WalkSlot() {
+    for (Graph& g : graphs) {
+      (void)hipGraphExecDestroy(g.x);
+      (void)hipGraphDestroy(g.g);
+    }
+    if (trace_buf) (void)hipFree(trace_buf);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    ps.destroy();
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+// Host maps a run needs to return its state in the caller's order, and the
+// problem's idle walk slot. Shared by the problem and its runs, so a run may
+// outlive its problem.
+struct WalkPool {
+  int32_t n = 0, m = 0, mp = 0;
+  std::vector<int32_t> perm, nidx;
+  std::vector<uint8_t> pair;
+  std::vector<std::unique_ptr<WalkSlot>> idle;
+  void give_back(std::unique_ptr<WalkSlot>& slot) {
+    if (slot && idle.empty()) idle.push_back(std::move(slot));
+    slot.reset();
+  }
+};
+
+}  // namespace chap
+
 struct chap_run {
   std::vector<chap_trace_record> trace;
   std::vector<double> x, resid, best_x;
@@ -657,6 +731,16 @@ struct chap_run {
   double cutoff_rhs = HUGE_VAL;
   bool has_best = false;
   double elapsed_ms = 0.0;
+  // single walks: x, resid, w and best_x are read from the walk's device
+  // buffers on the first chap_run_state that asks for them; the buffers then
+  // go back to the problem
+  mutable std::shared_ptr<chap::WalkPool> pool;
+  mutable std::unique_ptr<chap::WalkSlot> slot;
+  chap::WalkState st_end{};
+  mutable bool state_ready = true;
+  ~chap_run() {
+    if (pool) pool->give_back(slot);
+  }
   // learned walks
   int64_t evals = 0, hits = 0, stalls = 0;
   std::vector<int32_t> sets;     // proposal sets (original indices)
@@ -682,8 +766,15 @@ struct WalkSpec {
   const double* x0;
 };
 
-// Allocates one walk's buffers in A, uploads its start point and runs the
-// set-up kernels on stream s (residual, unit weights, state, incumbent).
+// Allocates one walk's buffers in A (a trace of trace_cap records when
+// trace_cap > 0; the compact row copy when the problem allows it).
+int alloc_walk(const chap_problem* p, int64_t trace_cap, DeviceArena& A, WalkCtx& c);
+// Start point (seeded on the device, or the caller's x0) and the set-up
+// kernels of a walk on stream s: tabu list, residuals with unit weights (and
+// c.grow when set), state, incumbent check.
+int init_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, const WalkCtx& c, double* partial,
+              uint32_t* ticket, hipStream_t s);
+// alloc_walk + init_walk (the compact copy only when `compact`).
 int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceArena& A, WalkCtx& c, double* partial,
                  uint32_t* ticket, hipStream_t s, int compact);
 // 1 when every walk of a run may keep the compact GatherRow copy.

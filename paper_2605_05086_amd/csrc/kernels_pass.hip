@@ -1903,7 +1903,7 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_SHORT: return (p.short_seg[kShortMax + 2] - p.short_seg[0] + 255) / 256;
     case KS_FLIP: return (p.flip_end - p.flip_begin + 3) / 4;
     case KS_PACK: return p.n_packs;
-    case KS_CHUNK: return p.n_chunks;
+    case KS_CHUNK: return p.stage ? 0 : p.n_chunks;  // a staged pass scores its chunks in k_stage_score
     case KS_COMBINE: return (p.n_chunk_cols + 3) / 4;
     case KS_LONG: return p.n_long;
     case KS_STAGE: return p.n_stage_rtasks;
@@ -1960,7 +1960,7 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   // the staged scoring is one launch on the main stream; the side streams
   // carry the short, flip, chunk and long-sort kernels of unstaged columns
   const bool fork = ps && (L.total[KS_SHORT] > 0 || L.total[KS_FLIP] > 0 || L.total[KS_LONG] > 0 ||
-                           (L.total[KS_STAGE_SCORE] == 0 && L.total[KS_CHUNK] > 0));
+                           L.total[KS_CHUNK] > 0);
   hipStream_t s_short = stream, s_long = stream;
   hipError_t e = hipSuccess;
   if (fork) {
@@ -1978,14 +1978,23 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   // scoring of every staged task and long-column chunk
   if (L.total[KS_STAGE] > 0)
     CHAP_LAUNCH(k_stage_rows<Rows>, grid(KS_STAGE), dim3(512), 0, stream, L.walks, L.off[KS_STAGE], nw);
-  if (L.total[KS_STAGE_SCORE] > 0) {
+  // long narrow columns: the chunks of staged walks are roles of
+  // k_stage_score, those of unstaged walks k_narrow_chunk workgroups; a batch
+  // may hold both, and k_narrow_combine then waits for both (after the join)
+  bool combine_after_join = false;
+  const bool combine = L.total[KS_COMBINE] > 0 && !(defer_combine && pass_defers_combine(L));
+  if (L.total[KS_STAGE_SCORE] > 0)
     CHAP_LAUNCH(k_stage_score<Rows>, grid(KS_STAGE_SCORE), dim3(256), 0, stream, L.walks, L.off[KS_STAGE_SCORE],
                 nw);
-    if (L.total[KS_COMBINE] > 0 && !(defer_combine && pass_defers_combine(L)))
-      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
-  } else if (L.total[KS_CHUNK] > 0) {
+  if (L.total[KS_CHUNK] > 0)
     CHAP_LAUNCH(k_narrow_chunk<Rows>, grid(KS_CHUNK), dim3(256), 0, s_long, L.walks, L.off[KS_CHUNK], nw);
-    CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+  if (combine) {
+    if (L.total[KS_CHUNK] == 0)
+      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
+    else if (L.total[KS_STAGE_SCORE] == 0)
+      CHAP_LAUNCH(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, s_long, L.walks, L.off[KS_COMBINE], nw);
+    else
+      combine_after_join = true;
   }
   if (L.total[KS_LONG] > 0)
     CHAP_LAUNCH(k_sort_long<Rows>, grid(KS_LONG), dim3(1024), 0, s_long, L.walks, L.off[KS_LONG], nw);
@@ -2009,6 +2018,10 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
       e = hipEventRecord(ps->join[k], ps->side[k]);
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, ps->join[k], 0);
     }
+  }
+  if (e == hipSuccess && combine_after_join) {
+    hipLaunchKernelGGL(k_narrow_combine, grid(KS_COMBINE), dim3(256), 0, stream, L.walks, L.off[KS_COMBINE], nw);
+    e = hipGetLastError();
   }
   return e;
 }

@@ -92,36 +92,85 @@ __device__ void incumbent_check(WalkState* st, double eps) {
   st->V = (st->rc > eps) ? 1 : 0;
 }
 
+// Residual from scratch of every stored row, r_i = sum_k a_ik x_k - b_i,
+// with the row's products summed one after another in the row's stored
+// order (the order of the caller's CSR, as the definition is written). A
+// group of kResidualLanes lanes owns a row: the lanes load consecutive
+// entries and form their products side by side (coalesced row reads), and
+// every lane of the group then adds the products in entry order from its
+// neighbours' registers, so the sum is the sequential one bit for bit.
+// Weights: kWeightsKeep leaves them, kWeightsUnit sets every weight to 1,
+// kWeightsScatter copies the caller's normalised weights. With grow, the
+// compact row copy is written too (unit weights, all-integer instances).
+constexpr int kResidualLanes = 8;
+enum { kWeightsKeep = 0, kWeightsUnit = 1, kWeightsScatter = 2 };
+
+template <int kWeights>
 __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __restrict__ x,
-                                                  RowState* __restrict__ rs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.ms) return;
-  double acc = 0.0;
+                                                  RowState* __restrict__ rs, const int32_t* __restrict__ nidx,
+                                                  const uint8_t* __restrict__ pair, const float* __restrict__ w,
+                                                  GatherRow* __restrict__ grow) {
+  const int g = threadIdx.x & (kResidualLanes - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kResidualLanes;
+  if (i >= P.ms) return;  // whole groups leave together
+  const gptr<const double> val = gmem(P.row_val);
+  const gptr<const int32_t> col = gmem(P.row_col);
+  const gptr<const double> xg = gmem(x);
   const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
-  for (int e = beg; e < end; ++e) {
-    const double prod = P.row_val[e] * x[P.row_col[e]];
-    acc = acc + prod;
+  double acc = 0.0;
+  for (int e0 = beg; e0 < end; e0 += kResidualLanes) {
+    const int e = e0 + g;
+    double prod = 0.0;
+    if (e < end) prod = val[e] * xg[col[e]];
+    const int cnt = min(kResidualLanes, end - e0);
+    for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod, t, kResidualLanes);
   }
-  rs[i].r = acc - P.row_rhs[i];
+  if (g != 0) return;
+  const double r = acc - P.row_rhs[i];
+  if constexpr (kWeights == kWeightsKeep) {
+    rs[i].r = r;
+  } else {
+    RowState q;
+    q.r = r;
+    if constexpr (kWeights == kWeightsUnit) {
+      const bool tw = pair[i] != 0;
+      q.w0 = 1.0f;
+      q.w1 = tw ? 1.0f : -1.0f;
+      if (grow) {
+        GatherRow c;
+        c.r = (int32_t)r;
+        c.w0 = 1;
+        c.w1 = tw ? (uint16_t)1 : kNoTwin;
+        grow[i] = c;
+      }
+    } else {
+      const int k = nidx[i];
+      q.w0 = w[k];
+      q.w1 = pair[i] ? w[k + 1] : -1.0f;
+    }
+    rs[i] = q;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_weights_unit(const uint8_t* __restrict__ pair, RowState* __restrict__ rs,
-                                                      int32_t ms) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ms) return;
-  rs[i].w0 = 1.0f;
-  rs[i].w1 = pair[i] ? 1.0f : -1.0f;
-}
-
-__global__ __launch_bounds__(256) void k_weights_scatter(const int32_t* __restrict__ nidx,
-                                                         const uint8_t* __restrict__ pair,
-                                                         const float* __restrict__ w, RowState* __restrict__ rs,
-                                                         int32_t ms) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ms) return;
-  const int k = nidx[i];
-  rs[i].w0 = w[k];
-  rs[i].w1 = pair[i] ? w[k + 1] : -1.0f;
+// Start point of a seeded walk (internal order): with seed > 0 an integer
+// variable with finite bounds starts at l + (h mod (u - l + 1)), h the
+// (j+1)-th SplitMix64 output of the seed for original index j; every other
+// variable starts at 0 clamped into its bounds.
+__global__ __launch_bounds__(256) void k_start_point(DevProblem P, uint64_t seed, double* __restrict__ x) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  const double l = P.lb[q], u = P.ub[q];
+  double v;
+  if (seed != 0 && P.is_int[q] && isfinite(l) && isfinite(u)) {
+    const uint64_t h = splitmix64(seed, (uint64_t)P.perm[q]);
+    const uint64_t width = (uint64_t)(u - l) + 1;
+    v = l + (double)(h % width);
+  } else {
+    v = 0.0;
+    if (v < l) v = l;
+    if (v > u) v = u;
+  }
+  x[q] = v;
 }
 
 // f = c^T x and V = violated rows, as fixed-order (deterministic) grid
@@ -664,21 +713,39 @@ inline int blocks_for(int64_t work, int cap) {
 
 }  // namespace
 
+namespace {
+
+inline dim3 residual_grid(int32_t ms) {
+  return dim3((unsigned)(((int64_t)ms * kResidualLanes + 255) / 256));
+}
+
+}  // namespace
+
 hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream) {
-  if (P.ms > 0) hipLaunchKernelGGL(k_residual, dim3((P.ms + 255) / 256), dim3(256), 0, stream, P, x, rs);
+  if (P.ms > 0)
+    hipLaunchKernelGGL(k_residual<kWeightsKeep>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nullptr,
+                       nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_set_weights_unit(const uint8_t* pair, RowState* rs, int32_t ms, hipStream_t stream) {
-  if (ms > 0) hipLaunchKernelGGL(k_weights_unit, dim3((ms + 255) / 256), dim3(256), 0, stream, pair, rs, ms);
+hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, RowState* rs,
+                                GatherRow* grow, hipStream_t stream) {
+  if (P.ms > 0)
+    hipLaunchKernelGGL(k_residual<kWeightsUnit>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nullptr, pair,
+                       nullptr, grow);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_weights(const int32_t* nidx, const uint8_t* pair, const float* w_norm, RowState* rs,
-                                  int32_t ms, hipStream_t stream) {
-  if (ms > 0)
-    hipLaunchKernelGGL(k_weights_scatter, dim3((ms + 255) / 256), dim3(256), 0, stream, nidx, pair, w_norm, rs,
-                       ms);
+hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair, const float* w,
+                                   const double* x, RowState* rs, hipStream_t stream) {
+  if (P.ms > 0)
+    hipLaunchKernelGGL(k_residual<kWeightsScatter>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nidx, pair,
+                       w, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hipStream_t stream) {
+  if (P.n > 0) hipLaunchKernelGGL(k_start_point, dim3((P.n + 255) / 256), dim3(256), 0, stream, P, seed, x);
   return hipGetLastError();
 }
 

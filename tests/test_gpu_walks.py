@@ -1,0 +1,100 @@
+"""GPU walks on cached buffers and mixed batches, through the C ABI.
+
+chap_tabu_run keeps one walk's device buffers and captured iteration graphs
+with its problem between calls and reads the final state back only when it
+is asked for. These tests run many walks of different lengths, seeds and
+start points on one problem, with earlier runs kept alive or released, and
+compare each with the oracle bit for bit. A batch mixing staged walks
+(all-integer, row-block records) and unstaged walks (row_stage=-1, or
+continuous variables) with long narrow columns must equal the plain walks.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import mipgen
+import oracle
+from test_gpu_parity import chap, compare_runs, say  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def test_repeated_runs_on_one_problem(chap):
+    mip = mipgen.random_mixed(81, n=300, m=200, max_row_nnz=8, frac_bin=0.3, frac_int=0.7, int_width=30,
+                              long_cols=4, long_deg=80)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip, graph_iters=16, chunk_min=24, chunk_len=16)
+    kept = []
+    for k, (iters, seed) in enumerate([(0, 0), (1, 3), (5, 0), (37, 2), (16, 1), (100, 4), (3, 5), (70, 2)]):
+        say(f"cached slot run {k}: iters={iters} seed={seed}")
+        g = G.tabu_run(iters, 7, seed)
+        o = P.tabu_run(iters, 7, seed)
+        if k % 2:
+            kept.append((g, o, iters, seed))   # state read later, after other runs used the problem
+        else:
+            compare_runs(g, o, f"run {k}")
+    x0 = mipgen.random_point(mip, 9)
+    say("cached slot run with x0")
+    compare_runs(G.tabu_run(45, 5, 0, x0=x0), P.tabu_run(45, 5, 0, x0=x0), "x0")
+    for g, o, iters, seed in kept:
+        say(f"deferred state of run iters={iters} seed={seed}")
+        compare_runs(g, o, f"kept run iters={iters} seed={seed}")
+
+
+def test_run_outlives_problem(chap):
+    mip = mipgen.powerlaw(82, n=6000, m=3000, nnz=60_000, cap=2000)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    say("run outliving its problem")
+    g = G.tabu_run(50, 10, 1)
+    del G
+    import gc
+    gc.collect()
+    compare_runs(g, P.tabu_run(50, 10, 1), "after problem release")
+
+
+def test_compact_rows_toggle_on_one_slot(chap):
+    """A walk of 65540 iterations cannot keep compact rows; short walks before
+    and after it on the same problem do. All equal the oracle."""
+    mip = mipgen.random_mixed(74, n=40, m=30, max_row_nnz=6, frac_bin=0.3, frac_int=0.7)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    say("short walk (compact rows)")
+    compare_runs(G.tabu_run(200, 3, 1), P.tabu_run(200, 3, 1), "before")
+    say("65540-iteration walk on the same slot (full rows)")
+    compare_runs(G.tabu_run(65540, 3, 1), P.tabu_run(65540, 3, 1), "long")
+    say("short walk again (compact rows)")
+    compare_runs(G.tabu_run(300, 3, 2), P.tabu_run(300, 3, 2), "after")
+
+
+def test_mixed_batch_staged_and_unstaged(chap):
+    """Staged walks (long columns scored by k_stage_score, combined in the move
+    selection when alone) batched with unstaged walks whose long narrow
+    columns go through k_narrow_chunk: every walk equals its plain walk, and
+    walks of each kind equal the oracle."""
+    base = mipgen.powerlaw(83, n=9000, m=6000, nnz=90_000, cap=4000)
+    cont = mipgen.general(84, n=6000, m=3000)
+    probs = [chap.Problem(base, chunk_min=24), chap.Problem(base, chunk_min=24, row_stage=-1),
+             chap.Problem(cont, chunk_min=24)]
+    walk_prob = [0, 1, 2, 0, 1, 2]
+    walk_seed = [3, 3, 4, 5, 6, 7]
+    say("mixed batch: staged + unstaged + continuous, 60 iterations")
+    runs = chap.batch_run(probs, walk_prob, walk_seed, 60, 5)
+    for w, r in enumerate(runs):
+        say(f"plain walk {w} (problem {walk_prob[w]})")
+        g = probs[walk_prob[w]].tabu_run(60, 5, walk_seed[w])
+        assert r.trace.tobytes() == g.trace.tobytes(), f"walk {w} trace"
+        assert r.x.tobytes() == g.x.tobytes() and r.w.tobytes() == g.w.tobytes()
+        assert r.resid.tobytes() == g.resid.tobytes()
+    assert runs[0].trace.tobytes() == runs[1].trace.tobytes()
+    for w in (0, 4):
+        say(f"oracle walk {w}")
+        o = oracle.OracleProblem(base).tabu_run(60, 5, walk_seed[w])
+        compare_runs(runs[w], o, f"mixed batch walk {w}")
+    # the same mixture with only staged walks and unstaged walks of integer data
+    say("mixed batch: staged + unstaged only")
+    runs2 = chap.batch_run(probs[:2], [0, 1, 1, 0], [9, 9, 10, 10], 40, 5)
+    assert runs2[0].trace.tobytes() == runs2[1].trace.tobytes()
+    assert runs2[2].trace.tobytes() == runs2[3].trace.tobytes()
+    compare_runs(runs2[2], oracle.OracleProblem(base).tabu_run(40, 5, 10), "staged+unstaged walk 2")
