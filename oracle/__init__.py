@@ -56,6 +56,10 @@ def _load():
     lib.orc_start_point.argtypes = [P, u64, P]
     lib.orc_splitmix64.restype = u64
     lib.orc_splitmix64.argtypes = [u64, u64]
+    lib.orc_exact_sum.restype = f64
+    lib.orc_exact_sum.argtypes = [P, i64]
+    lib.orc_objective.restype = f64
+    lib.orc_objective.argtypes = [P, P]
     lib.orc_tabu_run.restype = i64
     lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P]
     lib.orc_learned_replay.restype = i64
@@ -70,6 +74,12 @@ def _p(a: np.ndarray):
 
 def splitmix64(seed: int, index: int) -> int:
     return int(_load().orc_splitmix64(seed, index))
+
+
+def exact_sum(values) -> float:
+    """The oracle's exactly rounded sum of a list of doubles."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    return float(_load().orc_exact_sum(_p(v), v.shape[0]))
 
 
 class OracleProblem:
@@ -135,6 +145,10 @@ class OracleProblem:
             self._lib.orc_best_shift(self.h, _p(x), _p(w), float(cutoff_rhs), _p(cols), cols.shape[0],
                                      _p(xh), _p(s))
         return xh, s
+
+    def objective(self, x) -> float:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return float(self._lib.orc_objective(self.h, _p(x)))
 
     def start_point(self, seed: int):
         x = np.empty(self.n)

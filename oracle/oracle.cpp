@@ -195,6 +195,66 @@ void best_shift_one(const OracleProblem& P, int32_t j, const double* x, const st
 }
 
 // r = A'x - b' over the normalised rows, in CSR order; cutoff row c^T x - bc.
+// Exactly rounded sum of a list of doubles. Each term is merged into a list
+// of nonoverlapping partials with error-free additions (Shewchuk, "Adaptive
+// Precision Floating-Point Arithmetic and Fast Robust Geometric Predicates",
+// 1997); the partials are then added from the largest down until an addition
+// is inexact, and a tie at half an ulp is settled by the sign of the next
+// partial (the method of Python's math.fsum). The result is the exact sum
+// rounded once to nearest, ties to even; an exact zero gives +0.
+double exact_sum(const std::vector<double>& terms) {
+  std::vector<double> part;  // nonoverlapping, increasing magnitude
+  for (double v : terms) {
+    double x = v;
+    size_t keep = 0;
+    for (size_t q = 0; q < part.size(); ++q) {
+      double y = part[q];
+      if (std::fabs(x) < std::fabs(y)) std::swap(x, y);
+      const double hi = x + y;
+      const double lo = y - (hi - x);
+      if (lo != 0.0) part[keep++] = lo;
+      x = hi;
+    }
+    part.resize(keep);
+    part.push_back(x);
+  }
+  if (part.empty()) return 0.0;
+  size_t k = part.size() - 1;
+  double hi = part[k];
+  double lo = 0.0;
+  while (k > 0) {
+    const double x = hi;
+    const double y = part[--k];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  if (k > 0 && ((lo < 0.0 && part[k - 1] < 0.0) || (lo > 0.0 && part[k - 1] > 0.0))) {
+    const double y = lo * 2.0;
+    const double x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi == 0.0 ? 0.0 : hi;
+}
+
+// The terms of c^T x: for every nonzero c_j the product c_j x_j as the pair
+// (p, e) with p the rounded product and e = fma(c_j, x_j, -p) its rounding
+// error, so that p + e equals c_j x_j exactly (unless the product underflows).
+std::vector<double> objective_terms(const OracleProblem& P, const double* x) {
+  std::vector<double> t;
+  for (int32_t j = 0; j < P.n; ++j) {
+    if (P.obj[j] == 0.0) continue;
+    const double p = P.obj[j] * x[j];
+    t.push_back(p);
+    t.push_back(std::fma(P.obj[j], x[j], -p));
+  }
+  return t;
+}
+
+// The objective row is one sum over every variable; its FP64 value depends
+// on the summation order unless it is rounded once. Reading: the objective
+// f = c^T x and the cutoff residual c^T x - b_c are the exact values rounded
+// once to nearest (section 3.2 does not fix an order).
 void residual_from_scratch(const OracleProblem& P, const double* x, bool cutoff_active, double bc,
                            std::vector<double>& r) {
   r.assign((size_t)P.mp + 1, 0.0);
@@ -207,13 +267,9 @@ void residual_from_scratch(const OracleProblem& P, const double* x, bool cutoff_
     r[i] = acc - P.rb[i];
   }
   if (cutoff_active) {
-    double acc = 0.0;
-    for (int32_t j = 0; j < P.n; ++j) {
-      if (P.obj[j] == 0.0) continue;
-      double prod = P.obj[j] * x[j];
-      acc = acc + prod;
-    }
-    r[P.mp] = acc - bc;
+    std::vector<double> t = objective_terms(P, x);
+    t.push_back(-bc);
+    r[P.mp] = exact_sum(t);
   }
 }
 
@@ -224,15 +280,7 @@ int64_t count_violated(const OracleProblem& P, const std::vector<double>& r, boo
   return v;
 }
 
-double objective(const OracleProblem& P, const double* x) {
-  double acc = 0.0;
-  for (int32_t j = 0; j < P.n; ++j) {
-    if (P.obj[j] == 0.0) continue;
-    double prod = P.obj[j] * x[j];
-    acc = acc + prod;
-  }
-  return acc;
-}
+double objective(const OracleProblem& P, const double* x) { return exact_sum(objective_terms(P, x)); }
 
 uint64_t splitmix64_output(uint64_t seed, uint64_t index) {
   // The (index+1)-th output of SplitMix64 (Steele, Lea & Flood 2014) started
@@ -392,6 +440,12 @@ void orc_best_shift(void* h, const double* x, const float* w, double cutoff_rhs,
       best_shift_one(*P, cols[q], x, r, w, active, &xhat[q], &s[q]);
   }
 }
+
+// Exactly rounded sum of n doubles (the summation used for the objective).
+double orc_exact_sum(const double* v, int64_t n) { return exact_sum(std::vector<double>(v, v + n)); }
+
+// c^T x rounded once.
+double orc_objective(void* h, const double* x) { return objective(*(OracleProblem*)h, x); }
 
 void orc_start_point(void* h, uint64_t seed, double* x) { start_point(*(OracleProblem*)h, seed, x); }
 

@@ -174,6 +174,16 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     P->is_int[j] = is_int[j];
     if (obj[j] != 0.0 && (!is_int[j] || std::floor(obj[j]) != obj[j])) P->obj_integral = 0;
   }
+  {
+    double mag = 0.0;
+    bool fast = P->obj_integral != 0;
+    for (int32_t j = 0; j < n && fast; ++j) {
+      if (obj[j] == 0.0) continue;
+      fast = std::isfinite(P->lb[j]) && std::isfinite(P->ub[j]);
+      mag += std::fabs(obj[j]) * std::max(std::fabs(P->lb[j]), std::fabs(P->ub[j]));
+    }
+    P->obj_fast = (fast && mag < 4503599627370496.0) ? 1 : 0;  // 2^52
+  }
   // ---- CSR and CSC must be the same matrix (stored zeros dropped) --------
   // transpose of the CSR, rows ascending within each column
   std::vector<int64_t> tptr((size_t)n + 1, 0);
@@ -717,7 +727,8 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(A.alloc(&P->bs_s, (size_t)n));
   CHAP_HIP(A.alloc(&P->bs_rs, (size_t)m));
   CHAP_HIP(A.alloc(&P->bs_state, 1));
-  CHAP_HIP(A.alloc(&P->bs_partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&P->bs_partial, kInitPartial));
+  if (!P->obj_fast) CHAP_HIP(A.alloc(&P->bs_objacc, kExactLimbs));
   CHAP_HIP(A.alloc(&P->bs_ticket, 1));
   CHAP_HIP(hipMemset(P->bs_ticket, 0, sizeof(uint32_t)));
   {
@@ -767,8 +778,8 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(launch_gather(p->dev.perm, d_x, p->bs_x, p->n, s));
   CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_rs, s));
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
-  CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, 1, 0,
-                             p->obj_integral, cut, d_w + p->mp, 0, s));
+  CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, p->bs_objacc, 1,
+                             0, p->obj_integral, cut, d_w + p->mp, 0, s));
   if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
   if (p->n > 0 && !p->bs_exec) {
     // capture the pass once (its arguments are the problem's own buffers)
@@ -838,6 +849,7 @@ int alloc_walk(const chap_problem* p, int64_t trace_cap, DeviceArena& A, WalkCtx
   CHAP_HIP(A.alloc(&c.long_marker, (size_t)p->plan.long_scratch));
   CHAP_HIP(A.alloc(&c.stage_rec, (size_t)p->plan.n_stage_ent));
   if (p->compact_ok) CHAP_HIP(A.alloc(&c.grow, (size_t)p->m));
+  if (!p->obj_fast) CHAP_HIP(A.alloc(&c.objacc, (size_t)kExactLimbs));
   return CHAP_OK;
 }
 
@@ -863,8 +875,8 @@ int init_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, const WalkCtx
     CHAP_HIP(hipGetLastError());
   }
   CHAP_HIP(launch_residual_unit(p->dev, p->d_pair, c.x, c.rs, c.grow, s));
-  CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, iters, tenure, p->obj_integral, HUGE_VAL,
-                             nullptr, 1, s));
+  CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, c.objacc, iters, tenure, p->obj_integral,
+                             HUGE_VAL, nullptr, 1, s));
   CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
   return CHAP_OK;
 }
@@ -987,7 +999,7 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   std::vector<WalkCtx> ctx(nw);
   double* partial;
   uint32_t* ticket;
-  CHAP_HIP(A.alloc(&partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&partial, kInitPartial));
   CHAP_HIP(A.alloc(&ticket, 1));
   hipStream_t s;
   CHAP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -1073,7 +1085,7 @@ int slot_setup(const chap_problem* p, WalkSlot& S) {
   if (rc != CHAP_OK) return rc;
   S.grow_buf = S.ctx.grow;
   S.ctx.grow = nullptr;
-  CHAP_HIP(S.A.alloc(&S.partial, 2 * 1024));
+  CHAP_HIP(S.A.alloc(&S.partial, kInitPartial));
   CHAP_HIP(S.A.alloc(&S.ticket, 1));
   CHAP_HIP(hipMemset(S.ticket, 0, sizeof(uint32_t)));
   CHAP_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));

@@ -171,7 +171,7 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
   DeviceArena A;
   double* partial;
   uint32_t* ticket;
-  CHAP_HIP(A.alloc(&partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&partial, kInitPartial));
   CHAP_HIP(A.alloc(&ticket, 1));
   CHAP_HIP(hipMemset(ticket, 0, sizeof(uint32_t)));
   hipStream_t s;
@@ -332,14 +332,15 @@ int chap_features(chap_problem* p, const double* d_x, const float* d_w, double c
   CHAP_HIP(A.alloc(&c.st, 1));
   double* partial;
   uint32_t* ticket;
-  CHAP_HIP(A.alloc(&partial, 2 * 1024));
+  CHAP_HIP(A.alloc(&partial, kInitPartial));
   CHAP_HIP(A.alloc(&ticket, 1));
   CHAP_HIP(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
   CHAP_HIP(launch_gather(p->dev.perm, d_x, c.x, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_s_last, c.s, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_xhat_last, c.xhat, n, s));
   CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, c.x, c.rs, s));
-  CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, 1, 0, p->obj_integral, cutoff_rhs,
+  if (!p->obj_fast) CHAP_HIP(A.alloc(&c.objacc, (size_t)kExactLimbs));
+  CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, c.objacc, 1, 0, p->obj_integral, cutoff_rhs,
                              d_w + p->mp, 0, s));
   chap_learned_options o;
   chap_learned_options_default(&o);

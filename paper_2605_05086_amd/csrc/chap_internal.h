@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "chap.h"
+#include "exact_sum.h"
 
 namespace chap {
 
@@ -101,6 +102,10 @@ constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
 constexpr int kArgmaxBlocks = 512;  // workgroups of the move-selection reduction
 constexpr int kArgmaxRecord = 8;     // doubles per workgroup record of that reduction
+constexpr int kInitBlocks = 256;     // workgroups of the walk state initialisation
+// its scratch in doubles: (f, V) per workgroup, then the workgroups' exact
+// objective sums (kExactLimbs 64-bit limbs each)
+constexpr int kInitPartial = kInitBlocks * (2 + kExactLimbs);
 
 // Residual and weights of one stored row. A stored row is a normalised row;
 // an equality row is stored once in its '<=' orientation and carries a second
@@ -332,6 +337,9 @@ struct WalkCtx {
   double* long_delta;
   int32_t* long_marker;
   uint64_t* stage_rec;  // records of the staged entries (row-block staging)
+  // exact fixed-point sum of c^T x (kExactLimbs limbs) when FP64 sums of the
+  // objective may be inexact; null otherwise
+  long long* objacc;
   int32_t argmax_blocks;
   // further move-selection workgroups, one wavefront per long narrow column:
   // they combine those columns' partial bins when the pass leaves that to
@@ -416,8 +424,11 @@ hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, con
 hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hipStream_t stream);
 // Initialise a walk state; computes f = c^T x, V, and the cutoff from
 // cutoff_rhs (active iff finite) or the incumbent rule when check_incumbent.
+// partial: kInitPartial doubles; ticket: zero on entry (left zero); objacc:
+// the exact objective sum to initialise (kExactLimbs), or null when FP64
+// sums of the objective are exact.
 hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
-                             double* partial, uint32_t* ticket, int64_t iters, int32_t tenure,
+                             double* partial, uint32_t* ticket, long long* objacc, int64_t iters, int32_t tenure,
                              int32_t obj_integral, double cutoff_rhs, const float* cutoff_w,
                              int check_incumbent, hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
@@ -607,6 +618,11 @@ struct chap_problem {
   // 1 when additionally every row activity fits int32 (walks may then gather
   // residuals from the compact GatherRow copy)
   int32_t compact_ok = 0;
+  // 1 when every variable with c_j != 0 is integer with finite bounds, every
+  // such c_j is an integer and sum |c_j| max(|l_j|, |u_j|) < 2^52: every FP64
+  // sum of the objective (and the cutoff residual) is then exact, in any order;
+  // otherwise walks keep the exact fixed-point sum of c^T x
+  int32_t obj_fast = 1;
   // host copies used by runs
   std::vector<double> lb, ub, obj;
   std::vector<uint8_t> is_int;
@@ -630,6 +646,7 @@ struct chap_problem {
   double* bs_xhat = nullptr;
   double* bs_s = nullptr;
   chap::GatherRow* bs_grow = nullptr;
+  long long* bs_objacc = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
   // host copy of the caller's arrays (the autotuner re-plans from them)
   struct Raw {

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "chap_internal.h"
+#include "exact_sum.h"
 #include "learned_rows.h"
 #include "narrow_finish.h"
 
@@ -74,23 +75,57 @@ __device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int n
   return lo;
 }
 
-// Incumbent rule, run by one thread when no normalised row is violated: the
-// point is feasible; record it if it improves the best objective and (re)set
-// the cutoff row c^T x <= f_best - delta (section 3.2).
-__device__ void incumbent_check(WalkState* st, double eps) {
-  if (st->V != 0) return;
-  const double f = st->f;
-  if (!st->has_best || f < st->fbest) {
-    st->fbest = f;
-    st->has_best = 1;
-    st->copy_best = 1;
+// The objective-related part of a walk state, held in registers by every
+// lane of one wavefront (uniform values; lane 0 writes them back).
+struct ObjState {
+  double f, fbest, bc, rc;
+  long long V;
+  float wc;
+  int has_best, copy_best, cut_active, obj_integral;
+  __device__ void load(const WalkState* st) {
+    f = st->f;
+    fbest = st->fbest;
+    bc = st->bc;
+    rc = st->rc;
+    V = st->V;
+    wc = st->wc;
+    has_best = st->has_best;
+    copy_best = st->copy_best;
+    cut_active = st->cut_active;
+    obj_integral = st->obj_integral;
   }
-  const double delta = st->obj_integral ? 1.0 : 1e-4 * fmax(1.0, fabs(st->fbest));
-  st->bc = st->fbest - delta;
-  st->cut_active = 1;
-  st->rc = f - st->bc;
-  st->V = (st->rc > eps) ? 1 : 0;
-}
+  __device__ void store(WalkState* st) const {
+    st->f = f;
+    st->fbest = fbest;
+    st->bc = bc;
+    st->rc = rc;
+    st->V = V;
+    st->wc = wc;
+    st->has_best = has_best;
+    st->copy_best = copy_best;
+    st->cut_active = cut_active;
+    st->obj_integral = obj_integral;
+  }
+  // Cutoff residual c^T x - bc: rounded once from the exact sum acc, or (acc
+  // null: FP64 sums of the objective are exact) f - bc.
+  __device__ double cutoff_residual(const WaveExact* acc) const { return acc ? acc->round_plus(-bc) : f - bc; }
+  // Incumbent rule when no normalised row is violated: the point is
+  // feasible; record it if it improves the best objective and (re)set the
+  // cutoff row c^T x <= f_best - delta (section 3.2).
+  __device__ void incumbent_check(double eps, const WaveExact* acc) {
+    if (V != 0) return;
+    if (!has_best || f < fbest) {
+      fbest = f;
+      has_best = 1;
+      copy_best = 1;
+    }
+    const double delta = obj_integral ? 1.0 : 1e-4 * fmax(1.0, fabs(fbest));
+    bc = fbest - delta;
+    cut_active = 1;
+    rc = cutoff_residual(acc);
+    V = (rc > eps) ? 1 : 0;
+  }
+};
 
 // Residual from scratch of every stored row, r_i = sum_k a_ik x_k - b_i,
 // with the row's products summed one after another in the row's stored
@@ -103,6 +138,7 @@ __device__ void incumbent_check(WalkState* st, double eps) {
 // kWeightsScatter copies the caller's normalised weights. With grow, the
 // compact row copy is written too (unit weights, all-integer instances).
 constexpr int kResidualLanes = 8;
+constexpr int kResidualSteps = 4;
 enum { kWeightsKeep = 0, kWeightsUnit = 1, kWeightsScatter = 2 };
 
 template <int kWeights>
@@ -118,12 +154,25 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
   const gptr<const double> xg = gmem(x);
   const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
   double acc = 0.0;
-  for (int e0 = beg; e0 < end; e0 += kResidualLanes) {
-    const int e = e0 + g;
-    double prod = 0.0;
-    if (e < end) prod = val[e] * xg[col[e]];
-    const int cnt = min(kResidualLanes, end - e0);
-    for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod, t, kResidualLanes);
+  // kResidualSteps entries per lane in flight: every load of a round is
+  // issued before its products are summed
+  constexpr int kRound = kResidualLanes * kResidualSteps;
+  for (int e0 = beg; e0 < end; e0 += kRound) {
+    int c[kResidualSteps];
+    double a[kResidualSteps], prod[kResidualSteps];
+#pragma unroll
+    for (int u = 0; u < kResidualSteps; ++u) {
+      const int e = e0 + u * kResidualLanes + g;
+      c[u] = e < end ? col[e] : 0;
+      a[u] = e < end ? val[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * xg[c[u]];
+#pragma unroll
+    for (int u = 0; u < kResidualSteps; ++u) {
+      const int cnt = min(kResidualLanes, end - (e0 + u * kResidualLanes));
+      for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod[u], t, kResidualLanes);
+    }
   }
   if (g != 0) return;
   const double r = acc - P.row_rhs[i];
@@ -173,23 +222,42 @@ __global__ __launch_bounds__(256) void k_start_point(DevProblem P, uint64_t seed
   x[q] = v;
 }
 
-// f = c^T x and V = violated rows, as fixed-order (deterministic) grid
-// reductions; the last workgroup writes the walk state.
+// f = c^T x and V = violated rows as grid reductions; the last workgroup
+// writes the walk state. With objacc (objectives whose FP64 sums may be
+// inexact) every workgroup adds its products exactly into a fixed-point sum
+// in LDS, the last one adds the workgroups' sums, keeps the result in objacc
+// and rounds f and the cutoff residual from it; otherwise the FP64 sum is
+// exact and its order does not matter.
 __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* __restrict__ x,
                                                     const RowState* __restrict__ rs, WalkState* st,
-                                                    double* partial, uint32_t* ticket, int64_t iters,
-                                                    int32_t tenure, int32_t obj_integral, double cutoff_rhs,
-                                                    const float* cutoff_w, int32_t check_incumbent) {
+                                                    double* partial, uint32_t* ticket, long long* objacc,
+                                                    int64_t iters, int32_t tenure, int32_t obj_integral,
+                                                    double cutoff_rhs, const float* cutoff_w,
+                                                    int32_t check_incumbent) {
   __shared__ double redd[4];
   __shared__ long long redl[4];
+  __shared__ long long lacc[kExactLimbs];
   __shared__ uint32_t last;
+  long long* plimb = (long long*)(partial + 2 * kInitBlocks);
   const double eps = P.eps;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int gs = gridDim.x * blockDim.x;
+  if (objacc) {
+    for (int t = threadIdx.x; t < kExactLimbs; t += blockDim.x) lacc[t] = 0;
+    __syncthreads();
+  }
   double f = 0.0;
   for (int j = gt; j < P.n; j += gs) {
     const double c = P.obj[j];
-    if (c != 0.0) f += c * x[j];
+    if (c == 0.0) continue;
+    if (objacc) {
+      double p, e;
+      exact_product(c, x[j], p, e);
+      exact_atomic_add(lacc, p);
+      exact_atomic_add(lacc, e);
+    } else {
+      f += c * x[j];
+    }
   }
   long long v = 0;
   for (int i = gt; i < P.ms; i += gs) {
@@ -203,45 +271,67 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
     partial[2 * blockIdx.x] = f;
     partial[2 * blockIdx.x + 1] = (double)v;
   }
+  if (objacc)
+    for (int t = threadIdx.x; t < kExactLimbs; t += blockDim.x) plimb[blockIdx.x * kExactLimbs + t] = lacc[t];
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(ticket, 1u);
   __syncthreads();
   if (last != gridDim.x - 1) return;
   __threadfence();
-  if (threadIdx.x != 0) return;
+  if (objacc) {
+    for (int t = threadIdx.x; t < kExactLimbs; t += blockDim.x) {
+      long long sum = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b) sum += plimb[b * kExactLimbs + t];
+      lacc[t] = sum;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x >= 64) return;
+  // one wavefront finishes; every lane computes the same values
   double ft = 0.0, vt = 0.0;
   for (unsigned b = 0; b < gridDim.x; ++b) {
     ft += partial[2 * b];
     vt += partial[2 * b + 1];
   }
+  WaveExact acc;
+  if (objacc) {
+    acc.a = lacc[threadIdx.x];
+    acc.b = threadIdx.x < kExactLimbs - 64 ? lacc[64 + threadIdx.x] : 0;
+    acc.normalize();
+    acc.store(objacc);
+    ft = acc.round_nearest();
+  }
+  ObjState o;
+  o.f = ft;
+  o.fbest = HUGE_VAL;
+  o.has_best = 0;
+  o.copy_best = 0;
+  o.obj_integral = obj_integral;
+  o.V = (long long)vt;
+  o.wc = cutoff_w ? *cutoff_w : 1.0f;
+  o.bc = 0.0;
+  o.rc = 0.0;
+  o.cut_active = 0;
+  if (isfinite(cutoff_rhs)) {
+    o.cut_active = 1;
+    o.bc = cutoff_rhs;
+    o.rc = o.cutoff_residual(objacc ? &acc : nullptr);
+    if (o.rc > eps) o.V += 1;
+  }
+  if (check_incumbent) o.incumbent_check(eps, objacc ? &acc : nullptr);
+  if (threadIdx.x != 0) return;
   *ticket = 0u;
   st->k = 0;
   st->iters = iters;
   st->tenure = tenure;
-  st->obj_integral = obj_integral;
-  st->f = ft;
-  st->fbest = HUGE_VAL;
-  st->has_best = 0;
-  st->copy_best = 0;
-  st->V = (int64_t)vt;
-  st->wc = cutoff_w ? *cutoff_w : 1.0f;
-  st->bc = 0.0;
-  st->rc = 0.0;
-  st->cut_active = 0;
-  if (isfinite(cutoff_rhs)) {
-    st->cut_active = 1;
-    st->bc = cutoff_rhs;
-    st->rc = ft - cutoff_rhs;
-    if (st->rc > eps) st->V += 1;
-  }
+  o.store(st);
   st->j_all = -1;
   st->j_nt = -1;
   st->mv_j = -1;
   st->mv_kind = 2;
   st->dV = 0ull;
   st->compact_rows = 1;
-  if (check_incumbent) incumbent_check(st, eps);
 }
 
 __device__ __forceinline__ bool better(double sa, int ja, double sb, int jb) {
@@ -605,37 +695,65 @@ __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks
 }
 
 // Ends the iteration: objective, cutoff row, incumbent rule, trace, k + 1.
-__global__ void k_finish(const WalkCtx* __restrict__ walks) {
+// One wavefront per walk (the exact objective sum is spread over its lanes);
+// lane 0 writes.
+__global__ __launch_bounds__(64) void k_finish(const WalkCtx* __restrict__ walks) {
   const WalkCtx& C = walks[blockIdx.x];
   const DevProblem& P = C.P;
-  double* x = C.x;
-  int32_t* tabu = C.tabu;
   WalkState* st = C.st;
-  chap_trace_record* trace = C.trace;
-  if (threadIdx.x != 0 || st->k >= st->iters || st->skip) return;
+  if (st->k >= st->iters || st->skip) return;
+  const int lane = threadIdx.x;
   const double eps = P.eps;
   const int64_t k = st->k;
   const int jstar = st->mv_j;
-  long long V = st->V + (long long)st->dV;
+  ObjState o;
+  o.load(st);
+  o.V += (long long)st->dV;
+  const bool exact = C.objacc != nullptr;
+  WaveExact acc;
+  if (exact) acc.load(C.objacc);
   if (jstar >= 0) {
     const double c = P.obj[jstar];
-    const double d = st->mv_delta;
-    if (st->cut_active && c != 0.0) {
-      const double r2 = st->rc + c * d;
-      V += viol_change(st->rc, r2, eps);
-      st->rc = r2;
+    const double xo = st->mv_old, xn = st->mv_new;
+    if (c != 0.0) {
+      double r2 = 0.0;
+      if (exact) {
+        double p, e;
+        exact_product(c, xn, p, e);
+        acc.add(p);
+        acc.add(e);
+        exact_product(c, xo, p, e);
+        acc.add(-p);
+        acc.add(-e);
+        acc.normalize();
+        acc.store(C.objacc);
+        o.f = acc.round_nearest();
+        if (o.cut_active) r2 = o.cutoff_residual(&acc);
+      } else {
+        const double d = st->mv_delta;
+        r2 = o.rc + c * d;
+        o.f = o.f + c * d;
+      }
+      if (o.cut_active) {
+        o.V += viol_change(o.rc, r2, eps);
+        o.rc = r2;
+      }
     }
-    if (c != 0.0) st->f = st->f + c * d;
-    x[jstar] = st->mv_new;
-    tabu[jstar] = (int32_t)(k + st->tenure);
-  } else if (st->mv_kind != kStallKind && st->cut_active && st->rc > eps) {
-    st->wc = st->wc + 1.0f;
+    if (lane == 0) {
+      C.x[jstar] = xn;
+      C.tabu[jstar] = (int32_t)(k + st->tenure);
+    }
+  } else if (st->mv_kind != kStallKind && o.cut_active && o.rc > eps) {
+    o.wc = o.wc + 1.0f;
   }
+  if (lane == 0) {
+    C.trace[k].viol = o.V;
+    C.trace[k].obj = o.f;
+  }
+  o.incumbent_check(eps, exact ? &acc : nullptr);
+  if (lane != 0) return;
+  o.store(st);
   st->dV = 0ull;
-  st->V = V;
-  trace[k].viol = V;
-  trace[k].obj = st->f;
-  incumbent_check(st, eps);
   st->k = k + 1;
 }
 
@@ -749,14 +867,13 @@ hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hip
   return hipGetLastError();
 }
 
-constexpr int kInitBlocks = 256;
-
 hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
-                             double* partial, uint32_t* ticket, int64_t iters, int32_t tenure, int32_t obj_integral,
-                             double cutoff_rhs, const float* cutoff_w, int check_incumbent, hipStream_t stream) {
+                             double* partial, uint32_t* ticket, long long* objacc, int64_t iters, int32_t tenure,
+                             int32_t obj_integral, double cutoff_rhs, const float* cutoff_w, int check_incumbent,
+                             hipStream_t stream) {
   const int blocks = blocks_for((int64_t)(P.n > P.ms ? P.n : P.ms), kInitBlocks);
-  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, partial, ticket, iters, tenure,
-                     obj_integral, cutoff_rhs, cutoff_w, check_incumbent);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, partial, ticket, objacc, iters,
+                     tenure, obj_integral, cutoff_rhs, cutoff_w, check_incumbent);
   return hipGetLastError();
 }
 

@@ -162,6 +162,9 @@ class ExactProblem:
         return x
 
     def tabu_run(self, iters, tenure, x0):
+        """Residuals, the objective and the cutoff residual are exact
+        rationals; the oracle holds them rounded once to FP64 (compare with
+        float(), which rounds a Fraction to nearest)."""
         x = [F(v) for v in x0]
         n, mp = self.n, self.mp
         w = [Fraction(1)] * (mp + 1)
@@ -198,10 +201,12 @@ class ExactProblem:
             f = objective()
             if fbest is None or f < fbest:
                 fbest = f
-            delta = Fraction(1) if self.obj_integral else None
-            if delta is None:
-                raise ValueError("exact walk only for integral objectives")
-            bc = fbest - delta
+            # delta and the cutoff right-hand side are FP64 numbers computed as
+            # the reading writes them: delta = 1 for an integral objective, else
+            # 1e-4 max(1, |f_best|), and b_c = f_best - delta, each rounded
+            fb = float(fbest)
+            delta = 1.0 if self.obj_integral else 1e-4 * max(1.0, abs(fb))
+            bc = Fraction(fb - delta)
             r = resid()
             V = nviol(r)
 

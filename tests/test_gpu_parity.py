@@ -1,12 +1,12 @@
 """GPU parity: the HIP library against the CPU oracle, through the C ABI.
 
-Integer data: bit-exact (scores are sums of +-w, +-w/2 with integer weights,
-exact in FP64; breakpoints and residuals use the same IEEE operations in the
-same order). A single pass on continuous data: residuals of ordinary rows are
-computed in the same order and match bit for bit; the cutoff row's activity
-is a parallel sum on the GPU, so with an active cutoff the shifts agree to
-1e-12 relative and the scores exactly. Walks are bit-exact on all-integer
-instances; with continuous variables see test_tabu_continuous_variables.
+Bit-exact everywhere. Scores are sums of +-w, +-w/2 with integer weights,
+exact in FP64; breakpoints and residuals of ordinary rows use the same IEEE
+operations in the same order (rows summed in the caller's CSR order). The
+objective row's activity c^T x, a sum over every variable, is the exact
+value rounded once on both sides (an exactly rounded sum in the oracle, a
+fixed-point exact sum kept incrementally on the GPU), so walks on continuous
+data agree bit for bit too, past the first incumbent.
 """
 from __future__ import annotations
 
@@ -81,15 +81,7 @@ def test_best_shift_random_mixed(chap, route, cut):
         xh, s = gpu_best_shift(chap, mip, x, w, cutoff, **opts)
         oxh, os_ = P.best_shift(x, w, cutoff)
         assert_same(s, os_, f"score seed={seed}")
-        if cut:
-            # the cutoff activity c^T x has real-valued terms from continuous
-            # variables: a parallel sum on the GPU, a sequential one in the
-            # oracle, so continuous shifts agree to rounding
-            ints = mip.is_int == 1
-            assert_same(xh[ints], oxh[ints], f"integer shift seed={seed}")
-            np.testing.assert_allclose(xh[~ints], oxh[~ints], rtol=1e-12, atol=1e-12)
-        else:
-            assert_same(xh, oxh, f"shift seed={seed}")
+        assert_same(xh, oxh, f"shift seed={seed}")
 
 
 @pytest.mark.parametrize("deg", [70, 300, 1500, 2500])
@@ -109,22 +101,33 @@ def test_best_shift_long_general_columns(chap, deg):
         assert_same(xh, oxh, "shift")
 
 
-def test_best_shift_continuous_data(chap):
+@pytest.mark.parametrize("objective", ["plain", "irrational", "wide"])
+def test_best_shift_continuous_data(chap, objective):
+    """Continuous data with an active cutoff row: the cutoff residual is
+    c^T x - b_c rounded once (objective products that are inexact in FP64,
+    magnitudes from 1e-9 to 1e9 that cancel), so shifts and scores are
+    bit-exact."""
     for seed in range(6):
         mip = mipgen.random_mixed(500 + seed, n=80, m=60, integer_data=False, frac_bin=0.2, frac_int=0.3)
+        rng = np.random.default_rng(seed)
+        if objective == "irrational":
+            mip.obj[:] = mip.obj * np.pi
+        elif objective == "wide":
+            mip.obj[:] = mip.obj * 10.0 ** rng.integers(-9, 10, size=mip.n)
         P = oracle.OracleProblem(mip)
         x = mipgen.random_point(mip, seed)
         w = mipgen.random_weights(P.mp + 1, seed)
-        say(f"best_shift continuous seed={seed}")
+        say(f"best_shift continuous {objective} seed={seed}")
         xh, s = gpu_best_shift(chap, mip, x, w)
         oxh, os_ = P.best_shift(x, w)
         assert_same(s, os_, "score")
         assert_same(xh, oxh, "shift")
-        cutoff = float(mip.obj @ x) - 0.37
-        xh, s = gpu_best_shift(chap, mip, x, w, cutoff)
-        oxh, os_ = P.best_shift(x, w, cutoff)
-        assert_same(s, os_, "score (cutoff)")
-        np.testing.assert_allclose(xh, oxh, rtol=1e-12, atol=1e-12)
+        for off in (0.37, -2.5e-7, 1e-3):
+            cutoff = P.objective(x) - off
+            xh, s = gpu_best_shift(chap, mip, x, w, cutoff)
+            oxh, os_ = P.best_shift(x, w, cutoff)
+            assert_same(s, os_, f"score (cutoff offset {off})")
+            assert_same(xh, oxh, f"shift (cutoff offset {off})")
 
 
 def test_best_shift_workload_shapes(chap):
@@ -143,29 +146,21 @@ def test_best_shift_workload_shapes(chap):
             assert_same(xh, oxh, f"{name} shift")
 
 
-def compare_runs(g, o, what, exact=True, exact_obj=True):
-    """exact_obj=False: the objective c^T x (a sum over all variables, kept
-    incrementally on the GPU) is compared to 1e-12 relative; everything else
-    bit for bit."""
+def compare_runs(g, o, what):
+    """Trace, final point, residuals, weights, best objective, cutoff and
+    best point, bit for bit."""
     gt, ot = g.trace, o["trace"]
     assert gt.shape == ot.shape
-    for f in ("iter", "var", "kind", "viol"):
+    for f in ("iter", "var", "kind", "viol", "x_old", "x_new", "score", "obj"):
         assert_same(gt[f], ot[f], f"{what} trace.{f}")
-    for f in ("x_old", "x_new", "score", "obj"):
-        if exact and (exact_obj or f != "obj"):
-            assert_same(gt[f], ot[f], f"{what} trace.{f}")
-        else:
-            np.testing.assert_allclose(gt[f], ot[f], rtol=1e-12, atol=1e-9)
-    if exact:
-        assert_same(g.x, o["x"], f"{what} x")
-        assert_same(g.resid, o["r"], f"{what} resid")
-        assert_same(g.w, o["w"], f"{what} w")
-        if exact_obj:
-            assert g.best_obj == o["best_obj"] and g.cutoff_rhs == o["cutoff_rhs"]
-        if o["best_x"] is not None:
-            assert_same(g.best_x, o["best_x"], f"{what} best_x")
-        else:
-            assert g.best_x is None
+    assert_same(g.x, o["x"], f"{what} x")
+    assert_same(g.resid, o["r"], f"{what} resid")
+    assert_same(g.w, o["w"], f"{what} w")
+    assert g.best_obj == o["best_obj"] and g.cutoff_rhs == o["cutoff_rhs"]
+    if o["best_x"] is not None:
+        assert_same(g.best_x, o["best_x"], f"{what} best_x")
+    else:
+        assert g.best_x is None
 
 
 def test_tabu_tiny_binary_full(chap):
@@ -203,59 +198,33 @@ def test_tabu_powerlaw_scaled(chap):
         compare_runs(G.tabu_run(200, 10, seed), P.tabu_run(200, 10, seed), f"powerlaw seed={seed}")
 
 
-def first_divergence(g, o):
-    gt, ot = g.trace, o["trace"]
-    for k in range(gt.shape[0]):
-        if (gt["var"][k], gt["kind"][k], gt["viol"][k]) != (ot["var"][k], ot["kind"][k], ot["viol"][k]):
-            return k
-        for f in ("x_old", "x_new", "score", "obj"):
-            a, b = gt[f][k], ot[f][k]
-            if abs(a - b) > 1e-12 * max(1.0, abs(a), abs(b)):
-                return k
-    return gt.shape[0]
-
-
-def check_walk_consistency(P, g, mip):
-    """Properties of a GPU walk that hold at any size: the kept residuals
-    equal a from-scratch evaluation at the final point, and every trace step
-    is a positive-score move or a reweight."""
-    r, v = P.residual(g.x, g.cutoff_rhs)
-    scale = np.abs(r) + 1.0
-    assert np.all(np.abs(g.resid - r) <= 1e-9 * scale)
-    t = g.trace
-    moves = t["var"] >= 0
-    assert np.all(t["score"][moves] > 0) and np.all(t["kind"][~moves] == 2)
-    assert np.all((t["x_new"][moves] >= mip.lb[t["var"][moves]]) & (t["x_new"][moves] <= mip.ub[t["var"][moves]]))
-
-
 def test_tabu_continuous_variables(chap):
-    """Instances with continuous variables and real right-hand sides. The
-    walk recomputes every touched row from scratch in the caller's CSR order,
-    so its residuals equal the oracle's bit for bit and the traces are
-    identical while the cutoff row is inactive. Once a feasible point
-    activates the cutoff row, its activity c^T x (kept incrementally on the
-    GPU, summed from scratch by the oracle) may differ in the last bit, and
-    a later decision on that row can differ; the GPU walk is then checked
-    for internal consistency."""
-    cases = [("general n=4000", mipgen.general(1, n=4000, m=2000), 150),
+    """Instances with continuous variables, real right-hand sides and
+    fractional objectives. The walk recomputes every touched row from scratch
+    in the caller's CSR order and keeps c^T x as an exact sum, so its trace,
+    residuals, cutoff and incumbents equal the oracle's bit for bit, also after
+    the first feasible point activates the cutoff row."""
+    cases = [("general n=4000", mipgen.general(1, n=4000, m=2000), 300),
              ("general n=100k", mipgen.general(0), 60),
-             ("mixed", mipgen.random_mixed(41, n=60, m=50, frac_bin=0.3, frac_int=0.3), 150),
-             ("mixed 2", mipgen.random_mixed(42, n=80, m=40, frac_bin=0.2, frac_int=0.3, integer_data=False), 150)]
+             ("mixed", mipgen.random_mixed(41, n=60, m=50, frac_bin=0.3, frac_int=0.3), 300),
+             ("mixed 2", mipgen.random_mixed(42, n=80, m=40, frac_bin=0.2, frac_int=0.3, integer_data=False), 300),
+             ("mixed 3", mipgen.random_mixed(43, n=40, m=12, frac_bin=0.2, frac_int=0.3, integer_data=False), 400),
+             ("mixed 4", mipgen.random_mixed(44, n=30, m=10, frac_bin=0.3, frac_int=0.2, integer_data=False), 400)]
+    incumbents = 0
     for name, mip, iters in cases:
+        if name.startswith("mixed"):
+            mip.obj[:] = mip.obj * np.pi / 3.0   # products inexact in FP64
         P = oracle.OracleProblem(mip)
         G = chap.Problem(mip)
         say(f"tabu continuous {name} {iters} iters")
         g = G.tabu_run(iters, 10, 0)
         o = P.tabu_run(iters, 10, 0)
-        k = first_divergence(g, o)
         feas = np.flatnonzero(o["trace"]["viol"] == 0)
-        k_inc = int(feas[0]) + 1 if feas.size else iters
-        print(f"{name}: traces agree for {k} of {iters} iterations; cutoff row first active after step {k_inc}",
+        print(f"{name}: first feasible point after step {int(feas[0]) + 1 if feas.size else None} of {iters}",
               flush=True)
-        assert k >= k_inc
-        if k_inc == iters:
-            compare_runs(g, o, name, exact_obj=False)
-        check_walk_consistency(P, g, mip)
+        incumbents += int(o["best_x"] is not None)
+        compare_runs(g, o, name)
+    assert incumbents >= 2
 
 
 def test_tabu_edge_cases(chap):
@@ -358,7 +327,7 @@ def test_batch_equals_plain(chap):
     for w in (3, 7):
         say(f"oracle walk {w}")
         o = oracle.OracleProblem(mips[walk_prob[w]]).tabu_run(120, 10, walk_seed[w])
-        compare_runs(runs[w], o, f"batch walk {w}", exact=True, exact_obj=walk_prob[w] == 3)
+        compare_runs(runs[w], o, f"batch walk {w}")
 
 
 def test_autotune_picks_a_candidate(chap):
