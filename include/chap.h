@@ -178,8 +178,9 @@ int chap_best_shift_pass_ms(chap_problem *p, double *ms);
  * `tenure` iterations; when no move is admissible, the weight of every
  * violated normalised row (cutoff included) grows by 1.
  *   iters >= 0, tenure >= 0, iters + tenure < 2^31.
- *   x0         optional host start point (n doubles) replacing the seed rule;
- *              NULL to use the seed rule.
+ *   x0         optional host start point (n doubles, caller's order) replacing
+ *              the seed rule: inside the bounds and integral on integer
+ *              variables (CHAP_EINVAL otherwise); NULL to use the seed rule.
  *   hip_stream work is ordered after what is queued on this stream.
  * Synchronous: on return *out holds the trace and the final state.
  * Errors: CHAP_EINVAL, CHAP_ENOMEM, CHAP_EHIP.

@@ -184,6 +184,9 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     }
     P->obj_fast = (fast && mag < 4503599627370496.0) ? 1 : 0;  // 2^52
   }
+  P->x_small = 1;
+  for (int32_t j = 0; j < n && P->x_small; ++j)
+    P->x_small = P->is_int[j] && P->lb[j] >= -128.0 && P->ub[j] <= 127.0;
   // ---- CSR and CSC must be the same matrix (stored zeros dropped) --------
   // transpose of the CSR, rows ascending within each column
   std::vector<int64_t> tptr((size_t)n + 1, 0);
@@ -663,6 +666,11 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(A.upload(&d_obj, objq));
   CHAP_HIP(A.upload(&d_isint, isintq));
   CHAP_HIP(A.upload(&d_perm, perm));
+  {
+    int32_t* d_inv;
+    CHAP_HIP(A.upload(&d_inv, inv));
+    P->d_inv = d_inv;
+  }
   CHAP_HIP(A.upload(&d_pair, P->pair));
   CHAP_HIP(A.upload(&d_nidx, P->nidx));
   D.col_ptr = d_cptr;
@@ -729,6 +737,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   CHAP_HIP(A.alloc(&P->bs_state, 1));
   CHAP_HIP(A.alloc(&P->bs_partial, kInitPartial));
   if (!P->obj_fast) CHAP_HIP(A.alloc(&P->bs_objacc, kExactLimbs));
+  if (P->x_small) CHAP_HIP(A.alloc(&P->bs_xc, (size_t)n));
   CHAP_HIP(A.alloc(&P->bs_ticket, 1));
   CHAP_HIP(hipMemset(P->bs_ticket, 0, sizeof(uint32_t)));
   {
@@ -775,11 +784,13 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   if (!d_w) return fail(CHAP_EINVAL, "chap_best_shift: null weights");
   if (std::isnan(cutoff_rhs)) return fail(CHAP_EINVAL, "chap_best_shift: cutoff_rhs is NaN");
   hipStream_t s = (hipStream_t)hip_stream;
-  CHAP_HIP(launch_gather(p->dev.perm, d_x, p->bs_x, p->n, s));
-  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_rs, s));
+  const uint32_t epoch = ++p->bs_epoch == 0 ? ++p->bs_epoch : p->bs_epoch;  // never 0
+  CHAP_HIP(launch_stage_x(p->dev.perm, d_x, p->bs_x, p->bs_xc, p->bs_state, epoch, p->n, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
+                                   p->bs_rs, s));
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, p->bs_objacc, 1,
-                             0, p->obj_integral, cut, d_w + p->mp, 0, s));
+                             0, p->obj_integral, cut, d_w + p->mp, 0, 0, s));
   if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
   if (p->n > 0 && !p->bs_exec) {
     // capture the pass once (its arguments are the problem's own buffers)
@@ -805,7 +816,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
   if (p->n > 0) CHAP_HIP(hipGraphLaunch(p->bs_exec, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
-  CHAP_HIP(launch_scatter2(p->dev.perm, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
+  CHAP_HIP(launch_gather2(p->d_inv, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
   p->pass_timed = true;
   return CHAP_OK;
 }
@@ -850,6 +861,7 @@ int alloc_walk(const chap_problem* p, int64_t trace_cap, DeviceArena& A, WalkCtx
   CHAP_HIP(A.alloc(&c.stage_rec, (size_t)p->plan.n_stage_ent));
   if (p->compact_ok) CHAP_HIP(A.alloc(&c.grow, (size_t)p->m));
   if (!p->obj_fast) CHAP_HIP(A.alloc(&c.objacc, (size_t)kExactLimbs));
+  if (p->x_small) CHAP_HIP(A.alloc(&c.xc, (size_t)n));
   return CHAP_OK;
 }
 
@@ -858,25 +870,33 @@ int init_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, const WalkCtx
   const chap_problem* p = spec.p;
   const int32_t n = p->n;
   if (spec.x0) {
-    for (int32_t j = 0; j < n; ++j)
-      if (!std::isfinite(spec.x0[j])) return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
+    for (int32_t j = 0; j < n; ++j) {
+      const double v = spec.x0[j];
+      if (!std::isfinite(v)) return fail(CHAP_EINVAL, "non-finite start value at " + std::to_string(j));
+      if (v < p->lb[j] || v > p->ub[j] || (p->is_int[j] && std::floor(v) != v))
+        return fail(CHAP_EINVAL, "start value at " + std::to_string(j) +
+                                     " outside the bounds or fractional on an integer variable");
+    }
+  }
+  // the cleared state has x_misfit = 0; this call's epoch is 1
+  CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
+  if (spec.x0) {
     // caller's order into xhat (free until the first pass), then internal order
     if (n > 0) {
       CHAP_HIP(hipStreamSynchronize(s));
       CHAP_HIP(hipMemcpy(c.xhat, spec.x0, sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
-      CHAP_HIP(launch_gather(p->dev.perm, c.xhat, c.x, n, s));
+      CHAP_HIP(launch_stage_x(p->dev.perm, c.xhat, c.x, c.xc, c.st, 1u, n, s));
     }
   } else {
-    CHAP_HIP(launch_start_point(p->dev, spec.seed, c.x, s));
+    CHAP_HIP(launch_start_point(p->dev, spec.seed, c.x, c.xc, s));
   }
-  CHAP_HIP(hipMemsetAsync(c.st, 0, sizeof(WalkState), s));
   if (n > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)n);
     CHAP_HIP(hipGetLastError());
   }
-  CHAP_HIP(launch_residual_unit(p->dev, p->d_pair, c.x, c.rs, c.grow, s));
+  CHAP_HIP(launch_residual_unit(p->dev, p->d_pair, c.x, c.xc, c.st, 1u, c.rs, c.grow, s));
   CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, c.objacc, iters, tenure, p->obj_integral,
-                             HUGE_VAL, nullptr, 1, s));
+                             HUGE_VAL, nullptr, 1, 1, s));
   CHAP_HIP(launch_copy_best(c.x, c.best_x, c.st, n, s));
   return CHAP_OK;
 }

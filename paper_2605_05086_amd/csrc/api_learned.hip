@@ -338,10 +338,10 @@ int chap_features(chap_problem* p, const double* d_x, const float* d_w, double c
   CHAP_HIP(launch_gather(p->dev.perm, d_x, c.x, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_s_last, c.s, n, s));
   CHAP_HIP(launch_gather(p->dev.perm, d_xhat_last, c.xhat, n, s));
-  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, c.x, c.rs, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, c.x, nullptr, nullptr, 0u, c.rs, s));
   if (!p->obj_fast) CHAP_HIP(A.alloc(&c.objacc, (size_t)kExactLimbs));
   CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, c.objacc, 1, 0, p->obj_integral, cutoff_rhs,
-                             d_w + p->mp, 0, s));
+                             d_w + p->mp, 0, 1, s));
   chap_learned_options o;
   chap_learned_options_default(&o);
   o.log_pairs = 0;

@@ -178,6 +178,10 @@ struct __align__(16) WalkState {
   unsigned long long dV;  // two's complement accumulator of violation changes
   int32_t skip;           // learned walks: this iteration does nothing (block idle)
   int32_t compact_rows;   // single passes: the compact row copy is exact for these weights
+  // the call (epoch) whose point did not fit the byte copy of x (see
+  // launch_stage_x); 0 after the state is cleared
+  uint32_t x_misfit;
+  uint32_t pad_;
 };
 
 // A slice of a long narrow-integer column handled by one workgroup; col < 0
@@ -340,6 +344,9 @@ struct WalkCtx {
   // exact fixed-point sum of c^T x (kExactLimbs limbs) when FP64 sums of the
   // objective may be inexact; null otherwise
   long long* objacc;
+  // byte copy of x for residuals from scratch (problems whose variables are
+  // all integers with bounds in [-128, 127]), or null
+  int8_t* xc;
   int32_t argmax_blocks;
   // further move-selection workgroups, one wavefront per long narrow column:
   // they combine those columns' partial bins when the pass leaves that to
@@ -411,26 +418,37 @@ inline bool pass_defers_combine(const BatchLaunch& L) {
 
 // ---- launchers (kernels_walk.hip) -----------------------------------------
 // Single-walk set-up kernels.
-// Residuals from scratch (weights left as they are).
+// The point of a call in internal order: dst[q] = src[perm[q]] (src already
+// in internal order when perm is null, dst then equal to src or null). With
+// xc, also its byte copy: a value that is not an integer in [-128, 127]
+// stores `epoch` in st->x_misfit, and residuals of this call then read dst.
+hipError_t launch_stage_x(const int32_t* perm, const double* src, double* dst, int8_t* xc, WalkState* st,
+                          uint32_t epoch, int32_t n, hipStream_t stream);
+// Residuals from scratch (weights left as they are). With xc (and
+// st->x_misfit != epoch) the products read the byte copy of x.
 hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream);
 // Residuals from scratch with unit weights, and the compact copy when grow
 // is not null.
-hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, RowState* rs,
-                                GatherRow* grow, hipStream_t stream);
+hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, const int8_t* xc,
+                                const WalkState* st, uint32_t epoch, RowState* rs, GatherRow* grow,
+                                hipStream_t stream);
 // Residuals from scratch with the caller's normalised weights w_norm.
 hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair,
-                                   const float* w_norm, const double* x, RowState* rs, hipStream_t stream);
-// Seeded start point (internal order).
-hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hipStream_t stream);
+                                   const float* w_norm, const double* x, const int8_t* xc, const WalkState* st,
+                                   uint32_t epoch, RowState* rs, hipStream_t stream);
+// Seeded start point (internal order), and its byte copy when xc is set.
+hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, int8_t* xc, hipStream_t stream);
 // Initialise a walk state; computes f = c^T x, V, and the cutoff from
 // cutoff_rhs (active iff finite) or the incumbent rule when check_incumbent.
 // partial: kInitPartial doubles; ticket: zero on entry (left zero); objacc:
 // the exact objective sum to initialise (kExactLimbs), or null when FP64
-// sums of the objective are exact.
+// sums of the objective are exact. V is counted with check_incumbent or
+// count_violated; f with check_incumbent or a finite cutoff_rhs (a single
+// pass needs neither V nor, without a cutoff row, f).
 hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
                              double* partial, uint32_t* ticket, long long* objacc, int64_t iters, int32_t tenure,
                              int32_t obj_integral, double cutoff_rhs, const float* cutoff_w,
-                             int check_incumbent, hipStream_t stream);
+                             int check_incumbent, int count_violated, hipStream_t stream);
 hipError_t launch_copy_best(const double* x, double* best_x, WalkState* st, int32_t n, hipStream_t stream);
 // grow[i] = compact copy of rs[i]
 hipError_t launch_fill_compact(const RowState* rs, GatherRow* grow, int32_t ms, hipStream_t stream);
@@ -440,9 +458,9 @@ hipError_t launch_fill_compact_checked(const RowState* rs, GatherRow* grow, Walk
                                        hipStream_t stream);
 // dst[q] = src[perm[q]] (original order -> internal order)
 hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream);
-// da[perm[q]] = a[q], db[perm[q]] = b[q] (internal order -> original order)
-hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
-                           hipStream_t stream);
+// da[j] = a[inv[j]], db[j] = b[inv[j]] (internal order -> original order)
+hipError_t launch_gather2(const int32_t* inv, const double* a, const double* b, double* da, double* db, int32_t n,
+                          hipStream_t stream);
 // Move selection, application and iteration end for every walk of the batch
 // (combine: after a pass launched with defer_combine).
 hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream, bool combine = false);
@@ -623,6 +641,10 @@ struct chap_problem {
   // sum of the objective (and the cutoff residual) is then exact, in any order;
   // otherwise walks keep the exact fixed-point sum of c^T x
   int32_t obj_fast = 1;
+  // 1 when every variable is an integer with bounds in [-128, 127]: points
+  // within the bounds have an exact byte copy, which residuals from scratch
+  // gather instead of FP64 values (a 1-byte gather per nonzero)
+  int32_t x_small = 0;
   // host copies used by runs
   std::vector<double> lb, ub, obj;
   std::vector<uint8_t> is_int;
@@ -636,6 +658,7 @@ struct chap_problem {
   chap::PassPlan plan{};
   const int32_t* d_nidx = nullptr;
   const uint8_t* d_pair = nullptr;
+  const int32_t* d_inv = nullptr;  // internal index of each original column
   int32_t device = 0;
   // scratch of chap_best_shift
   chap::RowState* bs_rs = nullptr;
@@ -647,6 +670,8 @@ struct chap_problem {
   double* bs_s = nullptr;
   chap::GatherRow* bs_grow = nullptr;
   long long* bs_objacc = nullptr;
+  int8_t* bs_xc = nullptr;
+  uint32_t bs_epoch = 0;
   std::vector<int32_t> perm;  // original index of each internal column
   // host copy of the caller's arrays (the autotuner re-plans from them)
   struct Raw {

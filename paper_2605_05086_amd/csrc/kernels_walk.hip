@@ -143,15 +143,18 @@ enum { kWeightsKeep = 0, kWeightsUnit = 1, kWeightsScatter = 2 };
 
 template <int kWeights>
 __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __restrict__ x,
-                                                  RowState* __restrict__ rs, const int32_t* __restrict__ nidx,
-                                                  const uint8_t* __restrict__ pair, const float* __restrict__ w,
-                                                  GatherRow* __restrict__ grow) {
+                                                  const int8_t* __restrict__ xc, const WalkState* st,
+                                                  uint32_t epoch, RowState* __restrict__ rs,
+                                                  const int32_t* __restrict__ nidx, const uint8_t* __restrict__ pair,
+                                                  const float* __restrict__ w, GatherRow* __restrict__ grow) {
   const int g = threadIdx.x & (kResidualLanes - 1);
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kResidualLanes;
   if (i >= P.ms) return;  // whole groups leave together
   const gptr<const double> val = gmem(P.row_val);
   const gptr<const int32_t> col = gmem(P.row_col);
   const gptr<const double> xg = gmem(x);
+  const gptr<const int8_t> xcg = gmem(xc);
+  const bool small = xc != nullptr && st->x_misfit != epoch;
   const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
   double acc = 0.0;
   // kResidualSteps entries per lane in flight: every load of a round is
@@ -166,8 +169,13 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
       c[u] = e < end ? col[e] : 0;
       a[u] = e < end ? val[e] : 0.0;
     }
+    if (small) {
 #pragma unroll
-    for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * xg[c[u]];
+      for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * (double)xcg[c[u]];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * xg[c[u]];
+    }
 #pragma unroll
     for (int u = 0; u < kResidualSteps; ++u) {
       const int cnt = min(kResidualLanes, end - (e0 + u * kResidualLanes));
@@ -205,7 +213,8 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
 // variable with finite bounds starts at l + (h mod (u - l + 1)), h the
 // (j+1)-th SplitMix64 output of the seed for original index j; every other
 // variable starts at 0 clamped into its bounds.
-__global__ __launch_bounds__(256) void k_start_point(DevProblem P, uint64_t seed, double* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_start_point(DevProblem P, uint64_t seed, double* __restrict__ x,
+                                                     int8_t* __restrict__ xc) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
   const double l = P.lb[q], u = P.ub[q];
@@ -220,6 +229,21 @@ __global__ __launch_bounds__(256) void k_start_point(DevProblem P, uint64_t seed
     if (v > u) v = u;
   }
   x[q] = v;
+  if (xc) xc[q] = (int8_t)v;  // an integer within [l, u] (byte copies are kept only then)
+}
+
+__global__ __launch_bounds__(256) void k_stage_x(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                                                 double* __restrict__ dst, int8_t* __restrict__ xc, WalkState* st,
+                                                 uint32_t epoch, int32_t n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double v = src[perm ? perm[q] : q];
+  if (dst && dst != src) dst[q] = v;
+  if (xc) {
+    const bool fits = v == floor(v) && v >= -128.0 && v <= 127.0;
+    xc[q] = fits ? (int8_t)v : (int8_t)0;
+    if (!fits) st->x_misfit = epoch;  // every writer stores the same value
+  }
 }
 
 // f = c^T x and V = violated rows as grid reductions; the last workgroup
@@ -233,7 +257,7 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
                                                     double* partial, uint32_t* ticket, long long* objacc,
                                                     int64_t iters, int32_t tenure, int32_t obj_integral,
                                                     double cutoff_rhs, const float* cutoff_w,
-                                                    int32_t check_incumbent) {
+                                                    int32_t check_incumbent, int32_t need_obj, int32_t need_v) {
   __shared__ double redd[4];
   __shared__ long long redl[4];
   __shared__ long long lacc[kExactLimbs];
@@ -246,24 +270,45 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
     for (int t = threadIdx.x; t < kExactLimbs; t += blockDim.x) lacc[t] = 0;
     __syncthreads();
   }
+  // kU items per thread and step, every load issued before any is used
+  constexpr int kU = 4;
   double f = 0.0;
-  for (int j = gt; j < P.n; j += gs) {
-    const double c = P.obj[j];
-    if (c == 0.0) continue;
-    if (objacc) {
-      double p, e;
-      exact_product(c, x[j], p, e);
-      exact_atomic_add(lacc, p);
-      exact_atomic_add(lacc, e);
-    } else {
-      f += c * x[j];
+  const int n_obj = need_obj ? P.n : 0;
+  for (int j0 = gt; j0 < n_obj; j0 += kU * gs) {
+    double c[kU], xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * gs;
+      c[u] = j < n_obj ? P.obj[j] : 0.0;
+      xv[u] = j < n_obj ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (c[u] == 0.0) continue;
+      if (objacc) {
+        double p, e;
+        exact_product(c[u], xv[u], p, e);
+        exact_atomic_add(lacc, p);
+        exact_atomic_add(lacc, e);
+      } else {
+        f += c[u] * xv[u];
+      }
     }
   }
   long long v = 0;
-  for (int i = gt; i < P.ms; i += gs) {
-    const RowState q = rs[i];
-    v += (q.r > eps) ? 1 : 0;
-    if (q.w1 >= 0.0f && -q.r > eps) v += 1;
+  const int m_v = need_v ? P.ms : 0;
+  for (int i0 = gt; i0 < m_v; i0 += kU * gs) {
+    RowState q[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * gs;
+      q[u] = i < m_v ? rs[i] : RowState{0.0, 0.0f, -1.0f};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      v += (q[u].r > eps) ? 1 : 0;
+      if (q[u].w1 >= 0.0f && -q[u].r > eps) v += 1;
+    }
   }
   f = block_sum_d(f, redd);
   v = block_sum_ll(v, redl);
@@ -779,12 +824,14 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ perm
   if (q < n) dst[q] = src[perm[q]];
 }
 
-__global__ __launch_bounds__(256) void k_scatter2(const int32_t* __restrict__ perm, const double* __restrict__ a,
-                                                  const double* __restrict__ b, double* __restrict__ da,
-                                                  double* __restrict__ db, int32_t n) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const int j = perm[q];
+// da[j] = a[inv[j]], db[j] = b[inv[j]] (internal order -> caller's order),
+// written in the caller's order so that the stores are coalesced.
+__global__ __launch_bounds__(256) void k_gather2(const int32_t* __restrict__ inv, const double* __restrict__ a,
+                                                 const double* __restrict__ b, double* __restrict__ da,
+                                                 double* __restrict__ db, int32_t n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int q = inv[j];
   da[j] = a[q];
   db[j] = b[q];
 }
@@ -841,39 +888,52 @@ inline dim3 residual_grid(int32_t ms) {
 
 hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, hipStream_t stream) {
   if (P.ms > 0)
-    hipLaunchKernelGGL(k_residual<kWeightsKeep>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nullptr,
-                       nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_residual<kWeightsKeep>, residual_grid(P.ms), dim3(256), 0, stream, P, x, nullptr, nullptr,
+                       0u, rs, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, RowState* rs,
-                                GatherRow* grow, hipStream_t stream) {
+hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, const int8_t* xc,
+                                const WalkState* st, uint32_t epoch, RowState* rs, GatherRow* grow,
+                                hipStream_t stream) {
   if (P.ms > 0)
-    hipLaunchKernelGGL(k_residual<kWeightsUnit>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nullptr, pair,
-                       nullptr, grow);
+    hipLaunchKernelGGL(k_residual<kWeightsUnit>, residual_grid(P.ms), dim3(256), 0, stream, P, x, xc, st, epoch, rs,
+                       nullptr, pair, nullptr, grow);
   return hipGetLastError();
 }
 
 hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair, const float* w,
-                                   const double* x, RowState* rs, hipStream_t stream) {
+                                   const double* x, const int8_t* xc, const WalkState* st, uint32_t epoch,
+                                   RowState* rs, hipStream_t stream) {
   if (P.ms > 0)
-    hipLaunchKernelGGL(k_residual<kWeightsScatter>, residual_grid(P.ms), dim3(256), 0, stream, P, x, rs, nidx, pair,
-                       w, nullptr);
+    hipLaunchKernelGGL(k_residual<kWeightsScatter>, residual_grid(P.ms), dim3(256), 0, stream, P, x, xc, st, epoch,
+                       rs, nidx, pair, w, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, hipStream_t stream) {
-  if (P.n > 0) hipLaunchKernelGGL(k_start_point, dim3((P.n + 255) / 256), dim3(256), 0, stream, P, seed, x);
+hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, int8_t* xc, hipStream_t stream) {
+  if (P.n > 0) hipLaunchKernelGGL(k_start_point, dim3((P.n + 255) / 256), dim3(256), 0, stream, P, seed, x, xc);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_x(const int32_t* perm, const double* src, double* dst, int8_t* xc, WalkState* st,
+                          uint32_t epoch, int32_t n, hipStream_t stream) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_stage_x, dim3((n + 255) / 256), dim3(256), 0, stream, perm, src, dst, xc, st, epoch, n);
   return hipGetLastError();
 }
 
 hipError_t launch_state_init(const DevProblem& P, const double* x, const RowState* rs, WalkState* st,
                              double* partial, uint32_t* ticket, long long* objacc, int64_t iters, int32_t tenure,
                              int32_t obj_integral, double cutoff_rhs, const float* cutoff_w, int check_incumbent,
-                             hipStream_t stream) {
-  const int blocks = blocks_for((int64_t)(P.n > P.ms ? P.n : P.ms), kInitBlocks);
+                             int count_violated, hipStream_t stream) {
+  // a single pass needs neither V nor, without a cutoff row, f
+  const int32_t need_v = (check_incumbent || count_violated) ? 1 : 0;
+  const int32_t need_obj = (check_incumbent || std::isfinite(cutoff_rhs)) ? 1 : 0;
+  const int64_t work = std::max<int64_t>(need_obj ? P.n : 0, need_v ? P.ms : 0);
+  const int blocks = work > 0 ? blocks_for((work + 3) / 4, kInitBlocks) : 1;
   hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(256), 0, stream, P, x, rs, st, partial, ticket, objacc, iters,
-                     tenure, obj_integral, cutoff_rhs, cutoff_w, check_incumbent);
+                     tenure, obj_integral, cutoff_rhs, cutoff_w, check_incumbent, need_obj, need_v);
   return hipGetLastError();
 }
 
@@ -919,9 +979,9 @@ hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, in
   return hipGetLastError();
 }
 
-hipError_t launch_scatter2(const int32_t* perm, const double* a, const double* b, double* da, double* db, int32_t n,
-                           hipStream_t stream) {
-  if (n > 0) hipLaunchKernelGGL(k_scatter2, dim3((n + 255) / 256), dim3(256), 0, stream, perm, a, b, da, db, n);
+hipError_t launch_gather2(const int32_t* inv, const double* a, const double* b, double* da, double* db, int32_t n,
+                          hipStream_t stream) {
+  if (n > 0) hipLaunchKernelGGL(k_gather2, dim3((n + 255) / 256), dim3(256), 0, stream, inv, a, b, da, db, n);
   return hipGetLastError();
 }
 

@@ -98,3 +98,52 @@ def test_mixed_batch_staged_and_unstaged(chap):
     assert runs2[0].trace.tobytes() == runs2[1].trace.tobytes()
     assert runs2[2].trace.tobytes() == runs2[3].trace.tobytes()
     compare_runs(runs2[2], oracle.OracleProblem(base).tabu_run(40, 5, 10), "staged+unstaged walk 2")
+
+
+def test_byte_copy_of_x(chap):
+    """Instances whose variables are all integers with bounds in [-128, 127]
+    let residuals from scratch gather a byte copy of x. Points at the bounds
+    (the ends of the byte range, and a narrow domain whose columns take the
+    staged path) give passes and walks equal to the oracle."""
+    import torch
+
+    for lo, hi in ((-128.0, 127.0), (-20.0, 43.0)):
+        mip = mipgen.powerlaw(85, n=20_000, m=10_000, nnz=200_000, cap=3000)
+        mip.lb[:] = lo
+        mip.ub[:] = hi
+        P = oracle.OracleProblem(mip)
+        G = chap.Problem(mip)
+        w = mipgen.random_weights(P.mp + 1, 2, wmax=6)
+        wd = torch.from_numpy(w).cuda()
+        base = np.clip(mipgen.random_point(mip, 3), lo, hi)
+        j = np.arange(mip.n)
+        cases = [("random", base), ("lower bounds", np.full(mip.n, lo)), ("upper bounds", np.full(mip.n, hi)),
+                 ("mixed ends", np.where(j % 3 == 0, lo, np.where(j % 3 == 1, hi, base)))]
+        for name, x in cases:
+            say(f"best_shift byte copy [{lo}, {hi}]: {name}")
+            xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+            xh, s = G.best_shift(xd, wd)
+            torch.cuda.synchronize()
+            oxh, os_ = P.best_shift(x, w)
+            assert np.array_equal(s.cpu().numpy(), os_), name
+            assert np.array_equal(xh.cpu().numpy(), oxh), name
+        say(f"walk byte copy [{lo}, {hi}] from the upper bounds")
+        x0 = np.full(mip.n, hi)
+        compare_runs(G.tabu_run(30, 5, 0, x0=x0), P.tabu_run(30, 5, 0, x0=x0), f"x0 at {hi}")
+
+
+def test_start_point_validation(chap):
+    """A start point must lie within the bounds and be integral on integer
+    variables (CHAP_EINVAL otherwise)."""
+    mip = mipgen.random_mixed(86, n=30, m=20)
+    G = chap.Problem(mip)
+    ok = np.clip(np.zeros(mip.n), mip.lb, mip.ub)
+    G.tabu_run(3, 2, 0, x0=ok)
+    ints = np.flatnonzero(mip.is_int == 1)
+    bad_frac = ok.copy()
+    bad_frac[ints[0]] += 0.5
+    bad_high = ok.copy()
+    bad_high[0] = mip.ub[0] + 1.0
+    for bad in (bad_frac, bad_high):
+        with pytest.raises(chap.ChapError, match="CHAP_EINVAL"):
+            G.tabu_run(3, 2, 0, x0=bad)
