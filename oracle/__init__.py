@@ -62,6 +62,8 @@ def _load():
     lib.orc_objective.argtypes = [P, P]
     lib.orc_tabu_run.restype = i64
     lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P]
+    lib.orc_tabu_resume.restype = i64
+    lib.orc_tabu_resume.argtypes = [P, i64, i32, P, P, P, i64, i32, f64, P, f64, P, P, P, P, P, P, P, P]
     lib.orc_learned_replay.restype = i64
     lib.orc_learned_replay.argtypes = [P, i64, i32, u64, P, i32, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
@@ -164,6 +166,22 @@ class OracleProblem:
         assert offs.shape[0] == iters + 1
         return self._walk(iters, tenure, seed, x0, lambda *a: self._lib.orc_learned_replay(
             self.h, int(iters), int(tenure), int(seed), a[0], int(full_every), _p(sets), _p(offs), *a[1:]))
+
+    def tabu_resume(self, iters: int, tenure: int, x, w, tabu_until, k0: int, best_obj: float = float("inf"),
+                    best_x=None, cutoff_rhs: float = float("inf")):
+        """The plain walk continued for `iters` iterations from its state at the
+        start of iteration k0 (point x, weights w of m'+1 rows, last tabu
+        iteration of every variable, best feasible objective and point, cutoff
+        right-hand side); trace records k0 .. k0 + iters - 1."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        tb = np.ascontiguousarray(tabu_until, dtype=np.int64)
+        has = best_x is not None and np.isfinite(best_obj)
+        bx = np.ascontiguousarray(best_x if has else np.zeros(self.n), dtype=np.float64)
+        assert x.shape[0] == self.n and w.shape[0] == self.mp + 1 and tb.shape[0] == self.n
+        return self._walk(iters, tenure, 0, None, lambda *a: self._lib.orc_tabu_resume(
+            self.h, int(iters), int(tenure), _p(x), _p(w), _p(tb), int(k0), int(has),
+            float(best_obj) if has else 0.0, _p(bx), float(cutoff_rhs), *a[1:]))
 
     def tabu_run(self, iters: int, tenure: int, seed: int, x0=None):
         return self._walk(iters, tenure, seed, x0, lambda *a: self._lib.orc_tabu_run(

@@ -459,10 +459,23 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t index) { return splitmix64_outpu
 // sets[set_off[k] .. set_off[k+1]) (original indices) and chooses among them
 // with the same rules; without an admissible move there it is a stall (kind
 // 3: no move, no reweight). Moves chosen from a list get kind + 8.
+// The state of a walk at the start of iteration k0, to continue it from
+// there: weights (mp+1), the last tabu iteration of every variable, the best
+// feasible point and objective, the cutoff right-hand side (+inf: inactive).
+struct WalkResume {
+  const float* w;
+  const int64_t* tabu_until;
+  int64_t k0;
+  int32_t has_best;
+  double fbest;
+  const double* best_x;
+  double cutoff_rhs;
+};
+
 int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
                      int32_t full_every, const int32_t* sets, const int64_t* set_off, void* trace_out,
                      double* x_out, double* r_out, float* w_out, double* best_obj, double* best_x, int32_t* has_best,
-                     double* cutoff_rhs_out) {
+                     double* cutoff_rhs_out, const WalkResume* resume = nullptr) {
   const int32_t n = P.n;
   std::vector<double> x(n);
   if (x0)
@@ -476,6 +489,19 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
   bool found = false;
   bool cutoff = false;
   double bc = 0.0;
+  int64_t k0 = 0;
+  if (resume) {
+    w.assign(resume->w, resume->w + P.mp + 1);
+    tabu_until.assign(resume->tabu_until, resume->tabu_until + n);
+    k0 = resume->k0;
+    found = resume->has_best != 0;
+    if (found) {
+      fbest = resume->fbest;
+      xbest.assign(resume->best_x, resume->best_x + n);
+    }
+    cutoff = !std::isinf(resume->cutoff_rhs);
+    bc = cutoff ? resume->cutoff_rhs : 0.0;
+  }
   std::vector<double> r;
   std::vector<double> xhat(n), s(n);
   std::vector<int32_t> cands;
@@ -500,10 +526,10 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
   };
   incumbent_check();
 
-  int64_t k_last_full = 0;
+  int64_t k_last_full = k0;
   bool stalled = false;
-  for (int64_t k = 0; k < iters; ++k) {
-    const bool full = full_every <= 1 || k == 0 || stalled || k - k_last_full >= full_every;
+  for (int64_t k = k0; k < k0 + iters; ++k) {
+    const bool full = full_every <= 1 || k == k0 || stalled || k - k_last_full >= full_every;
     if (full) k_last_full = k;
     residual_from_scratch(P, x.data(), cutoff, bc, r);
     V = count_violated(P, r, cutoff);
@@ -544,7 +570,7 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
     }
     if (jstar >= 0 && !full) kind += 8;
     stalled = (jstar < 0 && !full);
-    TraceRec& t = trace[k];
+    TraceRec& t = trace[k - k0];
     t.iter = k;
     t.kind = kind;
     if (jstar < 0) {
@@ -591,6 +617,17 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
                      double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
   return learned_walk(*(OracleProblem*)h, iters, tenure, seed, x0, 1, nullptr, nullptr, trace_out, x_out, r_out,
                       w_out, best_obj, best_x, has_best, cutoff_rhs_out);
+}
+
+// The plain walk continued for `iters` iterations from a given state at the
+// start of iteration k0 (trace records k0 .. k0 + iters - 1).
+int64_t orc_tabu_resume(void* h, int64_t iters, int32_t tenure, const double* x, const float* w,
+                        const int64_t* tabu_until, int64_t k0, int32_t has_best_in, double fbest_in,
+                        const double* best_x_in, double cutoff_rhs_in, void* trace_out, double* x_out, double* r_out,
+                        float* w_out, double* best_obj, double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
+  const WalkResume R{w, tabu_until, k0, has_best_in, fbest_in, best_x_in, cutoff_rhs_in};
+  return learned_walk(*(OracleProblem*)h, iters, tenure, 0, x, 1, nullptr, nullptr, trace_out, x_out, r_out, w_out,
+                      best_obj, best_x, has_best, cutoff_rhs_out, &R);
 }
 
 // The learned proposal form of the walk, replaying the listed sets.

@@ -41,3 +41,12 @@ def normalised_weights(orig_row, sign, per_original_row_weights, cutoff_w=1.0):
     """Expand weights listed per normalised row (in normalised order) plus the cutoff."""
     return np.concatenate([np.asarray(per_original_row_weights, dtype=np.float32),
                            np.array([cutoff_w], dtype=np.float32)])
+
+
+def tabu_until_from_trace(trace, n, tenure):
+    """Last iteration through which each variable is tabu, from a walk's trace
+    (a variable moved at iteration k is tabu through k + tenure)."""
+    t = np.full(n, -1, dtype=np.int64)
+    moved = trace["var"] >= 0
+    t[trace["var"][moved]] = trace["iter"][moved] + tenure  # later moves overwrite earlier ones
+    return t

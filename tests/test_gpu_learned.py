@@ -249,3 +249,81 @@ def test_trained_network_gains_over_untrained(chap):
     say(f"gain: (hit rate, mean proposal-move score, final violations) {out}; plain final {vp}")
     assert out["trained"][0] >= 0.5 and out["trained"][0] >= out["untrained"][0] + 0.3, out
     assert out["trained"][1] > 1.2 * out["untrained"][1], out
+
+
+def test_learned_replay_full_size_paths(chap):
+    """The proposal paths the 20M-nonzero workload runs, at their full sizes:
+    a 2M-nonzero power-law instance (200k columns) whose proposable columns
+    include narrow columns far beyond one 2048-entry subset chunk and one
+    4096-entry refresh chunk, and general columns of 3500..4094 entries (the
+    largest that one workgroup's sort holds); top-K of 1024 over every
+    proposable column (all radix digits), a full evaluation every 16
+    iterations, online training. The walk replays in the oracle from its
+    logged proposal sets bit for bit, and one proposal set is checked to be a
+    valid top-K set of the reference network scores."""
+    mip = mipgen.powerlaw(0, n=200_000, m=100_000, nnz=2_000_000, cap=20_000)
+    # normalised entries per column (equality rows count twice)
+    is_e = (mip.sense == ord("E"))[mip.csc_row]
+    col_of = np.repeat(np.arange(mip.n), np.diff(mip.csc_col_ptr))
+    ne = np.bincount(col_of, weights=1.0 + is_e, minlength=mip.n).astype(np.int64) + (mip.obj != 0)
+    general = np.flatnonzero((ne >= 3500) & (ne + 2 <= 4096))[:6]
+    assert general.size >= 3
+    mip.ub[general] = 400.0   # wider than 64 values: general columns
+    P = oracle.OracleProblem(mip)
+    assert int(ne.max()) > 8192
+    G = chap.Problem(mip)
+    M = chap.Model(3)
+    iters, F_, K, seed = 96, 16, 1024, 1
+    say("learned full-size paths: walk")
+    run = chap.learned_run(G, M, iters, 10, seed, full_every=F_, topk=K, train_steps=2, train_pairs=256, lr=1e-3,
+                           log_sets=1)
+    say("learned full-size paths: oracle replay")
+    ref = P.learned_replay(iters, 10, seed, F_, run.sets, run.set_offsets)
+    compare_traces(run.trace, ref["trace"], "learned full-size")
+    np.testing.assert_array_equal(run.x, ref["x"])
+    np.testing.assert_array_equal(run.w, ref["w"])
+    kinds = run.trace["kind"]
+    prop_iters = np.flatnonzero(~np.isin(kinds, [0, 1, 2]))
+    assert prop_iters.size > 40 and (kinds >= 8).sum() > 20
+    sizes = [run.proposal_set(k).size for k in prop_iters]
+    assert min(sizes) == max(sizes) == K
+    moved_general = np.isin(run.trace["var"], general).sum() + sum(
+        np.isin(run.proposal_set(k), general).any() for k in prop_iters)
+    print(f"general columns moved or proposed: {moved_general}", flush=True)
+
+
+def test_learned_topk_valid_full_size(chap):
+    """One proposal set of a 200k-column walk with an untrained network and no
+    training (fixed parameters) is a valid top-1024 set of the reference scores
+    within the accumulation bound."""
+    mip = mipgen.powerlaw(0, n=200_000, m=100_000, nnz=2_000_000, cap=20_000)
+    G = chap.Problem(mip)
+    M = chap.Model(9)
+    params = M.get_params().astype(np.float64)
+    F_, K, iters, seed = 16, 1024, 8, 2
+    say("top-K validity at full size: walk")
+    run = chap.learned_run(G, M, iters, 10, seed, full_every=F_, topk=K, log_sets=1)
+    P = oracle.OracleProblem(mip)
+    kinds = run.trace["kind"]
+    kstar = 5
+    assert not np.isin(kinds[kstar], [0, 1, 2]) and kinds[kstar - 1] != 3
+    now = _state_at(P, kstar, F_, run.sets, run.set_offsets, seed)
+    at_full = _state_at(P, 0, F_, run.sets, run.set_offsets, seed)
+    after_full = _state_at(P, 1, F_, run.sets, run.set_offsets, seed)
+    xh, s_last = P.best_shift(at_full["x"], at_full["w"], at_full["cutoff_rhs"])
+    tr = run.trace[:kstar]
+    last_move = np.full(mip.n, -1024)
+    moves = np.zeros(mip.n, dtype=np.int64)
+    for k in np.flatnonzero(tr["var"] >= 0):
+        last_move[tr["var"][k]] = k
+        moves[tr["var"][k]] += 1
+    say("top-K validity at full size: reference inputs")
+    X, ok = F.inputs(mip, P, now["x"], now["w"], now["cutoff_rhs"], s_last, xh, last_move, moves, kstar, 0,
+                     refresh=(after_full["x"], after_full["w"], after_full["cutoff_rhs"]))
+    y, _ = mlp.forward(params, X, True)
+    ey, _ = mlp.forward_bound(params, X)
+    chosen = np.zeros(mip.n, dtype=bool)
+    chosen[run.proposal_set(kstar)] = True
+    assert not (chosen & ~ok).any()
+    assert chosen.sum() == min(K, ok.sum())
+    assert np.min((y + ey)[chosen]) >= np.max((y - ey)[ok & ~chosen])

@@ -285,6 +285,43 @@ def test_full_size_powerlaw(chap):
     compare_runs(G.tabu_run(3, 10, 0), P.tabu_run(3, 10, 0), "powerlaw full")
 
 
+@pytest.mark.slow
+def test_full_size_snapshot_parity(chap):
+    """The 20M-nonzero walk at iterations 1000, 5000 and 9999: the GPU walk's
+    state (point, weights, tabu list, incumbent, cutoff) is downloaded there;
+    every column's best shift at that state equals the oracle's, and the next
+    two GPU iterations equal the oracle walk continued from that state, bit
+    for bit."""
+    import torch
+
+    from helpers import tabu_until_from_trace
+
+    mip = mipgen.powerlaw(0)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    for k0 in (1000, 5000, 9999):
+        say(f"snapshot parity at iteration {k0}: GPU walk")
+        g = G.tabu_run(k0, 10, 0)
+        tb = tabu_until_from_trace(g.trace, mip.n, 10)
+        xd = torch.from_numpy(g.x).cuda()
+        wd = torch.from_numpy(g.w).cuda()
+        xh, s = G.best_shift(xd, wd, g.cutoff_rhs)
+        torch.cuda.synchronize()
+        say(f"snapshot parity at iteration {k0}: oracle best shift")
+        oxh, os_ = P.best_shift(g.x, g.w, g.cutoff_rhs)
+        assert_same(s.cpu().numpy(), os_, f"score at {k0}")
+        assert_same(xh.cpu().numpy(), oxh, f"shift at {k0}")
+        say(f"snapshot parity at iteration {k0}: next two iterations")
+        g2 = G.tabu_run(k0 + 2, 10, 0)
+        assert g2.trace[:k0].tobytes() == g.trace.tobytes()
+        o = P.tabu_resume(2, 10, g.x, g.w, tb, k0, g.best_obj, g.best_x, g.cutoff_rhs)
+        for f in ("iter", "var", "kind", "viol", "x_old", "x_new", "score", "obj"):
+            assert_same(g2.trace[f][k0:], o["trace"][f], f"trace.{f} after {k0}")
+        assert_same(g2.x, o["x"], f"x after {k0}")
+        assert_same(g2.resid, o["r"], f"resid after {k0}")
+        assert_same(g2.w, o["w"], f"w after {k0}")
+
+
 def test_best_shift_repeatable(chap):
     """Identical passes on one problem give identical results equal to the
     oracle (catches timing-dependent corruption in the pass kernels)."""

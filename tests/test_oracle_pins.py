@@ -24,7 +24,7 @@ import pytest
 import mipgen
 import oracle
 from exact import ExactProblem
-from helpers import make_mip, splitmix64_py
+from helpers import make_mip, splitmix64_py, tabu_until_from_trace
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -307,3 +307,21 @@ def test_generator_shapes():
         k2 = mip.csc_row.astype(np.int64) * mip.n + cols
         o1, o2 = np.argsort(k1), np.argsort(k2)
         assert np.array_equal(k1[o1], k2[o2]) and np.array_equal(mip.csr_val[o1], mip.csc_val[o2])
+
+
+@pytest.mark.parametrize("k0", [1, 17, 45])
+def test_resumed_walk_continues_the_walk(k0):
+    """A walk continued from its state at iteration k0 (point, weights, tabu
+    list, incumbent, cutoff) is the same walk: trace and final state equal the
+    uninterrupted walk's."""
+    for mip in list(_tiny_instances(8, seed0=700)) + [mipgen.random_mixed(9, n=60, m=40, integer_data=False)]:
+        P = oracle.OracleProblem(mip)
+        full = P.tabu_run(60, 3, 2)
+        head = P.tabu_run(k0, 3, 2)
+        tb = tabu_until_from_trace(head["trace"], mip.n, 3)
+        rest = P.tabu_resume(60 - k0, 3, head["x"], head["w"], tb, k0, head["best_obj"], head["best_x"],
+                             head["cutoff_rhs"])
+        assert rest["trace"].tobytes() == full["trace"][k0:].tobytes(), mip.name
+        for f in ("x", "r", "w"):
+            assert np.array_equal(rest[f], full[f]), (mip.name, f)
+        assert rest["best_obj"] == full["best_obj"] and rest["cutoff_rhs"] == full["cutoff_rhs"]
