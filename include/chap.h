@@ -35,6 +35,7 @@
 #ifndef CHAP_H
 #define CHAP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -151,6 +152,25 @@ int chap_problem_norm_row_map(const chap_problem *p, int32_t *orig_row, int8_t *
  */
 int chap_best_shift(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
                     double *d_shift, double *d_score, void *hip_stream);
+
+/*
+ * chap_best_shift_noalloc - chap_best_shift for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc. Same arguments, results and errors as
+ * chap_best_shift (results bit for bit equal); it calls no hipMalloc, hipFree
+ * or allocating routine, creates no graph, stream or event, and launches the
+ * pass kernels one by one on hip_stream. Every per-call buffer comes from one
+ * scratch array of chap_best_shift_noalloc_max_bytes() (64 MiB) per GPU,
+ * held by the library until the process ends and shared by every call on
+ * that GPU: calls that overlap on one GPU (any problem, any stream) race and
+ * must be serialised by the caller. The problem's device must be current.
+ * CHAP_EINVAL when the problem needs more scratch than that (the message
+ * says how much; about 25 bytes per variable, 24 per row and 8 per entry of
+ * the staged narrow columns), or on the checks of chap_best_shift.
+ */
+int chap_best_shift_noalloc(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
+                            double *d_shift, double *d_score, void *hip_stream);
+size_t chap_best_shift_noalloc_max_bytes(void);
 
 /*
  * chap_best_shift_pass_ms - duration of the best-shift kernels (the pass

@@ -69,6 +69,10 @@ def load_library():
     lib.chap_problem_norm_row_map.restype = ctypes.c_int
     lib.chap_best_shift.argtypes = [P, P, P, f64, P, P, P]
     lib.chap_best_shift.restype = ctypes.c_int
+    lib.chap_best_shift_noalloc.argtypes = [P, P, P, f64, P, P, P]
+    lib.chap_best_shift_noalloc.restype = ctypes.c_int
+    lib.chap_best_shift_noalloc_max_bytes.argtypes = []
+    lib.chap_best_shift_noalloc_max_bytes.restype = ctypes.c_size_t
     lib.chap_best_shift_pass_ms.argtypes = [P, ctypes.POINTER(f64)]
     lib.chap_best_shift_pass_ms.restype = ctypes.c_int
     lib.chap_tabu_run.argtypes = [P, i64, i32, u64, P, ctypes.POINTER(P), P]
@@ -297,6 +301,19 @@ class Problem:
         _check(load_library().chap_best_shift(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
                                               float(cutoff_rhs), ctypes.c_void_p(out_shift.data_ptr()),
                                               ctypes.c_void_p(out_score.data_ptr()), _stream_handle(stream)))
+        return out_shift, out_score
+
+    def best_shift_noalloc(self, x, w, out_shift, out_score, cutoff_rhs: float = math.inf, stream=None):
+        """chap_best_shift_noalloc into caller-provided device tensors (no
+        allocation anywhere on the call's path)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n
+        assert w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.numel() == self.mp + 1
+        for t in (out_shift, out_score):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.n
+        _check(load_library().chap_best_shift_noalloc(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()), float(cutoff_rhs),
+            ctypes.c_void_p(out_shift.data_ptr()), ctypes.c_void_p(out_score.data_ptr()), _stream_handle(stream)))
         return out_shift, out_score
 
     def last_pass_ms(self) -> float:
