@@ -641,18 +641,35 @@ __device__ __forceinline__ void chunk_task(const WalkCtx& C, int lb, ChunkSmem& 
     const gptr<const double> cval = gmem(P.col_val);
     int32_t ib = 0, ia = 0;
     int e = T.e_beg + tid;
+    // software pipeline: the next step's row indices and coefficients are in
+    // flight while this step's rows are gathered and binned
+    int ni0 = 0, ni1 = 0;
+    double na0 = 0.0, na1 = 0.0;
+    if (e < T.e_end) {
+      ni0 = __builtin_nontemporal_load(&crow[e]);
+      na0 = __builtin_nontemporal_load(&cval[e]);
+      if (e + 256 < T.e_end) {
+        ni1 = __builtin_nontemporal_load(&crow[e + 256]);
+        na1 = __builtin_nontemporal_load(&cval[e + 256]);
+      }
+    }
     for (; e < T.e_end; e += 512) {
       const bool two = e + 256 < T.e_end;
-      const int i0 = __builtin_nontemporal_load(&crow[e]);
-      const double a0 = __builtin_nontemporal_load(&cval[e]);
-      int i1 = i0;
-      double a1 = a0;
-      if (two) {
-        i1 = __builtin_nontemporal_load(&crow[e + 256]);
-        a1 = __builtin_nontemporal_load(&cval[e + 256]);
-      }
+      const int i0 = ni0;
+      const double a0 = na0;
+      const int i1 = two ? ni1 : i0;
+      const double a1 = two ? na1 : a0;
       const RowState r0 = rs[i0];
       const RowState r1 = rs[i1];
+      const int en = e + 512;
+      if (en < T.e_end) {
+        ni0 = __builtin_nontemporal_load(&crow[en]);
+        na0 = __builtin_nontemporal_load(&cval[en]);
+        if (en + 256 < T.e_end) {
+          ni1 = __builtin_nontemporal_load(&crow[en + 256]);
+          na1 = __builtin_nontemporal_load(&cval[en + 256]);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (u == 1 && !two) break;
@@ -818,6 +835,28 @@ __device__ __forceinline__ void add_row(bool ap, int d, V half, int k0, int W, V
   if (d != 0 && k >= 0 && k < W) atomicOr(cand, 1ull << k);
 }
 
+// add_row for a run of rows of one column: beta, alpha and the candidate
+// mask go to the caller's registers (flushed once per run), the delta to its
+// bin; deltas for bin 0 join beta, those beyond u (the sink bin, never read)
+// are dropped.
+template <typename V>
+__device__ __forceinline__ void add_row_run(bool ap, int d, V half, int k0, int W, V* bins, V& beta, V& alpha,
+                                            unsigned long long& cand) {
+  const int cs = (ap ? 4 : 1) + (d > 0 ? 1 : 0) - (d < 0 ? 1 : 0);
+  beta += (V)row_coef(kCoefBeta, cs) * half;
+  alpha += (V)row_coef(kCoefAlpha, cs) * half;
+  const V dl = (V)row_coef(kCoefDelta, cs) * half;
+  const int k = k0 + d;
+  const int kb = k + (ap ? 1 : 0);
+  if (dl != (V)0) {
+    if (k < 0)
+      beta += dl;
+    else if (k < W && kb < W)
+      atomicAdd(&bins[kb], dl);
+  }
+  if (d != 0 && k >= 0 && k < W) cand |= 1ull << k;
+}
+
 struct StageRec {
   bool ap, twin;
   int d0, d1, lc;
@@ -921,6 +960,20 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
       const int len = G.pre[sg + 1] - G.pre[sg];
       const int per = (len + tps - 1) / tps;
       const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
+      // a thread's run is sorted by column: beta, alpha and the candidate mask
+      // of the current column stay in registers until the column changes
+      int cur = -1, k0 = 0, W = 0;
+      V rb_ = 0, ra_ = 0;
+      unsigned long long rc_ = 0ull;
+      auto flush = [&]() {
+        if (cur < 0) return;
+        if (rb_ != zero) atomicAdd(&S.bins[cur][0], rb_);
+        if (ra_ != zero && k0 + 1 < W) atomicAdd(&S.bins[cur][k0 + 1], ra_);
+        if (rc_) atomicOr(&S.cand[cur], rc_);
+        rb_ = zero;
+        ra_ = zero;
+        rc_ = 0ull;
+      };
       for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
         uint64_t r[kRun];
 #pragma unroll
@@ -931,13 +984,19 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
           if (i0 + u < i1) {
             const int lc = (int)(r[u] & 0xFFu) - c0;
             if (lc < 0 || lc >= ncw) continue;
+            if (lc != cur) {
+              flush();
+              cur = lc;
+              k0 = S.k0[lc];
+              W = S.W[lc];
+            }
             const StageRec e = decode_rec(r[u], wts, rs);
-            const int k0 = S.k0[lc], W = S.W[lc];
-            add_row(e.ap, e.d0, stage_half(e.w0, zero), k0, W, S.bins[lc], &S.cand[lc]);
-            if (e.twin) add_row(!e.ap, e.d1, stage_half(e.w1, zero), k0, W, S.bins[lc], &S.cand[lc]);
+            add_row_run(e.ap, e.d0, stage_half(e.w0, zero), k0, W, S.bins[lc], rb_, ra_, rc_);
+            if (e.twin) add_row_run(!e.ap, e.d1, stage_half(e.w1, zero), k0, W, S.bins[lc], rb_, ra_, rc_);
           }
         }
       }
+      flush();
     }
     if (tid < ncw && st->cut_active) {
       const double c = gmem(P.obj)[T.q_begin + c0 + tid];
@@ -1267,14 +1326,7 @@ __device__ __forceinline__ void stage_short(const WalkCtx& C, const Rows& rs, bo
 // every entry of the slice becomes the record of the same index, and the
 // slice's single-entry columns (their entry lies in this block) are scored.
 template <typename Rows>
-__global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
-                                                    const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (C.st->k >= C.st->iters) return;
-  const StageRowTask T = C.plan.stage_rtasks[lb];
-  if (T.rb < 0) return;
-  __shared__ GatherRow rows[kStageRowBlock];
+__device__ __forceinline__ void stage_rows_body(const WalkCtx& C, const StageRowTask& T, GatherRow* rows) {
   const Rows rs = rows_of<Rows>(C);
   const bool wts = stage_weights<Rows>(C);
   const int r0 = T.rb * kStageRowBlock;
@@ -1391,6 +1443,28 @@ __global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ 
   }
 }
 
+// Single passes with caller weights (DualRows) choose the row source once
+// per workgroup from the walk state and run the specialised body, so the
+// kernel holds the registers of one row accessor, not of both.
+template <typename Rows>
+__global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
+                                                    const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  const StageRowTask T = C.plan.stage_rtasks[lb];
+  if (T.rb < 0) return;
+  __shared__ GatherRow rows[kStageRowBlock];
+  if constexpr (std::is_same<Rows, DualRows>::value) {
+    if (C.st->compact_rows)
+      stage_rows_body<CompactRows>(C, T, rows);
+    else
+      stage_rows_body<FullRows>(C, T, rows);
+  } else {
+    stage_rows_body<Rows>(C, T, rows);
+  }
+}
+
 // Workgroups of a walk over ntask scoring tasks: kXcds * ceil(ntask / kXcds)
 // of them, workgroup lb taking task (lb mod kXcds) * ceil(ntask / kXcds) +
 // lb / kXcds, so that each XCD scores a contiguous run of tasks (whose
@@ -1416,13 +1490,7 @@ union StageScoreSmem {
 };
 
 template <typename Rows>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(
-    const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off, int32_t nw) {
-  int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
-  if (C.st->k >= C.st->iters) return;
-  __shared__ StageScoreSmem sm;
-  __shared__ StageSegs G;
+__device__ __forceinline__ void stage_score_body(const WalkCtx& C, int lb, StageScoreSmem& sm, StageSegs& G) {
   const int32_t unit = gmem(C.plan.stage_units)[lb / kXcds];
   const int role = unit >> 28;
   const int rb = (unit & kStageUnitMask) * kXcds + lb % kXcds;
@@ -1444,6 +1512,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
   const int t = stage_task_of(rb, C.plan.n_stage_tasks - npk);
   if (t >= 0) stage_short<Rows>(C, rs, wts, npk + t, sm.sh, G);
+}
+
+template <typename Rows>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(
+    const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off, int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  if (C.st->k >= C.st->iters) return;
+  __shared__ StageScoreSmem sm;
+  __shared__ StageSegs G;
+  if constexpr (std::is_same<Rows, DualRows>::value) {
+    if (C.st->compact_rows)
+      stage_score_body<CompactRows>(C, lb, sm, G);
+    else
+      stage_score_body<FullRows>(C, lb, sm, G);
+  } else {
+    stage_score_body<Rows>(C, lb, sm, G);
+  }
 }
 
 // ---------------------------------------------------------------------------
