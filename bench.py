@@ -48,17 +48,47 @@ def algorithmic_bytes(mip, cutoff_active: bool) -> int:
     return 12 * nnz + 12 * mip.m + 4 * m_e + 48 * mip.n
 
 
-def cpu_baseline(mip, iters: int):
+def cpu_info():
+    """Host cores the oracle may use (the machine's CPU share: OMP_NUM_THREADS when
+    set, else every core up to 16), the core count and the CPU model."""
+    nproc = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, nproc)
+    return threads, nproc, model
+
+
+def cpu_baseline(mip, iters_single: int, iters_all: int):
+    """The oracle walk on the host: iters_single iterations on one core, then
+    iters_all iterations with its per-column and per-row loops on every core
+    the box gives this job (same results)."""
     import oracle
 
+    threads, nproc, model = cpu_info()
     P = oracle.OracleProblem(mip)
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    out = P.tabu_run(iters, 10, 0)
+    out1 = P.tabu_run(iters_single, 10, 0)
+    dt1 = time.perf_counter() - t0
+    used = oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    out = P.tabu_run(iters_all, 10, 0)
     dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} tabu iterations (tenure 10, seed 0) of the same 20M-nonzero instance, "
-                      f"single-threaded C++ oracle recomputing residuals and all best shifts each iteration; "
-                      f"{dt:.1f} s", "last_viol": int(out["trace"]["viol"][-1])}
+    oracle.set_threads(1)
+    assert out["trace"][:iters_single].tobytes() == out1["trace"].tobytes()
+    return {"value": iters_all / dt, "unit": "moves/s", "cores": used, "kind": "oracle",
+            "sample": f"{iters_all} tabu iterations (tenure 10, seed 0) of the same 20M-nonzero instance with "
+                      f"{used} threads ({dt:.1f} s), and {iters_single} on one core ({dt1:.1f} s); the oracle "
+                      f"recomputes every residual and every best shift each iteration",
+            "single_core_value": iters_single / dt1, "nproc": nproc, "cpu_model": model,
+            "last_viol": int(out["trace"]["viol"][-1])}
 
 
 def main():
@@ -67,7 +97,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--pass-reps", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations on one core")
+    ap.add_argument("--cpu-iters-all", type=int, default=24, help="oracle iterations on all cores")
+    ap.add_argument("--compare-iters", type=int, default=2000,
+                    help="length of the plain walk the learned forms are compared against")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--small", action="store_true", help="reduced instance for quick checks")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -182,63 +215,138 @@ def main():
                      "bytes_per_launch": B},
     }
     if not args.no_compare:
-        result["learned"] = compare_learned(chap, G, tr, wall, args.steps, tenure, seed)
+        result["learned"] = compare_learned(chap, G, args.compare_iters, tenure, seed)
         del G
         if not args.no_batched:
             result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small)
+        result["configs"] = small_configs(chap, tenure)
     if not args.no_cpu:
-        log(f"cpu baseline: {args.cpu_iters} oracle iterations")
-        result["cpu_baseline"] = cpu_baseline(mip, args.cpu_iters)
+        log(f"cpu baseline: {args.cpu_iters} oracle iterations on one core, {args.cpu_iters_all} on all")
+        result["cpu_baseline"] = cpu_baseline(mip, args.cpu_iters, args.cpu_iters_all)
     print(json.dumps(result), flush=True)
 
 
-def compare_learned(chap, G, plain_trace, plain_wall, steps, tenure, seed):
-    """Learned proposal against the plain walk on the same instance and start
-    point: violation reduction per second at equal final score. The network
-    is trained beforehand (not timed) on pairs logged by a plain walk from
-    another start point (seed + 7)."""
+def heuristic_params():
+    """Parameters of a hand-set network that outputs input 3, the last exact
+    score of the column per unit of its row weight (clamped to [-4, 4]), as
+    relu(relu(x3)) - relu(relu(-x3)) (exact in bfloat16). Its top-K set is the
+    K columns that scored best at the last full evaluation: the heuristic
+    top-k baseline."""
+    p = np.zeros(5313, dtype=np.float32)
+    w1, b1, w2, b2, w3 = 0, 1024, 1088, 1088 + 4096, 1088 + 4096 + 64
+    p[w1 + 0 * 16 + 3] = 1.0
+    p[w1 + 1 * 16 + 3] = -1.0
+    p[w2 + 0 * 64 + 0] = 1.0
+    p[w2 + 1 * 64 + 1] = 1.0
+    p[w3 + 0] = 1.0
+    p[w3 + 1] = -1.0
+    assert b1 == 1024 and b2 == 5184 and w3 + 64 == 5312
+    return p
+
+
+def compare_learned(chap, G, iters, tenure, seed):
+    """The learned proposal against the plain walk on the same instance and
+    start point: violation reduction per second at equal final score. The
+    plain walk runs `iters` iterations; each proposal form runs until it
+    reaches the plain walk's final violation count (at most 2 iters), and
+    the time to get there is measured by a second run of exactly that many
+    iterations. Forms: a network trained offline on pairs logged by a plain
+    walk from another start point (seed + 7), the same network untrained,
+    the heuristic top-k (hand-set network ranking by the last exact score),
+    an untrained network trained online during the walk, and the trained and
+    heuristic forms with a proposal set kept for 8 proposal iterations."""
     import torch
 
-    v0 = int(plain_trace["viol"][0])
-    vp = int(plain_trace["viol"][-1])
+    chap.learned_run(G, chap.Model(0), 64, tenure, seed, full_every=64, topk=1024)   # warm-up
+    G.tabu_run(iters, tenure, seed)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    M = chap.Model(0)
-    logrun = chap.learned_run(G, M, 100, tenure, seed + 7, full_every=1, topk=1024, train_pairs=1024,
+    plain = G.tabu_run(iters, tenure, seed)
+    torch.cuda.synchronize()
+    pwall = time.perf_counter() - t0
+    v0 = int(plain.trace["viol"][0])
+    vp = int(plain.trace["viol"][-1])
+    t0 = time.perf_counter()
+    trained = chap.Model(0)
+    logrun = chap.learned_run(G, trained, 100, tenure, seed + 7, full_every=1, topk=1024, train_pairs=1024,
                               log_pairs=100 * 2048)
     feat = torch.from_numpy(logrun.pair_feat.view(np.int16)).cuda()
     tgt = torch.from_numpy(logrun.pair_target).cuda()
-    M.train(feat, tgt, steps=1000, batch=1024, lr=1e-3, seed=1)
+    trained.train(feat, tgt, steps=1000, batch=1024, lr=1e-3, seed=1)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    opts = dict(full_every=64, topk=1024)
-    chap.learned_run(G, M, 64, tenure, seed, **opts)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run = chap.learned_run(G, M, steps, tenure, seed, **opts)
-    torch.cuda.synchronize()
-    lwall = time.perf_counter() - t0
-    viol = run.trace["viol"]
-    reach = np.flatnonzero(viol <= vp)
-    out = {"instance": "the same 20M-nonzero instance and start point", "iters": steps,
-           "options": dict(opts, train_steps=0), "ms_per_iter": lwall * 1e3 / steps,
-           "plain_ms_per_iter": plain_wall * 1e3 / steps, "final_viol": int(viol[-1]), "plain_final_viol": vp,
-           "judge_hits": run.hits, "judge_evals": run.evals, "stalls": run.stalls,
-           "training": f"1000 Adam steps (batch 1024, lr 1e-3) on {logrun.pair_target.shape[0]} pairs from 100 "
-                       f"full evaluations of a plain walk from seed {seed + 7}; {train_s:.1f} s, not timed"}
-    if reach.size:
-        it = int(reach[0]) + 1
-        t0 = time.perf_counter()
-        again = chap.learned_run(G, M, it, tenure, seed, **opts)
+    heur = chap.Model(0)
+    heur.set_params(heuristic_params())
+    forms = [("trained", trained, {}), ("untrained", chap.Model(0), {}), ("heuristic_topk", heur, {}),
+             ("online", chap.Model(0), dict(train_steps=4, train_pairs=512, lr=1e-3)),
+             ("trained_refresh8", trained, dict(refresh_every=8)),
+             ("heuristic_topk_refresh8", heur, dict(refresh_every=8))]
+    out = {"instance": "the same 20M-nonzero instance and start point", "plain_iters": iters,
+           "plain_seconds": pwall, "plain_ms_per_iter": pwall * 1e3 / iters, "plain_final_viol": vp,
+           "options": dict(full_every=64, topk=1024),
+           "training": f"offline: 1000 Adam steps (batch 1024, lr 1e-3) on {logrun.pair_target.shape[0]} pairs from "
+                       f"100 full evaluations of a plain walk from seed {seed + 7}; {train_s:.1f} s, not timed; "
+                       f"online: 4 Adam steps on 512 pairs at every full evaluation, timed"}
+    for name, M, extra in forms:
+        opts = dict(full_every=64, topk=1024, **extra)
+        probe = chap.learned_run(G, M if name != "online" else chap.Model(0), 2 * iters, tenure, seed, **opts)
+        viol = probe.trace["viol"]
+        reach = np.flatnonzero(viol <= vp)
+        rec = {"final_viol_at_2x": int(viol[-1]), "judge_hits": probe.hits, "judge_evals": probe.evals,
+               "stalls": probe.stalls}
+        if reach.size:
+            it = int(reach[0]) + 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            again = chap.learned_run(G, M if name != "online" else chap.Model(0), it, tenure, seed, **opts)
+            torch.cuda.synchronize()
+            treach = time.perf_counter() - t0
+            assert int(again.trace["viol"][-1]) <= vp
+            rec.update({"iters_to_plain_final": it, "seconds_to_plain_final": treach,
+                        "ms_per_iter": treach * 1e3 / it,
+                        "violation_reduction_per_s": (v0 - vp) / treach,
+                        "speedup_at_equal_final_score": pwall / treach})
+        else:
+            rec.update({"iters_to_plain_final": None, "speedup_at_equal_final_score": None})
+        out[name] = rec
+        log(f"learned {name}: reaches plain final at {rec['iters_to_plain_final']}, "
+            f"speedup {rec['speedup_at_equal_final_score']}")
+    out["plain_violation_reduction_per_s"] = (v0 - vp) / pwall
+    return out
+
+
+def small_configs(chap, tenure):
+    """Configurations 1 and 2: iterations per second of the walk and the
+    best-shift pass time (HIP events), with nonzeros per second."""
+    import torch
+
+    import mipgen
+
+    out = {}
+    for name, mip, iters in (("tiny_binary n=200 m=100 (1000 iterations)", mipgen.tiny_binary(0), 1000),
+                             ("general n=100k m=50k (10000 iterations)", mipgen.general(0), 10000)):
+        G = chap.Problem(mip)
+        G.tabu_run(iters, tenure, 0)
         torch.cuda.synchronize()
-        treach = time.perf_counter() - t0
-        assert int(again.trace["viol"][-1]) <= vp
-        out.update({"iters_to_plain_final": it, "seconds_to_plain_final": treach, "plain_seconds": plain_wall,
-                    "violation_reduction_per_s": {"plain": (v0 - vp) / plain_wall, "learned": (v0 - vp) / treach},
-                    "speedup_at_equal_final_score": plain_wall / treach})
-    else:
-        out.update({"iters_to_plain_final": None, "speedup_at_equal_final_score": None})
-    log(f"learned: {out['ms_per_iter']:.3f} ms/iter, reaches plain final at {out['iters_to_plain_final']}, "
-        f"speedup {out['speedup_at_equal_final_score']}")
+        t0 = time.perf_counter()
+        run = G.tabu_run(iters, tenure, 0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        xd = torch.from_numpy(run.x).cuda()
+        wd = torch.from_numpy(run.w).cuda()
+        ox, os_ = torch.empty_like(xd), torch.empty_like(xd)
+        times = []
+        for _ in range(23):
+            G.best_shift(xd, wd, run.cutoff_rhs, ox, os_)
+            times.append(G.last_pass_ms())
+        pass_ms = float(np.mean(times[3:]))
+        nnz = mip.nnz + (mip.nnz_obj if math.isfinite(run.cutoff_rhs) else 0)
+        out[name] = {"iters_per_s": iters / wall, "ms_per_iter": wall * 1e3 / iters,
+                     "graph_ms_per_iter": run.elapsed_ms / iters, "best_shift_pass_us": pass_ms * 1e3,
+                     "best_shift_nnz_per_s": nnz / (pass_ms * 1e-3),
+                     "final_viol": int(run.trace["viol"][-1]), "best_obj": run.best_obj}
+        log(f"{name}: {iters / wall:.0f} it/s, pass {pass_ms * 1e3:.1f} us")
+        del G
     return out
 
 

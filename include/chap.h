@@ -395,6 +395,13 @@ typedef struct {
   int32_t log_sets;    /* 1: keep every proposal set in the run */
   int64_t log_pairs;   /* capacity of the pair log (pairs); default 0 */
   uint64_t train_seed; /* seed of the random training pairs; default 0 */
+  int32_t refresh_every; /* proposal iterations per proposal set: the
+                            network scores every column and a new set is
+                            chosen at the first proposal iteration of a
+                            block and every refresh_every proposal
+                            iterations after it; the iterations between
+                            evaluate the same set exactly at their own
+                            point. Default 1 (a new set every iteration) */
 } chap_learned_options;
 
 void chap_learned_options_default(chap_learned_options *opt);
@@ -402,8 +409,8 @@ void chap_learned_options_default(chap_learned_options *opt);
 /* One learned walk with model m (same device as p; trained in place when
  * train_steps > 0). Start point, seed, tenure and iters as chap_tabu_run;
  * opt may be NULL for the defaults. Synchronous; *out as chap_tabu_run.
- * CHAP_EINVAL on invalid options (topk, full_every, train_pairs <= 0,
- * lr <= 0, train_steps < 0). */
+ * CHAP_EINVAL on invalid options (topk, full_every, train_pairs,
+ * refresh_every <= 0, lr <= 0, train_steps < 0). */
 int chap_learned_run(chap_problem *p, chap_model *m, const chap_learned_options *opt,
                      int64_t iters, int32_t tenure, uint64_t seed, const double *x0,
                      chap_run **out, void *hip_stream);

@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.cpp with g++ (IEEE FP64, no contraction, no fast-math)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                SRC, "-o", tmp]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB)
@@ -56,6 +56,11 @@ def _load():
     lib.orc_start_point.argtypes = [P, u64, P]
     lib.orc_splitmix64.restype = u64
     lib.orc_splitmix64.argtypes = [u64, u64]
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_set_threads.restype = None
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = i32
+    lib.orc_set_threads(1)
     lib.orc_exact_sum.restype = f64
     lib.orc_exact_sum.argtypes = [P, i64]
     lib.orc_objective.restype = f64
@@ -76,6 +81,14 @@ def _p(a: np.ndarray):
 
 def splitmix64(seed: int, index: int) -> int:
     return int(_load().orc_splitmix64(seed, index))
+
+
+def set_threads(k: int) -> int:
+    """Threads of the oracle's per-column and per-row loops (results do not
+    depend on it); returns the count in effect."""
+    lib = _load()
+    lib.orc_set_threads(int(k))
+    return int(lib.orc_threads())
 
 
 def exact_sum(values) -> float:

@@ -25,7 +25,10 @@
 // Feasibility tolerance eps: a normalised row is violated iff r_i > eps, and
 // the breakpoint of row i on variable j is tau = xbar_j + (eps - r_i)/a_ij.
 //
-// Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no fast-math).
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -fPIC -shared (no
+// fast-math). Threads (orc_set_threads, default 1) only split the
+// independent per-column best shifts and per-row residuals of a full
+// evaluation across cores; every value is computed exactly as with one.
 
 #include <algorithm>
 #include <cmath>
@@ -33,6 +36,8 @@
 #include <cstring>
 #include <limits>
 #include <vector>
+
+#include <omp.h>
 
 namespace {
 
@@ -258,6 +263,7 @@ std::vector<double> objective_terms(const OracleProblem& P, const double* x) {
 void residual_from_scratch(const OracleProblem& P, const double* x, bool cutoff_active, double bc,
                            std::vector<double>& r) {
   r.assign((size_t)P.mp + 1, 0.0);
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < P.mp; ++i) {
     double acc = 0.0;
     for (int64_t k = P.rptr[i]; k < P.rptr[i + 1]; ++k) {
@@ -434,12 +440,18 @@ void orc_best_shift(void* h, const double* x, const float* w, double cutoff_rhs,
   std::vector<double> r;
   residual_from_scratch(*P, x, active, cutoff_rhs, r);
   if (cols == nullptr) {
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int32_t j = 0; j < P->n; ++j) best_shift_one(*P, j, x, r, w, active, &xhat[j], &s[j]);
   } else {
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t q = 0; q < ncols; ++q)
       best_shift_one(*P, cols[q], x, r, w, active, &xhat[q], &s[q]);
   }
 }
+
+// Threads of the per-column and per-row loops (1 = sequential).
+void orc_set_threads(int32_t k) { omp_set_num_threads(k > 0 ? k : 1); }
+int32_t orc_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 // Exactly rounded sum of n doubles (the summation used for the objective).
 double orc_exact_sum(const double* v, int64_t n) { return exact_sum(std::vector<double>(v, v + n)); }
@@ -539,7 +551,12 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
     } else {
       for (int64_t t = set_off[k]; t < set_off[k + 1]; ++t) cands.push_back(sets[t]);
     }
-    for (int32_t j : cands) best_shift_one(P, j, x.data(), r, w.data(), cutoff, &xhat[j], &s[j]);
+    const int64_t nc = (int64_t)cands.size();
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t t = 0; t < nc; ++t) {
+      const int32_t j = cands[t];
+      best_shift_one(P, j, x.data(), r, w.data(), cutoff, &xhat[j], &s[j]);
+    }
     int32_t j_all = -1, j_nt = -1;
     for (int32_t j : cands) {
       if (!(s[j] > 0.0)) continue;

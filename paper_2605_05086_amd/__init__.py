@@ -33,7 +33,8 @@ class ChapOptions(ctypes.Structure):
 class LearnedOptions(ctypes.Structure):
     _fields_ = [("topk", ctypes.c_int32), ("full_every", ctypes.c_int32), ("train_steps", ctypes.c_int32),
                 ("train_pairs", ctypes.c_int32), ("lr", ctypes.c_float), ("log_sets", ctypes.c_int32),
-                ("log_pairs", ctypes.c_int64), ("train_seed", ctypes.c_uint64)]
+                ("log_pairs", ctypes.c_int64), ("train_seed", ctypes.c_uint64),
+                ("refresh_every", ctypes.c_int32)]
 
 
 class ChapError(RuntimeError):

@@ -15,7 +15,7 @@ namespace {
 
 int check_options(const chap_learned_options& o) {
   if (o.topk <= 0 || o.full_every <= 0 || o.train_steps < 0 || o.train_pairs <= 0 || !(o.lr > 0.0f) ||
-      !std::isfinite(o.lr) || o.log_pairs < 0)
+      !std::isfinite(o.lr) || o.log_pairs < 0 || o.refresh_every <= 0)
     return fail(CHAP_EINVAL, "chap_learned_run: invalid options");
   if (o.topk > kTopkMax || o.train_pairs > kTopkMax)
     return fail(CHAP_EINVAL, "chap_learned_run: topk and train_pairs must be at most " + std::to_string(kTopkMax));
@@ -129,9 +129,17 @@ hipError_t capture_block(const BatchLaunch& BL, const WalkCtx* C, const LearnCtx
   if (e == hipSuccess) e = launch_walk_apply(BL, s);
   if (e == hipSuccess) e = launch_walk_finish(BL, s);
   if (e == hipSuccess) e = launch_learn_refresh(C, L, Lh, s);
-  // proposal iterations
+  // proposal iterations: a new set from the network every refresh_every of
+  // them (the scoring kernel also copies a pending incumbent); otherwise the
+  // last set is logged again and the pending copy runs on its own
   for (int32_t t = 1; t < o.full_every && e == hipSuccess; ++t) {
-    if (Lh.n_elig > 0) e = launch_learn_propose(C, L, Lh, M, n, 0, s);
+    const bool fresh = (t - 1) % o.refresh_every == 0;
+    if (Lh.n_elig > 0 && fresh) {
+      e = launch_learn_propose(C, L, Lh, M, n, 0, s);
+    } else {
+      e = launch_copy_best_batch(BL, s);
+      if (e == hipSuccess && Lh.n_elig > 0) e = launch_learn_keep_set(C, L, s);
+    }
     if (e == hipSuccess && Lh.n_elig > 0) e = launch_subset_pass(C, L, Lh, has_general, BL.compact, s);
     if (e == hipSuccess) e = launch_subset_select(C, L, s);
     if (e == hipSuccess) e = launch_walk_apply(BL, s);
@@ -154,6 +162,7 @@ void chap_learned_options_default(chap_learned_options* o) {
   o->log_sets = 0;
   o->log_pairs = 0;
   o->train_seed = 0;
+  o->refresh_every = 1;
 }
 
 int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options* opt, int64_t iters, int32_t tenure,

@@ -603,6 +603,8 @@ hipError_t launch_learn_propose(const WalkCtx* C, const LearnCtx* L, const Learn
 // network update.
 hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, const ModelDev& M,
                               int32_t n, int32_t steps, float lr, hipStream_t s);
+// A proposal iteration that keeps the last proposal set (logs it again).
+hipError_t launch_learn_keep_set(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
 // Judge of a full evaluation and the stored-row update of its move.
 hipError_t launch_learn_judge(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
 // Materialised inputs of every column at the walk's state (original order).

@@ -570,6 +570,33 @@ __global__ __launch_bounds__(256) void k_topk_write(const WalkCtx* __restrict__ 
   }
 }
 
+// Appends the c2 first columns of the proposal set to the set log as the set
+// of the current iteration (one workgroup; no-op without the log).
+__device__ void log_set(const WalkCtx& C, const LearnCtx& L, int c2) {
+  if (L.set_off == nullptr) return;
+  const int64_t k = C.st->k;
+  const int64_t pos = L.ls->set_pos;
+  const bool fits = pos + c2 <= L.set_log_cap;
+  if (fits)
+    for (int i = threadIdx.x; i < c2; i += blockDim.x) L.set_log[pos + i] = C.P.perm[L.sel[0][i]];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t end = fits ? pos + c2 : pos;
+    L.set_off[k] = pos;
+    L.set_off[k + 1] = end;
+    L.ls->set_pos = end;
+  }
+}
+
+// A proposal iteration that keeps the last proposal set: logs it again.
+__global__ __launch_bounds__(256) void k_keep_set(const WalkCtx* __restrict__ walks,
+                                                  const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  if (!active(C.st, L.ls)) return;
+  log_set(C, L, L.ls->tk[0].count);
+}
+
 // End of a selection (one workgroup): the selected count; for the proposal
 // set also the subset-pass chunk offsets and the set log; then clears the
 // histograms for the next selection.
@@ -617,21 +644,7 @@ __global__ __launch_bounds__(256) void k_topk_finish(const WalkCtx* __restrict__
       L.ls->tk[0].chunks = carry;
     }
     // proposal-set log (original indices); a full evaluation records an empty range
-    if (L.set_off != nullptr) {
-      const int64_t k = st->k;
-      const int64_t pos = L.ls->set_pos;
-      const int c2 = full ? 0 : cnt;
-      const bool fits = pos + c2 <= L.set_log_cap;
-      if (fits)
-        for (int i = threadIdx.x; i < c2; i += blockDim.x) L.set_log[pos + i] = C.P.perm[L.sel[0][i]];
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const int64_t end = fits ? pos + c2 : pos;
-        L.set_off[k] = pos;
-        L.set_off[k + 1] = end;
-        L.ls->set_pos = end;
-      }
-    }
+    log_set(C, L, full ? 0 : cnt);
   }
   if (threadIdx.x == 0) L.ls->tk[which].count = cnt;
   // every reader of the histograms has finished (earlier kernels, derive above)
@@ -795,6 +808,11 @@ hipError_t launch_learn_train(const WalkCtx* C, const LearnCtx* L, const LearnCt
     e = launch_mlp_reduce_guarded(M, &Lh.ls->train_active, 2 * (int64_t)Lh.T, lr, s);
     if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_learn_keep_set(const WalkCtx* C, const LearnCtx* L, hipStream_t s) {
+  hipLaunchKernelGGL(k_keep_set, dim3(1), dim3(256), 0, s, C, L);
   return hipGetLastError();
 }
 

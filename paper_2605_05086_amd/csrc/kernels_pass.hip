@@ -1675,6 +1675,143 @@ __device__ __forceinline__ void scan_argmax(PosT pos, MarkT mk, DelT dl, int cap
   bestp = found ? pos[bk] : xb;
 }
 
+// General columns with at most 64 breakpoint slots: one wavefront per column
+// (four per workgroup), one slot per lane. Phase 1 emits the entries into
+// the wavefront's LDS slots by a ballot prefix count, the bitonic sort runs
+// across lanes with exchanges between partner lanes (no barriers), then a
+// wavefront scan and argmax.
+struct WaveSortSmem {
+  double pos[4][kWave];
+  double del[4][kWave];
+  int32_t mk[4][kWave];
+};
+
+// Inclusive prefix sum across the wavefront.
+__device__ __forceinline__ double wave_inclusive(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                                   int32_t nw) {
+  int lb;
+  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const DevProblem& P = C.P;
+  const WalkState* st = C.st;
+  if (st->k >= st->iters) return;
+  __shared__ WaveSortSmem S;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+  const int j = C.plan.sort_begin[0] + lb * 4 + wv;
+  if (j >= C.plan.sort_begin[1]) return;  // whole wavefronts leave together
+  const Rows rs = rows_of<Rows>(C);
+  const double eps = P.eps;
+  const double xb = gmem((const double*)C.x)[j];
+  const bool isint = P.is_int[j] != 0;
+  const int beg = P.col_ptr[j], end = P.col_ptr[j + 1];
+  double beta = 0.0, alpha = 0.0;
+  // up to two entries per lane (a row and its twin), lane 0 adds the bounds
+  // and the cutoff row; the class guarantees at most 64 in all
+  BkEntry en[2];
+  int ne = 0;
+  const int e = beg + lane;
+  if (e < end) {
+    const RowState q = rs[P.col_row[e]];
+    const double a = P.col_val[e];
+    en[0] = phase1(xb, q.r, a, (double)q.w0, eps, isint, beta, alpha);
+    if (en[0].has) ne = 1;
+    if (q.w1 >= 0.0f) {
+      const BkEntry b1 = phase1(xb, -q.r, -a, (double)q.w1, eps, isint, beta, alpha);
+      if (b1.has) en[ne++] = b1;
+    }
+  }
+  BkEntry ex[3];
+  int nx = 0;
+  if (lane == 0) {
+    const double l = P.lb[j], u = P.ub[j];
+    if (isfinite(l)) ex[nx++] = BkEntry{l, 0.0, -1, true};
+    if (isfinite(u)) ex[nx++] = BkEntry{u, 0.0, -1, true};
+    if (st->cut_active) {
+      const double c = P.obj[j];
+      if (c != 0.0) {
+        const BkEntry b2 = phase1(xb, st->rc, c, (double)st->wc, eps, isint, beta, alpha);
+        if (b2.has) ex[nx++] = b2;
+      }
+    }
+  }
+  // slot of each lane's first entry: exclusive prefix count of entries
+  const int cnt_lane = ne + nx;
+  int incl = cnt_lane;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, kWave - 1, kWave);
+  int slot = incl - cnt_lane;
+  for (int k = 0; k < ne; ++k, ++slot) {
+    S.pos[wv][slot] = en[k].t + 0.0;
+    S.mk[wv][slot] = en[k].marker;
+    S.del[wv][slot] = en[k].delta;
+  }
+  for (int k = 0; k < nx; ++k, ++slot) {
+    S.pos[wv][slot] = ex[k].t + 0.0;
+    S.mk[wv][slot] = ex[k].marker;
+    S.del[wv][slot] = ex[k].delta;
+  }
+  // the slots written by other lanes of this wavefront become visible
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double p = HUGE_VAL, d = 0.0;
+  int m = kPadMarker;
+  if (lane < total) {
+    p = S.pos[wv][lane];
+    m = S.mk[wv][lane];
+    d = S.del[wv][lane];
+  }
+  // bitonic sort of (position, marker) across the lanes; both lanes of a
+  // pair take the same decision from the lower lane's point of view
+#pragma unroll
+  for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const double po = __shfl_xor(p, stride, kWave);
+      const int mo = __shfl_xor(m, stride, kWave);
+      const double dlo = __shfl_xor(d, stride, kWave);
+      const bool lower = (lane & stride) == 0;
+      const bool up = (lane & size) == 0;
+      const double pl = lower ? p : po, ph = lower ? po : p;
+      const int ml = lower ? m : mo, mh = lower ? mo : m;
+      const bool swap = up ? key_greater(pl, ml, ph, mh) : key_greater(ph, mh, pl, ml);
+      if (swap) {
+        p = po;
+        m = mo;
+        d = dlo;
+      }
+    }
+  }
+  beta = wave_sum(beta);
+  alpha = wave_sum(alpha);
+  const double inc = wave_inclusive(d, lane);
+  const double prefix = inc - d;
+  double bv = -DBL_MAX;
+  int bk = INT_MAX;
+  const double l = P.lb[j], u = P.ub[j];
+  if (m != kPadMarker && isfinite(p) && p >= l && p <= u && p != xb) {
+    bv = beta + ((m < 0) ? inc : prefix) + ((p > xb) ? alpha : 0.0);
+    bk = lane;
+  }
+  wave_argmax(bv, bk);
+  const bool found = bk != INT_MAX;
+  const double bestp = __shfl(p, found ? bk : 0, kWave);
+  if (lane == 0) write_result(C.xhat, C.s, j, found, bv, found ? bestp : xb, xb);
+}
+
 template <int CAP, typename Rows>
 __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                     int32_t nw) {
@@ -1999,7 +2136,8 @@ int32_t kernel_blocks(const WalkCtx& c, int slot) {
     case KS_APPLY: return c.apply_blocks;
     case KS_FINISH: return 1;
     default:
-      if (slot >= KS_SORT0 && slot < KS_SORT0 + kSortCaps)
+      if (slot == KS_SORT0) return (p.sort_begin[1] - p.sort_begin[0] + 3) / 4;  // a wavefront per column
+      if (slot > KS_SORT0 && slot < KS_SORT0 + kSortCaps)
         return p.sort_begin[slot - KS_SORT0 + 1] - p.sort_begin[slot - KS_SORT0];
       return 0;
   }
@@ -2087,7 +2225,7 @@ hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const Pass
   if (L.total[KS_PACK] > 0)
     CHAP_LAUNCH(k_narrow_pack<Rows>, grid(KS_PACK), dim3(256), 0, stream, L.walks, L.off[KS_PACK], nw);
   if (L.total[KS_SORT0] > 0)
-    CHAP_LAUNCH((k_sort_block<64, Rows>), grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
+    CHAP_LAUNCH(k_sort_wave<Rows>, grid(KS_SORT0), dim3(256), 0, stream, L.walks, L.off[KS_SORT0], nw);
   if (L.total[KS_SORT0 + 1] > 0)
     CHAP_LAUNCH((k_sort_block<256, Rows>), grid(KS_SORT0 + 1), dim3(256), 0, stream, L.walks,
                        L.off[KS_SORT0 + 1], nw);

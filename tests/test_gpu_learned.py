@@ -105,22 +105,24 @@ def test_full_every_one_is_plain(chap):
 
 
 CASES = [
-    # (generator seed, n, m, iters, full_every, topk, train_steps)
-    (420, 200, 150, 400, 8, 16, 0),
-    (421, 300, 200, 500, 16, 32, 2),
-    (422, 120, 100, 300, 4, 8, 1),
+    # (generator seed, n, m, iters, full_every, topk, train_steps, refresh_every)
+    (420, 200, 150, 400, 8, 16, 0, 1),
+    (421, 300, 200, 500, 16, 32, 2, 1),
+    (422, 120, 100, 300, 4, 8, 1, 1),
+    (423, 300, 200, 500, 16, 32, 1, 4),
+    (424, 200, 150, 400, 32, 16, 0, 7),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"seed{c[0]}-F{c[4]}-K{c[5]}-T{c[6]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"seed{c[0]}-F{c[4]}-K{c[5]}-T{c[6]}-R{c[7]}")
 def test_learned_walk_replays_exactly(chap, case):
-    gseed, n, m, iters, F_, K, steps = case
+    gseed, n, m, iters, F_, K, steps, R = case
     mip = mipgen.random_mixed(gseed, n=n, m=m, max_row_nnz=8, int_width=30, long_cols=2, long_deg=50)
     G = chap.Problem(mip)
     M = chap.Model(gseed)
     say(f"learned walk {case}")
     run = chap.learned_run(G, M, iters, 10, 2, full_every=F_, topk=K, train_steps=steps, train_pairs=24, lr=3e-3,
-                           log_sets=1)
+                           log_sets=1, refresh_every=R)
     P = oracle.OracleProblem(mip)
     ref = P.learned_replay(iters, 10, 2, F_, run.sets, run.set_offsets)
     compare_traces(run.trace, ref["trace"], f"learned {case}")
@@ -135,6 +137,13 @@ def test_learned_walk_replays_exactly(chap, case):
     for k in np.flatnonzero(~full):
         s = run.proposal_set(k)
         assert 0 < s.size <= K and np.unique(s).size == s.size
+    if R > 1:
+        # a set is kept for R proposal iterations after each refresh
+        kept = 0
+        for k in np.flatnonzero(~full[1:]) + 1:
+            if not full[k - 1] and kinds[k - 1] != 3 and np.array_equal(run.proposal_set(k), run.proposal_set(k - 1)):
+                kept += 1
+        assert kept > 0
 
 
 def test_tiny_binary_learned_replay(chap):
@@ -200,7 +209,8 @@ def test_learned_options_rejected(chap):
     mip = mipgen.random_mixed(440, n=50, m=40)
     G = chap.Problem(mip)
     M = chap.Model(0)
-    for bad in (dict(topk=0), dict(full_every=0), dict(train_pairs=0), dict(lr=0.0), dict(train_steps=-1)):
+    for bad in (dict(topk=0), dict(full_every=0), dict(train_pairs=0), dict(lr=0.0), dict(train_steps=-1),
+                dict(refresh_every=0)):
         with pytest.raises(chap.ChapError) as e:
             chap.learned_run(G, M, 10, 10, 0, **bad)
         assert e.value.code == -1

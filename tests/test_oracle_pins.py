@@ -325,3 +325,25 @@ def test_resumed_walk_continues_the_walk(k0):
         for f in ("x", "r", "w"):
             assert np.array_equal(rest[f], full[f]), (mip.name, f)
         assert rest["best_obj"] == full["best_obj"] and rest["cutoff_rhs"] == full["cutoff_rhs"]
+
+
+def test_threads_do_not_change_results():
+    """The oracle's per-column and per-row loops split across threads give
+    the same best shifts and walks as one thread."""
+    mip = mipgen.powerlaw(4, n=20_000, m=10_000, nnz=150_000, cap=3000)
+    cont = mipgen.random_mixed(11, n=300, m=200, integer_data=False)
+    try:
+        for m in (mip, cont):
+            P = oracle.OracleProblem(m)
+            x = mipgen.random_point(m, 1)
+            w = mipgen.random_weights(P.mp + 1, 1)
+            oracle.set_threads(1)
+            a = P.best_shift(x, w)
+            ta = P.tabu_run(40, 5, 3)
+            assert oracle.set_threads(4) == 4
+            b = P.best_shift(x, w)
+            tb = P.tabu_run(40, 5, 3)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert ta["trace"].tobytes() == tb["trace"].tobytes() and np.array_equal(ta["r"], tb["r"])
+    finally:
+        oracle.set_threads(1)
