@@ -213,13 +213,15 @@ int chap_tabu_run(chap_problem *p, int64_t iters, int32_t tenure, uint64_t seed,
  * 3.1 "Parallel Tabu Search Instances": each walk has its own point, tabu
  * list and weights).
  *
- * Walk w runs on problem probs[walk_prob[w]] from the start point of seed
+ * Walk w runs on problem probs[walk_prob[w]] from the start point
+ * walk_x0[w] when walk_x0 and walk_x0[w] are not NULL (n host doubles, the
+ * rules of chap_tabu_run's x0), else from the start point of seed
  * walk_seed[w] (the rule of chap_tabu_run). All walks run `iters`
  * iterations with the same tenure. Every iteration is one launch per kernel
  * over all walks (the blocks of each launch are divided among the walks by
  * their work), several iterations are recorded in one HIP graph. Walk w's
  * result is identical to chap_tabu_run(probs[walk_prob[w]], iters, tenure,
- * walk_seed[w], NULL, ...).
+ * walk_seed[w], walk_x0 ? walk_x0[w] : NULL, ...).
  *   probs      nprob problem handles (same device); a problem may serve any
  *              number of walks.
  *   walk_prob  nwalks indices into probs.    walk_seed  nwalks seeds.
@@ -228,8 +230,8 @@ int chap_tabu_run(chap_problem *p, int64_t iters, int32_t tenure, uint64_t seed,
  * Synchronous. Errors: CHAP_EINVAL, CHAP_ENOMEM, CHAP_EHIP.
  */
 int chap_batch_run(chap_problem *const *probs, int32_t nprob, const int32_t *walk_prob,
-                   const uint64_t *walk_seed, int32_t nwalks, int64_t iters, int32_t tenure,
-                   chap_run **out, void *hip_stream);
+                   const uint64_t *walk_seed, const double *const *walk_x0, int32_t nwalks, int64_t iters,
+                   int32_t tenure, chap_run **out, void *hip_stream);
 
 /*
  * chap_autotune - picks the kernel routing thresholds and graph size for an
@@ -263,6 +265,21 @@ int chap_run_trace(const chap_run *r, const chap_trace_record **records, int64_t
  */
 int chap_run_state(const chap_run *r, double *x, double *resid, float *w, double *best_obj,
                    double *best_x, double *cutoff_rhs);
+
+/*
+ * chap_run_best_infeasible - the best infeasible point the walk visited (the
+ * pool keeps partial solutions besides feasible ones, section 3.2 and
+ * Fig. 1): among its start point and the point after each iteration, those
+ * violating at least one normalised row of the problem (the cutoff row not
+ * counted), the first with the fewest such rows.
+ *   x         optional host array of n doubles (caller's order), filled when
+ *             such a point exists.
+ *   violated  its violated normalised rows (0 when none exists).
+ *   iter      the iteration after which it was reached; -1 for the start
+ *             point, -2 when every visited point was feasible.
+ * Errors: CHAP_EINVAL, CHAP_EHIP.
+ */
+int chap_run_best_infeasible(const chap_run *r, double *x, int64_t *violated, int64_t *iter);
 
 /* GPU time of the run's iteration graphs in milliseconds (HIP events); for
  * a batch, the time of the whole batch. */

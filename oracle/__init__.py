@@ -66,11 +66,11 @@ def _load():
     lib.orc_objective.restype = f64
     lib.orc_objective.argtypes = [P, P]
     lib.orc_tabu_run.restype = i64
-    lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P]
+    lib.orc_tabu_run.argtypes = [P, i64, i32, u64, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_tabu_resume.restype = i64
-    lib.orc_tabu_resume.argtypes = [P, i64, i32, P, P, P, i64, i32, f64, P, f64, P, P, P, P, P, P, P, P]
+    lib.orc_tabu_resume.argtypes = [P, i64, i32, P, P, P, i64, i32, f64, P, f64, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_learned_replay.restype = i64
-    lib.orc_learned_replay.argtypes = [P, i64, i32, u64, P, i32, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_learned_replay.argtypes = [P, i64, i32, u64, P, i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -213,9 +213,13 @@ class OracleProblem:
         if x0 is not None:
             x0 = np.ascontiguousarray(x0, dtype=np.float64)
             x0p = _p(x0)
+        inf_v = ctypes.c_int64()
+        inf_k = ctypes.c_int64()
+        inf_x = np.empty(self.n)
         call(x0p, _p(trace), _p(x), _p(r), _p(w), ctypes.byref(best_obj), _p(best_x), ctypes.byref(has_best),
-             ctypes.byref(bc))
+             ctypes.byref(bc), ctypes.byref(inf_v), ctypes.byref(inf_k), _p(inf_x))
         return {
             "trace": trace[:iters], "x": x, "r": r, "w": w, "best_obj": best_obj.value,
             "best_x": best_x if has_best.value else None, "cutoff_rhs": bc.value,
+            "inf_viol": inf_v.value, "inf_iter": inf_k.value, "inf_x": inf_x if inf_k.value != -2 else None,
         }

@@ -484,10 +484,23 @@ struct WalkResume {
   double cutoff_rhs;
 };
 
+// The best infeasible point of a walk (reading of the pool's partial
+// solutions, section 3.2): among the points the walk visits (its start and
+// the point after each iteration) that violate at least one normalised row
+// of the problem (the cutoff row not counted), the first with the fewest
+// such rows. iter = -1 for the start point, -2 when every point was
+// feasible.
+struct WalkInfeasible {
+  int64_t* viol;
+  int64_t* iter;
+  double* x;
+};
+
 int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
                      int32_t full_every, const int32_t* sets, const int64_t* set_off, void* trace_out,
                      double* x_out, double* r_out, float* w_out, double* best_obj, double* best_x, int32_t* has_best,
-                     double* cutoff_rhs_out, const WalkResume* resume = nullptr) {
+                     double* cutoff_rhs_out, const WalkResume* resume = nullptr,
+                     const WalkInfeasible* inf_out = nullptr) {
   const int32_t n = P.n;
   std::vector<double> x(n);
   if (x0)
@@ -521,6 +534,17 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
 
   residual_from_scratch(P, x.data(), cutoff, bc, r);
   int64_t V = count_violated(P, r, cutoff);
+  int64_t inf_v = std::numeric_limits<int64_t>::max(), inf_k = -2;
+  std::vector<double> inf_x(n, 0.0);
+  auto track_infeasible = [&](int64_t k) {
+    const int64_t v = count_violated(P, r, false);
+    if (v > 0 && v < inf_v) {
+      inf_v = v;
+      inf_k = k;
+      inf_x = x;
+    }
+  };
+  track_infeasible(k0 - 1);
 
   auto incumbent_check = [&]() {
     if (V != 0) return;
@@ -613,6 +637,7 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
       V = count_violated(P, r, cutoff);
       t.viol = V;
       t.obj = objective(P, x.data());
+      track_infeasible(k);
     }
     incumbent_check();
   }
@@ -624,6 +649,11 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
   std::memcpy(best_x, xbest.data(), sizeof(double) * (size_t)n);
   *has_best = found ? 1 : 0;
   *cutoff_rhs_out = cutoff ? bc : kInf;
+  if (inf_out) {
+    *inf_out->viol = inf_k == -2 ? 0 : inf_v;
+    *inf_out->iter = inf_k;
+    std::memcpy(inf_out->x, inf_x.data(), sizeof(double) * (size_t)n);
+  }
   return iters;
 }
 
@@ -631,9 +661,11 @@ int64_t learned_walk(OracleProblem& P, int64_t iters, int32_t tenure, uint64_t s
 // records written (== iters).
 int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
                      void* trace_out, double* x_out, double* r_out, float* w_out, double* best_obj,
-                     double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
+                     double* best_x, int32_t* has_best, double* cutoff_rhs_out, int64_t* inf_viol,
+                     int64_t* inf_iter, double* inf_x) {
+  const WalkInfeasible I{inf_viol, inf_iter, inf_x};
   return learned_walk(*(OracleProblem*)h, iters, tenure, seed, x0, 1, nullptr, nullptr, trace_out, x_out, r_out,
-                      w_out, best_obj, best_x, has_best, cutoff_rhs_out);
+                      w_out, best_obj, best_x, has_best, cutoff_rhs_out, nullptr, &I);
 }
 
 // The plain walk continued for `iters` iterations from a given state at the
@@ -641,19 +673,23 @@ int64_t orc_tabu_run(void* h, int64_t iters, int32_t tenure, uint64_t seed, cons
 int64_t orc_tabu_resume(void* h, int64_t iters, int32_t tenure, const double* x, const float* w,
                         const int64_t* tabu_until, int64_t k0, int32_t has_best_in, double fbest_in,
                         const double* best_x_in, double cutoff_rhs_in, void* trace_out, double* x_out, double* r_out,
-                        float* w_out, double* best_obj, double* best_x, int32_t* has_best, double* cutoff_rhs_out) {
+                        float* w_out, double* best_obj, double* best_x, int32_t* has_best, double* cutoff_rhs_out,
+                        int64_t* inf_viol, int64_t* inf_iter, double* inf_x) {
   const WalkResume R{w, tabu_until, k0, has_best_in, fbest_in, best_x_in, cutoff_rhs_in};
+  const WalkInfeasible I{inf_viol, inf_iter, inf_x};
   return learned_walk(*(OracleProblem*)h, iters, tenure, 0, x, 1, nullptr, nullptr, trace_out, x_out, r_out, w_out,
-                      best_obj, best_x, has_best, cutoff_rhs_out, &R);
+                      best_obj, best_x, has_best, cutoff_rhs_out, &R, &I);
 }
 
 // The learned proposal form of the walk, replaying the listed sets.
 int64_t orc_learned_replay(void* h, int64_t iters, int32_t tenure, uint64_t seed, const double* x0,
                            int32_t full_every, const int32_t* sets, const int64_t* set_off, void* trace_out,
                            double* x_out, double* r_out, float* w_out, double* best_obj, double* best_x,
-                           int32_t* has_best, double* cutoff_rhs_out) {
+                           int32_t* has_best, double* cutoff_rhs_out, int64_t* inf_viol, int64_t* inf_iter,
+                           double* inf_x) {
+  const WalkInfeasible I{inf_viol, inf_iter, inf_x};
   return learned_walk(*(OracleProblem*)h, iters, tenure, seed, x0, full_every, sets, set_off, trace_out, x_out,
-                      r_out, w_out, best_obj, best_x, has_best, cutoff_rhs_out);
+                      r_out, w_out, best_obj, best_x, has_best, cutoff_rhs_out, nullptr, &I);
 }
 
 }  // extern "C"

@@ -78,12 +78,14 @@ def load_library():
     lib.chap_best_shift_pass_ms.restype = ctypes.c_int
     lib.chap_tabu_run.argtypes = [P, i64, i32, u64, P, ctypes.POINTER(P), P]
     lib.chap_tabu_run.restype = ctypes.c_int
-    lib.chap_batch_run.argtypes = [P, i32, P, P, i32, i64, i32, P, P]
+    lib.chap_batch_run.argtypes = [P, i32, P, P, P, i32, i64, i32, P, P]
     lib.chap_batch_run.restype = ctypes.c_int
     lib.chap_run_trace.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(i64)]
     lib.chap_run_trace.restype = ctypes.c_int
     lib.chap_run_state.argtypes = [P, P, P, P, ctypes.POINTER(f64), P, ctypes.POINTER(f64)]
     lib.chap_run_state.restype = ctypes.c_int
+    lib.chap_run_best_infeasible.argtypes = [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.chap_run_best_infeasible.restype = ctypes.c_int
     lib.chap_run_elapsed_ms.argtypes = [P]
     lib.chap_run_elapsed_ms.restype = f64
     lib.chap_run_destroy.argtypes = [P]
@@ -208,6 +210,17 @@ class Run:
             _check(load_library().chap_run_state(self._h, _ptr(x), _ptr(resid), _ptr(w), None, _ptr(best_x), None))
             self._state = (x, resid, w, None if math.isinf(self.best_obj) else best_x)
         return self._state
+
+    def best_infeasible(self):
+        """(point or None, violated rows, iteration; -1 = start, -2 = none)."""
+        v, k = ctypes.c_int64(), ctypes.c_int64()
+        lib = load_library()
+        _check(lib.chap_run_best_infeasible(self._h, None, ctypes.byref(v), ctypes.byref(k)))
+        if k.value == -2:
+            return None, v.value, k.value
+        x = np.empty(self._n)
+        _check(lib.chap_run_best_infeasible(self._h, _ptr(x), None, None))
+        return x, v.value, k.value
 
     @property
     def x(self):
@@ -398,18 +411,30 @@ def features(problem, x, w, cutoff_rhs, s_last, xhat_last, last_move, moves, k: 
     return out
 
 
-def batch_run(problems, walk_prob, walk_seed, iters: int, tenure: int, stream=None):
-    """chap_batch_run: walk w runs on problems[walk_prob[w]] with seed
-    walk_seed[w]; returns one Run per walk."""
+def batch_run(problems, walk_prob, walk_seed, iters: int, tenure: int, stream=None, walk_x0=None):
+    """chap_batch_run: walk w runs on problems[walk_prob[w]] from walk_x0[w]
+    (host array, or None) or else the start point of seed walk_seed[w];
+    returns one Run per walk."""
     lib = load_library()
     nprob = len(problems)
     handles = (ctypes.c_void_p * nprob)(*[p._h.value for p in problems])
     wp = np.ascontiguousarray(walk_prob, dtype=np.int32)
     ws = np.ascontiguousarray(walk_seed, dtype=np.uint64)
     nw = wp.shape[0]
+    x0p = None
+    keep = []
+    if walk_x0 is not None:
+        x0p = (ctypes.c_void_p * nw)()
+        for w in range(nw):
+            if walk_x0[w] is not None:
+                a = np.ascontiguousarray(walk_x0[w], dtype=np.float64)
+                assert a.shape[0] == problems[wp[w]].n
+                keep.append(a)
+                x0p[w] = a.ctypes.data
+        x0p = ctypes.cast(x0p, ctypes.c_void_p)
     out = (ctypes.c_void_p * nw)()
-    _check(lib.chap_batch_run(ctypes.cast(handles, ctypes.c_void_p), nprob, _ptr(wp), _ptr(ws), nw, int(iters),
-                              int(tenure), ctypes.cast(out, ctypes.c_void_p), _stream_handle(stream)))
+    _check(lib.chap_batch_run(ctypes.cast(handles, ctypes.c_void_p), nprob, _ptr(wp), _ptr(ws), x0p, nw,
+                              int(iters), int(tenure), ctypes.cast(out, ctypes.c_void_p), _stream_handle(stream)))
     return [Run(ctypes.c_void_p(out[w]), problems[wp[w]].n, problems[wp[w]].mp) for w in range(nw)]
 
 

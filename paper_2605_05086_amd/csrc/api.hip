@@ -946,6 +946,20 @@ void fill_summary(const WalkState& st, chap_run* R) {
   R->has_best = st.has_best != 0;
   R->best_obj = st.has_best ? st.fbest : HUGE_VAL;
   R->cutoff_rhs = st.cut_active ? st.bc : HUGE_VAL;
+  R->inf_iter = st.inf_k;
+  R->inf_viol = st.inf_k == -2 ? 0 : st.inf_V;
+}
+
+// The best infeasible point from the final point: the moves after the
+// iteration that reached it are undone in reverse order.
+void rebuild_infeasible(chap_run* R) {
+  R->inf_x.clear();
+  if (R->inf_iter == -2) return;
+  R->inf_x = R->x;
+  for (int64_t k = (int64_t)R->trace.size() - 1; k > R->inf_iter; --k) {
+    const chap_trace_record& t = R->trace[(size_t)k];
+    if (t.var >= 0) R->inf_x[t.var] = t.x_old;
+  }
 }
 
 }  // namespace
@@ -967,6 +981,7 @@ int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double 
   CHAP_HIP(hipMemcpy(&st, c.st, sizeof(WalkState), hipMemcpyDeviceToHost));
   fill_summary(st, R);
   fill_state(n, m, p->mp, p->perm.data(), p->nidx.data(), p->pair.data(), xin.data(), bxin.data(), rs.data(), st, R);
+  rebuild_infeasible(R);
   return CHAP_OK;
 }
 
@@ -986,6 +1001,7 @@ int materialize(const chap_run* R) {
   chap_run* W = const_cast<chap_run*>(R);
   fill_state(M.n, M.m, M.mp, M.perm.data(), M.nidx.data(), M.pair.data(), xin.data(), bxin.data(), rs.data(),
              R->st_end, W);
+  rebuild_infeasible(W);
   R->state_ready = true;
   R->pool->give_back(R->slot);
   return CHAP_OK;
@@ -1243,14 +1259,15 @@ int chap_tabu_run(chap_problem* p, int64_t iters, int32_t tenure, uint64_t seed,
 }
 
 int chap_batch_run(chap_problem* const* probs, int32_t nprob, const int32_t* walk_prob, const uint64_t* walk_seed,
-                   int32_t nwalks, int64_t iters, int32_t tenure, chap_run** out, void* hip_stream) {
+                   const double* const* walk_x0, int32_t nwalks, int64_t iters, int32_t tenure, chap_run** out,
+                   void* hip_stream) {
   if (!probs || !walk_prob || !walk_seed || !out || nprob <= 0 || nwalks <= 0)
     return fail(CHAP_EINVAL, "chap_batch_run: null argument or empty batch");
   std::vector<WalkSpec> specs;
   for (int32_t w = 0; w < nwalks; ++w) {
     if (walk_prob[w] < 0 || walk_prob[w] >= nprob || !probs[walk_prob[w]])
       return fail(CHAP_EINVAL, "chap_batch_run: walk " + std::to_string(w) + " names no problem");
-    specs.push_back(WalkSpec{probs[walk_prob[w]], walk_seed[w], nullptr});
+    specs.push_back(WalkSpec{probs[walk_prob[w]], walk_seed[w], walk_x0 ? walk_x0[w] : nullptr});
   }
   const int dev = specs[0].p->device;
   for (const WalkSpec& ws : specs)
@@ -1329,6 +1346,18 @@ int chap_run_state(const chap_run* r, double* x, double* resid, float* w, double
   if (best_obj) *best_obj = r->best_obj;
   if (best_x && r->has_best) std::copy(r->best_x.begin(), r->best_x.end(), best_x);
   if (cutoff_rhs) *cutoff_rhs = r->cutoff_rhs;
+  return CHAP_OK;
+}
+
+int chap_run_best_infeasible(const chap_run* r, double* x, int64_t* violated, int64_t* iter) {
+  if (!r) return fail(CHAP_EINVAL, "chap_run_best_infeasible: null run");
+  if (x && r->inf_iter != -2) {
+    const int rc = materialize(r);
+    if (rc != CHAP_OK) return rc;
+    std::copy(r->inf_x.begin(), r->inf_x.end(), x);
+  }
+  if (violated) *violated = r->inf_viol;
+  if (iter) *iter = r->inf_iter;
   return CHAP_OK;
 }
 

@@ -182,6 +182,11 @@ struct __align__(16) WalkState {
   // launch_stage_x); 0 after the state is cleared
   uint32_t x_misfit;
   uint32_t pad_;
+  // best infeasible point so far: the fewest violated normalised rows (the
+  // cutoff row not counted) among the infeasible points visited, and the
+  // iteration after which it was reached (-1: the start, -2: none yet)
+  int64_t inf_V;
+  int64_t inf_k;
 };
 
 // A slice of a long narrow-integer column handled by one workgroup; col < 0
@@ -782,6 +787,12 @@ struct chap_run {
   mutable std::unique_ptr<chap::WalkSlot> slot;
   chap::WalkState st_end{};
   mutable bool state_ready = true;
+  // best infeasible point (see WalkState::inf_V): its violated rows, the
+  // iteration after which it was reached, and the point (caller's order,
+  // rebuilt from the final point and the trace when the state is read)
+  int64_t inf_viol = 0;
+  int64_t inf_iter = -2;
+  std::vector<double> inf_x;
   ~chap_run() {
     if (pool) pool->give_back(slot);
   }

@@ -226,11 +226,24 @@ __device__ __forceinline__ void flip_column(const DevProblem& P, const double* x
   const double d = xn - xb;
   double s = 0.0;
   const int beg = P.col_ptr[q], end = P.col_ptr[q + 1];
-  for (int e = beg; e < end; ++e) {
-    const RowState r = rs[P.col_row[e]];
-    const double r2 = r.r + P.col_val[e] * d;
-    s += penalty(r.r, r2, (double)r.w0, eps);
-    if (r.w1 >= 0.0f) s += penalty(-r.r, -r2, (double)r.w1, eps);
+  // at most kShortMax entries here: every gather is issued before any is used
+  RowState rr[kShortMax];
+  double av[kShortMax];
+#pragma unroll
+  for (int k = 0; k < kShortMax; ++k) {
+    if (beg + k < end) {
+      av[k] = P.col_val[beg + k];
+      rr[k] = rs[P.col_row[beg + k]];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kShortMax; ++k) {
+    if (beg + k < end) {
+      const RowState& r = rr[k];
+      const double r2 = r.r + av[k] * d;
+      s += penalty(r.r, r2, (double)r.w0, eps);
+      if (r.w1 >= 0.0f) s += penalty(-r.r, -r2, (double)r.w1, eps);
+    }
   }
   if (st->cut_active) {
     const double c = P.obj[q];

@@ -364,8 +364,12 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
     o.rc = o.cutoff_residual(objacc ? &acc : nullptr);
     if (o.rc > eps) o.V += 1;
   }
+  // the start point is the first candidate for the best infeasible point
+  const long long v_orig = (long long)vt;
   if (check_incumbent) o.incumbent_check(eps, objacc ? &acc : nullptr);
   if (threadIdx.x != 0) return;
+  st->inf_V = v_orig > 0 ? v_orig : LLONG_MAX;
+  st->inf_k = v_orig > 0 ? -1 : -2;
   *ticket = 0u;
   st->k = 0;
   st->iters = iters;
@@ -674,18 +678,6 @@ __global__ __launch_bounds__(256) void k_subset_select(const WalkCtx* __restrict
   }
 }
 
-// Residual of stored row i from scratch at x with x_j replaced by xj, in
-// the row's stored order (the order of the caller's CSR).
-__device__ __forceinline__ double row_residual(const DevProblem& P, const double* x, int i, int j, double xj) {
-  double acc = 0.0;
-  const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
-  for (int e = beg; e < end; ++e) {
-    const int c = P.row_col[e];
-    const double prod = P.row_val[e] * ((c == j) ? xj : x[c]);
-    acc = acc + prod;
-  }
-  return acc - P.row_rhs[i];
-}
 
 // Applies the chosen move to the rows of one column, or the weight update to
 // every violated row; violation changes are summed into st->dV (read by
@@ -709,14 +701,44 @@ __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks
   const int gt = lb * blockDim.x + threadIdx.x;
   const int gs = C.apply_blocks * blockDim.x;
   long long dv = 0;
-  if (jstar >= 0) {
-    const double d = st->mv_delta;
+  if (jstar >= 0 && recompute) {
+    // kResidualLanes lanes per touched row: the row is summed again in its
+    // stored order (products side by side, added in entry order)
     const double xn = st->mv_new;
+    const int beg = P.col_ptr[jstar], end = P.col_ptr[jstar + 1];
+    const int g = gt & (kResidualLanes - 1);
+    for (int e = beg + gt / kResidualLanes; e < end; e += gs / kResidualLanes) {
+      const int i = P.col_row[e];
+      double acc = 0.0;
+      const int rb = P.row_ptr[i], re = P.row_ptr[i + 1];
+      for (int e0 = rb; e0 < re; e0 += kResidualLanes) {
+        const int f = e0 + g;
+        double prod = 0.0;
+        if (f < re) {
+          const int c = P.row_col[f];
+          prod = P.row_val[f] * ((c == jstar) ? xn : x[c]);
+        }
+        const int cnt = min(kResidualLanes, re - e0);
+        for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod, t, kResidualLanes);
+      }
+      if (g == 0) {
+        const RowState q = rs[i];
+        const double r2 = acc - P.row_rhs[i];
+        rs[i].r = r2;
+        if (C.grow) C.grow[i].r = (int32_t)r2;
+        dv += viol_change(q.r, r2, eps);
+        if (q.w1 >= 0.0f) dv += viol_change(-q.r, -r2, eps);
+      }
+    }
+    dv = block_sum_ll(dv, red);
+    if (threadIdx.x == 0 && dv != 0) atomicAdd(&st->dV, (unsigned long long)dv);
+  } else if (jstar >= 0) {
+    const double d = st->mv_delta;
     const int beg = P.col_ptr[jstar], end = P.col_ptr[jstar + 1];
     for (int e = beg + gt; e < end; e += gs) {
       const int i = P.col_row[e];
       const RowState q = rs[i];
-      const double r2 = recompute ? row_residual(P, x, i, jstar, xn) : q.r + P.col_val[e] * d;
+      const double r2 = q.r + P.col_val[e] * d;
       rs[i].r = r2;
       if (C.grow) C.grow[i].r = (int32_t)r2;
       dv += viol_change(q.r, r2, eps);
@@ -794,6 +816,13 @@ __global__ __launch_bounds__(64) void k_finish(const WalkCtx* __restrict__ walks
   if (lane == 0) {
     C.trace[k].viol = o.V;
     C.trace[k].obj = o.f;
+    if (jstar >= 0) {
+      const long long v_orig = o.V - ((o.cut_active && o.rc > eps) ? 1 : 0);
+      if (v_orig > 0 && v_orig < st->inf_V) {
+        st->inf_V = v_orig;
+        st->inf_k = k;
+      }
+    }
   }
   o.incumbent_check(eps, exact ? &acc : nullptr);
   if (lane != 0) return;

@@ -147,3 +147,49 @@ def test_start_point_validation(chap):
     for bad in (bad_frac, bad_high):
         with pytest.raises(chap.ChapError, match="CHAP_EINVAL"):
             G.tabu_run(3, 2, 0, x0=bad)
+
+
+def test_best_infeasible_point(chap):
+    """The best infeasible point a walk visited (fewest violated rows, the
+    cutoff row not counted, first reached) equals the oracle's: its point,
+    row count and iteration, for walks that reach feasibility and walks that
+    do not."""
+    cases = [("tiny_binary", mipgen.tiny_binary(0), 400),
+             ("mixed integer", mipgen.random_mixed(87, n=300, m=200, max_row_nnz=8, frac_bin=0.3, frac_int=0.7,
+                                                   long_cols=3, long_deg=60), 300),
+             ("continuous", mipgen.random_mixed(88, n=80, m=40, integer_data=False), 300),
+             ("powerlaw", mipgen.powerlaw(89, n=20_000, m=10_000, nnz=200_000, cap=3000), 200)]
+    for name, mip, iters in cases:
+        P = oracle.OracleProblem(mip)
+        G = chap.Problem(mip)
+        for seed in (0, 2):
+            say(f"best infeasible {name} seed={seed}")
+            g = G.tabu_run(iters, 10, seed)
+            o = P.tabu_run(iters, 10, seed)
+            x, v, k = g.best_infeasible()
+            assert (v, k) == (o["inf_viol"], o["inf_iter"]), (name, seed, v, k, o["inf_viol"], o["inf_iter"])
+            if k == -2:
+                assert x is None and o["inf_x"] is None
+            else:
+                assert np.array_equal(x, o["inf_x"]), (name, seed)
+
+
+def test_batch_with_start_points(chap):
+    """Batched walks from given start points (some walks seeded): each equals
+    the plain walk from the same start, and one equals the oracle."""
+    mips = [mipgen.random_mixed(90, n=400, m=250, max_row_nnz=8, frac_bin=0.3, frac_int=0.7),
+            mipgen.general(91, n=3000, m=1500)]
+    probs = [chap.Problem(m) for m in mips]
+    walk_prob = [0, 1, 0, 1, 0]
+    walk_seed = [1, 2, 3, 4, 5]
+    walk_x0 = [mipgen.random_point(mips[0], 7), None, None, mipgen.random_point(mips[1], 8),
+               mipgen.random_point(mips[0], 9)]
+    say("batch with start points")
+    runs = chap.batch_run(probs, walk_prob, walk_seed, 60, 5, walk_x0=walk_x0)
+    for w, r in enumerate(runs):
+        g = probs[walk_prob[w]].tabu_run(60, 5, walk_seed[w], x0=walk_x0[w])
+        assert r.trace.tobytes() == g.trace.tobytes(), f"walk {w}"
+        assert r.x.tobytes() == g.x.tobytes() and r.w.tobytes() == g.w.tobytes()
+        assert r.best_infeasible()[1:] == g.best_infeasible()[1:]
+    o = oracle.OracleProblem(mips[0]).tabu_run(60, 5, 0, x0=walk_x0[0])
+    compare_runs(runs[0], o, "batch walk from x0")

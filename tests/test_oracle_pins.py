@@ -347,3 +347,33 @@ def test_threads_do_not_change_results():
             assert ta["trace"].tobytes() == tb["trace"].tobytes() and np.array_equal(ta["r"], tb["r"])
     finally:
         oracle.set_threads(1)
+
+
+def test_best_infeasible_point_by_replaying_the_trace():
+    """The oracle's best infeasible point against a recount: the points of the
+    walk are rebuilt from the start point and the trace's moves, each one's
+    violated rows (cutoff row not counted) are counted from scratch, and the
+    first point with the fewest (more than zero) must be the one reported."""
+    cases = list(_tiny_instances(10, seed0=900)) + [mipgen.random_mixed(14, n=60, m=40, integer_data=False),
+                                                   mipgen.tiny_binary(0)]
+    for mip in cases:
+        P = oracle.OracleProblem(mip)
+        for seed in (0, 3):
+            iters = 80
+            out = P.tabu_run(iters, 3, seed)
+            x = P.start_point(seed)
+            best_v, best_k, best_x = None, -2, None
+            pts = [(-1, x.copy())]
+            for rec in out["trace"]:
+                if rec["var"] >= 0:
+                    x[rec["var"]] = rec["x_new"]
+                    pts.append((int(rec["iter"]), x.copy()))
+            for k, xk in pts:
+                _, v = P.residual(xk)
+                if v > 0 and (best_v is None or v < best_v):
+                    best_v, best_k, best_x = v, k, xk
+            assert out["inf_iter"] == best_k, (mip.name, seed)
+            if best_k == -2:
+                assert out["inf_viol"] == 0 and out["inf_x"] is None
+            else:
+                assert out["inf_viol"] == best_v and np.array_equal(out["inf_x"], best_x)
