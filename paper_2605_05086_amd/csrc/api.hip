@@ -37,21 +37,71 @@ __global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
 
 namespace chap {
 
-// Uploads per-walk contexts and the per-kernel block prefix tables.
-hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLaunch* L) {
-  L->nw = (int32_t)ctx.size();
+// Uploads per-walk contexts and the per-kernel block prefix tables. A batch
+// (more than one walk) is placed by XCD: every walk goes to one XCD, chosen
+// greedily by its pass work (largest walks first, to the least loaded XCD),
+// ctx is reordered XCD by XCD (order[i] = caller's index of ctx[i]) and each
+// table gets the first virtual block and block count of every XCD appended
+// (see block_walk); a kernel then launches kXcds x its largest XCD share.
+hipError_t build_launch(DeviceArena& A, std::vector<WalkCtx>& ctx, BatchLaunch* L, std::vector<int32_t>* order) {
+  const size_t nw = ctx.size();
+  L->nw = (int32_t)nw;
+  std::vector<int32_t> xcd(nw, 0), perm(nw);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (nw > 1) {
+    std::vector<int64_t> work(nw, 0);
+    for (size_t w = 0; w < nw; ++w)
+      for (int k = KS_SHORT; k <= KS_STAGE_SCORE; ++k) work[w] += kernel_blocks(ctx[w], k);
+    std::vector<int32_t> by(nw);
+    std::iota(by.begin(), by.end(), 0);
+    std::stable_sort(by.begin(), by.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    int64_t load[kXcds] = {0};
+    for (int32_t w : by) {
+      int x = 0;
+      for (int y = 1; y < kXcds; ++y)
+        if (load[y] < load[x]) x = y;
+      xcd[w] = x;
+      load[x] += std::max<int64_t>(work[w], 1);
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return xcd[a] < xcd[b]; });
+    std::vector<WalkCtx> sorted(nw);
+    std::vector<int32_t> xs(nw);
+    for (size_t i = 0; i < nw; ++i) {
+      sorted[i] = ctx[perm[i]];
+      xs[i] = xcd[perm[i]];
+    }
+    ctx.swap(sorted);
+    xcd.swap(xs);
+  }
+  if (order) *order = perm;
   WalkCtx* d;
   hipError_t e = A.upload(&d, ctx);
   if (e != hipSuccess) return e;
   L->walks = d;
   for (int k = 0; k < KS_COUNT; ++k) {
-    std::vector<int32_t> off(ctx.size() + 1, 0);
-    for (size_t w = 0; w < ctx.size(); ++w) off[w + 1] = off[w] + kernel_blocks(ctx[w], k);
+    std::vector<int32_t> off(nw + 1, 0);
+    for (size_t w = 0; w < nw; ++w) off[w + 1] = off[w] + kernel_blocks(ctx[w], k);
+    L->total[k] = off.back();
+    L->grid[k] = off.back();
+    if (nw > 1) {
+      int32_t first[kXcds], count[kXcds] = {0};
+      for (int x = 0; x < kXcds; ++x) first[x] = off.back();
+      for (size_t w = 0; w < nw; ++w) {
+        first[xcd[w]] = std::min(first[xcd[w]], off[w]);
+        count[xcd[w]] += off[w + 1] - off[w];
+      }
+      int32_t most = 0;
+      for (int x = 0; x < kXcds; ++x) {
+        off.push_back(first[x]);
+        most = std::max(most, count[x]);
+      }
+      for (int x = 0; x < kXcds; ++x) off.push_back(count[x]);
+      L->grid[k] = kXcds * most;
+    }
     int32_t* doff;
     e = A.upload(&doff, off);
     if (e != hipSuccess) return e;
     L->off[k] = doff;
-    L->total[k] = off.back();
   }
   return hipSuccess;
 }
@@ -759,7 +809,8 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.alloc(&c.long_delta, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.long_marker, (size_t)P->plan.long_scratch));
     CHAP_HIP(A.alloc(&c.stage_rec, (size_t)P->plan.n_stage_ent));
-    CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &P->bs_launch));
+    std::vector<WalkCtx> one{c};
+    CHAP_HIP(build_launch(A, one, &P->bs_launch, nullptr));
     P->bs_launch.compact = P->compact_ok ? 2 : 0;
   }
   CHAP_HIP(P->bs_streams.create());
@@ -1069,7 +1120,8 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
     if (rc != CHAP_OK) return rc;
   }
   BatchLaunch L;
-  CHAP_HIP(build_launch(A, ctx, &L));
+  std::vector<int32_t> order;
+  CHAP_HIP(build_launch(A, ctx, &L, &order));
   L.compact = compact;
   double ms_total = 0.0;
   if (iters > 0) {
@@ -1106,11 +1158,13 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   }
   CHAP_HIP(hipStreamSynchronize(s));
   out.clear();
-  for (size_t w = 0; w < nw; ++w) {
+  out.resize(nw);
+  for (size_t i = 0; i < nw; ++i) {
+    const int32_t w = order[i];  // ctx is in XCD order
     std::unique_ptr<chap_run> R(new chap_run());
-    const int rc = collect_walk(specs[w].p, ctx[w], iters, ms_total, R.get());
+    const int rc = collect_walk(specs[w].p, ctx[i], iters, ms_total, R.get());
     if (rc != CHAP_OK) return rc;
-    out.push_back(std::move(R));
+    out[w] = std::move(R);
   }
   return CHAP_OK;
 }
@@ -1127,7 +1181,8 @@ int slot_setup(const chap_problem* p, WalkSlot& S) {
   CHAP_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
   CHAP_HIP(S.ps.create());
   for (hipEvent_t& e : S.ev) CHAP_HIP(hipEventCreate(&e));
-  CHAP_HIP(build_launch(S.A, std::vector<WalkCtx>{S.ctx}, &S.L));
+  std::vector<WalkCtx> one{S.ctx};
+  CHAP_HIP(build_launch(S.A, one, &S.L, nullptr));
   return CHAP_OK;
 }
 

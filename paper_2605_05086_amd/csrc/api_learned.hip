@@ -213,7 +213,8 @@ int chap_learned_run(chap_problem* p, chap_model* m, const chap_learned_options*
   rc = prepare_walk(WalkSpec{p, seed, x0}, iters, tenure, A, c, partial, ticket, s, compact);
   if (rc != CHAP_OK) return rc;
   BatchLaunch BL;
-  CHAP_HIP(build_launch(A, std::vector<WalkCtx>{c}, &BL));
+  std::vector<WalkCtx> one{c};
+  CHAP_HIP(build_launch(A, one, &BL, nullptr));
   BL.compact = compact;
   LearnCtx Lh;
   rc = build_learn_ctx(p, o, iters, A, Lh);

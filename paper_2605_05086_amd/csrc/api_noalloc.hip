@@ -125,6 +125,7 @@ int chap_best_shift_noalloc(chap_problem* p, const double* d_x, const float* d_w
     r.off[k][1] = kernel_blocks(c, k);
     L.off[k] = rec->off[k];
     L.total[k] = r.off[k][1];
+    L.grid[k] = r.off[k][1];
   }
   L.compact = p->compact_ok ? 2 : 0;
   hipStream_t s = (hipStream_t)hip_stream;

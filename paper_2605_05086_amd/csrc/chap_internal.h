@@ -390,10 +390,37 @@ struct BatchLaunch {
   const WalkCtx* walks = nullptr;
   const int32_t* off[KS_COUNT] = {};
   int32_t total[KS_COUNT] = {};
+  int32_t grid[KS_COUNT] = {};  // workgroups to launch (total, or kXcds x the largest XCD share)
 };
 
 // Blocks kernel `slot` needs for one walk.
 int32_t kernel_blocks(const WalkCtx& c, int slot);
+
+// Walk of this workgroup and its index inside that walk, or -1 for a
+// padding workgroup. off holds the prefix of per-walk block counts (nw + 1
+// values). A batch (nw > 1) places every walk on one XCD: its walks are
+// ordered by XCD and off is followed by the first virtual block of each XCD
+// and the XCD's block count; workgroup b runs on XCD b mod kXcds (the
+// dispatch order) and takes the (b / kXcds)-th block of that XCD, so a
+// walk's row states stay in one L2.
+__device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int nw, int& local) {
+  int b = blockIdx.x;
+  if (nw > 1) {
+    const int x = b % kXcds, s = b / kXcds;
+    if (s >= off[nw + 1 + kXcds + x]) return -1;
+    b = off[nw + 1 + x] + s;
+  }
+  int lo = 0, hi = nw - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  local = b - off[lo];
+  return lo;
+}
 
 // Side streams on which the pass kernels run beside the main stream (they
 // write disjoint columns): fork and join events order them with the main
@@ -836,8 +863,9 @@ int prepare_walk(const WalkSpec& spec, int64_t iters, int32_t tenure, DeviceAren
 int compact_walks(const std::vector<WalkSpec>& specs, int64_t iters);
 // Copies a finished walk back into R (host order).
 int collect_walk(const chap_problem* p, const WalkCtx& c, int64_t iters, double ms, chap_run* R);
-// Device copy of the walk contexts and the per-kernel launch tables.
-hipError_t build_launch(DeviceArena& A, const std::vector<WalkCtx>& ctx, BatchLaunch* L);
+// Device copy of the walk contexts and the per-kernel launch tables; a batch
+// is reordered by XCD (order[i]: caller's index of ctx[i]; may be null).
+hipError_t build_launch(DeviceArena& A, std::vector<WalkCtx>& ctx, BatchLaunch* L, std::vector<int32_t>* order);
 int blocks_for_host(int64_t work, int cap);
 // The parts of launch_walk_step: argmax + selection, application, end of
 // iteration.

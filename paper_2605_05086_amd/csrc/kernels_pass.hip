@@ -197,21 +197,6 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
   return v;
 }
 
-// Walk of this block and the block's index inside that walk: the largest w
-// with off[w] <= blockIdx.x (off is the prefix of per-walk block counts).
-__device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int nw, int& local) {
-  const int b = blockIdx.x;
-  int lo = 0, hi = nw - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  local = b - off[lo];
-  return lo;
-}
 
 // ---------------------------------------------------------------------------
 // k_short: one lane per column (at most 8 normalised entries).
@@ -360,7 +345,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const Rows rs = rows_of<Rows>(C);
   if (C.st->k >= C.st->iters) return;
   const int32_t* seg = C.plan.short_seg;
@@ -395,7 +382,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) void k_flip_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                    int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const double* x = C.x;
   const Rows rs = rows_of<Rows>(C);
@@ -463,7 +452,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__ walks,
                                                      const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const double* x = C.x;
   const Rows rs = rows_of<Rows>(C);
@@ -760,7 +751,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict__ walks,
                                                       const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   __shared__ ChunkSmem S;
   chunk_task<Rows>(C, lb, S);
 }
@@ -769,7 +762,9 @@ __global__ __launch_bounds__(256) void k_narrow_chunk(const WalkCtx* __restrict_
 __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restrict__ walks,
                                                         const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& W0 = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& W0 = walks[w_];
   if (W0.st->k >= W0.st->iters) return;
   const int idx = lb * 4 + (threadIdx.x >> 6);
   if (idx >= W0.plan.n_chunk_cols) return;
@@ -952,7 +947,6 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
   const int nrb = C.plan.n_stage_rb;
   stage_segments(C, tix, G);
   const gptr<const uint64_t> recs = gmem((const uint64_t*)C.stage_rec);
-  const int tps = max(1, (int)blockDim.x / nrb);
   for (int c0 = 0; c0 < nc; c0 += kCols) {
     const int ncw = min(kCols, nc - c0);
     if (tid < ncw) {
@@ -966,15 +960,29 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
     for (int i = tid; i < ncw * (kNarrowBins + 1); i += blockDim.x)
       S.bins[i / (kNarrowBins + 1)][i % (kNarrowBins + 1)] = 0;
     __syncthreads();
-    // tps threads per row-block segment, each a contiguous part of it, kRun
-    // records per step; records of columns outside this window are skipped
+    // every thread takes an equal contiguous share of the task's records (in
+    // segment order, crossing row-block segments), kRun records per step;
+    // records of columns outside this window are skipped
     constexpr int kRun = 4;
-    for (int sg = tid / tps; sg < nrb; sg += (int)blockDim.x / tps) {
-      const int len = G.pre[sg + 1] - G.pre[sg];
-      const int per = (len + tps - 1) / tps;
-      const int i1 = G.beg[sg] + min(len, (tid % tps + 1) * per);
-      // a thread's run is sorted by column: beta, alpha and the candidate mask
-      // of the current column stay in registers until the column changes
+    {
+      const int total = G.pre[nrb];
+      const int per = (total + (int)blockDim.x - 1) / (int)blockDim.x;
+      const int f0 = min(total, tid * per), f1 = min(total, f0 + per);
+      // segment of f0: the last one starting at or before it
+      int lo = 0, hi = nrb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G.pre[mid] <= f0)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      int sg = lo;
+      int base = G.beg[sg] - G.pre[sg];  // record index of flat position f: base + f
+      int send = G.pre[sg + 1];
+      // a thread's run is sorted by column within a segment: beta, alpha and
+      // the candidate mask of the current column stay in registers until the
+      // column changes
       int cur = -1, k0 = 0, W = 0;
       V rb_ = 0, ra_ = 0;
       unsigned long long rc_ = 0ull;
@@ -987,14 +995,23 @@ __device__ __forceinline__ void stage_pack(const WalkCtx& C, const Rows& rs, boo
         ra_ = zero;
         rc_ = 0ull;
       };
-      for (int i0 = G.beg[sg] + min(len, (tid % tps) * per); i0 < i1; i0 += kRun) {
+      for (int f = f0; f < f1; f += kRun) {
         uint64_t r[kRun];
 #pragma unroll
-        for (int u = 0; u < kRun; ++u)
-          if (i0 + u < i1) r[u] = recs[i0 + u];
+        for (int u = 0; u < kRun; ++u) {
+          const int fu = f + u;
+          if (fu < f1) {
+            while (fu >= send) {
+              ++sg;
+              base = G.beg[sg] - G.pre[sg];
+              send = G.pre[sg + 1];
+            }
+            r[u] = recs[base + fu];
+          }
+        }
 #pragma unroll
         for (int u = 0; u < kRun; ++u) {
-          if (i0 + u < i1) {
+          if (f + u < f1) {
             const int lc = (int)(r[u] & 0xFFu) - c0;
             if (lc < 0 || lc >= ncw) continue;
             if (lc != cur) {
@@ -1463,7 +1480,9 @@ template <typename Rows>
 __global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ walks,
                                                     const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   if (C.st->k >= C.st->iters) return;
   const StageRowTask T = C.plan.stage_rtasks[lb];
   if (T.rb < 0) return;
@@ -1531,7 +1550,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_score(
     const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   if (C.st->k >= C.st->iters) return;
   __shared__ StageScoreSmem sm;
   __shared__ StageSegs G;
@@ -1713,7 +1734,9 @@ template <typename Rows>
 __global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                    int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters) return;
@@ -1829,7 +1852,9 @@ template <int CAP, typename Rows>
 __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                     int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const double* x = C.x;
   const Rows rs = rows_of<Rows>(C);
@@ -1880,7 +1905,9 @@ template <typename Rows>
 __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ walks,
                                                     const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const double* x = C.x;
   const Rows rs = rows_of<Rows>(C);
@@ -2186,7 +2213,7 @@ template <typename Rows>
 
 hipError_t launch_pass_rows(const BatchLaunch& L, hipStream_t stream, const PassStreams* ps, bool defer_combine) {
   const int nw = L.nw;
-  auto grid = [&](int slot) { return dim3((unsigned)L.total[slot]); };
+  auto grid = [&](int slot) { return dim3((unsigned)L.grid[slot]); };
   // a launch error (say, an LDS size the device refuses) is kept by the first
   // check after it; later successful calls would otherwise clear it
   hipError_t first = hipSuccess;

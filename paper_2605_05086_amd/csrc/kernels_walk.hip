@@ -59,21 +59,6 @@ __device__ __forceinline__ int viol_change(double r, double r2, double eps) {
   return (r2 > eps ? 1 : 0) - (r > eps ? 1 : 0);
 }
 
-// Walk of this block and the block's index inside that walk (off is the
-// prefix of per-walk block counts).
-__device__ __forceinline__ int block_walk(const int32_t* __restrict__ off, int nw, int& local) {
-  const int b = blockIdx.x;
-  int lo = 0, hi = nw - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  local = b - off[lo];
-  return lo;
-}
 
 // The objective-related part of a walk state, held in registers by every
 // lane of one wavefront (uniform values; lane 0 writes them back).
@@ -419,7 +404,9 @@ constexpr int kPartialStride = kArgmaxRecord;
 __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                 int32_t nw, int32_t combine) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const gptr<const double> s = gmem((const double*)C.s);
   const gptr<const int32_t> tabu = gmem((const int32_t*)C.tabu);
   const gptr<const int32_t> perm = gmem(C.P.perm);
@@ -688,7 +675,9 @@ __global__ __launch_bounds__(256) void k_subset_select(const WalkCtx* __restrict
 __global__ __launch_bounds__(256) void k_apply(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   const DevProblem& P = C.P;
   const double* x = C.x;
   RowState* rs = C.rs;
@@ -841,7 +830,9 @@ __global__ __launch_bounds__(256) void k_copy_best(const double* __restrict__ x,
 __global__ __launch_bounds__(256) void k_copy_best_batch(const WalkCtx* __restrict__ walks,
                                                          const int32_t* __restrict__ off, int32_t nw) {
   int lb;
-  const WalkCtx& C = walks[block_walk(off, nw, lb)];
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
   if (!C.st->copy_best || lb >= C.argmax_blocks) return;
   const int gs = C.argmax_blocks * blockDim.x;
   for (int q = lb * blockDim.x + threadIdx.x; q < C.P.n; q += gs) C.best_x[q] = C.x[q];
@@ -969,14 +960,14 @@ hipError_t launch_state_init(const DevProblem& P, const double* x, const RowStat
 hipError_t launch_walk_choose(const BatchLaunch& L, hipStream_t stream, bool combine) {
   const int nw = L.nw;
   const int32_t comb = (combine && pass_defers_combine(L)) ? 1 : 0;
-  hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw,
+  hipLaunchKernelGGL(k_argmax, dim3((unsigned)L.grid[KS_ARGMAX]), dim3(256), 0, stream, L.walks, L.off[KS_ARGMAX], nw,
                      comb);
   hipLaunchKernelGGL(k_select, dim3((unsigned)nw), dim3(256), 0, stream, L.walks);
   return hipGetLastError();
 }
 
 hipError_t launch_walk_apply(const BatchLaunch& L, hipStream_t stream) {
-  hipLaunchKernelGGL(k_apply, dim3((unsigned)L.total[KS_APPLY]), dim3(256), 0, stream, L.walks, L.off[KS_APPLY], L.nw);
+  hipLaunchKernelGGL(k_apply, dim3((unsigned)L.grid[KS_APPLY]), dim3(256), 0, stream, L.walks, L.off[KS_APPLY], L.nw);
   return hipGetLastError();
 }
 
@@ -998,7 +989,7 @@ hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t
 }
 
 hipError_t launch_copy_best_batch(const BatchLaunch& L, hipStream_t stream) {
-  hipLaunchKernelGGL(k_copy_best_batch, dim3((unsigned)L.total[KS_ARGMAX]), dim3(256), 0, stream, L.walks,
+  hipLaunchKernelGGL(k_copy_best_batch, dim3((unsigned)L.grid[KS_ARGMAX]), dim3(256), 0, stream, L.walks,
                      L.off[KS_ARGMAX], L.nw);
   return hipGetLastError();
 }
