@@ -109,6 +109,9 @@ def main():
                     help="skip the learned-proposal and batched-walk comparisons against the plain walk")
     ap.add_argument("--batch-iters", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-walk comparison")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="of the comparisons run only the batch itself (no learned forms, no one-by-one "
+                         "walks); for kernel traces of the batched iteration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path does not "
@@ -214,7 +217,9 @@ def main():
                                "instance)",
                      "bytes_per_launch": B},
     }
-    if not args.no_compare:
+    if args.batched_only:
+        result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small, plain=False)
+    elif not args.no_compare:
         result["learned"] = compare_learned(chap, G, args.compare_iters, tenure, seed)
         del G
         if not args.no_batched:
@@ -350,11 +355,11 @@ def small_configs(chap, tenure):
     return out
 
 
-def compare_batched(chap, iters, tenure, small):
+def compare_batched(chap, iters, tenure, small, plain=True):
     """256 walks over the pool of general instances (walk w on instance
     w mod P, start seed w + 1) as one batch, against the same walks run one by
-    one. Both give identical trajectories (same final score); the ratio of
-    GPU times is the speedup at equal final score."""
+    one (plain=False: the batch alone). Both give identical trajectories (same
+    final score); the ratio of GPU times is the speedup at equal final score."""
     import torch
 
     import mipgen
@@ -373,6 +378,19 @@ def compare_batched(chap, iters, tenure, small):
     runs = chap.batch_run(probs, wp, ws, iters, tenure)
     bwall = time.perf_counter() - t0
     bms = runs[0].elapsed_ms
+    # algorithmic bytes of one batched iteration: every walk's pass (cutoff
+    # rows counted where a walk's cutoff is active at its end)
+    bpi = sum(algorithmic_bytes(pool[wp[w]], math.isfinite(runs[w].cutoff_rhs)) for w in range(nw))
+    roof = {"bytes_per_batched_iter": int(bpi), "achieved_GBps": bpi * iters / (bms * 1e-3) / 1e9,
+            "peak_GBps": 8000.0}
+    roof["frac"] = roof["achieved_GBps"] / roof["peak_GBps"]
+    log(f"batched roofline: {bpi / 1e6:.1f} MB per batched iteration, {roof['achieved_GBps']:.0f} GB/s "
+        f"({100 * roof['frac']:.1f} % of 8 TB/s, graph time including walk set-up)")
+    if not plain:
+        log(f"batched: {bms:.1f} ms (GPU graphs), {bms / iters:.3f} ms per batched iteration")
+        return {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
+                "batched_gpu_ms": bms, "batched_wall_s": bwall, "roofline": roof,
+                "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3)}}
     pms = 0.0
     pwall = 0.0
     same = True
@@ -384,7 +402,7 @@ def compare_batched(chap, iters, tenure, small):
         same = same and np.array_equal(r.trace, runs[w].trace)
     out = {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
            "batched_gpu_ms": bms, "plain_gpu_ms_sum": pms, "batched_wall_s": bwall, "plain_wall_s": pwall,
-           "identical_trajectories": bool(same), "speedup_at_equal_final_score": pms / bms,
+           "identical_trajectories": bool(same), "speedup_at_equal_final_score": pms / bms, "roofline": roof,
            "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3), "plain": nw * iters / (pms * 1e-3)}}
     log(f"batched: {bms:.1f} ms vs plain {pms:.1f} ms (GPU graphs), identical={same}")
     return out
