@@ -109,6 +109,8 @@ def main():
                     help="skip the learned-proposal and batched-walk comparisons against the plain walk")
     ap.add_argument("--batch-iters", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-walk comparison")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="run only configurations 1 and 2 (plain and affected rescoring) and print them")
     ap.add_argument("--batched-only", action="store_true",
                     help="of the comparisons run only the batch itself (no learned forms, no one-by-one "
                          "walks); for kernel traces of the batched iteration")
@@ -125,6 +127,10 @@ def main():
 
     assert torch.cuda.is_available()
     chap.load_library()
+    if args.configs_only:
+        # configurations 1 and 2 alone (kernel traces of their paths); not the bench line
+        print(json.dumps({"configs": small_configs(chap, 10)}), flush=True)
+        return
     t0 = time.perf_counter()
     if args.small:
         mip = mipgen.powerlaw(0, n=200_000, m=100_000, nnz=2_000_000, cap=20_000)
@@ -322,7 +328,8 @@ def compare_learned(chap, G, iters, tenure, seed):
 
 def small_configs(chap, tenure):
     """Configurations 1 and 2: iterations per second of the walk and the
-    best-shift pass time (HIP events), with nonzeros per second."""
+    best-shift pass time (HIP events), with nonzeros per second; and the same
+    walks with affected rescoring."""
     import torch
 
     import mipgen
@@ -351,7 +358,23 @@ def small_configs(chap, tenure):
                      "best_shift_nnz_per_s": nnz / (pass_ms * 1e-3),
                      "final_viol": int(run.trace["viol"][-1]), "best_obj": run.best_obj}
         log(f"{name}: {iters / wall:.0f} it/s, pass {pass_ms * 1e3:.1f} us")
-        del G
+        # affected rescoring: the same walk, scoring after each plain move only
+        # the columns that share a row with the moved column
+        R = chap.Problem(mip, rescore_cap=1024)
+        R.tabu_run(iters, tenure, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr = R.tabu_run(iters, tenure, 0)
+        torch.cuda.synchronize()
+        rwall = time.perf_counter() - t0
+        out[name]["affected_rescoring"] = {
+            "rescore_cap": 1024, "iters_per_s": iters / rwall, "ms_per_iter": rwall * 1e3 / iters,
+            "graph_ms_per_iter": rr.elapsed_ms / iters, "rescored_iters": int(rr.rescored),
+            "identical_trajectory": bool(np.array_equal(rr.trace, run.trace)),
+            "speedup": (iters / rwall) / (iters / wall)}
+        log(f"{name} affected rescoring: {iters / rwall:.0f} it/s ({rr.rescored} of {iters} iterations rescored "
+            f"the affected columns only), identical={out[name]['affected_rescoring']['identical_trajectory']}")
+        del G, R
     return out
 
 

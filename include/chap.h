@@ -69,6 +69,20 @@ typedef struct {
                            records made by workgroups that each gather rows
                            from one eighth of the rows (the same results,
                            fewer HBM bytes); -1: never */
+  int32_t rescore_cap;  /* affected rescoring of chap_tabu_run walks: 0
+                           (default) scores every column every iteration;
+                           > 0 (at most 4096): after a move that changes
+                           no weight, no incumbent and no cutoff residual,
+                           only the columns sharing a row with the moved
+                           column (and the moved column) are scored again
+                           when they are at most rescore_cap columns, every
+                           other score being unchanged (section 3.1 "Memory
+                           Considerations", first paragraph); otherwise the
+                           iteration scores every column. Same trajectory as
+                           0. Disables row_stage (the staged pass leaves the
+                           long columns' scores to the move selection).
+                           chap_batch_run and chap_learned_run walks score
+                           every column. */
 } chap_options;
 
 /* One trace record per tabu iteration (48 bytes, host order). */
@@ -284,6 +298,12 @@ int chap_run_best_infeasible(const chap_run *r, double *x, int64_t *violated, in
 /* GPU time of the run's iteration graphs in milliseconds (HIP events); for
  * a batch, the time of the whole batch. */
 double chap_run_elapsed_ms(const chap_run *r);
+
+/* Iterations of a chap_tabu_run walk that scored only the columns affected
+ * by the previous move (problems created with rescore_cap > 0; section 3.1
+ * "Memory Considerations", first paragraph); 0 for other runs. Errors:
+ * CHAP_EINVAL (null argument). */
+int chap_run_rescored(const chap_run *r, int64_t *iters);
 
 void chap_run_destroy(chap_run *r);
 

@@ -27,7 +27,8 @@ TRACE_DTYPE = np.dtype([
 
 class ChapOptions(ctypes.Structure):
     _fields_ = [("feas_tol", ctypes.c_double), ("graph_iters", ctypes.c_int32), ("short_max", ctypes.c_int32),
-                ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("row_stage", ctypes.c_int32)]
+                ("chunk_min", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("row_stage", ctypes.c_int32),
+                ("rescore_cap", ctypes.c_int32)]
 
 
 class LearnedOptions(ctypes.Structure):
@@ -112,6 +113,8 @@ def load_library():
     lib.chap_learned_run.restype = ctypes.c_int
     lib.chap_run_learned_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.chap_run_learned_stats.restype = ctypes.c_int
+    lib.chap_run_rescored.argtypes = [P, ctypes.POINTER(i64)]
+    lib.chap_run_rescored.restype = ctypes.c_int
     lib.chap_run_proposals.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
     lib.chap_run_proposals.restype = ctypes.c_int
     lib.chap_run_pairs.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
@@ -183,6 +186,9 @@ class Run:
         ev, hi, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.chap_run_learned_stats(handle, ctypes.byref(ev), ctypes.byref(hi), ctypes.byref(st)))
         self.evals, self.hits, self.stalls = ev.value, hi.value, st.value
+        rs = ctypes.c_int64()
+        _check(lib.chap_run_rescored(handle, ctypes.byref(rs)))
+        self.rescored = rs.value
         sets, offs, iters = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
         _check(lib.chap_run_proposals(handle, ctypes.byref(sets), ctypes.byref(offs), ctypes.byref(iters)))
         self.set_offsets = None
@@ -254,7 +260,7 @@ class Problem:
     """chap_problem_create on a MIP in original form (host numpy arrays)."""
 
     def __init__(self, mip, feas_tol: float = 1e-6, graph_iters: int = 0, short_max: int = 0, chunk_min: int = 0,
-                 chunk_len: int = 0, row_stage: int = 0):
+                 chunk_len: int = 0, row_stage: int = 0, rescore_cap: int = 0):
         lib = load_library()
         self._keep = dict(
             csr_row_ptr=np.ascontiguousarray(mip.csr_row_ptr, dtype=np.int64),
@@ -277,6 +283,7 @@ class Problem:
         o.chunk_min = chunk_min
         o.chunk_len = chunk_len
         o.row_stage = row_stage
+        o.rescore_cap = rescore_cap
         h = ctypes.c_void_p()
         k = self._keep
         _check(lib.chap_problem_create(ctypes.byref(h), int(mip.n), int(mip.m), _ptr(k["csr_row_ptr"]),

@@ -123,6 +123,7 @@ void chap_options_default(chap_options* opt) {
   opt->chunk_min = 4096;
   opt->chunk_len = 4096;
   opt->row_stage = 1;
+  opt->rescore_cap = 0;
 }
 
 const char* chap_last_error(void) { return g_error.c_str(); }
@@ -154,8 +155,10 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
       return fail(CHAP_EINVAL, "chap_problem_create: feas_tol must be finite and >= 0");
     o.feas_tol = opt->feas_tol;
     if (opt->graph_iters < 0 || opt->short_max < 0 || opt->short_max > kShortMax || opt->chunk_min < 0 ||
-        opt->chunk_len < 0 || opt->row_stage < -1 || opt->row_stage > 1)
+        opt->chunk_len < 0 || opt->row_stage < -1 || opt->row_stage > 1 || opt->rescore_cap < 0 ||
+        opt->rescore_cap > kRescoreCapMax)
       return fail(CHAP_EINVAL, "chap_problem_create: option out of range");
+    o.rescore_cap = opt->rescore_cap;
     if (opt->row_stage) o.row_stage = opt->row_stage;
     if (opt->graph_iters) o.graph_iters = opt->graph_iters;
     if (opt->short_max) o.short_max = opt->short_max;
@@ -366,7 +369,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   // xbar + (eps - r)/a near [l, u] (error below 6 * 2^-53 * max(|l|,|u|) + 1
   // relative units) under eps / max|a|, the least distance of that quotient
   // from an integer, so the FP64 breakpoint equals the integer one.
-  bool stage = P->compact_ok && o.row_stage == 1 && P->eps > 0.0 && P->eps <= 0.5;
+  bool stage = P->compact_ok && o.row_stage == 1 && o.rescore_cap == 0 && P->eps > 0.0 && P->eps <= 0.5;
   if (stage) {
     double amax = 0.0, lmax = 0.0;
     for (double a : rval) amax = std::max(amax, std::fabs(a));
@@ -1183,6 +1186,72 @@ int slot_setup(const chap_problem* p, WalkSlot& S) {
   for (hipEvent_t& e : S.ev) CHAP_HIP(hipEventCreate(&e));
   std::vector<WalkCtx> one{S.ctx};
   CHAP_HIP(build_launch(S.A, one, &S.L, nullptr));
+  if (p->opt.rescore_cap > 0) {
+    // affected rescoring: the subset pass's record and the lane list, fed
+    // with the affected columns of each iteration (or with all columns)
+    const int32_t n = p->n;
+    const int32_t cap = p->opt.rescore_cap;
+    const int32_t* seg = p->plan.short_seg;
+    AffLists& F = S.aff;
+    CHAP_HIP(S.A.alloc(&F.stamp, (size_t)std::max<int32_t>(n, 1)));
+    CHAP_HIP(S.A.alloc(&F.slist, (size_t)cap + (size_t)kWave * kAffClasses));
+    CHAP_HIP(S.A.alloc(&F.olist, (size_t)cap));
+    CHAP_HIP(S.A.alloc(&F.ooff, (size_t)cap + 1));
+    CHAP_HIP(S.A.alloc(&F.run, 1));
+    CHAP_HIP(hipMemset(F.run, 0, sizeof(AffRun)));
+    F.cap = cap;
+    // all columns, split as an iteration's list is, when every column outside
+    // the short range has a subset form
+    bool all = n > 0;
+    std::vector<int32_t> sl, ol, oo(1, 0);
+    for (int c = 0; c < kAffClasses; ++c) {
+      const int32_t lo = seg[c], hi = seg[c + 1];
+      for (int32_t q = lo; q < hi; ++q) sl.push_back(q);
+      while (sl.size() % kWave) sl.push_back(-1);
+    }
+    for (int32_t q = 0; q < n; ++q) {
+      if (q >= seg[0] && q < seg[kShortMax + 2]) continue;
+      const uint8_t cl = p->sub_cls[q];
+      if (cl == SUB_NONE) all = false;
+      ol.push_back(q);
+      const int32_t c = (cl == SUB_GENERAL || cl == SUB_NONE)
+                            ? 0
+                            : std::max<int32_t>(1, (p->col_entries[q] + kSubsetChunk - 1) / kSubsetChunk);
+      oo.push_back(oo.back() + c);
+    }
+    int64_t sub_cap = p->nnz / kSubsetChunk + cap + 1;
+    if (all) {
+      int32_t *d_sl = nullptr, *d_ol = nullptr, *d_oo = nullptr;
+      CHAP_HIP(S.A.upload(&d_sl, sl.empty() ? std::vector<int32_t>(1, -1) : sl));
+      CHAP_HIP(S.A.upload(&d_ol, ol.empty() ? std::vector<int32_t>(1, 0) : ol));
+      CHAP_HIP(S.A.upload(&d_oo, oo));
+      F.full_slist = d_sl;
+      F.full_olist = d_ol;
+      F.full_ooff = d_oo;
+      F.n_full_s = (int32_t)sl.size();
+      F.n_full_o = (int32_t)ol.size();
+      F.full_chunks = oo.back();
+      sub_cap = std::max<int64_t>(sub_cap, oo.back());
+    }
+    F.sub_cap = (int32_t)std::min<int64_t>(INT32_MAX, sub_cap);
+    LearnCtx& L = S.aff_Lh;
+    L = LearnCtx{};
+    uint8_t* d_cls;
+    CHAP_HIP(S.A.upload(&d_cls, p->sub_cls));
+    L.cls = d_cls;
+    L.short_lane = 1;
+    L.K[0] = cap;
+    L.sel[0] = F.olist;
+    L.sub_off = F.ooff;
+    L.sub_cap = F.sub_cap;
+    CHAP_HIP(S.A.alloc(&L.sub_parts, (size_t)L.sub_cap));
+    CHAP_HIP(S.A.alloc(&L.ls, 1));
+    CHAP_HIP(hipMemset(L.ls, 0, sizeof(LearnState)));
+    CHAP_HIP(S.A.alloc(&S.aff_L, 1));
+    CHAP_HIP(hipMemcpy(S.aff_L, &L, sizeof(LearnCtx), hipMemcpyHostToDevice));
+    S.aff_general = 0;
+    for (uint8_t c : p->sub_cls) S.aff_general |= (c == SUB_GENERAL) ? 1 : 0;
+  }
   return CHAP_OK;
 }
 
@@ -1196,8 +1265,25 @@ int slot_graph(WalkSlot& S, int64_t K, int compact, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
   CHAP_HIP(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
   hipError_t cap_err = hipSuccess;
+  const AffLists& F = S.aff;
+  const int32_t n = S.ctx.P.n;
   for (int64_t q = 0; q < K && cap_err == hipSuccess; ++q) {
-    cap_err = launch_pass(S.L, S.s, &S.ps, true);
+    if (S.aff_L) {
+      // affected rescoring: the lists, the full pass only where no split of
+      // all columns exists, the short columns by lanes, the rest by the
+      // subset kernels
+      cap_err = launch_affected(S.L.walks, S.aff_L, F, S.s);
+      if (cap_err == hipSuccess && !F.full_slist) cap_err = launch_pass(S.L, S.s, &S.ps, true);
+      if (cap_err == hipSuccess)
+        cap_err = launch_aff_short(S.L.walks, F.run, std::min(1024, (n + 255) / 256), compact, S.s);
+      if (cap_err == hipSuccess && S.aff_general)
+        cap_err = launch_aff_wave(S.L.walks, S.aff_L, std::min(256, (n + 3) / 4), compact, S.s);
+      if (cap_err == hipSuccess)
+        cap_err = launch_subset_grids(S.L.walks, S.aff_L, std::min(256, F.sub_cap), 64, 32, S.aff_general, compact,
+                                      S.s);
+    } else {
+      cap_err = launch_pass(S.L, S.s, &S.ps, true);
+    }
     if (cap_err == hipSuccess) cap_err = launch_walk_step(S.L, S.s, true);
   }
   const hipError_t end_err = hipStreamEndCapture(S.s, &graph);
@@ -1275,6 +1361,13 @@ int run_single(chap_problem* p, uint64_t seed, const double* x0, int64_t iters, 
   CHAP_HIP(hipStreamWaitEvent(S.s, S.ev[0], 0));
   int rc = init_walk(spec, iters, tenure, S.ctx, S.partial, S.ticket, S.s);
   if (rc != CHAP_OK) return rc;
+  if (S.aff_L) {
+    // stamps of earlier runs on this slot could equal this run's iteration tags
+    if (p->n > 0) {
+      hipLaunchKernelGGL(k_fill_i32, dim3((p->n + 255) / 256), dim3(256), 0, S.s, S.aff.stamp, 0, (int64_t)p->n);
+      CHAP_HIP(hipGetLastError());
+    }
+  }
   std::unique_ptr<chap_run> R(new chap_run());
   R->trace.resize((size_t)iters);
   WalkState st;

@@ -305,6 +305,12 @@ int chap_run_learned_stats(const chap_run* r, int64_t* evals, int64_t* hits, int
   return CHAP_OK;
 }
 
+int chap_run_rescored(const chap_run* r, int64_t* iters) {
+  if (!r || !iters) return fail(CHAP_EINVAL, "chap_run_rescored: null argument");
+  *iters = r->st_end.aff_iters;
+  return CHAP_OK;
+}
+
 int chap_run_proposals(const chap_run* r, const int32_t** sets, const int64_t** offsets, int64_t* iters) {
   if (!r || !sets || !offsets || !iters) return fail(CHAP_EINVAL, "chap_run_proposals: null argument");
   *sets = r->sets.data();

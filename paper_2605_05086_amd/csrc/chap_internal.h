@@ -181,12 +181,20 @@ struct __align__(16) WalkState {
   // the call (epoch) whose point did not fit the byte copy of x (see
   // launch_stage_x); 0 after the state is cleared
   uint32_t x_misfit;
-  uint32_t pad_;
+  // 1 when the last step was a move whose only effect on the scores is
+  // through the rows of the moved column: no reweight, no incumbent update,
+  // and no cutoff row change (inactive, or c = 0 on the moved column)
+  int32_t aff_ok;
   // best infeasible point so far: the fewest violated normalised rows (the
   // cutoff row not counted) among the infeasible points visited, and the
   // iteration after which it was reached (-1: the start, -2: none yet)
   int64_t inf_V;
   int64_t inf_k;
+  // affected rescoring: this iteration's full pass does nothing (the
+  // affected columns are scored by the subset pass instead)
+  int32_t pass_skip;
+  int32_t pad2_;
+  int64_t aff_iters;  // iterations scored by the subset pass (affected rescoring)
 };
 
 // A slice of a long narrow-integer column handled by one workgroup; col < 0
@@ -541,6 +549,7 @@ constexpr int kTopkMax = 8192;      // largest proposal set
 constexpr int kSubsetCap = 4096;    // breakpoint capacity of the subset sort workgroup
 constexpr int kSubsetChunk = 2048;  // stored entries per workgroup chunk of the subset pass
 constexpr int kSubsetGrid = 2048;   // workgroups of the subset chunk kernel (grid-stride)
+constexpr int kRescoreCapMax = 4096;  // largest rescore_cap (columns of an affected set, listed in LDS)
 constexpr int kRefreshShort = 64;   // stored entries up to which 8 lanes refresh a column
 constexpr int kRefreshChunk = 4096; // stored entries per workgroup chunk of the long-column refresh
 constexpr int kStallKind = 3;       // trace kind of a proposal iteration without a move
@@ -582,6 +591,9 @@ struct LearnCtx {
   const uint8_t* cls;        // SUB_* per internal column
   const int32_t* elig_list;  // internal indices of proposable columns
   int32_t n_elig;
+  // 1: listed short columns (the plan's short range) are scored one per lane
+  // by k_aff_short, and the subset kernels leave them alone
+  int32_t short_lane;
   int32_t mp;                // normalised rows (for the violated fraction)
   double c_max;              // max |c_j| (0 when c = 0)
   // row refresh work: short proposable columns, chunks of long ones
@@ -645,6 +657,54 @@ hipError_t launch_learn_features_out(const WalkCtx* C, const LearnCtx* L, int32_
 // Exact best shift of the proposal set (kernels_pass.hip).
 hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
                               hipStream_t s);
+// The same kernels with explicit grids (each kernel strides over its work).
+hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
+                               int has_general, int compact, hipStream_t s);
+
+// The lists of affected rescoring. The affected columns of an iteration are
+// split into its short columns (slist: grouped by short class, binaries then
+// D = 0..8 stored entries, each class padded with -1 to a multiple of 64 so
+// that a wavefront holds one class) and the rest (olist, with the subset
+// chunk offsets ooff). When every column has a subset form, the same split
+// of all columns (full_*) serves iterations that must score every column.
+struct AffRun {
+  const int32_t* slist;  // short columns of this iteration (-1: padding)
+  int32_t n_s;           // entries of slist, padding included
+  int32_t pad_;
+};
+constexpr int kAffClasses = kShortMax + 2;  // binaries, then D = 0..kShortMax
+constexpr int kAffRows = 256;  // rows of a moved column up to which its affected columns are listed
+
+struct AffLists {
+  int32_t* stamp = nullptr;  // n
+  int32_t* slist = nullptr;  // cap + 64 kAffClasses
+  int32_t* olist = nullptr;  // cap
+  int32_t* ooff = nullptr;   // cap + 1
+  AffRun* run = nullptr;     // 1
+  int32_t cap = 0;
+  int32_t sub_cap = 0;
+  const int32_t* full_slist = nullptr;  // null: those iterations run the full pass
+  const int32_t* full_olist = nullptr;
+  const int32_t* full_ooff = nullptr;
+  int32_t n_full_s = 0;
+  int32_t n_full_o = 0;
+  int32_t full_chunks = 0;
+};
+
+// Affected rescoring of one walk (kernels_walk.hip). After a move whose
+// effect on the scores goes only through the rows of the moved column,
+// those rows' columns (and the moved column) are the only ones whose best
+// shift can change: k_aff_plan lists them and hands the list to the lane
+// kernel and the subset pass or, when it holds more than `cap` columns, a
+// column the subset pass cannot score, or more than `sub_cap` chunks, makes
+// the iteration score every column.
+hipError_t launch_affected(const WalkCtx* C, LearnCtx* L, const AffLists& A, hipStream_t s);
+// The iteration's short columns (AffRun), one lane each, as the full pass
+// scores them (kernels_pass.hip); grid-stride over the list.
+hipError_t launch_aff_short(const WalkCtx* C, const AffRun* run, int grid, int compact, hipStream_t s);
+// The iteration's listed general columns of at most 64 breakpoints, one
+// wavefront each (kernels_pass.hip).
+hipError_t launch_aff_wave(const WalkCtx* C, const LearnCtx* L, int grid, int compact, hipStream_t s);
 // Move choice over the proposal set and the stored-row update of its move
 // (kernels_walk.hip).
 hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s);
@@ -767,6 +827,11 @@ struct WalkSlot {
     hipGraphExec_t x;
   };
   std::vector<Graph> graphs;  // K iterations each (K a power of two or graph_iters)
+  // affected rescoring (problems created with rescore_cap > 0)
+  AffLists aff{};
+  LearnCtx* aff_L = nullptr;     // device record for the subset pass
+  LearnCtx aff_Lh{};             // its host copy
+  int aff_general = 0;           // the problem has general columns
   WalkSlot() = default;
   WalkSlot(const WalkSlot&) = delete;
   WalkSlot& operator=(const WalkSlot&) = delete;

@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks
   if (w_ < 0) return;
   const WalkCtx& C = walks[w_];
   const Rows rs = rows_of<Rows>(C);
-  if (C.st->k >= C.st->iters) return;
+  if (C.st->k >= C.st->iters || C.st->pass_skip) return;
   const int32_t* seg = C.plan.short_seg;
   const int q = seg[0] + lb * 256 + threadIdx.x;
   if (q >= seg[kShortMax + 2]) return;
@@ -374,6 +374,42 @@ __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks
   }
 }
 
+// The short columns of an affected-rescoring iteration, one lane each
+// (grid-stride over the list; classes padded to whole wavefronts, -1 marks
+// padding), with the full pass's per-column code.
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_aff_short(const WalkCtx* __restrict__ walks, const AffRun* __restrict__ run) {
+  const WalkCtx& C = walks[0];
+  if (C.st->k >= C.st->iters) return;
+  const Rows rs = rows_of<Rows>(C);
+  const int32_t* seg = C.plan.short_seg;
+  const int count = run->n_s;
+  const int32_t* list = run->slist;
+  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < count; i += (int)(gridDim.x * blockDim.x)) {
+    const int q = list[i];
+    if (q < 0) continue;
+    if (q < seg[1]) {
+      flip_column(C.P, C.x, rs, C.st, C.xhat, C.s, q);
+      continue;
+    }
+    int D = 0;
+#pragma unroll
+    for (int k = 1; k <= kShortMax; ++k)
+      if (q >= seg[1 + k]) D = k;
+    switch (D) {
+      case 0: short_general<0>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 1: short_general<1>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 2: short_general<2>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 3: short_general<3>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 4: short_general<4>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 5: short_general<5>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 6: short_general<6>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      case 7: short_general<7>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+      default: short_general<8>(C.P, C.x, rs, C.st, C.xhat, C.s, q); break;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_flip_wave: one wavefront per longer binary column.
 // ---------------------------------------------------------------------------
@@ -391,7 +427,7 @@ __global__ __launch_bounds__(256) void k_flip_wave(const WalkCtx* __restrict__ w
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->pass_skip) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int q = C.plan.flip_begin + lb * 4 + (threadIdx.x >> 6);
   if (q >= C.plan.flip_end) return;
@@ -461,7 +497,7 @@ __global__ __launch_bounds__(256) void k_narrow_pack(const WalkCtx* __restrict__
   const WalkState* st = C.st;
   double* xhat = C.xhat;
   double* sc = C.s;
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->pass_skip) return;
   __shared__ double bins[kPackCols][kNarrowBins];
   __shared__ double sbeta[kPackCols], salpha[kPackCols], sxb[kPackCols], sl[kPackCols], su[kPackCols];
   __shared__ unsigned long long scand[kPackCols];
@@ -616,7 +652,7 @@ __device__ __forceinline__ void chunk_task(const WalkCtx& C, int lb, ChunkSmem& 
   const Rows rs = rows_of<Rows>(C);
   const WalkState* st = C.st;
   ChunkPartial* partials = C.partials;
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->pass_skip) return;
   double* bins = S.bins;
   int32_t* ibins = S.ibins;
   double* red_b = S.red_b;
@@ -765,7 +801,7 @@ __global__ __launch_bounds__(256) void k_narrow_combine(const WalkCtx* __restric
   const int w_ = block_walk(off, nw, lb);
   if (w_ < 0) return;
   const WalkCtx& W0 = walks[w_];
-  if (W0.st->k >= W0.st->iters) return;
+  if (W0.st->k >= W0.st->iters || W0.st->pass_skip) return;
   const int idx = lb * 4 + (threadIdx.x >> 6);
   if (idx >= W0.plan.n_chunk_cols) return;
   int q;
@@ -1483,7 +1519,7 @@ __global__ __launch_bounds__(512) void k_stage_rows(const WalkCtx* __restrict__ 
   const int w_ = block_walk(off, nw, lb);
   if (w_ < 0) return;
   const WalkCtx& C = walks[w_];
-  if (C.st->k >= C.st->iters) return;
+  if (C.st->k >= C.st->iters || C.st->pass_skip) return;
   const StageRowTask T = C.plan.stage_rtasks[lb];
   if (T.rb < 0) return;
   __shared__ GatherRow rows[kStageRowBlock];
@@ -1553,7 +1589,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int w_ = block_walk(off, nw, lb);
   if (w_ < 0) return;
   const WalkCtx& C = walks[w_];
-  if (C.st->k >= C.st->iters) return;
+  if (C.st->k >= C.st->iters || C.st->pass_skip) return;
   __shared__ StageScoreSmem sm;
   __shared__ StageSegs G;
   if constexpr (std::is_same<Rows, DualRows>::value) {
@@ -1730,21 +1766,15 @@ __device__ __forceinline__ double wave_inclusive(double v, int lane) {
   return v;
 }
 
+// Algorithm 1 for general column j with at most 64 breakpoints (bounds and
+// cutoff included), by one wavefront: entries and breakpoints in registers,
+// a bitonic sort across the lanes, wavefront scan and argmax. Every lane of
+// the wavefront calls it with the same j; wv is the wavefront's slot in S.
 template <typename Rows>
-__global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
-                                                   int32_t nw) {
-  int lb;
-  const int w_ = block_walk(off, nw, lb);
-  if (w_ < 0) return;
-  const WalkCtx& C = walks[w_];
+__device__ __forceinline__ void sort_wave_column(const WalkCtx& C, const Rows& rs, int j, WaveSortSmem& S, int wv) {
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
-  if (st->k >= st->iters) return;
-  __shared__ WaveSortSmem S;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
-  const int j = C.plan.sort_begin[0] + lb * 4 + wv;
-  if (j >= C.plan.sort_begin[1]) return;  // whole wavefronts leave together
-  const Rows rs = rows_of<Rows>(C);
+  const int lane = threadIdx.x & (kWave - 1);
   const double eps = P.eps;
   const double xb = gmem((const double*)C.x)[j];
   const bool isint = P.is_int[j] != 0;
@@ -1848,6 +1878,43 @@ __global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ w
   if (lane == 0) write_result(C.xhat, C.s, j, found, bv, found ? bestp : xb, xb);
 }
 
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
+                                                   int32_t nw) {
+  int lb;
+  const int w_ = block_walk(off, nw, lb);
+  if (w_ < 0) return;
+  const WalkCtx& C = walks[w_];
+  const WalkState* st = C.st;
+  if (st->k >= st->iters || st->pass_skip) return;
+  __shared__ WaveSortSmem S;
+  const int wv = threadIdx.x >> 6;
+  const int j = C.plan.sort_begin[0] + lb * 4 + wv;
+  if (j >= C.plan.sort_begin[1]) return;  // whole wavefronts leave together
+  const Rows rs = rows_of<Rows>(C);
+  sort_wave_column<Rows>(C, rs, j, S, wv);
+}
+
+// The listed general columns of the wave-sort class (at most 64
+// breakpoints) in an affected-rescoring iteration: one wavefront each
+// (grid-stride over the subset list).
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_aff_wave(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
+  const WalkCtx& C = walks[0];
+  const LearnCtx& L = *lc;
+  if (C.st->k >= C.st->iters || L.ls->idle) return;
+  __shared__ WaveSortSmem S;
+  const int wv = threadIdx.x >> 6;
+  const Rows rs = rows_of<Rows>(C);
+  const int count = L.ls->tk[0].count;
+  const int q0 = C.plan.sort_begin[0], q1 = C.plan.sort_begin[1];
+  for (int i = (int)blockIdx.x * 4 + wv; i < count; i += (int)gridDim.x * 4) {
+    const int q = L.sel[0][i];
+    if (q < q0 || q >= q1) continue;  // uniform across the wavefront
+    sort_wave_column<Rows>(C, rs, q, S, wv);
+  }
+}
+
 template <int CAP, typename Rows>
 __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ walks, const int32_t* __restrict__ off,
                                                     int32_t nw) {
@@ -1864,7 +1931,7 @@ __global__ __launch_bounds__(256) void k_sort_block(const WalkCtx* __restrict__ 
   int c = 0;
   while (c < kSortCaps - 1 && kSortCap[c] != CAP) ++c;
   const int32_t q0 = C.plan.sort_begin[c];
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->pass_skip) return;
   __shared__ double spos[CAP];
   __shared__ double sdel[CAP];
   __shared__ int smk[CAP];
@@ -1917,7 +1984,7 @@ __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ 
   double* gpos = C.long_pos;
   int32_t* gmk = C.long_marker;
   double* gdel = C.long_delta;
-  if (st->k >= st->iters) return;
+  if (st->k >= st->iters || st->pass_skip) return;
   __shared__ int scount;
   __shared__ double red[16];
   __shared__ int redk[16];
@@ -2058,8 +2125,8 @@ __global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict
   }
 }
 
-// One wavefront per selected binary or narrow column: its chunks in order,
-// then the flip score or the bins' scan and argmax.
+// One wavefront per selected binary or narrow column (grid-stride): its
+// chunks in order, then the flip score or the bins' scan and argmax.
 __global__ __launch_bounds__(256) void k_subset_combine(const WalkCtx* __restrict__ walks,
                                                         const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
@@ -2067,38 +2134,41 @@ __global__ __launch_bounds__(256) void k_subset_combine(const WalkCtx* __restric
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= L.ls->tk[0].count) return;
-  const int q = L.sel[0][i];
-  const uint8_t cl = L.cls[q];
-  if (cl == SUB_GENERAL) return;
+  const int count = L.ls->tk[0].count;
   const int lane = threadIdx.x & 63;
-  const int c0 = L.sub_off[i], c1 = L.sub_off[i + 1];
-  const double xb = C.x[q];
-  if (cl == SUB_FLIP) {
-    double v = 0.0;
-    for (int c = c0; c < c1; ++c) v += L.sub_parts[c].beta;
-    if (lane == 0) write_result(C.xhat, C.s, q, true, v, 1.0 - xb, xb);
-    return;
+  for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += gridDim.x * 4) {
+    const int q = L.sel[0][i];
+    const uint8_t cl = L.cls[q];
+    if (cl == SUB_GENERAL) continue;
+    if (L.short_lane && q >= C.plan.short_seg[0] && q < C.plan.short_seg[kShortMax + 2]) continue;
+    const int c0 = L.sub_off[i], c1 = L.sub_off[i + 1];
+    const double xb = C.x[q];
+    if (cl == SUB_FLIP) {
+      double v = 0.0;
+      for (int c = c0; c < c1; ++c) v += L.sub_parts[c].beta;
+      if (lane == 0) write_result(C.xhat, C.s, q, true, v, 1.0 - xb, xb);
+      continue;
+    }
+    double bv = 0.0, b = 0.0, a = 0.0;
+    unsigned long long cand = 0ull;
+    for (int c = c0; c < c1; ++c) {
+      const ChunkPartial* pp = L.sub_parts + c;
+      bv += pp->bins[lane];
+      b += pp->beta;
+      a += pp->alpha;
+      cand |= pp->cand;
+    }
+    const double l = P.lb[q];
+    const int W = (int)(P.ub[q] - l) + 1;
+    bool found;
+    double best, bestp;
+    narrow_finish(bv, b, a, cand, xb, l, W, lane, found, best, bestp);
+    if (lane == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
   }
-  double bv = 0.0, b = 0.0, a = 0.0;
-  unsigned long long cand = 0ull;
-  for (int c = c0; c < c1; ++c) {
-    const ChunkPartial* pp = L.sub_parts + c;
-    bv += pp->bins[lane];
-    b += pp->beta;
-    a += pp->alpha;
-    cand |= pp->cand;
-  }
-  const double l = P.lb[q];
-  const int W = (int)(P.ub[q] - l) + 1;
-  bool found;
-  double best, bestp;
-  narrow_finish(bv, b, a, cand, xb, l, W, lane, found, best, bestp);
-  if (lane == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
 }
 
-// One workgroup per selected general column (Algorithm 1 with the LDS sort).
+// One workgroup per selected general column (grid-stride; Algorithm 1 with
+// the LDS sort).
 __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restrict__ walks,
                                                         const LearnCtx* __restrict__ lc) {
   const WalkCtx& C = walks[0];
@@ -2106,9 +2176,6 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
-  if ((int)blockIdx.x >= L.ls->tk[0].count) return;
-  const int q = L.sel[0][blockIdx.x];
-  if (L.cls[q] != SUB_GENERAL) return;
   __shared__ double spos[kSubsetCap];
   __shared__ double sdel[kSubsetCap];
   __shared__ int smk[kSubsetCap];
@@ -2116,48 +2183,82 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
   __shared__ double red[8];
   __shared__ int redk[8];
   const int tid = threadIdx.x;
-  const double xb = C.x[q];
-  if (tid == 0) scount = 0;
-  __syncthreads();
-  double beta = 0.0, alpha = 0.0;
-  general_phase1(P, FullRows{gmem((const RowState*)C.rs)}, st, q, xb, tid, blockDim.x, beta, alpha, [&](double p, int m, double d) {
-    const int k = atomicAdd(&scount, 1);
-    spos[k] = p;
-    smk[k] = m;
-    sdel[k] = d;
-  });
-  beta = block_sum256(beta, red);
-  alpha = block_sum256(alpha, red);
-  __syncthreads();
-  const int cnt = scount;
-  int cap = 64;
-  while (cap < cnt) cap <<= 1;
-  for (int i = cnt + tid; i < cap; i += blockDim.x) {
-    spos[i] = HUGE_VAL;
-    smk[i] = kPadMarker;
-    sdel[i] = 0.0;
+  const int count = L.ls->tk[0].count;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int q = L.sel[0][i];
+    if (L.cls[q] != SUB_GENERAL) continue;
+    // affected rescoring: short columns go to lanes, the wave-sort class to k_aff_wave
+    if (L.short_lane && ((q >= C.plan.short_seg[0] && q < C.plan.short_seg[kShortMax + 2]) ||
+                         (q >= C.plan.sort_begin[0] && q < C.plan.sort_begin[1])))
+      continue;
+    const double xb = C.x[q];
+    if (tid == 0) scount = 0;
+    __syncthreads();
+    double beta = 0.0, alpha = 0.0;
+    general_phase1(P, FullRows{gmem((const RowState*)C.rs)}, st, q, xb, tid, blockDim.x, beta, alpha,
+                   [&](double p, int m, double d) {
+                     const int k = atomicAdd(&scount, 1);
+                     spos[k] = p;
+                     smk[k] = m;
+                     sdel[k] = d;
+                   });
+    beta = block_sum256(beta, red);
+    alpha = block_sum256(alpha, red);
+    __syncthreads();
+    const int cnt = scount;
+    int cap = 64;
+    while (cap < cnt) cap <<= 1;
+    for (int t = cnt + tid; t < cap; t += blockDim.x) {
+      spos[t] = HUGE_VAL;
+      smk[t] = kPadMarker;
+      sdel[t] = 0.0;
+    }
+    __syncthreads();
+    bitonic_sort(spos, smk, sdel, cap);
+    bool found;
+    double best, bestp;
+    scan_argmax(spos, smk, sdel, cap, beta, alpha, xb, P.lb[q], P.ub[q], red, redk, found, best, bestp);
+    if (tid == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
+    // every reader of this column's LDS arrays is done before the next one
+    __syncthreads();
   }
-  __syncthreads();
-  bitonic_sort(spos, smk, sdel, cap);
-  bool found;
-  double best, bestp;
-  scan_argmax(spos, smk, sdel, cap, beta, alpha, xb, P.lb[q], P.ub[q], red, redk, found, best, bestp);
-  if (tid == 0) write_result(C.xhat, C.s, q, found, best, bestp, xb);
 }
 
 }  // namespace
 
-hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
-                              hipStream_t s) {
-  const int K = Lh.K[0];
-  const dim3 grid((unsigned)std::min(kSubsetGrid, std::max(Lh.sub_cap, 1)));
+hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
+                               int has_general, int compact, hipStream_t s) {
+  const dim3 grid((unsigned)std::max(chunk_grid, 1));
   if (compact)
     hipLaunchKernelGGL(k_subset_chunks<CompactRows>, grid, dim3(256), 0, s, C, L);
   else
     hipLaunchKernelGGL(k_subset_chunks<FullRows>, grid, dim3(256), 0, s, C, L);
-  hipLaunchKernelGGL(k_subset_combine, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, C, L);
-  if (has_general) hipLaunchKernelGGL(k_subset_general, dim3((unsigned)K), dim3(256), 0, s, C, L);
+  hipLaunchKernelGGL(k_subset_combine, dim3((unsigned)std::max(combine_grid, 1)), dim3(256), 0, s, C, L);
+  if (has_general) hipLaunchKernelGGL(k_subset_general, dim3((unsigned)std::max(general_grid, 1)), dim3(256), 0, s, C, L);
   return hipGetLastError();
+}
+
+hipError_t launch_aff_wave(const WalkCtx* C, const LearnCtx* L, int grid, int compact, hipStream_t s) {
+  if (compact)
+    hipLaunchKernelGGL(k_aff_wave<CompactRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, L);
+  else
+    hipLaunchKernelGGL(k_aff_wave<FullRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_aff_short(const WalkCtx* C, const AffRun* run, int grid, int compact, hipStream_t s) {
+  if (compact)
+    hipLaunchKernelGGL(k_aff_short<CompactRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, run);
+  else
+    hipLaunchKernelGGL(k_aff_short<FullRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
+                              hipStream_t s) {
+  const int K = Lh.K[0];
+  return launch_subset_grids(C, L, std::min(kSubsetGrid, std::max(Lh.sub_cap, 1)), (K + 3) / 4, K, has_general,
+                             compact, s);
 }
 
 int32_t kernel_blocks(const WalkCtx& c, int slot) {

@@ -366,6 +366,10 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
   st->mv_kind = 2;
   st->dV = 0ull;
   st->compact_rows = 1;
+  st->skip = 0;
+  st->aff_ok = 0;
+  st->pass_skip = 0;
+  st->aff_iters = 0;
 }
 
 __device__ __forceinline__ bool better(double sa, int ja, double sb, int jb) {
@@ -813,9 +817,16 @@ __global__ __launch_bounds__(64) void k_finish(const WalkCtx* __restrict__ walks
       }
     }
   }
+  // the next iteration may rescore only the columns of the moved column's
+  // rows when this step changed nothing else the scores depend on: no
+  // reweight, no cutoff residual change, no incumbent (which moves the
+  // cutoff row)
+  int aff = (jstar >= 0 && !(o.cut_active && P.obj[jstar] != 0.0)) ? 1 : 0;
+  if (o.V == 0) aff = 0;
   o.incumbent_check(eps, exact ? &acc : nullptr);
   if (lane != 0) return;
   o.store(st);
+  st->aff_ok = aff;
   st->dV = 0ull;
   st->k = k + 1;
 }
@@ -894,6 +905,214 @@ inline int blocks_for(int64_t work, int cap) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (int)b;
+}
+
+
+// ---------------------------------------------------------------------------
+// Affected rescoring. The best shift of column q depends on x_q, its bounds,
+// the residuals and weights of its rows and, when the cutoff row is active,
+// that row's residual and weight. A move of column j* with no reweight and
+// no change of the cutoff row changes only the residuals of j*'s rows, so
+// only x_j* and the columns sharing one of those rows need a new score.
+// ---------------------------------------------------------------------------
+
+// Short class of internal column q: 0 for a short binary, 1 + D for a short
+// non-binary column with D stored entries, -1 for a column outside the
+// short range.
+__device__ __forceinline__ int aff_class(const int32_t* seg, int q) {
+  if (q < seg[0] || q >= seg[kShortMax + 2]) return -1;
+  if (q < seg[1]) return 0;
+  int c = 1;
+#pragma unroll
+  for (int k = 1; k <= kShortMax; ++k)
+    if (q >= seg[1 + k]) c = 1 + k;
+  return c;
+}
+
+// One workgroup: lists the affected columns, splits the list into its short columns (grouped by
+// class, each class padded to whole wavefronts) and the rest, with the rest's
+// subset chunk offsets (ceil(entries / kSubsetChunk) chunks per binary or
+// narrow column, none for a general one), and skips the full pass. When the
+// step was not a plain move, the list is longer than cap, a listed column
+// has no subset form, or the chunks exceed sub_cap, the iteration scores
+// every column: through the split of all columns when there is one, else
+// through the full pass. Points the subset record and the lane list at the
+// lists it takes and clears the count.
+__global__ __launch_bounds__(256) void k_aff_plan(const WalkCtx* __restrict__ walks, LearnCtx* __restrict__ lc,
+                                                  AffLists A) {
+  const WalkCtx& C = walks[0];
+  WalkState* st = C.st;
+  LearnCtx& L = *lc;
+  if (st->k >= st->iters) return;
+  __shared__ int ccount[kAffClasses], cfill[kAffClasses], cbase[kAffClasses];
+  __shared__ int wsum[4];
+  __shared__ int carry, bad, n_other, n_s, n_mark;
+  const int tid = threadIdx.x;
+  // the affected columns: the moved column and the columns of its rows
+  // (stamp[q] = iteration + 1 marks a column already listed; stamps are
+  // cleared when the walk starts); at most cap are listed, all are counted.
+  // The rows' entries are taken as one flat range (prefix of the row
+  // lengths in LDS), so every thread's stamps are in flight at once; a
+  // column of more than kAffRows rows is left to the full scoring.
+  __shared__ int rpre[kAffRows + 1];
+  __shared__ int rrow[kAffRows];
+  __shared__ int lst[kRescoreCapMax];  // the affected list
+  __shared__ int olst[kRescoreCapMax];  // its columns outside the short range
+  if (tid == 0) n_mark = 0;
+  __syncthreads();
+  if (st->aff_ok) {
+    const DevProblem& P = C.P;
+    const int32_t tag = (int32_t)st->k + 1;
+    const int q0 = st->mv_j;
+    const int beg = P.col_ptr[q0], deg = P.col_ptr[q0 + 1] - beg;
+    if (deg > kAffRows) {
+      if (tid == 0) n_mark = A.cap + 1;
+    } else {
+      const int lane = tid & 63, wv = tid >> 6;
+      int len = 0;
+      if (tid < deg) {
+        const int i = P.col_row[beg + tid];
+        rrow[tid] = i;
+        len = P.row_ptr[i + 1] - P.row_ptr[i];
+      }
+      int inc = len;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) wsum[wv] = inc;
+      __syncthreads();
+      int off = inc - len;
+      for (int k = 0; k < wv; ++k) off += wsum[k];
+      if (tid < deg) rpre[tid] = off;
+      if (tid == deg - 1) rpre[deg] = off + len;
+      if (deg == 0 && tid == 0) rpre[0] = 0;
+      __syncthreads();
+      const int total = rpre[deg];
+      auto push = [&](int q) {
+        if (atomicExch(&A.stamp[q], tag) != tag) {
+          const int k = atomicAdd(&n_mark, 1);
+          if (k < A.cap) lst[k] = q;
+        }
+      };
+      if (tid == 0) push(q0);
+      for (int f = tid; f < total; f += 256) {
+        int lo = 0, hi = deg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rpre[mid] <= f)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        push(P.row_col[P.row_ptr[rrow[lo]] + (f - rpre[lo])]);
+      }
+    }
+  }
+  __syncthreads();
+  const int n_list = st->aff_ok ? n_mark : 0;
+  const bool listed = st->aff_ok && n_list <= A.cap;
+  const int32_t* seg = C.plan.short_seg;
+  if (tid < kAffClasses) {
+    ccount[tid] = 0;
+    cfill[tid] = 0;
+  }
+  if (tid == 0) {
+    carry = 0;
+    bad = 0;
+    n_other = 0;
+    n_s = 0;
+  }
+  __syncthreads();
+  if (listed) {
+    for (int i = tid; i < n_list; i += 256) {
+      const int q = lst[i];
+      const int c = aff_class(seg, q);
+      if (c >= 0) {
+        atomicAdd(&ccount[c], 1);
+      } else {
+        if (L.cls[q] == SUB_NONE) bad = 1;
+        const int k = atomicAdd(&n_other, 1);
+        olst[k] = q;
+        A.olist[k] = q;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int base = 0;
+      for (int c = 0; c < kAffClasses; ++c) {
+        cbase[c] = base;
+        base += (ccount[c] + kWave - 1) / kWave * kWave;
+      }
+      n_s = base;
+    }
+    __syncthreads();
+    for (int i = tid; i < n_list; i += 256) {
+      const int q = lst[i];
+      const int c = aff_class(seg, q);
+      if (c >= 0) A.slist[cbase[c] + atomicAdd(&cfill[c], 1)] = q;
+    }
+    for (int c = 0; c < kAffClasses; ++c) {
+      const int end = (ccount[c] + kWave - 1) / kWave * kWave;
+      for (int t = ccount[c] + tid; t < end; t += 256) A.slist[cbase[c] + t] = -1;
+    }
+    const int n_o = n_other;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int base = 0; base < n_o; base += 256) {
+      const int i = base + tid;
+      int c = 0;
+      if (i < n_o) {
+        const int q = olst[i];
+        const uint8_t cl = L.cls[q];
+        const int e = C.P.col_ptr[q + 1] - C.P.col_ptr[q];
+        c = (cl == SUB_GENERAL || cl == SUB_NONE) ? 0 : max(1, (e + kSubsetChunk - 1) / kSubsetChunk);
+      }
+      int inc = c;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) wsum[wv] = inc;
+      __syncthreads();
+      int off = carry + inc - c;
+      for (int k = 0; k < wv; ++k) off += wsum[k];
+      if (i < n_o) A.ooff[i] = off;
+      __syncthreads();
+      if (tid == 255) carry = off + c;
+      __syncthreads();
+    }
+  }
+  if (tid != 0) return;
+  const bool subset = listed && !bad && carry <= A.sub_cap;
+  if (subset) {
+    A.ooff[n_other] = carry;
+    L.sel[0] = A.olist;
+    L.sub_off = A.ooff;
+    L.ls->tk[0].count = n_other;
+    L.ls->tk[0].chunks = carry;
+    L.ls->idle = 0;
+    A.run->slist = A.slist;
+    A.run->n_s = n_s;
+    st->pass_skip = 1;
+    st->aff_iters += 1;
+  } else if (A.full_slist) {
+    L.sel[0] = const_cast<int32_t*>(A.full_olist);
+    L.sub_off = const_cast<int32_t*>(A.full_ooff);
+    L.ls->tk[0].count = A.n_full_o;
+    L.ls->tk[0].chunks = A.full_chunks;
+    L.ls->idle = 0;
+    A.run->slist = A.full_slist;
+    A.run->n_s = A.n_full_s;
+    st->pass_skip = 1;
+  } else {
+    L.ls->tk[0].count = 0;
+    L.ls->tk[0].chunks = 0;
+    L.ls->idle = 1;
+    A.run->n_s = 0;
+    st->pass_skip = 0;
+  }
 }
 
 }  // namespace
@@ -981,6 +1200,11 @@ hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream, bool combi
   if (e == hipSuccess) e = launch_walk_apply(L, stream);
   if (e == hipSuccess) e = launch_walk_finish(L, stream);
   return e;
+}
+
+hipError_t launch_affected(const WalkCtx* C, LearnCtx* L, const AffLists& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_aff_plan, dim3(1), dim3(256), 0, s, C, L, A);
+  return hipGetLastError();
 }
 
 hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s) {

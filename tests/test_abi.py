@@ -41,7 +41,14 @@ def test_header_symbols_exported(lib):
 def test_options_defaults(lib):
     o = chap.default_options()
     assert o.feas_tol == 1e-6 and o.graph_iters == 64 and o.short_max == 8
-    assert o.chunk_min == 4096 and o.chunk_len == 4096 and o.row_stage == 1
+    assert o.chunk_min == 4096 and o.chunk_len == 4096 and o.row_stage == 1 and o.rescore_cap == 0
+
+
+@pytest.mark.parametrize("cap", [-1, 4097])
+def test_rescore_cap_out_of_range(lib, cap):
+    mip = mipgen.random_mixed(3, n=10, m=6)
+    with pytest.raises(chap.ChapError, match="CHAP_EINVAL"):
+        chap.Problem(mip, rescore_cap=cap)
 
 
 def _create_rc(mip, **over):
