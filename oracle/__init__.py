@@ -53,6 +53,8 @@ def _load():
     lib.orc_residual.restype = i64
     lib.orc_residual.argtypes = [P, P, f64, P]
     lib.orc_best_shift.argtypes = [P, P, P, f64, P, i64, P, P]
+    lib.orc_jump_values.argtypes = [P, P, P, f64, P, P]
+    lib.orc_jump_values.restype = None
     lib.orc_start_point.argtypes = [P, u64, P]
     lib.orc_splitmix64.restype = u64
     lib.orc_splitmix64.argtypes = [u64, u64]
@@ -160,6 +162,16 @@ class OracleProblem:
             self._lib.orc_best_shift(self.h, _p(x), _p(w), float(cutoff_rhs), _p(cols), cols.shape[0],
                                      _p(xh), _p(s))
         return xh, s
+
+    def jump_values(self, x, w, cutoff_rhs: float = float("inf")):
+        """Jump value and jump score of every column (weighted violation)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape[0] == self.mp + 1
+        jv = np.empty(self.n)
+        js = np.empty(self.n)
+        self._lib.orc_jump_values(self.h, _p(x), _p(w), float(cutoff_rhs), _p(jv), _p(js))
+        return jv, js
 
     def objective(self, x) -> float:
         x = np.ascontiguousarray(x, dtype=np.float64)

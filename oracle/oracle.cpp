@@ -199,6 +199,84 @@ void best_shift_one(const OracleProblem& P, int32_t j, const double* x, const st
     alg1_best_shift(P, j, x[j], r, w, cutoff_active, xhat, s);
 }
 
+// ---- jump values (weighted violation, after Feasibility Jump) ------------
+// Section 3.1 "Best Shift Moves" recalls the jump value of Feasibility Jump
+// (its line sweep motivates Algorithm 1): the value of x_j that minimises the
+// weighted violation of x_j's constraints with the other variables held.
+// Readings (design notes): the violation of normalised row i at x_j = t is
+// max(0, r_i + a_ij (t - xbar_j)), its amount beyond the right-hand side,
+// weighted by w_i, and the cutoff row takes part when active, as in the
+// score; the jump leaves xbar_j (t != xbar_j); ties go to the value closest
+// to xbar_j, then to the smaller one; the jump score is V(xbar_j) - V(t*).
+
+// V_j(t): the weighted violation of j's normalised rows (ascending) and then
+// the cutoff row, with x_j = t and every other variable at the point.
+double weighted_violation(const OracleProblem& P, int32_t j, double xbar, const std::vector<double>& r,
+                          const float* w, bool cutoff_active, double t) {
+  const double d = t - xbar;
+  double v = 0.0;
+  for (const ColEntry& e : column_rows(P, j, cutoff_active)) {
+    const double y = r[e.row] + e.a * d;
+    v += (double)w[e.row] * (y > 0.0 ? y : 0.0);
+  }
+  return v;
+}
+
+// The jump value of column j and its score. An integer variable with at most
+// 64 values is tried at every value of its domain. Otherwise V_j is convex
+// and piecewise linear with kinks where a row's violation reaches zero,
+// t = xbar - r_i / a_ij, so its minimum over the domain lies at a kink (an
+// integer variable: the integers on either side of one), a finite bound, or,
+// for an integer variable whose minimum is at xbar itself, xbar - 1 or
+// xbar + 1; those are the values tried. No value to try: (xbar, 0).
+void jump_value_one(const OracleProblem& P, int32_t j, const double* x, const std::vector<double>& r,
+                    const float* w, bool cutoff_active, double* jv, double* js) {
+  const double xbar = x[j];
+  const double l = P.lb[j], u = P.ub[j];
+  const bool integer = P.is_int[j] != 0;
+  std::vector<double> cand;
+  if (integer && std::isfinite(l) && std::isfinite(u) && u - l + 1.0 <= 64.0) {
+    for (double t = l; t <= u; t += 1.0) cand.push_back(t);
+  } else {
+    for (const ColEntry& e : column_rows(P, j, cutoff_active)) {
+      const double kink = xbar - r[e.row] / e.a;
+      if (integer) {
+        cand.push_back(std::floor(kink));
+        cand.push_back(std::ceil(kink));
+      } else {
+        cand.push_back(kink);
+      }
+    }
+    cand.push_back(l);
+    cand.push_back(u);
+    if (integer) {
+      cand.push_back(xbar - 1.0);
+      cand.push_back(xbar + 1.0);
+    }
+  }
+  bool found = false;
+  double bt = xbar, bv = 0.0;
+  for (double t : cand) {
+    if (!std::isfinite(t) || t < l || t > u || t == xbar) continue;
+    const double v = weighted_violation(P, j, xbar, r, w, cutoff_active, t);
+    const bool better = !found || v < bv ||
+                        (v == bv && (std::fabs(t - xbar) < std::fabs(bt - xbar) ||
+                                     (std::fabs(t - xbar) == std::fabs(bt - xbar) && t < bt)));
+    if (better) {
+      found = true;
+      bt = t;
+      bv = v;
+    }
+  }
+  if (!found) {
+    *jv = xbar;
+    *js = 0.0;
+    return;
+  }
+  *jv = bt;
+  *js = weighted_violation(P, j, xbar, r, w, cutoff_active, xbar) - bv;
+}
+
 // r = A'x - b' over the normalised rows, in CSR order; cutoff row c^T x - bc.
 // Exactly rounded sum of a list of doubles. Each term is merged into a list
 // of nonoverlapping partials with error-free additions (Shewchuk, "Adaptive
@@ -447,6 +525,17 @@ void orc_best_shift(void* h, const double* x, const float* w, double cutoff_rhs,
     for (int64_t q = 0; q < ncols; ++q)
       best_shift_one(*P, cols[q], x, r, w, active, &xhat[q], &s[q]);
   }
+}
+
+// Jump value and jump score of every column at point x with weights w
+// (mp+1 entries), cutoff row active iff cutoff_rhs is finite.
+void orc_jump_values(void* h, const double* x, const float* w, double cutoff_rhs, double* jv, double* js) {
+  OracleProblem* P = (OracleProblem*)h;
+  bool active = !std::isinf(cutoff_rhs);
+  std::vector<double> r;
+  residual_from_scratch(*P, x, active, cutoff_rhs, r);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t j = 0; j < P->n; ++j) jump_value_one(*P, j, x, r, w, active, &jv[j], &js[j]);
 }
 
 // Threads of the per-column and per-row loops (1 = sequential).
