@@ -187,6 +187,39 @@ int chap_best_shift_noalloc(chap_problem *p, const double *d_x, const float *d_w
 size_t chap_best_shift_noalloc_max_bytes(void);
 
 /*
+ * chap_jump_values - the jump value of every variable: the value that
+ * minimises the weighted violation of the variable's constraints with every
+ * other variable held at d_x (the jump value of Feasibility Jump, which
+ * section 3.1 "Best Shift Moves" recalls as the move its line sweep
+ * generalises).
+ * For variable j, V_j(t) is the sum, over j's normalised rows in ascending
+ * order (an equality row: the row, then its negation) and then the cutoff
+ * row when active and c_j != 0, of w_i max(0, r_i + a_ij (t - xbar_j)), each
+ * term added to the sum in that order. The jump value minimises V_j over the
+ * domain (integers for integer variables) without xbar_j; ties go to the
+ * value closest to xbar_j, then to the smaller one. An integer variable with
+ * at most 64 values tries every value; any other variable the kinks of V_j
+ * (xbar_j - r_i / a_ij, for integers the integers on either side), its
+ * finite bounds and, for integers, xbar_j +- 1. The score is V_j(xbar_j) -
+ * V_j(t*) (may be negative); with no value to try the result is (xbar_j, 0).
+ *   d_x, d_w, cutoff_rhs, hip_stream  as chap_best_shift.
+ *   d_jump     device, n doubles, out: t*_j (original order).
+ *   d_score    device, n doubles, out: the jump score.
+ * Asynchronous. Columns with more than 4096 entries add per-chunk partial
+ * sums (exact on integer data; within rounding of the stored-order sum
+ * otherwise). Uses the buffers of chap_best_shift: calls of either function
+ * on one problem must not overlap. Errors: CHAP_EINVAL, CHAP_ENOMEM,
+ * CHAP_EHIP.
+ */
+int chap_jump_values(chap_problem *p, const double *d_x, const float *d_w, double cutoff_rhs,
+                     double *d_jump, double *d_score, void *hip_stream);
+
+/* Duration of the jump kernels (after the residual and weight set-up) of the
+ * most recent chap_jump_values call on this problem (HIP events on that
+ * call's stream); waits for that call. *ms = 0 before the first call. */
+int chap_jump_values_ms(chap_problem *p, double *ms);
+
+/*
  * chap_best_shift_pass_ms - duration of the best-shift kernels (the pass
  * after the residual and weight set-up) of the most recent chap_best_shift
  * call on this problem, measured with HIP events recorded on that call's

@@ -55,6 +55,8 @@ def _load():
     lib.orc_best_shift.argtypes = [P, P, P, f64, P, i64, P, P]
     lib.orc_jump_values.argtypes = [P, P, P, f64, P, P]
     lib.orc_jump_values.restype = None
+    lib.orc_weighted_violation.argtypes = [P, P, P, f64, i32, f64]
+    lib.orc_weighted_violation.restype = f64
     lib.orc_start_point.argtypes = [P, u64, P]
     lib.orc_splitmix64.restype = u64
     lib.orc_splitmix64.argtypes = [u64, u64]
@@ -172,6 +174,12 @@ class OracleProblem:
         js = np.empty(self.n)
         self._lib.orc_jump_values(self.h, _p(x), _p(w), float(cutoff_rhs), _p(jv), _p(js))
         return jv, js
+
+    def weighted_violation(self, x, w, j: int, t: float, cutoff_rhs: float = float("inf")) -> float:
+        """V_j(t): the weighted violation of column j's rows with x_j = t."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        return float(self._lib.orc_weighted_violation(self.h, _p(x), _p(w), float(cutoff_rhs), int(j), float(t)))
 
     def objective(self, x) -> float:
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -538,6 +538,15 @@ void orc_jump_values(void* h, const double* x, const float* w, double cutoff_rhs
   for (int32_t j = 0; j < P->n; ++j) jump_value_one(*P, j, x, r, w, active, &jv[j], &js[j]);
 }
 
+// V_j(t) at point x (the weighted violation the jump value minimises).
+double orc_weighted_violation(void* h, const double* x, const float* w, double cutoff_rhs, int32_t j, double t) {
+  OracleProblem* P = (OracleProblem*)h;
+  bool active = !std::isinf(cutoff_rhs);
+  std::vector<double> r;
+  residual_from_scratch(*P, x, active, cutoff_rhs, r);
+  return weighted_violation(*P, j, x[j], r, w, active, t);
+}
+
 // Threads of the per-column and per-row loops (1 = sequential).
 void orc_set_threads(int32_t k) { omp_set_num_threads(k > 0 ? k : 1); }
 int32_t orc_threads(void) { return (int32_t)omp_get_max_threads(); }

@@ -113,6 +113,10 @@ def load_library():
     lib.chap_learned_run.restype = ctypes.c_int
     lib.chap_run_learned_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.chap_run_learned_stats.restype = ctypes.c_int
+    lib.chap_jump_values.argtypes = [P, P, P, ctypes.c_double, P, P, P]
+    lib.chap_jump_values.restype = ctypes.c_int
+    lib.chap_jump_values_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.chap_jump_values_ms.restype = ctypes.c_int
     lib.chap_run_rescored.argtypes = [P, ctypes.POINTER(i64)]
     lib.chap_run_rescored.restype = ctypes.c_int
     lib.chap_run_proposals.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
@@ -336,6 +340,27 @@ class Problem:
             self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()), float(cutoff_rhs),
             ctypes.c_void_p(out_shift.data_ptr()), ctypes.c_void_p(out_score.data_ptr()), _stream_handle(stream)))
         return out_shift, out_score
+
+    def jump_values(self, x, w, cutoff_rhs: float = math.inf, out_jump=None, out_score=None, stream=None):
+        """chap_jump_values on device tensors x (n, float64) and w (m'+1,
+        float32); returns (jump value, jump score) device tensors."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n
+        assert w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.numel() == self.mp + 1
+        if out_jump is None:
+            out_jump = torch.empty_like(x)
+        if out_score is None:
+            out_score = torch.empty_like(x)
+        _check(load_library().chap_jump_values(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                               float(cutoff_rhs), ctypes.c_void_p(out_jump.data_ptr()),
+                                               ctypes.c_void_p(out_score.data_ptr()), _stream_handle(stream)))
+        return out_jump, out_score
+
+    def last_jump_ms(self) -> float:
+        """chap_jump_values_ms: HIP-event duration of the last jump kernels."""
+        ms = ctypes.c_double()
+        _check(load_library().chap_jump_values_ms(self._h, ctypes.byref(ms)))
+        return ms.value
 
     def last_pass_ms(self) -> float:
         """chap_best_shift_pass_ms: HIP-event duration of the last pass."""

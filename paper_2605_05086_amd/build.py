@@ -12,9 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchap.so")
-SOURCES = ["api.hip", "api_model.hip", "api_learned.hip", "api_noalloc.hip", "kernels_pass.hip", "kernels_walk.hip", "kernels_mlp.hip",
-           "kernels_learned.hip"]
-HEADERS = [os.path.join(CSRC, h) for h in ("chap_internal.h", "mlp_core.h", "narrow_finish.h", "learned_rows.h")]
+SOURCES = ["api.hip", "api_model.hip", "api_learned.hip", "api_noalloc.hip", "api_jump.hip", "kernels_pass.hip",
+           "kernels_walk.hip", "kernels_mlp.hip", "kernels_learned.hip", "kernels_jump.hip"]
+HEADERS = [os.path.join(CSRC, h) for h in ("chap_internal.h", "mlp_core.h", "narrow_finish.h", "learned_rows.h", "exact_sum.h")]
 HEADERS.append(os.path.join(INCLUDE, "chap.h"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

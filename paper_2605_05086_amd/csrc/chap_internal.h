@@ -549,6 +549,10 @@ constexpr int kTopkMax = 8192;      // largest proposal set
 constexpr int kSubsetCap = 4096;    // breakpoint capacity of the subset sort workgroup
 constexpr int kSubsetChunk = 2048;  // stored entries per workgroup chunk of the subset pass
 constexpr int kSubsetGrid = 2048;   // workgroups of the subset chunk kernel (grid-stride)
+constexpr int kJumpLane = 8;       // stored entries up to which one lane finds a column's jump value
+constexpr int kJumpChunk = 4096;   // entries per wavefront task of a longer column
+constexpr int kJumpNarrow = 64;    // integer domains up to this size try every value
+constexpr int kJumpSpecials = 7;   // cutoff kinks (2), l, u, xbar - 1, xbar + 1, xbar
 constexpr int kRescoreCapMax = 4096;  // largest rescore_cap (columns of an affected set, listed in LDS)
 constexpr int kRefreshShort = 64;   // stored entries up to which 8 lanes refresh a column
 constexpr int kRefreshChunk = 4096; // stored entries per workgroup chunk of the long-column refresh
@@ -657,6 +661,20 @@ hipError_t launch_learn_features_out(const WalkCtx* C, const LearnCtx* L, int32_
 // Exact best shift of the proposal set (kernels_pass.hip).
 hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCtx& Lh, int has_general, int compact,
                               hipStream_t s);
+// Jump values (kernels_jump.hip): one wavefront task of a longer column (its
+// candidate tile and entry chunk; slot = the column's first slot + tile x
+// chunks + chunk), and the column's record for the combine.
+struct JumpTask {
+  int32_t q, tile, chunk, slot;
+};
+struct JumpCol {
+  int32_t q, first_slot, ntiles, nchunks;
+};
+// Jump value and score of every column (internal order) into jv, js; part
+// holds kWave doubles per task slot.
+hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs, const WalkState* st,
+                       const JumpTask* tasks, int32_t ntasks, const JumpCol* cols, int32_t ncols, double* part,
+                       double* jv, double* js, hipStream_t s);
 // The same kernels with explicit grids (each kernel strides over its work).
 hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
                                int has_general, int compact, hipStream_t s);
@@ -792,8 +810,19 @@ struct chap_problem {
   hipGraphExec_t bs_exec = nullptr;
   // buffers of single walks kept between chap_tabu_run calls
   std::shared_ptr<chap::WalkPool> pool;
+  // jump values: wavefront tasks of the longer columns (built on the first
+  // chap_jump_values call), their partial sums, timing events
+  bool jump_ready = false;
+  const chap::JumpTask* jump_tasks = nullptr;
+  const chap::JumpCol* jump_cols = nullptr;
+  int32_t n_jump_tasks = 0, n_jump_cols = 0;
+  double* jump_part = nullptr;
+  hipEvent_t jump_ev[2] = {nullptr, nullptr};
+  bool jump_timed = false;
   ~chap_problem() {
     for (hipEvent_t e : pass_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : jump_ev)
       if (e) (void)hipEventDestroy(e);
     if (bs_exec) (void)hipGraphExecDestroy(bs_exec);
     if (bs_graph) (void)hipGraphDestroy(bs_graph);
