@@ -243,3 +243,78 @@ class OracleProblem:
             "best_x": best_x if has_best.value else None, "cutoff_rhs": bc.value,
             "inf_viol": inf_v.value, "inf_iter": inf_k.value, "inf_x": inf_x if inf_k.value != -2 else None,
         }
+
+
+# ---- diversity-driven restarts of parallel walks --------------------------
+# Section 3.1 "Parallel Tabu Search Instances" (a paragraph the compiled
+# paper leaves out): the diversity of an instance is measured against the
+# other active instances by the Hamming distance over the discrete variables,
+# d(x, y) = #{i in I : x_i != y_i}, and instances too similar to others are
+# restarted. Readings (design notes): walks run in segments of `every`
+# iterations; at the end of each segment (before the last) walk w restarts
+# when some walk w' < w on the same problem lies at distance < min_distance
+# (all distances taken at the points before any restart of that boundary);
+# a restart keeps the walk's iteration count, best feasible point and cutoff
+# row, and starts again from the start point of seed walk_seed + c * GOLDEN
+# (mod 2^64, c = the walk's restart count) with unit weights and an empty
+# tabu list.
+
+RESTART_SEED_STEP = 0x9E3779B97F4A7C15
+
+
+def hamming_discrete(x, y, is_int) -> int:
+    """d(x, y) over the integer (binary and general integer) variables."""
+    return int(np.count_nonzero((np.asarray(x) != np.asarray(y)) & (np.asarray(is_int) == 1)))
+
+
+def restart_seed(seed: int, count: int) -> int:
+    return (int(seed) + int(count) * RESTART_SEED_STEP) % (1 << 64)
+
+
+def batch_restarts(problems, walk_prob, walk_seed, iters: int, tenure: int, every: int, min_distance: int):
+    """Independent walks with diversity-driven restarts. problems: list of
+    (OracleProblem, MIP). Returns per walk a dict with the trace, final x, r,
+    w, best objective and point, cutoff, and the iterations at which the
+    walk restarted."""
+    nw = len(walk_prob)
+    st = []
+    for w in range(nw):
+        P, mip = problems[walk_prob[w]]
+        st.append({"x": P.start_point(int(walk_seed[w])), "w": np.ones(P.mp + 1, dtype=np.float32),
+                   "tabu": np.full(P.n, -1, dtype=np.int64), "best_obj": float("inf"), "best_x": None,
+                   "cutoff": float("inf"), "traces": [], "restarts": [], "count": 0, "r": None})
+    k0 = 0
+    while k0 < iters:
+        seg = min(every, iters - k0) if every > 0 else iters - k0
+        for w in range(nw):
+            P, mip = problems[walk_prob[w]]
+            S = st[w]
+            o = P.tabu_resume(seg, tenure, S["x"], S["w"], S["tabu"], k0, S["best_obj"], S["best_x"], S["cutoff"])
+            tr = o["trace"]
+            moved = tr["var"] >= 0
+            for k, j in zip(tr["iter"][moved], tr["var"][moved]):
+                S["tabu"][j] = k + tenure
+            S.update(x=o["x"], w=o["w"], r=o["r"], best_obj=o["best_obj"], best_x=o["best_x"], cutoff=o["cutoff_rhs"])
+            S["traces"].append(tr)
+        k0 += seg
+        if k0 >= iters or every <= 0:
+            continue
+        points = [st[w]["x"].copy() for w in range(nw)]
+        for w in range(nw):
+            P, mip = problems[walk_prob[w]]
+            close = any(walk_prob[v] == walk_prob[w] and hamming_discrete(points[w], points[v], mip.is_int) < min_distance
+                        for v in range(w))
+            if not close:
+                continue
+            S = st[w]
+            S["count"] += 1
+            S["restarts"].append(k0)
+            S["x"] = P.start_point(restart_seed(walk_seed[w], S["count"]))
+            S["w"] = np.ones(P.mp + 1, dtype=np.float32)
+            S["tabu"] = np.full(P.n, -1, dtype=np.int64)
+    out = []
+    for S in st:
+        out.append({"trace": np.concatenate(S["traces"]) if S["traces"] else np.zeros(0, dtype=TRACE_DTYPE),
+                    "x": S["x"], "r": S["r"], "w": S["w"], "best_obj": S["best_obj"], "best_x": S["best_x"],
+                    "cutoff_rhs": S["cutoff"], "restarts": list(S["restarts"])})
+    return out
