@@ -297,6 +297,37 @@ int chap_batch_run(chap_problem *const *probs, int32_t nprob, const int32_t *wal
  *   ms_per_iter   optional, one entry per candidate (8 for the grid)
  * Synchronous; uses the current device. CHAP_EINVAL on bad arguments.
  */
+/*
+ * chap_batch_restarts - chap_batch_run with diversity-driven restarts
+ * (section 3.1 "Parallel Tabu Search Instances": the paper measures the
+ * diversity of an instance against the other active ones by the Hamming
+ * distance over the discrete variables, d(x, y) = #{i in I : x_i != y_i},
+ * and restarts instances that come too close to others).
+ * The walks run in segments of restart_every iterations. At the end of each
+ * segment but the last, walk w restarts when a walk w' < w on the same
+ * problem lies at distance < min_distance (all distances taken at the points
+ * before any restart of that boundary). A restart keeps the walk's
+ * iteration count, best feasible point and cutoff row (a restart point that
+ * is feasible under the cutoff becomes the new incumbent) and starts again
+ * from the start point of seed walk_seed[w] + c * 0x9E3779B97F4A7C15 (mod
+ * 2^64; c = 1, 2, ... counts the walk's restarts) with unit weights and an
+ * empty tabu list. Between segments the host reads the distances (one
+ * kernel over every pair of walks on a problem) and re-initialises the
+ * restarted walks; each segment is the batched graph of chap_batch_run.
+ *   restart_every  > 0.    min_distance  >= 0 (0: no restarts).
+ * Other arguments as chap_batch_run (no start points). Walk w's iterations
+ * at which it restarted: chap_run_restarts. chap_run_best_infeasible is not
+ * recorded for a walk that restarted (CHAP_EINVAL). Synchronous. Errors:
+ * CHAP_EINVAL, CHAP_ENOMEM, CHAP_EHIP.
+ */
+int chap_batch_restarts(chap_problem *const *probs, int32_t nprob, const int32_t *walk_prob,
+                        const uint64_t *walk_seed, int32_t nwalks, int64_t iters, int32_t tenure,
+                        int64_t restart_every, int64_t min_distance, chap_run **out, void *hip_stream);
+
+/* The iterations at which a walk of chap_batch_restarts restarted (*count of
+ * them, ascending; owned by the run). Zero for other runs. */
+int chap_run_restarts(const chap_run *r, const int64_t **iters, int64_t *count);
+
 int chap_autotune(const chap_problem *p, const chap_options *cands, int32_t ncand, int64_t walk_iters,
                   chap_options *best, double *ms_per_iter);
 

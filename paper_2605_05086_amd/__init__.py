@@ -117,6 +117,10 @@ def load_library():
     lib.chap_jump_values.restype = ctypes.c_int
     lib.chap_jump_values_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.chap_jump_values_ms.restype = ctypes.c_int
+    lib.chap_batch_restarts.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, i64, ctypes.c_int32, i64, i64, P, P]
+    lib.chap_batch_restarts.restype = ctypes.c_int
+    lib.chap_run_restarts.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(i64)]
+    lib.chap_run_restarts.restype = ctypes.c_int
     lib.chap_run_rescored.argtypes = [P, ctypes.POINTER(i64)]
     lib.chap_run_rescored.restype = ctypes.c_int
     lib.chap_run_proposals.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64)]
@@ -193,6 +197,10 @@ class Run:
         rs = ctypes.c_int64()
         _check(lib.chap_run_rescored(handle, ctypes.byref(rs)))
         self.rescored = rs.value
+        rp, rc_ = ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib.chap_run_restarts(handle, ctypes.byref(rp), ctypes.byref(rc_)))
+        self.restarts = (list(np.ctypeslib.as_array((ctypes.c_int64 * rc_.value).from_address(rp.value)))
+                         if rc_.value > 0 else [])
         sets, offs, iters = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
         _check(lib.chap_run_proposals(handle, ctypes.byref(sets), ctypes.byref(offs), ctypes.byref(iters)))
         self.set_offsets = None
@@ -467,6 +475,24 @@ def batch_run(problems, walk_prob, walk_seed, iters: int, tenure: int, stream=No
     out = (ctypes.c_void_p * nw)()
     _check(lib.chap_batch_run(ctypes.cast(handles, ctypes.c_void_p), nprob, _ptr(wp), _ptr(ws), x0p, nw,
                               int(iters), int(tenure), ctypes.cast(out, ctypes.c_void_p), _stream_handle(stream)))
+    return [Run(ctypes.c_void_p(out[w]), problems[wp[w]].n, problems[wp[w]].mp) for w in range(nw)]
+
+
+def batch_restarts(problems, walk_prob, walk_seed, iters: int, tenure: int, restart_every: int, min_distance: int,
+                   stream=None):
+    """chap_batch_restarts: batched walks with diversity-driven restarts;
+    returns one Run per walk (Run.restarts: the iterations at which it
+    restarted)."""
+    lib = load_library()
+    nprob = len(problems)
+    handles = (ctypes.c_void_p * nprob)(*[p._h.value for p in problems])
+    wp = np.ascontiguousarray(walk_prob, dtype=np.int32)
+    ws = np.ascontiguousarray(walk_seed, dtype=np.uint64)
+    nw = wp.shape[0]
+    out = (ctypes.c_void_p * nw)()
+    _check(lib.chap_batch_restarts(ctypes.cast(handles, ctypes.c_void_p), nprob, _ptr(wp), _ptr(ws), nw, int(iters),
+                                   int(tenure), int(restart_every), int(min_distance),
+                                   ctypes.cast(out, ctypes.c_void_p), _stream_handle(stream)))
     return [Run(ctypes.c_void_p(out[w]), problems[wp[w]].n, problems[wp[w]].mp) for w in range(nw)]
 
 

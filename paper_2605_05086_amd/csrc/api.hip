@@ -1077,11 +1077,42 @@ int compact_walks(const std::vector<WalkSpec>& specs, int64_t iters) {
 
 namespace {
 
+// Diversity restarts of a batch: segments of `every` iterations; at the end
+// of each segment but the last, walk w restarts when a walk w' < w on the
+// same problem lies at Hamming distance < min_distance over the discrete
+// variables (distances of the points before any restart of that boundary).
+struct RestartSpec {
+  int64_t every = 0;
+  int64_t min_distance = 0;
+};
+
+constexpr uint64_t kRestartSeedStep = 0x9E3779B97F4A7C15ull;
+
+// Hamming tasks of every pair (w' < w) of walks on one problem, in chunks of
+// 65536 columns; pair index = position in `pairs`.
+void hamming_tasks(const std::vector<WalkSpec>& specs, const std::vector<WalkCtx>& ctx,
+                   const std::vector<int32_t>& slot_of, std::vector<std::pair<int32_t, int32_t>>& pairs,
+                   std::vector<HamTask>& tasks) {
+  const int32_t nw = (int32_t)specs.size();
+  for (int32_t w = 0; w < nw; ++w)
+    for (int32_t v = 0; v < w; ++v) {
+      if (specs[v].p != specs[w].p) continue;
+      const int32_t pair = (int32_t)pairs.size();
+      pairs.emplace_back(w, v);
+      const WalkCtx& a = ctx[slot_of[w]];
+      const WalkCtx& b = ctx[slot_of[v]];
+      const int32_t n = specs[w].p->n;
+      for (int32_t q = 0; q < n; q += 65536)
+        tasks.push_back(HamTask{a.x, b.x, a.P.is_int, q, std::min(n, q + 65536), pair, 0});
+    }
+}
+
 // Runs every walk for `iters` iterations: per-walk buffers, set-up kernels,
 // then a HIP graph of `graph_iters` iterations in which each kernel is one
 // launch over all walks. Results are copied back into chap_run objects.
+// With rsp, the walks run in segments with diversity restarts between them.
 int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure, hipStream_t user,
-              std::vector<std::unique_ptr<chap_run>>& out) {
+              std::vector<std::unique_ptr<chap_run>>& out, const RestartSpec* rsp = nullptr) {
   if (iters < 0 || tenure < 0 || iters + (int64_t)tenure >= (int64_t)INT32_MAX)
     return fail(CHAP_EINVAL, "iters and tenure must be >= 0 with iters + tenure < 2^31");
   const size_t nw = specs.size();
@@ -1127,8 +1158,10 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
   CHAP_HIP(build_launch(A, ctx, &L, &order));
   L.compact = compact;
   double ms_total = 0.0;
+  std::vector<std::vector<int64_t>> restarts;
   if (iters > 0) {
-    const int64_t K = std::min<int64_t>(iters, specs[0].p->opt.graph_iters);
+    int64_t K = std::min<int64_t>(iters, specs[0].p->opt.graph_iters);
+    if (rsp && rsp->every > 0) K = std::min<int64_t>(K, rsp->every);
     hipGraph_t graph;
     CHAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
@@ -1145,19 +1178,80 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
       (void)hipGraphDestroy(graph);
       return fail(CHAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
-    const int64_t launches = (iters + K - 1) / K;
-    hipError_t le = hipEventRecord(e0, s);
-    for (int64_t q = 0; q < launches && le == hipSuccess; ++q) le = hipGraphLaunch(exec, s);
-    if (le == hipSuccess) le = hipEventRecord(e1, s);
-    // an incumbent found by a walk's last iteration is copied here
-    if (le == hipSuccess) le = launch_copy_best_batch(L, s);
-    if (le == hipSuccess) le = hipStreamSynchronize(s);
-    float ms = 0.0f;
-    if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (le != hipSuccess) return fail(CHAP_EHIP, std::string("graph launch: ") + hipGetErrorString(le));
-    ms_total = ms;
+    struct GraphGuard {
+      hipGraph_t g;
+      hipGraphExec_t x;
+      ~GraphGuard() {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+      }
+    } gg{graph, exec};
+    const int64_t every = (rsp && rsp->every > 0) ? rsp->every : iters;
+    std::vector<int32_t> slot_of(nw);
+    for (size_t i = 0; i < nw; ++i) slot_of[order[i]] = (int32_t)i;
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    std::vector<HamTask> htasks;
+    HamTask* d_htasks = nullptr;
+    int32_t* d_dist = nullptr;
+    std::vector<WalkState> hst;
+    if (every < iters) {
+      hamming_tasks(specs, ctx, slot_of, pairs, htasks);
+      if (!htasks.empty()) CHAP_HIP(A.upload(&d_htasks, htasks));
+      CHAP_HIP(A.alloc(&d_dist, std::max<size_t>(pairs.size(), 1)));
+      hst.resize(nw);
+    }
+    restarts.assign(nw, {});
+    std::vector<int64_t> count(nw, 0);
+    for (int64_t k0 = 0; k0 < iters;) {
+      const int64_t k1 = std::min(iters, k0 + every);
+      // the segment: every walk stops at k1; surplus iterations of the last
+      // graph launch do nothing
+      if (every < iters) CHAP_HIP(launch_set_iters(L, k1, s));
+      const int64_t launches = (k1 - k0 + K - 1) / K;
+      hipError_t le = hipEventRecord(e0, s);
+      for (int64_t q = 0; q < launches && le == hipSuccess; ++q) le = hipGraphLaunch(exec, s);
+      if (le == hipSuccess) le = hipEventRecord(e1, s);
+      // an incumbent found by a walk's last iteration is copied here
+      if (le == hipSuccess) le = launch_copy_best_batch(L, s);
+      if (le == hipSuccess) le = hipStreamSynchronize(s);
+      float ms = 0.0f;
+      if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
+      if (le != hipSuccess) return fail(CHAP_EHIP, std::string("graph launch: ") + hipGetErrorString(le));
+      ms_total += ms;
+      k0 = k1;
+      if (k1 >= iters || pairs.empty()) continue;
+      // distances at the boundary, then the restarts
+      CHAP_HIP(hipMemsetAsync(d_dist, 0, sizeof(int32_t) * pairs.size(), s));
+      CHAP_HIP(launch_hamming(d_htasks, (int32_t)htasks.size(), d_dist, s));
+      std::vector<int32_t> dist(pairs.size());
+      CHAP_HIP(hipMemcpyAsync(dist.data(), d_dist, sizeof(int32_t) * pairs.size(), hipMemcpyDeviceToHost, s));
+      for (size_t i = 0; i < nw; ++i)
+        CHAP_HIP(hipMemcpyAsync(&hst[i], ctx[i].st, sizeof(WalkState), hipMemcpyDeviceToHost, s));
+      CHAP_HIP(hipStreamSynchronize(s));
+      std::vector<char> restart(nw, 0);
+      for (size_t pi = 0; pi < pairs.size(); ++pi)
+        if (dist[pi] < rsp->min_distance) restart[pairs[pi].first] = 1;
+      for (size_t w = 0; w < nw; ++w) {
+        if (!restart[w]) continue;
+        const int32_t i = slot_of[w];
+        const WalkCtx& c = ctx[i];
+        const chap_problem* p = specs[w].p;
+        const WalkState& old = hst[i];
+        count[w] += 1;
+        restarts[w].push_back(k1);
+        const uint64_t seed = specs[w].seed + (uint64_t)count[w] * kRestartSeedStep;
+        CHAP_HIP(launch_start_point(p->dev, seed, c.x, c.xc, s));
+        if (p->n > 0) {
+          hipLaunchKernelGGL(k_fill_i32, dim3((p->n + 255) / 256), dim3(256), 0, s, c.tabu, -1, (int64_t)p->n);
+          CHAP_HIP(hipGetLastError());
+        }
+        CHAP_HIP(launch_residual_unit(p->dev, p->d_pair, c.x, c.xc, c.st, 1u, c.rs, c.grow, s));
+        CHAP_HIP(launch_state_init(p->dev, c.x, c.rs, c.st, partial, ticket, c.objacc, k1, tenure, p->obj_integral,
+                                   old.cut_active ? old.bc : HUGE_VAL, nullptr, 1, 1, s));
+        RestartKeep keep{old.k, old.fbest, old.inf_V, old.inf_k, old.has_best, 0};
+        CHAP_HIP(launch_restart_fix(c.st, keep, s));
+      }
+    }
   }
   CHAP_HIP(hipStreamSynchronize(s));
   out.clear();
@@ -1167,6 +1261,10 @@ int run_walks(const std::vector<WalkSpec>& specs, int64_t iters, int32_t tenure,
     std::unique_ptr<chap_run> R(new chap_run());
     const int rc = collect_walk(specs[w].p, ctx[i], iters, ms_total, R.get());
     if (rc != CHAP_OK) return rc;
+    if (rsp) {
+      R->restarts = restarts.empty() ? std::vector<int64_t>() : restarts[w];
+      R->restart_run = true;
+    }
     out[w] = std::move(R);
   }
   return CHAP_OK;
@@ -1427,6 +1525,39 @@ int chap_batch_run(chap_problem* const* probs, int32_t nprob, const int32_t* wal
   return CHAP_OK;
 }
 
+int chap_batch_restarts(chap_problem* const* probs, int32_t nprob, const int32_t* walk_prob, const uint64_t* walk_seed,
+                        int32_t nwalks, int64_t iters, int32_t tenure, int64_t restart_every, int64_t min_distance,
+                        chap_run** out, void* hip_stream) {
+  if (!probs || !walk_prob || !walk_seed || !out || nprob <= 0 || nwalks <= 0)
+    return fail(CHAP_EINVAL, "chap_batch_restarts: null argument or empty batch");
+  if (restart_every <= 0 || min_distance < 0)
+    return fail(CHAP_EINVAL, "chap_batch_restarts: restart_every must be > 0 and min_distance >= 0");
+  std::vector<WalkSpec> specs;
+  for (int32_t w = 0; w < nwalks; ++w) {
+    if (walk_prob[w] < 0 || walk_prob[w] >= nprob || !probs[walk_prob[w]])
+      return fail(CHAP_EINVAL, "chap_batch_restarts: walk " + std::to_string(w) + " names no problem");
+    specs.push_back(WalkSpec{probs[walk_prob[w]], walk_seed[w], nullptr});
+  }
+  const int dev = specs[0].p->device;
+  for (const WalkSpec& ws : specs)
+    if (ws.p->device != dev) return fail(CHAP_EINVAL, "chap_batch_restarts: problems on different devices");
+  RestartSpec rs;
+  rs.every = restart_every;
+  rs.min_distance = min_distance;
+  std::vector<std::unique_ptr<chap_run>> runs;
+  const int rc = run_walks(specs, iters, tenure, (hipStream_t)hip_stream, runs, &rs);
+  if (rc != CHAP_OK) return rc;
+  for (int32_t w = 0; w < nwalks; ++w) out[w] = runs[w].release();
+  return CHAP_OK;
+}
+
+int chap_run_restarts(const chap_run* r, const int64_t** iters, int64_t* count) {
+  if (!r || !iters || !count) return fail(CHAP_EINVAL, "chap_run_restarts: null argument");
+  *iters = r->restarts.data();
+  *count = (int64_t)r->restarts.size();
+  return CHAP_OK;
+}
+
 int chap_autotune(const chap_problem* p, const chap_options* cands, int32_t ncand, int64_t walk_iters,
                   chap_options* best, double* ms_per_iter) {
   if (!p || !best || ncand < 0 || (ncand > 0 && !cands) || walk_iters <= 0 || walk_iters > (1 << 20))
@@ -1499,6 +1630,8 @@ int chap_run_state(const chap_run* r, double* x, double* resid, float* w, double
 
 int chap_run_best_infeasible(const chap_run* r, double* x, int64_t* violated, int64_t* iter) {
   if (!r) return fail(CHAP_EINVAL, "chap_run_best_infeasible: null run");
+  if (!r->restarts.empty())
+    return fail(CHAP_EINVAL, "chap_run_best_infeasible: not recorded for a walk that restarted");
   if (x && r->inf_iter != -2) {
     const int rc = materialize(r);
     if (rc != CHAP_OK) return rc;

@@ -717,6 +717,35 @@ struct AffLists {
 // column the subset pass cannot score, or more than `sub_cap` chunks, makes
 // the iteration score every column.
 hipError_t launch_affected(const WalkCtx* C, LearnCtx* L, const AffLists& A, hipStream_t s);
+// Diversity restarts of batched walks (kernels_walk.hip). A Hamming task
+// counts, over internal columns [begin, end) of one problem, the discrete
+// variables at which two walks' points differ, into dist[pair].
+struct HamTask {
+  const double* xa;
+  const double* xb;
+  const uint8_t* is_int;
+  int32_t begin, end;
+  int32_t pair;
+  int32_t pad_;
+};
+// What a restarted walk keeps: its iteration count, best feasible objective
+// and its best infeasible point's record.
+struct RestartKeep {
+  int64_t k;
+  double fbest;
+  int64_t inf_V;
+  int64_t inf_k;
+  int32_t has_best;
+  int32_t pad_;
+};
+// st->iters = iters_end for every walk of the launch table.
+hipError_t launch_set_iters(const BatchLaunch& L, int64_t iters_end, hipStream_t s);
+hipError_t launch_hamming(const HamTask* tasks, int32_t ntasks, int32_t* dist, hipStream_t s);
+// After the set-up kernels of a restart (start point, residuals, state at
+// the kept cutoff): the kept iteration count and, unless the restart point
+// is a new incumbent, the kept best objective; the better best infeasible
+// record.
+hipError_t launch_restart_fix(WalkState* st, const RestartKeep& keep, hipStream_t s);
 // The iteration's short columns (AffRun), one lane each, as the full pass
 // scores them (kernels_pass.hip); grid-stride over the list.
 hipError_t launch_aff_short(const WalkCtx* C, const AffRun* run, int grid, int compact, hipStream_t s);
@@ -914,6 +943,9 @@ struct chap_run {
   int64_t inf_viol = 0;
   int64_t inf_iter = -2;
   std::vector<double> inf_x;
+  // walks of chap_batch_restarts: the iterations at which the walk restarted
+  std::vector<int64_t> restarts;
+  bool restart_run = false;
   ~chap_run() {
     if (pool) pool->give_back(slot);
   }

@@ -1115,6 +1115,47 @@ __global__ __launch_bounds__(256) void k_aff_plan(const WalkCtx* __restrict__ wa
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Diversity restarts of batched walks (section 3.1 "Parallel Tabu Search
+// Instances": walks whose points come too close to another walk's restart).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_set_iters(const WalkCtx* __restrict__ walks, int32_t nw, int64_t iters_end) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nw) walks[w].st->iters = iters_end;
+}
+
+// One workgroup per task: discrete variables of the task's column range at
+// which the two points differ, added into dist[pair].
+__global__ __launch_bounds__(256) void k_hamming(const HamTask* __restrict__ tasks, int32_t* __restrict__ dist) {
+  const HamTask T = tasks[blockIdx.x];
+  __shared__ long long red[4];
+  long long c = 0;
+  for (int q = T.begin + (int)threadIdx.x; q < T.end; q += (int)blockDim.x)
+    c += (T.is_int[q] != 0 && T.xa[q] != T.xb[q]) ? 1 : 0;
+  c = block_sum_ll(c, red);
+  if (threadIdx.x == 0 && c != 0) atomicAdd(&dist[T.pair], (int32_t)c);
+}
+
+__global__ void k_restart_fix(WalkState* st, RestartKeep keep) {
+  if (threadIdx.x != 0) return;
+  const bool improved = st->has_best && st->copy_best;  // the restart point is a new incumbent
+  if (!improved) {
+    st->has_best = keep.has_best;
+    st->fbest = keep.fbest;
+    st->copy_best = 0;
+  }
+  st->k = keep.k;
+  const bool fresh = st->inf_k != -2;  // the restart point is infeasible
+  if (keep.inf_k != -2 && (!fresh || keep.inf_V <= st->inf_V)) {
+    st->inf_V = keep.inf_V;
+    st->inf_k = keep.inf_k;
+  } else if (fresh) {
+    st->inf_k = keep.k - 1;
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -1204,6 +1245,21 @@ hipError_t launch_walk_step(const BatchLaunch& L, hipStream_t stream, bool combi
 
 hipError_t launch_affected(const WalkCtx* C, LearnCtx* L, const AffLists& A, hipStream_t s) {
   hipLaunchKernelGGL(k_aff_plan, dim3(1), dim3(256), 0, s, C, L, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_iters(const BatchLaunch& L, int64_t iters_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_iters, dim3((unsigned)((L.nw + 63) / 64)), dim3(64), 0, s, L.walks, L.nw, iters_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_hamming(const HamTask* tasks, int32_t ntasks, int32_t* dist, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_hamming, dim3((unsigned)ntasks), dim3(256), 0, s, tasks, dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_fix(WalkState* st, const RestartKeep& keep, hipStream_t s) {
+  hipLaunchKernelGGL(k_restart_fix, dim3(1), dim3(64), 0, s, st, keep);
   return hipGetLastError();
 }
 
