@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # by the counters of a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
 # see profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the
 # pass kernels as they are; None until they are measured again after a change.
-PASS_TRAFFIC_BYTES = 511_300_000
+PASS_TRAFFIC_BYTES = 498_700_000
+FP64_VECTOR_TFLOPS = 78.6
 METRIC = "tabu moves/s, best-shift nnz/s, % HBM peak; plain vs batched/learned"
 
 
@@ -186,6 +187,9 @@ def main():
     log(f"best-shift pass {pass_ms * 1e3:.1f} us (whole call {call_ms * 1e3:.1f} us), {B / 1e6:.1f} MB algorithmic, "
         f"{achieved:.0f} GB/s")
 
+    # jump values at the same point: the second pass on the same primitives
+    jump = jump_values_leg(G, mip, xd, wd, cutoff, args.pass_reps)
+
     if args.calibrate_copy_mb > 0:
         src = torch.ones(args.calibrate_copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -223,6 +227,7 @@ def main():
                                "instance)",
                      "bytes_per_launch": B},
     }
+    result["jump_values"] = jump
     if args.batched_only:
         result["batched"] = compare_batched(chap, args.batch_iters, tenure, args.small, plain=False)
     elif not args.no_compare:
@@ -235,6 +240,52 @@ def main():
         log(f"cpu baseline: {args.cpu_iters} oracle iterations on one core, {args.cpu_iters_all} on all")
         result["cpu_baseline"] = cpu_baseline(mip, args.cpu_iters, args.cpu_iters_all)
     print(json.dumps(result), flush=True)
+
+
+def jump_flops(mip, cutoff_active: bool) -> int:
+    """FP64 operations of one jump-value pass as the kernels evaluate it: each
+    evaluated value t of column j (every value of an integer domain of at
+    most 64 values; otherwise two per entry, the cutoff kinks, both bounds
+    and xbar +- 1 for integers, one per entry and both bounds for continuous
+    variables; plus xbar itself) sums one term per normalised row of j (and
+    the cutoff row), 4 operations each (product, sum, weight product,
+    accumulation)."""
+    deg = np.diff(mip.csc_col_ptr).astype(np.int64)
+    eq_row = (mip.sense == ord("E")).astype(np.int64)
+    twins = np.add.reduceat(eq_row[mip.csc_row], mip.csc_col_ptr[:-1]) if mip.nnz else np.zeros(mip.n, np.int64)
+    twins = np.where(deg > 0, twins, 0)
+    cut = ((mip.obj != 0) & cutoff_active).astype(np.int64)
+    terms = deg + twins + cut
+    W = mip.ub - mip.lb + 1
+    narrow = (mip.is_int == 1) & np.isfinite(W) & (W <= 64)
+    integer = mip.is_int == 1
+    evals = np.where(narrow, np.where(np.isfinite(W), W, 0),
+                     np.where(integer, 2 * (deg + cut) + 5, deg + cut + 3)).astype(np.int64)
+    return int(4 * np.sum(evals * terms))
+
+
+def jump_values_leg(G, mip, xd, wd, cutoff, reps):
+    """chap_jump_values on the walk's final point: kernel time (HIP events),
+    nonzeros per second, and its FP64 arithmetic rate against the vector
+    FP64 peak (the pass evaluates V at every value it tries: ALU-bound)."""
+    import torch
+
+    times = []
+    for _ in range(reps + 3):
+        G.jump_values(xd, wd, cutoff)
+        times.append(G.last_jump_ms())
+    torch.cuda.synchronize()
+    ms = float(np.mean(times[3:]))
+    act = math.isfinite(cutoff)
+    flops = jump_flops(mip, act)
+    nnz = mip.nnz + (mip.nnz_obj if act else 0)
+    out = {"pass_us": ms * 1e3, "nnz_per_s": nnz / (ms * 1e-3),
+           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "flops_per_pass": flops}}
+    out["roofline"]["frac"] = out["roofline"]["achieved"] / FP64_VECTOR_TFLOPS
+    log(f"jump values {ms * 1e3:.1f} us, {flops / 1e9:.2f} GFLOP FP64, "
+        f"{out['roofline']['achieved']:.1f} TFLOP/s ({100 * out['roofline']['frac']:.1f} % of FP64 vector peak)")
+    return out
 
 
 def heuristic_params():
@@ -409,10 +460,22 @@ def compare_batched(chap, iters, tenure, small, plain=True):
     roof["frac"] = roof["achieved_GBps"] / roof["peak_GBps"]
     log(f"batched roofline: {bpi / 1e6:.1f} MB per batched iteration, {roof['achieved_GBps']:.0f} GB/s "
         f"({100 * roof['frac']:.1f} % of 8 TB/s, graph time including walk set-up)")
+    # diversity-driven restarts: the same batch in segments of 50 iterations,
+    # restarting walks that come within 64 discrete variables of another walk
+    # on the same instance
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rruns = chap.batch_restarts(probs, wp, ws, iters, tenure, 50, 64)
+    rwall = time.perf_counter() - t0
+    restarts = {"restart_every": 50, "min_distance": 64, "restarts": int(sum(len(r.restarts) for r in rruns)),
+                "gpu_ms": rruns[0].elapsed_ms, "wall_s": rwall, "batched_wall_s": bwall,
+                "wall_overhead_vs_batched": rwall / bwall}
+    log(f"batched with restarts: {rruns[0].elapsed_ms:.1f} ms GPU, {rwall:.3f} s wall vs {bwall:.3f} s, "
+        f"{restarts['restarts']} restarts")
     if not plain:
         log(f"batched: {bms:.1f} ms (GPU graphs), {bms / iters:.3f} ms per batched iteration")
         return {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
-                "batched_gpu_ms": bms, "batched_wall_s": bwall, "roofline": roof,
+                "batched_gpu_ms": bms, "batched_wall_s": bwall, "roofline": roof, "restarts": restarts,
                 "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3)}}
     pms = 0.0
     pwall = 0.0
@@ -426,6 +489,7 @@ def compare_batched(chap, iters, tenure, small, plain=True):
     out = {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
            "batched_gpu_ms": bms, "plain_gpu_ms_sum": pms, "batched_wall_s": bwall, "plain_wall_s": pwall,
            "identical_trajectories": bool(same), "speedup_at_equal_final_score": pms / bms, "roofline": roof,
+           "restarts": restarts,
            "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3), "plain": nw * iters / (pms * 1e-3)}}
     log(f"batched: {bms:.1f} ms vs plain {pms:.1f} ms (GPU graphs), identical={same}")
     return out
