@@ -551,6 +551,7 @@ constexpr int kSubsetChunk = 2048;  // stored entries per workgroup chunk of the
 constexpr int kSubsetGrid = 2048;   // workgroups of the subset chunk kernel (grid-stride)
 constexpr int kJumpLane = 8;       // stored entries up to which one lane finds a column's jump value
 constexpr int kJumpChunk = 4096;   // entries per wavefront task of a longer column
+constexpr int kJumpBinChunk = 1024;  // entries per wavefront of a column scored from bins
 constexpr int kJumpNarrow = 64;    // integer domains up to this size try every value
 constexpr int kJumpSpecials = 7;   // cutoff kinks (2), l, u, xbar - 1, xbar + 1, xbar
 constexpr int kRescoreCapMax = 4096;  // largest rescore_cap (columns of an affected set, listed in LDS)
@@ -666,15 +667,31 @@ hipError_t launch_subset_pass(const WalkCtx* C, const LearnCtx* L, const LearnCt
 // chunks + chunk), and the column's record for the combine.
 struct JumpTask {
   int32_t q, tile, chunk, slot;
+  int32_t bins;  // the column also has a bins form (see JumpBinTask)
 };
 struct JumpCol {
   int32_t q, first_slot, ntiles, nchunks;
+  int32_t bfirst, bn;  // its bins slots (bn = 0: no bins form; -1: one bins task finishes it)
+};
+// A chunk of a narrow column's entries scored into slope and offset bins
+// (exact integer data): V(l + p) = sum_{k <= p} K[k] + p sum_{k <= p} S[k].
+struct JumpBinTask {
+  int32_t q, e_beg, e_end, slot;  // q < 0: padding; slot < 0: the whole column, finished by the task
 };
 // Jump value and score of every column (internal order) into jv, js; part
 // holds kWave doubles per task slot.
+// exact_data: the instance's compact row copy is exact (all-integer data,
+// residuals within int32); obj_small: objective sums are exact small
+// integers. With integer weights (checked on the device) the lane kernel
+// then tries fewer values of narrow columns, with the same results.
+// Columns with a bins form are scored from int64 slope and offset bins
+// when the call's data are exact (integer weights; then every V is an
+// integer below 2^53 and any order of summation gives the oracle's value),
+// else by the wavefront tasks like every other long column.
 hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs, const WalkState* st,
-                       const JumpTask* tasks, int32_t ntasks, const JumpCol* cols, int32_t ncols, double* part,
-                       double* jv, double* js, hipStream_t s);
+                       int32_t exact_data, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
+                       const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols, int32_t ncols, double* part,
+                       long long* bpart, double* jv, double* js, hipStream_t s);
 // The same kernels with explicit grids (each kernel strides over its work).
 hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
                                int has_general, int compact, hipStream_t s);
@@ -844,8 +861,10 @@ struct chap_problem {
   bool jump_ready = false;
   const chap::JumpTask* jump_tasks = nullptr;
   const chap::JumpCol* jump_cols = nullptr;
-  int32_t n_jump_tasks = 0, n_jump_cols = 0;
+  const chap::JumpBinTask* jump_btasks = nullptr;
+  int32_t n_jump_tasks = 0, n_jump_cols = 0, n_jump_btasks = 0;
   double* jump_part = nullptr;
+  long long* jump_bpart = nullptr;
   hipEvent_t jump_ev[2] = {nullptr, nullptr};
   bool jump_timed = false;
   ~chap_problem() {

@@ -19,12 +19,14 @@
 //
 // Every V_q(t) is one sum in the order above, evaluated directly at t:
 //   k_jump_lane    columns with at most kJumpLane stored entries, one lane
-//                  each, entries in registers, candidates one after another;
+//                  each, entries in registers, candidates one after another
+//                  (on exact integer data narrow columns too try only the
+//                  kinks' neighbours, bounds and xbar +- 1);
 //   k_jump_tasks   longer columns: one wavefront per (column, tile of 64
 //                  candidates, chunk of kJumpChunk entries), a lane per
-//                  candidate; the wavefront loads 64 entries at a time and
-//                  every lane adds each entry's terms in order (entry values
-//                  broadcast from the loading lane);
+//                  candidate; the wavefront loads 64 entries at a time into
+//                  its LDS slice and every lane adds each entry's terms in
+//                  order (one broadcast read per entry);
 //   k_jump_combine one wavefront per longer column: the chunks' partial sums
 //                  in chunk order, the cutoff term, the argmin over tiles.
 // A column of one chunk is summed exactly in the stored order; longer
@@ -49,15 +51,22 @@ __device__ __forceinline__ bool jump_better(double v, double t, double bv, doubl
   return t < bt;
 }
 
-__device__ __forceinline__ double bcast(double v, int k) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+// Exact data for this call: the instance's data are integers with every
+// residual within the bounds in int32 (exact_data), the weights are integers
+// below 2^16 (st->compact_rows), and the cutoff row, when active, has small
+// integer terms.
+__device__ __forceinline__ bool jump_exact(const WalkState* st, int32_t exact_data, int32_t obj_small) {
+  return exact_data && st->compact_rows &&
+         (!st->cut_active || (obj_small && st->rc == floor(st->rc) && fabs(st->rc) < 2147483648.0));
 }
-__device__ __forceinline__ float bcastf(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
+
+// One entry of a column as the wavefront tasks read it from LDS.
+struct JumpEntry {
+  double r;
+  double a;
+  float w0;
+  float w1;
+};
 
 // Candidate c of a longer column (its tile-major numbering): for a narrow
 // column the value l + c; otherwise entry c / 2's kink (integer: floor for
@@ -136,9 +145,19 @@ __device__ __forceinline__ int jump_tiles(bool narrow, int deg) {
   return narrow ? 1 : (2 * deg + kJumpSpecials + kWave - 1) / kWave;
 }
 
+// exact_data: every residual within the bounds fits int32 and the data are
+// integers; with integer weights below 2^16 (st->compact_rows) and a cutoff
+// term of small integers, every V the lane forms is an exact integer below
+// 2^53, and then the kinks' neighbours, the bounds and xbar +- 1 hold the
+// chosen value of a narrow column too (a value strictly between them has
+// neighbours on one line through it; a zero slope makes the neighbour
+// towards xbar tie and win, any other slope makes a neighbour smaller), so
+// narrow columns try those (and the integers next to them) instead of
+// every value.
 __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* __restrict__ x,
                                                    const RowState* __restrict__ rs, const WalkState* __restrict__ st,
-                                                   double* __restrict__ jv, double* __restrict__ js) {
+                                                   int32_t exact_data, int32_t obj_small, double* __restrict__ jv,
+                                                   double* __restrict__ js) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
   const int beg = P.col_ptr[q], deg = P.col_ptr[q + 1] - beg;
@@ -189,31 +208,28 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
       bv = v;
     }
   };
-  if (jump_narrow(isint, l, u)) {
+  const bool exact = jump_exact(st, exact_data, obj_small);
+  const bool narrow = jump_narrow(isint, l, u);
+  // a narrow column on exact data: each kink's neighbours, widened by one
+  // on either side so that a rounding of the FP64 kink across an integer
+  // cannot hide one
+  const int pad = narrow ? 1 : 0;
+  auto kink_values = [&](double kink) {
+    if (isint) {
+      for (int o = -pad; o <= 0; ++o) consider(floor(kink) + (double)o);
+      for (int o = 0; o <= pad; ++o) consider(ceil(kink) + (double)o);
+    } else {
+      consider(kink);
+    }
+  };
+  if (narrow && !exact) {
     const int W = (int)(u - l) + 1;
     for (int p = 0; p < W; ++p) consider(l + (double)p);
   } else {
 #pragma unroll
-    for (int k = 0; k < kJumpLane; ++k) {
-      if (k < deg) {
-        const double kink = xb - r[k] / a[k];
-        if (isint) {
-          consider(floor(kink));
-          consider(ceil(kink));
-        } else {
-          consider(kink);
-        }
-      }
-    }
-    if (cact) {
-      const double kink = xb - rc / cq;
-      if (isint) {
-        consider(floor(kink));
-        consider(ceil(kink));
-      } else {
-        consider(kink);
-      }
-    }
+    for (int k = 0; k < kJumpLane; ++k)
+      if (k < deg) kink_values(xb - r[k] / a[k]);
+    if (cact) kink_values(xb - rc / cq);
     consider(l);
     consider(u);
     if (isint) {
@@ -227,12 +243,14 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
 
 __global__ __launch_bounds__(256) void k_jump_tasks(DevProblem P, const double* __restrict__ x,
                                                     const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                                    int32_t exact_data, int32_t obj_small,
                                                     const JumpTask* __restrict__ tasks, int32_t ntasks,
                                                     double* __restrict__ part) {
   const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (id >= ntasks) return;  // whole wavefronts leave together
   const int lane = threadIdx.x & (kWave - 1);
   const JumpTask T = tasks[id];
+  if (T.bins && jump_exact(st, exact_data, obj_small)) return;  // scored from bins
   const int q = T.q;
   const int beg = P.col_ptr[q], deg = P.col_ptr[q + 1] - beg;
   const double xb = x[q], l = P.lb[q], u = P.ub[q];
@@ -242,35 +260,205 @@ __global__ __launch_bounds__(256) void k_jump_tasks(DevProblem P, const double* 
   const double d = cd.t - xb;
   const int e0 = beg + T.chunk * kJumpChunk;
   const int e1 = min(beg + deg, e0 + kJumpChunk);
+  // each batch of 64 entries goes through this wavefront's LDS slice; every
+  // lane then reads entry k at one address (a broadcast)
+  __shared__ JumpEntry S[4][kWave];
+  JumpEntry* E = S[threadIdx.x >> 6];
   double v = 0.0;
   for (int base = e0; base < e1; base += kWave) {
     const int e = base + lane;
-    double rr = 0.0, aa = 0.0;
-    float ww0 = 0.0f, ww1 = -1.0f;
+    JumpEntry me{0.0, 0.0, 0.0f, -1.0f};
     if (e < e1) {
       const RowState s = rs[P.col_row[e]];
-      rr = s.r;
-      ww0 = s.w0;
-      ww1 = s.w1;
-      aa = P.col_val[e];
+      me.r = s.r;
+      me.w0 = s.w0;
+      me.w1 = s.w1;
+      me.a = P.col_val[e];
     }
+    // the previous batch's reads are done before the slice is overwritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    E[lane] = me;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int cnt = min(kWave, e1 - base);
+#pragma unroll 4
     for (int k = 0; k < cnt; ++k) {
-      const double rk = bcast(rr, k), ak = bcast(aa, k);
-      const float w0k = bcastf(ww0, k), w1k = bcastf(ww1, k);
-      const double y = rk + ak * d;
-      v = v + (double)w0k * relu(y);
-      if (w1k >= 0.0f) v = v + (double)w1k * relu(-y);
+      const JumpEntry q = E[k];
+      const double y = q.r + q.a * d;
+      v = v + (double)q.w0 * relu(y);
+      if (q.w1 >= 0.0f) v = v + (double)q.w1 * relu(-y);
     }
   }
   part[(size_t)T.slot * kWave + lane] = v;
 }
 
+// floor(n / d) and ceil(n / d) for d > 0 and |n|, |d| < 2^31, through one
+// FP64 division: an integer quotient is exact, and any other lies at least
+// 1/d from an integer while the rounding moves it by at most |n/d| 2^-53 <
+// 2^-22 / d, so floor and ceil are unchanged (64-bit integer division is a
+// long software sequence on the GPU).
+__device__ __forceinline__ long long floor_div(long long n, long long d) {
+  return (long long)floor((double)n / (double)d);
+}
+__device__ __forceinline__ long long ceil_div(long long n, long long d) {
+  return (long long)ceil((double)n / (double)d);
+}
+
+// One term w max(0, c + a p) over positions p = 0 .. W-1 as bin updates:
+// from the first positive position on (a > 0), or up to the last one
+// (a < 0), the term is w c + w a p.
+__device__ __forceinline__ void add_ramp(unsigned long long* K, unsigned long long* S, long long c, long long a,
+                                         long long w, int W) {
+  if (w == 0) return;
+  if (a > 0) {
+    const long long p0 = floor_div(-c, a) + 1;  // first p with c + a p > 0
+    if (p0 < W) {
+      const int k = (int)(p0 > 0 ? p0 : 0);
+      atomicAdd(&K[k], (unsigned long long)(w * c));
+      atomicAdd(&S[k], (unsigned long long)(w * a));
+    }
+  } else {
+    const long long p1 = ceil_div(c, -a);  // first p with c + a p <= 0
+    const int k = (int)(p1 < 0 ? 0 : (p1 > W ? W : p1));
+    if (k > 0) {
+      atomicAdd(&K[0], (unsigned long long)(w * c));
+      atomicAdd(&S[0], (unsigned long long)(w * a));
+      if (k < W) {
+        atomicAdd(&K[k], (unsigned long long)(-w * c));
+        atomicAdd(&S[k], (unsigned long long)(-w * a));
+      }
+    }
+  }
+}
+
+// The argmin of a narrow column from its bins (lane p holds bin p of the
+// offsets k and slopes sl, summed over the column's chunks): prefix sums
+// across the lanes give V(l + p) exactly, the cutoff term is added in
+// integers; lane 0 writes the jump value and score.
+__device__ __forceinline__ void bins_finish(const DevProblem& P, const WalkState* st, int q, double xb, long long k,
+                                            long long sl, double* jv, double* js) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double l = P.lb[q];
+  const int W = (int)(P.ub[q] - l) + 1;
+  const double cq = P.obj[q];
+  const bool cact = st->cut_active && cq != 0.0;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long yk = __shfl_up(k, o, kWave), ys = __shfl_up(sl, o, kWave);
+    if (lane >= o) {
+      k += yk;
+      sl += ys;
+    }
+  }
+  long long vi = k + (long long)lane * sl;
+  const double t = l + (double)lane;
+  if (cact) {
+    const long long y = (long long)st->rc + (long long)cq * (long long)(t - xb);
+    vi += (long long)st->wc * (y > 0 ? y : 0);
+  }
+  const double v = (double)vi;
+  bool found = false, have0 = false;
+  double bt = xb, bv = 0.0, v0 = 0.0;
+  if (lane < W) {
+    if (t == xb) {
+      v0 = v;
+      have0 = true;
+    } else {
+      found = true;
+      bt = t;
+      bv = v;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double ov = __shfl_xor(bv, o, kWave), ot = __shfl_xor(bt, o, kWave);
+    const bool of = __shfl_xor((int)found, o, kWave) != 0;
+    if (of && (!found || jump_better(ov, ot, bv, bt, xb))) {
+      found = true;
+      bt = ot;
+      bv = ov;
+    }
+  }
+  const unsigned long long m0 = __ballot(have0);
+  v0 = __shfl(v0, m0 ? __builtin_ctzll(m0) : 0, kWave);
+  if (lane == 0) {
+    jv[q] = found ? bt : xb;
+    js[q] = found ? v0 - bv : 0.0;
+  }
+}
+
+// One wavefront per bins task: the chunk's entries (and the twins of
+// equality rows), one per lane, as slope and offset bins of the column's
+// positions in the wavefront's own LDS slice. A task's entries lie in one
+// eighth of the rows, and the four tasks of a workgroup in the same eighth,
+// which the task order places on one XCD, so the row gathers stay in that
+// XCD's L2.
+__global__ __launch_bounds__(256) void k_jump_bins(DevProblem P, const double* __restrict__ x,
+                                                   const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                                   int32_t exact_data, int32_t obj_small,
+                                                   const JumpBinTask* __restrict__ tasks, int32_t ntasks,
+                                                   long long* __restrict__ bpart, double* __restrict__ jv,
+                                                   double* __restrict__ js) {
+  if (!jump_exact(st, exact_data, obj_small)) return;
+  const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (id >= ntasks) return;  // whole wavefronts leave together
+  const int lane = threadIdx.x & (kWave - 1);
+  __shared__ unsigned long long KB[4][kWave], SB[4][kWave];
+  unsigned long long* K = KB[threadIdx.x >> 6];
+  unsigned long long* S = SB[threadIdx.x >> 6];
+  K[lane] = 0ull;
+  S[lane] = 0ull;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const JumpBinTask T = tasks[id];
+  if (T.q < 0) return;  // padding of the row-range interleave
+  const int q = T.q;
+  const double xb = x[q], l = P.lb[q];
+  const int W = (int)(P.ub[q] - l) + 1;
+  // four entries per lane in flight: all loads of a step before any use
+  constexpr int kU = 4;
+  for (int e0 = T.e_beg + lane; e0 < T.e_end; e0 += kU * kWave) {
+    RowState r[kU];
+    double a[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * kWave;
+      if (e < T.e_end) {
+        r[u] = rs[P.col_row[e]];
+        a[u] = P.col_val[e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (e0 + u * kWave >= T.e_end) break;
+      const long long c = (long long)(r[u].r + a[u] * (l - xb));  // residual at x_q = l: an integer
+      const long long ai = (long long)a[u];
+      add_ramp(K, S, c, ai, (long long)r[u].w0, W);
+      if (r[u].w1 >= 0.0f) add_ramp(K, S, -c, -ai, (long long)r[u].w1, W);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (T.slot < 0) {
+    bins_finish(P, st, q, xb, (long long)K[lane], (long long)S[lane], jv, js);  // the whole column
+    return;
+  }
+  bpart[(size_t)T.slot * 2 * kWave + lane] = (long long)K[lane];
+  bpart[(size_t)T.slot * 2 * kWave + kWave + lane] = (long long)S[lane];
+}
+
 __global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double* __restrict__ x,
                                                       const RowState* __restrict__ rs,
                                                       const WalkState* __restrict__ st,
+                                                      int32_t exact_data, int32_t obj_small,
                                                       const JumpCol* __restrict__ cols, int32_t ncols,
-                                                      const double* __restrict__ part, double* __restrict__ jv,
+                                                      const double* __restrict__ part,
+                                                      const long long* __restrict__ bpart, double* __restrict__ jv,
                                                       double* __restrict__ js) {
   const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (id >= ncols) return;  // whole wavefronts leave together
@@ -287,6 +475,16 @@ __global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double
   bool found = false;
   double bt = xb, bv = 0.0, v0 = 0.0;
   bool have0 = false;
+  if (J.bn != 0 && jump_exact(st, exact_data, obj_small)) {
+    if (J.bn < 0) return;  // finished by its bins task
+    long long k = 0, sl = 0;
+    for (int ch = 0; ch < J.bn; ++ch) {
+      k += bpart[(size_t)(J.bfirst + ch) * 2 * kWave + lane];
+      sl += bpart[(size_t)(J.bfirst + ch) * 2 * kWave + kWave + lane];
+    }
+    bins_finish(P, st, q, xb, k, sl, jv, js);
+    return;
+  }
   for (int tile = 0; tile < J.ntiles; ++tile) {
     const JumpCand cd = jump_candidate(P, rs, st, q, beg, deg, xb, l, u, isint, narrow, tile * kWave + lane);
     const int s0 = J.first_slot + tile * J.nchunks;
@@ -326,14 +524,21 @@ __global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double
 }  // namespace
 
 hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs, const WalkState* st,
-                       const JumpTask* tasks, int32_t ntasks, const JumpCol* cols, int32_t ncols, double* part,
-                       double* jv, double* js, hipStream_t s) {
-  if (P.n > 0) hipLaunchKernelGGL(k_jump_lane, dim3((P.n + 255) / 256), dim3(256), 0, s, P, x, rs, st, jv, js);
-  if (ntasks > 0)
-    hipLaunchKernelGGL(k_jump_tasks, dim3((ntasks + 3) / 4), dim3(256), 0, s, P, x, rs, st, tasks, ntasks, part);
-  if (ncols > 0)
-    hipLaunchKernelGGL(k_jump_combine, dim3((ncols + 3) / 4), dim3(256), 0, s, P, x, rs, st, cols, ncols, part, jv,
+                       int32_t exact_data, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
+                       const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols, int32_t ncols, double* part,
+                       long long* bpart, double* jv, double* js, hipStream_t s) {
+  if (P.n > 0)
+    hipLaunchKernelGGL(k_jump_lane, dim3((P.n + 255) / 256), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small, jv,
                        js);
+  if (nbtasks > 0)
+    hipLaunchKernelGGL(k_jump_bins, dim3((unsigned)((nbtasks + 3) / 4)), dim3(256), 0, s, P, x, rs, st, exact_data,
+                       obj_small, btasks, nbtasks, bpart, jv, js);
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_jump_tasks, dim3((ntasks + 3) / 4), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small,
+                       tasks, ntasks, part);
+  if (ncols > 0)
+    hipLaunchKernelGGL(k_jump_combine, dim3((ncols + 3) / 4), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small,
+                       cols, ncols, part, bpart, jv, js);
   return hipGetLastError();
 }
 

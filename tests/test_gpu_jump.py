@@ -123,3 +123,22 @@ def test_jump_edge_cases(chap):
         say(f"jump edge cases call {k}")
         check_exact(chap, mip, x, w, P.objective(x) - 1.0 if k else math.inf, f"edge {k}", G)
     assert G.last_jump_ms() > 0.0
+
+
+def test_jump_narrow_long_columns_exact_and_not(chap):
+    """Narrow integer columns longer than one lane's entries on integer data:
+    with integer weights and an integral cutoff residual they are scored from
+    slope and offset bins, with fractional weights or a fractional cutoff
+    residual by the wavefront tasks; both equal the oracle bit for bit."""
+    mip = mipgen.random_mixed(341, n=400, m=3000, max_row_nnz=6, frac_bin=0.3, frac_int=0.7, int_width=30,
+                              long_cols=6, long_deg=2500)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    x = mipgen.random_point(mip, 5)
+    w_int = mipgen.random_weights(P.mp + 1, 5, wmax=9)
+    w_frac = (w_int * 0.5 + 0.25).astype(np.float32)
+    f = P.objective(x)
+    for name, w, cut in (("integer weights", w_int, math.inf), ("integral cutoff", w_int, f - 2.0),
+                         ("fractional cutoff", w_int, f - 2.5), ("fractional weights", w_frac, math.inf)):
+        say(f"jump narrow long columns: {name}")
+        check_exact(chap, mip, x, w, cut, name, G)
