@@ -30,7 +30,6 @@ HBM_PEAK_GBS = 8000.0
 # see profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the
 # pass kernels as they are; None until they are measured again after a change.
 PASS_TRAFFIC_BYTES = 498_700_000
-FP64_VECTOR_TFLOPS = 78.6
 METRIC = "tabu moves/s, best-shift nnz/s, % HBM peak; plain vs batched/learned"
 
 
@@ -242,32 +241,11 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def jump_flops(mip, cutoff_active: bool) -> int:
-    """FP64 operations of one jump-value pass as the kernels evaluate it: each
-    evaluated value t of column j (every value of an integer domain of at
-    most 64 values; otherwise two per entry, the cutoff kinks, both bounds
-    and xbar +- 1 for integers, one per entry and both bounds for continuous
-    variables; plus xbar itself) sums one term per normalised row of j (and
-    the cutoff row), 4 operations each (product, sum, weight product,
-    accumulation)."""
-    deg = np.diff(mip.csc_col_ptr).astype(np.int64)
-    eq_row = (mip.sense == ord("E")).astype(np.int64)
-    twins = np.add.reduceat(eq_row[mip.csc_row], mip.csc_col_ptr[:-1]) if mip.nnz else np.zeros(mip.n, np.int64)
-    twins = np.where(deg > 0, twins, 0)
-    cut = ((mip.obj != 0) & cutoff_active).astype(np.int64)
-    terms = deg + twins + cut
-    W = mip.ub - mip.lb + 1
-    narrow = (mip.is_int == 1) & np.isfinite(W) & (W <= 64)
-    integer = mip.is_int == 1
-    evals = np.where(narrow, np.where(np.isfinite(W), W, 0),
-                     np.where(integer, 2 * (deg + cut) + 5, deg + cut + 3)).astype(np.int64)
-    return int(4 * np.sum(evals * terms))
-
-
 def jump_values_leg(G, mip, xd, wd, cutoff, reps):
     """chap_jump_values on the walk's final point: kernel time (HIP events),
-    nonzeros per second, and its FP64 arithmetic rate against the vector
-    FP64 peak (the pass evaluates V at every value it tries: ALU-bound)."""
+    nonzeros per second, and the pass's algorithmic bytes (the data of the
+    best-shift pass: every nonzero's index, value and row state, every
+    column's bounds, point and results) against the HBM peak."""
     import torch
 
     times = []
@@ -277,14 +255,14 @@ def jump_values_leg(G, mip, xd, wd, cutoff, reps):
     torch.cuda.synchronize()
     ms = float(np.mean(times[3:]))
     act = math.isfinite(cutoff)
-    flops = jump_flops(mip, act)
+    B = algorithmic_bytes(mip, act)
     nnz = mip.nnz + (mip.nnz_obj if act else 0)
+    achieved = B / (ms * 1e-3) / 1e9
     out = {"pass_us": ms * 1e3, "nnz_per_s": nnz / (ms * 1e-3),
-           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "flops_per_pass": flops}}
-    out["roofline"]["frac"] = out["roofline"]["achieved"] / FP64_VECTOR_TFLOPS
-    log(f"jump values {ms * 1e3:.1f} us, {flops / 1e9:.2f} GFLOP FP64, "
-        f"{out['roofline']['achieved']:.1f} TFLOP/s ({100 * out['roofline']['frac']:.1f} % of FP64 vector peak)")
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": B}}
+    log(f"jump values {ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f} % "
+        f"of 8 TB/s)")
     return out
 
 
