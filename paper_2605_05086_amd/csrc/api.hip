@@ -702,6 +702,7 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   DevProblem& D = P->dev;
   D.n = n;
   D.ms = m;
+  D.sums_exact = P->exact_incremental;
   D.eps = P->eps;
   int32_t *d_cptr, *d_crow, *d_rptr, *d_rcol, *d_perm;
   double *d_cval, *d_rval, *d_rrhs, *d_lb, *d_ub, *d_obj;

@@ -145,6 +145,11 @@ struct DevProblem {
   const double* obj;
   const uint8_t* is_int;
   const int32_t* perm;  // original index of each internal column
+  // 1: every row activity within the bounds is an exact integer below 2^52,
+  // so the residual sums of a point inside the bounds may be added in any
+  // order
+  int32_t sums_exact;
+  int32_t pad_;
 };
 
 // Mutable state of one walk (also used, with k = 0 and iters = 1, by a single

@@ -118,7 +118,10 @@ struct ObjState {
 // group of kResidualLanes lanes owns a row: the lanes load consecutive
 // entries and form their products side by side (coalesced row reads), and
 // every lane of the group then adds the products in entry order from its
-// neighbours' registers, so the sum is the sequential one bit for bit.
+// neighbours' registers, so the sum is the sequential one bit for bit. On
+// instances whose row activities are exact integers (P.sums_exact) the
+// order cannot change the sum: each lane adds its own products and the
+// group combines the lanes' sums in three exchanges.
 // Weights: kWeightsKeep leaves them, kWeightsUnit sets every weight to 1,
 // kWeightsScatter copies the caller's normalised weights. With grow, the
 // compact row copy is written too (unit weights, all-integer instances).
@@ -161,11 +164,22 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
 #pragma unroll
       for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * xg[c[u]];
     }
+    if (P.sums_exact) {
+      // integer products with exact partial sums: each lane keeps its own
+      // sum, the group adds them once at the end
 #pragma unroll
-    for (int u = 0; u < kResidualSteps; ++u) {
-      const int cnt = min(kResidualLanes, end - (e0 + u * kResidualLanes));
-      for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod[u], t, kResidualLanes);
+      for (int u = 0; u < kResidualSteps; ++u) acc = acc + prod[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kResidualSteps; ++u) {
+        const int cnt = min(kResidualLanes, end - (e0 + u * kResidualLanes));
+        for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod[u], t, kResidualLanes);
+      }
     }
+  }
+  if (P.sums_exact) {
+#pragma unroll
+    for (int o = 1; o < kResidualLanes; o <<= 1) acc = acc + __shfl_xor(acc, o, kResidualLanes);
   }
   if (g != 0) return;
   const double r = acc - P.row_rhs[i];
