@@ -1373,13 +1373,11 @@ int slot_graph(WalkSlot& S, int64_t K, int compact, hipGraphExec_t* out) {
       // subset kernels
       cap_err = launch_affected(S.L.walks, S.aff_L, F, S.s);
       if (cap_err == hipSuccess && !F.full_slist) cap_err = launch_pass(S.L, S.s, &S.ps, true);
-      if (cap_err == hipSuccess)
-        cap_err = launch_aff_short(S.L.walks, F.run, std::min(1024, (n + 255) / 256), compact, S.s);
-      if (cap_err == hipSuccess && S.aff_general)
-        cap_err = launch_aff_wave(S.L.walks, S.aff_L, std::min(256, (n + 3) / 4), compact, S.s);
-      if (cap_err == hipSuccess)
-        cap_err = launch_subset_grids(S.L.walks, S.aff_L, std::min(256, F.sub_cap), 64, 32, S.aff_general, compact,
-                                      S.s);
+      if (cap_err == hipSuccess) {
+        const int g[4] = {std::min(1024, (n + 255) / 256), S.aff_general ? std::min(256, (n + 3) / 4) : 0,
+                          std::min(256, F.sub_cap), S.aff_general ? 32 : 0};
+        cap_err = launch_aff_score(S.L.walks, S.aff_L, F.run, g, 64, compact, S.s);
+      }
     } else {
       cap_err = launch_pass(S.L, S.s, &S.ps, true);
     }

@@ -602,7 +602,7 @@ struct LearnCtx {
   const int32_t* elig_list;  // internal indices of proposable columns
   int32_t n_elig;
   // 1: listed short columns (the plan's short range) are scored one per lane
-  // by k_aff_short, and the subset kernels leave them alone
+  // by k_aff_score's lane role, and the subset kernels leave them alone
   int32_t short_lane;
   int32_t mp;                // normalised rows (for the violated fraction)
   double c_max;              // max |c_j| (0 when c = 0)
@@ -768,12 +768,12 @@ hipError_t launch_hamming(const HamTask* tasks, int32_t ntasks, int32_t* dist, h
 // is a new incumbent, the kept best objective; the better best infeasible
 // record.
 hipError_t launch_restart_fix(WalkState* st, const RestartKeep& keep, hipStream_t s);
-// The iteration's short columns (AffRun), one lane each, as the full pass
-// scores them (kernels_pass.hip); grid-stride over the list.
-hipError_t launch_aff_short(const WalkCtx* C, const AffRun* run, int grid, int compact, hipStream_t s);
-// The iteration's listed general columns of at most 64 breakpoints, one
-// wavefront each (kernels_pass.hip).
-hipError_t launch_aff_wave(const WalkCtx* C, const LearnCtx* L, int grid, int compact, hipStream_t s);
+// The whole scoring of an affected-rescoring iteration: one launch whose
+// workgroups take four roles: the short columns by lanes (g[0]), general
+// columns of at most 64 breakpoints by wavefronts (g[1]), the subset chunks
+// (g[2]) and the subset general columns (g[3]); then the subset combine.
+hipError_t launch_aff_score(const WalkCtx* C, const LearnCtx* L, const AffRun* run, const int g[4], int combine_grid,
+                            int compact, hipStream_t s);
 // Move choice over the proposal set and the stored-row update of its move
 // (kernels_walk.hip).
 hipError_t launch_subset_select(const WalkCtx* C, const LearnCtx* L, hipStream_t s);

@@ -377,15 +377,15 @@ __global__ __launch_bounds__(256) void k_short(const WalkCtx* __restrict__ walks
 // The short columns of an affected-rescoring iteration, one lane each
 // (grid-stride over the list; classes padded to whole wavefronts, -1 marks
 // padding), with the full pass's per-column code.
+// b, nb: this workgroup's index among the nb workgroups of the role.
 template <typename Rows>
-__global__ __launch_bounds__(256) void k_aff_short(const WalkCtx* __restrict__ walks, const AffRun* __restrict__ run) {
-  const WalkCtx& C = walks[0];
+__device__ __forceinline__ void aff_short_body(const WalkCtx& C, const AffRun* run, int b, int nb) {
   if (C.st->k >= C.st->iters) return;
   const Rows rs = rows_of<Rows>(C);
   const int32_t* seg = C.plan.short_seg;
   const int count = run->n_s;
   const int32_t* list = run->slist;
-  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < count; i += (int)(gridDim.x * blockDim.x)) {
+  for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < count; i += nb * (int)blockDim.x) {
     const int q = list[i];
     if (q < 0) continue;
     if (q < seg[1]) {
@@ -1899,16 +1899,13 @@ __global__ __launch_bounds__(256) void k_sort_wave(const WalkCtx* __restrict__ w
 // breakpoints) in an affected-rescoring iteration: one wavefront each
 // (grid-stride over the subset list).
 template <typename Rows>
-__global__ __launch_bounds__(256) void k_aff_wave(const WalkCtx* __restrict__ walks, const LearnCtx* __restrict__ lc) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
+__device__ __forceinline__ void aff_wave_body(const WalkCtx& C, const LearnCtx& L, int b, int nb, WaveSortSmem& S) {
   if (C.st->k >= C.st->iters || L.ls->idle) return;
-  __shared__ WaveSortSmem S;
   const int wv = threadIdx.x >> 6;
   const Rows rs = rows_of<Rows>(C);
   const int count = L.ls->tk[0].count;
   const int q0 = C.plan.sort_begin[0], q1 = C.plan.sort_begin[1];
-  for (int i = (int)blockIdx.x * 4 + wv; i < count; i += (int)gridDim.x * 4) {
+  for (int i = b * 4 + wv; i < count; i += nb * 4) {
     const int q = L.sel[0][i];
     if (q < q0 || q >= q1) continue;  // uniform across the wavefront
     sort_wave_column<Rows>(C, rs, q, S, wv);
@@ -2047,23 +2044,27 @@ __global__ __launch_bounds__(1024) void k_sort_long(const WalkCtx* __restrict__ 
 // (k_subset_general).
 // ---------------------------------------------------------------------------
 
+struct SubsetChunkSmem {
+  double bins[kNarrowBins];
+  double red[4];
+  unsigned long long scand;
+};
+
 template <typename Rows>
-__global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict__ walks,
-                                                       const LearnCtx* __restrict__ lc) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
+__device__ __forceinline__ void subset_chunks_body(const WalkCtx& C, const LearnCtx& L, int b, int nb,
+                                                   SubsetChunkSmem& SM) {
   const Rows rs = rows_of<Rows>(C);
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
-  __shared__ double bins[kNarrowBins];
-  __shared__ double red[4];
-  __shared__ unsigned long long scand;
+  double* bins = SM.bins;
+  double* red = SM.red;
+  unsigned long long& scand = SM.scand;
   const int cnt = L.ls->tk[0].count;
   const int chunks = L.ls->tk[0].chunks;
   const int tid = threadIdx.x;
   const double eps = P.eps;
-  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+  for (int c = b; c < chunks; c += nb) {
     // selected column of chunk c: the largest i with sub_off[i] <= c
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {
@@ -2125,6 +2126,14 @@ __global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict
   }
 }
 
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_subset_chunks(const WalkCtx* __restrict__ walks,
+                                                       const LearnCtx* __restrict__ lc) {
+  __shared__ SubsetChunkSmem SM;
+  subset_chunks_body<Rows>(walks[0], *lc, (int)blockIdx.x, (int)gridDim.x, SM);
+}
+
+
 // One wavefront per selected binary or narrow column (grid-stride): its
 // chunks in order, then the flip score or the bins' scan and argmax.
 __global__ __launch_bounds__(256) void k_subset_combine(const WalkCtx* __restrict__ walks,
@@ -2169,25 +2178,32 @@ __global__ __launch_bounds__(256) void k_subset_combine(const WalkCtx* __restric
 
 // One workgroup per selected general column (grid-stride; Algorithm 1 with
 // the LDS sort).
-__global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restrict__ walks,
-                                                        const LearnCtx* __restrict__ lc) {
-  const WalkCtx& C = walks[0];
-  const LearnCtx& L = *lc;
+struct SubsetGeneralSmem {
+  double spos[kSubsetCap];
+  double sdel[kSubsetCap];
+  int smk[kSubsetCap];
+  int scount;
+  double red[8];
+  int redk[8];
+};
+
+__device__ __forceinline__ void subset_general_body(const WalkCtx& C, const LearnCtx& L, int b, int nb,
+                                                    SubsetGeneralSmem& SM) {
   const DevProblem& P = C.P;
   const WalkState* st = C.st;
   if (st->k >= st->iters || L.ls->idle) return;
-  __shared__ double spos[kSubsetCap];
-  __shared__ double sdel[kSubsetCap];
-  __shared__ int smk[kSubsetCap];
-  __shared__ int scount;
-  __shared__ double red[8];
-  __shared__ int redk[8];
+  double* spos = SM.spos;
+  double* sdel = SM.sdel;
+  int* smk = SM.smk;
+  int& scount = SM.scount;
+  double* red = SM.red;
+  int* redk = SM.redk;
   const int tid = threadIdx.x;
   const int count = L.ls->tk[0].count;
-  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+  for (int i = b; i < count; i += nb) {
     const int q = L.sel[0][i];
     if (L.cls[q] != SUB_GENERAL) continue;
-    // affected rescoring: short columns go to lanes, the wave-sort class to k_aff_wave
+    // affected rescoring: short columns go to lanes, the wave-sort class to wavefronts (k_aff_score)
     if (L.short_lane && ((q >= C.plan.short_seg[0] && q < C.plan.short_seg[kShortMax + 2]) ||
                          (q >= C.plan.sort_begin[0] && q < C.plan.sort_begin[1])))
       continue;
@@ -2224,6 +2240,38 @@ __global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restric
   }
 }
 
+__global__ __launch_bounds__(256) void k_subset_general(const WalkCtx* __restrict__ walks,
+                                                        const LearnCtx* __restrict__ lc) {
+  __shared__ SubsetGeneralSmem SM;
+  subset_general_body(walks[0], *lc, (int)blockIdx.x, (int)gridDim.x, SM);
+}
+
+// The scoring of an affected-rescoring iteration in one launch: workgroups
+// [0, g[0]) score the short columns by lanes, the next g[1] the wave-sort
+// class, the next g[2] the subset chunks and the last g[3] the other general
+// columns (each role strides over its own work).
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_aff_score(const WalkCtx* __restrict__ walks,
+                                                   const LearnCtx* __restrict__ lc, const AffRun* __restrict__ run,
+                                                   int g0, int g1, int g2, int g3) {
+  __shared__ union {
+    WaveSortSmem w;
+    SubsetChunkSmem c;
+    SubsetGeneralSmem g;
+  } U;
+  const WalkCtx& C = walks[0];
+  const int b = (int)blockIdx.x;
+  if (b < g0) {
+    aff_short_body<Rows>(C, run, b, g0);
+  } else if (b < g0 + g1) {
+    aff_wave_body<Rows>(C, *lc, b - g0, g1, U.w);
+  } else if (b < g0 + g1 + g2) {
+    subset_chunks_body<Rows>(C, *lc, b - g0 - g1, g2, U.c);
+  } else if (b < g0 + g1 + g2 + g3) {
+    subset_general_body(C, *lc, b - g0 - g1 - g2, g3, U.g);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
@@ -2238,19 +2286,14 @@ hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_gr
   return hipGetLastError();
 }
 
-hipError_t launch_aff_wave(const WalkCtx* C, const LearnCtx* L, int grid, int compact, hipStream_t s) {
+hipError_t launch_aff_score(const WalkCtx* C, const LearnCtx* L, const AffRun* run, const int g[4], int combine_grid,
+                            int compact, hipStream_t s) {
+  const unsigned total = (unsigned)(g[0] + g[1] + g[2] + g[3]);
   if (compact)
-    hipLaunchKernelGGL(k_aff_wave<CompactRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, L);
+    hipLaunchKernelGGL(k_aff_score<CompactRows>, dim3(total), dim3(256), 0, s, C, L, run, g[0], g[1], g[2], g[3]);
   else
-    hipLaunchKernelGGL(k_aff_wave<FullRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, L);
-  return hipGetLastError();
-}
-
-hipError_t launch_aff_short(const WalkCtx* C, const AffRun* run, int grid, int compact, hipStream_t s) {
-  if (compact)
-    hipLaunchKernelGGL(k_aff_short<CompactRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, run);
-  else
-    hipLaunchKernelGGL(k_aff_short<FullRows>, dim3((unsigned)std::max(grid, 1)), dim3(256), 0, s, C, run);
+    hipLaunchKernelGGL(k_aff_score<FullRows>, dim3(total), dim3(256), 0, s, C, L, run, g[0], g[1], g[2], g[3]);
+  hipLaunchKernelGGL(k_subset_combine, dim3((unsigned)std::max(combine_grid, 1)), dim3(256), 0, s, C, L);
   return hipGetLastError();
 }
 
