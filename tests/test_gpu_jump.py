@@ -142,3 +142,18 @@ def test_jump_narrow_long_columns_exact_and_not(chap):
                          ("fractional cutoff", w_int, f - 2.5), ("fractional weights", w_frac, math.inf)):
         say(f"jump narrow long columns: {name}")
         check_exact(chap, mip, x, w, cut, name, G)
+
+
+def test_jump_without_rows(chap):
+    """Variables in no row: the cutoff row alone (c != 0) or nothing to
+    violate (every value ties at V = 0: the value next to xbar, the smaller
+    first)."""
+    from helpers import make_mip
+    mip = make_mip(4, [({3: 1.0}, "L", 2.0)], [0, -5, 0, 0], [10, 5, 7.5, 4], [1, 1, 0, 1], obj=[3, -2, 1.5, 0])
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    x = np.array([4.0, 0.0, 2.5, 4.0])
+    w = np.ones(P.mp + 1, dtype=np.float32)
+    for cut in (math.inf, P.objective(x) - 3.0, P.objective(x) + 7.0):
+        say(f"jump without rows cutoff={cut}")
+        check_exact(chap, mip, x, w, cut, f"no rows {cut}", G)

@@ -116,3 +116,31 @@ def test_rescore_repeated_runs_and_start_points(chap):
         compare_runs(G.tabu_run(iters, 5, seed), P.tabu_run(iters, 5, seed), f"run {k}")
     x0 = mipgen.random_point(mip, 5)
     compare_runs(G.tabu_run(90, 5, 0, x0=x0), P.tabu_run(90, 5, 0, x0=x0), "x0")
+
+
+def test_rescore_problem_in_batches_and_single_passes(chap):
+    """A problem created with rescore_cap scores every column in batched
+    walks and single passes (the option only changes chap_tabu_run walks),
+    with the same results as a problem without it and as the oracle."""
+    import math
+
+    import torch
+
+    mip = mipgen.random_mixed(181, n=300, m=200, max_row_nnz=6, frac_bin=0.4, frac_int=0.4, long_cols=3, long_deg=60)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip, rescore_cap=256)
+    F = chap.Problem(mip, row_stage=-1)
+    say("rescore problem in a batch")
+    runs = chap.batch_run([G, F], [0, 1, 0], [3, 3, 4], 80, 5)
+    assert runs[0].trace.tobytes() == runs[1].trace.tobytes()
+    compare_runs(runs[2], P.tabu_run(80, 5, 4), "batch walk on the rescore problem")
+    say("rescore problem single pass")
+    x = mipgen.random_point(mip, 2)
+    w = mipgen.random_weights(P.mp + 1, 2)
+    xd = torch.from_numpy(x).cuda()
+    wd = torch.from_numpy(w).cuda()
+    for cut in (math.inf, P.objective(x) - 1.0):
+        xh, s = G.best_shift(xd, wd, cut)
+        torch.cuda.synchronize()
+        oxh, os_ = P.best_shift(x, w, cut)
+        assert np.array_equal(xh.cpu().numpy(), oxh) and np.array_equal(s.cpu().numpy(), os_)

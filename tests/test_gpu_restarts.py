@@ -64,3 +64,16 @@ def test_restart_argument_checks(chap):
     for every, dmin in ((0, 1), (-5, 1), (10, -1)):
         with pytest.raises(chap.ChapError, match="CHAP_EINVAL"):
             chap.batch_restarts([G], [0], [1], 30, 5, every, dmin)
+
+
+def test_restart_segments_longer_than_the_walk(chap):
+    """restart_every >= iters: one segment, no restart, the plain batch."""
+    mips = [mipgen.random_mixed(405, n=60, m=40, max_row_nnz=5), mipgen.tiny_binary(0)]
+    probs = [chap.Problem(m) for m in mips]
+    wp, ws = [0, 1, 0], [2, 2, 2]
+    runs = chap.batch_restarts(probs, wp, ws, 90, 5, 90, 10**9)
+    plain = chap.batch_run(probs, wp, ws, 90, 5)
+    for g, p in zip(runs, plain):
+        assert g.restarts == []
+        assert g.trace.tobytes() == p.trace.tobytes()
+        assert g.x.tobytes() == p.x.tobytes()
