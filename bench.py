@@ -107,7 +107,7 @@ def main():
                     help="also run one plain device copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned-proposal and batched-walk comparisons against the plain walk")
-    ap.add_argument("--batch-iters", type=int, default=200)
+    ap.add_argument("--batch-iters", type=int, default=1000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-walk comparison")
     ap.add_argument("--configs-only", action="store_true",
                     help="run only configurations 1 and 2 (plain and affected rescoring) and print them")
@@ -419,6 +419,19 @@ def compare_batched(chap, iters, tenure, small, plain=True):
     t0 = time.perf_counter()
     pool = mipgen.batch_pool(total_nnz=2_000_000 if small else 20_000_000)
     probs = [chap.Problem(m) for m in pool]
+    # per-instance plan chosen by chap_autotune (short-column threshold; the
+    # pool's columns are short and general, so the long-column knobs do not
+    # apply), timed on a 32-iteration walk of each instance
+    t1 = time.perf_counter()
+    chosen = {}
+    for i, m in enumerate(pool):
+        best, _ = chap.autotune(probs[i], candidates=[{"short_max": 4}, {"short_max": 8}], walk_iters=32)
+        chosen[int(best.short_max)] = chosen.get(int(best.short_max), 0) + 1
+        if best.short_max != 8:
+            probs[i] = chap.Problem(m, short_max=int(best.short_max))
+    tune = {"candidates": [{"short_max": 4}, {"short_max": 8}], "chosen_short_max": chosen,
+            "seconds": time.perf_counter() - t1}
+    log(f"autotune over the pool: {chosen} in {tune['seconds']:.1f} s")
     nw = 256
     wp = np.arange(nw) % len(pool)
     ws = np.arange(nw) + 1
@@ -453,7 +466,7 @@ def compare_batched(chap, iters, tenure, small, plain=True):
     if not plain:
         log(f"batched: {bms:.1f} ms (GPU graphs), {bms / iters:.3f} ms per batched iteration")
         return {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
-                "batched_gpu_ms": bms, "batched_wall_s": bwall, "roofline": roof, "restarts": restarts,
+                "batched_gpu_ms": bms, "batched_wall_s": bwall, "roofline": roof, "restarts": restarts, "autotune": tune,
                 "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3)}}
     pms = 0.0
     pwall = 0.0
@@ -467,7 +480,7 @@ def compare_batched(chap, iters, tenure, small, plain=True):
     out = {"walks": nw, "instances": len(pool), "pool_nnz": int(sum(m.nnz for m in pool)), "iters": iters,
            "batched_gpu_ms": bms, "plain_gpu_ms_sum": pms, "batched_wall_s": bwall, "plain_wall_s": pwall,
            "identical_trajectories": bool(same), "speedup_at_equal_final_score": pms / bms, "roofline": roof,
-           "restarts": restarts,
+           "restarts": restarts, "autotune": tune,
            "walk_iters_per_s": {"batched": nw * iters / (bms * 1e-3), "plain": nw * iters / (pms * 1e-3)}}
     log(f"batched: {bms:.1f} ms vs plain {pms:.1f} ms (GPU graphs), identical={same}")
     return out
