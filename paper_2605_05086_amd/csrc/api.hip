@@ -725,6 +725,10 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
     CHAP_HIP(A.upload(&d_inv, inv));
     P->d_inv = d_inv;
   }
+  // caller's order -> internal order sends j to inv[j]; back, q to perm[q]
+  CHAP_HIP(build_perm_plan(inv, A, &P->to_internal));
+  CHAP_HIP(build_perm_plan(perm, A, &P->to_caller));
+  CHAP_HIP(A.alloc(&P->bs_stage, 2 * (size_t)n));
   CHAP_HIP(A.upload(&d_pair, P->pair));
   CHAP_HIP(A.upload(&d_nidx, P->nidx));
   D.col_ptr = d_cptr;
@@ -741,6 +745,18 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
   D.perm = d_perm;
   P->d_pair = d_pair;
   P->d_nidx = d_nidx;
+  D.row_c8 = nullptr;
+  {
+    bool fits = true;
+    for (double a : rval) fits = fits && a == std::nearbyint(a) && std::fabs(a) <= 127.0;
+    if (fits && !rval.empty()) {
+      std::vector<int8_t> c8(rval.size());
+      for (size_t e = 0; e < rval.size(); ++e) c8[e] = (int8_t)rval[e];
+      int8_t* d_c8;
+      CHAP_HIP(A.upload(&d_c8, c8));
+      D.row_c8 = d_c8;
+    }
+  }
   if (!packs.empty()) {
     PackTask* dp;
     CHAP_HIP(A.upload(&dp, packs));
@@ -840,13 +856,14 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   if (std::isnan(cutoff_rhs)) return fail(CHAP_EINVAL, "chap_best_shift: cutoff_rhs is NaN");
   hipStream_t s = (hipStream_t)hip_stream;
   const uint32_t epoch = ++p->bs_epoch == 0 ? ++p->bs_epoch : p->bs_epoch;  // never 0
-  CHAP_HIP(launch_stage_x(p->dev.perm, d_x, p->bs_x, p->bs_xc, p->bs_state, epoch, p->n, s));
-  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
-                                   p->bs_rs, s));
+  CHAP_HIP(launch_stage_x_plan(p->to_internal, d_x, p->bs_x, p->bs_xc, p->bs_state, epoch, p->bs_stage, s));
+  // the state first (a single pass counts no violated rows, so it reads no
+  // residual), then the residuals with the compact copy and its check
   const double cut = (cutoff_rhs == HUGE_VAL) ? HUGE_VAL : cutoff_rhs;
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, p->bs_objacc, 1,
                              0, p->obj_integral, cut, d_w + p->mp, 0, 0, s));
-  if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
+                                   p->bs_rs, s, p->bs_grow));
   if (p->n > 0 && !p->bs_exec) {
     // capture the pass once (its arguments are the problem's own buffers)
     if (!p->bs_cap) CHAP_HIP(hipStreamCreateWithFlags(&p->bs_cap, hipStreamNonBlocking));
@@ -871,7 +888,7 @@ int chap_best_shift(chap_problem* p, const double* d_x, const float* d_w, double
   CHAP_HIP(hipEventRecord(p->pass_ev[0], s));
   if (p->n > 0) CHAP_HIP(hipGraphLaunch(p->bs_exec, s));
   CHAP_HIP(hipEventRecord(p->pass_ev[1], s));
-  CHAP_HIP(launch_gather2(p->d_inv, p->bs_xhat, p->bs_s, d_shift, d_score, p->n, s));
+  CHAP_HIP(launch_gather2_plan(p->to_caller, p->bs_xhat, p->bs_s, d_shift, d_score, p->bs_stage, s));
   p->pass_timed = true;
   return CHAP_OK;
 }
@@ -890,6 +907,41 @@ int chap_best_shift_pass_ms(chap_problem* p, double* ms) {
 }  // extern "C"
 
 namespace chap {
+
+hipError_t build_perm_plan(const std::vector<int32_t>& dest, DeviceArena& A, PermPlan* plan) {
+  const int32_t n = (int32_t)dest.size();
+  plan->n = n;
+  if (n == 0) return hipSuccess;
+  const int32_t nb = (int32_t)(((int64_t)n + kPermBlock - 1) / kPermBlock);
+  std::vector<uint16_t> lpos((size_t)n), dl((size_t)n);
+  std::vector<int32_t> sdst((size_t)n);
+  std::vector<int32_t> filled((size_t)nb, 0);  // slots of each output block taken by earlier chunks
+  std::vector<std::pair<int32_t, int32_t>> items;
+  items.reserve(kPermChunk);
+  for (int64_t base = 0; base < n; base += kPermChunk) {
+    const int64_t end = std::min<int64_t>(n, base + kPermChunk);
+    items.clear();
+    for (int64_t e = base; e < end; ++e) items.emplace_back(dest[(size_t)e] / kPermBlock, (int32_t)e);
+    std::sort(items.begin(), items.end());  // by output block, then input index
+    for (size_t r = 0; r < items.size(); ++r) {
+      const int32_t b = items[r].first, e = items[r].second;
+      const int32_t slot = b * kPermBlock + filled[(size_t)b]++;
+      lpos[(size_t)e] = (uint16_t)r;
+      sdst[(size_t)(base + (int64_t)r)] = slot;
+      dl[(size_t)slot] = (uint16_t)(dest[(size_t)e] - b * kPermBlock);
+    }
+  }
+  uint16_t *d_lpos, *d_dl;
+  int32_t* d_sdst;
+  hipError_t e;
+  if ((e = A.upload(&d_lpos, lpos)) != hipSuccess) return e;
+  if ((e = A.upload(&d_sdst, sdst)) != hipSuccess) return e;
+  if ((e = A.upload(&d_dl, dl)) != hipSuccess) return e;
+  plan->lpos = d_lpos;
+  plan->sdst = d_sdst;
+  plan->dl = d_dl;
+  return hipSuccess;
+}
 
 int alloc_walk(const chap_problem* p, int64_t trace_cap, DeviceArena& A, WalkCtx& c) {
   const int32_t n = p->n;

@@ -169,19 +169,20 @@ int chap_jump_values(chap_problem* p, const double* d_x, const float* d_w, doubl
   }
   hipStream_t s = (hipStream_t)hip_stream;
   const uint32_t epoch = ++p->bs_epoch == 0 ? ++p->bs_epoch : p->bs_epoch;  // never 0
-  CHAP_HIP(launch_stage_x(p->dev.perm, d_x, p->bs_x, p->bs_xc, p->bs_state, epoch, p->n, s));
-  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
-                                   p->bs_rs, s));
+  CHAP_HIP(launch_stage_x_plan(p->to_internal, d_x, p->bs_x, p->bs_xc, p->bs_state, epoch, p->bs_stage, s));
+  // the state first (no violated rows are counted, so it reads no
+  // residual), then the residuals with the compact copy and its check
+  // (integer weights below 2^16)
   CHAP_HIP(launch_state_init(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_partial, p->bs_ticket, p->bs_objacc, 1,
                              0, p->obj_integral, cutoff_rhs, d_w + p->mp, 0, 0, s));
-  // the weight check of the compact row copy (integer weights below 2^16)
-  if (p->bs_grow) CHAP_HIP(launch_fill_compact_checked(p->bs_rs, p->bs_grow, p->bs_state, p->m, s));
+  CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
+                                   p->bs_rs, s, p->bs_grow));
   CHAP_HIP(hipEventRecord(p->jump_ev[0], s));
   CHAP_HIP(launch_jump(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_grow ? 1 : 0, p->obj_fast, p->jump_tasks,
                        p->n_jump_tasks, p->jump_btasks, p->n_jump_btasks, p->jump_cols, p->n_jump_cols, p->jump_part,
                        p->jump_bpart, p->bs_xhat, p->bs_s, s));
   CHAP_HIP(hipEventRecord(p->jump_ev[1], s));
-  CHAP_HIP(launch_gather2(p->d_inv, p->bs_xhat, p->bs_s, d_jump, d_score, p->n, s));
+  CHAP_HIP(launch_gather2_plan(p->to_caller, p->bs_xhat, p->bs_s, d_jump, d_score, p->bs_stage, s));
   p->jump_timed = true;
   return CHAP_OK;
 }

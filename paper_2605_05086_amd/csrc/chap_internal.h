@@ -145,6 +145,9 @@ struct DevProblem {
   const double* obj;
   const uint8_t* is_int;
   const int32_t* perm;  // original index of each internal column
+  // row_val as int8 when every stored coefficient is an integer in
+  // [-127, 127] (the same values, a fifth of the bytes); null otherwise
+  const int8_t* row_c8;
   // 1: every row activity within the bounds is an exact integer below 2^52,
   // so the residual sums of a point inside the bounds may be added in any
   // order
@@ -461,6 +464,24 @@ inline bool pass_defers_combine(const BatchLaunch& L) {
   return L.compact == 1 && L.total[KS_STAGE_SCORE] > 0 && L.total[KS_COMBINE] > 0 && L.total[KS_CHUNK] == 0;
 }
 
+// A fixed permutation out[i] = in[src[i]] of n FP64 values applied in two
+// coalesced passes through LDS instead of one gather of random 8-byte
+// words: the first pass sorts each input chunk of kPermChunk values by
+// output block in LDS and writes it to a staging array in which each
+// output block's values are contiguous (one run per chunk); the second
+// places each block's values at their offsets in LDS and writes the block.
+constexpr int kPermChunk = 8192;  // input values per workgroup of the first pass
+constexpr int kPermBlock = 4096;  // output values per workgroup of the second pass
+struct PermPlan {
+  int32_t n = 0;
+  const uint16_t* lpos = nullptr;  // input e: rank in its chunk's (output block, e) order
+  const int32_t* sdst = nullptr;   // chunk base + rank: its staging slot
+  const uint16_t* dl = nullptr;    // staging slot s: offset of its value in its output block
+};
+// Plan of the permutation that sends input e to output dest[e] (dest a
+// bijection of [0, n)), uploaded into A.
+hipError_t build_perm_plan(const std::vector<int32_t>& dest, DeviceArena& A, PermPlan* plan);
+
 // ---- launchers (kernels_walk.hip) -----------------------------------------
 // Single-walk set-up kernels.
 // The point of a call in internal order: dst[q] = src[perm[q]] (src already
@@ -477,10 +498,12 @@ hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, h
 hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, const int8_t* xc,
                                 const WalkState* st, uint32_t epoch, RowState* rs, GatherRow* grow,
                                 hipStream_t stream);
-// Residuals from scratch with the caller's normalised weights w_norm.
+// Residuals from scratch with the caller's normalised weights w_norm. With
+// grow, also the checked compact copy (launch_fill_compact_checked's work):
+// the state initialisation must have run, and st is then written.
 hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair,
                                    const float* w_norm, const double* x, const int8_t* xc, const WalkState* st,
-                                   uint32_t epoch, RowState* rs, hipStream_t stream);
+                                   uint32_t epoch, RowState* rs, hipStream_t stream, GatherRow* grow = nullptr);
 // Seeded start point (internal order), and its byte copy when xc is set.
 hipError_t launch_start_point(const DevProblem& P, uint64_t seed, double* x, int8_t* xc, hipStream_t stream);
 // Initialise a walk state; computes f = c^T x, V, and the cutoff from
@@ -503,6 +526,13 @@ hipError_t launch_fill_compact_checked(const RowState* rs, GatherRow* grow, Walk
                                        hipStream_t stream);
 // dst[q] = src[perm[q]] (original order -> internal order)
 hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream);
+// launch_stage_x (dst not null, not src) through a plan of the same
+// permutation; stage: n doubles.
+hipError_t launch_stage_x_plan(const PermPlan& plan, const double* src, double* dst, int8_t* xc, WalkState* st,
+                               uint32_t epoch, double* stage, hipStream_t stream);
+// launch_gather2 through a plan of the same permutation; stage: 2n doubles.
+hipError_t launch_gather2_plan(const PermPlan& plan, const double* a, const double* b, double* da, double* db,
+                               double* stage, hipStream_t stream);
 // da[j] = a[inv[j]], db[j] = b[inv[j]] (internal order -> original order)
 hipError_t launch_gather2(const int32_t* inv, const double* a, const double* b, double* da, double* db, int32_t n,
                           hipStream_t stream);
@@ -835,6 +865,11 @@ struct chap_problem {
   long long* bs_objacc = nullptr;
   int8_t* bs_xc = nullptr;
   uint32_t bs_epoch = 0;
+  // chap_best_shift and chap_jump_values: the caller's point into internal
+  // order and the results back, as two-pass permutations over bs_stage
+  // (2n doubles)
+  chap::PermPlan to_internal, to_caller;
+  double* bs_stage = nullptr;
   std::vector<int32_t> perm;  // original index of each internal column
   // host copy of the caller's arrays (the autotuner re-plans from them)
   struct Raw {

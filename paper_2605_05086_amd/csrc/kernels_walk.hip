@@ -112,22 +112,115 @@ struct ObjState {
   }
 };
 
-// Residual from scratch of every stored row, r_i = sum_k a_ik x_k - b_i,
-// with the row's products summed one after another in the row's stored
+// Residual from scratch of every stored row, r_i = sum_k a_ik x_k - b_i
+// (coefficients from the int8 row copy when the instance has one), with the
+// row's products summed one after another in the row's stored
 // order (the order of the caller's CSR, as the definition is written). A
-// group of kResidualLanes lanes owns a row: the lanes load consecutive
-// entries and form their products side by side (coalesced row reads), and
-// every lane of the group then adds the products in entry order from its
-// neighbours' registers, so the sum is the sequential one bit for bit. On
+// group of kResidualLanes lanes owns kResidualRows consecutive rows, read
+// side by side so that more loads are in flight: for each row the lanes
+// load consecutive entries and form their products (coalesced row reads),
+// and every lane of the group then adds the products in entry order from
+// its neighbours' registers, so the sum is the sequential one bit for bit. On
 // instances whose row activities are exact integers (P.sums_exact) the
 // order cannot change the sum: each lane adds its own products and the
 // group combines the lanes' sums in three exchanges.
 // Weights: kWeightsKeep leaves them, kWeightsUnit sets every weight to 1,
 // kWeightsScatter copies the caller's normalised weights. With grow, the
-// compact row copy is written too (unit weights, all-integer instances).
+// compact row copy is written too (all-integer instances); with the
+// caller's weights it is checked as well: st->compact_rows, set by the
+// state initialisation that runs first, is cleared when a residual or a
+// weight (the cutoff's included) does not fit.
 constexpr int kResidualLanes = 8;
 constexpr int kResidualSteps = 4;
+constexpr int kResidualRows = 1;  // consecutive rows per group
+static_assert(kResidualRows <= kResidualLanes, "a lane of the group writes each row");
 enum { kWeightsKeep = 0, kWeightsUnit = 1, kWeightsScatter = 2 };
+
+constexpr int kResidualRound = kResidualLanes * kResidualSteps;
+
+// Sums of the products of one group's kResidualRows rows: where the row
+// activities are exact (P.sums_exact) each lane's share, added up by the
+// caller; otherwise the whole sequential sum on every lane of the group.
+// kResidualSteps entries of each row per lane in flight, every load of a
+// round issued before its products are summed. kSmall: int8 coefficients
+// and the byte copy of x, whose products are exact integers, summed in any
+// order (instances with exact row activities); otherwise the FP64 values
+// (the byte copy of x when xc is given) and, unless P.sums_exact, the
+// sequential order within each row.
+template <bool kSmall>
+__device__ __forceinline__ void residual_rounds(const DevProblem& P, const double* x, const int8_t* xc, int g,
+                                                const int* beg, const int* end, int rounds, double* acc) {
+  constexpr int R = kResidualRows, S = kResidualSteps;
+  const gptr<const double> val = gmem(P.row_val);
+  const gptr<const int8_t> c8 = gmem(P.row_c8);
+  const gptr<const int32_t> col = gmem(P.row_col);
+  const gptr<const double> xg = gmem(x);
+  const gptr<const int8_t> xcg = gmem(xc);
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) acc[rr] = 0.0;
+  for (int t0 = 0; t0 < rounds; ++t0) {
+    int c[R][S];
+    if constexpr (kSmall) {
+      int a[R][S];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+          const int e = beg[rr] + t0 * kResidualRound + u * kResidualLanes + g;
+          const bool in = e < end[rr];
+          c[rr][u] = in ? col[e] : 0;
+          a[rr][u] = in ? (int)c8[e] : 0;
+        }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int u = 0; u < S; ++u) acc[rr] = acc[rr] + (double)(a[rr][u] * (int)xcg[c[rr][u]]);
+    }
+  }
+  if constexpr (!kSmall) {
+    // one row after another: the FP64 path keeps the register count of a
+    // single row in flight
+#pragma unroll 1
+    for (int rr = 0; rr < R; ++rr) {
+      // register arrays indexed by a loop variable would go to scratch:
+      // this row's range by selection
+      int rb = 0, re = 0;
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+        if (t == rr) {
+          rb = beg[t];
+          re = end[t];
+        }
+      double sum = 0.0;
+      for (int e0 = rb; e0 < re; e0 += kResidualRound) {
+        int c[S];
+        double a[S], prod[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+          const int e = e0 + u * kResidualLanes + g;
+          const bool in = e < re;
+          c[u] = in ? col[e] : 0;
+          a[u] = in ? val[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < S; ++u) prod[u] = a[u] * (xc ? (double)xcg[c[u]] : xg[c[u]]);
+        if (P.sums_exact) {
+#pragma unroll
+          for (int u = 0; u < S; ++u) sum = sum + prod[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < S; ++u) {
+            const int cnt = min(kResidualLanes, re - (e0 + u * kResidualLanes));
+            for (int t = 0; t < cnt; ++t) sum = sum + __shfl(prod[u], t, kResidualLanes);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+        if (t == rr) acc[t] = sum;
+    }
+  }
+}
 
 template <int kWeights>
 __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __restrict__ x,
@@ -135,76 +228,86 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
                                                   uint32_t epoch, RowState* __restrict__ rs,
                                                   const int32_t* __restrict__ nidx, const uint8_t* __restrict__ pair,
                                                   const float* __restrict__ w, GatherRow* __restrict__ grow) {
+  constexpr int R = kResidualRows;
+  WalkState* st_w = const_cast<WalkState*>(st);
   const int g = threadIdx.x & (kResidualLanes - 1);
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kResidualLanes;
-  if (i >= P.ms) return;  // whole groups leave together
-  const gptr<const double> val = gmem(P.row_val);
-  const gptr<const int32_t> col = gmem(P.row_col);
-  const gptr<const double> xg = gmem(x);
-  const gptr<const int8_t> xcg = gmem(xc);
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kResidualLanes * R;
+  if (i0 >= P.ms) return;  // whole groups leave together
   const bool small = xc != nullptr && st->x_misfit != epoch;
-  const int beg = P.row_ptr[i], end = P.row_ptr[i + 1];
-  double acc = 0.0;
-  // kResidualSteps entries per lane in flight: every load of a round is
-  // issued before its products are summed
-  constexpr int kRound = kResidualLanes * kResidualSteps;
-  for (int e0 = beg; e0 < end; e0 += kRound) {
-    int c[kResidualSteps];
-    double a[kResidualSteps], prod[kResidualSteps];
-#pragma unroll
-    for (int u = 0; u < kResidualSteps; ++u) {
-      const int e = e0 + u * kResidualLanes + g;
-      c[u] = e < end ? col[e] : 0;
-      a[u] = e < end ? val[e] : 0.0;
-    }
-    if (small) {
-#pragma unroll
-      for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * (double)xcg[c[u]];
-    } else {
-#pragma unroll
-      for (int u = 0; u < kResidualSteps; ++u) prod[u] = a[u] * xg[c[u]];
-    }
-    if (P.sums_exact) {
-      // integer products with exact partial sums: each lane keeps its own
-      // sum, the group adds them once at the end
-#pragma unroll
-      for (int u = 0; u < kResidualSteps; ++u) acc = acc + prod[u];
-    } else {
-#pragma unroll
-      for (int u = 0; u < kResidualSteps; ++u) {
-        const int cnt = min(kResidualLanes, end - (e0 + u * kResidualLanes));
-        for (int t = 0; t < cnt; ++t) acc = acc + __shfl(prod[u], t, kResidualLanes);
-      }
+  // lane g < R owns row i0 + g's right-hand side and weights: loaded first,
+  // they arrive while the entries are read
+  const int64_t mine = i0 + g;
+  const bool owner = g < R && mine < P.ms;
+  double rhs = 0.0;
+  float w0 = 1.0f, w1 = -1.0f;
+  bool twin = false;
+  if (owner) {
+    rhs = P.row_rhs[mine];
+    if constexpr (kWeights != kWeightsKeep) twin = pair[mine] != 0;
+    if constexpr (kWeights == kWeightsScatter) {
+      const int k = nidx[mine];
+      w0 = w[k];
+      if (twin) w1 = w[k + 1];
     }
   }
+  int beg[R], end[R], rounds = 0;
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) {
+    const int64_t i = i0 + rr;
+    beg[rr] = i < P.ms ? P.row_ptr[i] : 0;
+    end[rr] = i < P.ms ? P.row_ptr[i + 1] : 0;
+  }
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) rounds = max(rounds, (end[rr] - beg[rr] + kResidualRound - 1) / kResidualRound);
+  double acc[R];
+  if (P.row_c8 && small && P.sums_exact)
+    residual_rounds<true>(P, x, xc, g, beg, end, rounds, acc);
+  else
+    residual_rounds<false>(P, x, small ? xc : nullptr, g, beg, end, rounds, acc);
   if (P.sums_exact) {
 #pragma unroll
-    for (int o = 1; o < kResidualLanes; o <<= 1) acc = acc + __shfl_xor(acc, o, kResidualLanes);
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int o = 1; o < kResidualLanes; o <<= 1) acc[rr] = acc[rr] + __shfl_xor(acc[rr], o, kResidualLanes);
   }
-  if (g != 0) return;
-  const double r = acc - P.row_rhs[i];
+  // every lane of the group holds every row's sum; lane g writes row i0 + g
+  double sum = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr)
+    if (g == rr) sum = acc[rr];
+  if (!owner) return;
+  const double r = sum - rhs;
   if constexpr (kWeights == kWeightsKeep) {
-    rs[i].r = r;
+    rs[mine].r = r;
   } else {
     RowState q;
     q.r = r;
+    q.w0 = w0;
+    q.w1 = twin ? w1 : -1.0f;
     if constexpr (kWeights == kWeightsUnit) {
-      const bool tw = pair[i] != 0;
       q.w0 = 1.0f;
-      q.w1 = tw ? 1.0f : -1.0f;
+      q.w1 = twin ? 1.0f : -1.0f;
       if (grow) {
-        GatherRow c;
-        c.r = (int32_t)r;
-        c.w0 = 1;
-        c.w1 = tw ? (uint16_t)1 : kNoTwin;
-        grow[i] = c;
+        GatherRow cr;
+        cr.r = (int32_t)r;
+        cr.w0 = 1;
+        cr.w1 = twin ? (uint16_t)1 : kNoTwin;
+        grow[mine] = cr;
       }
-    } else {
-      const int k = nidx[i];
-      q.w0 = w[k];
-      q.w1 = pair[i] ? w[k + 1] : -1.0f;
+    } else if (grow) {
+      // the compact copy of the caller's weights, as k_fill_compact_checked
+      // writes it (the state initialisation has run and checked the cutoff
+      // weight)
+      const bool ok = r == floor(r) && fabs(r) <= 2147483647.0 && q.w0 == floorf(q.w0) && q.w0 >= 0.0f &&
+                      q.w0 < 65535.0f && (q.w1 < 0.0f || (q.w1 == floorf(q.w1) && q.w1 < 65535.0f));
+      if (!ok) st_w->compact_rows = 0;  // every writer stores the same value
+      GatherRow cr;
+      cr.r = ok ? (int32_t)r : 0;
+      cr.w0 = ok ? (uint16_t)q.w0 : 0;
+      cr.w1 = (ok && q.w1 >= 0.0f) ? (uint16_t)q.w1 : kNoTwin;
+      grow[mine] = cr;
     }
-    rs[i] = q;
+    rs[mine] = q;
   }
 }
 
@@ -379,7 +482,10 @@ __global__ __launch_bounds__(256) void k_state_init(DevProblem P, const double* 
   st->mv_j = -1;
   st->mv_kind = 2;
   st->dV = 0ull;
-  st->compact_rows = 1;
+  // single passes: the compact copy holds the cutoff weight as a count of
+  // half weights only when it is an integer below 2^16 (the rows are
+  // checked where the copy is written)
+  st->compact_rows = (o.wc == floorf(o.wc) && o.wc >= 0.0f && o.wc < 65535.0f) ? 1 : 0;
   st->skip = 0;
   st->aff_ok = 0;
   st->pass_skip = 0;
@@ -881,6 +987,100 @@ __global__ __launch_bounds__(256) void k_gather2(const int32_t* __restrict__ inv
   db[j] = b[q];
 }
 
+// Planned permutation, first pass: workgroup c sorts input chunk c by output
+// block in LDS, then writes the sorted chunk to its runs' staging slots
+// (consecutive slots within a run). Arrays 0 and 1 (in1 may be null) one
+// after the other.
+constexpr int kPermRunsThreads = 1024;
+constexpr int kPermPlaceThreads = 512;
+__global__ __launch_bounds__(kPermRunsThreads) void k_perm_runs(PermPlan pl, const double* __restrict__ in0,
+                                                                const double* __restrict__ in1,
+                                                                double* __restrict__ st0, double* __restrict__ st1) {
+  __shared__ double lds[kPermChunk];
+  constexpr int kU = kPermChunk / kPermRunsThreads;
+  const int64_t base = (int64_t)blockIdx.x * kPermChunk;
+  const int cnt = (int)min((int64_t)kPermChunk, (int64_t)pl.n - base);
+  for (int a = 0; a < 2; ++a) {
+    const double* in = a ? in1 : in0;
+    double* st = a ? st1 : st0;
+    if (!in) break;
+    double v[kU];
+    int pos[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = threadIdx.x + u * kPermRunsThreads;
+      if (t < cnt) {
+        v[u] = in[base + t];
+        pos[u] = pl.lpos[base + t];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (threadIdx.x + u * kPermRunsThreads < cnt) lds[pos[u]] = v[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = threadIdx.x + u * kPermRunsThreads;
+      if (t < cnt) pos[u] = pl.sdst[base + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = threadIdx.x + u * kPermRunsThreads;
+      if (t < cnt) st[pos[u]] = lds[t];
+    }
+    __syncthreads();
+  }
+}
+
+// Second pass: workgroup b places output block b's values (contiguous in
+// staging) at their offsets in LDS and writes the block. With xc, the byte
+// copy of array 0 as in k_stage_x.
+__global__ __launch_bounds__(kPermPlaceThreads) void k_perm_place(PermPlan pl, const double* __restrict__ st0,
+                                                                  const double* __restrict__ st1,
+                                                                  double* __restrict__ out0, double* __restrict__ out1,
+                                                                  int8_t* __restrict__ xc, WalkState* ws,
+                                                                  uint32_t epoch) {
+  __shared__ double lds[kPermBlock];
+  constexpr int kU = kPermBlock / kPermPlaceThreads;
+  const int64_t base = (int64_t)blockIdx.x * kPermBlock;
+  const int cnt = (int)min((int64_t)kPermBlock, (int64_t)pl.n - base);
+  bool misfit = false;
+  for (int a = 0; a < 2; ++a) {
+    const double* st = a ? st1 : st0;
+    double* out = a ? out1 : out0;
+    if (!st) break;
+    double v[kU];
+    int pos[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = threadIdx.x + u * kPermPlaceThreads;
+      if (t < cnt) {
+        v[u] = st[base + t];
+        pos[u] = pl.dl[base + t];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (threadIdx.x + u * kPermPlaceThreads < cnt) lds[pos[u]] = v[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = threadIdx.x + u * kPermPlaceThreads;
+      if (t < cnt) {
+        const double x = lds[t];
+        out[base + t] = x;
+        if (a == 0 && xc) {
+          const bool fits = x == floor(x) && x >= -128.0 && x <= 127.0;
+          xc[base + t] = fits ? (int8_t)x : (int8_t)0;
+          misfit = misfit || !fits;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (misfit) ws->x_misfit = epoch;  // every writer stores the same value
+}
+
 __global__ __launch_bounds__(256) void k_fill_compact(const RowState* __restrict__ rs, GatherRow* __restrict__ grow,
                                                       int32_t ms) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1175,7 +1375,8 @@ __global__ void k_restart_fix(WalkState* st, RestartKeep keep) {
 namespace {
 
 inline dim3 residual_grid(int32_t ms) {
-  return dim3((unsigned)(((int64_t)ms * kResidualLanes + 255) / 256));
+  const int64_t groups = ((int64_t)ms + kResidualRows - 1) / kResidualRows;
+  return dim3((unsigned)((groups * kResidualLanes + 255) / 256));
 }
 
 }  // namespace
@@ -1198,10 +1399,10 @@ hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const 
 
 hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair, const float* w,
                                    const double* x, const int8_t* xc, const WalkState* st, uint32_t epoch,
-                                   RowState* rs, hipStream_t stream) {
+                                   RowState* rs, hipStream_t stream, GatherRow* grow) {
   if (P.ms > 0)
     hipLaunchKernelGGL(k_residual<kWeightsScatter>, residual_grid(P.ms), dim3(256), 0, stream, P, x, xc, st, epoch,
-                       rs, nidx, pair, w, nullptr);
+                       rs, nidx, pair, w, grow);
   return hipGetLastError();
 }
 
@@ -1290,6 +1491,32 @@ hipError_t launch_copy_best_batch(const BatchLaunch& L, hipStream_t stream) {
 
 hipError_t launch_gather(const int32_t* perm, const double* src, double* dst, int32_t n, hipStream_t stream) {
   if (n > 0) hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, stream, perm, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_x_plan(const PermPlan& plan, const double* src, double* dst, int8_t* xc, WalkState* st,
+                               uint32_t epoch, double* stage, hipStream_t stream) {
+  if (plan.n > 0) {
+    const unsigned nc = (unsigned)((plan.n + kPermChunk - 1) / kPermChunk);
+    const unsigned nb = (unsigned)((plan.n + kPermBlock - 1) / kPermBlock);
+    hipLaunchKernelGGL(k_perm_runs, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, src, nullptr, stage,
+                       nullptr);
+    hipLaunchKernelGGL(k_perm_place, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, nullptr, dst,
+                       nullptr, xc, st, epoch);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather2_plan(const PermPlan& plan, const double* a, const double* b, double* da, double* db,
+                               double* stage, hipStream_t stream) {
+  if (plan.n > 0) {
+    const unsigned nc = (unsigned)((plan.n + kPermChunk - 1) / kPermChunk);
+    const unsigned nb = (unsigned)((plan.n + kPermBlock - 1) / kPermBlock);
+    double* stage_b = stage + plan.n;
+    hipLaunchKernelGGL(k_perm_runs, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, a, b, stage, stage_b);
+    hipLaunchKernelGGL(k_perm_place, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, stage_b, da, db,
+                       nullptr, nullptr, 0u);
+  }
   return hipGetLastError();
 }
 

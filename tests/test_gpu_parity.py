@@ -146,6 +146,23 @@ def test_best_shift_workload_shapes(chap):
             assert_same(xh, oxh, f"{name} shift")
 
 
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 8191, 8192, 8193, 12289, 20000])
+def test_best_shift_point_permutation_sizes(chap, n):
+    """The caller's point enters internal column order, and the results leave
+    it, through two-pass permutations over chunks of 8192 and blocks of 4096
+    columns: sizes at, around and past those edges, with ragged last chunks
+    and blocks."""
+    mip = mipgen.random_mixed(900 + n % 97, n=n, m=max(4, n // 2), max_row_nnz=6, int_width=20, long_cols=0)
+    P = oracle.OracleProblem(mip)
+    x = mipgen.random_point(mip, 1)
+    w = mipgen.random_weights(P.mp + 1, 2)
+    say(f"best_shift permutation sizes n={n}")
+    xh, s = gpu_best_shift(chap, mip, x, w)
+    oxh, os_ = P.best_shift(x, w)
+    assert_same(s, os_, f"score n={n}")
+    assert_same(xh, oxh, f"shift n={n}")
+
+
 def compare_runs(g, o, what):
     """Trace, final point, residuals, weights, best objective, cutoff and
     best point, bit for bit."""
@@ -383,22 +400,28 @@ def test_autotune_picks_a_candidate(chap):
     np.testing.assert_array_equal(T.tabu_run(100, 10, 3).trace, G.tabu_run(100, 10, 3).trace)
 
 
-@pytest.mark.parametrize("wkind", ["integral", "fractional", "large"])
+@pytest.mark.parametrize("wkind", ["integral", "fractional", "large", "cutoff fractional", "cutoff large"])
 def test_best_shift_weight_kinds(chap, wkind):
     """All-integer instances let a single pass gather a compact copy of the
     rows when the caller's weights are integers below 65535; fractional or
-    large weights must take the full-row path. Both agree with the oracle."""
+    large weights must take the full-row path, and so must an active cutoff
+    row whose weight alone is fractional or large. Both agree with the
+    oracle."""
     mip = mipgen.random_mixed(91, n=300, m=200, max_row_nnz=8, int_width=30, long_cols=3, long_deg=60)
     P = oracle.OracleProblem(mip)
     x = mipgen.random_point(mip, 4)
     w = mipgen.random_weights(P.mp + 1, 5)
+    cutoff = math.inf
     if wkind == "fractional":
         w = w + np.float32(0.5)
     elif wkind == "large":
         w[::7] = 70000.0
+    elif wkind.startswith("cutoff"):
+        w[P.mp] = 2.5 if wkind == "cutoff fractional" else 70000.0
+        cutoff = float(np.floor(mip.obj @ x)) - 3.0
     say(f"best_shift weights {wkind}")
-    xh, s = gpu_best_shift(chap, mip, x, w)
-    oxh, os_ = P.best_shift(x, w)
+    xh, s = gpu_best_shift(chap, mip, x, w, cutoff)
+    oxh, os_ = P.best_shift(x, w, cutoff)
     assert_same(xh, oxh, f"shift ({wkind} weights)")
     assert_same(s, os_, f"score ({wkind} weights)")
 
