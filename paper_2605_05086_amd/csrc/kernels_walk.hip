@@ -563,7 +563,7 @@ __global__ __launch_bounds__(256) void k_argmax(const WalkCtx* __restrict__ walk
     if (copy)
       for (int q = gt; q < n; q += gs) best_x[q] = x[q];
     // kU columns per thread and step, every load issued before any is used
-    constexpr int kU = 4;
+    constexpr int kU = 8;
     for (int q0 = gt; q0 < n; q0 += kU * gs) {
       double v[kU];
       int j[kU], tb[kU];

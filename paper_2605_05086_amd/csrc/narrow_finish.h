@@ -68,7 +68,10 @@ __device__ __forceinline__ void narrow_finish(double binv, double beta, double a
 // Long narrow column idx (a ChunkCol record) from its chunks' partial bins,
 // added in slot order (a fixed summation order); one wavefront. Writes the
 // column's best shift and returns, on every lane, the score it kept; *q gets
-// the column's internal index.
+// the column's internal index. Up to 64 partials at a time: lane t loads the
+// scalars of partial t (added in slot order from its neighbours' registers)
+// and every lane its bin of kCombineInFlight partials per load round.
+constexpr int kCombineInFlight = 8;
 __device__ __forceinline__ double combine_col(const WalkCtx& W0, int idx, int lane, int* q) {
   const DevProblem& P = W0.P;
   const ChunkCol C = W0.plan.chunk_cols[idx];
@@ -78,28 +81,32 @@ __device__ __forceinline__ double combine_col(const WalkCtx& W0, int idx, int la
   const int W = (int)(u - l) + 1;
   double bv = 0.0, b = 0.0, a = 0.0;
   unsigned long long c = 0;
-  // kU partials loaded at a time
-  constexpr int kU = 4;
   const gptr<const ChunkPartial> pp = gmem((const ChunkPartial*)W0.partials) + C.first;
-  for (int k0 = 0; k0 < C.nparts; k0 += kU) {
-    double pv[kU], pb[kU], pa[kU];
-    unsigned long long pc[kU];
+  for (int k0 = 0; k0 < C.nparts; k0 += kWave) {
+    const int cnt = min(kWave, C.nparts - k0);
+    double sb = 0.0, sa = 0.0;
+    unsigned long long sc = 0;
+    if (lane < cnt) {
+      sb = pp[k0 + lane].beta;
+      sa = pp[k0 + lane].alpha;
+      sc = pp[k0 + lane].cand;
+    }
+    for (int k1 = 0; k1 < cnt; k1 += kCombineInFlight) {
+      double pv[kCombineInFlight];
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        pv[u] = pp[k0 + u].bins[lane];
-        pb[u] = pp[k0 + u].beta;
-        pa[u] = pp[k0 + u].alpha;
-        pc[u] = pp[k0 + u].cand;
-      }
+      for (int t = 0; t < kCombineInFlight; ++t)
+        if (k1 + t < cnt) pv[t] = pp[k0 + k1 + t].bins[lane];
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (k0 + u < C.nparts) {
-        bv += pv[u];
-        b += pb[u];
-        a += pa[u];
-        c |= pc[u];
-      }
+      for (int t = 0; t < kCombineInFlight; ++t)
+        if (k1 + t < cnt) bv += pv[t];
+    }
+    for (int t = 0; t < cnt; ++t) {
+      b += __shfl(sb, t, kWave);
+      a += __shfl(sa, t, kWave);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sc |= __shfl_xor(sc, o, kWave);
+    c |= sc;
   }
   bool found;
   double best, bestp;
