@@ -757,6 +757,50 @@ int chap_problem_create(chap_problem** out, int32_t n, int32_t m, const int64_t*
       D.row_c8 = d_c8;
     }
   }
+  D.rb_ent = nullptr;
+  D.rb_c8 = nullptr;
+  D.rb_seg = nullptr;
+  D.rb_nxb = 0;
+  if (D.row_c8 && P->x_small && P->exact_incremental && m > 0 && n > 0) {
+    // int32 row sums: |a| <= 127 and |x| <= 128, so sum |a| < 2^24 bounds them
+    bool fits = true;
+    for (int32_t i = 0; i < m && fits; ++i) {
+      double mag = 0.0;
+      for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e) mag += std::fabs(rval[e]);
+      fits = mag < 16777216.0;
+    }
+    if (fits) {
+      const int32_t ng = (m + kResGroupRows - 1) / kResGroupRows;
+      const int32_t nxb = (int32_t)(((int64_t)n + kResXBlock - 1) / kResXBlock);
+      std::vector<int32_t> seg((size_t)ng * nxb + 1, 0);
+      for (int32_t i = 0; i < m; ++i)
+        for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e)
+          ++seg[(size_t)(i / kResGroupRows) * nxb + rcol[e] / kResXBlock + 1];
+      for (size_t k = 1; k < seg.size(); ++k) seg[k] += seg[k - 1];
+      std::vector<int32_t> fill(seg.begin(), seg.end() - 1);
+      std::vector<uint32_t> ent(rcol.size());
+      std::vector<int8_t> c8(rcol.size());
+      for (int32_t i = 0; i < m; ++i) {
+        const int32_t g = i / kResGroupRows;
+        for (int32_t e = rptr[i]; e < rptr[i + 1]; ++e) {
+          const int32_t b = rcol[e] / kResXBlock;
+          const int32_t at = fill[(size_t)g * nxb + b]++;
+          ent[at] = ((uint32_t)(i - g * kResGroupRows) << 17) | (uint32_t)(rcol[e] - b * kResXBlock);
+          c8[at] = (int8_t)rval[e];
+        }
+      }
+      uint32_t* d_ent;
+      int8_t* d_c8b;
+      int32_t* d_seg;
+      CHAP_HIP(A.upload(&d_ent, ent));
+      CHAP_HIP(A.upload(&d_c8b, c8));
+      CHAP_HIP(A.upload(&d_seg, seg));
+      D.rb_ent = d_ent;
+      D.rb_c8 = d_c8b;
+      D.rb_seg = d_seg;
+      D.rb_nxb = nxb;
+    }
+  }
   if (!packs.empty()) {
     PackTask* dp;
     CHAP_HIP(A.upload(&dp, packs));

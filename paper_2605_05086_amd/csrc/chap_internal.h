@@ -100,6 +100,8 @@ constexpr int kNarrowBins = 64;
 constexpr int32_t kStageUnitMask = 0x0FFFFFFF;    // values of a narrow integer column
 constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
+constexpr int kResGroupRows = 4096;  // rows per workgroup of the x-block residual kernel
+constexpr int kResXBlock = 131072;   // columns of x (bytes) per LDS block of that kernel
 constexpr int kArgmaxBlocks = 512;  // workgroups of the move-selection reduction
 constexpr int kArgmaxRecord = 8;     // doubles per workgroup record of that reduction
 constexpr int kInitBlocks = 256;     // workgroups of the walk state initialisation
@@ -148,6 +150,18 @@ struct DevProblem {
   // row_val as int8 when every stored coefficient is an integer in
   // [-127, 127] (the same values, a fifth of the bytes); null otherwise
   const int8_t* row_c8;
+  // Row-group x-block copy of the rows for residuals from the byte copy of
+  // x (all-integer instances with row_c8, bytes for x and exact activities
+  // whose byte-range bound fits int32), else null: the entries of rows
+  // [g kResGroupRows, (g + 1) kResGroupRows) whose column lies in
+  // [b kResXBlock, (b + 1) kResXBlock) are rb_ent/rb_c8[rb_seg[g rb_nxb + b]
+  // .. rb_seg[g rb_nxb + b + 1]), each word (row in group << 17) | (column
+  // in block)
+  const uint32_t* rb_ent;
+  const int8_t* rb_c8;
+  const int32_t* rb_seg;
+  int32_t rb_nxb;
+  int32_t rb_pad_;
   // 1: every row activity within the bounds is an exact integer below 2^52,
   // so the residual sums of a point inside the bounds may be added in any
   // order

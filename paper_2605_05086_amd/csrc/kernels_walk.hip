@@ -222,6 +222,46 @@ __device__ __forceinline__ void residual_rounds(const DevProblem& P, const doubl
   }
 }
 
+// Writes row i's residual r and weights (kWeightsKeep: r only; Unit: 1 and
+// the twin's 1; Scatter: the caller's w0 and w1) and, with grow, its compact
+// copy; with the caller's weights the copy is checked as well: the state
+// initialisation has run and checked the cutoff weight, and a residual or
+// weight that does not fit clears st->compact_rows.
+template <int kWeights>
+__device__ __forceinline__ void write_residual(int64_t i, double r, float w0, float w1, bool twin,
+                                               RowState* __restrict__ rs, GatherRow* __restrict__ grow,
+                                               WalkState* st_w) {
+  if constexpr (kWeights == kWeightsKeep) {
+    rs[i].r = r;
+  } else {
+    RowState q;
+    q.r = r;
+    q.w0 = w0;
+    q.w1 = twin ? w1 : -1.0f;
+    if constexpr (kWeights == kWeightsUnit) {
+      q.w0 = 1.0f;
+      q.w1 = twin ? 1.0f : -1.0f;
+      if (grow) {
+        GatherRow cr;
+        cr.r = (int32_t)r;
+        cr.w0 = 1;
+        cr.w1 = twin ? (uint16_t)1 : kNoTwin;
+        grow[i] = cr;
+      }
+    } else if (grow) {
+      const bool ok = r == floor(r) && fabs(r) <= 2147483647.0 && q.w0 == floorf(q.w0) && q.w0 >= 0.0f &&
+                      q.w0 < 65535.0f && (q.w1 < 0.0f || (q.w1 == floorf(q.w1) && q.w1 < 65535.0f));
+      if (!ok) st_w->compact_rows = 0;  // every writer stores the same value
+      GatherRow cr;
+      cr.r = ok ? (int32_t)r : 0;
+      cr.w0 = ok ? (uint16_t)q.w0 : 0;
+      cr.w1 = (ok && q.w1 >= 0.0f) ? (uint16_t)q.w1 : kNoTwin;
+      grow[i] = cr;
+    }
+    rs[i] = q;
+  }
+}
+
 template <int kWeights>
 __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __restrict__ x,
                                                   const int8_t* __restrict__ xc, const WalkState* st,
@@ -276,38 +316,125 @@ __global__ __launch_bounds__(256) void k_residual(DevProblem P, const double* __
   for (int rr = 0; rr < R; ++rr)
     if (g == rr) sum = acc[rr];
   if (!owner) return;
-  const double r = sum - rhs;
-  if constexpr (kWeights == kWeightsKeep) {
-    rs[mine].r = r;
-  } else {
-    RowState q;
-    q.r = r;
-    q.w0 = w0;
-    q.w1 = twin ? w1 : -1.0f;
-    if constexpr (kWeights == kWeightsUnit) {
-      q.w0 = 1.0f;
-      q.w1 = twin ? 1.0f : -1.0f;
-      if (grow) {
-        GatherRow cr;
-        cr.r = (int32_t)r;
-        cr.w0 = 1;
-        cr.w1 = twin ? (uint16_t)1 : kNoTwin;
-        grow[mine] = cr;
+  write_residual<kWeights>(mine, sum - rhs, w0, w1, twin, rs, grow, st_w);
+}
+
+// Row sums of one workgroup's kResGroupRows rows with x held in LDS: the
+// byte copy of x is swept in kResXBlock-column blocks (the next block's
+// bytes loaded into registers while the current one is used), and the
+// group's entries of each block (int8 coefficient, word = row in group and
+// column in block) add their products into int32 LDS sums (exact: the
+// layout exists only where every row's byte-range activity fits). This
+// trades the one random L2 request per nonzero of k_residual for whole-line
+// reads of x. A call whose point does not fit the byte copy sums the rows
+// from x as k_residual does.
+constexpr int kResBlockedThreads = 1024;
+static_assert(kResXBlock == (1 << 17) && kResGroupRows <= (1 << 15), "entry word: row << 17 | column");
+template <int kWeights>
+__global__ __launch_bounds__(kResBlockedThreads) void k_residual_blocked(
+    DevProblem P, const double* __restrict__ x, const int8_t* __restrict__ xc, const WalkState* st, uint32_t epoch,
+    RowState* __restrict__ rs, const int32_t* __restrict__ nidx, const uint8_t* __restrict__ pair,
+    const float* __restrict__ w, GatherRow* __restrict__ grow) {
+  __shared__ int32_t acc[kResGroupRows];
+  __shared__ __align__(16) int8_t xs[kResXBlock];
+  WalkState* st_w = const_cast<WalkState*>(st);
+  const int64_t i0 = (int64_t)blockIdx.x * kResGroupRows;
+  const int rows = (int)min((int64_t)kResGroupRows, (int64_t)P.ms - i0);
+  const bool small = st->x_misfit != epoch;
+  if (small) {
+    constexpr int kV = kResXBlock / 16 / kResBlockedThreads;  // 16-byte words of a block per thread
+    constexpr int kE = 4;                                      // entries per thread in flight
+    const int4* __restrict__ xv = (const int4*)xc;
+    const gptr<const int8_t> xb = gmem(xc);
+    const gptr<const uint32_t> ent = gmem(P.rb_ent);
+    const gptr<const int8_t> c8 = gmem(P.rb_c8);
+    const int nxb = P.rb_nxb;
+    const int32_t* seg = P.rb_seg + (int64_t)blockIdx.x * nxb;
+    for (int t = threadIdx.x; t < kResGroupRows; t += kResBlockedThreads) acc[t] = 0;
+    // block b's bytes: whole 16-byte words below n, single bytes past the
+    // last whole word
+    int4 pre[kV];
+    auto load_block = [&](int b) {
+      const int64_t c0 = (int64_t)b * kResXBlock;
+      const int64_t words = ((int64_t)P.n - c0) / 16;
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const int t = threadIdx.x + v * kResBlockedThreads;
+        if (t < words) {
+          pre[v] = xv[c0 / 16 + t];
+        } else {
+          int32_t part[4] = {0, 0, 0, 0};
+          for (int k = 0; k < 16; ++k) {
+            const int64_t c = c0 + 16 * (int64_t)t + k;
+            if (c < P.n) part[k >> 2] |= (int32_t)(uint8_t)xb[c] << (8 * (k & 3));
+          }
+          pre[v] = make_int4(part[0], part[1], part[2], part[3]);
+        }
       }
-    } else if (grow) {
-      // the compact copy of the caller's weights, as k_fill_compact_checked
-      // writes it (the state initialisation has run and checked the cutoff
-      // weight)
-      const bool ok = r == floor(r) && fabs(r) <= 2147483647.0 && q.w0 == floorf(q.w0) && q.w0 >= 0.0f &&
-                      q.w0 < 65535.0f && (q.w1 < 0.0f || (q.w1 == floorf(q.w1) && q.w1 < 65535.0f));
-      if (!ok) st_w->compact_rows = 0;  // every writer stores the same value
-      GatherRow cr;
-      cr.r = ok ? (int32_t)r : 0;
-      cr.w0 = ok ? (uint16_t)q.w0 : 0;
-      cr.w1 = (ok && q.w1 >= 0.0f) ? (uint16_t)q.w1 : kNoTwin;
-      grow[mine] = cr;
+    };
+    int b = 0;
+    while (b < nxb && seg[b] == seg[b + 1]) ++b;  // blocks without entries are skipped
+    if (b < nxb) load_block(b);
+    while (b < nxb) {
+      int nb = b + 1;
+      while (nb < nxb && seg[nb] == seg[nb + 1]) ++nb;
+      __syncthreads();  // the previous block's readers are done
+#pragma unroll
+      for (int v = 0; v < kV; ++v) ((int4*)xs)[threadIdx.x + v * kResBlockedThreads] = pre[v];
+      if (nb < nxb) load_block(nb);  // in flight while this block is used
+      __syncthreads();
+      const int e_end = seg[b + 1];
+      for (int e0 = seg[b] + threadIdx.x; e0 < e_end; e0 += kE * kResBlockedThreads) {
+        uint32_t wd[kE];
+        int a[kE];
+#pragma unroll
+        for (int u = 0; u < kE; ++u) {
+          const int e = e0 + u * kResBlockedThreads;
+          wd[u] = e < e_end ? ent[e] : 0u;
+          a[u] = e < e_end ? (int)c8[e] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kE; ++u)
+          if (a[u] != 0) atomicAdd(&acc[wd[u] >> 17], a[u] * (int)xs[wd[u] & (kResXBlock - 1)]);
+      }
+      b = nb;
     }
-    rs[mine] = q;
+    __syncthreads();
+    for (int t = threadIdx.x; t < rows; t += kResBlockedThreads) {
+      const int64_t i = i0 + t;
+      float w0 = 1.0f, w1 = -1.0f;
+      bool twin = false;
+      if constexpr (kWeights != kWeightsKeep) twin = pair[i] != 0;
+      if constexpr (kWeights == kWeightsScatter) {
+        const int k = nidx[i];
+        w0 = w[k];
+        if (twin) w1 = w[k + 1];
+      }
+      write_residual<kWeights>(i, (double)acc[t] - P.row_rhs[i], w0, w1, twin, rs, grow, st_w);
+    }
+  } else {
+    // kResidualLanes lanes per row, rows of the group one group of lanes
+    // after another (the FP64 path of k_residual)
+    const int g = threadIdx.x & (kResidualLanes - 1);
+    for (int t = threadIdx.x / kResidualLanes; t < rows; t += kResBlockedThreads / kResidualLanes) {
+      const int64_t i = i0 + t;
+      const int beg[1] = {P.row_ptr[i]}, end[1] = {P.row_ptr[i + 1]};
+      const int rounds = (end[0] - beg[0] + kResidualRound - 1) / kResidualRound;
+      double sum[1];
+      residual_rounds<false>(P, x, nullptr, g, beg, end, rounds, sum);
+#pragma unroll
+      for (int o = 1; o < kResidualLanes; o <<= 1) sum[0] = sum[0] + __shfl_xor(sum[0], o, kResidualLanes);
+      if (g != 0) continue;
+      float w0 = 1.0f, w1 = -1.0f;
+      bool twin = false;
+      if constexpr (kWeights != kWeightsKeep) twin = pair[i] != 0;
+      if constexpr (kWeights == kWeightsScatter) {
+        const int k = nidx[i];
+        w0 = w[k];
+        if (twin) w1 = w[k + 1];
+      }
+      write_residual<kWeights>(i, sum[0] - P.row_rhs[i], w0, w1, twin, rs, grow, st_w);
+    }
   }
 }
 
@@ -1388,10 +1515,19 @@ hipError_t launch_residual(const DevProblem& P, const double* x, RowState* rs, h
   return hipGetLastError();
 }
 
+// The x-block kernel where the problem has its row layout and the call has
+// a byte copy of x (its own fallback covers a point that does not fit).
+inline bool residual_blocked(const DevProblem& P, const int8_t* xc) { return P.rb_ent != nullptr && xc != nullptr; }
+
+inline dim3 residual_blocked_grid(int32_t ms) { return dim3((unsigned)((ms + kResGroupRows - 1) / kResGroupRows)); }
+
 hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const double* x, const int8_t* xc,
                                 const WalkState* st, uint32_t epoch, RowState* rs, GatherRow* grow,
                                 hipStream_t stream) {
-  if (P.ms > 0)
+  if (P.ms > 0 && residual_blocked(P, xc))
+    hipLaunchKernelGGL(k_residual_blocked<kWeightsUnit>, residual_blocked_grid(P.ms), dim3(kResBlockedThreads), 0,
+                       stream, P, x, xc, st, epoch, rs, nullptr, pair, nullptr, grow);
+  else if (P.ms > 0)
     hipLaunchKernelGGL(k_residual<kWeightsUnit>, residual_grid(P.ms), dim3(256), 0, stream, P, x, xc, st, epoch, rs,
                        nullptr, pair, nullptr, grow);
   return hipGetLastError();
@@ -1400,7 +1536,10 @@ hipError_t launch_residual_unit(const DevProblem& P, const uint8_t* pair, const 
 hipError_t launch_residual_scatter(const DevProblem& P, const int32_t* nidx, const uint8_t* pair, const float* w,
                                    const double* x, const int8_t* xc, const WalkState* st, uint32_t epoch,
                                    RowState* rs, hipStream_t stream, GatherRow* grow) {
-  if (P.ms > 0)
+  if (P.ms > 0 && residual_blocked(P, xc))
+    hipLaunchKernelGGL(k_residual_blocked<kWeightsScatter>, residual_blocked_grid(P.ms), dim3(kResBlockedThreads), 0,
+                       stream, P, x, xc, st, epoch, rs, nidx, pair, w, grow);
+  else if (P.ms > 0)
     hipLaunchKernelGGL(k_residual<kWeightsScatter>, residual_grid(P.ms), dim3(256), 0, stream, P, x, xc, st, epoch,
                        rs, nidx, pair, w, grow);
   return hipGetLastError();
