@@ -123,9 +123,25 @@ int build_jump_plan(chap_problem* p) {
     for (const JumpBinTask& t : btasks) any = any || t.q >= 0;
     if (!any) btasks.clear();
   }
+  // tasks of columns without a bins form first (the only ones an exact call
+  // runs), each part by chunk length; column records as [no bins form]
+  // [chunked bins form] [finished by one bins task]
   std::vector<int32_t> order(tasks.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (tasks[a].bins != tasks[b].bins) return tasks[a].bins < tasks[b].bins;
+    return len[a] > len[b];
+  });
+  int32_t n_plain_tasks = 0;
+  for (const JumpTask& t : tasks) n_plain_tasks += t.bins ? 0 : 1;
+  auto col_group = [](const JumpCol& c) { return c.bn == 0 ? 0 : (c.bn > 0 ? 1 : 2); };
+  std::stable_sort(cols.begin(), cols.end(),
+                   [&](const JumpCol& a, const JumpCol& b) { return col_group(a) < col_group(b); });
+  int32_t n_plain_cols = 0, n_chunk_cols = 0;
+  for (const JumpCol& c : cols) {
+    n_plain_cols += col_group(c) == 0 ? 1 : 0;
+    n_chunk_cols += col_group(c) == 1 ? 1 : 0;
+  }
   std::vector<JumpTask> sorted(tasks.size());
   for (size_t i = 0; i < order.size(); ++i) sorted[i] = tasks[order[i]];
   DeviceArena& A = p->arena;
@@ -146,6 +162,9 @@ int build_jump_plan(chap_problem* p) {
   }
   p->n_jump_tasks = (int32_t)sorted.size();
   p->n_jump_cols = (int32_t)cols.size();
+  p->n_jump_plain_tasks = n_plain_tasks;
+  p->n_jump_plain_cols = n_plain_cols;
+  p->n_jump_chunk_cols = n_chunk_cols;
   p->n_jump_btasks = (int32_t)btasks.size();
   CHAP_HIP(hipEventCreate(&p->jump_ev[0]));
   CHAP_HIP(hipEventCreate(&p->jump_ev[1]));
@@ -178,8 +197,9 @@ int chap_jump_values(chap_problem* p, const double* d_x, const float* d_w, doubl
   CHAP_HIP(launch_residual_scatter(p->dev, p->d_nidx, p->d_pair, d_w, p->bs_x, p->bs_xc, p->bs_state, epoch,
                                    p->bs_rs, s, p->bs_grow));
   CHAP_HIP(hipEventRecord(p->jump_ev[0], s));
-  CHAP_HIP(launch_jump(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_grow ? 1 : 0, p->obj_fast, p->jump_tasks,
-                       p->n_jump_tasks, p->jump_btasks, p->n_jump_btasks, p->jump_cols, p->n_jump_cols, p->jump_part,
+  CHAP_HIP(launch_jump(p->dev, p->bs_x, p->bs_rs, p->bs_state, p->bs_grow, p->obj_fast, p->jump_tasks,
+                       p->n_jump_tasks, p->n_jump_plain_tasks, p->jump_btasks, p->n_jump_btasks, p->jump_cols,
+                       p->n_jump_cols, p->n_jump_plain_cols, p->n_jump_chunk_cols, p->jump_part,
                        p->jump_bpart, p->bs_xhat, p->bs_s, s));
   CHAP_HIP(hipEventRecord(p->jump_ev[1], s));
   CHAP_HIP(launch_gather2_plan(p->to_caller, p->bs_xhat, p->bs_s, d_jump, d_score, p->bs_stage, s));

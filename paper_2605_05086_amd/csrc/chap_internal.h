@@ -729,18 +729,24 @@ struct JumpBinTask {
 };
 // Jump value and score of every column (internal order) into jv, js; part
 // holds kWave doubles per task slot.
-// exact_data: the instance's compact row copy is exact (all-integer data,
-// residuals within int32); obj_small: objective sums are exact small
-// integers. With integer weights (checked on the device) the lane kernel
+// grow: the instance's compact row copy as this call wrote it, when that
+// copy can be exact (all-integer data, residuals within int32), else null
+// (exact_data below is grow != null); obj_small: objective sums are exact
+// small integers. With integer weights (checked on the device) the lane kernel
 // then tries fewer values of narrow columns, with the same results.
 // Columns with a bins form are scored from int64 slope and offset bins
 // when the call's data are exact (integer weights; then every V is an
 // integer below 2^53 and any order of summation gives the oracle's value),
 // else by the wavefront tasks like every other long column.
+// Tasks come as [tasks of columns without a bins form (n_plain_tasks)]
+// [the others]; column records as [no bins form (n_plain_cols)] [chunked
+// bins form (n_chunk_cols)] [bins form finished by one bins task], so that
+// exact calls visit only what they need.
 hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs, const WalkState* st,
-                       int32_t exact_data, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
-                       const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols, int32_t ncols, double* part,
-                       long long* bpart, double* jv, double* js, hipStream_t s);
+                       const GatherRow* grow, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
+                       int32_t n_plain_tasks, const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols,
+                       int32_t ncols, int32_t n_plain_cols, int32_t n_chunk_cols, double* part, long long* bpart,
+                       double* jv, double* js, hipStream_t s);
 // The same kernels with explicit grids (each kernel strides over its work).
 hipError_t launch_subset_grids(const WalkCtx* C, const LearnCtx* L, int chunk_grid, int combine_grid, int general_grid,
                                int has_general, int compact, hipStream_t s);
@@ -917,6 +923,7 @@ struct chap_problem {
   const chap::JumpCol* jump_cols = nullptr;
   const chap::JumpBinTask* jump_btasks = nullptr;
   int32_t n_jump_tasks = 0, n_jump_cols = 0, n_jump_btasks = 0;
+  int32_t n_jump_plain_tasks = 0, n_jump_plain_cols = 0, n_jump_chunk_cols = 0;
   double* jump_part = nullptr;
   long long* jump_bpart = nullptr;
   hipEvent_t jump_ev[2] = {nullptr, nullptr};

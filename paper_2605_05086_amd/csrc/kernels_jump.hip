@@ -28,9 +28,13 @@
 //                  its LDS slice and every lane adds each entry's terms in
 //                  order (one broadcast read per entry);
 //   k_jump_combine one wavefront per longer column: the chunks' partial sums
-//                  in chunk order, the cutoff term, the argmin over tiles.
+//                  in chunk order, the cutoff term, the argmin over tiles;
+//   k_jump_bins_combine one workgroup per chunked column with a bins form on
+//                  exact data: the chunks' bins, the scan and the argmin.
 // A column of one chunk is summed exactly in the stored order; longer
 // columns add per-chunk partial sums, exact on integer data.
+
+#include <algorithm>
 
 #include "chap_internal.h"
 
@@ -241,16 +245,9 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
   js[q] = found ? V(xb) - bv : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_jump_tasks(DevProblem P, const double* __restrict__ x,
-                                                    const RowState* __restrict__ rs, const WalkState* __restrict__ st,
-                                                    int32_t exact_data, int32_t obj_small,
-                                                    const JumpTask* __restrict__ tasks, int32_t ntasks,
-                                                    double* __restrict__ part) {
-  const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (id >= ntasks) return;  // whole wavefronts leave together
+__device__ void jump_task(const DevProblem& P, const double* __restrict__ x, const RowState* __restrict__ rs,
+                          const WalkState* __restrict__ st, const JumpTask T, double* __restrict__ part) {
   const int lane = threadIdx.x & (kWave - 1);
-  const JumpTask T = tasks[id];
-  if (T.bins && jump_exact(st, exact_data, obj_small)) return;  // scored from bins
   const int q = T.q;
   const int beg = P.col_ptr[q], deg = P.col_ptr[q + 1] - beg;
   const double xb = x[q], l = P.lb[q], u = P.ub[q];
@@ -295,6 +292,19 @@ __global__ __launch_bounds__(256) void k_jump_tasks(DevProblem P, const double* 
   part[(size_t)T.slot * kWave + lane] = v;
 }
 
+// Grid-stride over the tasks, one wavefront per task: every task, or on
+// exact data only the first n_plain (the tasks of columns without a bins
+// form; the others are scored from bins).
+__global__ __launch_bounds__(256) void k_jump_tasks(DevProblem P, const double* __restrict__ x,
+                                                    const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                                    int32_t exact_data, int32_t obj_small,
+                                                    const JumpTask* __restrict__ tasks, int32_t ntasks,
+                                                    int32_t n_plain, double* __restrict__ part) {
+  const int nt = jump_exact(st, exact_data, obj_small) ? n_plain : ntasks;
+  for (int id = blockIdx.x * 4 + (threadIdx.x >> 6); id < nt; id += gridDim.x * 4)  // whole wavefronts
+    jump_task(P, x, rs, st, tasks[id], part);
+}
+
 // floor(n / d) and ceil(n / d) for d > 0 and |n|, |d| < 2^31, through one
 // FP64 division: an integer quotient is exact, and any other lies at least
 // 1/d from an integer while the rounding moves it by at most |n/d| 2^-53 <
@@ -309,23 +319,30 @@ __device__ __forceinline__ long long ceil_div(long long n, long long d) {
 
 // One term w max(0, c + a p) over positions p = 0 .. W-1 as bin updates:
 // from the first positive position on (a > 0), or up to the last one
-// (a < 0), the term is w c + w a p.
-__device__ __forceinline__ void add_ramp(unsigned long long* K, unsigned long long* S, long long c, long long a,
-                                         long long w, int W) {
+// (a < 0), the term is w c + w a p. Updates of bin 0 (every term with a < 0
+// that is positive at p = 0, and every term with a > 0 positive from p = 0)
+// go to the lane's own k0 and s0, added into the bin once per wavefront:
+// as LDS atomics they would all hit one address.
+__device__ __forceinline__ void add_ramp(unsigned long long* K, unsigned long long* S, long long& k0, long long& s0,
+                                         long long c, long long a, long long w, int W) {
   if (w == 0) return;
   if (a > 0) {
     const long long p0 = floor_div(-c, a) + 1;  // first p with c + a p > 0
     if (p0 < W) {
-      const int k = (int)(p0 > 0 ? p0 : 0);
-      atomicAdd(&K[k], (unsigned long long)(w * c));
-      atomicAdd(&S[k], (unsigned long long)(w * a));
+      if (p0 > 0) {
+        atomicAdd(&K[p0], (unsigned long long)(w * c));
+        atomicAdd(&S[p0], (unsigned long long)(w * a));
+      } else {
+        k0 += w * c;
+        s0 += w * a;
+      }
     }
   } else {
     const long long p1 = ceil_div(c, -a);  // first p with c + a p <= 0
     const int k = (int)(p1 < 0 ? 0 : (p1 > W ? W : p1));
     if (k > 0) {
-      atomicAdd(&K[0], (unsigned long long)(w * c));
-      atomicAdd(&S[0], (unsigned long long)(w * a));
+      k0 += w * c;
+      s0 += w * a;
       if (k < W) {
         atomicAdd(&K[k], (unsigned long long)(-w * c));
         atomicAdd(&S[k], (unsigned long long)(-w * a));
@@ -397,7 +414,7 @@ __device__ __forceinline__ void bins_finish(const DevProblem& P, const WalkState
 // which the task order places on one XCD, so the row gathers stay in that
 // XCD's L2.
 __global__ __launch_bounds__(256) void k_jump_bins(DevProblem P, const double* __restrict__ x,
-                                                   const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                                   const GatherRow* __restrict__ grow, const WalkState* __restrict__ st,
                                                    int32_t exact_data, int32_t obj_small,
                                                    const JumpBinTask* __restrict__ tasks, int32_t ntasks,
                                                    long long* __restrict__ bpart, double* __restrict__ jv,
@@ -419,27 +436,39 @@ __global__ __launch_bounds__(256) void k_jump_bins(DevProblem P, const double* _
   const int q = T.q;
   const double xb = x[q], l = P.lb[q];
   const int W = (int)(P.ub[q] - l) + 1;
-  // four entries per lane in flight: all loads of a step before any use
+  long long k0 = 0, s0 = 0;
+  // four entries per lane in flight: all loads of a step before any use;
+  // rows from the compact copy (exact on this path: integer residuals and
+  // weights)
   constexpr int kU = 4;
   for (int e0 = T.e_beg + lane; e0 < T.e_end; e0 += kU * kWave) {
-    RowState r[kU];
+    GatherRow r[kU];
     double a[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int e = e0 + u * kWave;
       if (e < T.e_end) {
-        r[u] = rs[P.col_row[e]];
+        r[u] = grow[P.col_row[e]];
         a[u] = P.col_val[e];
       }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (e0 + u * kWave >= T.e_end) break;
-      const long long c = (long long)(r[u].r + a[u] * (l - xb));  // residual at x_q = l: an integer
+      const long long c = (long long)((double)r[u].r + a[u] * (l - xb));  // residual at x_q = l: an integer
       const long long ai = (long long)a[u];
-      add_ramp(K, S, c, ai, (long long)r[u].w0, W);
-      if (r[u].w1 >= 0.0f) add_ramp(K, S, -c, -ai, (long long)r[u].w1, W);
+      add_ramp(K, S, k0, s0, c, ai, (long long)r[u].w0, W);
+      if (r[u].w1 != kNoTwin) add_ramp(K, S, k0, s0, -c, -ai, (long long)r[u].w1, W);
     }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    k0 += __shfl_xor(k0, o, kWave);
+    s0 += __shfl_xor(s0, o, kWave);
+  }
+  if (lane == 0) {
+    atomicAdd(&K[0], (unsigned long long)k0);
+    atomicAdd(&S[0], (unsigned long long)s0);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -452,18 +481,53 @@ __global__ __launch_bounds__(256) void k_jump_bins(DevProblem P, const double* _
   bpart[(size_t)T.slot * 2 * kWave + kWave + lane] = (long long)S[lane];
 }
 
-__global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double* __restrict__ x,
-                                                      const RowState* __restrict__ rs,
-                                                      const WalkState* __restrict__ st,
-                                                      int32_t exact_data, int32_t obj_small,
-                                                      const JumpCol* __restrict__ cols, int32_t ncols,
-                                                      const double* __restrict__ part,
-                                                      const long long* __restrict__ bpart, double* __restrict__ jv,
-                                                      double* __restrict__ js) {
-  const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (id >= ncols) return;  // whole wavefronts leave together
+constexpr int kJumpInFlight = 16;  // chunk partials per load round of the combines
+
+// A chunked column with a bins form on exact data (one workgroup per such
+// column record): each wavefront adds every fourth chunk's bins,
+// kJumpInFlight chunks per load round (integer sums, so any order gives the
+// same bins), wavefront 0 adds the four partial sums and finishes.
+__global__ __launch_bounds__(256) void k_jump_bins_combine(DevProblem P, const double* __restrict__ x,
+                                                           const WalkState* __restrict__ st, int32_t exact_data,
+                                                           int32_t obj_small, const JumpCol* __restrict__ cols,
+                                                           const long long* __restrict__ bpart,
+                                                           double* __restrict__ jv, double* __restrict__ js) {
+  const JumpCol J = cols[blockIdx.x];  // the records of chunked columns with a bins form
+  if (J.bn <= 0 || !jump_exact(st, exact_data, obj_small)) return;  // whole workgroup
+  __shared__ long long red[2][3][kWave];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+  long long k = 0, sl = 0;
+  for (int ch0 = wv * kJumpInFlight; ch0 < J.bn; ch0 += 4 * kJumpInFlight) {
+    long long kk[kJumpInFlight], ss[kJumpInFlight];
+#pragma unroll
+    for (int t = 0; t < kJumpInFlight; ++t) {
+      const size_t b = (size_t)(J.bfirst + ch0 + t) * 2 * kWave + lane;
+      kk[t] = ch0 + t < J.bn ? bpart[b] : 0ll;
+      ss[t] = ch0 + t < J.bn ? bpart[b + kWave] : 0ll;
+    }
+#pragma unroll
+    for (int t = 0; t < kJumpInFlight; ++t) {
+      k += kk[t];
+      sl += ss[t];
+    }
+  }
+  if (wv > 0) {
+    red[0][wv - 1][lane] = k;
+    red[1][wv - 1][lane] = sl;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  for (int w = 0; w < 3; ++w) {
+    k += red[0][w][lane];
+    sl += red[1][w][lane];
+  }
+  bins_finish(P, st, J.q, x[J.q], k, sl, jv, js);
+}
+
+__device__ void jump_combine(const DevProblem& P, const double* __restrict__ x, const RowState* __restrict__ rs,
+                             const WalkState* __restrict__ st, int32_t exact_data, int32_t obj_small, const JumpCol J,
+                             const double* __restrict__ part, double* __restrict__ jv, double* __restrict__ js) {
   const int lane = threadIdx.x & (kWave - 1);
-  const JumpCol J = cols[id];
   const int q = J.q;
   const int beg = P.col_ptr[q], deg = P.col_ptr[q + 1] - beg;
   const double xb = x[q], l = P.lb[q], u = P.ub[q];
@@ -475,21 +539,23 @@ __global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double
   bool found = false;
   double bt = xb, bv = 0.0, v0 = 0.0;
   bool have0 = false;
-  if (J.bn != 0 && jump_exact(st, exact_data, obj_small)) {
-    if (J.bn < 0) return;  // finished by its bins task
-    long long k = 0, sl = 0;
-    for (int ch = 0; ch < J.bn; ++ch) {
-      k += bpart[(size_t)(J.bfirst + ch) * 2 * kWave + lane];
-      sl += bpart[(size_t)(J.bfirst + ch) * 2 * kWave + kWave + lane];
-    }
-    bins_finish(P, st, q, xb, k, sl, jv, js);
-    return;
-  }
+  // bins form on exact data: finished by its bins task or by k_jump_bins_combine
+  if (J.bn != 0 && jump_exact(st, exact_data, obj_small)) return;
   for (int tile = 0; tile < J.ntiles; ++tile) {
     const JumpCand cd = jump_candidate(P, rs, st, q, beg, deg, xb, l, u, isint, narrow, tile * kWave + lane);
     const int s0 = J.first_slot + tile * J.nchunks;
+    // the chunks' partial sums added in chunk order, kJumpInFlight loaded
+    // at a time
     double v = part[(size_t)s0 * kWave + lane];
-    for (int ch = 1; ch < J.nchunks; ++ch) v = v + part[(size_t)(s0 + ch) * kWave + lane];
+    for (int ch0 = 1; ch0 < J.nchunks; ch0 += kJumpInFlight) {
+      double pv[kJumpInFlight];
+#pragma unroll
+      for (int t = 0; t < kJumpInFlight; ++t)
+        if (ch0 + t < J.nchunks) pv[t] = part[(size_t)(s0 + ch0 + t) * kWave + lane];
+#pragma unroll
+      for (int t = 0; t < kJumpInFlight; ++t)
+        if (ch0 + t < J.nchunks) v = v + pv[t];
+    }
     if (cact) v = v + wc * relu(rc + cq * (cd.t - xb));
     if (cd.current) {
       v0 = v;
@@ -521,24 +587,45 @@ __global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double
   }
 }
 
+// Grid-stride over the column records, one wavefront per record: every
+// record, or on exact data only the first n_plain (the columns without a
+// bins form).
+__global__ __launch_bounds__(256) void k_jump_combine(DevProblem P, const double* __restrict__ x,
+                                                      const RowState* __restrict__ rs,
+                                                      const WalkState* __restrict__ st,
+                                                      int32_t exact_data, int32_t obj_small,
+                                                      const JumpCol* __restrict__ cols, int32_t ncols,
+                                                      int32_t n_plain, const double* __restrict__ part,
+                                                      double* __restrict__ jv, double* __restrict__ js) {
+  const int nc = jump_exact(st, exact_data, obj_small) ? n_plain : ncols;
+  for (int id = blockIdx.x * 4 + (threadIdx.x >> 6); id < nc; id += gridDim.x * 4)  // whole wavefronts
+    jump_combine(P, x, rs, st, exact_data, obj_small, cols[id], part, jv, js);
+}
+
 }  // namespace
 
 hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs, const WalkState* st,
-                       int32_t exact_data, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
-                       const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols, int32_t ncols, double* part,
-                       long long* bpart, double* jv, double* js, hipStream_t s) {
+                       const GatherRow* grow, int32_t obj_small, const JumpTask* tasks, int32_t ntasks,
+                       int32_t n_plain_tasks, const JumpBinTask* btasks, int32_t nbtasks, const JumpCol* cols,
+                       int32_t ncols, int32_t n_plain_cols, int32_t n_chunk_cols, double* part, long long* bpart,
+                       double* jv, double* js, hipStream_t s) {
+  const int32_t exact_data = grow != nullptr ? 1 : 0;
+  constexpr int kStrideGrid = 2048;  // workgroups of the grid-stride kernels
   if (P.n > 0)
     hipLaunchKernelGGL(k_jump_lane, dim3((P.n + 255) / 256), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small, jv,
                        js);
   if (nbtasks > 0)
-    hipLaunchKernelGGL(k_jump_bins, dim3((unsigned)((nbtasks + 3) / 4)), dim3(256), 0, s, P, x, rs, st, exact_data,
+    hipLaunchKernelGGL(k_jump_bins, dim3((unsigned)((nbtasks + 3) / 4)), dim3(256), 0, s, P, x, grow, st, exact_data,
                        obj_small, btasks, nbtasks, bpart, jv, js);
   if (ntasks > 0)
-    hipLaunchKernelGGL(k_jump_tasks, dim3((ntasks + 3) / 4), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small,
-                       tasks, ntasks, part);
+    hipLaunchKernelGGL(k_jump_tasks, dim3((unsigned)std::min((ntasks + 3) / 4, kStrideGrid)), dim3(256), 0, s, P, x,
+                       rs, st, exact_data, obj_small, tasks, ntasks, n_plain_tasks, part);
   if (ncols > 0)
-    hipLaunchKernelGGL(k_jump_combine, dim3((ncols + 3) / 4), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small,
-                       cols, ncols, part, bpart, jv, js);
+    hipLaunchKernelGGL(k_jump_combine, dim3((unsigned)std::min((ncols + 3) / 4, kStrideGrid)), dim3(256), 0, s, P, x,
+                       rs, st, exact_data, obj_small, cols, ncols, n_plain_cols, part, jv, js);
+  if (n_chunk_cols > 0)
+    hipLaunchKernelGGL(k_jump_bins_combine, dim3((unsigned)n_chunk_cols), dim3(256), 0, s, P, x, st, exact_data,
+                       obj_small, cols + n_plain_cols, bpart, jv, js);
   return hipGetLastError();
 }
 

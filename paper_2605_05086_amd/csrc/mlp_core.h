@@ -1,18 +1,25 @@
 // Device core of the candidate-proposal network (16 inputs, two hidden
 // layers of 64 ReLU units, one output) on gfx950 matrix cores.
 //
-// Every product runs on v_mfma_f32_16x16x16_bf16: bfloat16 operands, FP32
+// Every product runs on the matrix cores with bfloat16 operands and FP32
 // accumulation. One wavefront handles a tile of 16 samples in the
 // "feature-major" orientation: the weights are the A operand (16 output
-// units x 16 inputs per instruction) and the activations the B operand
-// (16 inputs x 16 samples). Operand layout for lane l, g = l / 16, r = l % 16,
-// t = 0..3:
+// units x K inputs per instruction) and the activations the B operand
+// (K inputs x 16 samples). v_mfma_f32_16x16x16_bf16, operand layout for
+// lane l, g = l / 16, r = l % 16, t = 0..3:
 //   A[i][k]: i = r, k = 4g + t        B[k][j]: j = r, k = 4g + t
 //   D[i][j]: j = r, i = 4g + t
 // The D layout of one layer equals the B layout of the next, so hidden
 // activations pass between layers in registers: bias, ReLU and the rounding
 // to bfloat16 (the native packed conversion, round to nearest even) are
-// applied in place.
+// applied in place. The first layer (16 inputs) uses that instruction; the
+// 64-input layers use v_mfma_f32_16x16x32_bf16, whose lanes bring 8 values
+// of K each for A and for B under the same lane-and-element to k mapping:
+// each lane passes two of its 4-unit pieces side by side (hidden units
+// 32s + 4g + t and 32s + 16 + 4g + t for half s), and the weights in the
+// same arrangement, so every instruction sums the 32 products of one half of
+// the hidden layer (the order of those sums is the hardware's; the error
+// bound of the reference allows any FP32 order).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,6 +53,19 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// Two 4-value pieces as the 8 K values of one lane.
+__device__ __forceinline__ bf16x8 pair(bf16x4 lo, bf16x4 hi) {
+  const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Parameters of one wavefront in operand layout.
@@ -115,18 +135,19 @@ __device__ __forceinline__ void forward(const Weights& W, bf16x4 x, Acts& A) {
   for (int h = 0; h < 4; ++h) A.z1[h] = mma(W.a1[h], x, W.b1[h]);
 #pragma unroll
   for (int h = 0; h < 4; ++h) A.h1[h] = relu_bf16(A.z1[h]);
+  const bf16x8 h1a = pair(A.h1[0], A.h1[1]), h1b = pair(A.h1[2], A.h1[3]);
 #pragma unroll
   for (int o = 0; o < 4; ++o) {
     f32x4 acc = W.b2[o];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc = mma(W.a2[o][k], A.h1[k], acc);
+    acc = mma32(pair(W.a2[o][0], W.a2[o][1]), h1a, acc);
+    acc = mma32(pair(W.a2[o][2], W.a2[o][3]), h1b, acc);
     A.z2[o] = acc;
   }
 #pragma unroll
   for (int o = 0; o < 4; ++o) A.h2[o] = relu_bf16(A.z2[o]);
   f32x4 acc = {g == 0 ? W.b3 : 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) acc = mma(W.a3[k], A.h2[k], acc);
+  acc = mma32(pair(W.a3[0], W.a3[1]), pair(A.h2[0], A.h2[1]), acc);
+  acc = mma32(pair(W.a3[2], W.a3[3]), pair(A.h2[2], A.h2[3]), acc);
   A.y = acc[0];
 }
 
