@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # by the counters of a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
 # see profiles/best_shift_pass_hbm_counters_powerlaw_20M.md. Valid for the
 # pass kernels as they are; None until they are measured again after a change.
-PASS_TRAFFIC_BYTES = 498_700_000
+PASS_TRAFFIC_BYTES = 499_200_000
 METRIC = "tabu moves/s, best-shift nnz/s, % HBM peak; plain vs batched/learned"
 
 
