@@ -159,7 +159,8 @@ __device__ __forceinline__ int jump_tiles(bool narrow, int deg) {
 // narrow columns try those (and the integers next to them) instead of
 // every value.
 __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* __restrict__ x,
-                                                   const RowState* __restrict__ rs, const WalkState* __restrict__ st,
+                                                   const RowState* __restrict__ rs,
+                                                   const GatherRow* __restrict__ grow, const WalkState* __restrict__ st,
                                                    int32_t exact_data, int32_t obj_small, double* __restrict__ jv,
                                                    double* __restrict__ js) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,8 +169,11 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
   if (deg > kJumpLane) return;
   const double xb = x[q], l = P.lb[q], u = P.ub[q];
   const bool isint = P.is_int[q] != 0;
+  const bool exact = jump_exact(st, exact_data, obj_small);
   double r[kJumpLane], a[kJumpLane];
   float w0[kJumpLane], w1[kJumpLane];
+  // rows from the 8-byte compact copy on exact data (the same values), else
+  // the 16-byte row states
 #pragma unroll
   for (int k = 0; k < kJumpLane; ++k) {
     r[k] = 0.0;
@@ -177,10 +181,18 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
     w0[k] = 0.0f;
     w1[k] = -1.0f;
     if (k < deg) {
-      const RowState s = rs[P.col_row[beg + k]];
-      r[k] = s.r;
-      w0[k] = s.w0;
-      w1[k] = s.w1;
+      const int i = P.col_row[beg + k];
+      if (exact) {
+        const GatherRow g = grow[i];
+        r[k] = (double)g.r;
+        w0[k] = (float)g.w0;
+        w1[k] = g.w1 == kNoTwin ? -1.0f : (float)g.w1;
+      } else {
+        const RowState s = rs[i];
+        r[k] = s.r;
+        w0[k] = s.w0;
+        w1[k] = s.w1;
+      }
       a[k] = P.col_val[beg + k];
     }
   }
@@ -212,7 +224,6 @@ __global__ __launch_bounds__(256) void k_jump_lane(DevProblem P, const double* _
       bv = v;
     }
   };
-  const bool exact = jump_exact(st, exact_data, obj_small);
   const bool narrow = jump_narrow(isint, l, u);
   // a narrow column on exact data: each kink's neighbours, widened by one
   // on either side so that a rounding of the FP64 kink across an integer
@@ -612,8 +623,8 @@ hipError_t launch_jump(const DevProblem& P, const double* x, const RowState* rs,
   const int32_t exact_data = grow != nullptr ? 1 : 0;
   constexpr int kStrideGrid = 2048;  // workgroups of the grid-stride kernels
   if (P.n > 0)
-    hipLaunchKernelGGL(k_jump_lane, dim3((P.n + 255) / 256), dim3(256), 0, s, P, x, rs, st, exact_data, obj_small, jv,
-                       js);
+    hipLaunchKernelGGL(k_jump_lane, dim3((P.n + 255) / 256), dim3(256), 0, s, P, x, rs, grow, st, exact_data,
+                       obj_small, jv, js);
   if (nbtasks > 0)
     hipLaunchKernelGGL(k_jump_bins, dim3((unsigned)((nbtasks + 3) / 4)), dim3(256), 0, s, P, x, grow, st, exact_data,
                        obj_small, btasks, nbtasks, bpart, jv, js);

@@ -193,3 +193,61 @@ def test_batch_with_start_points(chap):
         assert r.best_infeasible()[1:] == g.best_infeasible()[1:]
     o = oracle.OracleProblem(mips[0]).tabu_run(60, 5, 0, x0=walk_x0[0])
     compare_runs(runs[0], o, "batch walk from x0")
+
+
+def _two_class_instance(seed: int) -> mipgen.MIP:
+    """150,000 binary columns in one row each and 150,000 integer columns in
+    [0, 10] in three rows each; the first 15,000 rows hold only binaries, the
+    other 45,000 only integers. Internal column order puts the two classes
+    in separate ranges, so with x held in 131,072-column blocks the row groups
+    of binary rows have no entries in the last block and those of integer
+    rows none in the first."""
+    rng = np.random.default_rng(seed)
+    nb, ni, mb, mi = 150_000, 150_000, 15_000, 45_000
+    rows_b = np.repeat(np.arange(mb), 10)
+    cols_b = rng.permutation(nb)
+    rows_i = np.repeat(np.arange(mb, mb + mi), 10)
+    cols_i = nb + rng.permutation(np.repeat(np.arange(ni), 3))
+    # rows of one integer row must not repeat a column: redraw until none do
+    while True:
+        key = rows_i.astype(np.int64) * (nb + ni) + cols_i
+        o = np.argsort(key, kind="stable")
+        dup = np.zeros(key.shape[0], dtype=bool)
+        dup[o[1:]] = key[o[1:]] == key[o[:-1]]
+        if not dup.any():
+            break
+        cols_i[dup] = nb + rng.integers(0, ni, size=int(dup.sum()))
+    rows = np.concatenate([rows_b, rows_i])
+    cols = np.concatenate([cols_b, cols_i])
+    vals = rng.integers(1, 6, size=rows.shape[0]) * (rng.integers(0, 2, size=rows.shape[0]) * 2 - 1)
+    n, m = nb + ni, mb + mi
+    lb = np.zeros(n)
+    ub = np.concatenate([np.ones(nb), np.full(ni, 10.0)])
+    is_int = np.ones(n, dtype=np.uint8)
+    hidden = np.concatenate([rng.integers(0, 2, size=nb), rng.integers(0, 11, size=ni)]).astype(np.float64)
+    sense = rng.choice(np.array([mipgen.SENSE_L, mipgen.SENSE_G, mipgen.SENSE_E]), size=m, p=[0.45, 0.45, 0.1])
+    obj = rng.integers(-3, 4, size=n).astype(np.float64)
+    return mipgen._finish(n, m, rows, cols, vals.astype(np.float64), sense, lambda act: act, lb, ub, is_int, obj,
+                          hidden, "two classes")
+
+
+def test_residuals_with_empty_x_blocks(chap):
+    """Residuals from scratch of an all-integer instance whose row groups
+    leave whole blocks of x without entries (skipped at the start and at the
+    end of a group's sweep): single passes and a walk equal the oracle."""
+    import torch
+
+    mip = _two_class_instance(91)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    for seed in (1, 2):
+        x = mipgen.random_point(mip, seed)
+        w = mipgen.random_weights(P.mp + 1, seed + 3, wmax=5)
+        say(f"best_shift two-class instance seed={seed}")
+        xh, s = G.best_shift(torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda())
+        torch.cuda.synchronize()
+        oxh, os_ = P.best_shift(x, w)
+        assert np.array_equal(s.cpu().numpy(), os_)
+        assert np.array_equal(xh.cpu().numpy(), oxh)
+    say("walk two-class instance")
+    compare_runs(G.tabu_run(25, 5, 3), P.tabu_run(25, 5, 3), "two classes")
