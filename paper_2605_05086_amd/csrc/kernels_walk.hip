@@ -132,7 +132,7 @@ struct ObjState {
 // weight (the cutoff's included) does not fit.
 constexpr int kResidualLanes = 8;
 constexpr int kResidualSteps = 4;
-constexpr int kResidualRows = 1;  // consecutive rows per group
+constexpr int kResidualRows = 1;  // consecutive rows per group (4 measured no faster: 98 against 94 us)
 static_assert(kResidualRows <= kResidualLanes, "a lane of the group writes each row");
 enum { kWeightsKeep = 0, kWeightsUnit = 1, kWeightsScatter = 2 };
 
