@@ -1116,94 +1116,97 @@ __global__ __launch_bounds__(256) void k_gather2(const int32_t* __restrict__ inv
 
 // Planned permutation, first pass: workgroup c sorts input chunk c by output
 // block in LDS, then writes the sorted chunk to its runs' staging slots
-// (consecutive slots within a run). Arrays 0 and 1 (in1 may be null) one
-// after the other.
+// (consecutive slots within a run). kArrays (1 or 2) arrays side by side,
+// sharing the plan's index loads.
 constexpr int kPermRunsThreads = 1024;
 constexpr int kPermPlaceThreads = 512;
+template <int kArrays>
 __global__ __launch_bounds__(kPermRunsThreads) void k_perm_runs(PermPlan pl, const double* __restrict__ in0,
                                                                 const double* __restrict__ in1,
                                                                 double* __restrict__ st0, double* __restrict__ st1) {
-  __shared__ double lds[kPermChunk];
+  __shared__ double lds[kArrays][kPermChunk];
   constexpr int kU = kPermChunk / kPermRunsThreads;
+  const double* in[2] = {in0, in1};
+  double* st[2] = {st0, st1};
   const int64_t base = (int64_t)blockIdx.x * kPermChunk;
   const int cnt = (int)min((int64_t)kPermChunk, (int64_t)pl.n - base);
-  for (int a = 0; a < 2; ++a) {
-    const double* in = a ? in1 : in0;
-    double* st = a ? st1 : st0;
-    if (!in) break;
-    double v[kU];
-    int pos[kU];
+  double v[kArrays][kU];
+  int pos[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = threadIdx.x + u * kPermRunsThreads;
-      if (t < cnt) {
-        v[u] = in[base + t];
-        pos[u] = pl.lpos[base + t];
-      }
+  for (int u = 0; u < kU; ++u) {
+    const int t = threadIdx.x + u * kPermRunsThreads;
+    if (t < cnt) {
+      pos[u] = pl.lpos[base + t];
+#pragma unroll
+      for (int a = 0; a < kArrays; ++a) v[a][u] = in[a][base + t];
     }
+  }
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (threadIdx.x + u * kPermRunsThreads < cnt) lds[pos[u]] = v[u];
-    __syncthreads();
+  for (int u = 0; u < kU; ++u)
+    if (threadIdx.x + u * kPermRunsThreads < cnt)
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = threadIdx.x + u * kPermRunsThreads;
-      if (t < cnt) pos[u] = pl.sdst[base + t];
-    }
+      for (int a = 0; a < kArrays; ++a) lds[a][pos[u]] = v[a][u];
+  __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = threadIdx.x + u * kPermRunsThreads;
-      if (t < cnt) st[pos[u]] = lds[t];
-    }
-    __syncthreads();
+  for (int u = 0; u < kU; ++u) {
+    const int t = threadIdx.x + u * kPermRunsThreads;
+    if (t < cnt) pos[u] = pl.sdst[base + t];
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int t = threadIdx.x + u * kPermRunsThreads;
+    if (t < cnt)
+#pragma unroll
+      for (int a = 0; a < kArrays; ++a) st[a][pos[u]] = lds[a][t];
   }
 }
 
 // Second pass: workgroup b places output block b's values (contiguous in
-// staging) at their offsets in LDS and writes the block. With xc, the byte
-// copy of array 0 as in k_stage_x.
+// staging) at their offsets in LDS and writes the block, kArrays arrays side
+// by side. With xc, the byte copy of array 0 as in k_stage_x.
+template <int kArrays>
 __global__ __launch_bounds__(kPermPlaceThreads) void k_perm_place(PermPlan pl, const double* __restrict__ st0,
                                                                   const double* __restrict__ st1,
                                                                   double* __restrict__ out0, double* __restrict__ out1,
                                                                   int8_t* __restrict__ xc, WalkState* ws,
                                                                   uint32_t epoch) {
-  __shared__ double lds[kPermBlock];
+  __shared__ double lds[kArrays][kPermBlock];
   constexpr int kU = kPermBlock / kPermPlaceThreads;
+  const double* st[2] = {st0, st1};
+  double* out[2] = {out0, out1};
   const int64_t base = (int64_t)blockIdx.x * kPermBlock;
   const int cnt = (int)min((int64_t)kPermBlock, (int64_t)pl.n - base);
+  double v[kArrays][kU];
+  int pos[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int t = threadIdx.x + u * kPermPlaceThreads;
+    if (t < cnt) {
+      pos[u] = pl.dl[base + t];
+#pragma unroll
+      for (int a = 0; a < kArrays; ++a) v[a][u] = st[a][base + t];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u)
+    if (threadIdx.x + u * kPermPlaceThreads < cnt)
+#pragma unroll
+      for (int a = 0; a < kArrays; ++a) lds[a][pos[u]] = v[a][u];
+  __syncthreads();
   bool misfit = false;
-  for (int a = 0; a < 2; ++a) {
-    const double* st = a ? st1 : st0;
-    double* out = a ? out1 : out0;
-    if (!st) break;
-    double v[kU];
-    int pos[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = threadIdx.x + u * kPermPlaceThreads;
-      if (t < cnt) {
-        v[u] = st[base + t];
-        pos[u] = pl.dl[base + t];
+  for (int u = 0; u < kU; ++u) {
+    const int t = threadIdx.x + u * kPermPlaceThreads;
+    if (t < cnt) {
+#pragma unroll
+      for (int a = 0; a < kArrays; ++a) out[a][base + t] = lds[a][t];
+      if (xc) {
+        const double x = lds[0][t];
+        const bool fits = x == floor(x) && x >= -128.0 && x <= 127.0;
+        xc[base + t] = fits ? (int8_t)x : (int8_t)0;
+        misfit = misfit || !fits;
       }
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (threadIdx.x + u * kPermPlaceThreads < cnt) lds[pos[u]] = v[u];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = threadIdx.x + u * kPermPlaceThreads;
-      if (t < cnt) {
-        const double x = lds[t];
-        out[base + t] = x;
-        if (a == 0 && xc) {
-          const bool fits = x == floor(x) && x >= -128.0 && x <= 127.0;
-          xc[base + t] = fits ? (int8_t)x : (int8_t)0;
-          misfit = misfit || !fits;
-        }
-      }
-    }
-    __syncthreads();
   }
   if (misfit) ws->x_misfit = epoch;  // every writer stores the same value
 }
@@ -1638,9 +1641,9 @@ hipError_t launch_stage_x_plan(const PermPlan& plan, const double* src, double* 
   if (plan.n > 0) {
     const unsigned nc = (unsigned)((plan.n + kPermChunk - 1) / kPermChunk);
     const unsigned nb = (unsigned)((plan.n + kPermBlock - 1) / kPermBlock);
-    hipLaunchKernelGGL(k_perm_runs, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, src, nullptr, stage,
+    hipLaunchKernelGGL(k_perm_runs<1>, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, src, nullptr, stage,
                        nullptr);
-    hipLaunchKernelGGL(k_perm_place, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, nullptr, dst,
+    hipLaunchKernelGGL(k_perm_place<1>, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, nullptr, dst,
                        nullptr, xc, st, epoch);
   }
   return hipGetLastError();
@@ -1652,8 +1655,8 @@ hipError_t launch_gather2_plan(const PermPlan& plan, const double* a, const doub
     const unsigned nc = (unsigned)((plan.n + kPermChunk - 1) / kPermChunk);
     const unsigned nb = (unsigned)((plan.n + kPermBlock - 1) / kPermBlock);
     double* stage_b = stage + plan.n;
-    hipLaunchKernelGGL(k_perm_runs, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, a, b, stage, stage_b);
-    hipLaunchKernelGGL(k_perm_place, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, stage_b, da, db,
+    hipLaunchKernelGGL(k_perm_runs<2>, dim3(nc), dim3(kPermRunsThreads), 0, stream, plan, a, b, stage, stage_b);
+    hipLaunchKernelGGL(k_perm_place<2>, dim3(nb), dim3(kPermPlaceThreads), 0, stream, plan, stage, stage_b, da, db,
                        nullptr, nullptr, 0u);
   }
   return hipGetLastError();
