@@ -54,6 +54,16 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2605_05086_amd/build.py (hipcc, gfx950)")
+    # PyTorch carries its own HIP runtime beside the system one the library
+    # links; PyTorch's must reach the device first (the other order leaves
+    # PyTorch without a visible GPU), so it is initialised before the library
+    # can make its first HIP call
+    try:
+        import torch
+
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
