@@ -102,7 +102,7 @@ constexpr int kSortCaps = 4;       // LDS sort capacities: 64, 256, 1024, 4096
 constexpr int kSortCap[kSortCaps] = {64, 256, 1024, 4096};
 constexpr int kResGroupRows = 4096;  // rows per workgroup of the x-block residual kernel
 constexpr int kResXBlock = 131072;   // columns of x (bytes) per LDS block of that kernel
-constexpr int kArgmaxBlocks = 512;  // workgroups of the move-selection reduction
+constexpr int kArgmaxBlocks = 256;  // workgroups of the move-selection reduction
 constexpr int kArgmaxRecord = 8;     // doubles per workgroup record of that reduction
 constexpr int kInitBlocks = 256;     // workgroups of the walk state initialisation
 // its scratch in doubles: (f, V) per workgroup, then the workgroups' exact
