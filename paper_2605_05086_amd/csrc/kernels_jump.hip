@@ -448,10 +448,11 @@ __global__ __launch_bounds__(256) void k_jump_bins(DevProblem P, const double* _
   const double xb = x[q], l = P.lb[q];
   const int W = (int)(P.ub[q] - l) + 1;
   long long k0 = 0, s0 = 0;
-  // four entries per lane in flight: all loads of a step before any use;
-  // rows from the compact copy (exact on this path: integer residuals and
-  // weights)
-  constexpr int kU = 4;
+  // one entry per lane and step (two or four in flight measured slower:
+  // 363 and 375 against 348 us for the call's kernels on the 20M
+  // instance); rows from the compact copy (exact on this path: integer
+  // residuals and weights)
+  constexpr int kU = 1;
   for (int e0 = T.e_beg + lane; e0 < T.e_end; e0 += kU * kWave) {
     GatherRow r[kU];
     double a[kU];
