@@ -251,3 +251,27 @@ def test_residuals_with_empty_x_blocks(chap):
         assert np.array_equal(xh.cpu().numpy(), oxh)
     say("walk two-class instance")
     compare_runs(G.tabu_run(25, 5, 3), P.tabu_run(25, 5, 3), "two classes")
+
+
+@pytest.mark.parametrize("n", [131071, 131072, 131073, 262145])
+def test_residuals_at_x_block_edges(chap, n):
+    """All-integer instances whose column count falls at and around the
+    residual kernel's 131,072-column blocks of x (a last block of one column,
+    an exact fit, a ragged tail) with 8,193 rows (a last row group of one
+    row): single passes and a short walk equal the oracle."""
+    import torch
+
+    mip = mipgen.random_mixed(700 + n % 11, n=n, m=8193, max_row_nnz=8, frac_bin=0.5, frac_int=0.5,
+                              int_width=40)
+    P = oracle.OracleProblem(mip)
+    G = chap.Problem(mip)
+    x = mipgen.random_point(mip, 5)
+    w = mipgen.random_weights(P.mp + 1, 6, wmax=5)
+    say(f"best_shift at x-block edges n={n}")
+    xh, s = G.best_shift(torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    oxh, os_ = P.best_shift(x, w)
+    assert np.array_equal(s.cpu().numpy(), os_)
+    assert np.array_equal(xh.cpu().numpy(), oxh)
+    say(f"walk at x-block edges n={n}")
+    compare_runs(G.tabu_run(6, 5, 2), P.tabu_run(6, 5, 2), f"n={n}")
